@@ -1,0 +1,642 @@
+/*
+ * Octree-GS render path: plain, slow CPU oracle.  TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the reference the HIP library is checked against.  It shares
+ * no code, header, table or constant with the HIP path.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg load it; the product
+ * path never calls it.
+ *
+ * Arithmetic:
+ *  - Continuous quantities (decoded attributes, 2D means, conics, colours,
+ *    transmittance, gradients) are computed in double precision from the
+ *    float inputs.
+ *  - Discrete decisions (anchor selection, visibility, Gaussian culls, screen
+ *    tile rectangles and depth keys) are taken in single precision by a fixed,
+ *    written-out sequence of operations (the "canonical FP32 decisions"),
+ *    because a GPU kernel working in float must reach bit-identical integer
+ *    results.  Each decision function below lists its operation order; every
+ *    fused multiply-add is an explicit fmaf and the file is compiled with
+ *    -ffp-contract=off so no other operation is fused.
+ *
+ * Paper passages followed (Octree-GS, arXiv 2403.17898):
+ *  - Eq. 1 and the covariance factorisation Sigma = R S S^T R^T (Sec. III-A).
+ *  - Eq. 2, front-to-back alpha blending (Sec. III-A).
+ *  - Eq. 3, neural Gaussian positions mu_i = x_v + O_i * l_v (Sec. III-B).
+ *  - Eq. 4, attributes decoded by MLPs from feature, relative viewing
+ *    distance and viewing direction (Sec. III-B).
+ *  - Eq. 7 and the cumulative selection rule L_j <= L_hat (Sec. IV-A,
+ *    "Anchor Selection").
+ *
+ * Parity pins (checked by tests that do not call the HIP path): closed-form
+ * single- and two-Gaussian images, brute-force per-pixel compositing, the
+ * threshold form of Eq. 7 against its literal log2 form, invariants of the
+ * transmittance, and central finite differences of the backward pass.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_API __attribute__((visibility("default")))
+
+/* Camera record as passed from Python: R (9, row-major world->camera),
+ * C (3), fx, fy, cx, cy, z_near, s^2 (focal scale of Eq. 7, squared). */
+typedef struct {
+  float R[9], C[3], fx, fy, cx, cy, z_near, s2;
+  int W, H;
+} cam_t;
+
+static cam_t load_cam(const float *c, int W, int H) {
+  cam_t k;
+  memcpy(k.R, c, 9 * sizeof(float));
+  memcpy(k.C, c + 9, 3 * sizeof(float));
+  k.fx = c[12]; k.fy = c[13]; k.cx = c[14]; k.cy = c[15];
+  k.z_near = c[16]; k.s2 = c[17];
+  k.W = W; k.H = H;
+  return k;
+}
+
+/* Raster parameters: alpha_max, alpha_min, t_min, dilation, jac_clamp, bg[3]. */
+typedef struct {
+  float alpha_max, alpha_min, t_min, dilation, jac_clamp, bg[3];
+} prm_t;
+
+static prm_t load_prm(const float *p) {
+  prm_t q;
+  q.alpha_max = p[0]; q.alpha_min = p[1]; q.t_min = p[2];
+  q.dilation = p[3]; q.jac_clamp = p[4];
+  q.bg[0] = p[5]; q.bg[1] = p[6]; q.bg[2] = p[7];
+  return q;
+}
+
+/* ======================================================================
+ * Canonical FP32 decisions
+ * ====================================================================== */
+
+/* camera-space position, float: d = p - C; x_c = R d with each row as
+ * fmaf(R0, d0, fmaf(R1, d1, R2 * d2)). */
+static void cam_xform_f(const cam_t *k, float px, float py, float pz,
+                        float *xc, float *yc, float *zc) {
+  float d0 = px - k->C[0], d1 = py - k->C[1], d2 = pz - k->C[2];
+  *xc = fmaf(k->R[0], d0, fmaf(k->R[1], d1, k->R[2] * d2));
+  *yc = fmaf(k->R[3], d0, fmaf(k->R[4], d1, k->R[5] * d2));
+  *zc = fmaf(k->R[6], d0, fmaf(k->R[7], d1, k->R[8] * d2));
+}
+
+/* Sphere (camera-space centre, radius rho) against the near plane and the
+ * four side planes of the pinhole frustum.  tan of each side plane is a
+ * float division of the image-edge offset by the focal length; its secant is
+ * sqrtf(fmaf(t, t, 1)). */
+static int sphere_visible_f(const cam_t *k, float xc, float yc, float zc, float rho) {
+  float tl = k->cx / k->fx, tr = ((float)k->W - k->cx) / k->fx;
+  float tt = k->cy / k->fy, tb = ((float)k->H - k->cy) / k->fy;
+  float sl = sqrtf(fmaf(tl, tl, 1.0f)), sr = sqrtf(fmaf(tr, tr, 1.0f));
+  float st = sqrtf(fmaf(tt, tt, 1.0f)), sb = sqrtf(fmaf(tb, tb, 1.0f));
+  if (!(zc + rho >= k->z_near)) return 0;
+  if (!(xc <= fmaf(tr, zc, rho * sr))) return 0;
+  if (!(-xc <= fmaf(tl, zc, rho * sl))) return 0;
+  if (!(yc <= fmaf(tb, zc, rho * sb))) return 0;
+  if (!(-yc <= fmaf(tt, zc, rho * st))) return 0;
+  return 1;
+}
+
+/* Eq. 7 selection threshold.  With integer level L in [0, K-1] and the clamp
+ * Phi applied to the sum log2(d_max / (d s)) + Delta L, the rule
+ * L <= floor(Phi(...)) holds for every anchor of level 0 and, for L >= 1, iff
+ * L - Delta L <= log2(d_max / (d s)), i.e. iff d^2 s^2 <= (d_max 2^(Delta L - L))^2.
+ * thr2 is that square rounded once to float (computed in double); level-0
+ * anchors get +inf. */
+ORC_API void orc_lod_thr2(int64_t n, const uint8_t *level, const float *lod_bias,
+                          float d_max, float *thr2) {
+  for (int64_t j = 0; j < n; ++j) {
+    if (level[j] == 0) { thr2[j] = INFINITY; continue; }
+    double t = (double)d_max * exp2((double)lod_bias[j] - (double)level[j]);
+    thr2[j] = (float)(t * t);
+  }
+}
+
+/* Conservative bound radius of an anchor's Gaussians: the farthest offset
+ * |O_i * l| plus three times the largest base scale (decoded scales are the
+ * base scale times a sigmoid, so never larger).  Canonical float:
+ * a = O0*l0, b = O1*l1, c = O2*l2; n = sqrtf(fmaf(a,a,fmaf(b,b,c*c)));
+ * m = max_i n; rho = fmaf(3, max(bs0, bs1, bs2), m). */
+ORC_API void orc_bound_radius(int64_t n, int k, const float *offsets,
+                              const float *offset_scale, const float *base_scale,
+                              float *rho) {
+  for (int64_t j = 0; j < n; ++j) {
+    const float *l = offset_scale + 3 * j;
+    float m = 0.0f;
+    for (int i = 0; i < k; ++i) {
+      const float *o = offsets + (j * k + i) * 3;
+      float a = o[0] * l[0], b = o[1] * l[1], c = o[2] * l[2];
+      float nn = sqrtf(fmaf(a, a, fmaf(b, b, c * c)));
+      m = fmaxf(m, nn);
+    }
+    const float *bs = base_scale + 3 * j;
+    float bmax = fmaxf(fmaxf(bs[0], bs[1]), bs[2]);
+    rho[j] = fmaf(3.0f, bmax, m);
+  }
+}
+
+/* Canonical FP32 selection: visible(sphere) && d^2 * s^2 <= thr2, with
+ * d^2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) for d = p - C.  Writes a 0/1
+ * mask and returns the selected count. pos is [n][3]. */
+ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
+                                const float *rho, const float *camf, int W, int H,
+                                uint8_t *mask) {
+  cam_t k = load_cam(camf, W, H);
+  int64_t cnt = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    float px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+    float d0 = px - k.C[0], d1 = py - k.C[1], d2 = pz - k.C[2];
+    float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+    int sel = (dd * k.s2 <= thr2[j]);
+    if (sel) {
+      float xc, yc, zc;
+      cam_xform_f(&k, px, py, pz, &xc, &yc, &zc);
+      sel = sphere_visible_f(&k, xc, yc, zc, rho[j]);
+    }
+    mask[j] = (uint8_t)sel;
+    cnt += sel;
+  }
+  return cnt;
+}
+
+/* Literal Eq. 7 in double: L_hat = floor(Phi(log2(d_max / (d s)) + Delta L)),
+ * Phi clamping to [0, K-1]; select iff L <= L_hat, plus the same sphere
+ * visibility evaluated in double.  Used only to pin the threshold form. */
+ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level,
+                               const float *lod_bias, float d_max, int n_levels,
+                               const float *rho, const float *camf, int W, int H,
+                               uint8_t *mask) {
+  cam_t k = load_cam(camf, W, H);
+  double s = sqrt((double)k.s2);
+  double tl = (double)k.cx / k.fx, tr = ((double)W - k.cx) / k.fx;
+  double tt = (double)k.cy / k.fy, tb = ((double)H - k.cy) / k.fy;
+  int64_t cnt = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = (double)pos[3 * j + a] - (double)k.C[a];
+    double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double lstar = log2((double)d_max / (dist * s)) + (double)lod_bias[j];
+    if (lstar < 0) lstar = 0;
+    if (lstar > n_levels - 1) lstar = n_levels - 1;
+    int sel = ((double)level[j] <= floor(lstar));
+    if (sel) {
+      double xc = k.R[0] * d[0] + k.R[1] * d[1] + k.R[2] * d[2];
+      double yc = k.R[3] * d[0] + k.R[4] * d[1] + k.R[5] * d[2];
+      double zc = k.R[6] * d[0] + k.R[7] * d[1] + k.R[8] * d[2];
+      double r = rho[j];
+      sel = (zc + r >= k.z_near) && (xc <= tr * zc + r * sqrt(tr * tr + 1)) &&
+            (-xc <= tl * zc + r * sqrt(tl * tl + 1)) &&
+            (yc <= tb * zc + r * sqrt(tb * tb + 1)) &&
+            (-yc <= tt * zc + r * sqrt(tt * tt + 1));
+    }
+    mask[j] = (uint8_t)sel;
+    cnt += sel;
+  }
+  return cnt;
+}
+
+/* Canonical FP32 projection decisions for one Gaussian given its float
+ * attributes g[14] = mean(3), scale(3), quat(w,x,y,z), opacity, rgb(3).
+ * Returns 1 if it survives; fills the tile rectangle [x0,x1) x [y0,y1) and
+ * the camera-space depth.  Sequence:
+ *   cull unless opacity > 0
+ *   (xc, yc, zc) = cam_xform_f(mean); cull unless zc > z_near
+ *   rotation from q:  yy=y*y zz=z*z xx=x*x xy=x*y xz=x*z yz=y*z wx=w*x wy=w*y wz=w*z
+ *     R00=1-2*(yy+zz) R01=2*(xy-wz) R02=2*(xz+wy)
+ *     R10=2*(xy+wz)   R11=1-2*(xx+zz) R12=2*(yz-wx)
+ *     R20=2*(xz-wy)   R21=2*(yz+wx)   R22=1-2*(xx+yy)
+ *   M_ab = R_ab * s_b;  S_ab = fmaf(M_a0, M_b0, fmaf(M_a1, M_b1, M_a2 * M_b2))
+ *   txz = xc / zc clamped to [-lx, lx], lx = jac_clamp * ((0.5 * W) / fx); tx = txz * zc
+ *   (same for y with H, fy);  zc2 = zc * zc
+ *   J00 = fx / zc, J02 = -((fx * tx) / zc2), J11 = fy / zc, J12 = -((fy * ty) / zc2)
+ *   T0c = fmaf(J00, Rc_0c, J02 * Rc_2c),  T1c = fmaf(J11, Rc_1c, J12 * Rc_2c)
+ *   u = S T0^T, v = S T1^T (rows with the fmaf chain above)
+ *   a = dot(T0, u) + dil, b = dot(T1, u), c = dot(T1, v) + dil
+ *   det = a * c - b * b (two products, one subtraction); cull unless det > 0
+ *   mid = 0.5 * (a + c); lam = mid + sqrtf(fmaxf(mid * mid - det, 0))
+ *   r = ceilf(3 * sqrtf(lam))
+ *   px = fmaf(fx, xc / zc, cx), py = fmaf(fy, yc / zc, cy)
+ *   x0 = floorf((px - r) * 0.0625), x1 = floorf((px + r) * 0.0625) + 1,
+ *   each clamped to [0, tiles_x] by fminf/fmaxf; same for y; cull if empty.
+ * dot(p, q) = fmaf(p0, q0, fmaf(p1, q1, p2 * q2)). */
+static int project_decide_f(const cam_t *k, const prm_t *pp, const float *g, int tiles_x,
+                            int tiles_y, int rect[4], float *depth) {
+  if (!(g[10] > 0.0f)) return 0;
+  float xc, yc, zc;
+  cam_xform_f(k, g[0], g[1], g[2], &xc, &yc, &zc);
+  if (!(zc > k->z_near)) return 0;
+  float w = g[6], x = g[7], y = g[8], z = g[9];
+  float yy = y * y, zz = z * z, xx = x * x, xy = x * y, xz = x * z, yz = y * z;
+  float wx = w * x, wy = w * y, wz = w * z;
+  float Rq[9];
+  Rq[0] = 1.0f - 2.0f * (yy + zz); Rq[1] = 2.0f * (xy - wz); Rq[2] = 2.0f * (xz + wy);
+  Rq[3] = 2.0f * (xy + wz); Rq[4] = 1.0f - 2.0f * (xx + zz); Rq[5] = 2.0f * (yz - wx);
+  Rq[6] = 2.0f * (xz - wy); Rq[7] = 2.0f * (yz + wx); Rq[8] = 1.0f - 2.0f * (xx + yy);
+  float M[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * g[3 + b];
+  float S[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      float v = fmaf(M[3 * a], M[3 * b], fmaf(M[3 * a + 1], M[3 * b + 1], M[3 * a + 2] * M[3 * b + 2]));
+      S[3 * a + b] = v; S[3 * b + a] = v;
+    }
+  float lx = pp->jac_clamp * ((0.5f * (float)k->W) / k->fx);
+  float ly = pp->jac_clamp * ((0.5f * (float)k->H) / k->fy);
+  float rx = xc / zc, ry = yc / zc;
+  float tx = fminf(lx, fmaxf(-lx, rx)) * zc;
+  float ty = fminf(ly, fmaxf(-ly, ry)) * zc;
+  float zc2 = zc * zc;
+  float J00 = k->fx / zc, J02 = -((k->fx * tx) / zc2);
+  float J11 = k->fy / zc, J12 = -((k->fy * ty) / zc2);
+  const float *Rc = k->R;
+  float T0[3], T1[3];
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = fmaf(J00, Rc[c], J02 * Rc[6 + c]);
+    T1[c] = fmaf(J11, Rc[3 + c], J12 * Rc[6 + c]);
+  }
+  float u[3], v[3];
+  for (int a = 0; a < 3; ++a) {
+    u[a] = fmaf(S[3 * a], T0[0], fmaf(S[3 * a + 1], T0[1], S[3 * a + 2] * T0[2]));
+    v[a] = fmaf(S[3 * a], T1[0], fmaf(S[3 * a + 1], T1[1], S[3 * a + 2] * T1[2]));
+  }
+  float ca = fmaf(T0[0], u[0], fmaf(T0[1], u[1], T0[2] * u[2])) + pp->dilation;
+  float cb = fmaf(T1[0], u[0], fmaf(T1[1], u[1], T1[2] * u[2]));
+  float cc = fmaf(T1[0], v[0], fmaf(T1[1], v[1], T1[2] * v[2])) + pp->dilation;
+  float det = ca * cc - cb * cb;
+  if (!(det > 0.0f)) return 0;
+  float mid = 0.5f * (ca + cc);
+  float lam = mid + sqrtf(fmaxf(mid * mid - det, 0.0f));
+  float r = ceilf(3.0f * sqrtf(lam));
+  float px = fmaf(k->fx, rx, k->cx), py = fmaf(k->fy, ry, k->cy);
+  float fx0 = floorf((px - r) * 0.0625f), fx1 = floorf((px + r) * 0.0625f) + 1.0f;
+  float fy0 = floorf((py - r) * 0.0625f), fy1 = floorf((py + r) * 0.0625f) + 1.0f;
+  float tX = (float)tiles_x, tY = (float)tiles_y;
+  int x0 = (int)fminf(fmaxf(fx0, 0.0f), tX), x1 = (int)fminf(fmaxf(fx1, 0.0f), tX);
+  int y0 = (int)fminf(fmaxf(fy0, 0.0f), tY), y1 = (int)fminf(fmaxf(fy1, 0.0f), tY);
+  if (x0 >= x1 || y0 >= y1) return 0;
+  rect[0] = x0; rect[1] = y0; rect[2] = x1; rect[3] = y1;
+  *depth = zc;
+  return 1;
+}
+
+/* ======================================================================
+ * Decode (Eq. 3 and Eq. 4), double precision
+ * ====================================================================== */
+
+static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* One 2-layer head: out = W2^T relu(W1^T x + b1) + b2; W1 is [in][W],
+ * W2 is [W][out], both row-major.  Hidden pre-activations are returned for
+ * the backward pass. */
+static void head_fwd(const double *x, int in, int Wd, int out, const float *w1,
+                     const float *b1, const float *w2, const float *b2, double *hpre,
+                     double *y) {
+  for (int h = 0; h < Wd; ++h) {
+    double s = b1[h];
+    for (int i = 0; i < in; ++i) s += x[i] * (double)w1[i * Wd + h];
+    hpre[h] = s;
+  }
+  for (int o = 0; o < out; ++o) {
+    double s = b2[o];
+    for (int h = 0; h < Wd; ++h) s += (hpre[h] > 0 ? hpre[h] : 0.0) * (double)w2[h * out + o];
+    y[o] = s;
+  }
+}
+
+/* Network input of Eq. 4 for anchor position p seen from camera centre C:
+ * [feature (F), |p - C| / d_max, (p - C) / |p - C|]. */
+static void decode_input(const float *feat, int F, const float *p, const float *C,
+                         double d_max, double *x) {
+  double d[3], n2 = 0;
+  for (int a = 0; a < 3; ++a) { d[a] = (double)p[a] - (double)C[a]; n2 += d[a] * d[a]; }
+  double dist = sqrt(n2);
+  for (int i = 0; i < F; ++i) x[i] = feat[i];
+  x[F] = dist / d_max;
+  for (int a = 0; a < 3; ++a) x[F + 1 + a] = d[a] / dist;
+}
+
+/* Decode the selected anchors idx[0..m) into m*k Gaussians, planar
+ * out[14][m*k] (double).  Slot s*k + i holds Gaussian i of anchor idx[s]:
+ *   mean    = x_v + O_i * l_v                         (Eq. 3)
+ *   opacity = tanh(F_alpha(x)_i)                      (Eq. 4; kept iff > 0)
+ *   rgb     = sigmoid(F_c(x)_{3i..3i+2})
+ *   scale   = base_scale * sigmoid(F_cov(x)_{7i..7i+2})
+ *   quat    = F_cov(x)_{7i+3..7i+6} / |.| (identity when the norm is 0)
+ * mlp: w1a,b1a,w2a,b2a, w1c,b1c,w2c,b2c, w1s,b1s,w2s,b2s. */
+ORC_API void orc_decode(int64_t m, const int64_t *idx, const float *pos, const float *feat,
+                        const float *offsets, const float *offset_scale,
+                        const float *base_scale, int k, int F, int Wd,
+                        const float *const *mlp, const float *Cw, float d_max,
+                        double *out) {
+  int64_t G = m * k;
+  int in = F + 4;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t s = 0; s < m; ++s) {
+    int64_t j = idx[s];
+    double x[64], hp[256], ya[64], yc[192], ys[448];
+    decode_input(feat + j * F, F, pos + 3 * j, Cw, d_max, x);
+    head_fwd(x, in, Wd, k, mlp[0], mlp[1], mlp[2], mlp[3], hp, ya);
+    head_fwd(x, in, Wd, 3 * k, mlp[4], mlp[5], mlp[6], mlp[7], hp, yc);
+    head_fwd(x, in, Wd, 7 * k, mlp[8], mlp[9], mlp[10], mlp[11], hp, ys);
+    for (int i = 0; i < k; ++i) {
+      int64_t g = s * k + i;
+      const float *o = offsets + (j * k + i) * 3;
+      for (int a = 0; a < 3; ++a)
+        out[a * G + g] = (double)pos[3 * j + a] + (double)o[a] * (double)offset_scale[3 * j + a];
+      for (int a = 0; a < 3; ++a)
+        out[(3 + a) * G + g] = (double)base_scale[3 * j + a] * sigm(ys[7 * i + a]);
+      double q[4], qn = 0;
+      for (int a = 0; a < 4; ++a) { q[a] = ys[7 * i + 3 + a]; qn += q[a] * q[a]; }
+      qn = sqrt(qn);
+      for (int a = 0; a < 4; ++a)
+        out[(6 + a) * G + g] = qn > 0 ? q[a] / qn : (a == 0 ? 1.0 : 0.0);
+      out[10 * G + g] = tanh(ya[i]);
+      for (int a = 0; a < 3; ++a) out[(11 + a) * G + g] = sigm(yc[3 * i + a]);
+    }
+  }
+}
+
+/* ======================================================================
+ * Projection (EWA local-affine, Sec. III-A) in double, with the canonical
+ * FP32 decisions.
+ * ====================================================================== */
+
+typedef struct {
+  double mx, my;        /* 2D mean, pixels */
+  double ca, cb, cc;    /* conic = inverse 2D covariance (a b; b c)^-1 entries */
+  double op, rgb[3];
+} proj_t;
+
+/* Double-precision continuous projection of one Gaussian (same formulas as
+ * the canonical decision sequence, evaluated in double).  Also returns the
+ * intermediate 2D covariance (a, b, c) before inversion. */
+static void project_cont(const cam_t *k, const prm_t *pp, const double *g, proj_t *o,
+                         double cov[3]) {
+  double d[3] = {g[0] - k->C[0], g[1] - k->C[1], g[2] - k->C[2]};
+  double xc = k->R[0] * d[0] + k->R[1] * d[1] + k->R[2] * d[2];
+  double yc = k->R[3] * d[0] + k->R[4] * d[1] + k->R[5] * d[2];
+  double zc = k->R[6] * d[0] + k->R[7] * d[1] + k->R[8] * d[2];
+  double w = g[6], x = g[7], y = g[8], z = g[9];
+  double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  double M[9], S[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * g[3 + b];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      S[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+  double lx = (double)pp->jac_clamp * (0.5 * k->W / (double)k->fx);
+  double ly = (double)pp->jac_clamp * (0.5 * k->H / (double)k->fy);
+  double rx = xc / zc, ry = yc / zc;
+  double tx = fmin(lx, fmax(-lx, rx)) * zc, ty = fmin(ly, fmax(-ly, ry)) * zc;
+  double J00 = k->fx / zc, J02 = -k->fx * tx / (zc * zc);
+  double J11 = k->fy / zc, J12 = -k->fy * ty / (zc * zc);
+  double T0[3], T1[3];
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = J00 * k->R[c] + J02 * k->R[6 + c];
+    T1[c] = J11 * k->R[3 + c] + J12 * k->R[6 + c];
+  }
+  double a = 0, b = 0, c = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      a += T0[i] * S[3 * i + j] * T0[j];
+      b += T1[i] * S[3 * i + j] * T0[j];
+      c += T1[i] * S[3 * i + j] * T1[j];
+    }
+  a += pp->dilation; c += pp->dilation;
+  cov[0] = a; cov[1] = b; cov[2] = c;
+  double det = a * c - b * b;
+  o->mx = k->fx * rx + k->cx;
+  o->my = k->fy * ry + k->cy;
+  o->ca = c / det; o->cb = -b / det; o->cc = a / det;
+  o->op = g[10];
+  o->rgb[0] = g[11]; o->rgb[1] = g[12]; o->rgb[2] = g[13];
+}
+
+/* Project n Gaussians given planar float attributes gf[14][stride] (the
+ * values the decisions are taken on) and optionally double attributes
+ * gd[14][stride] for the continuous part (NULL: use the float values).
+ * Outputs per Gaussian: vis (0/1), rect[4] (x0,y0,x1,y1), depth (float
+ * canonical camera z), and proj[9] = mx, my, ca, cb, cc, op, r, g, b in
+ * double.  Returns the number of visible Gaussians. */
+ORC_API int64_t orc_project(int64_t n, int64_t stride, const float *gf, const double *gd,
+                            const float *camf, int W, int H, const float *prmf,
+                            uint8_t *vis, int32_t *rect, float *depth, double *proj) {
+  cam_t k = load_cam(camf, W, H);
+  prm_t pp = load_prm(prmf);
+  int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+  int64_t cnt = 0;
+#pragma omp parallel for reduction(+ : cnt) schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    float g[14];
+    double gdd[14];
+    for (int f = 0; f < 14; ++f) {
+      g[f] = gf[f * stride + i];
+      gdd[f] = gd ? gd[f * stride + i] : (double)g[f];
+    }
+    int r[4] = {0, 0, 0, 0};
+    float dz = 0;
+    int v = project_decide_f(&k, &pp, g, tiles_x, tiles_y, r, &dz);
+    vis[i] = (uint8_t)v;
+    for (int a = 0; a < 4; ++a) rect[4 * i + a] = r[a];
+    depth[i] = dz;
+    proj_t o;
+    double cov[3];
+    memset(&o, 0, sizeof o);
+    if (v) project_cont(&k, &pp, gdd, &o, cov);
+    double *p = proj + 9 * i;
+    p[0] = o.mx; p[1] = o.my; p[2] = o.ca; p[3] = o.cb; p[4] = o.cc;
+    p[5] = o.op; p[6] = o.rgb[0]; p[7] = o.rgb[1]; p[8] = o.rgb[2];
+    cnt += v;
+  }
+  return cnt;
+}
+
+/* ======================================================================
+ * Tile binning and depth ordering
+ * ====================================================================== */
+
+typedef struct {
+  uint32_t tile, dkey, gid;
+} pair_t;
+
+static int pair_cmp(const void *a, const void *b) {
+  const pair_t *p = a, *q = b;
+  if (p->tile != q->tile) return p->tile < q->tile ? -1 : 1;
+  if (p->dkey != q->dkey) return p->dkey < q->dkey ? -1 : 1;
+  if (p->gid != q->gid) return p->gid < q->gid ? -1 : 1;
+  return 0;
+}
+
+static uint32_t fbits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return u;
+}
+
+/* Count the (tile, Gaussian) pairs of the visible Gaussians. */
+ORC_API int64_t orc_count_pairs(int64_t n, const uint8_t *vis, const int32_t *rect) {
+  int64_t p = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (vis[i]) p += (int64_t)(rect[4 * i + 2] - rect[4 * i]) * (rect[4 * i + 3] - rect[4 * i + 1]);
+  return p;
+}
+
+/* All (tile, Gaussian) pairs ordered by tile, then depth (positive float
+ * bits order like the values), then Gaussian index; ranges[t] = [start, end)
+ * of tile t in that list.  Writes tile_of[P], gid_of[P]. */
+ORC_API int64_t orc_bin_sort(int64_t n, const uint8_t *vis, const int32_t *rect,
+                             const float *depth, int W, int H, uint32_t *tile_of,
+                             uint32_t *gid_of, uint32_t *ranges) {
+  int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+  int64_t P = orc_count_pairs(n, vis, rect);
+  pair_t *pr = (pair_t *)malloc(sizeof(pair_t) * (size_t)(P > 0 ? P : 1));
+  int64_t q = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!vis[i]) continue;
+    const int32_t *r = rect + 4 * i;
+    for (int y = r[1]; y < r[3]; ++y)
+      for (int x = r[0]; x < r[2]; ++x) {
+        pr[q].tile = (uint32_t)(y * tiles_x + x);
+        pr[q].dkey = fbits(depth[i]);
+        pr[q].gid = (uint32_t)i;
+        ++q;
+      }
+  }
+  qsort(pr, (size_t)P, sizeof(pair_t), pair_cmp);
+  int ntiles = tiles_x * tiles_y;
+  for (int t = 0; t < ntiles; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
+  for (int64_t i = 0; i < P; ++i) {
+    tile_of[i] = pr[i].tile;
+    gid_of[i] = pr[i].gid;
+    if (i == 0 || pr[i].tile != pr[i - 1].tile) ranges[2 * pr[i].tile] = (uint32_t)i;
+    if (i == P - 1 || pr[i].tile != pr[i + 1].tile) ranges[2 * pr[i].tile + 1] = (uint32_t)(i + 1);
+  }
+  free(pr);
+  return P;
+}
+
+/* ======================================================================
+ * Compositing (Eq. 2), double precision
+ * ====================================================================== */
+
+/* Blend one pixel over an ordered Gaussian list (Eq. 2):
+ *   a_i = min(alpha_max, op_i * exp(-0.5 (ca dx^2 + cc dy^2) - cb dx dy)),
+ *   dx = pixel_x - mx_i (pixel centres at integer + 0.5),
+ *   skip if a_i < alpha_min; C += T a_i c_i; T *= (1 - a_i);
+ *   stop after the Gaussian that takes T below t_min.
+ * Returns the count of list entries consumed; optional per-Gaussian blend
+ * weight accumulation w[gid] += a_i T_i. */
+static int blend_pixel(const prm_t *pp, const double *proj, const uint32_t *list, int n,
+                       double px, double py, double out[3], double *T_out, double *w) {
+  double T = 1.0, C[3] = {0, 0, 0};
+  int last = 0;
+  for (int i = 0; i < n; ++i) {
+    const double *p = proj + 9 * (size_t)list[i];
+    double dx = px - p[0], dy = py - p[1];
+    double pw = -0.5 * (p[2] * dx * dx + p[4] * dy * dy) - p[3] * dx * dy;
+    double a = p[5] * exp(pw);
+    if (a > pp->alpha_max) a = pp->alpha_max;
+    last = i + 1;
+    if (a < pp->alpha_min) continue;
+    double wt = a * T;
+    for (int c = 0; c < 3; ++c) C[c] += wt * p[6 + c];
+    if (w) {
+#pragma omp atomic
+      w[list[i]] += wt;
+    }
+    T *= (1.0 - a);
+    if (T < pp->t_min) break;
+  }
+  for (int c = 0; c < 3; ++c) out[c] = C[c] + T * pp->bg[c];
+  *T_out = T;
+  return last;
+}
+
+/* Tiled renderer: for each 16x16 tile, blend its pixels over the tile's
+ * range of the sorted pair list.  img is planar [3][H][W]; Tf [H][W];
+ * last [H][W] = entries of the tile list consumed by that pixel; w (nullable)
+ * accumulates per-Gaussian blend weights. */
+ORC_API void orc_composite(const uint32_t *gid_of, const uint32_t *ranges, const double *proj,
+                           int W, int H, const float *prmf, double *img, double *Tf,
+                           int32_t *last, double *w) {
+  prm_t pp = load_prm(prmf);
+  int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < tiles_x * tiles_y; ++t) {
+    int tx = t % tiles_x, ty = t / tiles_x;
+    uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+    for (int yy = 0; yy < 16; ++yy)
+      for (int xx = 0; xx < 16; ++xx) {
+        int x = tx * 16 + xx, y = ty * 16 + yy;
+        if (x >= W || y >= H) continue;
+        double c[3], T;
+        int l = blend_pixel(&pp, proj, gid_of + s, (int)(e - s), x + 0.5, y + 0.5, c, &T, w);
+        size_t pix = (size_t)y * W + x;
+        for (int a = 0; a < 3; ++a) img[(size_t)a * W * H + pix] = c[a];
+        Tf[pix] = T;
+        last[pix] = l;
+      }
+  }
+}
+
+typedef struct {
+  uint32_t dkey, gid;
+} dk_t;
+
+static int dk_cmp(const void *a, const void *b) {
+  const dk_t *p = a, *q = b;
+  if (p->dkey != q->dkey) return p->dkey < q->dkey ? -1 : 1;
+  return p->gid < q->gid ? -1 : (p->gid > q->gid);
+}
+
+/* Brute-force renderer: for every pixel, scan all Gaussians, keep those
+ * whose tile rectangle holds the pixel's tile, order them by (depth, index)
+ * and blend.  No pair list, no global sort. */
+ORC_API void orc_render_bruteforce(int64_t n, const uint8_t *vis, const int32_t *rect,
+                                   const float *depth, const double *proj, int W, int H,
+                                   const float *prmf, double *img, double *Tf) {
+  prm_t pp = load_prm(prmf);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = 0; y < H; ++y) {
+    dk_t *buf = (dk_t *)malloc(sizeof(dk_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    for (int x = 0; x < W; ++x) {
+      int tx = x / 16, ty = y / 16, m = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t *r = rect + 4 * i;
+        if (vis[i] && tx >= r[0] && tx < r[2] && ty >= r[1] && ty < r[3]) {
+          buf[m].dkey = fbits(depth[i]);
+          buf[m].gid = (uint32_t)i;
+          ++m;
+        }
+      }
+      qsort(buf, (size_t)m, sizeof(dk_t), dk_cmp);
+      for (int i = 0; i < m; ++i) lst[i] = buf[i].gid;
+      double c[3], T;
+      blend_pixel(&pp, proj, lst, m, x + 0.5, y + 0.5, c, &T, NULL);
+      size_t pix = (size_t)y * W + x;
+      for (int a = 0; a < 3; ++a) img[(size_t)a * W * H + pix] = c[a];
+      Tf[pix] = T;
+    }
+    free(buf);
+    free(lst);
+  }
+}
+
+ORC_API int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,251 @@
+"""Python shim over the plain C oracle (``octgs_oracle.c``).  TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this module.  It never imports the HIP package, and the HIP package never
+imports it.
+
+Conventions shared with the callers (not with the HIP code):
+  * a camera is passed as 18 float32 values: R (9, row-major world->camera),
+    C (3), fx, fy, cx, cy, z_near, s^2, plus the integer image size;
+  * raster parameters are 8 float32 values: alpha_max, alpha_min, t_min,
+    dilation (px^2), jac_clamp, background rgb;
+  * Gaussians are planar [14][n]: mean(3), scale(3), quat(w,x,y,z), opacity, rgb(3).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "octgs_oracle.c")
+_LIB = os.path.join(_HERE, "liboctgs_oracle.so")
+_lib = None
+
+DEFAULT_PARAMS = dict(alpha_max=0.99, alpha_min=0.0, t_min=1e-4, dilation=0.3,
+                      jac_clamp=1.3, bg=(0.0, 0.0, 0.0))
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no FP contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int
+
+
+def _declare(L):
+    L.orc_lod_thr2.argtypes = [_i64, _p, _p, ctypes.c_float, _p]
+    L.orc_bound_radius.argtypes = [_i64, _i32, _p, _p, _p, _p]
+    L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p]
+    L.orc_select_fp32.restype = _i64
+    L.orc_select_eq7.argtypes = [_i64, _p, _p, _p, ctypes.c_float, _i32, _p, _p, _i32, _i32, _p]
+    L.orc_select_eq7.restype = _i64
+    L.orc_decode.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
+                             ctypes.c_float, _p]
+    L.orc_project.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
+    L.orc_project.restype = _i64
+    L.orc_count_pairs.argtypes = [_i64, _p, _p]
+    L.orc_count_pairs.restype = _i64
+    L.orc_bin_sort.argtypes = [_i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_bin_sort.restype = _i64
+    L.orc_composite.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
+    L.orc_render_bruteforce.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_num_threads.restype = _i32
+    for name in ("orc_render_backward", "orc_decode_backward"):
+        if hasattr(L, name):
+            pass
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def cam_array(cam) -> np.ndarray:
+    return np.concatenate([cam.R.reshape(-1), cam.C.reshape(-1),
+                           [cam.fx, cam.fy, cam.cx, cam.cy, cam.z_near,
+                            cam.lod_scale * cam.lod_scale]]).astype(np.float32)
+
+
+def params_array(**kw) -> np.ndarray:
+    p = dict(DEFAULT_PARAMS)
+    p.update(kw)
+    return np.array([p["alpha_max"], p["alpha_min"], p["t_min"], p["dilation"],
+                     p["jac_clamp"], *p["bg"]], dtype=np.float32)
+
+
+# ----------------------------------------------------------------------------
+# selection
+# ----------------------------------------------------------------------------
+
+def lod_thr2(level, lod_bias, d_max) -> np.ndarray:
+    level = _c(level, np.uint8)
+    lod_bias = _c(lod_bias, np.float32)
+    out = np.empty(len(level), np.float32)
+    lib().orc_lod_thr2(len(level), _ptr(level), _ptr(lod_bias), float(d_max), _ptr(out))
+    return out
+
+
+def bound_radius(offsets, offset_scale, base_scale) -> np.ndarray:
+    offsets = _c(offsets, np.float32)
+    n, k = offsets.shape[0], offsets.shape[1]
+    out = np.empty(n, np.float32)
+    lib().orc_bound_radius(n, k, _ptr(offsets), _ptr(_c(offset_scale, np.float32)),
+                           _ptr(_c(base_scale, np.float32)), _ptr(out))
+    return out
+
+
+def select_mask(pos, thr2, rho, cam) -> np.ndarray:
+    pos = _c(pos, np.float32)
+    mask = np.empty(len(pos), np.uint8)
+    lib().orc_select_fp32(len(pos), _ptr(pos), _ptr(_c(thr2, np.float32)),
+                          _ptr(_c(rho, np.float32)), _ptr(cam_array(cam)), cam.width,
+                          cam.height, _ptr(mask))
+    return mask
+
+
+def select_eq7_mask(pos, level, lod_bias, d_max, n_levels, rho, cam) -> np.ndarray:
+    pos = _c(pos, np.float32)
+    mask = np.empty(len(pos), np.uint8)
+    lib().orc_select_eq7(len(pos), _ptr(pos), _ptr(_c(level, np.uint8)),
+                         _ptr(_c(lod_bias, np.float32)), float(d_max), int(n_levels),
+                         _ptr(_c(rho, np.float32)), _ptr(cam_array(cam)), cam.width,
+                         cam.height, _ptr(mask))
+    return mask
+
+
+def scene_thresholds(scene):
+    """(thr2, rho) of a synth.Scene."""
+    return (lod_thr2(scene.level, scene.lod_bias, scene.d_max),
+            bound_radius(scene.offsets, scene.offset_scale, scene.base_scale))
+
+
+def select(scene, cam, thr2=None, rho=None) -> np.ndarray:
+    """Ascending indices of the anchors selected for cam (canonical FP32 rule)."""
+    if thr2 is None or rho is None:
+        thr2, rho = scene_thresholds(scene)
+    return np.flatnonzero(select_mask(scene.pos, thr2, rho, cam)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# decode
+# ----------------------------------------------------------------------------
+
+MLP_ORDER = ("w1_a", "b1_a", "w2_a", "b2_a", "w1_c", "b1_c", "w2_c", "b2_c",
+             "w1_s", "b1_s", "w2_s", "b2_s")
+
+
+def decode(scene, idx, cam) -> np.ndarray:
+    """Double-precision decode of anchors idx: planar [14][len(idx) * k]."""
+    idx = _c(idx, np.int64)
+    m, k = len(idx), scene.k
+    keep = [_c(scene.mlp[name], np.float32) for name in MLP_ORDER]
+    arr = (ctypes.c_void_p * 12)(*[a.ctypes.data for a in keep])
+    out = np.empty((14, m * k), np.float64)
+    lib().orc_decode(m, _ptr(idx), _ptr(_c(scene.pos, np.float32)),
+                     _ptr(_c(scene.feat, np.float32)), _ptr(_c(scene.offsets, np.float32)),
+                     _ptr(_c(scene.offset_scale, np.float32)),
+                     _ptr(_c(scene.base_scale, np.float32)), k, scene.feat_dim,
+                     scene.width, arr, _ptr(cam.C), float(scene.d_max), _ptr(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# rasterizer
+# ----------------------------------------------------------------------------
+
+def project(gf: np.ndarray, cam, prm: np.ndarray, gd: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    gf = _c(gf, np.float32)
+    n = gf.shape[1]
+    gd = None if gd is None else _c(gd, np.float64)
+    vis = np.empty(n, np.uint8)
+    rect = np.empty((n, 4), np.int32)
+    depth = np.empty(n, np.float32)
+    proj = np.empty((n, 9), np.float64)
+    cnt = lib().orc_project(n, n, _ptr(gf), _ptr(gd), _ptr(cam_array(cam)), cam.width,
+                            cam.height, _ptr(_c(prm, np.float32)), _ptr(vis), _ptr(rect),
+                            _ptr(depth), _ptr(proj))
+    return dict(vis=vis, rect=rect, depth=depth, proj=proj, n_visible=int(cnt))
+
+
+def bin_sort(pj: Dict[str, np.ndarray], cam) -> Dict[str, np.ndarray]:
+    n = len(pj["vis"])
+    P = int(lib().orc_count_pairs(n, _ptr(pj["vis"]), _ptr(pj["rect"])))
+    tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    tile_of = np.empty(max(P, 1), np.uint32)
+    gid_of = np.empty(max(P, 1), np.uint32)
+    ranges = np.empty((tiles, 2), np.uint32)
+    lib().orc_bin_sort(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["depth"]), cam.width,
+                       cam.height, _ptr(tile_of), _ptr(gid_of), _ptr(ranges))
+    return dict(tile_of=tile_of[:P], gid_of=gid_of[:P], ranges=ranges, n_pairs=P)
+
+
+def composite(pj, bs, cam, prm, weights: bool = False):
+    W, H = cam.width, cam.height
+    img = np.empty((3, H, W), np.float64)
+    Tf = np.empty((H, W), np.float64)
+    last = np.empty((H, W), np.int32)
+    w = np.zeros(len(pj["vis"]), np.float64) if weights else None
+    gid = bs["gid_of"] if bs["n_pairs"] > 0 else np.zeros(1, np.uint32)
+    lib().orc_composite(_ptr(gid), _ptr(bs["ranges"]), _ptr(pj["proj"]), W, H,
+                        _ptr(_c(prm, np.float32)), _ptr(img), _ptr(Tf), _ptr(last), _ptr(w))
+    return dict(img=img, T=Tf, last=last, weights=w)
+
+
+def render_bruteforce(pj, cam, prm):
+    W, H = cam.width, cam.height
+    img = np.empty((3, H, W), np.float64)
+    Tf = np.empty((H, W), np.float64)
+    n = len(pj["vis"])
+    lib().orc_render_bruteforce(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["depth"]),
+                                _ptr(pj["proj"]), W, H, _ptr(_c(prm, np.float32)), _ptr(img),
+                                _ptr(Tf))
+    return dict(img=img, T=Tf)
+
+
+def rasterize(gf, cam, prm, gd=None, weights=False):
+    """Project, bin, sort and composite planar Gaussians (float decisions,
+    double continuous values)."""
+    pj = project(gf, cam, prm, gd)
+    bs = bin_sort(pj, cam)
+    out = composite(pj, bs, cam, prm, weights=weights)
+    out.update(pj=pj, bs=bs)
+    return out
+
+
+def render(scene, cam, prm, thr2=None, rho=None, weights=False):
+    """Full path for one view: select, decode, rasterize."""
+    idx = select(scene, cam, thr2, rho)
+    gd = decode(scene, idx, cam)
+    out = rasterize(gd.astype(np.float32), cam, prm, gd=gd, weights=weights)
+    out.update(idx=idx, gauss=gd)
+    return out

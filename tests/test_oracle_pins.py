@@ -1,0 +1,427 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests touches the HIP library.  Each one checks the oracle
+against something other than its own code: closed-form images, brute force,
+invariants of Eq. 2 and Eq. 7, and hand-evaluable special cases of the decode
+MLPs.  The paper prints no worked numeric example, so closed forms stand in
+for one.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from synth import scenes as S
+
+F32 = np.float32
+
+
+def ident_cam(W=64, H=64, f=80.0, C=(0.0, 0.0, 0.0)):
+    return S.Camera(R=np.eye(3), C=np.asarray(C, np.float64), fx=f, fy=f, cx=W / 2, cy=H / 2,
+                    width=W, height=H)
+
+
+def gauss(mean, scale, quat=(1, 0, 0, 0), op=0.8, rgb=(0.2, 0.5, 0.9)):
+    g = np.array([*mean, *scale, *quat, op, *rgb], np.float32).reshape(14, 1)
+    return g
+
+
+def cat(*gs):
+    return np.ascontiguousarray(np.concatenate(gs, axis=1))
+
+
+def pix_grid(W, H):
+    x = np.arange(W) + 0.5
+    y = np.arange(H) + 0.5
+    return np.meshgrid(x, y)
+
+
+def tile_mask(W, H, x0, y0, x1, y1):
+    X, Y = np.meshgrid(np.arange(W) // 16, np.arange(H) // 16)
+    return (X >= x0) & (X < x1) & (Y >= y0) & (Y < y1)
+
+
+# --------------------------------------------------------------------------
+# Eq. 1 / EWA projection / Eq. 2 closed forms
+# --------------------------------------------------------------------------
+
+def closed_form_axis_cov(cam, m, s, dil):
+    """2D covariance of an axis-aligned Gaussian seen by an identity-rotation
+    camera: J diag(s^2) J^T + dil I with J the perspective Jacobian at m."""
+    f = float(cam.fx)
+    x, y, z = (float(v) for v in m)
+    sx, sy, sz = (float(v) ** 2 for v in s)
+    a = f * f * sx / z ** 2 + f * f * x * x * sz / z ** 4 + dil
+    b = f * f * x * y * sz / z ** 4
+    c = f * f * sy / z ** 2 + f * f * y * y * sz / z ** 4 + dil
+    return a, b, c
+
+
+@pytest.mark.parametrize("mean", [(0.0, 0.0, 10.0), (1.3, -0.7, 9.0), (-2.0, 1.5, 14.0)])
+def test_single_gaussian_closed_form(orc, mean):
+    cam = ident_cam()
+    prm = orc.params_array()
+    dil = float(F32(0.3))
+    s = np.array([0.35, 0.2, 0.5], np.float32)
+    g = gauss(mean, s, op=0.7)
+    m32 = g[:3, 0].astype(np.float64)
+    out = orc.rasterize(g, cam, prm)
+    a, b, c = closed_form_axis_cov(cam, m32, g[3:6, 0].astype(np.float64), dil)
+    det = a * c - b * b
+    mx = cam.fx * m32[0] / m32[2] + cam.cx
+    my = cam.fy * m32[1] / m32[2] + cam.cy
+    X, Y = pix_grid(cam.width, cam.height)
+    dx, dy = X - mx, Y - my
+    G = np.exp(-0.5 * (c * dx * dx - 2 * b * dx * dy + a * dy * dy) / det)
+    alpha = np.minimum(0.99, float(g[10, 0]) * G)
+    lam = 0.5 * (a + c) + math.sqrt(max(0.25 * (a - c) ** 2 + b * b, 0))
+    r = math.ceil(3 * math.sqrt(lam))
+    tx0, tx1 = max(0, math.floor((mx - r) / 16)), min(4, math.floor((mx + r) / 16) + 1)
+    ty0, ty1 = max(0, math.floor((my - r) / 16)), min(4, math.floor((my + r) / 16) + 1)
+    inside = tile_mask(cam.width, cam.height, tx0, ty0, tx1, ty1)
+    assert tuple(out["pj"]["rect"][0]) == (tx0, ty0, tx1, ty1)
+    for ch in range(3):
+        exp_img = np.where(inside, alpha * float(g[11 + ch, 0]), 0.0)
+        np.testing.assert_allclose(out["img"][ch], exp_img, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(out["T"], np.where(inside, 1 - alpha, 1.0), rtol=1e-9, atol=1e-12)
+    # conic is the inverse of the closed-form 2D covariance
+    p = out["pj"]["proj"][0]
+    np.testing.assert_allclose(p[2:5], [c / det, -b / det, a / det], rtol=1e-9)
+
+
+def test_rotation_swaps_axes(orc):
+    """A 90-degree turn about the viewing axis swaps the x and y scales; a
+    90-degree turn about x swaps y and z (checks R(q) and Sigma = R S S^T R^T)."""
+    cam = ident_cam()
+    prm = orc.params_array()
+    h = math.sqrt(0.5)
+    m = (0.4, -0.3, 8.0)
+    ref = orc.rasterize(gauss(m, (0.2, 0.45, 0.3)), cam, prm)["img"]
+    rot = orc.rasterize(gauss(m, (0.45, 0.2, 0.3), quat=(h, 0, 0, h)), cam, prm)["img"]
+    np.testing.assert_allclose(rot, ref, atol=1e-6)
+    ref2 = orc.rasterize(gauss(m, (0.3, 0.25, 0.4)), cam, prm)["img"]
+    rot2 = orc.rasterize(gauss(m, (0.3, 0.4, 0.25), quat=(h, h, 0, 0)), cam, prm)["img"]
+    np.testing.assert_allclose(rot2, ref2, atol=1e-6)
+
+
+def test_two_gaussians_front_to_back(orc):
+    """C = a1 c1 + (1 - a1) a2 c2 + (1 - a1)(1 - a2) bg, nearer first,
+    whatever their index order."""
+    cam = ident_cam()
+    bg = (0.1, 0.2, 0.3)
+    prm = orc.params_array(bg=bg)
+    far = gauss((0.0, 0.0, 12.0), (0.5, 0.5, 0.5), op=0.6, rgb=(1.0, 0.0, 0.0))
+    near = gauss((0.1, 0.0, 6.0), (0.2, 0.2, 0.2), op=0.5, rgb=(0.0, 1.0, 0.5))
+    out = orc.rasterize(cat(far, near), cam, prm)
+    dil = float(F32(0.3))
+    X, Y = pix_grid(cam.width, cam.height)
+
+    def alpha(g):
+        m = g[:3, 0].astype(np.float64)
+        a, b, c = closed_form_axis_cov(cam, m, g[3:6, 0].astype(np.float64), dil)
+        det = a * c - b * b
+        dx = X - (cam.fx * m[0] / m[2] + cam.cx)
+        dy = Y - (cam.fy * m[1] / m[2] + cam.cy)
+        G = np.exp(-0.5 * (c * dx * dx - 2 * b * dx * dy + a * dy * dy) / det)
+        return np.minimum(0.99, float(g[10, 0]) * G)
+
+    a1, a2 = alpha(near), alpha(far)
+    r1 = out["pj"]["rect"][1]
+    r2 = out["pj"]["rect"][0]
+    in1 = tile_mask(64, 64, *r1)
+    in2 = tile_mask(64, 64, *r2)
+    a1 = np.where(in1, a1, 0)
+    a2 = np.where(in2, a2, 0)
+    for ch in range(3):
+        c1, c2 = float(near[11 + ch, 0]), float(far[11 + ch, 0])
+        exp_img = a1 * c1 + (1 - a1) * a2 * c2 + (1 - a1) * (1 - a2) * float(F32(bg[ch]))
+        np.testing.assert_allclose(out["img"][ch], exp_img, rtol=1e-9, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Compositing invariants and brute force
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,n,seed", [(64, 48, 300, 1), (50, 37, 500, 2), (33, 17, 80, 3)])
+def test_bruteforce_equals_tiled(orc, W, H, n, seed):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
+    g = S.random_gaussians(n, cam, seed, neg_opacity_frac=0.1, behind_frac=0.05)
+    prm = orc.params_array()
+    out = orc.rasterize(g, cam, prm)
+    bf = orc.render_bruteforce(out["pj"], cam, prm)
+    assert out["bs"]["n_pairs"] > n // 4
+    assert np.array_equal(bf["img"], out["img"])
+    assert np.array_equal(bf["T"], out["T"])
+
+
+def test_partition_of_unity_and_weights(orc):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), 64, 64, 60.0)
+    g = S.random_gaussians(800, cam, 5)
+    g[11:14] = 1.0
+    prm = orc.params_array()
+    out = orc.rasterize(g, cam, prm, weights=True)
+    T = out["T"]
+    assert np.all(T > 0) and np.all(T <= 1)
+    for ch in range(3):
+        np.testing.assert_allclose(out["img"][ch] + T, 1.0, atol=1e-12)
+    np.testing.assert_allclose(out["weights"].sum(), (1 - T).sum(), rtol=1e-10)
+    # a pixel that stops before the end of its tile list went below t_min
+    rng = out["bs"]["ranges"]
+    tiles_x = 4
+    for y in range(64):
+        for x in range(64):
+            t = (y // 16) * tiles_x + x // 16
+            n_list = int(rng[t, 1] - rng[t, 0])
+            if out["last"][y, x] < n_list:
+                assert T[y, x] < 1e-4
+
+
+def test_transmittance_monotone(orc):
+    """T after each prefix of a pixel's list is non-increasing: rendering the
+    first j Gaussians (front-most) of the depth order gives T_j >= T_{j+1}."""
+    cam = ident_cam(32, 32, 40.0)
+    rng = np.random.default_rng(4)
+    gs = []
+    for i in range(12):
+        gs.append(gauss((rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), 4.0 + i),
+                        rng.uniform(0.3, 1.0, 3), op=rng.uniform(0.1, 0.9)))
+    prm = orc.params_array(t_min=0.0)
+    prev = np.ones((32, 32))
+    for j in range(1, 13):
+        T = orc.rasterize(cat(*gs[:j]), cam, prm)["T"]
+        assert np.all(T <= prev + 1e-15) and np.all(T >= 0)
+        prev = T
+
+
+def test_bin_sort_against_enumeration(orc):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), 80, 70, 60.0)
+    g = S.random_gaussians(400, cam, 9)
+    prm = orc.params_array()
+    pj = orc.project(g, cam, prm)
+    bs = orc.bin_sort(pj, cam)
+    tx = (80 + 15) // 16
+    rows = []
+    for i in np.flatnonzero(pj["vis"]):
+        x0, y0, x1, y1 = pj["rect"][i]
+        for y in range(y0, y1):
+            for x in range(x0, x1):
+                rows.append((y * tx + x, pj["depth"][i].view(np.uint32), i))
+    rows = np.array(rows, dtype=np.int64)
+    order = np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))
+    rows = rows[order]
+    assert bs["n_pairs"] == len(rows)
+    assert np.array_equal(bs["tile_of"], rows[:, 0])
+    assert np.array_equal(bs["gid_of"], rows[:, 2])
+    for t in range(bs["ranges"].shape[0]):
+        s, e = bs["ranges"][t]
+        assert np.all(rows[s:e, 0] == t)
+        assert np.count_nonzero(rows[:, 0] == t) == e - s
+
+
+def test_equal_depth_tie_break(orc):
+    cam = ident_cam(64, 64, 60.0)
+    g = S.tile_aligned_gaussians(cam, [5.0] * 6 + [7.0] * 6, seed=3)
+    pj = orc.project(g, cam, orc.params_array())
+    bs = orc.bin_sort(pj, cam)
+    for t in range(bs["ranges"].shape[0]):
+        s, e = bs["ranges"][t]
+        ids = bs["gid_of"][s:e]
+        d = pj["depth"][ids]
+        for i in range(len(ids) - 1):
+            assert d[i] < d[i + 1] or (d[i] == d[i + 1] and ids[i] < ids[i + 1])
+
+
+# --------------------------------------------------------------------------
+# Eq. 7 selection
+# --------------------------------------------------------------------------
+
+def test_thr2_closed_form(orc):
+    """With Delta L = 0: thr2 = fl(d_max^2) / 4^L exactly, +inf at level 0."""
+    level = np.arange(10, dtype=np.uint8)
+    d_max = 1463.6878662109375
+    thr = orc.lod_thr2(level, np.zeros(10, np.float32), d_max)
+    assert np.isinf(thr[0])
+    sq = F32(d_max) * F32(d_max)
+    for L in range(1, 10):
+        assert thr[L] == F32(sq * F32(2.0 ** (-2 * L)))
+
+
+def _random_anchor_set(rng, n, K):
+    pos = rng.uniform(-60, 60, (n, 3)).astype(np.float32)
+    level = rng.integers(0, K, n).astype(np.uint8)
+    bias = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    rho = np.full(n, 1e6, np.float32)  # visibility always true
+    return pos, level, bias, rho
+
+
+def test_threshold_form_matches_literal_eq7(orc):
+    """The transcendental-free FP32 rule equals the literal
+    floor(clamp(log2(d_max / (d s)) + Delta L)) rule except within rounding
+    distance of a threshold."""
+    rng = np.random.default_rng(11)
+    K, d_max = 6, 150.0
+    pos, level, bias, rho = _random_anchor_set(rng, 200_000, K)
+    cam = S.look_at((5.0, -7.0, 3.0), (0.0, 0.0, 0.0), 256, 256, 60.0)
+    thr = orc.lod_thr2(level, bias, d_max)
+    a = orc.select_mask(pos, thr, rho, cam)
+    b = orc.select_eq7_mask(pos, level, bias, d_max, K, rho, cam)
+    diff = np.flatnonzero(a != b)
+    d = np.linalg.norm(pos.astype(np.float64) - cam.C.astype(np.float64), axis=1)
+    lim = float(F32(d_max)) * 2.0 ** (bias.astype(np.float64) - level)
+    for j in diff:
+        assert level[j] > 0 and abs(d[j] / lim[j] - 1) < 1e-5
+    assert len(diff) <= 3
+    # both readings of the clamp agree when Delta L = 0
+    z = np.zeros_like(bias)
+    a0 = orc.select_mask(pos, orc.lod_thr2(level, z, d_max), rho, cam)
+    b0 = orc.select_eq7_mask(pos, level, z, d_max, K, rho, cam)
+    assert np.count_nonzero(a0 != b0) <= 3
+
+
+def test_level_monotone_in_distance(orc):
+    """Along a ray from the camera, the anchors of each level that pass Eq. 7
+    form a prefix (near ones pass, far ones do not)."""
+    cam = S.look_at((0.0, 0.0, 0.0), (1.0, 0.3, 0.2), 64, 64, 60.0)
+    dirv = cam.R[2].astype(np.float64)
+    t = np.linspace(0.5, 400, 2000)
+    K, d_max = 8, 300.0
+    for L in range(K):
+        pos = (t[:, None] * dirv[None, :]).astype(np.float32)
+        level = np.full(len(t), L, np.uint8)
+        thr = orc.lod_thr2(level, np.zeros(len(t), np.float32), d_max)
+        m = orc.select_mask(pos, thr, np.full(len(t), 1e6, np.float32), cam).astype(bool)
+        k = np.argmin(m) if not m.all() else len(m)
+        assert m[:k].all() and not m[k:].any()
+        if L > 0:
+            assert abs(t[k - 1] - d_max / 2 ** L) < 0.25 or abs(t[k] - d_max / 2 ** L) < 0.25
+
+
+def test_cumulative_levels_nested(orc):
+    """Cumulative LOD: wherever a level-L anchor is selected, anchors of every
+    coarser level at the same place are selected too."""
+    rng = np.random.default_rng(3)
+    K = 7
+    base = rng.uniform(-80, 80, (3000, 3)).astype(np.float32)
+    pos = np.repeat(base, K, axis=0)
+    level = np.tile(np.arange(K, dtype=np.uint8), 3000)
+    cam = S.look_at((1.0, -2.0, 3.0), (0.0, 0.0, 0.0), 64, 64, 60.0)
+    thr = orc.lod_thr2(level, np.zeros(len(level), np.float32), 200.0)
+    m = orc.select_mask(pos, thr, np.full(len(level), 1e6, np.float32), cam).reshape(3000, K)
+    assert m[:, 0].all()
+    assert np.all(np.diff(m.astype(np.int8), axis=1) <= 0)
+    assert m[:, 1:].any() and not m.all()
+
+
+def test_all_levels_render_equals_flat_render(orc):
+    sc = S.make_config1()
+    cam = S.config1_camera()
+    prm = orc.params_array()
+    rho = orc.bound_radius(sc.offsets, sc.offset_scale, sc.base_scale)
+    thr_all = orc.lod_thr2(sc.level, sc.lod_bias, 1e30)
+    a = orc.render(sc, cam, prm, thr2=thr_all, rho=rho)
+    flat = np.full(sc.n, np.inf, np.float32)
+    b = orc.render(sc, cam, prm, thr2=flat, rho=rho)
+    assert np.array_equal(a["idx"], b["idx"])
+    assert np.array_equal(a["img"], b["img"])
+    assert len(a["idx"]) > len(orc.select(sc, cam))
+
+
+def test_bound_radius_covers_decoded_gaussians(orc):
+    sc = S.make_config1()
+    cam = S.config1_camera()
+    rho = orc.bound_radius(sc.offsets, sc.offset_scale, sc.base_scale)
+    idx = np.arange(0, sc.n, 7)
+    gd = orc.decode(sc, idx, cam)
+    mean = gd[0:3].T.reshape(len(idx), sc.k, 3)
+    smax = gd[3:6].max(axis=0).reshape(len(idx), sc.k)
+    reach = np.linalg.norm(mean - sc.pos[idx][:, None, :].astype(np.float64), axis=2) + 3 * smax
+    assert np.all(reach <= rho[idx][:, None].astype(np.float64) * (1 + 1e-6))
+
+
+# --------------------------------------------------------------------------
+# Eq. 3 / Eq. 4 decode special cases
+# --------------------------------------------------------------------------
+
+def tiny_scene(F=32, W=8, k=2, n=3, seed=0):
+    rng = np.random.default_rng(seed)
+    pos = np.array([[3.0, 4.0, 0.0], [0.0, 0.0, 2.0], [-1.0, 2.0, 2.0]], np.float32)[:n]
+    mlp = S.xavier_mlp(rng, F + 4, W, k)
+    for key in mlp:
+        mlp[key][:] = 0
+    sc = S.Scene(pos=pos, level=np.zeros(n, np.uint8), lod_bias=np.zeros(n, np.float32),
+                 feat=rng.standard_normal((n, F)).astype(np.float32),
+                 offsets=rng.standard_normal((n, k, 3)).astype(np.float32),
+                 offset_scale=rng.uniform(0.5, 2, (n, 3)).astype(np.float32),
+                 base_scale=rng.uniform(0.1, 1, (n, 3)).astype(np.float32), mlp=mlp,
+                 d_max=10.0, d_min=1.0, n_levels=1, delta=1.0, k=k, feat_dim=F, width=W,
+                 info={})
+    cam = ident_cam()
+    return sc, cam
+
+
+def sig(x):
+    return 1 / (1 + math.exp(-x))
+
+
+def test_decode_biases_only(orc):
+    """All weights zero: every output is its bias through its activation."""
+    sc, cam = tiny_scene()
+    k = sc.k
+    sc.mlp["b2_a"][:] = [0.3, -0.2]
+    sc.mlp["b2_c"][:] = np.arange(3 * k) * 0.1 - 0.2
+    b2s = np.zeros(7 * k, np.float32)
+    b2s[0:3] = [0.5, -1.0, 2.0]
+    b2s[3:7] = [0.0, 3.0, 0.0, 4.0]        # quaternion (0, .6, 0, .8)
+    b2s[7:10] = [0.0, 0.0, 0.0]
+    b2s[10:14] = [0.0, 0.0, 0.0, 0.0]      # zero quaternion -> identity
+    sc.mlp["b2_s"][:] = b2s
+    gd = orc.decode(sc, np.arange(3), cam)
+    G = 3 * k
+    for s in range(3):
+        for i in range(k):
+            g = s * k + i
+            np.testing.assert_allclose(gd[10, g], math.tanh(sc.mlp["b2_a"][i]), rtol=1e-15)
+            for c in range(3):
+                np.testing.assert_allclose(gd[11 + c, g], sig(sc.mlp["b2_c"][3 * i + c]), rtol=1e-15)
+                np.testing.assert_allclose(gd[3 + c, g], float(sc.base_scale[s, c]) * sig(b2s[7 * i + c]),
+                                           rtol=1e-15)
+                exp_mean = float(sc.pos[s, c]) + float(sc.offsets[s, i, c]) * float(sc.offset_scale[s, c])
+                np.testing.assert_allclose(gd[c, g], exp_mean, rtol=1e-15)
+        np.testing.assert_allclose(gd[6:10, s * k], [0, 0.6, 0, 0.8], atol=1e-15)
+        np.testing.assert_allclose(gd[6:10, s * k + 1], [1, 0, 0, 0], atol=0)
+    assert gd.shape == (14, G)
+
+
+def test_decode_input_distance_and_direction(orc):
+    """Route inputs F..F+3 (relative distance, direction) straight to the
+    opacity of Gaussian 0 and 1 through identity-like weights: the anchor
+    at (3, 4, 0) seen from the origin with d_max = 10 has relative distance
+    0.5 and direction (0.6, 0.8, 0)."""
+    sc, cam = tiny_scene()
+    F = sc.feat_dim
+    w1 = sc.mlp["w1_a"]
+    w1[F + 0, 0] = 1.0   # hidden 0 = relu(dist / d_max)
+    w1[F + 2, 1] = 1.0   # hidden 1 = relu(dir_y)
+    w1[F + 1, 2] = -1.0  # hidden 2 = relu(-dir_x) -> 0 for this anchor
+    w2 = sc.mlp["w2_a"]
+    w2[0, 0] = 1.0
+    w2[1, 1] = 1.0
+    w2[2, 1] = 5.0
+    gd = orc.decode(sc, np.array([0]), cam)
+    np.testing.assert_allclose(gd[10, 0], math.tanh(0.5), rtol=1e-15)
+    np.testing.assert_allclose(gd[10, 1], math.tanh(0.8), rtol=1e-14)
+
+
+def test_decode_relu_and_feature_path(orc):
+    """A hidden unit fed feature 0 with weight 1 and bias -b: the output is
+    relu(f0 - b) times the second-layer weight."""
+    sc, cam = tiny_scene()
+    sc.mlp["w1_c"][0, 3] = 1.0
+    sc.mlp["b1_c"][3] = 0.25
+    sc.mlp["w2_c"][3, 4] = 2.0
+    gd = orc.decode(sc, np.arange(3), cam)
+    for s in range(3):
+        h = max(float(sc.feat[s, 0]) + 0.25, 0.0)
+        # output 4 = Gaussian 1, green channel
+        np.testing.assert_allclose(gd[12, s * sc.k + 1], sig(2.0 * h), rtol=1e-14)
