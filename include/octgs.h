@@ -1,0 +1,222 @@
+/*
+ * octgs.h - C ABI of the Octree-GS render path for AMD MI355X (gfx950).
+ *
+ * The library renders one view of an anchor-based, octree-structured set of
+ * neural Gaussians (Octree-GS, arXiv 2403.17898) in five stages, each a
+ * hand-written HIP kernel sequence:
+ *   1. octgs_select_lod     - visible anchors at the level set by Eq. 7;
+ *   2. octgs_decode         - k neural Gaussians per selected anchor (Eq. 3, Eq. 4);
+ *   3-5. octgs_rasterize_fwd - EWA projection, 16x16 tile binning with depth
+ *                             order, front-to-back alpha blending (Eq. 2);
+ * plus the backward passes used for training and the anchor-skip predictor.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* or documented "device" are device memory owned by the
+ *    caller; the library never allocates, frees or retains them after return.
+ *    Host structs (octgs_camera, octgs_anchors, ...) are read during the call
+ *    only.
+ *  - Every call only enqueues work on `stream` (a hipStream_t passed as
+ *    void*, NULL = the null stream) and returns without synchronising.
+ *    Element counts produced on the device (selected anchors, Gaussians,
+ *    pairs) stay on the device; kernels read them from device scalars.
+ *  - Return value: OCTGS_OK, or a negative octgs_status when host-side
+ *    argument validation fails (nothing is enqueued then), or OCTGS_EHIP if a
+ *    launch reports an error.  Device-detected conditions (pair-list
+ *    overflow, a look-back wait that exceeded its bound) are reported in
+ *    octgs_raster_stats, readable once the stream has passed the call.
+ *  - Layouts are structure-of-arrays unless stated; "planar [F][cap]" means
+ *    field f of slot i at index f * cap + i.
+ */
+#ifndef OCTGS_H
+#define OCTGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define OCTGS_API __attribute__((visibility("default")))
+#else
+#define OCTGS_API
+#endif
+
+typedef void *octgs_stream; /* hipStream_t */
+
+typedef enum {
+  OCTGS_OK = 0,
+  OCTGS_EINVAL = -1,      /* bad argument (null pointer, size, range) */
+  OCTGS_ENOSPC = -2,      /* workspace smaller than octgs_*_workspace_bytes */
+  OCTGS_EHIP = -3,        /* a HIP launch or runtime call failed */
+  OCTGS_EUNSUPPORTED = -4 /* shape outside what the kernels implement */
+} octgs_status;
+
+typedef enum {
+  OCTGS_FP32 = 0, /* plain path: FP32 inputs, FP32 MFMA, FP32 activations */
+  OCTGS_BF16 = 1  /* fast path: BF16 features and weights on MFMA, FP32 accumulation */
+} octgs_precision;
+
+/* Pinhole camera.  Camera-space point = R (p - C); x right, y down, z forward.
+ * Pixel (i, j) is sampled at (i + 0.5, j + 0.5).  lod_scale2 is s^2, the
+ * squared focal scale factor s of Eq. 7 (Sec. IV-A, "Anchor Selection"). */
+typedef struct {
+  float R[9];  /* row-major world->camera rotation */
+  float C[3];  /* camera centre, world */
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;
+  float lod_scale2;
+} octgs_camera;
+
+/* Anchor set (Sec. IV-A): anchors of all octree levels in one flat array.
+ * All pointers are device memory. */
+typedef struct {
+  int64_t n;                 /* anchor count, < 2^31 */
+  int32_t k;                 /* neural Gaussians per anchor, 1..16 */
+  int32_t feat_dim;          /* anchor feature width; must be 32 */
+  int32_t n_levels;          /* octree depth K; level values are 0..K-1 */
+  float d_max;               /* the distance quantile d_max of Eq. 5 / Eq. 7 */
+  const float *pos;          /* [n][3] anchor position x_v */
+  const uint8_t *level;      /* [n] octree level L_v */
+  const float *lod_bias;     /* [n] learnable LOD bias Delta L_v */
+  const float *feat;         /* [n][feat_dim] FP32 feature (plain path) */
+  const uint16_t *feat_bf16; /* [n][feat_dim] BF16 bit patterns (BF16 path), may be NULL otherwise */
+  const float *offsets;      /* [n][k][3] offsets O_i of Eq. 3 */
+  const float *offset_scale; /* [n][3] scaling l_v of Eq. 3 */
+  const float *base_scale;   /* [n][3] upper bound of each decoded Gaussian scale */
+  const float *thr2;         /* [n] from octgs_prepare_anchors */
+  const float *bound_r;      /* [n] from octgs_prepare_anchors */
+} octgs_anchors;
+
+/* The three decoding MLPs of Eq. 4 (Sec. III-B): head 0 opacity (k outputs),
+ * head 1 colour (3k), head 2 covariance (7k: per Gaussian 3 scale logits then
+ * a quaternion w, x, y, z).  Each head is Linear(in, width) -> ReLU ->
+ * Linear(width, out) with in = feat_dim + 4 (feature, relative distance,
+ * viewing direction).  w1 is [in][width], w2 is [width][out], row-major,
+ * FP32, device memory; the BF16 path rounds them to BF16 itself. */
+typedef struct {
+  int32_t width; /* hidden width, 16..64, multiple of 16 */
+  const float *w1[3], *b1[3], *w2[3], *b2[3];
+} octgs_mlp;
+
+/* Decoded neural Gaussians, planar [14][capacity] FP32 in the field order
+ * mean(3), scale(3), quat(w, x, y, z), opacity, rgb(3).  Slot s*k + i holds
+ * Gaussian i of the s-th listed anchor.  *count (device) is the number of
+ * slots written by octgs_decode and read by octgs_rasterize_fwd. */
+typedef struct {
+  int64_t capacity;
+  float *data;
+  uint32_t *count;
+} octgs_gaussians;
+
+/* Rasterizer constants.  alpha_max clamps each per-pixel alpha; entries with
+ * alpha below alpha_min are skipped; a pixel stops after the Gaussian that
+ * takes its transmittance below t_min; dilation (px^2) is added to the
+ * diagonal of every 2D covariance; jac_clamp limits |x/z| and |y/z| in the
+ * projection Jacobian to jac_clamp times the half-image tangent; bg is the
+ * background added with the final transmittance. */
+typedef struct {
+  float alpha_max, alpha_min, t_min, dilation, jac_clamp;
+  float bg[3];
+} octgs_raster_params;
+
+#define OCTGS_RASTER_STAGES 5
+
+/* Counters the rasterizer leaves at byte 0 of its workspace. */
+typedef struct {
+  uint32_t n_slots;       /* Gaussian slots read (min(*count, capacity)) */
+  uint32_t n_visible;     /* slots that survived the projection culls */
+  uint32_t n_pairs;       /* (tile, Gaussian) pairs needed */
+  uint32_t pair_overflow; /* 1 if n_pairs exceeded the pair capacity (image incomplete) */
+  uint32_t sync_error;    /* 1 if a radix-sort look-back wait hit its bound (output invalid) */
+  uint32_t reserved[11];
+} octgs_raster_stats;
+
+/* ---------------------------------------------------------------------- */
+
+/* Per-scene preparation for Eq. 7 (Sec. IV-A, "Anchor Selection").
+ * thr2[j] = (d_max * 2^(lod_bias[j] - level[j]))^2 rounded once to FP32
+ * (evaluated in double), +inf for level 0: the anchor passes the LOD rule
+ * iff |x_v - C|^2 s^2 <= thr2 (the clamp of Eq. 7 applied to the sum of the
+ * log term and Delta L).  bound_r[j] = max_i |O_i * l_v| + 3 max(base_scale),
+ * a sphere around x_v that holds the 3-sigma extent of every Gaussian the
+ * anchor can decode.  Reads pos-independent fields of `a` (level, lod_bias,
+ * offsets, offset_scale, base_scale, d_max); a->thr2 / a->bound_r are
+ * ignored.  Outputs: device [n] each. */
+OCTGS_API int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
+                          octgs_stream stream);
+
+/* Workspace bytes octgs_select_lod needs for n anchors. */
+OCTGS_API size_t octgs_select_workspace_bytes(int64_t n);
+
+/* Anchor selection (Eq. 7 and the cumulative rule L_v <= L_hat, Sec. IV-A):
+ * anchor j is selected iff its bound sphere intersects the view frustum
+ * (near plane and the four side planes) and |x_v - C|^2 s^2 <= thr2[j].
+ * Every decision is taken in FP32 by a fixed operation order.  Outputs:
+ * sel_idx (device, capacity n) receives the selected indices in ascending
+ * order; *sel_count (device) their number.  ws: device, >= the size above. */
+OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
+                     uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream);
+
+/* Neural-Gaussian decode (Eq. 3 and Eq. 4, Sec. III-B) of the first
+ * min(*count, out->capacity / k) anchors listed in idx (device).  Network
+ * input x = [feature, |x_v - C| / d_max, (x_v - C) / |x_v - C|]; outputs
+ * opacity = tanh, rgb = sigmoid, scale = base_scale * sigmoid, quaternion
+ * normalised (identity when its norm is 0), mean = x_v + O_i * l_v.  A
+ * Gaussian with opacity <= 0 is written and later culled by the rasterizer.
+ * precision selects the FP32 or the BF16 (needs a->feat_bf16) MFMA path.
+ * Writes out->data and *out->count (device). */
+OCTGS_API int octgs_decode(const octgs_anchors *a, const octgs_mlp *mlp, const octgs_camera *cam,
+                 const uint32_t *idx, const uint32_t *count, int precision,
+                 const octgs_gaussians *out, octgs_stream stream);
+
+/* Workspace bytes of octgs_rasterize_fwd / _bwd for a Gaussian-slot capacity,
+ * a (tile, Gaussian) pair capacity and an image size. */
+OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pair_capacity,
+                                    int32_t width, int32_t height);
+
+/* Forward rasterization of *g->count Gaussians (Sec. III-A: EWA projection,
+ * tile-based front-to-back depth order, Eq. 2 blending):
+ *  - cull: opacity <= 0, camera z <= z_near, 2D covariance not positive
+ *    definite, or a 3-sigma rectangle outside the image;
+ *  - bin into 16x16 tiles and order each tile's list by camera-space depth
+ *    of the Gaussian centre, ties by slot index;
+ *  - per pixel: a_i = min(alpha_max, opacity_i * G'_i(x')), C = sum T_i a_i c_i,
+ *    T_i = prod_{j<i} (1 - a_j), stop after T < t_min, add T * bg.
+ * Outputs (device): rgb planar [3][H][W]; T_final [H][W]; last [H][W] = list
+ * entries the pixel consumed (needed by the backward pass); gauss_w (nullable,
+ * [g->capacity]) = per-slot sum over pixels of a_i T_i (blend-weight log).
+ * The workspace keeps the sorted lists for octgs_rasterize_bwd and starts
+ * with octgs_raster_stats.  stage_events (nullable): 2 * OCTGS_RASTER_STAGES
+ * hipEvent_t created by the caller; events 2s and 2s+1 are recorded on
+ * `stream` around stage s (0 project + compaction, 1 depth sort, 2 pair
+ * emission, 3 tile sort + ranges, 4 composite) for per-stage timing. */
+OCTGS_API int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
+                        const octgs_raster_params *p, int64_t pair_capacity, float *rgb,
+                        float *T_final, uint32_t *last, float *gauss_w, void *ws,
+                        size_t ws_bytes, void *const *stage_events, octgs_stream stream);
+
+/* Device pointers into a rasterizer workspace (as laid out for these
+ * capacities and image size) to the state octgs_rasterize_fwd leaves there:
+ * the stats header, the sorted pair list (tile id and slot per entry, length
+ * n_pairs when pair_overflow is 0) and the per-tile ranges [tiles][2] =
+ * [start, end).  Read-only views; valid until the workspace is reused.
+ * Needs no HIP call. */
+OCTGS_API int octgs_raster_views(const void *ws, int64_t gauss_capacity, int64_t pair_capacity,
+                       int32_t width, int32_t height, const octgs_raster_stats **stats,
+                       const uint32_t **pair_tile, const uint32_t **pair_slot,
+                       const uint32_t **tile_ranges);
+
+/* Error string of a status code (static storage). */
+OCTGS_API const char *octgs_strerror(int status);
+
+/* Library version, for load checks. */
+OCTGS_API int octgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTGS_H */

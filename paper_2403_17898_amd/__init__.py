@@ -1,0 +1,9 @@
+"""Octree-GS render path on AMD MI355X: HIP kernels behind a C ABI
+(include/octgs.h), with a thin ctypes binding.
+
+    from paper_2403_17898_amd import DeviceScene, ViewBuffers, make_camera, raster_params
+"""
+
+from ._lib import (OCTGS_BF16, OCTGS_FP32, OctgsError, lib)  # noqa: F401
+from .render import (DeviceScene, ViewBuffers, make_camera, raster_params,  # noqa: F401
+                     stream_handle)

@@ -1,0 +1,102 @@
+"""ctypes binding of liboctgs.so (the C ABI in include/octgs.h).
+
+Argument marshalling only: every step of the render path runs in the HIP
+library.  PyTorch provides device memory and the current stream.  Importing
+this module does not touch the GPU; `lib()` raises if the library is not
+built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboctgs.so")
+
+OCTGS_OK, OCTGS_EINVAL, OCTGS_ENOSPC, OCTGS_EHIP, OCTGS_EUNSUPPORTED = 0, -1, -2, -3, -4
+OCTGS_FP32, OCTGS_BF16 = 0, 1
+OCTGS_RASTER_STAGES = 5
+RASTER_STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
+
+_p = ctypes.c_void_p
+_f = ctypes.c_float
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", _f * 9), ("C", _f * 3), ("fx", _f), ("fy", _f), ("cx", _f), ("cy", _f),
+                ("width", _i32), ("height", _i32), ("z_near", _f), ("lod_scale2", _f)]
+
+
+class Anchors(ctypes.Structure):
+    _fields_ = [("n", _i64), ("k", _i32), ("feat_dim", _i32), ("n_levels", _i32),
+                ("d_max", _f), ("pos", _p), ("level", _p), ("lod_bias", _p), ("feat", _p),
+                ("feat_bf16", _p), ("offsets", _p), ("offset_scale", _p), ("base_scale", _p),
+                ("thr2", _p), ("bound_r", _p)]
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("width", _i32), ("w1", _p * 3), ("b1", _p * 3), ("w2", _p * 3), ("b2", _p * 3)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("capacity", _i64), ("data", _p), ("count", _p)]
+
+
+class RasterParams(ctypes.Structure):
+    _fields_ = [("alpha_max", _f), ("alpha_min", _f), ("t_min", _f), ("dilation", _f),
+                ("jac_clamp", _f), ("bg", _f * 3)]
+
+
+class RasterStats(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
+                ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
+                ("sync_error", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 11)]
+
+
+# (name, restype, argtypes); kept in the order of include/octgs.h
+SIGNATURES = [
+    ("octgs_prepare_anchors", _i32, [ctypes.POINTER(Anchors), _p, _p, _p]),
+    ("octgs_select_workspace_bytes", ctypes.c_size_t, [_i64]),
+    ("octgs_select_lod", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _p,
+                                ctypes.c_size_t, _p]),
+    ("octgs_decode", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp), ctypes.POINTER(Camera),
+                            _p, _p, _i32, ctypes.POINTER(Gaussians), _p]),
+    ("octgs_raster_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i32, _i32]),
+    ("octgs_rasterize_fwd", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                   ctypes.POINTER(RasterParams), _i64, _p, _p, _p, _p, _p,
+                                   ctypes.c_size_t, _p, _p]),
+    ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
+                                  ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
+    ("octgs_strerror", ctypes.c_char_p, [_i32]),
+    ("octgs_version", _i32, []),
+]
+
+_lib = None
+
+
+class OctgsError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load liboctgs.so; raises (never falls back) if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OctgsError(f"{LIB_PATH} is not built; run paper_2403_17898_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != OCTGS_OK:
+        msg = lib().octgs_strerror(status).decode()
+        raise OctgsError(f"{what} failed: {msg} ({status})")

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP translation units of liboctgs.
+// Written for gfx950 (CDNA4): 64-lane wavefronts, 256-thread blocks of four
+// waves, MFMA for the decode GEMMs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "../../include/octgs.h"
+
+namespace octgs {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per block in every kernel
+constexpr int kTile = 16;            // screen tile edge in pixels
+constexpr int kChunk = 4096;         // elements per block in the two-pass compactions
+constexpr int kChunkPerThread = kChunk / kBlock;  // 16
+constexpr int kGaussFields = 14;
+constexpr int kProjFields = 9;       // mx, my, conic a, b, c, opacity, r, g, b
+constexpr int kMaxK = 16;
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(int pred) { return __ballot(pred); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  int l = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns
+// the exclusive prefix and writes the block total to *total.  `tmp` is LDS of
+// at least 4 words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *total) {
+  int w = threadIdx.x / kWave, l = __lane_id();
+  uint32_t inc = wave_incl_scan(v);
+  if (l == 63) tmp[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / kWave; ++i) {
+    uint32_t s = tmp[i];
+    if (i < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+// Relaxed device-scope (all XCDs) atomics for look-back status words.
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Remap a linear block index so that each of the 8 XCDs (blocks are dealt
+// round-robin over XCDs) receives a contiguous range of work items.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
+  constexpr uint32_t kXcd = 8;
+  uint32_t per = nblocks / kXcd, rem = nblocks % kXcd;
+  uint32_t xcd = bid % kXcd, slot = bid / kXcd;
+  // XCDs with index < rem own per + 1 items
+  uint32_t start = xcd * per + (xcd < rem ? xcd : rem);
+  uint32_t own = per + (xcd < rem ? 1u : 0u);
+  return slot < own ? start + slot : bid;  // the fallback never triggers for full grids
+}
+
+// ---------------------------------------------------------------------------
+// rasterizer workspace
+// ---------------------------------------------------------------------------
+
+struct RasterHeader {
+  uint32_t n_slots, n_visible, n_pairs, pair_overflow, sync_error;
+  uint32_t reserved[11];
+  uint32_t part_counter[16];  // dynamic partition ids of the radix-sort passes
+};
+
+struct RasterWs {
+  RasterHeader *hdr;
+  uint64_t *vis_mask;     // [gcap / 64]
+  uint32_t *blk_cnt;      // [nblk_g]
+  float *proj;            // [9][gcap]
+  uint32_t *depth;        // [gcap] float bits of camera z
+  uint64_t *rect;         // [gcap] packed u16 x0, y0, x1, y1
+  uint32_t *dkey[2];      // [gcap] depth-sort keys (ping-pong)
+  uint32_t *dval[2];      // [gcap] depth-sort values = slot ids
+  uint32_t *pair_off;     // [gcap] exclusive prefix of tiles touched, depth order
+  uint32_t *emit_blk;     // [nblk_g]
+  uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
+  uint32_t *tval[2];      // [pcap] slot ids
+  uint32_t *ranges;       // [tiles][2]
+  uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 2..4 tile passes)
+  uint32_t *lookback;     // [max(4 * ceil(gcap/part), 4 * ceil(pcap/part))][256]
+  int64_t gcap, pcap;
+  int32_t tiles_x, tiles_y, nblk_g;
+  size_t bytes;
+};
+
+RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);
+
+// ---------------------------------------------------------------------------
+// radix sort (Onesweep: one histogram pass, then one pass per digit with
+// decoupled look-back across dynamically numbered partitions)
+// ---------------------------------------------------------------------------
+
+constexpr int kSortItems = 8;
+constexpr int kSortPart = kBlock * kSortItems;  // 2048 keys per partition
+constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
+
+// Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
+// key, stably.  On return the sorted data is in buffers index `passes % 2`.
+// hist: [passes][256] zeroed beforehand; part_counter: [passes] zeroed
+// beforehand; lookback: passes * ceil(cap / kSortPart) * 256 words.
+hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
+                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *part_counter,
+                      uint32_t *err_flag, hipStream_t stream);
+
+}  // namespace octgs

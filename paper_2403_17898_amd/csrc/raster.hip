@@ -1,0 +1,632 @@
+// Forward rasterizer (Octree-GS Sec. III-A: EWA projection of each 3D
+// Gaussian to a 2D one, tile-based front-to-back depth ordering, and the
+// alpha blending of Eq. 2).
+//
+// Stages, all on one stream with device-resident counts:
+//   init      zero counters, tile ranges, radix histograms
+//   project   per Gaussian slot: culls, 2D covariance, conic, 3-sigma tile
+//             rectangle, depth key; ballot of survivors
+//   compact   survivors in slot order -> (depth key, slot)
+//   sort      Onesweep on the 32-bit depth keys (4 passes over Gaussians)
+//   emit      pairs in depth order: per Gaussian its rectangle's tiles,
+//             offsets by a two-pass scan, writers balanced over pairs
+//   sort      Onesweep on the tile id (1-3 passes over pairs); stable, so
+//             each tile keeps depth order, ties by slot index
+//   ranges    [start, end) per tile
+//   composite one 256-thread block per 16x16 tile, batches of 256
+//             Gaussians staged in LDS, block exit once every pixel is done
+//
+// Sorting depth once per Gaussian and then only the tile id per pair gives
+// the same (tile, depth, slot) order as one sort of 64-bit tile|depth keys
+// while moving far fewer bytes: a pair list is typically several times
+// longer than the Gaussian list.
+//
+// Decisions (culls, rectangle, depth key) use the fixed FP32 operation
+// sequence documented at project_decide; continuous values are FP32.
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+struct Cam {
+  float R[9], C[3], fx, fy, cx, cy, z_near;
+  int W, H;
+};
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Canonical FP32 projection decisions and FP32 continuous outputs for one
+// Gaussian (attributes g[14]).  Sequence:
+//   cull unless opacity > 0
+//   d = mean - C; (xc, yc, zc) rows fmaf(R0, d0, fmaf(R1, d1, R2 * d2)); cull unless zc > z_near
+//   yy=y*y zz=z*z xx=x*x xy=x*y xz=x*z yz=y*z wx=w*x wy=w*y wz=w*z
+//   Rq = [1-2(yy+zz), 2(xy-wz), 2(xz+wy); 2(xy+wz), 1-2(xx+zz), 2(yz-wx); 2(xz-wy), 2(yz+wx), 1-2(xx+yy)]
+//   M_ab = Rq_ab * s_b; S_ab = fmaf(M_a0, M_b0, fmaf(M_a1, M_b1, M_a2 * M_b2))
+//   lx = jac_clamp * ((0.5 * W) / fx); rx = xc / zc; tx = min(lx, max(-lx, rx)) * zc (y alike)
+//   zc2 = zc * zc; J00 = fx / zc; J02 = -((fx * tx) / zc2); J11 = fy / zc; J12 = -((fy * ty) / zc2)
+//   T0_c = fmaf(J00, R_0c, J02 * R_2c); T1_c = fmaf(J11, R_1c, J12 * R_2c)
+//   u_a = fmaf(S_a0, T0_0, fmaf(S_a1, T0_1, S_a2 * T0_2)); v_a likewise with T1
+//   a = dot(T0, u) + dil; b = dot(T1, u); c = dot(T1, v) + dil;  dot = fmaf chain
+//   det = a * c - b * b; cull unless det > 0
+//   mid = 0.5 * (a + c); lam = mid + sqrtf(fmaxf(mid * mid - det, 0)); r = ceilf(3 * sqrtf(lam))
+//   px = fmaf(fx, rx, cx); py = fmaf(fy, ry, cy)
+//   x0 = clamp(floorf((px - r) * 0.0625)), x1 = clamp(floorf((px + r) * 0.0625) + 1) to [0, tiles]
+//   cull if x0 >= x1 or y0 >= y1
+struct ProjOut {
+  float mx, my, ca, cb, cc, zc;
+  int x0, y0, x1, y1;
+};
+
+__device__ __forceinline__ bool project_decide(const Cam &k, float dil, float jc, int tiles_x,
+                                               int tiles_y, const float *g, ProjOut &o) {
+  if (!(g[10] > 0.0f)) return false;
+  const float d0 = g[0] - k.C[0], d1 = g[1] - k.C[1], d2 = g[2] - k.C[2];
+  const float xc = fma_(k.R[0], d0, fma_(k.R[1], d1, k.R[2] * d2));
+  const float yc = fma_(k.R[3], d0, fma_(k.R[4], d1, k.R[5] * d2));
+  const float zc = fma_(k.R[6], d0, fma_(k.R[7], d1, k.R[8] * d2));
+  if (!(zc > k.z_near)) return false;
+  const float w = g[6], x = g[7], y = g[8], z = g[9];
+  const float yy = y * y, zz = z * z, xx = x * x, xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  float Rq[9];
+  Rq[0] = 1.0f - 2.0f * (yy + zz); Rq[1] = 2.0f * (xy - wz); Rq[2] = 2.0f * (xz + wy);
+  Rq[3] = 2.0f * (xy + wz); Rq[4] = 1.0f - 2.0f * (xx + zz); Rq[5] = 2.0f * (yz - wx);
+  Rq[6] = 2.0f * (xz - wy); Rq[7] = 2.0f * (yz + wx); Rq[8] = 1.0f - 2.0f * (xx + yy);
+  float M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * g[3 + b];
+  float S[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      const float v = fma_(M[3 * a], M[3 * b], fma_(M[3 * a + 1], M[3 * b + 1], M[3 * a + 2] * M[3 * b + 2]));
+      S[3 * a + b] = v;
+      S[3 * b + a] = v;
+    }
+  const float lx = jc * ((0.5f * (float)k.W) / k.fx);
+  const float ly = jc * ((0.5f * (float)k.H) / k.fy);
+  const float rx = xc / zc, ry = yc / zc;
+  const float tx = fminf(lx, fmaxf(-lx, rx)) * zc;
+  const float ty = fminf(ly, fmaxf(-ly, ry)) * zc;
+  const float zc2 = zc * zc;
+  const float J00 = k.fx / zc, J02 = -((k.fx * tx) / zc2);
+  const float J11 = k.fy / zc, J12 = -((k.fy * ty) / zc2);
+  float T0[3], T1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = fma_(J00, k.R[c], J02 * k.R[6 + c]);
+    T1[c] = fma_(J11, k.R[3 + c], J12 * k.R[6 + c]);
+  }
+  float u[3], v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = fma_(S[3 * a], T0[0], fma_(S[3 * a + 1], T0[1], S[3 * a + 2] * T0[2]));
+    v[a] = fma_(S[3 * a], T1[0], fma_(S[3 * a + 1], T1[1], S[3 * a + 2] * T1[2]));
+  }
+  const float ca = fma_(T0[0], u[0], fma_(T0[1], u[1], T0[2] * u[2])) + dil;
+  const float cb = fma_(T1[0], u[0], fma_(T1[1], u[1], T1[2] * u[2]));
+  const float cc = fma_(T1[0], v[0], fma_(T1[1], v[1], T1[2] * v[2])) + dil;
+  const float det = ca * cc - cb * cb;
+  if (!(det > 0.0f)) return false;
+  const float mid = 0.5f * (ca + cc);
+  const float lam = mid + sqrtf(fmaxf(mid * mid - det, 0.0f));
+  const float r = ceilf(3.0f * sqrtf(lam));
+  const float px = fma_(k.fx, rx, k.cx), py = fma_(k.fy, ry, k.cy);
+  const float fx0 = floorf((px - r) * 0.0625f), fx1 = floorf((px + r) * 0.0625f) + 1.0f;
+  const float fy0 = floorf((py - r) * 0.0625f), fy1 = floorf((py + r) * 0.0625f) + 1.0f;
+  const float tX = (float)tiles_x, tY = (float)tiles_y;
+  const int x0 = (int)fminf(fmaxf(fx0, 0.0f), tX), x1 = (int)fminf(fmaxf(fx1, 0.0f), tX);
+  const int y0 = (int)fminf(fmaxf(fy0, 0.0f), tY), y1 = (int)fminf(fmaxf(fy1, 0.0f), tY);
+  if (x0 >= x1 || y0 >= y1) return false;
+  const float inv = 1.0f / det;
+  o.mx = px; o.my = py;
+  o.ca = cc * inv; o.cb = -cb * inv; o.cc = ca * inv;
+  o.zc = zc;
+  o.x0 = x0; o.y0 = y0; o.x1 = x1; o.y1 = y1;
+  return true;
+}
+
+__device__ __forceinline__ uint64_t pack_rect(int x0, int y0, int x1, int y1) {
+  return (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)y0 << 16) | ((uint64_t)(uint16_t)x1 << 32) |
+         ((uint64_t)(uint16_t)y1 << 48);
+}
+
+__device__ __forceinline__ uint32_t rect_tiles(uint64_t r) {
+  const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff, y1 = r >> 48;
+  return (x1 - x0) * (y1 - y0);
+}
+
+__global__ void k_raster_init(RasterHeader *hdr, uint32_t *ranges, int ntiles, uint32_t *hist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int)(sizeof(RasterHeader) / 4)) ((uint32_t *)hdr)[i] = 0u;
+  if (i < 8 * 256) hist[i] = 0u;
+  for (int j = i; j < 2 * ntiles; j += gridDim.x * blockDim.x) ranges[j] = 0u;
+}
+
+struct ProjArgs {
+  Cam cam;
+  float dil, jc;
+  int tiles_x, tiles_y;
+  const float *g;
+  int64_t gstride;
+  const uint32_t *count;
+  int64_t gcap;
+  RasterWs ws;
+  float *gauss_w;
+};
+
+__global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
+  __shared__ uint32_t wsum[4];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t n = (uint32_t)min<int64_t>(*a.count, a.gcap);
+  if (blockIdx.x == 0 && t == 0) a.ws.hdr->n_slots = n;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  if (base >= n) return;
+  const int64_t cap = a.ws.gcap;
+  uint32_t cnt = 0;
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t s = base + i * kBlock + t;
+    bool vis = false;
+    if (s < n) {
+      float g[kGaussFields];
+#pragma unroll
+      for (int f = 0; f < kGaussFields; ++f) g[f] = a.g[f * a.gstride + s];
+      ProjOut o;
+      vis = project_decide(a.cam, a.dil, a.jc, a.tiles_x, a.tiles_y, g, o);
+      if (vis) {
+        float *p = a.ws.proj;
+        p[0 * cap + s] = o.mx; p[1 * cap + s] = o.my;
+        p[2 * cap + s] = o.ca; p[3 * cap + s] = o.cb; p[4 * cap + s] = o.cc;
+        p[5 * cap + s] = g[10]; p[6 * cap + s] = g[11]; p[7 * cap + s] = g[12];
+        p[8 * cap + s] = g[13];
+        a.ws.depth[s] = __float_as_uint(o.zc);
+        a.ws.rect[s] = pack_rect(o.x0, o.y0, o.x1, o.y1);
+      }
+      if (a.gauss_w) a.gauss_w[s] = 0.0f;
+    }
+    const uint64_t m = ballot(vis);
+    const int64_t gidx = base + i * kBlock + w * kWave;
+    if (l == 0 && gidx < n) a.ws.vis_mask[gidx >> 6] = m;
+    cnt += (uint32_t)__popcll(m);
+  }
+  if (l == 0) wsum[w] = cnt;
+  __syncthreads();
+  if (t == 0) a.ws.blk_cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Ordered compaction of the survivors: (depth key, slot) in slot order.
+__global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const uint32_t *count) {
+  __shared__ uint32_t red[4];
+  __shared__ uint32_t gpre[64];
+  __shared__ uint64_t gmask[64];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t n = (uint32_t)min<int64_t>(*count, ws.gcap);
+  const int b = blockIdx.x;
+  const int64_t base = (int64_t)b * kChunk;
+  if (n == 0) {
+    if (b == 0 && t == 0) ws.hdr->n_visible = 0;
+    return;
+  }
+  if (base >= n) return;
+  uint32_t s = 0;
+  for (int i = t; i < b; i += kBlock) s += ws.blk_cnt[i];
+  s = wave_sum(s);
+  if (l == 0) red[w] = s;
+  const int ngroups = (int)min<int64_t>(64, ((int64_t)n - base + 63) / 64);
+  if (w == 0) {
+    const uint64_t m = l < ngroups ? ws.vis_mask[(base >> 6) + l] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(m);
+    const uint32_t inc = wave_incl_scan(c);
+    gpre[l] = inc - c;
+    gmask[l] = m;
+  }
+  __syncthreads();
+  const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
+  for (int gi = w; gi < ngroups; gi += 4) {
+    const uint64_t m = gmask[gi];
+    if ((m >> l) & 1ull) {
+      const uint32_t pos = prefix + gpre[gi] + (uint32_t)__popcll(m & lanemask_lt());
+      const uint32_t slot = (uint32_t)(base + 64 * gi + l);
+      ws.dkey[0][pos] = ws.depth[slot];
+      ws.dval[0][pos] = slot;
+    }
+  }
+  if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0)
+    ws.hdr->n_visible = prefix + gpre[ngroups - 1] + (uint32_t)__popcll(gmask[ngroups - 1]);
+}
+
+// Pair counting over the depth-ordered survivors, chunk per block.
+__global__ __launch_bounds__(kBlock) void k_emit_count(RasterWs ws) {
+  __shared__ uint32_t wsum[4];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t n = ws.hdr->n_visible;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  if (base >= n) return;
+  uint32_t c = 0;
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t s = base + i * kBlock + t;
+    if (s < n) c += rect_tiles(ws.rect[ws.dval[0][s]]);
+  }
+  c = wave_sum(c);
+  if (l == 0) wsum[w] = c;
+  __syncthreads();
+  if (t == 0) ws.emit_blk[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Exclusive pair offsets per depth-ordered survivor; the block holding the
+// last survivor publishes the total and the overflow flag.
+__global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
+  __shared__ uint32_t red[4];
+  __shared__ uint32_t tmp[8];
+  __shared__ uint32_t carry;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t n = ws.hdr->n_visible;
+  const int b = blockIdx.x;
+  if (n == 0) {
+    if (b == 0 && t == 0) {
+      ws.hdr->n_pairs = 0;
+      ws.hdr->reserved[0] = 0;
+    }
+    return;
+  }
+  const int64_t base = (int64_t)b * kChunk;
+  if (base >= n) return;
+  uint32_t s = 0;
+  for (int i = t; i < b; i += kBlock) s += ws.emit_blk[i];
+  s = wave_sum(s);
+  if (l == 0) red[w] = s;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
+  // consecutive 256-entry rows of the chunk, scanned in order
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t sidx = base + i * kBlock + t;
+    const uint32_t c = sidx < n ? rect_tiles(ws.rect[ws.dval[0][sidx]]) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(c, tmp, &tot);
+    if (sidx < n) ws.pair_off[sidx] = prefix + carry + ex;
+    __syncthreads();
+    if (t == 0) carry += tot;
+    __syncthreads();
+  }
+  if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) {
+    const uint32_t total = prefix + carry;
+    ws.hdr->n_pairs = total;
+    const bool over = (int64_t)total > ws.pcap;
+    ws.hdr->pair_overflow = over ? 1u : 0u;
+    ws.hdr->reserved[0] = over ? 0u : total;  // pairs actually emitted
+  }
+}
+
+constexpr int kEmitRun = 2048;  // pairs per block iteration
+
+// Pair emission balanced over pairs: a block takes 2048 consecutive output
+// positions, finds the Gaussians covering them by binary search and writes
+// (tile id, slot) for each.
+__global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws) {
+  __shared__ uint32_t offs[kEmitRun + 1];
+  __shared__ uint32_t lo_s;
+  const int t = threadIdx.x;
+  const uint32_t P = ws.hdr->reserved[0];
+  const uint32_t n = ws.hdr->n_visible;
+  for (uint32_t p0 = blockIdx.x * kEmitRun; p0 < P; p0 += gridDim.x * kEmitRun) {
+    const uint32_t p1 = min(P, p0 + kEmitRun);
+    if (t == 0) {
+      // last survivor whose offset <= p0
+      uint32_t lo = 0, hi = n;  // invariant: off[lo] <= p0 < off[hi] (off[n] = P)
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ws.pair_off[mid] <= p0) lo = mid; else hi = mid;
+      }
+      lo_s = lo;
+    }
+    __syncthreads();
+    const uint32_t lo = lo_s;
+    const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
+    for (uint32_t i = t; i < cnt; i += kBlock) offs[i] = ws.pair_off[lo + i];
+    __syncthreads();
+    for (uint32_t p = p0 + t; p < p1; p += kBlock) {
+      uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
+      while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (offs[mid] <= p) a = mid; else b = mid;
+      }
+      const uint32_t slot = ws.dval[0][lo + a];
+      const uint64_t r = ws.rect[slot];
+      const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff;
+      const uint32_t wdt = x1 - x0;
+      const uint32_t loc = p - offs[a];
+      const uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
+      ws.tkey[0][p] = ty * (uint32_t)ws.tiles_x + tx;
+      ws.tval[0][p] = slot;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
+  const uint32_t P = ws.hdr->reserved[0];
+  const uint32_t *key = ws.tkey[buf];
+  for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
+    const uint32_t k = key[p];
+    if (p == 0 || key[p - 1] != k) ws.ranges[2 * k] = p;
+    if (p == P - 1 || key[p + 1] != k) ws.ranges[2 * k + 1] = p + 1;
+  }
+}
+
+struct CompArgs {
+  RasterWs ws;
+  int buf, W, H;
+  float alpha_max, alpha_min, t_min, bg[3];
+  float *rgb, *T_final;
+  uint32_t *last;
+  float *gauss_w;
+};
+
+template <bool LOG>
+__global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
+  __shared__ float s_mx[kBlock], s_my[kBlock], s_ca[kBlock], s_cb[kBlock], s_cc[kBlock];
+  __shared__ float s_op[kBlock], s_r[kBlock], s_g[kBlock], s_b[kBlock];
+  __shared__ uint32_t s_slot[kBlock];
+  __shared__ float s_w[LOG ? kBlock : 1];
+  const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
+  const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
+  const int t = threadIdx.x;
+  const int px = tx * kTile + (t % kTile), py = ty * kTile + (t / kTile);
+  const bool inside = px < a.W && py < a.H;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
+  const uint32_t *vals = a.ws.tval[a.buf];
+  const float *proj = a.ws.proj;
+  const int64_t cap = a.ws.gcap;
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (uint32_t b0 = start; b0 < end; b0 += kBlock) {
+    const uint32_t e = b0 + t;
+    if (e < end) {
+      const uint32_t s = vals[e];
+      s_slot[t] = s;
+      s_mx[t] = proj[s];
+      s_my[t] = proj[cap + s];
+      s_ca[t] = -0.5f * kLog2e * proj[2 * cap + s];
+      s_cb[t] = -kLog2e * proj[3 * cap + s];
+      s_cc[t] = -0.5f * kLog2e * proj[4 * cap + s];
+      s_op[t] = proj[5 * cap + s];
+      s_r[t] = proj[6 * cap + s];
+      s_g[t] = proj[7 * cap + s];
+      s_b[t] = proj[8 * cap + s];
+    }
+    if (LOG) s_w[t] = 0.0f;
+    __syncthreads();
+    const int nb = (int)min((uint32_t)kBlock, end - b0);
+    if (LOG) {
+      // uniform loop: every lane steps through the batch for the wave sums
+      for (int j = 0; j < nb; ++j) {
+        float wt = 0.0f;
+        if (!done) {
+          const float dx = fx - s_mx[j], dy = fy - s_my[j];
+          const float pw = fma_(s_ca[j] * dx, dx, fma_(s_cc[j] * dy, dy, s_cb[j] * dx * dy));
+          const float al = fminf(a.alpha_max, s_op[j] * __builtin_amdgcn_exp2f(pw));
+          last = b0 - start + j + 1;
+          if (!(al < a.alpha_min)) {
+            wt = al * T;
+            cr = fma_(wt, s_r[j], cr);
+            cg = fma_(wt, s_g[j], cg);
+            cbl = fma_(wt, s_b[j], cbl);
+            T = T * (1.0f - al);
+            if (T < a.t_min) done = true;
+          }
+        }
+        const float ws = wave_sum_f(wt);
+        if (__lane_id() == 0 && ws != 0.0f) atomicAdd(&s_w[j], ws);
+      }
+    } else if (!done) {
+      for (int j = 0; j < nb; ++j) {
+        const float dx = fx - s_mx[j], dy = fy - s_my[j];
+        const float pw = fma_(s_ca[j] * dx, dx, fma_(s_cc[j] * dy, dy, s_cb[j] * dx * dy));
+        const float al = fminf(a.alpha_max, s_op[j] * __builtin_amdgcn_exp2f(pw));
+        last = b0 - start + j + 1;
+        if (al < a.alpha_min) continue;
+        const float wt = al * T;
+        cr = fma_(wt, s_r[j], cr);
+        cg = fma_(wt, s_g[j], cg);
+        cbl = fma_(wt, s_b[j], cbl);
+        T = T * (1.0f - al);
+        if (T < a.t_min) {
+          done = true;
+          break;
+        }
+      }
+    }
+    if (LOG) {
+      __syncthreads();
+      if (t < nb && s_w[t] != 0.0f) atomicAdd(&a.gauss_w[s_slot[t]], s_w[t]);
+    }
+    if (__syncthreads_count(done) == kBlock) break;
+  }
+  if (inside) {
+    const size_t pix = (size_t)py * a.W + px, plane = (size_t)a.W * a.H;
+    a.rgb[pix] = fma_(T, a.bg[0], cr);
+    a.rgb[plane + pix] = fma_(T, a.bg[1], cg);
+    a.rgb[2 * plane + pix] = fma_(T, a.bg[2], cbl);
+    a.T_final[pix] = T;
+    a.last[pix] = last;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H) {
+  RasterWs ws;
+  char *p = (char *)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *r = p ? (void *)(p + off) : nullptr;
+    off += align256(bytes);
+    return r;
+  };
+  const int64_t g = std::max<int64_t>(gcap, 1), pc = std::max<int64_t>(pcap, 1);
+  ws.gcap = g;
+  ws.pcap = pc;
+  ws.tiles_x = (W + kTile - 1) / kTile;
+  ws.tiles_y = (H + kTile - 1) / kTile;
+  ws.nblk_g = (int)((g + kChunk - 1) / kChunk);
+  ws.hdr = (RasterHeader *)take(sizeof(RasterHeader));
+  ws.vis_mask = (uint64_t *)take((size_t)ws.nblk_g * 64 * 8);
+  ws.blk_cnt = (uint32_t *)take((size_t)ws.nblk_g * 4);
+  ws.proj = (float *)take((size_t)kProjFields * g * 4);
+  ws.depth = (uint32_t *)take((size_t)g * 4);
+  ws.rect = (uint64_t *)take((size_t)g * 8);
+  for (int i = 0; i < 2; ++i) ws.dkey[i] = (uint32_t *)take((size_t)g * 4);
+  for (int i = 0; i < 2; ++i) ws.dval[i] = (uint32_t *)take((size_t)g * 4);
+  ws.pair_off = (uint32_t *)take((size_t)g * 4);
+  ws.emit_blk = (uint32_t *)take((size_t)ws.nblk_g * 4);
+  for (int i = 0; i < 2; ++i) ws.tkey[i] = (uint32_t *)take((size_t)pc * 4);
+  for (int i = 0; i < 2; ++i) ws.tval[i] = (uint32_t *)take((size_t)pc * 4);
+  ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
+  ws.hist = (uint32_t *)take(8 * 256 * 4);
+  const int64_t parts = std::max((g + kSortPart - 1) / kSortPart, (pc + kSortPart - 1) / kSortPart);
+  ws.lookback = (uint32_t *)take((size_t)4 * parts * 256 * 4);
+  ws.bytes = off;
+  return ws;
+}
+
+int tile_sort_passes(int ntiles) {
+  int bits = 1;
+  while ((1 << bits) < ntiles) ++bits;
+  return (bits + 7) / 8;
+}
+
+}  // namespace octgs
+
+using namespace octgs;
+
+extern "C" {
+
+size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pair_capacity, int32_t width,
+                                    int32_t height) {
+  if (gauss_capacity < 0 || pair_capacity < 0 || width <= 0 || height <= 0) return 0;
+  return raster_layout(nullptr, gauss_capacity, pair_capacity, width, height).bytes;
+}
+
+int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
+                        const octgs_raster_params *p, int64_t pair_capacity, float *rgb,
+                        float *T_final, uint32_t *last, float *gauss_w, void *wsp,
+                        size_t ws_bytes, void *const *stage_events, octgs_stream stream) {
+  if (!g || !cam || !p || !rgb || !T_final || !last || !wsp) return OCTGS_EINVAL;
+  if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
+    return OCTGS_EINVAL;
+  if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30)) return OCTGS_EINVAL;
+  if (cam->width <= 0 || cam->height <= 0 || cam->width > 16 * 65535 || cam->height > 16 * 65535)
+    return OCTGS_EINVAL;
+  if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return OCTGS_EINVAL;
+  if (ws_bytes < octgs_raster_workspace_bytes(g->capacity, pair_capacity, cam->width, cam->height))
+    return OCTGS_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
+  const int ntiles = ws.tiles_x * ws.tiles_y;
+  auto mark = [&](int i) {
+    if (stage_events && stage_events[i]) hipEventRecord((hipEvent_t)stage_events[i], s);
+  };
+  hipLaunchKernelGGL(k_raster_init, dim3(std::max(8, std::min(1024, (2 * ntiles + 255) / 256))),
+                     dim3(256), 0, s, ws.hdr, ws.ranges, ntiles, ws.hist);
+  ProjArgs pa;
+  for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
+  for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];
+  pa.cam.fx = cam->fx; pa.cam.fy = cam->fy; pa.cam.cx = cam->cx; pa.cam.cy = cam->cy;
+  pa.cam.z_near = cam->z_near; pa.cam.W = cam->width; pa.cam.H = cam->height;
+  pa.dil = p->dilation;
+  pa.jc = p->jac_clamp;
+  pa.tiles_x = ws.tiles_x;
+  pa.tiles_y = ws.tiles_y;
+  pa.g = g->data;
+  pa.gstride = g->capacity;
+  pa.count = g->count;
+  pa.gcap = g->capacity;
+  pa.ws = ws;
+  pa.gauss_w = gauss_w;
+  mark(0);
+  hipLaunchKernelGGL(k_project_mark, dim3(ws.nblk_g), dim3(kBlock), 0, s, pa);
+  hipLaunchKernelGGL(k_project_compact, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws, g->count);
+  mark(1);
+  mark(2);
+  hipError_t e = radix_sort(ws.dkey, ws.dval, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
+                            ws.lookback, ws.hdr->part_counter, &ws.hdr->sync_error, s);
+  if (e != hipSuccess) return OCTGS_EHIP;
+  mark(3);
+  mark(4);
+  hipLaunchKernelGGL(k_emit_count, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
+  hipLaunchKernelGGL(k_emit_scan, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
+  const int emit_grid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kEmitRun - 1) / kEmitRun, 1), 4096);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(emit_grid), dim3(kBlock), 0, s, ws);
+  mark(5);
+  mark(6);
+  const int passes = tile_sort_passes(ntiles);
+  e = radix_sort(ws.tkey, ws.tval, &ws.hdr->reserved[0], ws.pcap, passes, ws.hist + 4 * 256,
+                 ws.lookback, ws.hdr->part_counter + 4, &ws.hdr->sync_error, s);
+  if (e != hipSuccess) return OCTGS_EHIP;
+  const int buf = passes % 2;
+  const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 8192);
+  hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kBlock), 0, s, ws, buf);
+  mark(7);
+  CompArgs ca;
+  ca.ws = ws;
+  ca.buf = buf;
+  ca.W = cam->width;
+  ca.H = cam->height;
+  ca.alpha_max = p->alpha_max;
+  ca.alpha_min = p->alpha_min;
+  ca.t_min = p->t_min;
+  for (int i = 0; i < 3; ++i) ca.bg[i] = p->bg[i];
+  ca.rgb = rgb;
+  ca.T_final = T_final;
+  ca.last = last;
+  ca.gauss_w = gauss_w;
+  mark(8);
+  if (gauss_w)
+    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kBlock), 0, s, ca);
+  else
+    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kBlock), 0, s, ca);
+  mark(9);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+int octgs_raster_views(const void *wsp, int64_t gauss_capacity, int64_t pair_capacity,
+                       int32_t width, int32_t height, const octgs_raster_stats **stats,
+                       const uint32_t **pair_tile, const uint32_t **pair_slot,
+                       const uint32_t **tile_ranges) {
+  if (!wsp || width <= 0 || height <= 0 || gauss_capacity < 0 || pair_capacity < 0)
+    return OCTGS_EINVAL;
+  RasterWs ws = raster_layout(const_cast<void *>(wsp), gauss_capacity, pair_capacity, width, height);
+  const int buf = tile_sort_passes(ws.tiles_x * ws.tiles_y) % 2;
+  if (stats) *stats = (const octgs_raster_stats *)ws.hdr;
+  if (pair_tile) *pair_tile = ws.tkey[buf];
+  if (pair_slot) *pair_slot = ws.tval[buf];
+  if (tile_ranges) *tile_ranges = ws.ranges;
+  return OCTGS_OK;
+}
+
+const char *octgs_strerror(int status) {
+  switch (status) {
+    case OCTGS_OK: return "ok";
+    case OCTGS_EINVAL: return "invalid argument";
+    case OCTGS_ENOSPC: return "workspace too small";
+    case OCTGS_EHIP: return "HIP launch or runtime error";
+    case OCTGS_EUNSUPPORTED: return "unsupported shape";
+    default: return "unknown status";
+  }
+}
+
+int octgs_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// Anchor selection (Octree-GS Sec. IV-A, "Anchor Selection", Eq. 7) and its
+// per-scene preparation.
+//
+// Eq. 7 picks, per view, every anchor whose level L satisfies
+// L <= floor(clamp(log2(d_max / (d s)) + Delta L, 0, K - 1)).  For an integer
+// level in [0, K-1] that is: level 0 always, otherwise d^2 s^2 <= thr2 with
+// thr2 = (d_max 2^(Delta L - L))^2, a per-anchor constant computed once per
+// scene.  The per-view test is then one squared distance and one compare,
+// with no transcendental, so the scan over all anchors is a pure HBM stream.
+//
+// Decisions are taken in FP32 with an explicit operation order (explicit
+// fmaf, no contraction - the library is built with -ffp-contract=off):
+//   d = p - C;  dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));  lod = dd * s2 <= thr2
+//   (xc, yc, zc) rows fmaf(R0, d0, fmaf(R1, d1, R2 * d2))
+//   tan of each side plane = edge offset / focal; sec = sqrtf(fmaf(t, t, 1))
+//   visible = zc + rho >= z_near and, per side, +-x (or +-y) <= fmaf(tan, zc, rho * sec)
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_max,
+                                                    const uint8_t *__restrict__ level,
+                                                    const float *__restrict__ bias,
+                                                    const float *__restrict__ offsets,
+                                                    const float *__restrict__ oscale,
+                                                    const float *__restrict__ bscale,
+                                                    float *__restrict__ thr2,
+                                                    float *__restrict__ rho) {
+  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int L = level[j];
+  if (L == 0) {
+    thr2[j] = __builtin_inff();
+  } else {
+    double t = (double)d_max * exp2((double)bias[j] - (double)L);
+    thr2[j] = (float)(t * t);
+  }
+  const float l0 = oscale[3 * j], l1 = oscale[3 * j + 1], l2 = oscale[3 * j + 2];
+  float m = 0.0f;
+  const float *o = offsets + (size_t)j * k * 3;
+  for (int i = 0; i < k; ++i) {
+    float a = o[3 * i] * l0, b = o[3 * i + 1] * l1, c = o[3 * i + 2] * l2;
+    float nn = sqrtf(__builtin_fmaf(a, a, __builtin_fmaf(b, b, c * c)));
+    m = fmaxf(m, nn);
+  }
+  const float bmax = fmaxf(fmaxf(bscale[3 * j], bscale[3 * j + 1]), bscale[3 * j + 2]);
+  rho[j] = __builtin_fmaf(3.0f, bmax, m);
+}
+
+struct Frustum {
+  float tl, tr, tt, tb, sl, sr, st, sb;
+};
+
+__device__ __forceinline__ Frustum frustum(const octgs_camera &c) {
+  Frustum f;
+  f.tl = c.cx / c.fx;
+  f.tr = ((float)c.width - c.cx) / c.fx;
+  f.tt = c.cy / c.fy;
+  f.tb = ((float)c.height - c.cy) / c.fy;
+  f.sl = sqrtf(__builtin_fmaf(f.tl, f.tl, 1.0f));
+  f.sr = sqrtf(__builtin_fmaf(f.tr, f.tr, 1.0f));
+  f.st = sqrtf(__builtin_fmaf(f.tt, f.tt, 1.0f));
+  f.sb = sqrtf(__builtin_fmaf(f.tb, f.tb, 1.0f));
+  return f;
+}
+
+__device__ __forceinline__ bool anchor_selected(const octgs_camera &c, const Frustum &f, float px,
+                                                float py, float pz, float thr2, float rho) {
+  const float d0 = px - c.C[0], d1 = py - c.C[1], d2 = pz - c.C[2];
+  const float dd = __builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2));
+  if (!(dd * c.lod_scale2 <= thr2)) return false;
+  const float xc = __builtin_fmaf(c.R[0], d0, __builtin_fmaf(c.R[1], d1, c.R[2] * d2));
+  const float yc = __builtin_fmaf(c.R[3], d0, __builtin_fmaf(c.R[4], d1, c.R[5] * d2));
+  const float zc = __builtin_fmaf(c.R[6], d0, __builtin_fmaf(c.R[7], d1, c.R[8] * d2));
+  if (!(zc + rho >= c.z_near)) return false;
+  if (!(xc <= __builtin_fmaf(f.tr, zc, rho * f.sr))) return false;
+  if (!(-xc <= __builtin_fmaf(f.tl, zc, rho * f.sl))) return false;
+  if (!(yc <= __builtin_fmaf(f.tb, zc, rho * f.sb))) return false;
+  if (!(-yc <= __builtin_fmaf(f.tt, zc, rho * f.st))) return false;
+  return true;
+}
+
+// Pass 1: block b tests anchors [b*4096, (b+1)*4096) with coalesced loads,
+// stores one 64-bit ballot per 64 consecutive anchors and the block count.
+__global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera cam,
+                                                        const float *__restrict__ pos,
+                                                        const float *__restrict__ thr2,
+                                                        const float *__restrict__ rho,
+                                                        uint64_t *__restrict__ masks,
+                                                        uint32_t *__restrict__ blk_cnt) {
+  __shared__ uint32_t wsum[4];
+  const Frustum f = frustum(cam);
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t cnt = 0;
+#pragma unroll 4
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t j = base + i * kBlock + t;
+    bool sel = false;
+    if (j < n) {
+      const float px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+      sel = anchor_selected(cam, f, px, py, pz, thr2[j], rho[j]);
+    }
+    const uint64_t m = ballot(sel);
+    if (l == 0 && base + i * kBlock + w * kWave < n) masks[(base + i * kBlock + w * kWave) >> 6] = m;
+    cnt += (uint32_t)__popcll(m);
+  }
+  if (l == 0) wsum[w] = cnt;
+  __syncthreads();
+  if (t == 0) blk_cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Pass 2: block b adds up the counts of blocks < b, scans its 64 ballots and
+// writes the selected indices in ascending order.
+__global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
+                                                           const uint64_t *__restrict__ masks,
+                                                           const uint32_t *__restrict__ blk_cnt,
+                                                           uint32_t *__restrict__ sel_idx,
+                                                           uint32_t *__restrict__ sel_count) {
+  __shared__ uint32_t red[4];
+  __shared__ uint32_t gpre[64];
+  __shared__ uint64_t gmask[64];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const int b = blockIdx.x;
+  uint32_t s = 0;
+  for (int i = t; i < b; i += kBlock) s += blk_cnt[i];
+  s = wave_sum(s);
+  if (l == 0) red[w] = s;
+  const int64_t base = (int64_t)b * kChunk;
+  const int ngroups = (int)min<int64_t>(64, (n - base + 63) / 64);
+  if (w == 0) {
+    uint64_t m = l < ngroups ? masks[(base >> 6) + l] : 0ull;
+    uint32_t c = (uint32_t)__popcll(m);
+    uint32_t inc = wave_incl_scan(c);
+    gpre[l] = inc - c;
+    gmask[l] = m;
+  }
+  __syncthreads();
+  const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
+  // group g covers anchors base + 64 g + lane; four waves cover 16 groups each
+  for (int g = w; g < ngroups; g += 4) {
+    const uint64_t m = gmask[g];
+    if ((m >> l) & 1ull) {
+      const uint32_t pos = prefix + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
+      sel_idx[pos] = (uint32_t)(base + 64 * g + l);
+    }
+  }
+  if (b == (int)gridDim.x - 1 && t == 0) {
+    const uint64_t last = gmask[ngroups - 1];
+    *sel_count = prefix + gpre[ngroups - 1] + (uint32_t)__popcll(last);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
+
+}  // namespace
+
+}  // namespace octgs
+
+using namespace octgs;
+
+extern "C" {
+
+int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
+                          octgs_stream stream) {
+  if (!a) return OCTGS_EINVAL;
+  if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
+  if (a->k < 1 || a->k > kMaxK) return OCTGS_EUNSUPPORTED;
+  if (a->n == 0) return OCTGS_OK;
+  if (!thr2 || !bound_r) return OCTGS_EINVAL;
+  if (!a->level || !a->lod_bias || !a->offsets || !a->offset_scale || !a->base_scale)
+    return OCTGS_EINVAL;
+  if (!(a->d_max > 0.0f)) return OCTGS_EINVAL;
+  const int grid = (int)((a->n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a->n, a->k,
+                     a->d_max, a->level, a->lod_bias, a->offsets, a->offset_scale,
+                     a->base_scale, thr2, bound_r);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+size_t octgs_select_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  const int64_t nblk = (n + kChunk - 1) / kChunk;
+  const int64_t ngrp = nblk * (kChunk / 64);
+  return (size_t)(ngrp * 8 + ((nblk * 4 + 255) / 256) * 256 + 256);
+}
+
+int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
+                     uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream) {
+  if (!a || !cam || !sel_idx || !sel_count) return OCTGS_EINVAL;
+  if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
+  if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
+    return OCTGS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (a->n == 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, sel_count);
+    return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+  }
+  if (!a->pos || !a->thr2 || !a->bound_r || !ws) return OCTGS_EINVAL;
+  if (ws_bytes < octgs_select_workspace_bytes(a->n)) return OCTGS_ENOSPC;
+  const int64_t nblk = (a->n + kChunk - 1) / kChunk;
+  uint64_t *masks = (uint64_t *)ws;
+  uint32_t *blk = (uint32_t *)((char *)ws + nblk * (kChunk / 64) * 8);
+  hipLaunchKernelGGL(k_select_mark, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, *cam,
+                     a->pos, a->thr2, a->bound_r, masks, blk);
+  hipLaunchKernelGGL(k_select_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, masks,
+                     blk, sel_idx, sel_count);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+}  // extern "C"

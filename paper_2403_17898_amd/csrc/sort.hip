@@ -1,0 +1,206 @@
+// Stable LSD radix sort of (u32 key, u32 value) pairs, 8-bit digits, in the
+// Onesweep structure (Adinets and Merrill, "Onesweep: A Faster Least
+// Significant Digit Radix Sort for GPUs", 2022): one kernel builds the
+// digit histograms of all passes, then each pass is a single kernel whose
+// blocks take partitions in the order they start (an atomic ticket), rank
+// keys locally and resolve the global digit offsets with a decoupled
+// look-back over the preceding partitions.
+//
+// CDNA4 specifics: local ranking is done per 64-lane wavefront with eight
+// ballots per item (a match-any on the digit bits); each wave owns a
+// contiguous run of the partition so ranks stay stable; look-back status
+// words are device-scope relaxed atomics, and every wait is bounded.
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1;
+
+// Histogram of every pass at once, plus clearing of the look-back words the
+// passes will use.  Grid-stride over the keys.
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint32_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ count,
+                                                      int passes, uint32_t *__restrict__ hist,
+                                                      uint32_t *__restrict__ lookback,
+                                                      uint64_t lb_stride) {
+  __shared__ uint32_t h[4][256];
+  const uint32_t n = *count;
+  const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+  // clear the look-back words of the partitions each pass will use
+  const uint64_t nlb = (uint64_t)nparts * 256u;
+  for (int p = 0; p < passes; ++p)
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nlb;
+         i += (uint64_t)gridDim.x * kBlock)
+      lookback[lb_stride * p + i] = 0u;
+  for (int i = threadIdx.x; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    uint32_t k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p) {
+    uint32_t v = h[p][threadIdx.x];
+    if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
+  }
+}
+
+struct PassSmem {
+  uint32_t wcnt[4][256];     // per-wave digit counters, then per-wave exclusive offsets
+  uint32_t dstart[256];      // local start of each digit in the partition
+  uint32_t gbase[256];       // global write base of each digit for this partition
+  uint32_t hexcl[256];       // global exclusive prefix of the pass histogram
+  uint32_t keys[kSortPart];
+  uint32_t vals[kSortPart];
+  uint32_t tmp[8];
+  uint32_t part;
+};
+
+__global__ __launch_bounds__(kBlock) void k_sort_pass(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const uint32_t *__restrict__ count,
+    int shift, const uint32_t *__restrict__ hist, uint32_t *__restrict__ lookback,
+    uint32_t *__restrict__ part_counter, uint32_t *__restrict__ err_flag) {
+  __shared__ PassSmem sm;
+  const uint32_t n = *count;
+  const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint64_t lt = lanemask_lt();
+
+  // exclusive scan of the pass histogram over digits
+  {
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(hist[t], sm.tmp, &tot);
+    sm.hexcl[t] = ex;
+  }
+
+  while (true) {
+    __syncthreads();
+    if (t == 0) sm.part = atomicAdd(part_counter, 1u);
+    for (int i = t; i < 4 * 256; i += kBlock) (&sm.wcnt[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t part = sm.part;
+    if (part >= nparts) break;
+    const uint32_t base = part * kSortPart;
+
+    // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    int dig[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
+      bool ok = idx < n;
+      key[j] = ok ? kin[idx] : 0u;
+      val[j] = ok ? vin[idx] : 0u;
+      dig[j] = ok ? (int)((key[j] >> shift) & 255u) : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int d = dig[j];
+      uint64_t peers = ballot(d >= 0);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        int bit = (d >> b) & 1;
+        uint64_t bal = ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      uint32_t before = 0;
+      if (d >= 0) before = sm.wcnt[w][d];
+      // all lanes of the wave have read before any leader writes
+      __builtin_amdgcn_wave_barrier();
+      if (d >= 0) {
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        if ((peers & lt) == 0) sm.wcnt[w][d] = before + (uint32_t)__popcll(peers);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // thread t owns digit t: per-wave exclusive offsets and the block total
+    uint32_t c0 = sm.wcnt[0][t], c1 = sm.wcnt[1][t], c2 = sm.wcnt[2][t], c3 = sm.wcnt[3][t];
+    uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t *lb = lookback + (size_t)part * 256u;
+    st_rel(&lb[t], (part == 0 ? kFlagInc : kFlagAgg) | tot);
+    uint32_t blk_tot;
+    uint32_t ds = block_excl_scan(tot, sm.tmp, &blk_tot);
+    sm.dstart[t] = ds;
+    sm.wcnt[0][t] = ds;
+    sm.wcnt[1][t] = ds + c0;
+    sm.wcnt[2][t] = ds + c0 + c1;
+    sm.wcnt[3][t] = ds + c0 + c1 + c2;
+
+    // decoupled look-back for digit t
+    uint32_t excl = 0;
+    if (part > 0) {
+      int64_t p = (int64_t)part - 1;
+      while (p >= 0) {
+        const uint32_t *q = lookback + (size_t)p * 256u + t;
+        uint32_t v = ld_acq(q);
+        uint32_t spins = 0;
+        while ((v & ~kValMask) == 0u && spins < kSpinLimit) {
+          __builtin_amdgcn_s_sleep(1);
+          v = ld_acq(q);
+          ++spins;
+        }
+        if ((v & ~kValMask) == 0u) {
+          atomicOr(err_flag, 1u);
+          break;
+        }
+        excl += v & kValMask;
+        if ((v & ~kValMask) == kFlagInc) break;
+        --p;
+      }
+      st_rel(&lb[t], kFlagInc | ((excl + tot) & kValMask));
+    }
+    sm.gbase[t] = sm.hexcl[t] + excl;
+    __syncthreads();
+
+    // place keys in LDS in local sorted order
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (dig[j] >= 0) {
+        uint32_t pos = sm.wcnt[w][dig[j]] + rank[j];
+        sm.keys[pos] = key[j];
+        sm.vals[pos] = val[j];
+      }
+    }
+    __syncthreads();
+    const uint32_t cnt = min((uint32_t)kSortPart, n - base);
+    for (uint32_t i = t; i < cnt; i += kBlock) {
+      uint32_t k = sm.keys[i];
+      uint32_t d = (k >> shift) & 255u;
+      uint32_t dst = sm.gbase[d] + (i - sm.dstart[d]);
+      if (dst < n) {  // always true unless a look-back wait hit its bound
+        kout[dst] = k;
+        vout[dst] = sm.vals[i];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
+                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *part_counter,
+                      uint32_t *err_flag, hipStream_t stream) {
+  if (passes <= 0) return hipSuccess;
+  const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
+  const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 1024);
+  const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
+  hipLaunchKernelGGL(k_sort_hist, dim3(hist_grid), dim3(kBlock), 0, stream, keys[0], count,
+                     passes, hist, lookback, (uint64_t)lb_stride);
+  const int pass_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 2048);
+  for (int p = 0; p < passes; ++p) {
+    const int src = p & 1, dst = src ^ 1;
+    hipLaunchKernelGGL(k_sort_pass, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
+                       vals[src], keys[dst], vals[dst], count, 8 * p, hist + 256 * p,
+                       lookback + lb_stride * p, part_counter + p, err_flag);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace octgs

@@ -1,0 +1,230 @@
+"""Device-side scene and per-view render driver over the C ABI.
+
+PyTorch allocates device memory and supplies the stream; every computation
+of the path runs in liboctgs kernels.  There is no CPU fallback: without a
+GPU or without the built library these classes raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+MLP_HEADS = ("a", "c", "s")  # opacity, colour, covariance
+GAUSS_FIELDS = 14
+
+
+def _dev() -> torch.device:
+    if not torch.cuda.is_available():
+        raise L.OctgsError("liboctgs needs a HIP device; none is visible")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def stream_handle(stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _events(events):
+    """ctypes array of hipEvent_t handles from torch.cuda.Event objects."""
+    if events is None:
+        return None
+    arr = (ctypes.c_void_p * len(events))()
+    for i, e in enumerate(events):
+        arr[i] = e.cuda_event if e is not None else None
+    return arr
+
+
+def make_camera(cam) -> L.Camera:
+    """octgs_camera from any object with R (3x3), C (3), fx, fy, cx, cy,
+    width, height, z_near and lod_scale (s of Eq. 7)."""
+    c = L.Camera()
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    C = np.asarray(cam.C, np.float32).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.C[i] = float(C[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.z_near = float(cam.z_near)
+    s = float(np.float32(getattr(cam, "lod_scale", 1.0)))
+    c.lod_scale2 = float(np.float32(s) * np.float32(s))
+    return c
+
+
+def raster_params(alpha_max=0.99, alpha_min=0.0, t_min=1e-4, dilation=0.3, jac_clamp=1.3,
+                  bg=(0.0, 0.0, 0.0)) -> L.RasterParams:
+    p = L.RasterParams()
+    p.alpha_max, p.alpha_min, p.t_min = alpha_max, alpha_min, t_min
+    p.dilation, p.jac_clamp = dilation, jac_clamp
+    for i in range(3):
+        p.bg[i] = bg[i]
+    return p
+
+
+class DeviceScene:
+    """An anchor set resident in HBM, with its per-scene Eq. 7 thresholds."""
+
+    def __init__(self, pos, level, lod_bias, feat, offsets, offset_scale, base_scale, mlp: Dict,
+                 d_max: float, n_levels: int, k: int, width: int, stream=None):
+        dev = _dev()
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.n = int(np.asarray(pos).shape[0])
+        self.k, self.width, self.n_levels = int(k), int(width), int(n_levels)
+        self.feat_dim = int(np.asarray(feat).shape[1])
+        self.d_max = float(np.float32(d_max))
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(**f32)
+        self.pos = t(pos)
+        self.level = torch.as_tensor(np.ascontiguousarray(level, np.uint8)).to(dev)
+        self.lod_bias = t(lod_bias)
+        self.feat = t(feat)
+        # BF16 copy for the fast path (round to nearest even)
+        self.feat_bf16 = self.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+        self.offsets = t(offsets)
+        self.offset_scale = t(offset_scale)
+        self.base_scale = t(base_scale)
+        self.mlp = {kk: t(v) for kk, v in mlp.items()}
+        self.thr2 = torch.empty(self.n, **f32)
+        self.bound_r = torch.empty(self.n, **f32)
+        self._anchors = self._make_anchors()
+        L.check(L.lib().octgs_prepare_anchors(ctypes.byref(self._anchors), _ptr(self.thr2),
+                                             _ptr(self.bound_r), stream_handle(stream)),
+                "octgs_prepare_anchors")
+        self._anchors = self._make_anchors()
+        self._mlp = L.Mlp()
+        self._mlp.width = self.width
+        for h, name in enumerate(MLP_HEADS):
+            self._mlp.w1[h] = self.mlp["w1_" + name].data_ptr()
+            self._mlp.b1[h] = self.mlp["b1_" + name].data_ptr()
+            self._mlp.w2[h] = self.mlp["w2_" + name].data_ptr()
+            self._mlp.b2[h] = self.mlp["b2_" + name].data_ptr()
+
+    @classmethod
+    def from_scene(cls, sc, stream=None) -> "DeviceScene":
+        return cls(sc.pos, sc.level, sc.lod_bias, sc.feat, sc.offsets, sc.offset_scale,
+                   sc.base_scale, sc.mlp, sc.d_max, sc.n_levels, sc.k, sc.width, stream)
+
+    def _make_anchors(self) -> L.Anchors:
+        a = L.Anchors()
+        a.n, a.k, a.feat_dim, a.n_levels, a.d_max = self.n, self.k, self.feat_dim, self.n_levels, self.d_max
+        a.pos = self.pos.data_ptr() if self.n else None
+        a.level = self.level.data_ptr() if self.n else None
+        a.lod_bias = self.lod_bias.data_ptr() if self.n else None
+        a.feat = self.feat.data_ptr() if self.n else None
+        a.feat_bf16 = self.feat_bf16.data_ptr() if self.n else None
+        a.offsets = self.offsets.data_ptr() if self.n else None
+        a.offset_scale = self.offset_scale.data_ptr() if self.n else None
+        a.base_scale = self.base_scale.data_ptr() if self.n else None
+        a.thr2 = getattr(self, "thr2", None).data_ptr() if hasattr(self, "thr2") and self.n else None
+        a.bound_r = self.bound_r.data_ptr() if hasattr(self, "bound_r") and self.n else None
+        return a
+
+    @property
+    def anchors(self) -> L.Anchors:
+        return self._anchors
+
+
+class ViewBuffers:
+    """Per-view device buffers: selection, decoded Gaussians, rasterizer
+    workspace and outputs, sized for a scene, an image and a pair capacity."""
+
+    def __init__(self, n_anchors: int, k: int, width: int, height: int, pair_capacity: int,
+                 gauss_capacity: Optional[int] = None, log_weights: bool = False):
+        dev = _dev()
+        lib = L.lib()
+        self.n, self.k, self.W, self.H = int(n_anchors), int(k), int(width), int(height)
+        self.gcap = int(gauss_capacity if gauss_capacity is not None else max(1, self.n) * k)
+        self.pcap = int(pair_capacity)
+        self.sel_idx = torch.empty(max(1, self.n), dtype=torch.int32, device=dev)
+        self.sel_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        sw = lib.octgs_select_workspace_bytes(self.n)
+        self.sel_ws = torch.empty(max(256, sw), dtype=torch.uint8, device=dev)
+        self.gauss = torch.empty((GAUSS_FIELDS, self.gcap), dtype=torch.float32, device=dev)
+        self.gauss_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        rw = lib.octgs_raster_workspace_bytes(self.gcap, self.pcap, self.W, self.H)
+        if rw == 0:
+            raise L.OctgsError("bad rasterizer sizes")
+        self.ras_ws = torch.empty(rw, dtype=torch.uint8, device=dev)
+        self.rgb = torch.empty((3, self.H, self.W), dtype=torch.float32, device=dev)
+        self.T = torch.empty((self.H, self.W), dtype=torch.float32, device=dev)
+        self.last = torch.empty((self.H, self.W), dtype=torch.int32, device=dev)
+        self.gauss_w = torch.empty(self.gcap, dtype=torch.float32, device=dev) if log_weights else None
+        self._g = L.Gaussians()
+        self._g.capacity = self.gcap
+        self._g.data = self.gauss.data_ptr()
+        self._g.count = self.gauss_count.data_ptr()
+
+    # ---- stages ----
+    def select(self, scene: DeviceScene, cam: L.Camera, stream=None):
+        L.check(L.lib().octgs_select_lod(ctypes.byref(scene.anchors), ctypes.byref(cam),
+                                         _ptr(self.sel_idx), _ptr(self.sel_count),
+                                         _ptr(self.sel_ws), self.sel_ws.numel(),
+                                         stream_handle(stream)), "octgs_select_lod")
+
+    def decode(self, scene: DeviceScene, cam: L.Camera, precision: int = L.OCTGS_FP32,
+               idx: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None,
+               stream=None):
+        idx = self.sel_idx if idx is None else idx
+        count = self.sel_count if count is None else count
+        L.check(L.lib().octgs_decode(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                     ctypes.byref(cam), _ptr(idx), _ptr(count), int(precision),
+                                     ctypes.byref(self._g), stream_handle(stream)), "octgs_decode")
+
+    def rasterize(self, cam: L.Camera, params: L.RasterParams, gauss: Optional[torch.Tensor] = None,
+                  count: Optional[torch.Tensor] = None, stream=None, stage_events=None):
+        g = self._g
+        if gauss is not None:
+            g = L.Gaussians()
+            g.capacity = gauss.shape[1]
+            g.data = gauss.data_ptr()
+            g.count = count.data_ptr()
+            if gauss.shape[1] != self.gcap:
+                raise L.OctgsError("Gaussian buffer capacity must equal the workspace capacity")
+        L.check(L.lib().octgs_rasterize_fwd(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(params),
+                                            self.pcap, _ptr(self.rgb), _ptr(self.T), _ptr(self.last),
+                                            _ptr(self.gauss_w), _ptr(self.ras_ws), self.ras_ws.numel(),
+                                            _events(stage_events), stream_handle(stream)),
+                "octgs_rasterize_fwd")
+
+    def render(self, scene: DeviceScene, cam: L.Camera, params: L.RasterParams,
+               precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
+        self.select(scene, cam, stream)
+        self.decode(scene, cam, precision, stream=stream)
+        self.rasterize(cam, params, stream=stream, stage_events=stage_events)
+
+    # ---- readback helpers (synchronise) ----
+    def stats(self) -> Dict[str, int]:
+        torch.cuda.synchronize()
+        h = self.ras_ws[:64].cpu().numpy().view(np.uint32)
+        return dict(n_slots=int(h[0]), n_visible=int(h[1]), n_pairs=int(h[2]),
+                    pair_overflow=int(h[3]), sync_error=int(h[4]), n_emitted=int(h[5]),
+                    n_selected=int(self.sel_count.item()))
+
+    def sorted_lists(self):
+        """(pair_tile, pair_slot, ranges) as CPU numpy arrays, after a forward."""
+        lib = L.lib()
+        st, pt, ps, rg = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        L.check(lib.octgs_raster_views(_ptr(self.ras_ws), self.gcap, self.pcap, self.W, self.H,
+                                       ctypes.byref(st), ctypes.byref(pt), ctypes.byref(ps),
+                                       ctypes.byref(rg)), "octgs_raster_views")
+        s = self.stats()
+        P = s["n_emitted"]
+        base = self.ras_ws.data_ptr()
+        ws32 = self.ras_ws.view(torch.int32)
+
+        def view(ptr, n):
+            off = (ptr.value - base) // 4
+            return ws32[off:off + n].cpu().numpy().view(np.uint32).copy()
+
+        ntiles = ((self.W + 15) // 16) * ((self.H + 15) // 16)
+        return view(pt, P), view(ps, P), view(rg, 2 * ntiles).reshape(ntiles, 2)

@@ -1,0 +1,95 @@
+"""Helpers for the GPU parity tests: device uploads, error bounds, reporting."""
+
+import math
+import sys
+
+import numpy as np
+
+U32 = 2.0 ** -24   # unit roundoff, FP32
+UBF = 2.0 ** -8    # unit roundoff, BF16 (8-bit significand)
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def decode_bounds(scene, idx, cam, bf16: bool):
+    """Element-wise bound on |decode_gpu - decode_exact| for the pre-activation
+    outputs of each head, from the standard dot-product error bound
+    |fl(w.x) - w.x| <= gamma_K sum |w||x| (gamma_K = K u / (1 - K u)), applied
+    to both layers, plus the input and weight rounding to BF16 on that path.
+    Returns (bound_a [m, k], bound_c [m, 3k], bound_s [m, 7k]) in float64."""
+    F = scene.feat_dim
+    pos = scene.pos[idx].astype(np.float64)
+    d = pos - cam.C.astype(np.float64)[None]
+    dist = np.linalg.norm(d, axis=1)
+    x = np.concatenate([scene.feat[idx].astype(np.float64), (dist / scene.d_max)[:, None],
+                        d / dist[:, None]], axis=1)
+    ax = np.abs(x)
+    # the FP32 path forms dist and dir in FP32: a few ulps each
+    ex_in = np.zeros_like(x)
+    ex_in[:, F:] = 4 * U32 * ax[:, F:] + 4 * U32
+    if bf16:
+        ex_in = ex_in + UBF * ax
+    out = []
+    raw = {}
+    for h in ("a", "c", "s"):
+        w1 = scene.mlp["w1_" + h].astype(np.float64)
+        b1 = scene.mlp["b1_" + h].astype(np.float64)
+        w2 = scene.mlp["w2_" + h].astype(np.float64)
+        b2 = scene.mlp["b2_" + h].astype(np.float64)
+        K1, W = w1.shape
+        aw1 = np.abs(w1)
+        hpre = x @ w1 + b1
+        hid = np.maximum(hpre, 0)
+        s1 = ax @ aw1 + np.abs(b1)
+        g1 = (K1 + 2) * U32 / (1 - (K1 + 2) * U32)
+        eh = g1 * s1 + ex_in @ aw1
+        if bf16:
+            eh = eh + UBF * (ax @ aw1)          # weight rounding
+            eh = eh + UBF * (np.abs(hid) + eh)  # hidden rounded to BF16
+        aw2 = np.abs(w2)
+        s2 = (np.abs(hid) + eh) @ aw2 + np.abs(b2)
+        g2 = (W + 2) * U32 / (1 - (W + 2) * U32)
+        ey = g2 * s2 + eh @ aw2
+        if bf16:
+            ey = ey + UBF * ((np.abs(hid) + eh) @ aw2)
+        out.append(ey)
+        raw[h] = hid @ w2 + b2
+    out.append(raw)
+    return out
+
+
+def decoded_field_bounds(scene, idx, cam, gd, bf16: bool):
+    """Per-element bound [14][m*k] on the decoded Gaussian fields: tanh and
+    sigmoid are 1- and 1/4-Lipschitz; scale = base_scale * sigmoid; the
+    normalised quaternion moves by at most 2 |dq| / |q|; the mean is one fused
+    multiply-add (half an ulp); 16 ulps cover each FP32 activation."""
+    k = scene.k
+    m = len(idx)
+    G = m * k
+    ba, bc, bs, raw = decode_bounds(scene, idx, cam, bf16)
+    act = 16 * U32
+    out = np.zeros((14, G))
+    out[10] = ba.reshape(G) + act
+    out[11:14] = (0.25 * bc.reshape(m, k, 3) + act).reshape(G, 3).T
+    bsx = bs.reshape(m, k, 7)
+    base = np.repeat(scene.base_scale[idx].astype(np.float64), k, axis=0)  # [G, 3]
+    out[3:6] = (base * (0.25 * bsx[:, :, 0:3].reshape(G, 3) + act)).T
+    qerr = np.linalg.norm(bsx[:, :, 3:7].reshape(G, 4), axis=1)
+    qraw = np.linalg.norm(raw["s"].reshape(m, k, 7)[:, :, 3:7].reshape(G, 4), axis=1)
+    out[6:10] = np.broadcast_to(2 * qerr / np.maximum(qraw - qerr, 1e-30) + act, (4, G))
+    out[0:3] = np.abs(gd[0:3]) * U32 * 1.01
+    return out
+
+
+def report(name, gpu, ref, tol):
+    diff = np.abs(np.asarray(gpu, np.float64) - np.asarray(ref, np.float64))
+    say(f"{name}: max abs err {diff.max() if diff.size else 0:.3e} (tol {tol:.1e})")
+    return diff

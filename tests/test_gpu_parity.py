@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: selections, tile lists and ranges bit-exact; FP32 images within 1e-4
+max-abs; decoded attributes within the FP32 / BF16 dot-product error bounds
+derived in gpu_util.decode_bounds.  Every input comes from the seeded
+generators (synth) or from the oracle; nothing the oracle reads comes from
+the GPU.
+"""
+
+import numpy as np
+import pytest
+
+from synth import scenes as S
+from tests.gpu_util import decoded_field_bounds, psnr, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_17898_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return S.make_config1()
+
+
+def _cams_c1():
+    base = S.config1_camera()
+    d = np.array([1.0, -2.0, 1.5]) / np.linalg.norm([1.0, -2.0, 1.5])
+    cams = [base]
+    for dist in (18.0, 9.0, 4.0):  # closer cameras reach levels 1 and 2
+        cams.append(S.look_at(dist * d, (0, 0, 0), 128, 128, 60.0))
+    cams.append(S.look_at((0.0, 0.0, 40.0), (0.0, 0.0, 80.0), 128, 128, 60.0))  # looks away
+    cams.append(S.look_at((2.0, -3.0, 1.0), (0.0, 0.0, 0.0), 97, 61, 70.0))    # ragged size
+    return cams
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_prepare_bit_exact(P, orc, c1):
+    rng = np.random.default_rng(5)
+    sc = c1
+    bias = rng.uniform(-0.5, 0.5, sc.n).astype(np.float32)
+    for b in (sc.lod_bias, bias):
+        say("prepare", "bias" if b is bias else "zero-bias", sc.n)
+        ds = P.DeviceScene(sc.pos, sc.level, b, sc.feat, sc.offsets, sc.offset_scale,
+                           sc.base_scale, sc.mlp, sc.d_max, sc.n_levels, sc.k, sc.width)
+        torch.cuda.synchronize()
+        thr = orc.lod_thr2(sc.level, b, sc.d_max)
+        rho = orc.bound_radius(sc.offsets, sc.offset_scale, sc.base_scale)
+        assert np.array_equal(_np(ds.thr2).view(np.uint32), thr.view(np.uint32))
+        assert np.array_equal(_np(ds.bound_r).view(np.uint32), rho.view(np.uint32))
+
+
+def test_select_bit_exact_c1(P, orc, c1):
+    sc = c1
+    ds = P.DeviceScene.from_scene(sc)
+    thr, rho = orc.scene_thresholds(sc)
+    for i, cam in enumerate(_cams_c1()):
+        say("select c1 camera", i)
+        vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
+        vb.select(ds, P.make_camera(cam))
+        torch.cuda.synchronize()
+        m = int(vb.sel_count.item())
+        got = _np(vb.sel_idx[:m]).astype(np.int64)
+        ref = orc.select(sc, cam, thr, rho)
+        assert np.array_equal(got, ref), (i, m, len(ref))
+    assert True
+
+
+def test_select_bit_exact_random_bias(P, orc):
+    rng = np.random.default_rng(2)
+    n, K = 300_001, 7
+    pos = rng.uniform(-100, 100, (n, 3)).astype(np.float32)
+    level = rng.integers(0, K, n).astype(np.uint8)
+    bias = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    k = 4
+    offsets = rng.normal(0, 0.5, (n, k, 3)).astype(np.float32)
+    osc = np.exp(rng.uniform(-2, 0, (n, 3))).astype(np.float32)
+    bsc = np.exp(rng.uniform(-3, -1, (n, 3))).astype(np.float32)
+    mlp = S.xavier_mlp(rng, 36, 16, k)
+    feat = rng.standard_normal((n, 32)).astype(np.float32)
+    say("select random-bias", n)
+    ds = P.DeviceScene(pos, level, bias, feat, offsets, osc, bsc, mlp, 180.0, K, k, 16)
+    thr = orc.lod_thr2(level, bias, 180.0)
+    rho = orc.bound_radius(offsets, osc, bsc)
+    for seed in range(4):
+        cam = S.random_views(1, seed, 80.0, 5.0, 120.0, 640, 480)[0]
+        vb = P.ViewBuffers(n, k, 640, 480, 1 << 16, gauss_capacity=1024)
+        vb.select(ds, P.make_camera(cam))
+        torch.cuda.synchronize()
+        m = int(vb.sel_count.item())
+        ref = np.flatnonzero(orc.select_mask(pos, thr, rho, cam))
+        assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref)
+        assert m > 0
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_decode_within_bounds(P, orc, c1, bf16):
+    sc = c1
+    cam = S.config1_camera()
+    idx = np.arange(3, sc.n, 5, dtype=np.int64)  # generator-chosen anchor list
+    say("decode", "bf16" if bf16 else "fp32", len(idx))
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    vb.decode(ds, P.make_camera(cam), P.OCTGS_BF16 if bf16 else P.OCTGS_FP32, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    G = len(idx) * sc.k
+    assert int(vb.gauss_count.item()) == G
+    got = _np(vb.gauss[:, :G]).astype(np.float64)
+    ref = orc.decode(sc, idx, cam)
+    bound = decoded_field_bounds(sc, idx, cam, ref, bf16)
+    err = np.abs(got - ref)
+    for f in range(14):
+        ratio = (err[f] / np.maximum(bound[f], 1e-30)).max()
+        say(f"  field {f}: max err {err[f].max():.2e}  max err/bound {ratio:.3f}")
+    assert np.all(err <= bound), np.argwhere(err > bound)[:5]
+
+
+def _gpu_raster(P, vb, gf, cam, prm):
+    gt = torch.as_tensor(gf).cuda()
+    cnt = torch.tensor([gf.shape[1]], dtype=torch.int32).cuda()
+    vb.rasterize(P.make_camera(cam), prm, gauss=gt, count=cnt)
+    torch.cuda.synchronize()
+
+
+CASES = [(64, 64, 300, 1), (128, 128, 3000, 2), (97, 61, 1500, 3), (333, 200, 20000, 4),
+         (1600, 1066, 60000, 5)]
+
+
+@pytest.mark.parametrize("W,H,n,seed", CASES)
+def test_raster_stage_parity(P, orc, W, H, n, seed):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
+    gf = S.random_gaussians(n, cam, seed, scale=(0.01, 0.4), neg_opacity_frac=0.1,
+                            behind_frac=0.05)
+    prm_o = orc.params_array()
+    say("raster stage", W, H, n, seed)
+    ref = orc.rasterize(gf, cam, prm_o, weights=True)
+    P_ref = ref["bs"]["n_pairs"]
+    vb = P.ViewBuffers(n, 1, W, H, max(P_ref, 1) + 7, gauss_capacity=n, log_weights=True)
+    _gpu_raster(P, vb, gf, cam, P.raster_params())
+    st = vb.stats()
+    assert st["sync_error"] == 0 and st["pair_overflow"] == 0
+    assert st["n_visible"] == ref["pj"]["n_visible"]
+    assert st["n_pairs"] == P_ref
+    tile, slot, ranges = vb.sorted_lists()
+    assert np.array_equal(tile, ref["bs"]["tile_of"])
+    assert np.array_equal(slot, ref["bs"]["gid_of"])
+    assert np.array_equal(ranges, ref["bs"]["ranges"])
+    img = _np(vb.rgb).astype(np.float64)
+    T = _np(vb.T).astype(np.float64)
+    e_img = np.abs(img - ref["img"]).max()
+    e_T = np.abs(T - ref["T"]).max()
+    same_last = np.mean(_np(vb.last) == ref["last"])
+    say(f"  img max abs {e_img:.2e}  PSNR {psnr(img, ref['img']):.1f} dB  T max abs {e_T:.2e}"
+        f"  last equal {same_last:.6f}")
+    assert e_img <= 1e-4 and e_T <= 1e-4
+    assert same_last >= 0.999
+    w = _np(vb.gauss_w).astype(np.float64)
+    np.testing.assert_allclose(w, ref["weights"], rtol=2e-4, atol=2e-4)
+
+
+def test_raster_equal_depths(P, orc):
+    cam = S.look_at((0.0, 0.0, -10.0), (0.0, 0.0, 0.0), 64, 64, 60.0)
+    gf = S.tile_aligned_gaussians(cam, [5.0] * 40 + [7.0] * 40, seed=3)
+    say("raster equal depths")
+    ref = orc.rasterize(gf, cam, orc.params_array())
+    vb = P.ViewBuffers(80, 1, 64, 64, 4096, gauss_capacity=80)
+    _gpu_raster(P, vb, gf, cam, P.raster_params())
+    tile, slot, ranges = vb.sorted_lists()
+    assert np.array_equal(slot, ref["bs"]["gid_of"])
+    assert np.abs(_np(vb.rgb) - ref["img"]).max() <= 1e-4
+
+
+def test_end_to_end_c1(P, orc, c1):
+    sc = c1
+    ds = P.DeviceScene.from_scene(sc)
+    prm = P.raster_params()
+    thr, rho = orc.scene_thresholds(sc)
+    for prec in (P.OCTGS_FP32, P.OCTGS_BF16):
+        for i, cam in enumerate(_cams_c1()[:4]):
+            say("end-to-end c1", "bf16" if prec else "fp32", i)
+            vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 18)
+            vb.render(ds, P.make_camera(cam), prm, precision=prec)
+            torch.cuda.synchronize()
+            ref = orc.render(sc, cam, orc.params_array(), thr, rho)
+            m = int(vb.sel_count.item())
+            assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
+            img = _np(vb.rgb).astype(np.float64)
+            err = np.abs(img - ref["img"])
+            p = psnr(img, ref["img"])
+            say(f"  max abs {err.max():.2e} PSNR {p:.1f} dB  pixels > 1e-4: {(err > 1e-4).sum()}")
+            if prec == P.OCTGS_FP32:
+                assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+            else:
+                assert p >= 40.0
+
+
+def test_zero_anchors_and_zero_selected(P, orc):
+    say("zero anchors")
+    k = 2
+    rng = np.random.default_rng(0)
+    mlp = S.xavier_mlp(rng, 36, 16, k)
+    e = np.zeros((0, 3), np.float32)
+    ds = P.DeviceScene(e, np.zeros(0, np.uint8), np.zeros(0, np.float32), np.zeros((0, 32), np.float32),
+                       np.zeros((0, k, 3), np.float32), e, e, mlp, 10.0, 1, k, 16)
+    cam = S.look_at((0, -5, 0), (0, 0, 0), 48, 40, 60.0)
+    vb = P.ViewBuffers(0, k, 48, 40, 1024, gauss_capacity=16)
+    vb.render(ds, P.make_camera(cam), P.raster_params(bg=(0.25, 0.5, 0.75)))
+    torch.cuda.synchronize()
+    assert int(vb.sel_count.item()) == 0
+    img = _np(vb.rgb)
+    for c, v in enumerate((0.25, 0.5, 0.75)):
+        assert np.all(img[c] == np.float32(v))
+    assert np.all(_np(vb.T) == 1.0) and np.all(_np(vb.last) == 0)
+
+
+def test_all_behind_near_plane(P, orc):
+    cam = S.look_at((0, 0, 0), (0, 0, 10), 64, 64, 60.0)
+    gf = S.random_gaussians(500, cam, 1, behind_frac=1.0)
+    say("all behind")
+    vb = P.ViewBuffers(500, 1, 64, 64, 1024, gauss_capacity=500)
+    _gpu_raster(P, vb, gf, cam, P.raster_params())
+    st = vb.stats()
+    assert st["n_visible"] == 0 and st["n_pairs"] == 0
+    assert np.all(_np(vb.rgb) == 0.0)
+
+
+def test_pair_overflow_flag(P, orc):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), 128, 128, 60.0)
+    gf = S.random_gaussians(2000, cam, 7)
+    ref = orc.rasterize(gf, cam, orc.params_array())
+    say("pair overflow")
+    vb = P.ViewBuffers(2000, 1, 128, 128, ref["bs"]["n_pairs"] // 2, gauss_capacity=2000)
+    _gpu_raster(P, vb, gf, cam, P.raster_params())
+    st = vb.stats()
+    assert st["pair_overflow"] == 1 and st["n_pairs"] == ref["bs"]["n_pairs"]
+    assert st["n_emitted"] == 0
+
+
+def test_degenerate_quaternion_decodes_to_identity(P, orc, c1):
+    sc = S.make_config1()
+    for key in ("w1_s", "b1_s", "w2_s", "b2_s"):
+        sc.mlp[key][:] = 0.0
+    cam = S.config1_camera()
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
+    idx = torch.arange(0, 64, dtype=torch.int32).cuda()
+    cnt = torch.tensor([64], dtype=torch.int32).cuda()
+    say("degenerate quaternion")
+    vb.decode(ds, P.make_camera(cam), P.OCTGS_FP32, idx=idx, count=cnt)
+    torch.cuda.synchronize()
+    q = _np(vb.gauss[6:10, :64 * sc.k])
+    assert np.all(q[0] == 1.0) and np.all(q[1:] == 0.0)
+    np.testing.assert_allclose(_np(vb.gauss[3:6, :64 * sc.k]),
+                               0.5 * np.repeat(sc.base_scale[:64], sc.k, axis=0).T, rtol=1e-6)
+
+
+def test_invalid_arguments_rejected(P):
+    import ctypes
+    from paper_2403_17898_amd import _lib as L
+    lib = L.lib()
+    assert lib.octgs_select_lod(None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
+    assert lib.octgs_raster_workspace_bytes(-1, 0, 10, 10) == 0
+    g = L.Gaussians()
+    assert lib.octgs_rasterize_fwd(ctypes.byref(g), None, None, 0, None, None, None, None, None, 0,
+                                   None, None) == L.OCTGS_EINVAL
