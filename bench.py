@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=3, help="views the CPU oracle renders")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the PSNR sweep (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -67,6 +69,15 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 x 256 MiB device-to-device copies")
+        del src, dst
 
     t0 = time.time()
     sc = S.make_config2()

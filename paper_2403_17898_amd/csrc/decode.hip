@@ -333,7 +333,8 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   a.idx = idx; a.count = count; a.out = out->data; a.cap = out->capacity;
   a.out_count = out->count;
   const int64_t tiles = std::max<int64_t>(1, (a.cap_anchors + kTM - 1) / kTM);
-  const int grid = (int)std::min<int64_t>(tiles, 2048);
+  // persistent blocks: each loads its weight slices once and loops over tiles
+  const int grid = (int)std::min<int64_t>(tiles, 512);
   hipStream_t s = (hipStream_t)stream;
   if (precision == OCTGS_BF16)
     hipLaunchKernelGGL(k_decode<true>, dim3(grid), dim3(kBlock), 0, s, a);

@@ -16,10 +16,11 @@ namespace octgs {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per block in every kernel
 constexpr int kTile = 16;            // screen tile edge in pixels
-constexpr int kChunk = 4096;         // elements per block in the two-pass compactions
-constexpr int kChunkPerThread = kChunk / kBlock;  // 16
+constexpr int kChunk = 1024;         // elements per block in the two-pass compactions
+constexpr int kChunkPerThread = kChunk / kBlock;  // 4
+constexpr int kGroups = kChunk / 64;              // 64-element ballot groups per block
 constexpr int kGaussFields = 14;
-constexpr int kProjFields = 9;       // mx, my, conic a, b, c, opacity, r, g, b
+constexpr int kProjVec = 3;          // float4 records per projected Gaussian
 constexpr int kMaxK = 16;
 
 // ---------------------------------------------------------------------------
@@ -112,7 +113,8 @@ struct RasterWs {
   RasterHeader *hdr;
   uint64_t *vis_mask;     // [gcap / 64]
   uint32_t *blk_cnt;      // [nblk_g]
-  float *proj;            // [9][gcap]
+  float4 *proj;           // [gcap][3]: (mx, my, A, B) (C, opacity, r, g) (b, -, -, -);
+                          // A, B, C = conic scaled for exp2: -0.5 log2e ca, -log2e cb, -0.5 log2e cc
   uint32_t *depth;        // [gcap] float bits of camera z
   uint64_t *rect;         // [gcap] packed u16 x0, y0, x1, y1
   uint32_t *dkey[2];      // [gcap] depth-sort keys (ping-pong)

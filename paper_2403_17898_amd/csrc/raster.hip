@@ -168,7 +168,6 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
   if (blockIdx.x == 0 && t == 0) a.ws.hdr->n_slots = n;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   if (base >= n) return;
-  const int64_t cap = a.ws.gcap;
   uint32_t cnt = 0;
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t s = base + i * kBlock + t;
@@ -180,11 +179,10 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
       ProjOut o;
       vis = project_decide(a.cam, a.dil, a.jc, a.tiles_x, a.tiles_y, g, o);
       if (vis) {
-        float *p = a.ws.proj;
-        p[0 * cap + s] = o.mx; p[1 * cap + s] = o.my;
-        p[2 * cap + s] = o.ca; p[3 * cap + s] = o.cb; p[4 * cap + s] = o.cc;
-        p[5 * cap + s] = g[10]; p[6 * cap + s] = g[11]; p[7 * cap + s] = g[12];
-        p[8 * cap + s] = g[13];
+        float4 *p = a.ws.proj + 3 * s;
+        p[0] = make_float4(o.mx, o.my, -0.5f * kLog2e * o.ca, -kLog2e * o.cb);
+        p[1] = make_float4(-0.5f * kLog2e * o.cc, g[10], g[11], g[12]);
+        p[2] = make_float4(g[13], 0.0f, 0.0f, 0.0f);
         a.ws.depth[s] = __float_as_uint(o.zc);
         a.ws.rect[s] = pack_rect(o.x0, o.y0, o.x1, o.y1);
       }
@@ -218,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
   for (int i = t; i < b; i += kBlock) s += ws.blk_cnt[i];
   s = wave_sum(s);
   if (l == 0) red[w] = s;
-  const int ngroups = (int)min<int64_t>(64, ((int64_t)n - base + 63) / 64);
+  const int ngroups = (int)min<int64_t>(kGroups, ((int64_t)n - base + 63) / 64);
   if (w == 0) {
     const uint64_t m = l < ngroups ? ws.vis_mask[(base >> 6) + l] : 0ull;
     const uint32_t c = (uint32_t)__popcll(m);
@@ -369,10 +367,14 @@ struct CompArgs {
   float *gauss_w;
 };
 
-template <bool LOG>
-__global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
-  __shared__ float s_mx[kBlock], s_my[kBlock], s_ca[kBlock], s_cb[kBlock], s_cc[kBlock];
-  __shared__ float s_op[kBlock], s_r[kBlock], s_g[kBlock], s_b[kBlock];
+// One 16x16 tile per 256-thread block, one pixel per thread.  Batches of
+// 256 list entries are staged in LDS as two float4 and one float per
+// Gaussian; the per-pixel loop is branch-free (lanes that are done blend
+// alpha 0) so a wave only branches on wave-uniform conditions.
+template <bool LOG, bool AMIN>
+__device__ __forceinline__ void composite_tile(const CompArgs &a) {
+  __shared__ float4 sA[kBlock], sB[kBlock];
+  __shared__ float sC[kBlock];
   __shared__ uint32_t s_slot[kBlock];
   __shared__ float s_w[LOG ? kBlock : 1];
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
@@ -384,66 +386,44 @@ __global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
   const uint32_t *vals = a.ws.tval[a.buf];
-  const float *proj = a.ws.proj;
-  const int64_t cap = a.ws.gcap;
+  const float4 *proj = a.ws.proj;
+  const float amax = a.alpha_max, amin = a.alpha_min, tmin = a.t_min;
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
-  uint32_t last = 0;
+  uint32_t last = end - start;
   bool done = !inside;
   for (uint32_t b0 = start; b0 < end; b0 += kBlock) {
     const uint32_t e = b0 + t;
     if (e < end) {
       const uint32_t s = vals[e];
       s_slot[t] = s;
-      s_mx[t] = proj[s];
-      s_my[t] = proj[cap + s];
-      s_ca[t] = -0.5f * kLog2e * proj[2 * cap + s];
-      s_cb[t] = -kLog2e * proj[3 * cap + s];
-      s_cc[t] = -0.5f * kLog2e * proj[4 * cap + s];
-      s_op[t] = proj[5 * cap + s];
-      s_r[t] = proj[6 * cap + s];
-      s_g[t] = proj[7 * cap + s];
-      s_b[t] = proj[8 * cap + s];
+      sA[t] = proj[3 * (size_t)s];
+      sB[t] = proj[3 * (size_t)s + 1];
+      sC[t] = proj[3 * (size_t)s + 2].x;
     }
     if (LOG) s_w[t] = 0.0f;
     __syncthreads();
     const int nb = (int)min((uint32_t)kBlock, end - b0);
-    if (LOG) {
-      // uniform loop: every lane steps through the batch for the wave sums
-      for (int j = 0; j < nb; ++j) {
-        float wt = 0.0f;
-        if (!done) {
-          const float dx = fx - s_mx[j], dy = fy - s_my[j];
-          const float pw = fma_(s_ca[j] * dx, dx, fma_(s_cc[j] * dy, dy, s_cb[j] * dx * dy));
-          const float al = fminf(a.alpha_max, s_op[j] * __builtin_amdgcn_exp2f(pw));
-          last = b0 - start + j + 1;
-          if (!(al < a.alpha_min)) {
-            wt = al * T;
-            cr = fma_(wt, s_r[j], cr);
-            cg = fma_(wt, s_g[j], cg);
-            cbl = fma_(wt, s_b[j], cbl);
-            T = T * (1.0f - al);
-            if (T < a.t_min) done = true;
-          }
-        }
+    const uint32_t base = b0 - start + 1u;
+    for (int j = 0; j < nb; ++j) {
+      if (!LOG && (j & 15) == 0 && __all(done)) break;
+      const float4 A = sA[j];
+      const float4 B = sB[j];
+      const float dx = fx - A.x, dy = fy - A.y;
+      const float pw = fma_(A.z * dx, dx, fma_(B.x * dy, dy, A.w * dx * dy));
+      float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(pw));
+      if (AMIN) al = al < amin ? 0.0f : al;
+      al = done ? 0.0f : al;
+      const float wt = al * T;
+      cr = fma_(wt, B.z, cr);
+      cg = fma_(wt, B.w, cg);
+      cbl = fma_(wt, sC[j], cbl);
+      T = T - wt;
+      const bool term = !done && T < tmin;
+      last = term ? base + (uint32_t)j : last;
+      done = done || term;
+      if (LOG) {
         const float ws = wave_sum_f(wt);
         if (__lane_id() == 0 && ws != 0.0f) atomicAdd(&s_w[j], ws);
-      }
-    } else if (!done) {
-      for (int j = 0; j < nb; ++j) {
-        const float dx = fx - s_mx[j], dy = fy - s_my[j];
-        const float pw = fma_(s_ca[j] * dx, dx, fma_(s_cc[j] * dy, dy, s_cb[j] * dx * dy));
-        const float al = fminf(a.alpha_max, s_op[j] * __builtin_amdgcn_exp2f(pw));
-        last = b0 - start + j + 1;
-        if (al < a.alpha_min) continue;
-        const float wt = al * T;
-        cr = fma_(wt, s_r[j], cr);
-        cg = fma_(wt, s_g[j], cg);
-        cbl = fma_(wt, s_b[j], cbl);
-        T = T * (1.0f - al);
-        if (T < a.t_min) {
-          done = true;
-          break;
-        }
       }
     }
     if (LOG) {
@@ -460,6 +440,14 @@ __global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
     a.T_final[pix] = T;
     a.last[pix] = last;
   }
+}
+
+template <bool LOG>
+__global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
+  if (a.alpha_min > 0.0f)
+    composite_tile<LOG, true>(a);
+  else
+    composite_tile<LOG, false>(a);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -482,9 +470,9 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.tiles_y = (H + kTile - 1) / kTile;
   ws.nblk_g = (int)((g + kChunk - 1) / kChunk);
   ws.hdr = (RasterHeader *)take(sizeof(RasterHeader));
-  ws.vis_mask = (uint64_t *)take((size_t)ws.nblk_g * 64 * 8);
+  ws.vis_mask = (uint64_t *)take((size_t)ws.nblk_g * kGroups * 8);
   ws.blk_cnt = (uint32_t *)take((size_t)ws.nblk_g * 4);
-  ws.proj = (float *)take((size_t)kProjFields * g * 4);
+  ws.proj = (float4 *)take((size_t)kProjVec * g * 16);
   ws.depth = (uint32_t *)take((size_t)g * 4);
   ws.rect = (uint64_t *)take((size_t)g * 8);
   for (int i = 0; i < 2; ++i) ws.dkey[i] = (uint32_t *)take((size_t)g * 4);

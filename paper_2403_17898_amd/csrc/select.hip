@@ -82,7 +82,7 @@ __device__ __forceinline__ bool anchor_selected(const octgs_camera &c, const Fru
   return true;
 }
 
-// Pass 1: block b tests anchors [b*4096, (b+1)*4096) with coalesced loads,
+// Pass 1: block b tests anchors [b*1024, (b+1)*1024) with coalesced loads,
 // stores one 64-bit ballot per 64 consecutive anchors and the block count.
 __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera cam,
                                                         const float *__restrict__ pos,
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera 
   if (t == 0) blk_cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// Pass 2: block b adds up the counts of blocks < b, scans its 64 ballots and
+// Pass 2: block b adds up the counts of blocks < b, scans its 16 ballots and
 // writes the selected indices in ascending order.
 __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
                                                            const uint64_t *__restrict__ masks,
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
   s = wave_sum(s);
   if (l == 0) red[w] = s;
   const int64_t base = (int64_t)b * kChunk;
-  const int ngroups = (int)min<int64_t>(64, (n - base + 63) / 64);
+  const int ngroups = (int)min<int64_t>(kGroups, (n - base + 63) / 64);
   if (w == 0) {
     uint64_t m = l < ngroups ? masks[(base >> 6) + l] : 0ull;
     uint32_t c = (uint32_t)__popcll(m);
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
   }
   __syncthreads();
   const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
-  // group g covers anchors base + 64 g + lane; four waves cover 16 groups each
+  // group g covers anchors base + 64 g + lane; the four waves take groups round-robin
   for (int g = w; g < ngroups; g += 4) {
     const uint64_t m = gmask[g];
     if ((m >> l) & 1ull) {

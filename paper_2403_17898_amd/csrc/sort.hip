@@ -19,6 +19,7 @@ namespace {
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
+constexpr int kLookWin = 16;
 
 // Histogram of every pass at once, plus clearing of the look-back words the
 // passes will use.  Grid-stride over the keys.
@@ -38,6 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint32_t *__restrict
       lookback[lb_stride * p + i] = 0u;
   for (int i = threadIdx.x; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
   __syncthreads();
+  if (blockIdx.x * kBlock >= n) return;  // no keys for this block
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     uint32_t k = keys[i];
     for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
@@ -70,6 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint64_t lt = lanemask_lt();
+
+  // blocks past the last partition leave before touching the ticket counter
+  if (blockIdx.x >= nparts) return;
 
   // exclusive scan of the pass histogram over digits
   {
@@ -133,26 +138,37 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     sm.wcnt[2][t] = ds + c0 + c1;
     sm.wcnt[3][t] = ds + c0 + c1 + c2;
 
-    // decoupled look-back for digit t
+    // decoupled look-back for digit t, reading a window of kLookWin
+    // predecessors per round trip (nearest first)
     uint32_t excl = 0;
     if (part > 0) {
       int64_t p = (int64_t)part - 1;
-      while (p >= 0) {
-        const uint32_t *q = lookback + (size_t)p * 256u + t;
-        uint32_t v = ld_acq(q);
-        uint32_t spins = 0;
-        while ((v & ~kValMask) == 0u && spins < kSpinLimit) {
-          __builtin_amdgcn_s_sleep(1);
-          v = ld_acq(q);
-          ++spins;
+      bool done = false;
+      while (!done && p >= 0) {
+        const int cnt = (int)min<int64_t>(kLookWin, p + 1);
+        uint32_t v[kLookWin];
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i)
+          v[i] = i < cnt ? ld_acq(lookback + (size_t)(p - i) * 256u + t) : 0u;
+#pragma unroll
+        for (int i = 0; i < kLookWin; ++i) {
+          if (done || i >= cnt) continue;
+          uint32_t s = v[i];
+          uint32_t spins = 0;
+          while ((s & ~kValMask) == 0u && spins < kSpinLimit) {
+            __builtin_amdgcn_s_sleep(1);
+            s = ld_acq(lookback + (size_t)(p - i) * 256u + t);
+            ++spins;
+          }
+          if ((s & ~kValMask) == 0u) {
+            atomicOr(err_flag, 1u);
+            done = true;
+            continue;
+          }
+          excl += s & kValMask;
+          if ((s & ~kValMask) == kFlagInc) done = true;
         }
-        if ((v & ~kValMask) == 0u) {
-          atomicOr(err_flag, 1u);
-          break;
-        }
-        excl += v & kValMask;
-        if ((v & ~kValMask) == kFlagInc) break;
-        --p;
+        p -= cnt;
       }
       st_rel(&lb[t], kFlagInc | ((excl + tot) & kValMask));
     }
@@ -189,7 +205,7 @@ hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *coun
                       uint32_t *err_flag, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
-  const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 1024);
+  const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 256);
   const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
   hipLaunchKernelGGL(k_sort_hist, dim3(hist_grid), dim3(kBlock), 0, stream, keys[0], count,
                      passes, hist, lookback, (uint64_t)lb_stride);
