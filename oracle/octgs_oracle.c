@@ -640,3 +640,307 @@ ORC_API int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ======================================================================
+ * Backward passes (double precision), for the training step of Sec. V
+ * (losses on rendered images) and the gradient checks.
+ * ====================================================================== */
+
+/* Compositing backward.  For each pixel the forward blend over its tile list
+ * is replayed (a_i, T_i), then walked in reverse:
+ *   dL/dc_i = a_i T_i dL/dC
+ *   dL/da_i = T_i (c_i . dL/dC) - (B_i . dL/dC) / (1 - a_i),
+ *     B_i = sum_{j>i} a_j T_j c_j + T_final bg  (colour behind entry i)
+ *   a_i = min(alpha_max, op_i G_i): no gradient to op_i or G_i when clamped
+ *   G_i = exp(p_i), p_i = -0.5 (ca dx^2 + cc dy^2) - cb dx dy, dx = px - mx.
+ * dproj[9 * g + .] accumulates dmx, dmy, dca, dcb, dcc, dop, dr, dg, db. */
+ORC_API void orc_composite_backward(const uint32_t *gid_of, const uint32_t *ranges,
+                                    const double *proj, int W, int H, const float *prmf,
+                                    const double *dimg, double *dproj) {
+  prm_t pp = load_prm(prmf);
+  int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < tiles_x * tiles_y; ++t) {
+    int tx = t % tiles_x, ty = t / tiles_x;
+    uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+    int n = (int)(e - s);
+    double *aa = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *TT = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int yy = 0; yy < 16; ++yy)
+      for (int xx = 0; xx < 16; ++xx) {
+        int x = tx * 16 + xx, y = ty * 16 + yy;
+        if (x >= W || y >= H) continue;
+        double px = x + 0.5, py = y + 0.5;
+        size_t pix = (size_t)y * W + x;
+        double dC[3];
+        for (int c = 0; c < 3; ++c) dC[c] = dimg[(size_t)c * W * H + pix];
+        /* forward replay */
+        double T = 1.0;
+        int last = 0;
+        for (int i = 0; i < n; ++i) {
+          const double *p = proj + 9 * (size_t)gid_of[s + i];
+          double dx = px - p[0], dy = py - p[1];
+          double pw = -0.5 * (p[2] * dx * dx + p[4] * dy * dy) - p[3] * dx * dy;
+          double a = p[5] * exp(pw);
+          if (a > pp.alpha_max) a = pp.alpha_max;
+          last = i + 1;
+          if (a < pp.alpha_min) { aa[i] = -1; TT[i] = T; continue; }
+          aa[i] = a;
+          TT[i] = T;
+          T *= (1.0 - a);
+          if (T < pp.t_min) break;
+        }
+        /* reverse walk */
+        double B[3];
+        for (int c = 0; c < 3; ++c) B[c] = T * pp.bg[c];
+        for (int i = last - 1; i >= 0; --i) {
+          if (aa[i] < 0) continue;
+          uint32_t g = gid_of[s + i];
+          const double *p = proj + 9 * (size_t)g;
+          double a = aa[i], Ti = TT[i], w = a * Ti;
+          double cdot = 0, bdot = 0;
+          for (int c = 0; c < 3; ++c) { cdot += p[6 + c] * dC[c]; bdot += B[c] * dC[c]; }
+          double dLda = Ti * cdot - bdot / (1.0 - a);
+          double dx = px - p[0], dy = py - p[1];
+          double pw = -0.5 * (p[2] * dx * dx + p[4] * dy * dy) - p[3] * dx * dy;
+          double G = exp(pw);
+          double d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          for (int c = 0; c < 3; ++c) d[6 + c] = w * dC[c];
+          if (p[5] * G <= pp.alpha_max) {
+            double dG = dLda * p[5];
+            d[5] = dLda * G;
+            double dpw = dG * G;
+            d[2] = dpw * (-0.5 * dx * dx);
+            d[4] = dpw * (-0.5 * dy * dy);
+            d[3] = dpw * (-dx * dy);
+            /* dp/dmx = ca dx + cb dy, dp/dmy = cb dx + cc dy */
+            d[0] = dpw * (p[2] * dx + p[3] * dy);
+            d[1] = dpw * (p[3] * dx + p[4] * dy);
+          }
+          for (int c = 0; c < 3; ++c) B[c] += w * p[6 + c];
+          for (int q = 0; q < 9; ++q) {
+#pragma omp atomic
+            dproj[9 * (size_t)g + q] += d[q];
+          }
+        }
+      }
+    free(aa);
+    free(TT);
+  }
+}
+
+/* Projection backward for one Gaussian with double attributes g[14] (the
+ * forward of project_cont), from dL/d(mx, my, ca, cb, cc, op, r, g, b) to
+ * dL/d(mean, scale, quat, opacity, rgb).  The inverse 2x2 covariance
+ * Q = Sigma2D^-1 has dL/dSigma2D = -Q Gq Q with Gq the gradient with respect
+ * to the symmetric conic (off-diagonal counted on both entries). */
+static void project_bwd_one(const cam_t *k, const prm_t *pp, const double *g, const double *dp,
+                            double *dg) {
+  double d[3] = {g[0] - k->C[0], g[1] - k->C[1], g[2] - k->C[2]};
+  const float *R = k->R;
+  double xc = R[0] * d[0] + R[1] * d[1] + R[2] * d[2];
+  double yc = R[3] * d[0] + R[4] * d[1] + R[5] * d[2];
+  double zc = R[6] * d[0] + R[7] * d[1] + R[8] * d[2];
+  double w = g[6], x = g[7], y = g[8], z = g[9];
+  double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  double M[9], S[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * g[3 + b];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      S[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+  double lx = (double)pp->jac_clamp * (0.5 * k->W / (double)k->fx);
+  double ly = (double)pp->jac_clamp * (0.5 * k->H / (double)k->fy);
+  double rx = xc / zc, ry = yc / zc;
+  int clx = (rx > lx || rx < -lx), cly = (ry > ly || ry < -ly);
+  double txz = fmin(lx, fmax(-lx, rx)), tyz = fmin(ly, fmax(-ly, ry));
+  double tx = txz * zc, ty = tyz * zc;
+  double fx = k->fx, fy = k->fy;
+  double J00 = fx / zc, J02 = -fx * tx / (zc * zc);
+  double J11 = fy / zc, J12 = -fy * ty / (zc * zc);
+  double T0[3], T1[3];
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = J00 * R[c] + J02 * R[6 + c];
+    T1[c] = J11 * R[3 + c] + J12 * R[6 + c];
+  }
+  double ST0[3], ST1[3];
+  for (int i = 0; i < 3; ++i) {
+    ST0[i] = S[3 * i] * T0[0] + S[3 * i + 1] * T0[1] + S[3 * i + 2] * T0[2];
+    ST1[i] = S[3 * i] * T1[0] + S[3 * i + 1] * T1[1] + S[3 * i + 2] * T1[2];
+  }
+  double a = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2] + pp->dilation;
+  double b = T1[0] * ST0[0] + T1[1] * ST0[1] + T1[2] * ST0[2];
+  double c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + pp->dilation;
+  double det = a * c - b * b;
+  double Q[4] = {c / det, -b / det, -b / det, a / det};
+  double Gq[4] = {dp[2], 0.5 * dp[3], 0.5 * dp[3], dp[4]};
+  /* H = -Q Gq Q */
+  double QG[4] = {Q[0] * Gq[0] + Q[1] * Gq[2], Q[0] * Gq[1] + Q[1] * Gq[3],
+                  Q[2] * Gq[0] + Q[3] * Gq[2], Q[2] * Gq[1] + Q[3] * Gq[3]};
+  double Hm[4] = {-(QG[0] * Q[0] + QG[1] * Q[2]), -(QG[0] * Q[1] + QG[1] * Q[3]),
+                  -(QG[2] * Q[0] + QG[3] * Q[2]), -(QG[2] * Q[1] + QG[3] * Q[3])};
+  double da = Hm[0], db = Hm[1] + Hm[2], dc = Hm[3];
+  /* a = T0 S T0, b = T1 S T0, c = T1 S T1 */
+  double GS[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      GS[3 * i + j] = da * T0[i] * T0[j] + db * T1[i] * T0[j] + dc * T1[i] * T1[j];
+  double dT0[3], dT1[3];
+  for (int i = 0; i < 3; ++i) {
+    dT0[i] = 2 * da * ST0[i] + db * ST1[i];
+    dT1[i] = db * ST0[i] + 2 * dc * ST1[i];
+  }
+  /* M: S = M M^T, dM = (GS + GS^T) M */
+  double dM[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int l = 0; l < 3; ++l) s += (GS[3 * i + l] + GS[3 * l + i]) * M[3 * l + j];
+      dM[3 * i + j] = s;
+    }
+  double ds[3] = {0, 0, 0}, dR[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      ds[j] += dM[3 * i + j] * Rq[3 * i + j];
+      dR[3 * i + j] = dM[3 * i + j] * g[3 + j];
+    }
+  double dw = 0, dx = 0, dy = 0, dz = 0;
+  dy += -4 * y * dR[0]; dz += -4 * z * dR[0];
+  dx += 2 * y * dR[1]; dy += 2 * x * dR[1]; dw += -2 * z * dR[1]; dz += -2 * w * dR[1];
+  dx += 2 * z * dR[2]; dz += 2 * x * dR[2]; dw += 2 * y * dR[2]; dy += 2 * w * dR[2];
+  dx += 2 * y * dR[3]; dy += 2 * x * dR[3]; dw += 2 * z * dR[3]; dz += 2 * w * dR[3];
+  dx += -4 * x * dR[4]; dz += -4 * z * dR[4];
+  dy += 2 * z * dR[5]; dz += 2 * y * dR[5]; dw += -2 * x * dR[5]; dx += -2 * w * dR[5];
+  dx += 2 * z * dR[6]; dz += 2 * x * dR[6]; dw += -2 * y * dR[6]; dy += -2 * w * dR[6];
+  dy += 2 * z * dR[7]; dz += 2 * y * dR[7]; dw += 2 * x * dR[7]; dx += 2 * w * dR[7];
+  dx += -4 * x * dR[8]; dy += -4 * y * dR[8];
+  /* T0 = J00 R0 + J02 R2, T1 = J11 R1 + J12 R2 */
+  double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+  for (int i = 0; i < 3; ++i) {
+    dJ00 += dT0[i] * R[i];
+    dJ02 += dT0[i] * R[6 + i];
+    dJ11 += dT1[i] * R[3 + i];
+    dJ12 += dT1[i] * R[6 + i];
+  }
+  double dxc = 0, dyc = 0, dzc = 0;
+  dzc += dJ00 * (-fx / (zc * zc));
+  dzc += dJ11 * (-fy / (zc * zc));
+  double dtx = dJ02 * (-fx / (zc * zc)), dty = dJ12 * (-fy / (zc * zc));
+  dzc += dJ02 * (2 * fx * tx / (zc * zc * zc)) + dJ12 * (2 * fy * ty / (zc * zc * zc));
+  if (clx) dzc += dtx * txz; else dxc += dtx;
+  if (cly) dzc += dty * tyz; else dyc += dty;
+  /* mean2d */
+  dxc += dp[0] * fx / zc;
+  dzc += dp[0] * (-fx * xc / (zc * zc));
+  dyc += dp[1] * fy / zc;
+  dzc += dp[1] * (-fy * yc / (zc * zc));
+  for (int a2 = 0; a2 < 3; ++a2) dg[a2] = R[a2] * dxc + R[3 + a2] * dyc + R[6 + a2] * dzc;
+  for (int a2 = 0; a2 < 3; ++a2) dg[3 + a2] = ds[a2];
+  dg[6] = dw; dg[7] = dx; dg[8] = dy; dg[9] = dz;
+  dg[10] = dp[5];
+  dg[11] = dp[6]; dg[12] = dp[7]; dg[13] = dp[8];
+}
+
+/* dL/dGaussian [14][stride] (double) from dproj [n][9] for visible ones. */
+ORC_API void orc_project_backward(int64_t n, int64_t stride, const double *gd, const uint8_t *vis,
+                                  const float *camf, int W, int H, const float *prmf,
+                                  const double *dproj, double *dgauss) {
+  cam_t k = load_cam(camf, W, H);
+  prm_t pp = load_prm(prmf);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double g[14], dg[14];
+    for (int f = 0; f < 14; ++f) { g[f] = gd[f * stride + i]; dg[f] = 0; }
+    if (vis[i]) project_bwd_one(&k, &pp, g, dproj + 9 * i, dg);
+    for (int f = 0; f < 14; ++f) dgauss[f * stride + i] = dg[f];
+  }
+}
+
+/* Decode backward.  dgauss [14][m*k] -> gradients of the anchor arrays
+ * (accumulated; caller zeroes) and of the 12 MLP arrays (accumulated).
+ * dmlp follows the order of mlp: w1a, b1a, w2a, b2a, w1c, ... */
+ORC_API void orc_decode_backward(int64_t m, const int64_t *idx, const float *pos,
+                                 const float *feat, const float *offsets,
+                                 const float *offset_scale, const float *base_scale, int k,
+                                 int F, int Wd, const float *const *mlp, const float *Cw,
+                                 float d_max, const double *dgauss, double *dpos, double *dfeat,
+                                 double *doffsets, double *doscale, double *dbscale,
+                                 double *const *dmlp) {
+  int64_t G = m * k;
+  int in = F + 4;
+  int outs[3] = {k, 3 * k, 7 * k};
+  for (int64_t s = 0; s < m; ++s) {
+    int64_t j = idx[s];
+    double x[64], hp[3][64], y[3][448];
+    decode_input(feat + j * F, F, pos + 3 * j, Cw, d_max, x);
+    for (int h = 0; h < 3; ++h)
+      head_fwd(x, in, Wd, outs[h], mlp[4 * h], mlp[4 * h + 1], mlp[4 * h + 2], mlp[4 * h + 3],
+               hp[h], y[h]);
+    double dy[3][448];
+    memset(dy, 0, sizeof dy);
+    for (int i = 0; i < k; ++i) {
+      int64_t g = s * k + i;
+      const float *o = offsets + (j * k + i) * 3;
+      for (int a = 0; a < 3; ++a) {
+        double dm = dgauss[a * G + g];
+        dpos[3 * j + a] += dm;
+        doffsets[(j * k + i) * 3 + a] += dm * offset_scale[3 * j + a];
+        doscale[3 * j + a] += dm * o[a];
+      }
+      for (int a = 0; a < 3; ++a) {
+        double sg = sigm(y[2][7 * i + a]);
+        double dsc = dgauss[(3 + a) * G + g];
+        dbscale[3 * j + a] += dsc * sg;
+        dy[2][7 * i + a] = dsc * base_scale[3 * j + a] * sg * (1 - sg);
+      }
+      double q[4], qn = 0;
+      for (int a = 0; a < 4; ++a) { q[a] = y[2][7 * i + 3 + a]; qn += q[a] * q[a]; }
+      qn = sqrt(qn);
+      if (qn > 0) {
+        double u[4], dqn[4], dot = 0;
+        for (int a = 0; a < 4; ++a) { u[a] = q[a] / qn; dqn[a] = dgauss[(6 + a) * G + g]; dot += u[a] * dqn[a]; }
+        for (int a = 0; a < 4; ++a) dy[2][7 * i + 3 + a] = (dqn[a] - u[a] * dot) / qn;
+      }
+      double op = tanh(y[0][i]);
+      dy[0][i] = dgauss[10 * G + g] * (1 - op * op);
+      for (int a = 0; a < 3; ++a) {
+        double sg = sigm(y[1][3 * i + a]);
+        dy[1][3 * i + a] = dgauss[(11 + a) * G + g] * sg * (1 - sg);
+      }
+    }
+    double dx[64];
+    memset(dx, 0, sizeof dx);
+    for (int h = 0; h < 3; ++h) {
+      const float *w1 = mlp[4 * h], *w2 = mlp[4 * h + 2];
+      double *dw1 = dmlp[4 * h], *db1 = dmlp[4 * h + 1], *dw2 = dmlp[4 * h + 2], *db2 = dmlp[4 * h + 3];
+      int out = outs[h];
+      double dh[64];
+      for (int u = 0; u < Wd; ++u) {
+        double hv = hp[h][u] > 0 ? hp[h][u] : 0.0, acc = 0;
+        for (int o = 0; o < out; ++o) {
+          dw2[u * out + o] += hv * dy[h][o];
+          acc += (double)w2[u * out + o] * dy[h][o];
+        }
+        dh[u] = hp[h][u] > 0 ? acc : 0.0;
+      }
+      for (int o = 0; o < out; ++o) db2[o] += dy[h][o];
+      for (int u = 0; u < Wd; ++u) {
+        db1[u] += dh[u];
+        for (int i2 = 0; i2 < in; ++i2) {
+          dw1[i2 * Wd + u] += x[i2] * dh[u];
+          dx[i2] += (double)w1[i2 * Wd + u] * dh[u];
+        }
+      }
+    }
+    for (int i2 = 0; i2 < F; ++i2) dfeat[j * F + i2] += dx[i2];
+    /* x[F] = |p - C| / d_max, x[F+1..F+3] = (p - C) / |p - C| */
+    double dd[3], n2 = 0;
+    for (int a = 0; a < 3; ++a) { dd[a] = (double)pos[3 * j + a] - (double)Cw[a]; n2 += dd[a] * dd[a]; }
+    double dist = sqrt(n2), u[3], dot = 0;
+    for (int a = 0; a < 3; ++a) { u[a] = dd[a] / dist; dot += u[a] * dx[F + 1 + a]; }
+    for (int a = 0; a < 3; ++a)
+      dpos[3 * j + a] += u[a] * dx[F] / d_max + (dx[F + 1 + a] - u[a] * dot) / dist;
+  }
+}

@@ -73,9 +73,10 @@ def _declare(L):
     L.orc_composite.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
     L.orc_render_bruteforce.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_num_threads.restype = _i32
-    for name in ("orc_render_backward", "orc_decode_backward"):
-        if hasattr(L, name):
-            pass
+    L.orc_composite_backward.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_project_backward.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_decode_backward.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
+                                      ctypes.c_float, _p, _p, _p, _p, _p, _p, _p]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -249,3 +250,62 @@ def render(scene, cam, prm, thr2=None, rho=None, weights=False):
     out = rasterize(gd.astype(np.float32), cam, prm, gd=gd, weights=weights)
     out.update(idx=idx, gauss=gd)
     return out
+
+
+# ----------------------------------------------------------------------------
+# backward passes
+# ----------------------------------------------------------------------------
+
+def composite_backward(pj, bs, cam, prm, dimg) -> np.ndarray:
+    """dL/dproj [n][9] (mx, my, ca, cb, cc, op, r, g, b) for L = sum(dimg * img)."""
+    n = len(pj["vis"])
+    dproj = np.zeros((n, 9), np.float64)
+    gid = bs["gid_of"] if bs["n_pairs"] > 0 else np.zeros(1, np.uint32)
+    lib().orc_composite_backward(_ptr(gid), _ptr(bs["ranges"]), _ptr(pj["proj"]), cam.width,
+                                 cam.height, _ptr(_c(prm, np.float32)),
+                                 _ptr(_c(dimg, np.float64)), _ptr(dproj))
+    return dproj
+
+
+def project_backward(gd, pj, cam, prm, dproj) -> np.ndarray:
+    """dL/dGaussian [14][n] from dL/dproj, at double attributes gd [14][n]."""
+    gd = _c(gd, np.float64)
+    n = gd.shape[1]
+    out = np.zeros((14, n), np.float64)
+    lib().orc_project_backward(n, n, _ptr(gd), _ptr(pj["vis"]), _ptr(cam_array(cam)), cam.width,
+                               cam.height, _ptr(_c(prm, np.float32)),
+                               _ptr(_c(dproj, np.float64)), _ptr(out))
+    return out
+
+
+def decode_backward(scene, idx, cam, dgauss):
+    """Gradients of the anchor arrays and MLP weights for L = sum(dgauss * decode)."""
+    idx = _c(idx, np.int64)
+    m, k = len(idx), scene.k
+    keep = [_c(scene.mlp[name], np.float32) for name in MLP_ORDER]
+    arr = (ctypes.c_void_p * 12)(*[a.ctypes.data for a in keep])
+    d = dict(pos=np.zeros((scene.n, 3)), feat=np.zeros((scene.n, scene.feat_dim)),
+             offsets=np.zeros((scene.n, k, 3)), offset_scale=np.zeros((scene.n, 3)),
+             base_scale=np.zeros((scene.n, 3)))
+    dm = {name: np.zeros(scene.mlp[name].shape) for name in MLP_ORDER}
+    darr = (ctypes.c_void_p * 12)(*[dm[name].ctypes.data for name in MLP_ORDER])
+    lib().orc_decode_backward(m, _ptr(idx), _ptr(_c(scene.pos, np.float32)),
+                              _ptr(_c(scene.feat, np.float32)), _ptr(_c(scene.offsets, np.float32)),
+                              _ptr(_c(scene.offset_scale, np.float32)),
+                              _ptr(_c(scene.base_scale, np.float32)), k, scene.feat_dim,
+                              scene.width, arr, _ptr(cam.C), float(scene.d_max),
+                              _ptr(_c(dgauss, np.float64)), _ptr(d["pos"]), _ptr(d["feat"]),
+                              _ptr(d["offsets"]), _ptr(d["offset_scale"]), _ptr(d["base_scale"]),
+                              darr)
+    d.update(dm)
+    return d
+
+
+def render_backward(scene, cam, prm, dimg, fwd=None):
+    """Full-chain gradients of L = sum(dimg * render(scene, cam)) with the
+    forward's discrete decisions held fixed."""
+    if fwd is None:
+        fwd = render(scene, cam, prm)
+    dproj = composite_backward(fwd["pj"], fwd["bs"], cam, prm, dimg)
+    dg = project_backward(fwd["gauss"], fwd["pj"], cam, prm, dproj)
+    return decode_backward(scene, fwd["idx"], cam, dg)
