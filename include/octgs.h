@@ -198,6 +198,60 @@ OCTGS_API int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *
                         float *T_final, uint32_t *last, float *gauss_w, void *ws,
                         size_t ws_bytes, void *const *stage_events, octgs_stream stream);
 
+/* Backward rasterization (training, Sec. V: losses on rendered images):
+ * given dL/drgb (planar [3][H][W], device) for the image the forward call
+ * produced, writes dL/dGaussian planar [14][g->capacity] (same field order
+ * as octgs_gaussians; zero for culled slots) into d_gauss.  Each pixel walks
+ * its tile list in reverse from the entry count `last` the forward stored and
+ * recovers transmittance as T_i = T_{i+1} / (1 - a_i) from T_final, so no
+ * per-pixel list is kept.  g, cam, p, the capacities and the workspace must be
+ * those of the forward call, unchanged since. */
+OCTGS_API int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera *cam,
+                                  const octgs_raster_params *p, int64_t pair_capacity,
+                                  const float *T_final, const uint32_t *last,
+                                  const float *dL_drgb, float *d_gauss, void *ws,
+                                  size_t ws_bytes, octgs_stream stream);
+
+/* Gradients of the anchor arrays (device, same shapes as octgs_anchors'
+ * pos, feat, offsets, offset_scale, base_scale).  Accumulated (+=). */
+typedef struct {
+  float *pos, *feat, *offsets, *offset_scale, *base_scale;
+} octgs_anchor_grads;
+
+/* Gradients of the three heads' weights and biases (device, same shapes as
+ * octgs_mlp).  Accumulated (+=). */
+typedef struct {
+  float *w1[3], *b1[3], *w2[3], *b2[3];
+} octgs_mlp_grads;
+
+/* Workspace bytes of octgs_decode_bwd for up to max_anchors listed anchors. */
+OCTGS_API size_t octgs_decode_bwd_workspace_bytes(int64_t max_anchors, int32_t k, int32_t width);
+
+/* Backward of the decode (Eq. 3 and Eq. 4, FP32): from dL/dGaussian planar
+ * [14][gauss_capacity] of the slots octgs_decode wrote for the first
+ * min(*count, gauss_capacity / k) anchors of idx, accumulates the gradients
+ * of the listed anchors' arrays (each listed anchor at most once per call)
+ * and of the MLP weights.  The forward activations are recomputed. */
+OCTGS_API int octgs_decode_bwd(const octgs_anchors *a, const octgs_mlp *mlp,
+                               const octgs_camera *cam, const uint32_t *idx,
+                               const uint32_t *count, const float *d_gauss,
+                               int64_t gauss_capacity, const octgs_anchor_grads *ga,
+                               const octgs_mlp_grads *gm, void *ws, size_t ws_bytes,
+                               octgs_stream stream);
+
+/* Mean-L1 image loss of the training step: dimg = scale * sign(img - target)
+ * and *loss += scale * sum |img - target| (device scalar, accumulated), over n
+ * elements.  scale is 1 / (elements averaged over). */
+OCTGS_API int octgs_l1_loss_grad(const float *img, const float *target, int64_t n, float scale,
+                                 float *dimg, float *loss, octgs_stream stream);
+
+/* One Adam update of n parameters (bias-corrected, step >= 1):
+ * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+OCTGS_API int octgs_adam_step(float *param, const float *grad, float *m, float *v, int64_t n,
+                              float lr, float beta1, float beta2, float eps, int32_t step,
+                              octgs_stream stream);
+
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:
  * the stats header, the sorted pair list (tile id and slot per entry, length

@@ -5,5 +5,6 @@
 """
 
 from ._lib import (OCTGS_BF16, OCTGS_FP32, OctgsError, lib)  # noqa: F401
-from .render import (DeviceScene, ViewBuffers, make_camera, raster_params,  # noqa: F401
-                     stream_handle)
+from .render import (DeviceScene, RenderFn, SceneGrads, ViewBuffers, adam_step,  # noqa: F401
+                     l1_loss_grad, make_camera, raster_params, render_diff, stream_handle,
+                     trainable)

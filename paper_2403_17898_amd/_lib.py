@@ -50,6 +50,15 @@ class RasterParams(ctypes.Structure):
                 ("jac_clamp", _f), ("bg", _f * 3)]
 
 
+class AnchorGrads(ctypes.Structure):
+    _fields_ = [("pos", _p), ("feat", _p), ("offsets", _p), ("offset_scale", _p),
+                ("base_scale", _p)]
+
+
+class MlpGrads(ctypes.Structure):
+    _fields_ = [("w1", _p * 3), ("b1", _p * 3), ("w2", _p * 3), ("b2", _p * 3)]
+
+
 class RasterStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
                 ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
@@ -68,6 +77,16 @@ SIGNATURES = [
     ("octgs_rasterize_fwd", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
                                    ctypes.POINTER(RasterParams), _i64, _p, _p, _p, _p, _p,
                                    ctypes.c_size_t, _p, _p]),
+    ("octgs_rasterize_bwd", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                   ctypes.POINTER(RasterParams), _i64, _p, _p, _p, _p, _p,
+                                   ctypes.c_size_t, _p]),
+    ("octgs_decode_bwd_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32]),
+    ("octgs_decode_bwd", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),
+                                ctypes.POINTER(Camera), _p, _p, _p, _i64,
+                                ctypes.POINTER(AnchorGrads), ctypes.POINTER(MlpGrads), _p,
+                                ctypes.c_size_t, _p]),
+    ("octgs_l1_loss_grad", _i32, [_p, _p, _i64, _f, _p, _p, _p]),
+    ("octgs_adam_step", _i32, [_p, _p, _p, _p, _i64, _f, _f, _f, _f, _i32, _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

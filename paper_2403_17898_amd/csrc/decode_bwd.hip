@@ -1,0 +1,384 @@
+// Backward pass of the neural-Gaussian decode (Octree-GS Sec. III-B, Eq. 3
+// and Eq. 4): from the gradients of the decoded Gaussian attributes to the
+// gradients of the anchor features, positions, offsets, scalings and of the
+// three MLP heads' weights and biases.
+//
+// Structure: the forward activations are recomputed (hidden pre-activations
+// and head outputs), the activation derivatives give dY, and the six GEMM
+// products of each head's backward (dW2 = relu(H)^T dY, dH = dY W2^T masked
+// by relu', dW1 = X^T dH, dX = dH W1^T) run on one tiled FP32 GEMM kernel.
+// Weight gradients reduce over anchors with split-K blocks and atomics.  The
+// anchor count lives on the device; every kernel reads it.
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// ---------------------------------------------------------------------------
+// FP32 GEMM: C (+)= op(A) op(B) [+ bias] [* (mask > 0)]
+// op(A) is M x K: A[m*lda + k], or A[k*lda + m] when transA.
+// op(B) is K x N: B[k*ldb + n], or B[n*ldb + k] when transB.
+// One of M (dyn_dim = 1) or K (dyn_dim = 2) may be min(*dyn, dyn_cap).
+// ---------------------------------------------------------------------------
+struct Gemm {
+  const float *A, *B;
+  float *C;
+  int64_t lda, ldb, ldc;
+  int transA, transB, reluA;
+  int M, N, K;
+  const uint32_t *dyn;
+  int dyn_dim, dyn_cap;
+  const float *bias;
+  const float *mask;
+  int64_t ldm;
+  int accumulate, splitk;
+};
+
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
+  __shared__ float As[GK][GT + 4];
+  __shared__ float Bs[GK][GT + 4];
+  int M = g.M, K = g.K;
+  if (g.dyn) {
+    const int d = (int)min(*g.dyn, (uint32_t)g.dyn_cap);
+    if (g.dyn_dim == 1) M = d; else K = d;
+  }
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  if (m0 >= M || n0 >= g.N) return;
+  const int kchunk = (K + g.splitk - 1) / g.splitk;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  if (kb >= ke) return;
+  const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+  float acc[4][4] = {};
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    // 64 x 16 tile of op(A) and 16 x 64 tile of op(B), zero outside
+    for (int i = t; i < GT * GK; i += kBlock) {
+      const int mm = i / GK, kk = i % GK;
+      const int m = m0 + mm, k = k0 + kk;
+      float v = 0.0f;
+      if (m < M && k < ke) v = g.transA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
+      if (g.reluA) v = fmaxf(v, 0.0f);
+      As[kk][mm] = v;
+      const int nn = i % GT, kk2 = i / GT;
+      const int n = n0 + nn, k2 = k0 + kk2;
+      float w = 0.0f;
+      if (n < g.N && k2 < ke) w = g.transB ? g.B[(int64_t)n * g.ldb + k2] : g.B[(int64_t)k2 * g.ldb + n];
+      Bs[kk2][nn] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma_(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty * 4 + i;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx * 4 + j;
+      if (n >= g.N) continue;
+      float v = acc[i][j];
+      if (g.bias) v += g.bias[n];
+      if (g.mask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
+      float *c = g.C + (int64_t)m * g.ldc + n;
+      if (g.accumulate) {
+        if (g.splitk > 1) atomicAdd(c, v); else *c += v;
+      } else {
+        *c = v;
+      }
+    }
+  }
+}
+
+hipError_t gemm(const Gemm &g0, int64_t m_cap, hipStream_t s) {
+  const int64_t mt = (std::max<int64_t>(m_cap, 1) + GT - 1) / GT;
+  const int nt = (g0.N + GT - 1) / GT;
+  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk), dim3(kBlock), 0, s, g0);
+  return hipGetLastError();
+}
+
+Gemm gemm_base() {
+  Gemm g;
+  memset(&g, 0, sizeof g);
+  g.splitk = 1;
+  return g;
+}
+
+// Column sums of a [M x N] block (row stride ld) into out[N] (+=), M on the device.
+__global__ __launch_bounds__(kBlock) void k_colsum(const float *Y, int64_t ld, int N,
+                                                   const uint32_t *dyn, int cap, float *out) {
+  const int M = (int)min(*dyn, (uint32_t)cap);
+  const int n = threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = blockIdx.x; m < M; m += gridDim.x) s += Y[(int64_t)m * ld + n];
+  if (s != 0.0f) atomicAdd(out + n, s);
+}
+
+struct BwdDecodeArgs {
+  int k, W, OT, F;
+  int off[3], outs[3];
+  float inv_dmax;
+  float C[3];
+  const float *pos, *feat, *offsets, *oscale, *bscale;
+  const uint32_t *idx, *count;
+  int cap_anchors;
+  const float *dgauss;
+  int64_t dstride;
+  float *X, *Dn, *Y, *dY, *dX;
+  float *gpos, *gfeat, *goff, *gosc, *gbsc;
+};
+
+// network input per listed anchor: X = [feature, dist / d_max, dir], Dn = (dist, dir)
+__global__ __launch_bounds__(kBlock) void k_bwd_gather(BwdDecodeArgs a) {
+  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
+  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+    const uint32_t j = a.idx[m];
+    float *x = a.X + (size_t)m * 36;
+    for (int f = 0; f < 32; ++f) x[f] = a.feat[(size_t)j * 32 + f];
+    const float d0 = a.pos[3 * (size_t)j] - a.C[0], d1 = a.pos[3 * (size_t)j + 1] - a.C[1];
+    const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
+    const float dist = sqrtf(fma_(d0, d0, fma_(d1, d1, d2 * d2)));
+    const float inv = 1.0f / dist;
+    x[32] = dist * a.inv_dmax;
+    x[33] = d0 * inv; x[34] = d1 * inv; x[35] = d2 * inv;
+    float *dn = a.Dn + (size_t)m * 4;
+    dn[0] = dist; dn[1] = x[33]; dn[2] = x[34]; dn[3] = x[35];
+  }
+}
+
+// Activation derivatives (one thread per anchor, looping over its k
+// Gaussians) and the anchor-array gradients of Eq. 3 and the scale bound.
+__global__ __launch_bounds__(kBlock) void k_act_bwd(BwdDecodeArgs a) {
+  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
+  const int k = a.k;
+  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+    const uint32_t j = a.idx[m];
+    const float *y = a.Y + (size_t)m * a.OT;
+    float *dy = a.dY + (size_t)m * a.OT;
+    float dp[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dbs[3] = {0, 0, 0};
+    const float *l = a.oscale + 3 * (size_t)j;
+    const float *bs = a.bscale + 3 * (size_t)j;
+    for (int i = 0; i < k; ++i) {
+      const size_t s = (size_t)m * k + i;
+      const float *o = a.offsets + ((size_t)j * k + i) * 3;
+      float *go = a.goff + ((size_t)j * k + i) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float dm = a.dgauss[c * a.dstride + s];
+        dp[c] += dm;
+        go[c] += dm * l[c];
+        dl[c] = fma_(dm, o[c], dl[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float sg = sigm(y[a.off[2] + 7 * i + c]);
+        const float dsc = a.dgauss[(3 + c) * a.dstride + s];
+        dbs[c] = fma_(dsc, sg, dbs[c]);
+        dy[a.off[2] + 7 * i + c] = dsc * bs[c] * sg * (1.0f - sg);
+      }
+      const float q0 = y[a.off[2] + 7 * i + 3], q1 = y[a.off[2] + 7 * i + 4];
+      const float q2 = y[a.off[2] + 7 * i + 5], q3 = y[a.off[2] + 7 * i + 6];
+      const float n2 = fma_(q0, q0, fma_(q1, q1, fma_(q2, q2, q3 * q3)));
+      float dq[4] = {0, 0, 0, 0};
+      if (n2 > 0.0f) {
+        const float inv = 1.0f / sqrtf(n2);
+        const float u[4] = {q0 * inv, q1 * inv, q2 * inv, q3 * inv};
+        float gq[4], dot = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          gq[c] = a.dgauss[(6 + c) * a.dstride + s];
+          dot = fma_(u[c], gq[c], dot);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dq[c] = (gq[c] - u[c] * dot) * inv;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dy[a.off[2] + 7 * i + 3 + c] = dq[c];
+      const float op = tanhf(y[a.off[0] + i]);
+      dy[a.off[0] + i] = a.dgauss[10 * a.dstride + s] * (1.0f - op * op);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float sg = sigm(y[a.off[1] + 3 * i + c]);
+        dy[a.off[1] + 3 * i + c] = a.dgauss[(11 + c) * a.dstride + s] * sg * (1.0f - sg);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.gpos[3 * (size_t)j + c] += dp[c];
+      a.gosc[3 * (size_t)j + c] += dl[c];
+      a.gbsc[3 * (size_t)j + c] += dbs[c];
+    }
+  }
+}
+
+// Input gradients back to the anchor: features, and the position through the
+// relative distance and the viewing direction.
+__global__ __launch_bounds__(kBlock) void k_x_bwd(BwdDecodeArgs a) {
+  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
+  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+    const uint32_t j = a.idx[m];
+    const float *dx = a.dX + (size_t)m * 36;
+    for (int f = 0; f < 32; ++f) a.gfeat[(size_t)j * 32 + f] += dx[f];
+    const float *dn = a.Dn + (size_t)m * 4;
+    const float dist = dn[0], u0 = dn[1], u1 = dn[2], u2 = dn[3];
+    const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
+    const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
+    a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
+    a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
+    a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
+  }
+}
+
+struct BwdLayout {
+  float *X, *Dn, *Hp, *Y, *dY, *dHp, *dX;
+  size_t bytes;
+};
+
+BwdLayout bwd_layout(void *base, int64_t mcap, int k, int W) {
+  BwdLayout L;
+  char *p = (char *)base;
+  size_t off = 0;
+  auto take = [&](size_t b) -> float * {
+    float *r = p ? (float *)(p + off) : nullptr;
+    off += (b + 255) & ~(size_t)255;
+    return r;
+  };
+  const int64_t m = std::max<int64_t>(mcap, 1);
+  const int OT = 11 * k;
+  L.X = take((size_t)m * 36 * 4);
+  L.Dn = take((size_t)m * 4 * 4);
+  L.Hp = take((size_t)m * 3 * W * 4);
+  L.Y = take((size_t)m * OT * 4);
+  L.dY = take((size_t)m * OT * 4);
+  L.dHp = take((size_t)m * 3 * W * 4);
+  L.dX = take((size_t)m * 36 * 4);
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace
+
+}  // namespace octgs
+
+using namespace octgs;
+
+extern "C" {
+
+size_t octgs_decode_bwd_workspace_bytes(int64_t max_anchors, int32_t k, int32_t width) {
+  if (max_anchors < 0 || k < 1 || k > kMaxK || width < 1) return 0;
+  return bwd_layout(nullptr, max_anchors, k, width).bytes;
+}
+
+int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_camera *cam,
+                     const uint32_t *idx, const uint32_t *count, const float *d_gauss,
+                     int64_t gauss_capacity, const octgs_anchor_grads *ga,
+                     const octgs_mlp_grads *gm, void *ws, size_t ws_bytes, octgs_stream stream) {
+  if (!an || !mlp || !cam || !idx || !count || !d_gauss || !ga || !gm || !ws) return OCTGS_EINVAL;
+  if (an->feat_dim != 32) return OCTGS_EUNSUPPORTED;
+  if (an->k < 1 || an->k > kMaxK) return OCTGS_EUNSUPPORTED;
+  if (mlp->width < 16 || mlp->width > 64 || mlp->width % 16) return OCTGS_EUNSUPPORTED;
+  if (!an->pos || !an->feat || !an->offsets || !an->offset_scale || !an->base_scale)
+    return OCTGS_EINVAL;
+  if (!ga->pos || !ga->feat || !ga->offsets || !ga->offset_scale || !ga->base_scale)
+    return OCTGS_EINVAL;
+  for (int h = 0; h < 3; ++h)
+    if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h] || !gm->w1[h] || !gm->b1[h] ||
+        !gm->w2[h] || !gm->b2[h])
+      return OCTGS_EINVAL;
+  if (gauss_capacity < an->k || !(an->d_max > 0.0f)) return OCTGS_EINVAL;
+  const int k = an->k, W = mlp->width;
+  const int64_t mcap = gauss_capacity / k;
+  if (mcap > 0x7fffffff) return OCTGS_EINVAL;
+  if (ws_bytes < octgs_decode_bwd_workspace_bytes(mcap, k, W)) return OCTGS_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  BwdLayout L = bwd_layout(ws, mcap, k, W);
+  BwdDecodeArgs a;
+  a.k = k; a.W = W; a.OT = 11 * k; a.F = 32;
+  a.outs[0] = k; a.outs[1] = 3 * k; a.outs[2] = 7 * k;
+  a.off[0] = 0; a.off[1] = k; a.off[2] = 4 * k;
+  a.inv_dmax = 1.0f / an->d_max;
+  for (int c = 0; c < 3; ++c) a.C[c] = cam->C[c];
+  a.pos = an->pos; a.feat = an->feat; a.offsets = an->offsets;
+  a.oscale = an->offset_scale; a.bscale = an->base_scale;
+  a.idx = idx; a.count = count; a.cap_anchors = (int)mcap;
+  a.dgauss = d_gauss; a.dstride = gauss_capacity;
+  a.X = L.X; a.Dn = L.Dn; a.Y = L.Y; a.dY = L.dY; a.dX = L.dX;
+  a.gpos = ga->pos; a.gfeat = ga->feat; a.goff = ga->offsets;
+  a.gosc = ga->offset_scale; a.gbsc = ga->base_scale;
+  const int grid = (int)std::min<int64_t>((mcap + kBlock - 1) / kBlock, 2048);
+  hipLaunchKernelGGL(k_bwd_gather, dim3(grid), dim3(kBlock), 0, s, a);
+  const int splitk = (int)std::min<int64_t>(std::max<int64_t>(mcap / 512, 1), 64);
+  hipError_t e = hipSuccess;
+  for (int h = 0; h < 3 && e == hipSuccess; ++h) {
+    // forward recompute: Hp_h = X W1_h + b1_h; Y_h = relu(Hp_h) W2_h + b2_h
+    Gemm g = gemm_base();
+    g.A = L.X; g.lda = 36; g.B = mlp->w1[h]; g.ldb = W; g.C = L.Hp + h * W; g.ldc = 3 * W;
+    g.M = (int)mcap; g.N = W; g.K = 36; g.dyn = count; g.dyn_dim = 1; g.dyn_cap = (int)mcap;
+    g.bias = mlp->b1[h];
+    e = gemm(g, mcap, s);
+    if (e != hipSuccess) break;
+    Gemm g2 = gemm_base();
+    g2.A = L.Hp + h * W; g2.lda = 3 * W; g2.reluA = 1; g2.B = mlp->w2[h]; g2.ldb = a.outs[h];
+    g2.C = L.Y + a.off[h]; g2.ldc = a.OT; g2.M = (int)mcap; g2.N = a.outs[h]; g2.K = W;
+    g2.dyn = count; g2.dyn_dim = 1; g2.dyn_cap = (int)mcap; g2.bias = mlp->b2[h];
+    e = gemm(g2, mcap, s);
+  }
+  if (e != hipSuccess) return OCTGS_EHIP;
+  hipLaunchKernelGGL(k_act_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  for (int h = 0; h < 3 && e == hipSuccess; ++h) {
+    // dW2_h += relu(Hp_h)^T dY_h
+    Gemm g = gemm_base();
+    g.A = L.Hp + h * W; g.lda = 3 * W; g.transA = 1; g.reluA = 1;
+    g.B = L.dY + a.off[h]; g.ldb = a.OT; g.C = gm->w2[h]; g.ldc = a.outs[h];
+    g.M = W; g.N = a.outs[h]; g.K = (int)mcap; g.dyn = count; g.dyn_dim = 2; g.dyn_cap = (int)mcap;
+    g.accumulate = 1; g.splitk = splitk;
+    e = gemm(g, W, s);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, L.dY + a.off[h], (int64_t)a.OT,
+                       a.outs[h], count, (int)mcap, gm->b2[h]);
+    // dHp_h = (dY_h W2_h^T) * (Hp_h > 0)
+    Gemm g3 = gemm_base();
+    g3.A = L.dY + a.off[h]; g3.lda = a.OT; g3.B = mlp->w2[h]; g3.ldb = a.outs[h]; g3.transB = 1;
+    g3.C = L.dHp + h * W; g3.ldc = 3 * W; g3.M = (int)mcap; g3.N = W; g3.K = a.outs[h];
+    g3.dyn = count; g3.dyn_dim = 1; g3.dyn_cap = (int)mcap; g3.mask = L.Hp + h * W; g3.ldm = 3 * W;
+    e = gemm(g3, mcap, s);
+    if (e != hipSuccess) break;
+    // dW1_h += X^T dHp_h
+    Gemm g4 = gemm_base();
+    g4.A = L.X; g4.lda = 36; g4.transA = 1; g4.B = L.dHp + h * W; g4.ldb = 3 * W;
+    g4.C = gm->w1[h]; g4.ldc = W; g4.M = 36; g4.N = W; g4.K = (int)mcap;
+    g4.dyn = count; g4.dyn_dim = 2; g4.dyn_cap = (int)mcap; g4.accumulate = 1; g4.splitk = splitk;
+    e = gemm(g4, 36, s);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, L.dHp + h * W, (int64_t)(3 * W), W,
+                       count, (int)mcap, gm->b1[h]);
+    // dX (+)= dHp_h W1_h^T
+    Gemm g5 = gemm_base();
+    g5.A = L.dHp + h * W; g5.lda = 3 * W; g5.B = mlp->w1[h]; g5.ldb = W; g5.transB = 1;
+    g5.C = L.dX; g5.ldc = 36; g5.M = (int)mcap; g5.N = 36; g5.K = W;
+    g5.dyn = count; g5.dyn_dim = 1; g5.dyn_cap = (int)mcap; g5.accumulate = h > 0 ? 1 : 0;
+    e = gemm(g5, mcap, s);
+  }
+  if (e != hipSuccess) return OCTGS_EHIP;
+  hipLaunchKernelGGL(k_x_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+}  // extern "C"

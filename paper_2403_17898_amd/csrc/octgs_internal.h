@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <cmath>
+#include <cstring>
 
 #include "../../include/octgs.h"
 
@@ -126,12 +128,22 @@ struct RasterWs {
   uint32_t *ranges;       // [tiles][2]
   uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 2..4 tile passes)
   uint32_t *lookback;     // [max(4 * ceil(gcap/part), 4 * ceil(pcap/part))][256]
+  float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
   int64_t gcap, pcap;
   int32_t tiles_x, tiles_y, nblk_g;
   size_t bytes;
 };
 
 RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);
+int tile_sort_passes(int ntiles);
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+struct CamParams {
+  float R[9], C[3], fx, fy, cx, cy, z_near;
+  int W, H;
+};
 
 // ---------------------------------------------------------------------------
 // radix sort (Onesweep: one histogram pass, then one pass per digit with

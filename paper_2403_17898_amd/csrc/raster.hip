@@ -29,12 +29,7 @@ namespace octgs {
 
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
-
-struct Cam {
-  float R[9], C[3], fx, fy, cx, cy, z_near;
-  int W, H;
-};
+typedef CamParams Cam;
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -485,6 +480,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.hist = (uint32_t *)take(8 * 256 * 4);
   const int64_t parts = std::max((g + kSortPart - 1) / kSortPart, (pc + kSortPart - 1) / kSortPart);
   ws.lookback = (uint32_t *)take((size_t)4 * parts * 256 * 4);
+  ws.dproj = (float *)take((size_t)g * 9 * 4);
   ws.bytes = off;
   return ws;
 }

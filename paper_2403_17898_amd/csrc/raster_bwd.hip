@@ -1,0 +1,356 @@
+// Backward pass of the rasterizer: gradients of a loss on the image with
+// respect to each Gaussian's mean, scale, rotation, opacity and colour
+// (the training step of Octree-GS renders and back-propagates through the
+// Eq. 2 blending and the EWA projection of Sec. III-A).
+//
+// composite backward: one block per 16x16 tile, one pixel per thread.  Each
+// pixel starts from its final transmittance and walks its tile list in
+// reverse from the last entry the forward consumed, recovering
+// T_i = T_{i+1} / (1 - a_i) instead of storing per-pixel lists; the colour
+// behind each entry is accumulated on the way.  Per-Gaussian gradients are
+// summed over the wave with cross-lane shuffles, over the block in LDS, and
+// added to global memory once per (tile, Gaussian).
+//
+// projection backward: one thread per Gaussian slot, recomputing the forward
+// quantities (rotation, 3D covariance, Jacobian, 2D covariance) in FP32.
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__global__ void k_zero_f32(float *p, const uint32_t *count_u, int64_t cap, int per) {
+  const uint64_t n = (uint64_t)min<int64_t>(*count_u, cap) * (uint64_t)per;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+struct BwdArgs {
+  RasterWs ws;
+  int buf, W, H;
+  float alpha_max, alpha_min, bg[3];
+  const float *T_final, *dimg;
+  const uint32_t *last;
+};
+
+template <bool AMIN>
+__device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
+  __shared__ float4 sA[kBlock], sB[kBlock];
+  __shared__ float sC[kBlock];
+  __shared__ uint32_t s_slot[kBlock];
+  __shared__ float sG[9][kBlock];
+  __shared__ uint32_t s_max;
+  const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
+  const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
+  const int t = threadIdx.x;
+  const int px = tx * kTile + (t % kTile), py = ty * kTile + (t / kTile);
+  const bool inside = px < a.W && py < a.H;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
+  const uint32_t *vals = a.ws.tval[a.buf];
+  const float4 *proj = a.ws.proj;
+  const size_t pix = (size_t)py * a.W + px, plane = (size_t)a.W * a.H;
+  float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
+  uint32_t last = 0;
+  if (inside) {
+    T = a.T_final[pix];
+    last = a.last[pix];
+    dr = a.dimg[pix];
+    dg = a.dimg[plane + pix];
+    db = a.dimg[2 * plane + pix];
+  }
+  // colour behind the current entry, starting with the background
+  float br = T * a.bg[0], bgc = T * a.bg[1], bb = T * a.bg[2];
+  if (t == 0) s_max = 0;
+  __syncthreads();
+  atomicMax(&s_max, last);
+  __syncthreads();
+  const uint32_t n_used = min(s_max, end - start);
+  const float amax = a.alpha_max, amin = a.alpha_min;
+  if (n_used == 0) return;
+  for (int32_t b0 = (int32_t)((n_used - 1) / kBlock) * kBlock; b0 >= 0; b0 -= kBlock) {
+    const uint32_t e = start + (uint32_t)b0 + t;
+    const int nb = (int)min((uint32_t)kBlock, n_used - (uint32_t)b0);
+    if (t < nb) {
+      const uint32_t s = vals[e];
+      s_slot[t] = s;
+      sA[t] = proj[3 * (size_t)s];
+      sB[t] = proj[3 * (size_t)s + 1];
+      sC[t] = proj[3 * (size_t)s + 2].x;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sG[q][t] = 0.0f;
+    __syncthreads();
+    for (int j = nb - 1; j >= 0; --j) {
+      const uint32_t li = (uint32_t)b0 + (uint32_t)j;  // index in the tile list
+      const float4 A = sA[j];
+      const float4 B = sB[j];
+      const float cb_ = sC[j];
+      const float dx = fx - A.x, dy = fy - A.y;
+      const float pw = fma_(A.z * dx, dx, fma_(B.x * dy, dy, A.w * dx * dy));
+      const float G = __builtin_amdgcn_exp2f(pw);
+      const float a0 = B.y * G;
+      const float al = fminf(amax, a0);
+      bool valid = li < last;
+      if (AMIN) valid = valid && !(al < amin);
+      float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (valid) {
+        const float inv1 = 1.0f / (1.0f - al);
+        const float Ti = T * inv1;
+        const float w = al * Ti;
+        g[6] = w * dr;
+        g[7] = w * dg;
+        g[8] = w * db;
+        const float cdot = fma_(B.z, dr, fma_(B.w, dg, cb_ * db));
+        const float bdot = fma_(br, dr, fma_(bgc, dg, bb * db));
+        const float dLda = Ti * cdot - bdot * inv1;
+        br = fma_(w, B.z, br);
+        bgc = fma_(w, B.w, bgc);
+        bb = fma_(w, cb_, bb);
+        T = Ti;
+        if (a0 <= amax) {
+          const float dG = dLda * B.y;
+          g[5] = dLda * G;
+          const float dpw = dG * G * kLn2;
+          // p = A' dx^2 + B' dx dy + C' dy^2 with the exp2-scaled conic
+          const float dAs = dpw * dx * dx, dBs = dpw * dx * dy, dCs = dpw * dy * dy;
+          g[2] = dAs * (-0.5f * kLog2e);
+          g[3] = dBs * (-kLog2e);
+          g[4] = dCs * (-0.5f * kLog2e);
+          g[0] = -dpw * fma_(2.0f * A.z, dx, A.w * dy);
+          g[1] = -dpw * fma_(A.w, dx, 2.0f * B.x * dy);
+        }
+      }
+      if (ballot(valid) != 0ull) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const float v = wave_sum_f(g[q]);
+          if (__lane_id() == 0 && v != 0.0f) atomicAdd(&sG[q][j], v);
+        }
+      }
+    }
+    __syncthreads();
+    if (t < nb) {
+      float *d = a.ws.dproj + 9 * (size_t)s_slot[t];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float v = sG[q][t];
+        if (v != 0.0f) atomicAdd(d + q, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_composite_bwd(BwdArgs a) {
+  if (a.alpha_min > 0.0f)
+    composite_bwd_tile<true>(a);
+  else
+    composite_bwd_tile<false>(a);
+}
+
+struct PBwdArgs {
+  CamParams cam;
+  float dil, jc;
+  const float *g;
+  int64_t gstride;
+  RasterWs ws;
+  float *dg;
+  int64_t dstride;
+};
+
+// Projection backward of one Gaussian (FP32).  Forward recap:
+//   (xc, yc, zc) = R (mu - C); Rq = rotation of q; M = Rq diag(s); S = M M^T
+//   tx = clamp(xc / zc) zc (same for y); J00 = fx / zc, J02 = -fx tx / zc^2, ...
+//   T0 = J00 R0 + J02 R2, T1 = J11 R1 + J12 R2;  (a, b, c) = (T0 S T0, T1 S T0, T1 S T1) + dil
+//   conic = (a, b; b, c)^-1;  mean2d = (fx xc / zc + cx, fy yc / zc + cy)
+// dL/dSigma2D = -Q Gq Q with Q the conic and Gq the gradient on the
+// symmetric conic (its off-diagonal gradient split over both entries).
+__device__ void project_bwd_one(const PBwdArgs &a, const float *g, const float *dp, float *out) {
+  const CamParams &k = a.cam;
+  const float d0 = g[0] - k.C[0], d1 = g[1] - k.C[1], d2 = g[2] - k.C[2];
+  const float xc = fma_(k.R[0], d0, fma_(k.R[1], d1, k.R[2] * d2));
+  const float yc = fma_(k.R[3], d0, fma_(k.R[4], d1, k.R[5] * d2));
+  const float zc = fma_(k.R[6], d0, fma_(k.R[7], d1, k.R[8] * d2));
+  const float w = g[6], x = g[7], y = g[8], z = g[9];
+  float Rq[9];
+  Rq[0] = 1.0f - 2.0f * (y * y + z * z); Rq[1] = 2.0f * (x * y - w * z); Rq[2] = 2.0f * (x * z + w * y);
+  Rq[3] = 2.0f * (x * y + w * z); Rq[4] = 1.0f - 2.0f * (x * x + z * z); Rq[5] = 2.0f * (y * z - w * x);
+  Rq[6] = 2.0f * (x * z - w * y); Rq[7] = 2.0f * (y * z + w * x); Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+  float M[9], S[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * g[3 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = fma_(M[3 * i], M[3 * j], fma_(M[3 * i + 1], M[3 * j + 1], M[3 * i + 2] * M[3 * j + 2]));
+  const float lx = a.jc * ((0.5f * (float)k.W) / k.fx), ly = a.jc * ((0.5f * (float)k.H) / k.fy);
+  const float rx = xc / zc, ry = yc / zc;
+  const bool clx = rx > lx || rx < -lx, cly = ry > ly || ry < -ly;
+  const float txz = fminf(lx, fmaxf(-lx, rx)), tyz = fminf(ly, fmaxf(-ly, ry));
+  const float tx = txz * zc, ty = tyz * zc;
+  const float iz = 1.0f / zc, iz2 = iz * iz;
+  const float J00 = k.fx * iz, J02 = -k.fx * tx * iz2, J11 = k.fy * iz, J12 = -k.fy * ty * iz2;
+  float T0[3], T1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = fma_(J00, k.R[c], J02 * k.R[6 + c]);
+    T1[c] = fma_(J11, k.R[3 + c], J12 * k.R[6 + c]);
+  }
+  float ST0[3], ST1[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ST0[i] = fma_(S[3 * i], T0[0], fma_(S[3 * i + 1], T0[1], S[3 * i + 2] * T0[2]));
+    ST1[i] = fma_(S[3 * i], T1[0], fma_(S[3 * i + 1], T1[1], S[3 * i + 2] * T1[2]));
+  }
+  const float ca = fma_(T0[0], ST0[0], fma_(T0[1], ST0[1], T0[2] * ST0[2])) + a.dil;
+  const float cb = fma_(T1[0], ST0[0], fma_(T1[1], ST0[1], T1[2] * ST0[2]));
+  const float cc = fma_(T1[0], ST1[0], fma_(T1[1], ST1[1], T1[2] * ST1[2])) + a.dil;
+  const float idet = 1.0f / (ca * cc - cb * cb);
+  const float Q0 = cc * idet, Q1 = -cb * idet, Q3 = ca * idet;
+  const float G0 = dp[2], G1 = 0.5f * dp[3], G3 = dp[4];
+  // H = -Q G Q (symmetric 2x2)
+  const float QG0 = Q0 * G0 + Q1 * G1, QG1 = Q0 * G1 + Q1 * G3;
+  const float QG2 = Q1 * G0 + Q3 * G1, QG3 = Q1 * G1 + Q3 * G3;
+  const float H0 = -(QG0 * Q0 + QG1 * Q1), H1 = -(QG0 * Q1 + QG1 * Q3);
+  const float H2 = -(QG2 * Q0 + QG3 * Q1), H3 = -(QG2 * Q1 + QG3 * Q3);
+  const float da = H0, db = H1 + H2, dc = H3;
+  float dT0[3], dT1[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    dT0[i] = 2.0f * da * ST0[i] + db * ST1[i];
+    dT1[i] = db * ST0[i] + 2.0f * dc * ST1[i];
+  }
+  // dL/dSigma (general) then dM = (GS + GS^T) M
+  float GS[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      GS[3 * i + j] = da * T0[i] * T0[j] + db * T1[i] * T0[j] + dc * T1[i] * T1[j];
+  float ds[3] = {0.0f, 0.0f, 0.0f}, dR[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) sum = fma_(GS[3 * i + l] + GS[3 * l + i], M[3 * l + j], sum);
+      ds[j] = fma_(sum, Rq[3 * i + j], ds[j]);
+      dR[3 * i + j] = sum * g[3 + j];
+    }
+  float dw = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f;
+  dy += -4.0f * y * dR[0]; dz += -4.0f * z * dR[0];
+  dx += 2.0f * y * dR[1]; dy += 2.0f * x * dR[1]; dw += -2.0f * z * dR[1]; dz += -2.0f * w * dR[1];
+  dx += 2.0f * z * dR[2]; dz += 2.0f * x * dR[2]; dw += 2.0f * y * dR[2]; dy += 2.0f * w * dR[2];
+  dx += 2.0f * y * dR[3]; dy += 2.0f * x * dR[3]; dw += 2.0f * z * dR[3]; dz += 2.0f * w * dR[3];
+  dx += -4.0f * x * dR[4]; dz += -4.0f * z * dR[4];
+  dy += 2.0f * z * dR[5]; dz += 2.0f * y * dR[5]; dw += -2.0f * x * dR[5]; dx += -2.0f * w * dR[5];
+  dx += 2.0f * z * dR[6]; dz += 2.0f * x * dR[6]; dw += -2.0f * y * dR[6]; dy += -2.0f * w * dR[6];
+  dy += 2.0f * z * dR[7]; dz += 2.0f * y * dR[7]; dw += 2.0f * x * dR[7]; dx += 2.0f * w * dR[7];
+  dx += -4.0f * x * dR[8]; dy += -4.0f * y * dR[8];
+  float dJ00 = 0.0f, dJ02 = 0.0f, dJ11 = 0.0f, dJ12 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    dJ00 = fma_(dT0[i], k.R[i], dJ00);
+    dJ02 = fma_(dT0[i], k.R[6 + i], dJ02);
+    dJ11 = fma_(dT1[i], k.R[3 + i], dJ11);
+    dJ12 = fma_(dT1[i], k.R[6 + i], dJ12);
+  }
+  float dxc = 0.0f, dyc = 0.0f, dzc = 0.0f;
+  dzc += -(dJ00 * k.fx + dJ11 * k.fy) * iz2;
+  const float dtx = -dJ02 * k.fx * iz2, dty = -dJ12 * k.fy * iz2;
+  dzc += 2.0f * (dJ02 * k.fx * tx + dJ12 * k.fy * ty) * iz2 * iz;
+  if (clx) dzc += dtx * txz; else dxc += dtx;
+  if (cly) dzc += dty * tyz; else dyc += dty;
+  dxc += dp[0] * k.fx * iz;
+  dzc += -dp[0] * k.fx * xc * iz2;
+  dyc += dp[1] * k.fy * iz;
+  dzc += -dp[1] * k.fy * yc * iz2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = fma_(k.R[c], dxc, fma_(k.R[3 + c], dyc, k.R[6 + c] * dzc));
+  out[3] = ds[0]; out[4] = ds[1]; out[5] = ds[2];
+  out[6] = dw; out[7] = dx; out[8] = dy; out[9] = dz;
+  out[10] = dp[5];
+  out[11] = dp[6]; out[12] = dp[7]; out[13] = dp[8];
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_bwd(PBwdArgs a) {
+  const uint32_t n = a.ws.hdr->n_slots;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+    float out[kGaussFields];
+    const bool vis = (a.ws.vis_mask[s >> 6] >> (s & 63)) & 1ull;
+    if (vis) {
+      float g[kGaussFields], dp[9];
+#pragma unroll
+      for (int f = 0; f < kGaussFields; ++f) g[f] = a.g[f * a.gstride + s];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dp[q] = a.ws.dproj[9 * (size_t)s + q];
+      project_bwd_one(a, g, dp, out);
+    } else {
+#pragma unroll
+      for (int f = 0; f < kGaussFields; ++f) out[f] = 0.0f;
+    }
+#pragma unroll
+    for (int f = 0; f < kGaussFields; ++f) a.dg[f * a.dstride + s] = out[f];
+  }
+}
+
+}  // namespace
+
+}  // namespace octgs
+
+using namespace octgs;
+
+extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera *cam,
+                                   const octgs_raster_params *p, int64_t pair_capacity,
+                                   const float *T_final, const uint32_t *last,
+                                   const float *dL_drgb, float *d_gauss, void *wsp,
+                                   size_t ws_bytes, octgs_stream stream) {
+  if (!g || !cam || !p || !T_final || !last || !dL_drgb || !d_gauss || !wsp) return OCTGS_EINVAL;
+  if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
+    return OCTGS_EINVAL;
+  if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30)) return OCTGS_EINVAL;
+  if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
+    return OCTGS_EINVAL;
+  if (ws_bytes < octgs_raster_workspace_bytes(g->capacity, pair_capacity, cam->width, cam->height))
+    return OCTGS_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
+  const int ntiles = ws.tiles_x * ws.tiles_y;
+  hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, ws.dproj, &ws.hdr->n_slots, ws.gcap, 9);
+  BwdArgs b;
+  b.ws = ws;
+  b.buf = tile_sort_passes(ntiles) % 2;
+  b.W = cam->width;
+  b.H = cam->height;
+  b.alpha_max = p->alpha_max;
+  b.alpha_min = p->alpha_min;
+  for (int i = 0; i < 3; ++i) b.bg[i] = p->bg[i];
+  b.T_final = T_final;
+  b.dimg = dL_drgb;
+  b.last = last;
+  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kBlock), 0, s, b);
+  PBwdArgs pa;
+  for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
+  for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];
+  pa.cam.fx = cam->fx; pa.cam.fy = cam->fy; pa.cam.cx = cam->cx; pa.cam.cy = cam->cy;
+  pa.cam.z_near = cam->z_near; pa.cam.W = cam->width; pa.cam.H = cam->height;
+  pa.dil = p->dilation;
+  pa.jc = p->jac_clamp;
+  pa.g = g->data;
+  pa.gstride = g->capacity;
+  pa.ws = ws;
+  pa.dg = d_gauss;
+  pa.dstride = g->capacity;
+  const int pgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.gcap + kBlock - 1) / kBlock, 1), 4096);
+  hipLaunchKernelGGL(k_project_bwd, dim3(pgrid), dim3(kBlock), 0, s, pa);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}

@@ -1,0 +1,70 @@
+// Training-step helpers: the mean-L1 image loss gradient and the Adam update
+// (Octree-GS trains its scenes with image losses; the optimiser is the usual
+// Adam).  Both are elementwise streams over HBM.
+#include "octgs_internal.h"
+
+namespace octgs {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_l1(const float *__restrict__ img,
+                                               const float *__restrict__ tgt, int64_t n,
+                                               float scale, float *__restrict__ dimg,
+                                               float *__restrict__ loss) {
+  float acc = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const float d = img[i] - tgt[i];
+    dimg[i] = d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+    acc += fabsf(d);
+  }
+  acc = wave_sum_f(acc);
+  if (__lane_id() == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                                 float *__restrict__ m, float *__restrict__ v,
+                                                 int64_t n, float lr, float b1, float b2, float eps,
+                                                 float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const float gi = g[i];
+    const float mi = __builtin_fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = __builtin_fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  }
+}
+
+}  // namespace
+
+}  // namespace octgs
+
+using namespace octgs;
+
+extern "C" {
+
+int octgs_l1_loss_grad(const float *img, const float *target, int64_t n, float scale, float *dimg,
+                       float *loss, octgs_stream stream) {
+  if (n < 0 || (n > 0 && (!img || !target || !dimg || !loss))) return OCTGS_EINVAL;
+  if (n == 0) return OCTGS_OK;
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_l1, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, img, target, n, scale,
+                     dimg, loss);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+int octgs_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
+                    float beta1, float beta2, float eps, int32_t step, octgs_stream stream) {
+  if (n < 0 || step < 1 || (n > 0 && (!param || !grad || !m || !v))) return OCTGS_EINVAL;
+  if (n == 0) return OCTGS_OK;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_adam, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, param, grad, m, v,
+                     n, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+}  // extern "C"

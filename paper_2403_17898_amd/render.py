@@ -134,6 +134,47 @@ class DeviceScene:
         return self._anchors
 
 
+PARAM_NAMES = ("pos", "feat", "offsets", "offset_scale", "base_scale")
+
+
+class SceneGrads:
+    """Device gradient buffers shaped like a DeviceScene's trainable arrays."""
+
+    def __init__(self, scene: "DeviceScene"):
+        self.arrays = {n: torch.zeros_like(getattr(scene, n)) for n in PARAM_NAMES}
+        self.mlp = {k: torch.zeros_like(v) for k, v in scene.mlp.items()}
+        self._ag = L.AnchorGrads(*[self.arrays[n].data_ptr() for n in PARAM_NAMES])
+        self._mg = L.MlpGrads()
+        for h, name in enumerate(MLP_HEADS):
+            self._mg.w1[h] = self.mlp["w1_" + name].data_ptr()
+            self._mg.b1[h] = self.mlp["b1_" + name].data_ptr()
+            self._mg.w2[h] = self.mlp["w2_" + name].data_ptr()
+            self._mg.b2[h] = self.mlp["b2_" + name].data_ptr()
+
+    def zero_(self):
+        for t in list(self.arrays.values()) + list(self.mlp.values()):
+            t.zero_()
+
+    def all(self) -> Dict[str, torch.Tensor]:
+        d = dict(self.arrays)
+        d.update(self.mlp)
+        return d
+
+
+def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, scale: float, dimg: torch.Tensor,
+                 loss: torch.Tensor, stream=None):
+    L.check(L.lib().octgs_l1_loss_grad(_ptr(img), _ptr(target), img.numel(), float(scale),
+                                       _ptr(dimg), _ptr(loss), stream_handle(stream)),
+            "octgs_l1_loss_grad")
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+              lr: float, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    L.check(L.lib().octgs_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
+                                    float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                    stream_handle(stream)), "octgs_adam_step")
+
+
 class ViewBuffers:
     """Per-view device buffers: selection, decoded Gaussians, rasterizer
     workspace and outputs, sized for a scene, an image and a pair capacity."""
@@ -202,6 +243,35 @@ class ViewBuffers:
         self.decode(scene, cam, precision, stream=stream)
         self.rasterize(cam, params, stream=stream, stage_events=stage_events)
 
+    def rasterize_bwd(self, cam: L.Camera, params: L.RasterParams, dimg: torch.Tensor,
+                      stream=None):
+        """dL/dGaussian planar [14][gcap] into self.dgauss, for the image of
+        the last rasterize() with these buffers."""
+        if getattr(self, "dgauss", None) is None:
+            self.dgauss = torch.empty_like(self.gauss)
+        L.check(L.lib().octgs_rasterize_bwd(ctypes.byref(self._g), ctypes.byref(cam),
+                                            ctypes.byref(params), self.pcap, _ptr(self.T),
+                                            _ptr(self.last), _ptr(dimg.contiguous()),
+                                            _ptr(self.dgauss), _ptr(self.ras_ws),
+                                            self.ras_ws.numel(), stream_handle(stream)),
+                "octgs_rasterize_bwd")
+
+    def decode_bwd(self, scene: "DeviceScene", cam: L.Camera, grads: SceneGrads,
+                   dgauss: Optional[torch.Tensor] = None, idx: Optional[torch.Tensor] = None,
+                   count: Optional[torch.Tensor] = None, stream=None):
+        lib = L.lib()
+        need = lib.octgs_decode_bwd_workspace_bytes(self.gcap // self.k, self.k, scene.width)
+        if getattr(self, "dec_ws", None) is None or self.dec_ws.numel() < need:
+            self.dec_ws = torch.empty(need, dtype=torch.uint8, device=self.gauss.device)
+        dg = self.dgauss if dgauss is None else dgauss
+        idx = self.sel_idx if idx is None else idx
+        count = self.sel_count if count is None else count
+        L.check(lib.octgs_decode_bwd(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                     ctypes.byref(cam), _ptr(idx), _ptr(count), _ptr(dg),
+                                     dg.shape[1], ctypes.byref(grads._ag), ctypes.byref(grads._mg),
+                                     _ptr(self.dec_ws), self.dec_ws.numel(),
+                                     stream_handle(stream)), "octgs_decode_bwd")
+
     # ---- readback helpers (synchronise) ----
     def stats(self) -> Dict[str, int]:
         torch.cuda.synchronize()
@@ -228,3 +298,36 @@ class ViewBuffers:
 
         ntiles = ((self.W + 15) // 16) * ((self.H + 15) // 16)
         return view(pt, P), view(ps, P), view(rg, 2 * ntiles).reshape(ntiles, 2)
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable view render: decode + rasterize forward through the
+    library, backward through octgs_rasterize_bwd and octgs_decode_bwd.
+    The inputs after the first four are the scene's trainable tensors (the
+    ones the DeviceScene points to), in PARAM_NAMES then sorted MLP-key order;
+    their gradients are returned."""
+
+    @staticmethod
+    def forward(ctx, vb, scene, cam, params, *tensors):
+        vb.render(scene, cam, params, precision=L.OCTGS_FP32)
+        ctx.vb, ctx.scene, ctx.cam, ctx.params = vb, scene, cam, params
+        return vb.rgb.clone()
+
+    @staticmethod
+    def backward(ctx, dimg):
+        vb, scene, cam, params = ctx.vb, ctx.scene, ctx.cam, ctx.params
+        vb.rasterize_bwd(cam, params, dimg.contiguous())
+        grads = SceneGrads(scene)
+        vb.decode_bwd(scene, cam, grads)
+        g = grads.all()
+        out = [g[n] for n in PARAM_NAMES] + [g[k] for k in sorted(scene.mlp)]
+        return (None, None, None, None, *out)
+
+
+def trainable(scene: "DeviceScene"):
+    """The tensors RenderFn differentiates, in its argument order."""
+    return [getattr(scene, n) for n in PARAM_NAMES] + [scene.mlp[k] for k in sorted(scene.mlp)]
+
+
+def render_diff(vb: "ViewBuffers", scene: "DeviceScene", cam: L.Camera, params: L.RasterParams):
+    return RenderFn.apply(vb, scene, cam, params, *trainable(scene))

@@ -1,0 +1,195 @@
+"""Parity of the HIP backward passes with the oracle's FP64 analytic
+gradients (themselves pinned by finite differences), through the C ABI.
+
+Bar: per-array normwise relative error <= 1e-3 (the gradient-check bar),
+and the FP32 GPU gradient against central differences of the FP64 oracle
+forward on the 50-anchor 64x64 scene.
+"""
+
+import numpy as np
+import pytest
+
+from synth import scenes as S
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_17898_amd as P
+    P.lib()
+    return P
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("W,H,n,seed", [(64, 48, 400, 1), (97, 61, 1500, 2), (320, 200, 8000, 3)])
+def test_raster_backward_parity(P, orc, W, H, n, seed):
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
+    gf = S.random_gaussians(n, cam, seed, scale=(0.05, 0.6), neg_opacity_frac=0.1,
+                            behind_frac=0.05)
+    prm = orc.params_array()
+    rng = np.random.default_rng(seed)
+    dimg = rng.standard_normal((3, H, W)).astype(np.float32)
+    say("raster backward", W, H, n)
+    ref = orc.rasterize(gf, cam, prm)
+    dproj = orc.composite_backward(ref["pj"], ref["bs"], cam, prm, dimg.astype(np.float64))
+    dref = orc.project_backward(gf.astype(np.float64), ref["pj"], cam, prm, dproj)
+    vb = P.ViewBuffers(n, 1, W, H, ref["bs"]["n_pairs"] + 16, gauss_capacity=n)
+    gt = torch.as_tensor(gf).cuda()
+    cnt = torch.tensor([n], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    vb.rasterize(c, P.raster_params(), gauss=gt, count=cnt)
+    vb.gauss.copy_(gt)  # the backward reads the Gaussians of the forward call
+    vb.gauss_count.copy_(cnt)
+    vb.rasterize_bwd(c, P.raster_params(), torch.as_tensor(dimg).cuda())
+    torch.cuda.synchronize()
+    got = _np(vb.dgauss).astype(np.float64)
+    names = ("mean", "scale", "quat", "opacity", "rgb")
+    spans = ((0, 3), (3, 6), (6, 10), (10, 11), (11, 14))
+    for nm, (a, b) in zip(names, spans):
+        e = rel(got[a:b], dref[a:b])
+        say(f"  d{nm}: rel err {e:.2e}")
+        assert e <= 1e-3, nm
+
+
+def test_decode_backward_parity(P, orc):
+    sc, cam = S.make_gradcheck_scene()
+    idx = np.arange(1, sc.n, 2, dtype=np.int64)
+    rng = np.random.default_rng(3)
+    G = len(idx) * sc.k
+    dgauss = rng.standard_normal((14, G)).astype(np.float32)
+    say("decode backward", len(idx))
+    ref = orc.decode_backward(sc, idx, cam, dgauss.astype(np.float64))
+    ds = P.DeviceScene.from_scene(sc)
+    grads = P.SceneGrads(ds)
+    vb = P.ViewBuffers(sc.n, sc.k, 64, 64, 1 << 12, gauss_capacity=G)
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    vb.decode_bwd(ds, P.make_camera(cam), grads, dgauss=torch.as_tensor(dgauss).cuda(), idx=idx_t,
+                  count=cnt)
+    torch.cuda.synchronize()
+    got = {k: _np(v) for k, v in grads.all().items()}
+    for name, r in ref.items():
+        e = rel(got[name], r)
+        say(f"  {name}: rel err {e:.2e}")
+        assert e <= 1e-4, name
+
+
+def test_full_chain_gradient(P, orc):
+    """50 anchors, 64x64: GPU FP32 gradient of sum(w * image) against the
+    oracle's FP64 analytic gradient and against central differences of the
+    oracle forward on sampled coordinates."""
+    sc, cam = S.make_gradcheck_scene()
+    prm = orc.params_array()
+    thr, rho = orc.scene_thresholds(sc)
+    rng = np.random.default_rng(7)
+    dimg = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+    fwd = orc.render(sc, cam, prm, thr, rho)
+    ref = orc.render_backward(sc, cam, prm, dimg.astype(np.float64), fwd)
+    say("full chain gradient", sc.n)
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
+    c = P.make_camera(cam)
+    pr = P.raster_params()
+    vb.render(ds, c, pr)
+    vb.rasterize_bwd(c, pr, torch.as_tensor(dimg).cuda())
+    grads = P.SceneGrads(ds)
+    vb.decode_bwd(ds, c, grads)
+    torch.cuda.synchronize()
+    got = {k: _np(v) for k, v in grads.all().items()}
+    errs = {name: rel(got[name], r) for name, r in ref.items()}
+    for name, e in errs.items():
+        say(f"  {name}: GPU vs oracle rel err {e:.2e}")
+    assert max(errs.values()) <= 1e-3, errs
+    # central differences of the FP64 oracle forward, float32-exact steps
+    fd_err = []
+    for name in ("feat", "offsets", "w1_a", "w2_c", "w2_s"):
+        arr = getattr(sc, name) if name in ("feat", "offsets") else sc.mlp[name]
+        pick = rng.choice(arr.size, 12, replace=False)
+        a_vals, f_vals = [], []
+        for fi in pick:
+            x = float(arr.flat[fi])
+            h = np.float32(2.0 ** -14 * max(1.0, abs(x)))
+            vals = []
+            for sgn in (1, -1):
+                a2 = arr.copy()
+                a2.flat[fi] = np.float32(x + sgn * h)
+                import copy
+                s2 = copy.copy(sc)
+                if name in sc.mlp:
+                    s2.mlp = dict(sc.mlp)
+                    s2.mlp[name] = a2
+                else:
+                    setattr(s2, name, a2)
+                o = orc.render(s2, cam, prm, thr, rho)
+                vals.append((float((dimg.astype(np.float64) * o["img"]).sum()), float(a2.flat[fi])))
+            f_vals.append((vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1]))
+            a_vals.append(float(got[name].flat[fi]))
+        fd_err.append(rel(a_vals, f_vals))
+        say(f"  {name}: GPU vs FD rel err {fd_err[-1]:.2e}")
+    assert max(fd_err) <= 1e-3
+
+
+def test_l1_and_adam(P):
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(10007).astype(np.float32)
+    b = rng.standard_normal(10007).astype(np.float32)
+    at, bt = torch.as_tensor(a).cuda(), torch.as_tensor(b).cuda()
+    d = torch.empty_like(at)
+    loss = torch.zeros(1, device="cuda")
+    say("l1 and adam")
+    P.l1_loss_grad(at, bt, 1.0 / a.size, d, loss)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(loss.item(), np.abs(a - b).mean(), rtol=1e-5)
+    np.testing.assert_array_equal(_np(d), np.sign(a - b).astype(np.float32) / np.float32(a.size))
+    p = rng.standard_normal(5000).astype(np.float32)
+    g = rng.standard_normal(5000).astype(np.float32)
+    pt, gt = torch.as_tensor(p).cuda(), torch.as_tensor(g).cuda()
+    m, v = torch.zeros_like(pt), torch.zeros_like(pt)
+    pe, me, ve = p.astype(np.float64), np.zeros(5000), np.zeros(5000)
+    for step in (1, 2, 3):
+        P.adam_step(pt, gt, m, v, 1e-2, step, eps=1e-8)
+        me = 0.9 * me + 0.1 * g
+        ve = 0.999 * ve + 0.001 * g.astype(np.float64) ** 2
+        pe = pe - 1e-2 * (me / (1 - 0.9 ** step)) / (np.sqrt(ve / (1 - 0.999 ** step)) + 1e-8)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(pt), pe, rtol=1e-5, atol=1e-6)
+
+
+def test_autograd_function_matches_direct(P):
+    sc, cam = S.make_gradcheck_scene()
+    ds = P.DeviceScene.from_scene(sc)
+    c = P.make_camera(cam)
+    pr = P.raster_params()
+    vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
+    ts = P.trainable(ds)
+    for t in ts:
+        t.requires_grad_(True)
+    say("autograd function")
+    img = P.render_diff(vb, ds, c, pr)
+    w = torch.linspace(-1, 1, img.numel(), device="cuda").reshape(img.shape)
+    (img * w).sum().backward()
+    grads = P.SceneGrads(ds)
+    vb2 = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
+    with torch.no_grad():
+        vb2.render(ds, c, pr)
+        vb2.rasterize_bwd(c, pr, w)
+        vb2.decode_bwd(ds, c, grads)
+    torch.cuda.synchronize()
+    names = list(P.render.PARAM_NAMES) + sorted(ds.mlp)
+    direct = grads.all()
+    for t, nm in zip(ts, names):
+        assert t.grad is not None, nm
+        assert rel(_np(t.grad), _np(direct[nm])) <= 1e-5, nm
