@@ -252,6 +252,57 @@ OCTGS_API int octgs_adam_step(float *param, const float *grad, float *m, float *
                               float lr, float beta1, float beta2, float eps, int32_t step,
                               octgs_stream stream);
 
+/* ---- learned anchor skip ---------------------------------------------
+ * A per-anchor contribution predictor extending the view-dependent anchor
+ * selection of Sec. IV-A: input z = [feature (32), unit direction camera ->
+ * anchor in camera coordinates R (x_v - C) / |x_v - C| (3),
+ * log2(|x_v - C| / d_max), level] (37 values); network 37 -> 64
+ * -> ReLU -> 64 -> ReLU -> 1 (logit).  Weights FP32, row-major [in][out],
+ * device memory. */
+typedef struct {
+  const float *w1, *b1, *w2, *b2, *w3, *b3; /* [37][64], [64], [64][64], [64], [64][1], [1] */
+} octgs_skip_net;
+
+typedef struct {
+  float *w1, *b1, *w2, *b2, *w3, *b3;
+} octgs_skip_net_grads;
+
+/* Per listed anchor, the sum of its k Gaussians' logged blend weights:
+ * w_out[m] = sum_i gauss_w[m * k + i] for m < min(*count, cap_anchors)
+ * (gauss_w from octgs_rasterize_fwd; count = listed anchors). */
+OCTGS_API int octgs_anchor_weights(const float *gauss_w, const uint32_t *count, int32_t k,
+                                   int64_t cap_anchors, float *w_out, octgs_stream stream);
+
+/* Predictor inputs z [cap][37] (FP32) of the first min(*count, cap) anchors of idx. */
+OCTGS_API int octgs_skip_features(const octgs_anchors *a, const octgs_camera *cam,
+                                  const uint32_t *idx, const uint32_t *count, int64_t cap,
+                                  float *z, octgs_stream stream);
+
+/* Workspace bytes of octgs_skip_predict for lists of up to cap anchors. */
+OCTGS_API size_t octgs_skip_predict_workspace_bytes(int64_t cap);
+
+/* Skip prediction over the selected anchors (BF16 MFMA, FP32 accumulation):
+ * keeps anchor sel_idx[p] iff its logit >= logit_threshold.  keep_idx (device,
+ * capacity cap) receives the kept indices in ascending order, *keep_count
+ * their number; logits (nullable, [cap]) the logit per list position. */
+OCTGS_API int octgs_skip_predict(const octgs_anchors *a, const octgs_camera *cam,
+                                 const octgs_skip_net *net, float logit_threshold,
+                                 const uint32_t *sel_idx, const uint32_t *sel_count, int64_t cap,
+                                 uint32_t *keep_idx, uint32_t *keep_count, float *logits,
+                                 void *ws, size_t ws_bytes, octgs_stream stream);
+
+/* Workspace bytes of octgs_skip_train_grad for a batch size. */
+OCTGS_API size_t octgs_skip_train_workspace_bytes(int32_t batch);
+
+/* Gradient of the mean weighted binary cross-entropy of the predictor (FP32)
+ * on a batch: z [batch][37], labels y [batch] in {0, 1}, positives weighted
+ * by pos_weight.  Gradients are overwritten; *loss (device) is incremented by
+ * the batch loss.  Pair with octgs_adam_step for the update. */
+OCTGS_API int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float *y,
+                                    int32_t batch, float pos_weight,
+                                    const octgs_skip_net_grads *grads, float *loss, void *ws,
+                                    size_t ws_bytes, octgs_stream stream);
+
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:
  * the stats header, the sorted pair list (tile id and slot per entry, length

@@ -944,3 +944,89 @@ ORC_API void orc_decode_backward(int64_t m, const int64_t *idx, const float *pos
       dpos[3 * j + a] += u[a] * dx[F] / d_max + (dx[F + 1 + a] - u[a] * dot) / dist;
   }
 }
+
+/* ======================================================================
+ * Anchor-skip predictor (extension of the per-view anchor selection):
+ * inputs, forward and binary cross-entropy gradient, double precision.
+ * ====================================================================== */
+
+/* z[s][0..36] = feature (32), unit direction camera -> anchor in camera
+ * coordinates R (x - C) / |x - C| (3), log2(|x - C| / d_max), level. */
+ORC_API void orc_skip_features(int64_t m, const int64_t *idx, const float *pos, const float *feat,
+                               const uint8_t *level, const float *Rw, const float *Cw, float d_max,
+                               double *z) {
+  for (int64_t s = 0; s < m; ++s) {
+    int64_t j = idx[s];
+    double *o = z + 37 * s;
+    for (int f = 0; f < 32; ++f) o[f] = feat[32 * j + f];
+    double d[3], n2 = 0;
+    for (int a = 0; a < 3; ++a) { d[a] = (double)pos[3 * j + a] - (double)Cw[a]; n2 += d[a] * d[a]; }
+    double dist = sqrt(n2);
+    for (int a = 0; a < 3; ++a)
+      o[32 + a] = (Rw[3 * a] * d[0] + Rw[3 * a + 1] * d[1] + Rw[3 * a + 2] * d[2]) / dist;
+    o[35] = log2(dist / (double)d_max);
+    o[36] = level[j];
+  }
+}
+
+/* Predictor 37 -> 64 -> ReLU -> 64 -> ReLU -> 1 on B rows of z.  logit[B];
+ * with labels y: *loss = mean of w (softplus(x) - y x), w = pos_weight for
+ * positives, and (grads non-NULL) its gradient w.r.t. w1, b1, w2, b2, w3, b3
+ * (overwritten).  net: w1 [37][64], b1, w2 [64][64], b2, w3 [64], b3 [1]. */
+ORC_API void orc_skip_mlp(int64_t B, const double *z, const float *y, float pos_weight,
+                          const float *const *net, double *logit, double *loss,
+                          double *const *grads) {
+  const float *w1 = net[0], *b1 = net[1], *w2 = net[2], *b2 = net[3], *w3 = net[4], *b3 = net[5];
+  if (grads) {
+    int sizes[6] = {37 * 64, 64, 64 * 64, 64, 64, 1};
+    for (int q = 0; q < 6; ++q) memset(grads[q], 0, sizeof(double) * (size_t)sizes[q]);
+  }
+  double L = 0;
+  for (int64_t r = 0; r < B; ++r) {
+    const double *x = z + 37 * r;
+    double h1[64], h2[64], a1[64], a2[64];
+    for (int u = 0; u < 64; ++u) {
+      double s = b1[u];
+      for (int i = 0; i < 37; ++i) s += x[i] * (double)w1[i * 64 + u];
+      h1[u] = s;
+      a1[u] = s > 0 ? s : 0;
+    }
+    for (int u = 0; u < 64; ++u) {
+      double s = b2[u];
+      for (int i = 0; i < 64; ++i) s += a1[i] * (double)w2[i * 64 + u];
+      h2[u] = s;
+      a2[u] = s > 0 ? s : 0;
+    }
+    double out = b3[0];
+    for (int i = 0; i < 64; ++i) out += a2[i] * (double)w3[i];
+    logit[r] = out;
+    if (!y) continue;
+    double yy = y[r], wgt = yy > 0.5 ? pos_weight : 1.0;
+    double sp = (out > 0 ? out : 0) + log1p(exp(-fabs(out)));
+    L += wgt * (sp - yy * out);
+    if (!grads) continue;
+    double dout = wgt * (1.0 / (1.0 + exp(-out)) - yy) / (double)B;
+    double da2[64], dh2[64], da1[64], dh1[64];
+    grads[5][0] += dout;
+    for (int i = 0; i < 64; ++i) {
+      grads[4][i] += a2[i] * dout;
+      da2[i] = (double)w3[i] * dout;
+      dh2[i] = h2[i] > 0 ? da2[i] : 0;
+    }
+    for (int i = 0; i < 64; ++i) {
+      double s = 0;
+      for (int u = 0; u < 64; ++u) {
+        grads[2][i * 64 + u] += a1[i] * dh2[u];
+        s += (double)w2[i * 64 + u] * dh2[u];
+      }
+      da1[i] = s;
+      dh1[i] = h1[i] > 0 ? s : 0;
+    }
+    for (int u = 0; u < 64; ++u) {
+      grads[3][u] += dh2[u];
+      grads[1][u] += dh1[u];
+      for (int i = 0; i < 37; ++i) grads[0][i * 64 + u] += x[i] * dh1[u];
+    }
+  }
+  if (loss) *loss = L / (double)B;
+}

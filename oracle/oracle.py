@@ -75,6 +75,8 @@ def _declare(L):
     L.orc_num_threads.restype = _i32
     L.orc_composite_backward.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_project_backward.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_skip_features.argtypes = [_i64, _p, _p, _p, _p, _p, _p, ctypes.c_float, _p]
+    L.orc_skip_mlp.argtypes = [_i64, _p, _p, ctypes.c_float, _p, _p, _p, _p]
     L.orc_decode_backward.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
                                       ctypes.c_float, _p, _p, _p, _p, _p, _p, _p]
 
@@ -309,3 +311,35 @@ def render_backward(scene, cam, prm, dimg, fwd=None):
     dproj = composite_backward(fwd["pj"], fwd["bs"], cam, prm, dimg)
     dg = project_backward(fwd["gauss"], fwd["pj"], cam, prm, dproj)
     return decode_backward(scene, fwd["idx"], cam, dg)
+
+
+# ----------------------------------------------------------------------------
+# anchor-skip predictor
+# ----------------------------------------------------------------------------
+
+SKIP_ORDER = ("w1", "b1", "w2", "b2", "w3", "b3")
+
+
+def skip_features(scene, idx, cam) -> np.ndarray:
+    idx = _c(idx, np.int64)
+    z = np.empty((len(idx), 37), np.float64)
+    lib().orc_skip_features(len(idx), _ptr(idx), _ptr(_c(scene.pos, np.float32)),
+                            _ptr(_c(scene.feat, np.float32)), _ptr(_c(scene.level, np.uint8)),
+                            _ptr(cam.R), _ptr(cam.C), float(scene.d_max), _ptr(z))
+    return z
+
+
+def skip_mlp(z, net, y=None, pos_weight=1.0, grads=False):
+    """(logits, loss, grads dict or None) of the predictor on rows z [B][37]."""
+    z = _c(z, np.float64)
+    B = z.shape[0]
+    keep = [_c(net[k], np.float32) for k in SKIP_ORDER]
+    arr = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in keep])
+    logit = np.empty(B, np.float64)
+    loss = np.zeros(1, np.float64)
+    g = {k: np.zeros(np.asarray(net[k]).shape, np.float64) for k in SKIP_ORDER} if grads else None
+    garr = (ctypes.c_void_p * 6)(*[g[k].ctypes.data for k in SKIP_ORDER]) if grads else None
+    yy = None if y is None else _c(y, np.float32)
+    lib().orc_skip_mlp(B, _ptr(z), _ptr(yy), float(pos_weight), arr, _ptr(logit),
+                       _ptr(loss) if y is not None else None, garr)
+    return logit, (float(loss[0]) if y is not None else None), g

@@ -59,6 +59,10 @@ class MlpGrads(ctypes.Structure):
     _fields_ = [("w1", _p * 3), ("b1", _p * 3), ("w2", _p * 3), ("b2", _p * 3)]
 
 
+class SkipNet(ctypes.Structure):
+    _fields_ = [("w1", _p), ("b1", _p), ("w2", _p), ("b2", _p), ("w3", _p), ("b3", _p)]
+
+
 class RasterStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
                 ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
@@ -87,6 +91,16 @@ SIGNATURES = [
                                 ctypes.c_size_t, _p]),
     ("octgs_l1_loss_grad", _i32, [_p, _p, _i64, _f, _p, _p, _p]),
     ("octgs_adam_step", _i32, [_p, _p, _p, _p, _i64, _f, _f, _f, _f, _i32, _p]),
+    ("octgs_anchor_weights", _i32, [_p, _p, _i32, _i64, _p, _p]),
+    ("octgs_skip_features", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _i64,
+                                   _p, _p]),
+    ("octgs_skip_predict_workspace_bytes", ctypes.c_size_t, [_i64]),
+    ("octgs_skip_predict", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera),
+                                  ctypes.POINTER(SkipNet), _f, _p, _p, _i64, _p, _p, _p, _p,
+                                  ctypes.c_size_t, _p]),
+    ("octgs_skip_train_workspace_bytes", ctypes.c_size_t, [_i32]),
+    ("octgs_skip_train_grad", _i32, [ctypes.POINTER(SkipNet), _p, _p, _i32, _f,
+                                     ctypes.POINTER(SkipNet), _p, _p, ctypes.c_size_t, _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

@@ -18,119 +18,6 @@ namespace {
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
-// ---------------------------------------------------------------------------
-// FP32 GEMM: C (+)= op(A) op(B) [+ bias] [* (mask > 0)]
-// op(A) is M x K: A[m*lda + k], or A[k*lda + m] when transA.
-// op(B) is K x N: B[k*ldb + n], or B[n*ldb + k] when transB.
-// One of M (dyn_dim = 1) or K (dyn_dim = 2) may be min(*dyn, dyn_cap).
-// ---------------------------------------------------------------------------
-struct Gemm {
-  const float *A, *B;
-  float *C;
-  int64_t lda, ldb, ldc;
-  int transA, transB, reluA;
-  int M, N, K;
-  const uint32_t *dyn;
-  int dyn_dim, dyn_cap;
-  const float *bias;
-  const float *mask;
-  int64_t ldm;
-  int accumulate, splitk;
-};
-
-constexpr int GT = 64, GK = 16;
-
-__global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
-  __shared__ float As[GK][GT + 4];
-  __shared__ float Bs[GK][GT + 4];
-  int M = g.M, K = g.K;
-  if (g.dyn) {
-    const int d = (int)min(*g.dyn, (uint32_t)g.dyn_cap);
-    if (g.dyn_dim == 1) M = d; else K = d;
-  }
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  if (m0 >= M || n0 >= g.N) return;
-  const int kchunk = (K + g.splitk - 1) / g.splitk;
-  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-  if (kb >= ke) return;
-  const int t = threadIdx.x, tx = t % 16, ty = t / 16;
-  float acc[4][4] = {};
-  for (int k0 = kb; k0 < ke; k0 += GK) {
-    // 64 x 16 tile of op(A) and 16 x 64 tile of op(B), zero outside
-    for (int i = t; i < GT * GK; i += kBlock) {
-      const int mm = i / GK, kk = i % GK;
-      const int m = m0 + mm, k = k0 + kk;
-      float v = 0.0f;
-      if (m < M && k < ke) v = g.transA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
-      if (g.reluA) v = fmaxf(v, 0.0f);
-      As[kk][mm] = v;
-      const int nn = i % GT, kk2 = i / GT;
-      const int n = n0 + nn, k2 = k0 + kk2;
-      float w = 0.0f;
-      if (n < g.N && k2 < ke) w = g.transB ? g.B[(int64_t)n * g.ldb + k2] : g.B[(int64_t)k2 * g.ldb + n];
-      Bs[kk2][nn] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      float av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma_(av[i], bv[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + ty * 4 + i;
-    if (m >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx * 4 + j;
-      if (n >= g.N) continue;
-      float v = acc[i][j];
-      if (g.bias) v += g.bias[n];
-      if (g.mask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
-      float *c = g.C + (int64_t)m * g.ldc + n;
-      if (g.accumulate) {
-        if (g.splitk > 1) atomicAdd(c, v); else *c += v;
-      } else {
-        *c = v;
-      }
-    }
-  }
-}
-
-hipError_t gemm(const Gemm &g0, int64_t m_cap, hipStream_t s) {
-  const int64_t mt = (std::max<int64_t>(m_cap, 1) + GT - 1) / GT;
-  const int nt = (g0.N + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk), dim3(kBlock), 0, s, g0);
-  return hipGetLastError();
-}
-
-Gemm gemm_base() {
-  Gemm g;
-  memset(&g, 0, sizeof g);
-  g.splitk = 1;
-  return g;
-}
-
-// Column sums of a [M x N] block (row stride ld) into out[N] (+=), M on the device.
-__global__ __launch_bounds__(kBlock) void k_colsum(const float *Y, int64_t ld, int N,
-                                                   const uint32_t *dyn, int cap, float *out) {
-  const int M = (int)min(*dyn, (uint32_t)cap);
-  const int n = threadIdx.x;
-  if (n >= N) return;
-  float s = 0.0f;
-  for (int m = blockIdx.x; m < M; m += gridDim.x) s += Y[(int64_t)m * ld + n];
-  if (s != 0.0f) atomicAdd(out + n, s);
-}
-
 struct BwdDecodeArgs {
   int k, W, OT, F;
   int off[3], outs[3];
@@ -351,8 +238,7 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
     g.accumulate = 1; g.splitk = splitk;
     e = gemm(g, W, s);
     if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, L.dY + a.off[h], (int64_t)a.OT,
-                       a.outs[h], count, (int)mcap, gm->b2[h]);
+    colsum(L.dY + a.off[h], (int64_t)a.OT, a.outs[h], count, (int)mcap, gm->b2[h], s);
     // dHp_h = (dY_h W2_h^T) * (Hp_h > 0)
     Gemm g3 = gemm_base();
     g3.A = L.dY + a.off[h]; g3.lda = a.OT; g3.B = mlp->w2[h]; g3.ldb = a.outs[h]; g3.transB = 1;
@@ -367,8 +253,7 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
     g4.dyn = count; g4.dyn_dim = 2; g4.dyn_cap = (int)mcap; g4.accumulate = 1; g4.splitk = splitk;
     e = gemm(g4, 36, s);
     if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, L.dHp + h * W, (int64_t)(3 * W), W,
-                       count, (int)mcap, gm->b1[h]);
+    colsum(L.dHp + h * W, (int64_t)(3 * W), W, count, (int)mcap, gm->b1[h], s);
     // dX (+)= dHp_h W1_h^T
     Gemm g5 = gemm_base();
     g5.A = L.dHp + h * W; g5.lda = 3 * W; g5.B = mlp->w1[h]; g5.ldb = W; g5.transB = 1;

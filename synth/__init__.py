@@ -17,6 +17,8 @@ from .scenes import (  # noqa: F401
     make_config1,
     make_config2,
     make_config3,
+    config3_views,
+    perturbed_copy,
     make_config5,
     make_gradcheck_scene,
     random_gaussians,

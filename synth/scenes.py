@@ -241,7 +241,10 @@ def _seg_dist(points: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
     """Distance from each point to the segment [a, b] (float64)."""
     p = points.astype(np.float64)
     ab = b - a
-    t = np.clip(((p - a) @ ab) / float(ab @ ab), 0.0, 1.0)
+    L2 = float(ab @ ab)
+    if L2 == 0.0:  # a single camera position
+        return np.linalg.norm(p - a, axis=1)
+    t = np.clip(((p - a) @ ab) / L2, 0.0, 1.0)
     return np.linalg.norm(p - (a + t[:, None] * ab), axis=1)
 
 
@@ -450,13 +453,30 @@ def config3_views(seed: int = 3):
     return random_views(4, seed, 500.0, 10.0, 800.0, 1600, 1066)
 
 
-def make_config3(seed: int = 3) -> Scene:
-    """500k anchors over 6 levels on the c2 procedural box scene."""
+# base voxel size bisected once for the default config-3 arguments
+# (498,520 anchors; per level 8000, 43649, 126737, 165092, 107526, 47516)
+C3_DELTA = 20.50295138003223
+
+
+def perturbed_copy(sc: Scene, sigma: float, seed: int) -> Scene:
+    """The scene with N(0, sigma^2) noise added to every anchor feature (the
+    source of the training targets of config 3)."""
+    rng = np.random.default_rng(seed)
+    out = dataclasses.replace(sc)
+    out.feat = (sc.feat + sigma * rng.standard_normal(sc.feat.shape)).astype(np.float32)
+    return out
+
+
+def make_config3(seed: int = 3, delta: Optional[float] = C3_DELTA) -> Scene:
+    """500k anchors over 6 levels on the c2 procedural box scene, kept near
+    the 4 training views (the same pruning model as config 2)."""
     rng = np.random.default_rng(1)
     pts = _street_points(rng, 20_000_000, 2000, 500.0)
-    return make_scene(pts, 6, 500_000, config3_views(seed), k=10, feat_dim=32, width=64,
+    views = config3_views(seed)
+    near = [(tuple(c.C.astype(np.float64)), tuple(c.C.astype(np.float64))) for c in views]
+    return make_scene(pts, 6, 500_000, views, k=10, feat_dim=32, width=64,
                       seed=seed, scale_mode="voxel", offset_sigma=0.25,
-                      subsample=2_500_000, info=dict(name="c3"))
+                      subsample=2_500_000, near=near, delta=delta, info=dict(name="c3"))
 
 
 def make_config5(seed: int = 5) -> Scene:

@@ -425,3 +425,76 @@ def test_decode_relu_and_feature_path(orc):
         h = max(float(sc.feat[s, 0]) + 0.25, 0.0)
         # output 4 = Gaussian 1, green channel
         np.testing.assert_allclose(gd[12, s * sc.k + 1], sig(2.0 * h), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# anchor-skip predictor (oracle)
+# --------------------------------------------------------------------------
+
+def _skip_net(rng):
+    a1, a2, a3 = (math.sqrt(6 / (37 + 64)), math.sqrt(6 / 128), math.sqrt(6 / 65))
+    return {"w1": rng.uniform(-a1, a1, (37, 64)).astype(np.float32),
+            "b1": rng.uniform(-0.1, 0.1, 64).astype(np.float32),
+            "w2": rng.uniform(-a2, a2, (64, 64)).astype(np.float32),
+            "b2": rng.uniform(-0.1, 0.1, 64).astype(np.float32),
+            "w3": rng.uniform(-a3, a3, (64, 1)).astype(np.float32),
+            "b3": np.array([0.05], np.float32)}
+
+
+def test_skip_features_closed_form(orc):
+    sc, cam = tiny_scene()
+    sc.level = np.array([0, 3, 7], np.uint8)
+    z = orc.skip_features(sc, np.arange(3), cam)
+    # anchor 0 at (3, 4, 0) from the origin: direction (0.6, 0.8, 0), distance 5
+    np.testing.assert_allclose(z[0, 32:35], [0.6, 0.8, 0.0], atol=1e-15)
+    # a camera turned 90 degrees about z sees that direction as (0.8, -0.6, 0)
+    cam2 = S.Camera(R=np.array([[0, 1, 0], [-1, 0, 0], [0, 0, 1]]), C=np.zeros(3), fx=80, fy=80,
+                    cx=32, cy=32, width=64, height=64)
+    z2 = orc.skip_features(sc, np.arange(1), cam2)
+    np.testing.assert_allclose(z2[0, 32:35], [0.8, -0.6, 0.0], atol=1e-15)
+    np.testing.assert_allclose(z[0, 35], math.log2(5.0 / 10.0), rtol=1e-15)
+    np.testing.assert_array_equal(z[:, 36], [0, 3, 7])
+    np.testing.assert_array_equal(z[:, :32], sc.feat.astype(np.float64))
+
+
+def test_skip_mlp_gradient_fd(orc):
+    rng = np.random.default_rng(0)
+    net = _skip_net(rng)
+    z = rng.standard_normal((64, 37))
+    y = (rng.random(64) < 0.4).astype(np.float32)
+    _, loss0, g = orc.skip_mlp(z, net, y, pos_weight=2.0, grads=True)
+    assert loss0 > 0
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        arr = net[name]
+        pick = rng.choice(arr.size, min(arr.size, 30), replace=False)
+        a_vals, f_vals = [], []
+        for fi in pick:
+            x = float(arr.flat[fi])
+            # small enough that no ReLU kink of the 64 rows is crossed
+            h = np.float32(2.0 ** -20 * max(1.0, abs(x)))
+            vals = []
+            for sgn in (1, -1):
+                n2 = dict(net)
+                n2[name] = arr.copy()
+                n2[name].flat[fi] = np.float32(x + sgn * h)
+                vals.append((orc.skip_mlp(z, n2, y, pos_weight=2.0)[1], float(n2[name].flat[fi])))
+            f_vals.append((vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1]))
+            a_vals.append(g[name].flat[fi])
+        a_vals, f_vals = np.array(a_vals), np.array(f_vals)
+        assert np.linalg.norm(a_vals - f_vals) <= 1e-5 * np.linalg.norm(f_vals) + 1e-12, name
+
+
+def test_skip_mlp_bce_closed_form(orc):
+    """A network that outputs its bias only: loss = softplus(b) - y b."""
+    rng = np.random.default_rng(1)
+    net = _skip_net(rng)
+    for k in ("w1", "w2", "w3", "b1", "b2"):
+        net[k] = np.zeros_like(net[k])
+    net["b3"] = np.array([0.7], np.float32)
+    z = rng.standard_normal((10, 37))
+    y = np.array([1, 0] * 5, np.float32)
+    logit, loss, _ = orc.skip_mlp(z, net, y, pos_weight=3.0)
+    b = float(np.float32(0.7))
+    sp = math.log1p(math.exp(b))
+    np.testing.assert_allclose(logit, b, rtol=1e-15)
+    np.testing.assert_allclose(loss, (5 * 3.0 * (sp - b) + 5 * sp) / 10, rtol=1e-14)
