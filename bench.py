@@ -248,7 +248,9 @@ def main():
         "config": {"workload": "street scene: 1M anchors / 8 LOD levels, 200-view zoom-out "
                                "10->800 m, 1920x1080",
                    "n_anchors": sc.n, "k": sc.k, "mlp_width": sc.width, "views": len(cams),
-                   "path": ("BF16 decode + learned anchor skip" if skip else "BF16 decode"),
+                   "path": ("BF16 decode" if not skip else
+                            ("BF16 decode; learned skip fell back to full decode"
+                             if skip["fallback_to_full_decode"] else "BF16 decode + learned anchor skip")),
                    "mean_selected": round(mean["selected"]), "mean_gaussians": round(mean["slots"]),
                    "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"])},
         "fps_plain_fp32": round(fps32, 2),
@@ -291,25 +293,40 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
     hist = SK.train(net, z, y, epochs=6, batch=16384, lr=2e-3, pos_weight=4.0)
     cands = [-6.0, -5.0, -4.0, -3.0, -2.5, -2.0, -1.5, -1.0, -0.5, 0.0]
     best = SK.choose_threshold(vbl, SK.SkipBuffers(vbl), ds, hold_cams, prm, net, cands, 47.0)
-    del vbl
+    # hold-out skip fraction at the chosen threshold; under 1 % the path
+    # falls back to full decode (no predictor launch)
+    thr = best[0] if best else -1e30
+    sbl = SK.SkipBuffers(vbl)
+    hsel = hkept = 0
+    for c in hold_cams:
+        vbl.select(ds, c)
+        SK.predict(vbl, sbl, ds, c, net, thr)
+        hsel += int(vbl.sel_count.item())
+        hkept += int(sbl.keep_count.item())
+    hold_skip = 1.0 - hkept / max(hsel, 1)
+    fallback = hold_skip < 0.01
+    del vbl, sbl
     torch.cuda.empty_cache()
     sb = SK.SkipBuffers(vb)
-    thr = best[0] if best else -1e30
     # judge on the zoom-out: every view against the plain FP32 full decode
     psn, sel, kept = [], 0, 0
     for c in ccams:
         vb.render(ds, c, prm, precision=P.OCTGS_FP32)
         ref = vb.rgb.clone()
         SK.render_skip(vb, sb, ds, c, prm, net, thr, precision=P.OCTGS_BF16)
-        psn.append(SK.psnr(vb.rgb, ref))
         sel += int(vb.sel_count.item())
         kept += int(sb.keep_count.item())
+        if fallback:
+            vb.render(ds, c, prm, precision=P.OCTGS_BF16)
+        psn.append(SK.psnr(vb.rgb, ref))
     fin = [p for p in psn if math.isfinite(p)]
-    res = {"train_views": len(train_cams), "rows": int(z.shape[0]),
+    res = {"fallback_to_full_decode": fallback, "holdout_skipped_fraction": round(hold_skip, 4),
+           "train_views": len(train_cams), "rows": int(z.shape[0]),
            "positive_fraction": round(float(y.mean().item()), 4),
            "loss_per_epoch": [round(h, 4) for h in hist],
            "logit_threshold": thr, "holdout_worst_psnr_db": round(best[1], 2) if best else None,
-           "skipped_fraction": round(1.0 - kept / max(sel, 1), 4),
+           "predictor_skipped_fraction": round(1.0 - kept / max(sel, 1), 4),
+           "skipped_fraction": 0.0 if fallback else round(1.0 - kept / max(sel, 1), 4),
            "psnr_min_db": round(min(psn), 2), "psnr_mean_db": round(float(np.mean(fin)), 2) if fin else None,
            "train_s": round(time.time() - t0, 1)}
     log(f"skip predictor: {res}")
@@ -321,9 +338,15 @@ def timed_skip(args, P, vb, ds, ccams, prm, skip, torch):
     from paper_2403_17898_amd import skip as SK
     net, sb, thr = skip.pop("_net"), skip.pop("_sb"), skip.pop("_thr")
 
+    fallback = skip["fallback_to_full_decode"]
+
     def run(n):
         for i in range(n):
-            SK.render_skip(vb, sb, ds, ccams[i % len(ccams)], prm, net, thr, precision=P.OCTGS_BF16)
+            c = ccams[i % len(ccams)]
+            if fallback:
+                vb.render(ds, c, prm, precision=P.OCTGS_BF16)
+            else:
+                SK.render_skip(vb, sb, ds, c, prm, net, thr, precision=P.OCTGS_BF16)
 
     run(args.warmup)
     torch.cuda.synchronize()
