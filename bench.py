@@ -103,13 +103,13 @@ def main():
             raise SystemExit(f"sizing pass failed: {st}")
         per_view.append(st)
     max_sel = max(s["n_selected"] for s in per_view)
-    max_pairs = max(s["n_pairs"] for s in per_view)
+    max_pairs = max(s["n_candidates"] for s in per_view)
     del vb
     torch.cuda.empty_cache()
     gcap = max(1, int(max_sel * sc.k * 1.05) + 1024)
     pcap = max(1, int(max_pairs * 1.10) + 4096)
     vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=pcap, gauss_capacity=gcap)
-    log(f"sizing: max selected {max_sel}, max pairs {max_pairs}; gcap {gcap}, pcap {pcap}")
+    log(f"sizing: max selected {max_sel}, max candidate pairs {max_pairs}; gcap {gcap}, pcap {pcap}")
 
     stream = torch.cuda.current_stream()
 
@@ -155,7 +155,7 @@ def main():
     names = ["select", "decode"] + list(L.RASTER_STAGE_NAMES)
     tot = {k: 0.0 for k in names}
     nviews = min(args.steps, len(ccams))
-    sums = dict(selected=0, slots=0, visible=0, pairs=0)
+    sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0)
     ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
     sh = P.stream_handle(stream)
     for i in range(nviews):
@@ -177,11 +177,13 @@ def main():
         sums["slots"] += s["n_slots"]
         sums["visible"] += s["n_visible"]
         sums["pairs"] += s["n_pairs"]
+        sums["candidates"] += s["n_candidates"]
     avg = {k: v / nviews for k, v in tot.items()}  # ms per launch
     mean = {k: v / nviews for k, v in sums.items()}
     log("per-stage ms/view: " + ", ".join(f"{k} {v:.4f}" for k, v in avg.items()))
     log(f"mean per view: selected {mean['selected']:.0f}, Gaussians {mean['slots']:.0f}, "
-        f"visible {mean['visible']:.0f}, pairs {mean['pairs']:.0f}")
+        f"visible {mean['visible']:.0f}, pairs {mean['pairs']:.0f} "
+        f"(of {mean['candidates']:.0f} rectangle candidates)")
 
     # algorithmic bytes per launch of each stage (see the design notes)
     npix = W * H
@@ -252,7 +254,8 @@ def main():
                             ("BF16 decode; learned skip fell back to full decode"
                              if skip["fallback_to_full_decode"] else "BF16 decode + learned anchor skip")),
                    "mean_selected": round(mean["selected"]), "mean_gaussians": round(mean["slots"]),
-                   "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"])},
+                   "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"]),
+                   "mean_candidates": round(mean["candidates"])},
         "fps_plain_fp32": round(fps32, 2),
         "fps_bf16_no_skip": round(fps16, 2),
         "ms_per_step_plain_fp32": round(ms32 / args.steps, 4),
@@ -382,7 +385,7 @@ def train_step_timing(args, P, S, torch, np):
         targets.append(vb.rgb.clone())
         vb.render(ds, c, prm)
         st = vb.stats()
-        max_sel, max_pairs = max(max_sel, st["n_selected"]), max(max_pairs, st["n_pairs"])
+        max_sel, max_pairs = max(max_sel, st["n_selected"]), max(max_pairs, st["n_candidates"])
     del vb
     vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=int(max_pairs * 1.2) + 4096,
                        gauss_capacity=int(max_sel * sc.k * 1.2) + 1024)

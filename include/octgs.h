@@ -128,10 +128,13 @@ typedef struct {
 typedef struct {
   uint32_t n_slots;       /* Gaussian slots read (min(*count, capacity)) */
   uint32_t n_visible;     /* slots that survived the projection culls */
-  uint32_t n_pairs;       /* (tile, Gaussian) pairs needed */
-  uint32_t pair_overflow; /* 1 if n_pairs exceeded the pair capacity (image incomplete) */
+  uint32_t n_pairs;       /* (tile, Gaussian) pairs listed: tiles the 3-sigma ellipse meets
+                             (0 on overflow) */
+  uint32_t pair_overflow; /* 1 if n_candidates exceeded the pair capacity (image incomplete) */
   uint32_t sync_error;    /* 1 if a radix-sort look-back wait hit its bound (output invalid) */
-  uint32_t reserved[11];
+  uint32_t n_candidates;  /* tiles of the survivors' 3-sigma rectangles, tested against the
+                             ellipse; the pair capacity must hold this many (saturates) */
+  uint32_t reserved[10];
 } octgs_raster_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -181,8 +184,11 @@ OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pa
  * tile-based front-to-back depth order, Eq. 2 blending):
  *  - cull: opacity <= 0, camera z <= z_near, 2D covariance not positive
  *    definite, or a 3-sigma rectangle outside the image;
- *  - bin into 16x16 tiles and order each tile's list by camera-space depth
- *    of the Gaussian centre, ties by slot index;
+ *  - bin into 16x16 tiles: candidates are the tiles of the rectangle around
+ *    the 3-sigma circle; a candidate is kept iff the 3-sigma ellipse
+ *    {q(x) <= 9} meets the box spanned by the tile's pixel centres
+ *    (canonical FP32 test); order each tile's list by camera-space depth of
+ *    the Gaussian centre, ties by slot index;
  *  - per pixel: a_i = min(alpha_max, opacity_i * G'_i(x')), C = sum T_i a_i c_i,
  *    T_i = prod_{j<i} (1 - a_j), stop after T < t_min, add T * bg.
  * Outputs (device): rgb planar [3][H][W]; T_final [H][W]; last [H][W] = list

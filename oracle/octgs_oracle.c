@@ -227,7 +227,7 @@ ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level
  *   each clamped to [0, tiles_x] by fminf/fmaxf; same for y; cull if empty.
  * dot(p, q) = fmaf(p0, q0, fmaf(p1, q1, p2 * q2)). */
 static int project_decide_f(const cam_t *k, const prm_t *pp, const float *g, int tiles_x,
-                            int tiles_y, int rect[4], float *depth) {
+                            int tiles_y, int rect[4], float *depth, float cf[5]) {
   if (!(g[10] > 0.0f)) return 0;
   float xc, yc, zc;
   cam_xform_f(k, g[0], g[1], g[2], &xc, &yc, &zc);
@@ -284,7 +284,48 @@ static int project_decide_f(const cam_t *k, const prm_t *pp, const float *g, int
   if (x0 >= x1 || y0 >= y1) return 0;
   rect[0] = x0; rect[1] = y0; rect[2] = x1; rect[3] = y1;
   *depth = zc;
+  /* float 2D mean and conic (inverse of (ca cb; cb cc)) for the tile test */
+  float inv = 1.0f / det;
+  cf[0] = px; cf[1] = py;
+  cf[2] = cc * inv; cf[3] = -cb * inv; cf[4] = ca * inv;
   return 1;
+}
+
+/* Tile test (canonical FP32): does the 3-sigma ellipse {q(p) <= 9},
+ * q(p) = qa dx^2 + 2 qb dx dy + qc dy^2 around the float 2D mean, meet the
+ * rectangle spanned by the tile's pixel centres [16 tx + 0.5, 16 tx + 15.5] x
+ * [16 ty + 0.5, 16 ty + 15.5]?  The minimum of the convex quadratic over the
+ * rectangle is 0 when the mean is inside, else it lies on an edge facing the
+ * mean, where the one-dimensional minimiser is clamped to the edge:
+ *   X0 = (float)(16 tx) + 0.5, X1 = X0 + 15 (Y alike)
+ *   if the mean's x is outside [X0, X1]: xe = nearer of X0, X1; dx = xe - mx;
+ *     ys = min(max(my - (qb * dx) / qc, Y0), Y1); dy = ys - my;
+ *     q1 = fmaf(qa * dx, dx, fmaf(2 * qb * dx, dy, qc * dy * dy))
+ *   if the mean's y is outside [Y0, Y1]: ye, dy = ye - my;
+ *     xs = min(max(mx - (qb * dy) / qa, X0), X1); dx = xs - mx; q2 = same form
+ *   keep iff min(q1, q2) <= 9. */
+static int tile_meets_ellipse_f(const float cf[5], int tx, int ty) {
+  float mx = cf[0], my = cf[1], qa = cf[2], qb = cf[3], qc = cf[4];
+  float X0 = (float)(16 * tx) + 0.5f, X1 = X0 + 15.0f;
+  float Y0 = (float)(16 * ty) + 0.5f, Y1 = Y0 + 15.0f;
+  int in_x = !(mx < X0) && !(mx > X1), in_y = !(my < Y0) && !(my > Y1);
+  if (in_x && in_y) return 1;
+  float q = INFINITY;
+  if (!in_x) {
+    float xe = mx < X0 ? X0 : X1;
+    float dx = xe - mx;
+    float ys = fminf(fmaxf(my - (qb * dx) / qc, Y0), Y1);
+    float dy = ys - my;
+    q = fmaf(qa * dx, dx, fmaf(2.0f * qb * dx, dy, qc * dy * dy));
+  }
+  if (!in_y) {
+    float ye = my < Y0 ? Y0 : Y1;
+    float dy = ye - my;
+    float xs = fminf(fmaxf(mx - (qb * dy) / qa, X0), X1);
+    float dx = xs - mx;
+    q = fminf(q, fmaf(qa * dx, dx, fmaf(2.0f * qb * dx, dy, qc * dy * dy)));
+  }
+  return q <= 9.0f;
 }
 
 /* ======================================================================
@@ -430,7 +471,7 @@ static void project_cont(const cam_t *k, const prm_t *pp, const double *g, proj_
  * double.  Returns the number of visible Gaussians. */
 ORC_API int64_t orc_project(int64_t n, int64_t stride, const float *gf, const double *gd,
                             const float *camf, int W, int H, const float *prmf,
-                            uint8_t *vis, int32_t *rect, float *depth, double *proj) {
+                            uint8_t *vis, int32_t *rect, float *depth, double *proj, float *cf) {
   cam_t k = load_cam(camf, W, H);
   prm_t pp = load_prm(prmf);
   int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
@@ -445,7 +486,9 @@ ORC_API int64_t orc_project(int64_t n, int64_t stride, const float *gf, const do
     }
     int r[4] = {0, 0, 0, 0};
     float dz = 0;
-    int v = project_decide_f(&k, &pp, g, tiles_x, tiles_y, r, &dz);
+    float c5[5] = {0, 0, 0, 0, 0};
+    int v = project_decide_f(&k, &pp, g, tiles_x, tiles_y, r, &dz, c5);
+    for (int a = 0; a < 5; ++a) cf[5 * i + a] = c5[a];
     vis[i] = (uint8_t)v;
     for (int a = 0; a < 4; ++a) rect[4 * i + a] = r[a];
     depth[i] = dz;
@@ -483,22 +526,39 @@ static uint32_t fbits(float f) {
   return u;
 }
 
-/* Count the (tile, Gaussian) pairs of the visible Gaussians. */
-ORC_API int64_t orc_count_pairs(int64_t n, const uint8_t *vis, const int32_t *rect) {
+/* Count the (tile, Gaussian) pairs: tiles of each visible Gaussian's
+ * rectangle that its 3-sigma ellipse meets. */
+ORC_API int64_t orc_count_pairs(int64_t n, const uint8_t *vis, const int32_t *rect,
+                                const float *cf) {
+  int64_t p = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!vis[i]) continue;
+    const int32_t *r = rect + 4 * i;
+    for (int y = r[1]; y < r[3]; ++y)
+      for (int x = r[0]; x < r[2]; ++x) p += tile_meets_ellipse_f(cf + 5 * i, x, y);
+  }
+  return p;
+}
+
+/* Rectangle candidates (before the ellipse test). */
+ORC_API int64_t orc_count_rect_pairs(int64_t n, const uint8_t *vis, const int32_t *rect) {
   int64_t p = 0;
   for (int64_t i = 0; i < n; ++i)
     if (vis[i]) p += (int64_t)(rect[4 * i + 2] - rect[4 * i]) * (rect[4 * i + 3] - rect[4 * i + 1]);
   return p;
 }
 
-/* All (tile, Gaussian) pairs ordered by tile, then depth (positive float
- * bits order like the values), then Gaussian index; ranges[t] = [start, end)
- * of tile t in that list.  Writes tile_of[P], gid_of[P]. */
+ORC_API int orc_tile_test(const float *cf, int tx, int ty) { return tile_meets_ellipse_f(cf, tx, ty); }
+
+/* All (tile, Gaussian) pairs (tiles of the rectangle that the 3-sigma
+ * ellipse meets) ordered by tile, then depth (positive float bits order like
+ * the values), then Gaussian index; ranges[t] = [start, end) of tile t in
+ * that list.  Writes tile_of[P], gid_of[P]. */
 ORC_API int64_t orc_bin_sort(int64_t n, const uint8_t *vis, const int32_t *rect,
-                             const float *depth, int W, int H, uint32_t *tile_of,
+                             const float *cf, const float *depth, int W, int H, uint32_t *tile_of,
                              uint32_t *gid_of, uint32_t *ranges) {
   int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
-  int64_t P = orc_count_pairs(n, vis, rect);
+  int64_t P = orc_count_pairs(n, vis, rect, cf);
   pair_t *pr = (pair_t *)malloc(sizeof(pair_t) * (size_t)(P > 0 ? P : 1));
   int64_t q = 0;
   for (int64_t i = 0; i < n; ++i) {
@@ -506,6 +566,7 @@ ORC_API int64_t orc_bin_sort(int64_t n, const uint8_t *vis, const int32_t *rect,
     const int32_t *r = rect + 4 * i;
     for (int y = r[1]; y < r[3]; ++y)
       for (int x = r[0]; x < r[2]; ++x) {
+        if (!tile_meets_ellipse_f(cf + 5 * i, x, y)) continue;
         pr[q].tile = (uint32_t)(y * tiles_x + x);
         pr[q].dkey = fbits(depth[i]);
         pr[q].gid = (uint32_t)i;
@@ -600,11 +661,11 @@ static int dk_cmp(const void *a, const void *b) {
 }
 
 /* Brute-force renderer: for every pixel, scan all Gaussians, keep those
- * whose tile rectangle holds the pixel's tile, order them by (depth, index)
- * and blend.  No pair list, no global sort. */
+ * whose 3-sigma ellipse meets the pixel's tile (inside its rectangle), order
+ * them by (depth, index) and blend.  No pair list, no global sort. */
 ORC_API void orc_render_bruteforce(int64_t n, const uint8_t *vis, const int32_t *rect,
-                                   const float *depth, const double *proj, int W, int H,
-                                   const float *prmf, double *img, double *Tf) {
+                                   const float *cf, const float *depth, const double *proj, int W,
+                                   int H, const float *prmf, double *img, double *Tf) {
   prm_t pp = load_prm(prmf);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int y = 0; y < H; ++y) {
@@ -614,7 +675,8 @@ ORC_API void orc_render_bruteforce(int64_t n, const uint8_t *vis, const int32_t 
       int tx = x / 16, ty = y / 16, m = 0;
       for (int64_t i = 0; i < n; ++i) {
         const int32_t *r = rect + 4 * i;
-        if (vis[i] && tx >= r[0] && tx < r[2] && ty >= r[1] && ty < r[3]) {
+        if (vis[i] && tx >= r[0] && tx < r[2] && ty >= r[1] && ty < r[3] &&
+            tile_meets_ellipse_f(cf + 5 * i, tx, ty)) {
           buf[m].dkey = fbits(depth[i]);
           buf[m].gid = (uint32_t)i;
           ++m;

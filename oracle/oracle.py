@@ -64,14 +64,18 @@ def _declare(L):
     L.orc_select_eq7.restype = _i64
     L.orc_decode.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
                              ctypes.c_float, _p]
-    L.orc_project.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
+    L.orc_project.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p, _p]
     L.orc_project.restype = _i64
-    L.orc_count_pairs.argtypes = [_i64, _p, _p]
+    L.orc_count_pairs.argtypes = [_i64, _p, _p, _p]
     L.orc_count_pairs.restype = _i64
-    L.orc_bin_sort.argtypes = [_i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_count_rect_pairs.argtypes = [_i64, _p, _p]
+    L.orc_count_rect_pairs.restype = _i64
+    L.orc_tile_test.argtypes = [_p, _i32, _i32]
+    L.orc_tile_test.restype = _i32
+    L.orc_bin_sort.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_bin_sort.restype = _i64
     L.orc_composite.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
-    L.orc_render_bruteforce.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
+    L.orc_render_bruteforce.argtypes = [_i64, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_num_threads.restype = _i32
     L.orc_composite_backward.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_project_backward.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
@@ -194,22 +198,33 @@ def project(gf: np.ndarray, cam, prm: np.ndarray, gd: Optional[np.ndarray] = Non
     rect = np.empty((n, 4), np.int32)
     depth = np.empty(n, np.float32)
     proj = np.empty((n, 9), np.float64)
+    cf = np.zeros((n, 5), np.float32)
     cnt = lib().orc_project(n, n, _ptr(gf), _ptr(gd), _ptr(cam_array(cam)), cam.width,
                             cam.height, _ptr(_c(prm, np.float32)), _ptr(vis), _ptr(rect),
-                            _ptr(depth), _ptr(proj))
-    return dict(vis=vis, rect=rect, depth=depth, proj=proj, n_visible=int(cnt))
+                            _ptr(depth), _ptr(proj), _ptr(cf))
+    return dict(vis=vis, rect=rect, depth=depth, proj=proj, cf=cf, n_visible=int(cnt))
+
+
+def tile_test(cf_row, tx, ty) -> bool:
+    """Canonical FP32 tile test of one Gaussian (cf_row = mx, my, qa, qb, qc)."""
+    return bool(lib().orc_tile_test(_ptr(_c(cf_row, np.float32)), int(tx), int(ty)))
+
+
+def count_rect_pairs(pj) -> int:
+    return int(lib().orc_count_rect_pairs(len(pj["vis"]), _ptr(pj["vis"]), _ptr(pj["rect"])))
 
 
 def bin_sort(pj: Dict[str, np.ndarray], cam) -> Dict[str, np.ndarray]:
     n = len(pj["vis"])
-    P = int(lib().orc_count_pairs(n, _ptr(pj["vis"]), _ptr(pj["rect"])))
+    P = int(lib().orc_count_pairs(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["cf"])))
     tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
     tile_of = np.empty(max(P, 1), np.uint32)
     gid_of = np.empty(max(P, 1), np.uint32)
     ranges = np.empty((tiles, 2), np.uint32)
-    lib().orc_bin_sort(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["depth"]), cam.width,
-                       cam.height, _ptr(tile_of), _ptr(gid_of), _ptr(ranges))
-    return dict(tile_of=tile_of[:P], gid_of=gid_of[:P], ranges=ranges, n_pairs=P)
+    lib().orc_bin_sort(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["cf"]), _ptr(pj["depth"]),
+                       cam.width, cam.height, _ptr(tile_of), _ptr(gid_of), _ptr(ranges))
+    return dict(tile_of=tile_of[:P], gid_of=gid_of[:P], ranges=ranges, n_pairs=P,
+                n_rect_pairs=count_rect_pairs(pj))
 
 
 def composite(pj, bs, cam, prm, weights: bool = False):
@@ -229,9 +244,9 @@ def render_bruteforce(pj, cam, prm):
     img = np.empty((3, H, W), np.float64)
     Tf = np.empty((H, W), np.float64)
     n = len(pj["vis"])
-    lib().orc_render_bruteforce(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["depth"]),
-                                _ptr(pj["proj"]), W, H, _ptr(_c(prm, np.float32)), _ptr(img),
-                                _ptr(Tf))
+    lib().orc_render_bruteforce(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["cf"]),
+                                _ptr(pj["depth"]), _ptr(pj["proj"]), W, H,
+                                _ptr(_c(prm, np.float32)), _ptr(img), _ptr(Tf))
     return dict(img=img, T=Tf)
 
 

@@ -66,7 +66,8 @@ class SkipNet(ctypes.Structure):
 class RasterStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
                 ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
-                ("sync_error", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 11)]
+                ("sync_error", ctypes.c_uint32), ("n_candidates", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 10)]
 
 
 # (name, restype, argtypes); kept in the order of include/octgs.h

@@ -107,7 +107,10 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
 
 struct RasterHeader {
   uint32_t n_slots, n_visible, n_pairs, pair_overflow, sync_error;
-  uint32_t reserved[11];
+  uint32_t n_candidates;  // rectangle tiles of the survivors (saturated at 2^32 - 1)
+  uint32_t n_cand_listed; // candidates written (n_candidates, or 0 on overflow)
+  uint32_t n_listed;      // pairs in the sorted list (n_pairs, or 0 on overflow)
+  uint32_t reserved[8];
   uint32_t part_counter[16];  // dynamic partition ids of the radix-sort passes
 };
 
@@ -121,18 +124,22 @@ struct RasterWs {
   uint64_t *rect;         // [gcap] packed u16 x0, y0, x1, y1
   uint32_t *dkey[2];      // [gcap] depth-sort keys (ping-pong)
   uint32_t *dval[2];      // [gcap] depth-sort values = slot ids
-  uint32_t *pair_off;     // [gcap] exclusive prefix of tiles touched, depth order
-  uint32_t *emit_blk;     // [nblk_g]
-  uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
+  uint32_t *pair_off;     // [gcap] exclusive prefix of rectangle tiles, depth order
+  uint64_t *emit_blk;     // [nblk_g] rectangle tiles per block of survivors
+  uint32_t *tkey[2];      // [pcap] tile keys (ping-pong; [1] first holds the candidates)
   uint32_t *tval[2];      // [pcap] slot ids
+  uint64_t *cmask;        // [nruns * 32] ellipse-test ballots of the candidates
+  uint32_t *run_cnt;      // [nruns] kept candidates per run, then their exclusive prefix
   uint32_t *ranges;       // [tiles][2]
   uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 2..4 tile passes)
   uint32_t *lookback;     // [max(4 * ceil(gcap/part), 4 * ceil(pcap/part))][256]
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
   int64_t gcap, pcap;
-  int32_t tiles_x, tiles_y, nblk_g;
+  int32_t tiles_x, tiles_y, nblk_g, nruns;
   size_t bytes;
 };
+
+constexpr int kEmitRun = 2048;  // candidate pairs per block iteration of the emission
 
 RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);
 int tile_sort_passes(int ntiles);

@@ -8,8 +8,11 @@
 //             rectangle, depth key; ballot of survivors
 //   compact   survivors in slot order -> (depth key, slot)
 //   sort      Onesweep on the 32-bit depth keys (4 passes over Gaussians)
-//   emit      pairs in depth order: per Gaussian its rectangle's tiles,
-//             offsets by a two-pass scan, writers balanced over pairs
+//   emit      candidates in depth order: per Gaussian its rectangle's
+//             tiles, offsets by a two-pass scan, writers balanced over
+//             candidates; each candidate is kept iff the 3-sigma ellipse
+//             meets the tile (tile_meets_ellipse); ordered compaction of
+//             the kept ones by ballots and a scan over runs
 //   sort      Onesweep on the tile id (1-3 passes over pairs); stable, so
 //             each tile keeps depth order, ties by slot index
 //   ranges    [start, end) per tile
@@ -21,8 +24,9 @@
 // while moving far fewer bytes: a pair list is typically several times
 // longer than the Gaussian list.
 //
-// Decisions (culls, rectangle, depth key) use the fixed FP32 operation
-// sequence documented at project_decide; continuous values are FP32.
+// Decisions (culls, rectangle, depth key, tile test) use the fixed FP32
+// operation sequences documented at project_decide and tile_meets_ellipse;
+// continuous values are FP32.
 #include "octgs_internal.h"
 
 namespace octgs {
@@ -127,6 +131,41 @@ __device__ __forceinline__ bool project_decide(const Cam &k, float dil, float jc
   return true;
 }
 
+// Tile test, canonical FP32: does the 3-sigma ellipse q(p) <= 9,
+// q = qa dx^2 + 2 qb dx dy + qc dy^2 around (mx, my), meet the box of the
+// tile's pixel centres [16 tx + 0.5, 16 tx + 15.5] x [16 ty + 0.5, 16 ty + 15.5]?
+// The convex quadratic's minimum over the box is 0 with the mean inside;
+// otherwise it lies on an edge facing the mean, at the 1D minimiser clamped
+// to the edge:
+//   X0 = (float)(16 tx) + 0.5, X1 = X0 + 15 (Y alike)
+//   mean's x outside [X0, X1]: xe = nearer of X0, X1; dx = xe - mx;
+//     ys = min(max(my - (qb * dx) / qc, Y0), Y1); dy = ys - my;
+//     q1 = fmaf(qa * dx, dx, fmaf(2 * qb * dx, dy, qc * dy * dy))
+//   mean's y outside [Y0, Y1]: the same with the roles of x and y swapped
+//   keep iff min(q1, q2) <= 9.
+__device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa, float qb, float qc,
+                                                   uint32_t tx, uint32_t ty) {
+  const float X0 = (float)(16u * tx) + 0.5f, X1 = X0 + 15.0f;
+  const float Y0 = (float)(16u * ty) + 0.5f, Y1 = Y0 + 15.0f;
+  const bool in_x = !(mx < X0) && !(mx > X1), in_y = !(my < Y0) && !(my > Y1);
+  float q = INFINITY;
+  if (!in_x) {
+    const float xe = mx < X0 ? X0 : X1;
+    const float dx = xe - mx;
+    const float ys = fminf(fmaxf(my - (qb * dx) / qc, Y0), Y1);
+    const float dy = ys - my;
+    q = fma_(qa * dx, dx, fma_(2.0f * qb * dx, dy, qc * dy * dy));
+  }
+  if (!in_y) {
+    const float ye = my < Y0 ? Y0 : Y1;
+    const float dy = ye - my;
+    const float xs = fminf(fmaxf(mx - (qb * dy) / qa, X0), X1);
+    const float dx = xs - mx;
+    q = fminf(q, fma_(qa * dx, dx, fma_(2.0f * qb * dx, dy, qc * dy * dy)));
+  }
+  return (in_x && in_y) || q <= 9.0f;
+}
+
 __device__ __forceinline__ uint64_t pack_rect(int x0, int y0, int x1, int y1) {
   return (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)y0 << 16) | ((uint64_t)(uint16_t)x1 << 32) |
          ((uint64_t)(uint16_t)y1 << 48);
@@ -177,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
         float4 *p = a.ws.proj + 3 * s;
         p[0] = make_float4(o.mx, o.my, -0.5f * kLog2e * o.ca, -kLog2e * o.cb);
         p[1] = make_float4(-0.5f * kLog2e * o.cc, g[10], g[11], g[12]);
-        p[2] = make_float4(g[13], 0.0f, 0.0f, 0.0f);
+        p[2] = make_float4(g[13], o.ca, o.cb, o.cc);
         a.ws.depth[s] = __float_as_uint(o.zc);
         a.ws.rect[s] = pack_rect(o.x0, o.y0, o.x1, o.y1);
       }
@@ -234,28 +273,32 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
     ws.hdr->n_visible = prefix + gpre[ngroups - 1] + (uint32_t)__popcll(gmask[ngroups - 1]);
 }
 
-// Pair counting over the depth-ordered survivors, chunk per block.
+// Candidate counting over the depth-ordered survivors, chunk per block
+// (64-bit sums: a rectangle can hold up to 2^32 tiles).
 __global__ __launch_bounds__(kBlock) void k_emit_count(RasterWs ws) {
-  __shared__ uint32_t wsum[4];
+  __shared__ uint64_t wsum[4];
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t n = ws.hdr->n_visible;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   if (base >= n) return;
-  uint32_t c = 0;
+  uint64_t c = 0;
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t s = base + i * kBlock + t;
     if (s < n) c += rect_tiles(ws.rect[ws.dval[0][s]]);
   }
-  c = wave_sum(c);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
   if (l == 0) wsum[w] = c;
   __syncthreads();
   if (t == 0) ws.emit_blk[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// Exclusive pair offsets per depth-ordered survivor; the block holding the
-// last survivor publishes the total and the overflow flag.
+// Exclusive candidate offsets per depth-ordered survivor; the block holding
+// the last survivor publishes the total and the overflow flag.  Offsets are
+// used only when the total fits the pair capacity (< 2^30), so 32-bit
+// arithmetic inside a block is exact wherever it matters.
 __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
-  __shared__ uint32_t red[4];
+  __shared__ uint64_t red[4];
   __shared__ uint32_t tmp[8];
   __shared__ uint32_t carry;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
@@ -263,53 +306,54 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
   const int b = blockIdx.x;
   if (n == 0) {
     if (b == 0 && t == 0) {
-      ws.hdr->n_pairs = 0;
-      ws.hdr->reserved[0] = 0;
+      ws.hdr->n_candidates = 0;
+      ws.hdr->n_cand_listed = 0;
     }
     return;
   }
   const int64_t base = (int64_t)b * kChunk;
   if (base >= n) return;
-  uint32_t s = 0;
+  uint64_t s = 0;
   for (int i = t; i < b; i += kBlock) s += ws.emit_blk[i];
-  s = wave_sum(s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (l == 0) red[w] = s;
   if (t == 0) carry = 0;
   __syncthreads();
-  const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
+  const uint64_t prefix = red[0] + red[1] + red[2] + red[3];
   // consecutive 256-entry rows of the chunk, scanned in order
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t sidx = base + i * kBlock + t;
     const uint32_t c = sidx < n ? rect_tiles(ws.rect[ws.dval[0][sidx]]) : 0u;
     uint32_t tot;
     const uint32_t ex = block_excl_scan(c, tmp, &tot);
-    if (sidx < n) ws.pair_off[sidx] = prefix + carry + ex;
+    if (sidx < n) ws.pair_off[sidx] = (uint32_t)prefix + carry + ex;
     __syncthreads();
     if (t == 0) carry += tot;
     __syncthreads();
   }
   if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) {
-    const uint32_t total = prefix + carry;
-    ws.hdr->n_pairs = total;
-    const bool over = (int64_t)total > ws.pcap;
+    const uint64_t total = prefix + ws.emit_blk[b];
+    const bool over = total > (uint64_t)ws.pcap;
+    ws.hdr->n_candidates = (uint32_t)std::min<uint64_t>(total, 0xffffffffull);
     ws.hdr->pair_overflow = over ? 1u : 0u;
-    ws.hdr->reserved[0] = over ? 0u : total;  // pairs actually emitted
+    ws.hdr->n_cand_listed = over ? 0u : (uint32_t)total;
   }
 }
 
-constexpr int kEmitRun = 2048;  // pairs per block iteration
-
-// Pair emission balanced over pairs: a block takes 2048 consecutive output
-// positions, finds the Gaussians covering them by binary search and writes
-// (tile id, slot) for each.
+// Candidate emission balanced over candidates: a block takes a run of 2048
+// consecutive candidate positions, finds the Gaussians covering them by
+// binary search, writes (tile id, slot) to tkey[1] / tval[1], the ellipse
+// test's ballot per 64 positions and the run's kept count.
 __global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws) {
   __shared__ uint32_t offs[kEmitRun + 1];
   __shared__ uint32_t lo_s;
-  const int t = threadIdx.x;
-  const uint32_t P = ws.hdr->reserved[0];
+  __shared__ uint32_t wsum[4];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t P = ws.hdr->n_cand_listed;
   const uint32_t n = ws.hdr->n_visible;
-  for (uint32_t p0 = blockIdx.x * kEmitRun; p0 < P; p0 += gridDim.x * kEmitRun) {
-    const uint32_t p1 = min(P, p0 + kEmitRun);
+  for (uint32_t r = blockIdx.x; (uint64_t)r * kEmitRun < P; r += gridDim.x) {
+    const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
     if (t == 0) {
       // last survivor whose offset <= p0
       uint32_t lo = 0, hi = n;  // invariant: off[lo] <= p0 < off[hi] (off[n] = P)
@@ -324,27 +368,110 @@ __global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws) {
     const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
     for (uint32_t i = t; i < cnt; i += kBlock) offs[i] = ws.pair_off[lo + i];
     __syncthreads();
-    for (uint32_t p = p0 + t; p < p1; p += kBlock) {
-      uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
-      while (b - a > 1) {
-        const uint32_t mid = (a + b) >> 1;
-        if (offs[mid] <= p) a = mid; else b = mid;
+    uint32_t kept = 0;
+#pragma unroll 1
+    for (int k = 0; k < kEmitRun / kBlock; ++k) {
+      const uint32_t p = p0 + k * kBlock + t;
+      bool keep = false;
+      if (p < p1) {
+        uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
+        while (b - a > 1) {
+          const uint32_t mid = (a + b) >> 1;
+          if (offs[mid] <= p) a = mid; else b = mid;
+        }
+        const uint32_t slot = ws.dval[0][lo + a];
+        const uint64_t rc = ws.rect[slot];
+        const uint32_t x0 = rc & 0xffff, y0 = (rc >> 16) & 0xffff, x1 = (rc >> 32) & 0xffff;
+        const uint32_t wdt = x1 - x0;
+        const uint32_t loc = p - offs[a];
+        const uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
+        const float4 pa = ws.proj[3 * (size_t)slot], pc = ws.proj[3 * (size_t)slot + 2];
+        keep = tile_meets_ellipse(pa.x, pa.y, pc.y, pc.z, pc.w, tx, ty);
+        ws.tkey[1][p] = ty * (uint32_t)ws.tiles_x + tx;
+        ws.tval[1][p] = slot;
       }
-      const uint32_t slot = ws.dval[0][lo + a];
-      const uint64_t r = ws.rect[slot];
-      const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff;
-      const uint32_t wdt = x1 - x0;
-      const uint32_t loc = p - offs[a];
-      const uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
-      ws.tkey[0][p] = ty * (uint32_t)ws.tiles_x + tx;
-      ws.tval[0][p] = slot;
+      const uint64_t m = ballot(keep);
+      if (l == 0) ws.cmask[(p0 + k * kBlock + w * kWave) >> 6] = m;
+      kept += (uint32_t)__popcll(m);
+    }
+    if (l == 0) wsum[w] = kept;
+    __syncthreads();
+    if (t == 0) ws.run_cnt[r] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
+// Exclusive prefix of the runs' kept counts, in place (one block); publishes
+// the number of listed pairs.
+__global__ __launch_bounds__(1024) void k_pair_scan(RasterWs ws) {
+  __shared__ uint32_t wtot[16];
+  __shared__ uint32_t carry;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t P = ws.hdr->n_cand_listed;
+  const uint32_t R = (P + kEmitRun - 1) / kEmitRun;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t r0 = 0; r0 < R; r0 += 1024) {
+    const uint32_t r = r0 + t;
+    const uint32_t v = r < R ? ws.run_cnt[r] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (l == 63) wtot[w] = inc;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t x = wtot[i];
+      if (i < w) off += x;
+      tot += x;
+    }
+    if (r < R) ws.run_cnt[r] = off + inc - v;
+    __syncthreads();
+    if (t == 0) carry += tot;
+    __syncthreads();
+  }
+  if (t == 0) {
+    ws.hdr->n_listed = carry;
+    ws.hdr->n_pairs = carry;
+  }
+}
+
+// Ordered compaction of the kept candidates into tkey[0] / tval[0].
+__global__ __launch_bounds__(kBlock) void k_pair_compact(RasterWs ws) {
+  __shared__ uint32_t gpre[kEmitRun / 64];
+  __shared__ uint64_t gmask[kEmitRun / 64];
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint32_t P = ws.hdr->n_cand_listed;
+  constexpr int kG = kEmitRun / 64;  // 32 ballot groups per run
+  for (uint32_t r = blockIdx.x; (uint64_t)r * kEmitRun < P; r += gridDim.x) {
+    const uint32_t p0 = r * kEmitRun;
+    if (w == 0) {
+      const uint64_t m = l < kG ? ws.cmask[(size_t)r * kG + l] : 0ull;
+      const uint32_t c = (uint32_t)__popcll(m);
+      const uint32_t inc = wave_incl_scan(c);
+      if (l < kG) {
+        gpre[l] = inc - c;
+        gmask[l] = m;
+      }
+    }
+    __syncthreads();
+    const uint32_t base = ws.run_cnt[r];
+#pragma unroll 1
+    for (int k = 0; k < kEmitRun / kBlock; ++k) {
+      const int g = k * (kBlock / kWave) + w;
+      const uint64_t m = gmask[g];
+      if ((m >> l) & 1ull) {
+        const uint32_t p = p0 + k * kBlock + t;
+        const uint32_t dst = base + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
+        ws.tkey[0][dst] = ws.tkey[1][p];
+        ws.tval[0][dst] = ws.tval[1][p];
+      }
     }
     __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
-  const uint32_t P = ws.hdr->reserved[0];
+  const uint32_t P = ws.hdr->n_listed;
   const uint32_t *key = ws.tkey[buf];
   for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
     const uint32_t k = key[p];
@@ -473,9 +600,12 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   for (int i = 0; i < 2; ++i) ws.dkey[i] = (uint32_t *)take((size_t)g * 4);
   for (int i = 0; i < 2; ++i) ws.dval[i] = (uint32_t *)take((size_t)g * 4);
   ws.pair_off = (uint32_t *)take((size_t)g * 4);
-  ws.emit_blk = (uint32_t *)take((size_t)ws.nblk_g * 4);
+  ws.emit_blk = (uint64_t *)take((size_t)ws.nblk_g * 8);
   for (int i = 0; i < 2; ++i) ws.tkey[i] = (uint32_t *)take((size_t)pc * 4);
   for (int i = 0; i < 2; ++i) ws.tval[i] = (uint32_t *)take((size_t)pc * 4);
+  ws.nruns = (int)((pc + kEmitRun - 1) / kEmitRun);
+  ws.cmask = (uint64_t *)take((size_t)ws.nruns * (kEmitRun / 64) * 8);
+  ws.run_cnt = (uint32_t *)take((size_t)ws.nruns * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
   ws.hist = (uint32_t *)take(8 * 256 * 4);
   const int64_t parts = std::max((g + kSortPart - 1) / kSortPart, (pc + kSortPart - 1) / kSortPart);
@@ -551,12 +681,14 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(4);
   hipLaunchKernelGGL(k_emit_count, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
   hipLaunchKernelGGL(k_emit_scan, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
-  const int emit_grid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kEmitRun - 1) / kEmitRun, 1), 4096);
+  const int emit_grid = std::min(std::max(ws.nruns, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(emit_grid), dim3(kBlock), 0, s, ws);
+  hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, ws);
+  hipLaunchKernelGGL(k_pair_compact, dim3(emit_grid), dim3(kBlock), 0, s, ws);
   mark(5);
   mark(6);
   const int passes = tile_sort_passes(ntiles);
-  e = radix_sort(ws.tkey, ws.tval, &ws.hdr->reserved[0], ws.pcap, passes, ws.hist + 4 * 256,
+  e = radix_sort(ws.tkey, ws.tval, &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
                  ws.lookback, ws.hdr->part_counter + 4, &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;

@@ -277,7 +277,7 @@ class ViewBuffers:
         torch.cuda.synchronize()
         h = self.ras_ws[:64].cpu().numpy().view(np.uint32)
         return dict(n_slots=int(h[0]), n_visible=int(h[1]), n_pairs=int(h[2]),
-                    pair_overflow=int(h[3]), sync_error=int(h[4]), n_emitted=int(h[5]),
+                    pair_overflow=int(h[3]), sync_error=int(h[4]), n_candidates=int(h[5]),
                     n_selected=int(self.sel_count.item()))
 
     def sorted_lists(self):
@@ -288,7 +288,7 @@ class ViewBuffers:
                                        ctypes.byref(st), ctypes.byref(pt), ctypes.byref(ps),
                                        ctypes.byref(rg)), "octgs_raster_views")
         s = self.stats()
-        P = s["n_emitted"]
+        P = s["n_pairs"]
         base = self.ras_ws.data_ptr()
         ws32 = self.ras_ws.view(torch.int32)
 

@@ -46,7 +46,7 @@ def test_raster_backward_parity(P, orc, W, H, n, seed):
     ref = orc.rasterize(gf, cam, prm)
     dproj = orc.composite_backward(ref["pj"], ref["bs"], cam, prm, dimg.astype(np.float64))
     dref = orc.project_backward(gf.astype(np.float64), ref["pj"], cam, prm, dproj)
-    vb = P.ViewBuffers(n, 1, W, H, ref["bs"]["n_pairs"] + 16, gauss_capacity=n)
+    vb = P.ViewBuffers(n, 1, W, H, ref["bs"]["n_rect_pairs"] + 16, gauss_capacity=n)
     gt = torch.as_tensor(gf).cuda()
     cnt = torch.tensor([n], dtype=torch.int32).cuda()
     c = P.make_camera(cam)

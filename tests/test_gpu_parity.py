@@ -149,11 +149,14 @@ def test_raster_stage_parity(P, orc, W, H, n, seed):
     say("raster stage", W, H, n, seed)
     ref = orc.rasterize(gf, cam, prm_o, weights=True)
     P_ref = ref["bs"]["n_pairs"]
-    vb = P.ViewBuffers(n, 1, W, H, max(P_ref, 1) + 7, gauss_capacity=n, log_weights=True)
+    C_ref = ref["bs"]["n_rect_pairs"]
+    # capacity exactly the candidate count: the tightest that must not overflow
+    vb = P.ViewBuffers(n, 1, W, H, max(C_ref, 1), gauss_capacity=n, log_weights=True)
     _gpu_raster(P, vb, gf, cam, P.raster_params())
     st = vb.stats()
     assert st["sync_error"] == 0 and st["pair_overflow"] == 0
     assert st["n_visible"] == ref["pj"]["n_visible"]
+    assert st["n_candidates"] == C_ref
     assert st["n_pairs"] == P_ref
     tile, slot, ranges = vb.sorted_lists()
     assert np.array_equal(tile, ref["bs"]["tile_of"])
@@ -243,11 +246,16 @@ def test_pair_overflow_flag(P, orc):
     gf = S.random_gaussians(2000, cam, 7)
     ref = orc.rasterize(gf, cam, orc.params_array())
     say("pair overflow")
-    vb = P.ViewBuffers(2000, 1, 128, 128, ref["bs"]["n_pairs"] // 2, gauss_capacity=2000)
+    # a capacity between the kept pairs and the candidates still overflows:
+    # candidates are written before the ellipse test
+    cap = (ref["bs"]["n_pairs"] + ref["bs"]["n_rect_pairs"]) // 2
+    assert ref["bs"]["n_pairs"] < cap < ref["bs"]["n_rect_pairs"]
+    vb = P.ViewBuffers(2000, 1, 128, 128, cap, gauss_capacity=2000)
     _gpu_raster(P, vb, gf, cam, P.raster_params())
     st = vb.stats()
-    assert st["pair_overflow"] == 1 and st["n_pairs"] == ref["bs"]["n_pairs"]
-    assert st["n_emitted"] == 0
+    assert st["pair_overflow"] == 1 and st["n_candidates"] == ref["bs"]["n_rect_pairs"]
+    assert st["n_pairs"] == 0
+    assert np.all(_np(vb.rgb) == 0.0)
 
 
 def test_degenerate_quaternion_decodes_to_identity(P, orc, c1):

@@ -24,7 +24,7 @@ def _decisions(pj, out=None):
     """Culls, rectangles, the sorted pair order and where each pixel stopped."""
     key = (pj["vis"].tobytes(), pj["rect"].tobytes())
     if out is not None:
-        key = key + (out["bs"]["gid_of"].tobytes(), out["last"].tobytes())
+        key = key + (out["bs"]["gid_of"].tobytes(), out["bs"]["tile_of"].tobytes(), out["last"].tobytes())
     return key
 
 

@@ -37,9 +37,50 @@ def pix_grid(W, H):
     return np.meshgrid(x, y)
 
 
-def tile_mask(W, H, x0, y0, x1, y1):
+def tile_mask(W, H, x0, y0, x1, y1, keep=None):
     X, Y = np.meshgrid(np.arange(W) // 16, np.arange(H) // 16)
-    return (X >= x0) & (X < x1) & (Y >= y0) & (Y < y1)
+    m = (X >= x0) & (X < x1) & (Y >= y0) & (Y < y1)
+    if keep is not None:
+        m &= np.vectorize(keep)(X, Y)
+    return m
+
+
+def ellipse_meets_box(mx, my, A, B, C, X0, X1, Y0, Y1):
+    """Does {A dx^2 + 2B dx dy + C dy^2 <= 9} (dx = x - mx) meet the box
+    [X0, X1] x [Y0, Y1]?  Root form, in double: the mean is inside, or on
+    some edge line the chord cut by the ellipse overlaps the edge."""
+    if X0 <= mx <= X1 and Y0 <= my <= Y1:
+        return True
+    # (P, Q, d, lo, hi): q(t) = P d^2 + 2 B d t + Q t^2 along an edge at
+    # offset d from the mean, t in [lo, hi]
+    edges = [(A, C, X - mx, Y0 - my, Y1 - my) for X in (X0, X1)]
+    edges += [(C, A, Y - my, X0 - mx, X1 - mx) for Y in (Y0, Y1)]
+    for P, Q, d, lo, hi in edges:
+        D = (B * d) ** 2 - Q * (P * d * d - 9.0)
+        if D >= 0:
+            r0, r1 = (-B * d - math.sqrt(D)) / Q, (-B * d + math.sqrt(D)) / Q
+            if r1 >= lo and r0 <= hi:
+                return True
+    return False
+
+
+def box_qmin_sampled(mx, my, A, B, C, X0, X1, Y0, Y1, k=2001):
+    """Minimum of the quadratic over the box boundary (and 0 inside), by
+    dense sampling: used only to leave out near-ties from exact checks."""
+    if X0 <= mx <= X1 and Y0 <= my <= Y1:
+        return 0.0
+    t = np.linspace(0.0, 1.0, k)
+    xs = np.concatenate([X0 + (X1 - X0) * t, X0 + (X1 - X0) * t, np.full(k, X0), np.full(k, X1)])
+    ys = np.concatenate([np.full(k, Y0), np.full(k, Y1), Y0 + (Y1 - Y0) * t, Y0 + (Y1 - Y0) * t])
+    dx, dy = xs - mx, ys - my
+    return float((A * dx * dx + 2 * B * dx * dy + C * dy * dy).min())
+
+
+def tile_keep(mx, my, A, B, C):
+    def keep(tx, ty):
+        X0, Y0 = 16.0 * tx + 0.5, 16.0 * ty + 0.5
+        return ellipse_meets_box(mx, my, A, B, C, X0, X0 + 15, Y0, Y0 + 15)
+    return keep
 
 
 # --------------------------------------------------------------------------
@@ -79,7 +120,8 @@ def test_single_gaussian_closed_form(orc, mean):
     r = math.ceil(3 * math.sqrt(lam))
     tx0, tx1 = max(0, math.floor((mx - r) / 16)), min(4, math.floor((mx + r) / 16) + 1)
     ty0, ty1 = max(0, math.floor((my - r) / 16)), min(4, math.floor((my + r) / 16) + 1)
-    inside = tile_mask(cam.width, cam.height, tx0, ty0, tx1, ty1)
+    inside = tile_mask(cam.width, cam.height, tx0, ty0, tx1, ty1,
+                       tile_keep(mx, my, c / det, -b / det, a / det))
     assert tuple(out["pj"]["rect"][0]) == (tx0, ty0, tx1, ty1)
     for ch in range(3):
         exp_img = np.where(inside, alpha * float(g[11 + ch, 0]), 0.0)
@@ -206,7 +248,8 @@ def test_bin_sort_against_enumeration(orc):
         x0, y0, x1, y1 = pj["rect"][i]
         for y in range(y0, y1):
             for x in range(x0, x1):
-                rows.append((y * tx + x, pj["depth"][i].view(np.uint32), i))
+                if orc.tile_test(pj["cf"][i], x, y):
+                    rows.append((y * tx + x, pj["depth"][i].view(np.uint32), i))
     rows = np.array(rows, dtype=np.int64)
     order = np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))
     rows = rows[order]
@@ -217,6 +260,56 @@ def test_bin_sort_against_enumeration(orc):
         s, e = bs["ranges"][t]
         assert np.all(rows[s:e, 0] == t)
         assert np.count_nonzero(rows[:, 0] == t) == e - s
+
+
+def test_tile_test_against_root_form(orc):
+    """The FP32 tile test keeps exactly the tiles whose pixel-centre box the
+    3-sigma ellipse meets (root form in double), away from near-ties; the
+    kept tiles are a subset of the rectangle and include every tile holding
+    a pixel centre inside the ellipse."""
+    rng = np.random.default_rng(7)
+    n_chk = n_tie = 0
+    for _ in range(400):
+        mx, my = rng.uniform(-20, 100, 2)
+        sx, sy = np.exp(rng.uniform(np.log(0.7), np.log(25), 2))
+        th = rng.uniform(0, np.pi)
+        c, s_ = math.cos(th), math.sin(th)
+        Rm = np.array([[c, -s_], [s_, c]])
+        cov = Rm @ np.diag([sx * sx, sy * sy]) @ Rm.T
+        con = np.linalg.inv(cov)
+        cf = np.array([mx, my, con[0, 0], con[0, 1], con[1, 1]], np.float32)
+        A, B, C = (float(v) for v in cf[2:])
+        fx, fy = float(cf[0]), float(cf[1])
+        for tx in range(-1, 8):
+            for ty in range(-1, 8):
+                X0, Y0 = 16.0 * tx + 0.5, 16.0 * ty + 0.5
+                got = orc.tile_test(cf, tx, ty)
+                qmin = box_qmin_sampled(fx, fy, A, B, C, X0, X0 + 15, Y0, Y0 + 15)
+                if abs(qmin - 9.0) < 1e-3:
+                    n_tie += 1
+                    continue
+                n_chk += 1
+                assert got == ellipse_meets_box(fx, fy, A, B, C, X0, X0 + 15, Y0, Y0 + 15), \
+                    (mx, my, sx, sy, th, tx, ty)
+                px = np.arange(16) + 16 * tx + 0.5
+                X, Y = np.meshgrid(px, np.arange(16) + 16 * ty + 0.5)
+                q = A * (X - fx) ** 2 + 2 * B * (X - fx) * (Y - fy) + C * (Y - fy) ** 2
+                if q.min() <= 9.0:
+                    assert got
+    assert n_chk > 30000 and n_tie < n_chk // 100
+
+
+def test_ellipse_binning_keeps_rect_subset(orc):
+    cam = ident_cam(200, 120)
+    g = S.random_gaussians(3000, cam, seed=4)
+    out = orc.rasterize(g, cam, orc.params_array())
+    bs = out["bs"]
+    assert 0 < bs["n_pairs"] < bs["n_rect_pairs"]
+    r = out["pj"]["rect"]
+    W16 = (cam.width + 15) // 16
+    tx, ty = bs["tile_of"] % W16, bs["tile_of"] // W16
+    gi = bs["gid_of"]
+    assert np.all((tx >= r[gi, 0]) & (tx < r[gi, 2]) & (ty >= r[gi, 1]) & (ty < r[gi, 3]))
 
 
 def test_equal_depth_tie_break(orc):
