@@ -118,8 +118,9 @@ struct RasterWs {
   RasterHeader *hdr;
   uint64_t *vis_mask;     // [gcap / 64]
   uint32_t *blk_cnt;      // [nblk_g]
-  float4 *proj;           // [gcap][3]: (mx, my, A, B) (C, opacity, r, g) (b, -, -, -);
-                          // A, B, C = conic scaled for exp2: -0.5 log2e ca, -log2e cb, -0.5 log2e cc
+  float4 *proj;           // [gcap][3]: (mx, my, A, B) (C, log2 opacity, r, g) (b, qa, qb, qc);
+                          // A, B, C = conic scaled for exp2: -0.5 log2e ca, -log2e cb, -0.5 log2e cc;
+                          // qa, qb, qc = the conic itself (tile test)
   uint32_t *depth;        // [gcap] float bits of camera z
   uint64_t *rect;         // [gcap] packed u16 x0, y0, x1, y1
   uint32_t *dkey[2];      // [gcap] depth-sort keys (ping-pong)
@@ -139,6 +140,8 @@ struct RasterWs {
   size_t bytes;
 };
 
+constexpr int kCompThreads = 128;  // forward composite: threads per 16x16 tile (2 pixels each)
+constexpr int kCompBatch = 256;    // list entries staged in LDS per batch
 constexpr int kEmitRun = 2048;  // candidate pairs per block iteration of the emission
 
 RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);

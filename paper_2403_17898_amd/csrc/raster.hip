@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
       if (vis) {
         float4 *p = a.ws.proj + 3 * s;
         p[0] = make_float4(o.mx, o.my, -0.5f * kLog2e * o.ca, -kLog2e * o.cb);
-        p[1] = make_float4(-0.5f * kLog2e * o.cc, g[10], g[11], g[12]);
+        p[1] = make_float4(-0.5f * kLog2e * o.cc, log2f(g[10]), g[11], g[12]);
         p[2] = make_float4(g[13], o.ca, o.cb, o.cc);
         a.ws.depth[s] = __float_as_uint(o.zc);
         a.ws.rect[s] = pack_rect(o.x0, o.y0, o.x1, o.y1);
@@ -489,83 +489,134 @@ struct CompArgs {
   float *gauss_w;
 };
 
-// One 16x16 tile per 256-thread block, one pixel per thread.  Batches of
-// 256 list entries are staged in LDS as two float4 and one float per
-// Gaussian; the per-pixel loop is branch-free (lanes that are done blend
-// alpha 0) so a wave only branches on wave-uniform conditions.
+// One 16x16 tile per block of 128 threads; each thread owns two vertically
+// adjacent pixels of one column, so the column's dx terms are shared.
+// Batches of 256 list entries are staged in LDS as three float4 per
+// Gaussian.  Per pixel and entry (the backward pass repeats this sequence):
+//   dx = x - mx; dy = y - my
+//   p = fma(C' dy, dy, fma(B' dx, dy, fma(A' dx, dx, log2 op)))
+//   a = min(alpha_max, exp2(p)) = min(alpha_max, op G')
+// The loop is branch-free (lanes that are done blend alpha 0), so a wave
+// only branches on wave-uniform conditions.
 template <bool LOG, bool AMIN>
 __device__ __forceinline__ void composite_tile(const CompArgs &a) {
-  __shared__ float4 sA[kBlock], sB[kBlock];
-  __shared__ float sC[kBlock];
-  __shared__ uint32_t s_slot[kBlock];
-  __shared__ float s_w[LOG ? kBlock : 1];
+  __shared__ float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
+  __shared__ uint32_t s_slot[LOG ? kCompBatch : 1];
+  __shared__ float s_w[LOG ? kCompBatch : 1];
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x;
-  const int px = tx * kTile + (t % kTile), py = ty * kTile + (t / kTile);
-  const bool inside = px < a.W && py < a.H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
+  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + 2 * (t / kTile), py1 = py0 + 1;
+  const bool in0 = px < a.W && py0 < a.H, in1 = px < a.W && py1 < a.H;
+  const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = fy0 + 1.0f;
+  const uint32_t start = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile]);
+  const uint32_t end = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile + 1]);
   const uint32_t *vals = a.ws.tval[a.buf];
   const float4 *proj = a.ws.proj;
   const float amax = a.alpha_max, amin = a.alpha_min, tmin = a.t_min;
-  float T = 1.0f, cr = 0.0f, cg = 0.0f, cbl = 0.0f;
-  uint32_t last = end - start;
-  bool done = !inside;
-  for (uint32_t b0 = start; b0 < end; b0 += kBlock) {
-    const uint32_t e = b0 + t;
-    if (e < end) {
-      const uint32_t s = vals[e];
-      s_slot[t] = s;
-      sA[t] = proj[3 * (size_t)s];
-      sB[t] = proj[3 * (size_t)s + 1];
-      sC[t] = proj[3 * (size_t)s + 2].x;
+  float T0 = in0 ? 1.0f : 0.0f, T1 = in1 ? 1.0f : 0.0f;
+  float r0 = 0.0f, g0 = 0.0f, b0c = 0.0f, r1 = 0.0f, g1 = 0.0f, b1c = 0.0f;
+  uint32_t last0 = end - start, last1 = end - start;
+  bool done0 = !in0, done1 = !in1;
+  for (uint32_t b0 = start; b0 < end; b0 += kCompBatch) {
+#pragma unroll
+    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
+      const int i = t + q * kCompThreads;
+      const uint32_t e = b0 + i;
+      if (e < end) {
+        const uint32_t s = vals[e];
+        if (LOG) s_slot[i] = s;
+        sA[i] = proj[3 * (size_t)s];
+        sB[i] = proj[3 * (size_t)s + 1];
+        sC[i] = proj[3 * (size_t)s + 2];
+      }
+      if (LOG) s_w[i] = 0.0f;
     }
-    if (LOG) s_w[t] = 0.0f;
     __syncthreads();
-    const int nb = (int)min((uint32_t)kBlock, end - b0);
+    const int nb = __builtin_amdgcn_readfirstlane((int)min((uint32_t)kCompBatch, end - b0));
     const uint32_t base = b0 - start + 1u;
-    for (int j = 0; j < nb; ++j) {
-      if (!LOG && (j & 15) == 0 && __all(done)) break;
+    auto step = [&](int j) {
       const float4 A = sA[j];
       const float4 B = sB[j];
-      const float dx = fx - A.x, dy = fy - A.y;
-      const float pw = fma_(A.z * dx, dx, fma_(B.x * dy, dy, A.w * dx * dy));
-      float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(pw));
-      if (AMIN) al = al < amin ? 0.0f : al;
-      al = done ? 0.0f : al;
-      const float wt = al * T;
-      cr = fma_(wt, B.z, cr);
-      cg = fma_(wt, B.w, cg);
-      cbl = fma_(wt, sC[j], cbl);
-      T = T - wt;
-      const bool term = !done && T < tmin;
-      last = term ? base + (uint32_t)j : last;
-      done = done || term;
+      const float cbl = sC[j].x;
+      const float dx = fx - A.x;
+      const float adx = fma_(A.z * dx, dx, B.y);
+      const float bdx = A.w * dx;
+      const float dy0 = fy0 - A.y, dy1 = fy1 - A.y;
+      const float p0 = fma_(B.x * dy0, dy0, fma_(bdx, dy0, adx));
+      const float p1 = fma_(B.x * dy1, dy1, fma_(bdx, dy1, adx));
+      float al0 = fminf(amax, __builtin_amdgcn_exp2f(p0));
+      float al1 = fminf(amax, __builtin_amdgcn_exp2f(p1));
+      if (AMIN) {
+        al0 = al0 < amin ? 0.0f : al0;
+        al1 = al1 < amin ? 0.0f : al1;
+      }
+      al0 = done0 ? 0.0f : al0;
+      al1 = done1 ? 0.0f : al1;
+      const float w0 = al0 * T0, w1 = al1 * T1;
+      r0 = fma_(w0, B.z, r0);
+      g0 = fma_(w0, B.w, g0);
+      b0c = fma_(w0, cbl, b0c);
+      r1 = fma_(w1, B.z, r1);
+      g1 = fma_(w1, B.w, g1);
+      b1c = fma_(w1, cbl, b1c);
+      T0 = T0 - w0;
+      T1 = T1 - w1;
+      // a done lane blends nothing more, so its T stays below t_min; an
+      // outside lane starts at T = 0
+      const bool n0 = T0 < tmin, n1 = T1 < tmin;
+      const uint32_t li = base + (uint32_t)j;
+      last0 = (n0 && !done0) ? li : last0;
+      last1 = (n1 && !done1) ? li : last1;
+      done0 = n0;
+      done1 = n1;
       if (LOG) {
-        const float ws = wave_sum_f(wt);
+        const float ws = wave_sum_f(w0 + w1);
         if (__lane_id() == 0 && ws != 0.0f) atomicAdd(&s_w[j], ws);
+      }
+    };
+    // groups of 16 entries, with a wave-uniform exit check between groups
+    for (int j0 = 0; j0 < nb; j0 += 16) {
+      if (!LOG && __all(done0 && done1)) break;
+      if (j0 + 16 <= nb) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) step(j0 + k);
+      } else {
+        for (int j = j0; j < nb; ++j) step(j);
       }
     }
     if (LOG) {
       __syncthreads();
-      if (t < nb && s_w[t] != 0.0f) atomicAdd(&a.gauss_w[s_slot[t]], s_w[t]);
+#pragma unroll
+      for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
+        const int i = t + q * kCompThreads;
+        if (i < nb && s_w[i] != 0.0f) atomicAdd(&a.gauss_w[s_slot[i]], s_w[i]);
+      }
     }
-    if (__syncthreads_count(done) == kBlock) break;
+    if (__syncthreads_count(done0 && done1) == kCompThreads) break;
   }
-  if (inside) {
-    const size_t pix = (size_t)py * a.W + px, plane = (size_t)a.W * a.H;
-    a.rgb[pix] = fma_(T, a.bg[0], cr);
-    a.rgb[plane + pix] = fma_(T, a.bg[1], cg);
-    a.rgb[2 * plane + pix] = fma_(T, a.bg[2], cbl);
-    a.T_final[pix] = T;
-    a.last[pix] = last;
+  const size_t plane = (size_t)a.W * a.H;
+  if (in0) {
+    const size_t pix = (size_t)py0 * a.W + px;
+    a.rgb[pix] = fma_(T0, a.bg[0], r0);
+    a.rgb[plane + pix] = fma_(T0, a.bg[1], g0);
+    a.rgb[2 * plane + pix] = fma_(T0, a.bg[2], b0c);
+    a.T_final[pix] = T0;
+    a.last[pix] = last0;
+  }
+  if (in1) {
+    const size_t pix = (size_t)py1 * a.W + px;
+    a.rgb[pix] = fma_(T1, a.bg[0], r1);
+    a.rgb[plane + pix] = fma_(T1, a.bg[1], g1);
+    a.rgb[2 * plane + pix] = fma_(T1, a.bg[2], b1c);
+    a.T_final[pix] = T1;
+    a.last[pix] = last1;
   }
 }
 
 template <bool LOG>
-__global__ __launch_bounds__(kBlock) void k_composite(CompArgs a) {
+__global__ __launch_bounds__(kCompThreads) void k_composite(CompArgs a) {
   if (a.alpha_min > 0.0f)
     composite_tile<LOG, true>(a);
   else
@@ -710,9 +761,9 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   ca.gauss_w = gauss_w;
   mark(8);
   if (gauss_w)
-    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kBlock), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kCompThreads), 0, s, ca);
   else
-    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kBlock), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kCompThreads), 0, s, ca);
   mark(9);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }

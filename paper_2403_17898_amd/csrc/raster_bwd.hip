@@ -90,10 +90,11 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
       const float4 A = sA[j];
       const float4 B = sB[j];
       const float cb_ = sC[j];
+      // the forward's sequence, so a0 (= op G') is bit-identical to it
       const float dx = fx - A.x, dy = fy - A.y;
-      const float pw = fma_(A.z * dx, dx, fma_(B.x * dy, dy, A.w * dx * dy));
-      const float G = __builtin_amdgcn_exp2f(pw);
-      const float a0 = B.y * G;
+      const float adx = fma_(A.z * dx, dx, B.y);
+      const float pwl = fma_(B.x * dy, dy, fma_(A.w * dx, dy, adx));
+      const float a0 = __builtin_amdgcn_exp2f(pwl);
       const float al = fminf(amax, a0);
       bool valid = li < last;
       if (AMIN) valid = valid && !(al < amin);
@@ -113,9 +114,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
         bb = fma_(w, cb_, bb);
         T = Ti;
         if (a0 <= amax) {
-          const float dG = dLda * B.y;
-          g[5] = dLda * G;
-          const float dpw = dG * G * kLn2;
+          g[5] = dLda * __builtin_amdgcn_exp2f(pwl - B.y);  // dL/dop = dL/da G'
+          const float dpw = dLda * a0 * kLn2;
           // p = A' dx^2 + B' dx dy + C' dy^2 with the exp2-scaled conic
           const float dAs = dpw * dx * dx, dBs = dpw * dx * dy, dCs = dpw * dy * dy;
           g[2] = dAs * (-0.5f * kLog2e);
