@@ -95,7 +95,8 @@ typedef struct {
  * a quaternion w, x, y, z).  Each head is Linear(in, width) -> ReLU ->
  * Linear(width, out) with in = feat_dim + 4 (feature, relative distance,
  * viewing direction).  w1 is [in][width], w2 is [width][out], row-major,
- * FP32, device memory; the BF16 path rounds them to BF16 itself. */
+ * FP32, device memory, each 16-byte aligned (octgs_decode returns
+ * OCTGS_EINVAL otherwise); the BF16 path rounds them to BF16 itself. */
 typedef struct {
   int32_t width; /* hidden width, 16..64, multiple of 16 */
   const float *w1[3], *b1[3], *w2[3], *b2[3];

@@ -76,9 +76,57 @@ struct alignas(16) Smem {
   uint32_t aidx[kTM];
 };
 
+// Weight staging into LDS in the path's precision T (float, or BF16 bits),
+// every 16-byte load in flight before the first store.  Loads and stores are
+// unconditional at a clamped index (a thread past the end rewrites the last
+// element with the value it holds), which keeps the code straight-line so
+// the loads are not serialised behind branches.  U bounds the float4 loads
+// per thread; n >= 1 float4.
+template <typename T>
+__device__ __forceinline__ void put4(T *dst, int i4, const float4 &v) {
+  if constexpr (std::is_same<T, float>::value) {
+    reinterpret_cast<float4 *>(dst)[i4] = v;
+  } else {
+    uint2 u;
+    u.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+    u.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+    reinterpret_cast<uint2 *>(dst)[i4] = u;
+  }
+}
+
+template <int U>
+struct Ld4 {
+  float4 v[U];
+  __device__ __forceinline__ void load(const float *src, int n, int t) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = reinterpret_cast<const float4 *>(src)[min(t + u * kBlock, n - 1)];
+  }
+  template <typename T>
+  __device__ __forceinline__ void store(T *dst, int n, int t) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) put4(dst, min(t + u * kBlock, n - 1), v[u]);
+  }
+};
+
+// One of three pointers by a lane-varying index, without indexing the
+// kernel-argument array through memory.
+__device__ __forceinline__ const float *pick3(const float *const p[3], int h) {
+  return h == 0 ? p[0] : (h == 1 ? p[1] : p[2]);
+}
+
+constexpr int kStageElems = 3 * kIn * kMaxW + kMaxW * kMaxNO;  // w1 then w2, every head
+
+template <bool BF16>
+union alignas(16) DecodeLds {
+  Smem<BF16> sm;
+  typename Smem<BF16>::T stage[kStageElems];
+};
+
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
-  __shared__ Smem<BF16> sm;
+  typedef typename Smem<BF16>::T T;
+  __shared__ DecodeLds<BF16> lds;
+  Smem<BF16> &sm = lds.sm;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const int g = l / 16, lc = l % 16;
   const int k = a.k, W = a.W;
@@ -87,7 +135,40 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
   const int n2tiles = t0 + t1 + t2;
   const int off_c = t0 * 16, off_s = (t0 + t1) * 16;
 
+  // blocks beyond the listed anchors exit before loading any weights
+  const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
+  if (blockIdx.x == 0 && t == 0) *a.out_count = m_total * (uint32_t)k;
+  if ((uint64_t)blockIdx.x * kTM >= m_total) return;
+
   // ---- weights of this wave's column tiles, kept in registers ----
+  // All weights are staged through LDS first (before the tile buffers are
+  // used) with one batch of coalesced loads; gathering the fragment layout
+  // straight from global memory would serialise dozens of L2 round trips.
+  // Layout: w1 of heads 0..2 ([kIn][W] each), then w2 of heads 0..2
+  // ([W][k], [W][3k], [W][7k]).
+  const int wk = W * k;
+  const int w2off[3] = {3 * kIn * W, 3 * kIn * W + wk, 3 * kIn * W + 4 * wk};
+  {
+    // float4 per thread: w1 head <= 576 / 256 -> 3; w2 heads <= 256, 768, 1792 -> 1, 3, 7
+    const int n1 = kIn * W / 4;
+    Ld4<3> x0, x1, x2;
+    Ld4<1> y0;
+    Ld4<3> y1;
+    Ld4<7> y2;
+    x0.load(a.w1[0], n1, t); x1.load(a.w1[1], n1, t); x2.load(a.w1[2], n1, t);
+    y0.load(a.w2[0], wk / 4, t); y1.load(a.w2[1], 3 * wk / 4, t); y2.load(a.w2[2], 7 * wk / 4, t);
+    x0.store(lds.stage, n1, t);
+    x1.store(lds.stage + kIn * W, n1, t);
+    x2.store(lds.stage + 2 * kIn * W, n1, t);
+    y0.store(lds.stage + w2off[0], wk / 4, t);
+    y1.store(lds.stage + w2off[1], 3 * wk / 4, t);
+    y2.store(lds.stage + w2off[2], 7 * wk / 4, t);
+  }
+  __syncthreads();
+  auto wval = [&](int off) -> float {
+    if constexpr (BF16) return __uint_as_float((uint32_t)lds.stage[off] << 16);
+    else return lds.stage[off];
+  };
   // layer 1: tiles w, w + 4, w + 8 of the 3W columns
   constexpr int KS1 = BF16 ? kInPad / 16 : kIn / 4;  // 3 or 9 k-steps
   constexpr int KV = BF16 ? 4 : 1;                   // k values per lane per step
@@ -99,17 +180,17 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
     const int n = ct * 16 + lc;
     const bool on = ct < n1tiles;
     const int head = on ? n / W : 0, hc = on ? n - head * W : 0;
-    b1r[q] = on ? a.b1[head][hc] : 0.0f;
+    b1r[q] = on ? pick3(a.b1, head)[hc] : 0.0f;
 #pragma unroll
     for (int ks = 0; ks < KS1; ++ks) {
       float v[KV];
 #pragma unroll
       for (int j = 0; j < KV; ++j) {
         const int kk = ks * (4 * KV) + g * KV + j;
-        v[j] = (on && kk < kIn) ? a.w1[head][kk * W + hc] : 0.0f;
+        v[j] = (on && kk < kIn) ? wval((head * kIn + kk) * W + hc) : 0.0f;
       }
       if constexpr (BF16) {
-        s4 s;
+        s4 s;  // already BF16 values: the conversion is exact
         s[0] = (short)f2bf(v[0]); s[1] = (short)f2bf(v[1]);
         s[2] = (short)f2bf(v[2]); s[3] = (short)f2bf(v[3]);
         B1[q][ks] = s;
@@ -131,14 +212,15 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
     if (on) l2_tile(c, k, head, col0, ncol);
     const int col = col0 + lc;
     const bool cv = on && col < ncol;
-    b2r[q] = cv ? a.b2[head][col] : 0.0f;
+    b2r[q] = cv ? pick3(a.b2, head)[col] : 0.0f;
+    const int base = head == 0 ? w2off[0] : (head == 1 ? w2off[1] : w2off[2]);
 #pragma unroll
     for (int ks = 0; ks < KS2; ++ks) {
       float v[KV];
 #pragma unroll
       for (int j = 0; j < KV; ++j) {
         const int kk = ks * (4 * KV) + g * KV + j;
-        v[j] = (cv && kk < W) ? a.w2[head][kk * ncol + col] : 0.0f;
+        v[j] = (cv && kk < W) ? wval(base + kk * ncol + col) : 0.0f;
       }
       if constexpr (BF16) {
         s4 s;
@@ -150,9 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
       }
     }
   }
+  __syncthreads();
 
-  const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
-  if (blockIdx.x == 0 && t == 0) *a.out_count = m_total * (uint32_t)k;
   const int64_t cap = a.cap;
 
   for (uint32_t tile = blockIdx.x; tile * kTM < m_total; tile += gridDim.x) {
@@ -315,8 +396,10 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   if (precision == OCTGS_FP32 && !an->feat) return OCTGS_EINVAL;
   if (precision == OCTGS_BF16 && !an->feat_bf16) return OCTGS_EINVAL;
   if (!(an->d_max > 0.0f)) return OCTGS_EINVAL;
-  for (int h = 0; h < 3; ++h)
+  for (int h = 0; h < 3; ++h) {
     if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h]) return OCTGS_EINVAL;
+    if (((uintptr_t)mlp->w1[h] | (uintptr_t)mlp->w2[h]) & 15) return OCTGS_EINVAL;
+  }
   if (out->capacity / an->k > 0x7fffffff) return OCTGS_EINVAL;
   DecodeArgs a;
   a.n = an->n;
@@ -333,8 +416,10 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   a.idx = idx; a.count = count; a.out = out->data; a.cap = out->capacity;
   a.out_count = out->count;
   const int64_t tiles = std::max<int64_t>(1, (a.cap_anchors + kTM - 1) / kTM);
-  // persistent blocks: each loads its weight slices once and loops over tiles
-  const int grid = (int)std::min<int64_t>(tiles, 512);
+  // persistent blocks: each loads its weight slices once and loops over
+  // tiles; as many as stay resident at once (LDS: 2 FP32 or 4 BF16 blocks
+  // per CU), blocks without a tile exit before loading weights
+  const int grid = (int)std::min<int64_t>(tiles, precision == OCTGS_BF16 ? 1024 : 512);
   hipStream_t s = (hipStream_t)stream;
   if (precision == OCTGS_BF16)
     hipLaunchKernelGGL(k_decode<true>, dim3(grid), dim3(kBlock), 0, s, a);
