@@ -110,8 +110,7 @@ struct RasterHeader {
   uint32_t n_candidates;  // rectangle tiles of the survivors (saturated at 2^32 - 1)
   uint32_t n_cand_listed; // candidates written (n_candidates, or 0 on overflow)
   uint32_t n_listed;      // pairs in the sorted list (n_pairs, or 0 on overflow)
-  uint32_t reserved[8];
-  uint32_t part_counter[16];  // dynamic partition ids of the radix-sort passes
+  uint32_t reserved[24];
 };
 
 struct RasterWs {
@@ -126,17 +125,19 @@ struct RasterWs {
   uint32_t *dkey[2];      // [gcap] depth-sort keys (ping-pong)
   uint32_t *dval[2];      // [gcap] depth-sort values = slot ids
   uint32_t *pair_off;     // [gcap] exclusive prefix of rectangle tiles, depth order
-  uint64_t *emit_blk;     // [nblk_g] rectangle tiles per block of survivors
-  uint32_t *tkey[2];      // [pcap] tile keys (ping-pong; [1] first holds the candidates)
+  uint32_t *lb_emit;      // [nblk_g] look-back status of the candidate scan's chunks
+  uint32_t *run_first;    // [nruns] depth-order index of the survivor holding candidate 2048 r
+  uint32_t *lb_pair;      // [nruns] look-back status of the emission's runs
+  uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
   uint32_t *tval[2];      // [pcap] slot ids
-  uint64_t *cmask;        // [nruns * 32] ellipse-test ballots of the candidates
-  uint32_t *run_cnt;      // [nruns] kept candidates per run, then their exclusive prefix
   uint32_t *ranges;       // [tiles][2]
-  uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 2..4 tile passes)
-  uint32_t *lookback;     // [max(4 * ceil(gcap/part), 4 * ceil(pcap/part))][256]
+  uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 1..4 tile passes)
+  uint32_t *lookback;     // [4][ceil(gcap / kSortPart)][256] depth-sort look-back
+  uint32_t *lookback_t;   // [tile passes][ceil(pcap / kSortPart)][256] tile-sort look-back
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
   int64_t gcap, pcap;
-  int32_t tiles_x, tiles_y, nblk_g, nruns;
+  int32_t tiles_x, tiles_y, nblk_g, nruns, tile_passes;
+  size_t lb_words, lbt_words;  // look-back words to clear before the sorts
   size_t bytes;
 };
 
@@ -157,7 +158,7 @@ struct CamParams {
 
 // ---------------------------------------------------------------------------
 // radix sort (Onesweep: one histogram pass, then one pass per digit with
-// decoupled look-back across dynamically numbered partitions)
+// decoupled look-back across the partitions)
 // ---------------------------------------------------------------------------
 
 constexpr int kSortItems = 8;
@@ -166,11 +167,66 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
 // key, stably.  On return the sorted data is in buffers index `passes % 2`.
-// hist: [passes][256] zeroed beforehand; part_counter: [passes] zeroed
-// beforehand; lookback: passes * ceil(cap / kSortPart) * 256 words.
+// lookback: passes * ceil(cap / kSortPart) * 256 words.  With prepared ==
+// false a first kernel builds hist ([passes][256], zeroed beforehand) and
+// clears the look-back words; with prepared == true the caller has done both.
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
-                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *part_counter,
-                      uint32_t *err_flag, hipStream_t stream);
+                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *err_flag,
+                      bool prepared, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// chained scan: decoupled look-back over one value per partition
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kLbAgg = 1u << 30;       // status flag: partition aggregate
+constexpr uint32_t kLbInc = 2u << 30;       // status flag: inclusive prefix
+constexpr uint32_t kLbVal = (1u << 30) - 1;  // value bits; values saturate here
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const uint32_t s = a + b;  // a, b <= kLbVal, so no wrap
+  return s > kLbVal ? kLbVal : s;
+}
+
+// Called by all 64 lanes of one wave.  Publishes partition `part`'s
+// aggregate `agg` (<= kLbVal), sums the predecessors' values back to the
+// nearest inclusive one, 64 partitions per round trip, publishes the
+// inclusive value and returns the exclusive prefix (saturating at kLbVal).
+// status[] must be zero before the first partition publishes.  A wait that
+// exceeds kSpinLimit sets *err and returns what it has.
+__device__ __forceinline__ uint32_t chained_lookback(uint32_t *status, uint32_t part, uint32_t agg,
+                                                     uint32_t *err, uint32_t spin_limit) {
+  const int l = __lane_id();
+  if (l == 0) st_rel(&status[part], (part == 0 ? kLbInc : kLbAgg) | agg);
+  uint32_t excl = 0;
+  int64_t p = (int64_t)part - 1;
+  uint32_t spins = 0;
+  while (p >= 0) {
+    const int64_t q = p - l;
+    const uint32_t s = q >= 0 ? ld_acq(&status[q]) : kLbInc;  // before partition 0: inclusive 0
+    const uint64_t ready = ballot((s & ~kLbVal) != 0u);
+    const uint64_t inc = ballot((s & ~kLbVal) == kLbInc);
+    const int first = inc ? __builtin_ctzll(inc) : 64;
+    const uint64_t need = first < 63 ? ((2ull << first) - 1ull) : ~0ull;
+    if ((ready & need) != need) {
+      if (++spins > spin_limit) {
+        if (l == 0) atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint32_t v = ((need >> l) & 1ull) ? (s & kLbVal) : 0u;
+    // saturating wave sum: 64 values of 30 bits fit in 36 bits
+    uint64_t v64 = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v64 += __shfl_xor(v64, o, 64);
+    excl = sat_add(excl, (uint32_t)(v64 > kLbVal ? kLbVal : v64));
+    if (first < 64) break;
+    p -= 64;
+  }
+  if (l == 0 && part > 0) st_rel(&status[part], kLbInc | sat_add(excl, agg));
+  return excl;
+}
 
 // ---------------------------------------------------------------------------
 // FP32 GEMM: C (+)= op(A) op(B) [+ bias] [* (mask > 0)]

@@ -166,6 +166,17 @@ __device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa,
   return (in_x && in_y) || q <= 9.0f;
 }
 
+// Zeroes the radix-sort look-back words (256 per partition) of partitions
+// j with kSortPart j in [a, b), j < nparts, in each of `passes` regions of
+// `stride` words; all threads of the block take part.
+__device__ __forceinline__ void clear_partitions(uint32_t *lb, size_t stride, uint32_t a, uint32_t b,
+                                                 int passes, size_t nparts) {
+  const uint32_t j0 = (a + kSortPart - 1) / kSortPart;
+  const uint32_t j1 = (uint32_t)std::min<uint64_t>(((uint64_t)b + kSortPart - 1) / kSortPart, nparts);
+  for (int p = 0; p < passes; ++p)
+    for (uint32_t j = j0; j < j1; ++j) lb[p * stride + (size_t)j * 256 + threadIdx.x] = 0u;
+}
+
 __device__ __forceinline__ uint64_t pack_rect(int x0, int y0, int x1, int y1) {
   return (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)y0 << 16) | ((uint64_t)(uint16_t)x1 << 32) |
          ((uint64_t)(uint16_t)y1 << 48);
@@ -174,13 +185,6 @@ __device__ __forceinline__ uint64_t pack_rect(int x0, int y0, int x1, int y1) {
 __device__ __forceinline__ uint32_t rect_tiles(uint64_t r) {
   const uint32_t x0 = r & 0xffff, y0 = (r >> 16) & 0xffff, x1 = (r >> 32) & 0xffff, y1 = r >> 48;
   return (x1 - x0) * (y1 - y0);
-}
-
-__global__ void k_raster_init(RasterHeader *hdr, uint32_t *ranges, int ntiles, uint32_t *hist) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (int)(sizeof(RasterHeader) / 4)) ((uint32_t *)hdr)[i] = 0u;
-  if (i < 8 * 256) hist[i] = 0u;
-  for (int j = i; j < 2 * ntiles; j += gridDim.x * blockDim.x) ranges[j] = 0u;
 }
 
 struct ProjArgs {
@@ -195,11 +199,24 @@ struct ProjArgs {
   float *gauss_w;
 };
 
+// Also clears the per-call state of the later stages (header, tile ranges,
+// radix histograms, the scans' look-back status words), which the kernel
+// itself never reads.
 __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
   __shared__ uint32_t wsum[4];
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t n = (uint32_t)min<int64_t>(*a.count, a.gcap);
-  if (blockIdx.x == 0 && t == 0) a.ws.hdr->n_slots = n;
+  {
+    const RasterWs &ws = a.ws;
+    const size_t gi = (size_t)blockIdx.x * kBlock + t, gs = (size_t)gridDim.x * kBlock;
+    if (blockIdx.x == 0 && t < (int)(sizeof(RasterHeader) / 4))
+      reinterpret_cast<uint32_t *>(ws.hdr)[t] = t == 0 ? n : 0u;  // n_slots is word 0
+    const size_t nr = 2 * (size_t)ws.tiles_x * ws.tiles_y;
+    for (size_t i = gi; i < nr; i += gs) ws.ranges[i] = 0u;
+    for (size_t i = gi; i < 8 * 256; i += gs) ws.hist[i] = 0u;
+    for (size_t i = gi; i < (size_t)ws.nblk_g; i += gs) ws.lb_emit[i] = 0u;
+    for (size_t i = gi; i < (size_t)ws.nruns; i += gs) ws.lb_pair[i] = 0u;
+  }
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   if (base >= n) return;
   uint32_t cnt = 0;
@@ -233,10 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
 }
 
 // Ordered compaction of the survivors: (depth key, slot) in slot order.
+// It also accumulates the four 8-bit digit histograms of the depth keys for
+// the radix sort.
 __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const uint32_t *count) {
   __shared__ uint32_t red[4];
   __shared__ uint32_t gpre[64];
   __shared__ uint64_t gmask[64];
+  __shared__ uint32_t h[4][256];
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t n = (uint32_t)min<int64_t>(*count, ws.gcap);
   const int b = blockIdx.x;
@@ -259,214 +279,217 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
     gmask[l] = m;
   }
   __syncthreads();
+  for (int i = t; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
+  __syncthreads();
   const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
   for (int gi = w; gi < ngroups; gi += 4) {
     const uint64_t m = gmask[gi];
     if ((m >> l) & 1ull) {
       const uint32_t pos = prefix + gpre[gi] + (uint32_t)__popcll(m & lanemask_lt());
       const uint32_t slot = (uint32_t)(base + 64 * gi + l);
-      ws.dkey[0][pos] = ws.depth[slot];
+      const uint32_t key = ws.depth[slot];
+      ws.dkey[0][pos] = key;
       ws.dval[0][pos] = slot;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) atomicAdd(&h[d][(key >> (8 * d)) & 255u], 1u);
     }
   }
-  if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0)
-    ws.hdr->n_visible = prefix + gpre[ngroups - 1] + (uint32_t)__popcll(gmask[ngroups - 1]);
-}
-
-// Candidate counting over the depth-ordered survivors, chunk per block
-// (64-bit sums: a rectangle can hold up to 2^32 tiles).
-__global__ __launch_bounds__(kBlock) void k_emit_count(RasterWs ws) {
-  __shared__ uint64_t wsum[4];
-  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
-  const uint32_t n = ws.hdr->n_visible;
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  if (base >= n) return;
-  uint64_t c = 0;
-  for (int i = 0; i < kChunkPerThread; ++i) {
-    const int64_t s = base + i * kBlock + t;
-    if (s < n) c += rect_tiles(ws.rect[ws.dval[0][s]]);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if (l == 0) wsum[w] = c;
+  const uint32_t mine = gpre[ngroups - 1] + (uint32_t)__popcll(gmask[ngroups - 1]);
+  if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) ws.hdr->n_visible = prefix + mine;
+  // clear the depth sort's look-back words of the partitions that start in
+  // this block's output range [prefix, prefix + mine), for all four passes
+  clear_partitions(ws.lookback, ws.lb_words / 4, prefix, prefix + mine, 4, ws.lb_words / 4 / 256);
   __syncthreads();
-  if (t == 0) ws.emit_blk[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const uint32_t v = h[d][t];
+    if (v) atomicAdd(&ws.hist[d * 256 + t], v);
+  }
 }
 
-// Exclusive candidate offsets per depth-ordered survivor; the block holding
-// the last survivor publishes the total and the overflow flag.  Offsets are
-// used only when the total fits the pair capacity (< 2^30), so 32-bit
-// arithmetic inside a block is exact wherever it matters.
+// Candidate scan over the depth-ordered survivors (one chunk of 1024 per
+// block, offsets chained by decoupled look-back): pair_off[s] = rectangle tiles of the survivors before s, and
+// run_first[r] = the survivor that holds candidate 2048 r.  The chunk
+// holding the last survivor publishes the total and the overflow flag.
+// Values saturate at 2^30 - 1, above any admissible pair capacity, so they
+// are exact whenever the candidates fit.
 __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
-  __shared__ uint64_t red[4];
   __shared__ uint32_t tmp[8];
-  __shared__ uint32_t carry;
+  __shared__ uint64_t red[4];
+  __shared__ uint32_t s_excl;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t n = ws.hdr->n_visible;
-  const int b = blockIdx.x;
-  if (n == 0) {
-    if (b == 0 && t == 0) {
-      ws.hdr->n_candidates = 0;
-      ws.hdr->n_cand_listed = 0;
-    }
-    return;
-  }
-  const int64_t base = (int64_t)b * kChunk;
-  if (base >= n) return;
-  uint64_t s = 0;
-  for (int i = t; i < b; i += kBlock) s += ws.emit_blk[i];
+  const uint32_t nch = (n + kChunk - 1) / kChunk;
+  if (blockIdx.x >= nch) return;  // n == 0: the cleared header already says 0
+  // chunk id = block id: blocks are dispatched in index order, so every
+  // chunk a block waits on belongs to a block that is already running
+  const uint32_t c = blockIdx.x;
+  const int64_t base = (int64_t)c * kChunk;
+  uint32_t cnt[kChunkPerThread];
+  uint64_t mine = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (l == 0) red[w] = s;
-  if (t == 0) carry = 0;
-  __syncthreads();
-  const uint64_t prefix = red[0] + red[1] + red[2] + red[3];
-  // consecutive 256-entry rows of the chunk, scanned in order
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t sidx = base + i * kBlock + t;
-    const uint32_t c = sidx < n ? rect_tiles(ws.rect[ws.dval[0][sidx]]) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(c, tmp, &tot);
-    if (sidx < n) ws.pair_off[sidx] = (uint32_t)prefix + carry + ex;
-    __syncthreads();
-    if (t == 0) carry += tot;
-    __syncthreads();
+    cnt[i] = sidx < n ? min(rect_tiles(ws.rect[ws.dval[0][sidx]]), kLbVal) : 0u;
+    mine += cnt[i];
   }
-  if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) {
-    const uint64_t total = prefix + ws.emit_blk[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+  if (l == 0) red[w] = mine;
+  __syncthreads();
+  const uint64_t total64 = red[0] + red[1] + red[2] + red[3];
+  const uint32_t agg = (uint32_t)std::min<uint64_t>(total64, kLbVal);
+  if (w == 0) {
+    const uint32_t ex = chained_lookback(ws.lb_emit, c, agg, &ws.hdr->sync_error, kSpinLimit);
+    if (l == 0) s_excl = ex;
+  }
+  __syncthreads();
+  const uint32_t excl = s_excl;
+  const bool exact = total64 < kLbVal && excl < kLbVal;  // else the call overflows
+  // the tile sort's partitions start inside the candidate range of some
+  // chunk (kept pairs are a prefix-closed subset of the positions)
+  if (excl < kLbVal)
+    clear_partitions(ws.lookback_t, ws.lbt_words / max(ws.tile_passes, 1), excl,
+                     sat_add(excl, agg), ws.tile_passes, ws.lbt_words / max(ws.tile_passes, 1) / 256);
+  // consecutive 256-entry rows of the chunk, scanned in order (32-bit sums
+  // are exact when the chunk total is below 2^30)
+  uint32_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t sidx = base + i * kBlock + t;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(cnt[i], tmp, &tot);
+    if (exact && sidx < n) {
+      const uint32_t o = excl + carry + ex;
+      ws.pair_off[sidx] = o;
+      // runs whose first candidate falls in [o, o + cnt)
+      for (uint32_t r = (o + kEmitRun - 1) / kEmitRun; (uint64_t)r * kEmitRun < (uint64_t)o + cnt[i] &&
+                                                       r < (uint32_t)ws.nruns; ++r)
+        ws.run_first[r] = (uint32_t)sidx;
+    }
+    carry += tot;
+  }
+  if (c == nch - 1 && t == 0) {
+    const uint32_t total = sat_add(excl, agg);
     const bool over = total > (uint64_t)ws.pcap;
-    ws.hdr->n_candidates = (uint32_t)std::min<uint64_t>(total, 0xffffffffull);
+    ws.hdr->n_candidates = total;
     ws.hdr->pair_overflow = over ? 1u : 0u;
-    ws.hdr->n_cand_listed = over ? 0u : (uint32_t)total;
+    ws.hdr->n_cand_listed = over ? 0u : total;
   }
 }
 
-// Candidate emission balanced over candidates: a block takes a run of 2048
-// consecutive candidate positions, finds the Gaussians covering them by
-// binary search, writes (tile id, slot) to tkey[1] / tval[1], the ellipse
-// test's ballot per 64 positions and the run's kept count.
-__global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws) {
+// Pair emission with the ellipse test and ordered compaction in one pass.
+// Block r takes the run of 2048 consecutive candidate positions from 2048 r
+// (blocks are dispatched in index order, so the runs a block waits on
+// belong to blocks already running); it locates the survivors covering the positions (run_first, then a
+// binary search of their offsets in LDS), tests each candidate tile, ranks
+// the kept ones by ballots, gets the run's output offset by decoupled
+// look-back over the preceding runs and writes (tile id, slot) in order.
+// It also accumulates the digit histograms of the kept tile ids.
+__global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws, int tile_passes) {
   __shared__ uint32_t offs[kEmitRun + 1];
-  __shared__ uint32_t lo_s;
-  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t gpre[kEmitRun / 64];
+  __shared__ uint64_t gmask[kEmitRun / 64];
+  __shared__ uint32_t h[4][256];
+  __shared__ uint32_t s_agg, s_excl;
+  constexpr int kG = kEmitRun / 64;  // 32 ballot groups per run
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t P = ws.hdr->n_cand_listed;
   const uint32_t n = ws.hdr->n_visible;
-  for (uint32_t r = blockIdx.x; (uint64_t)r * kEmitRun < P; r += gridDim.x) {
-    const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
-    if (t == 0) {
-      // last survivor whose offset <= p0
-      uint32_t lo = 0, hi = n;  // invariant: off[lo] <= p0 < off[hi] (off[n] = P)
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (ws.pair_off[mid] <= p0) lo = mid; else hi = mid;
-      }
-      lo_s = lo;
-    }
-    __syncthreads();
-    const uint32_t lo = lo_s;
-    const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
-    for (uint32_t i = t; i < cnt; i += kBlock) offs[i] = ws.pair_off[lo + i];
-    __syncthreads();
-    uint32_t kept = 0;
-#pragma unroll 1
-    for (int k = 0; k < kEmitRun / kBlock; ++k) {
-      const uint32_t p = p0 + k * kBlock + t;
-      bool keep = false;
-      if (p < p1) {
-        uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
-        while (b - a > 1) {
-          const uint32_t mid = (a + b) >> 1;
-          if (offs[mid] <= p) a = mid; else b = mid;
-        }
-        const uint32_t slot = ws.dval[0][lo + a];
-        const uint64_t rc = ws.rect[slot];
-        const uint32_t x0 = rc & 0xffff, y0 = (rc >> 16) & 0xffff, x1 = (rc >> 32) & 0xffff;
-        const uint32_t wdt = x1 - x0;
-        const uint32_t loc = p - offs[a];
-        const uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
-        const float4 pa = ws.proj[3 * (size_t)slot], pc = ws.proj[3 * (size_t)slot + 2];
-        keep = tile_meets_ellipse(pa.x, pa.y, pc.y, pc.z, pc.w, tx, ty);
-        ws.tkey[1][p] = ty * (uint32_t)ws.tiles_x + tx;
-        ws.tval[1][p] = slot;
-      }
-      const uint64_t m = ballot(keep);
-      if (l == 0) ws.cmask[(p0 + k * kBlock + w * kWave) >> 6] = m;
-      kept += (uint32_t)__popcll(m);
-    }
-    if (l == 0) wsum[w] = kept;
-    __syncthreads();
-    if (t == 0) ws.run_cnt[r] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
-  }
-}
-
-// Exclusive prefix of the runs' kept counts, in place (one block); publishes
-// the number of listed pairs.
-__global__ __launch_bounds__(1024) void k_pair_scan(RasterWs ws) {
-  __shared__ uint32_t wtot[16];
-  __shared__ uint32_t carry;
-  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
-  const uint32_t P = ws.hdr->n_cand_listed;
   const uint32_t R = (P + kEmitRun - 1) / kEmitRun;
-  if (t == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t r0 = 0; r0 < R; r0 += 1024) {
-    const uint32_t r = r0 + t;
-    const uint32_t v = r < R ? ws.run_cnt[r] : 0u;
-    const uint32_t inc = wave_incl_scan(v);
-    if (l == 63) wtot[w] = inc;
-    __syncthreads();
-    uint32_t off = carry, tot = 0;
+  if (blockIdx.x >= R) return;
+  for (int i = t; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
+  {
+    const uint32_t r = blockIdx.x;
+    const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
+    const uint32_t lo = ws.run_first[r];
+    const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
+    {
+      // all loads in flight before the first LDS store (clamped, so the
+      // code stays straight-line); a thread past the end rewrites the last
+      // entry with the value it holds
+      constexpr int kU = (kEmitRun + 1 + kBlock - 1) / kBlock;  // 9
+      uint32_t v[kU];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t x = wtot[i];
-      if (i < w) off += x;
-      tot += x;
+      for (int u = 0; u < kU; ++u) v[u] = ws.pair_off[lo + min((uint32_t)(t + u * kBlock), cnt - 1)];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) offs[min((uint32_t)(t + u * kBlock), cnt - 1)] = v[u];
     }
-    if (r < R) ws.run_cnt[r] = off + inc - v;
     __syncthreads();
-    if (t == 0) carry += tot;
+    // three phases over the thread's 8 candidates, so that each phase's
+    // global loads are all in flight together: locate (LDS search, slot),
+    // fetch (rectangle, 2D mean and conic), test
+    constexpr int kC = kEmitRun / kBlock;
+    uint32_t key[kC], val[kC], loc[kC];
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
+      const uint32_t p = min(p0 + k * kBlock + t, p1 - 1);  // clamped; masked below
+      uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
+      while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (offs[mid] <= p) a = mid; else b = mid;
+      }
+      loc[k] = p - offs[a];
+      val[k] = ws.dval[0][lo + a];
+    }
+    uint64_t rc[kC];
+    float4 pa[kC], pc[kC];
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
+      rc[k] = ws.rect[val[k]];
+      pa[k] = ws.proj[3 * (size_t)val[k]];
+      pc[k] = ws.proj[3 * (size_t)val[k] + 2];
+    }
+    uint32_t kept = 0;
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
+      const uint32_t x0 = rc[k] & 0xffff, y0 = (rc[k] >> 16) & 0xffff, x1 = (rc[k] >> 32) & 0xffff;
+      const uint32_t wdt = x1 - x0;
+      const uint32_t ty = y0 + loc[k] / wdt, tx = x0 + loc[k] % wdt;
+      const bool keep = p0 + k * kBlock + t < p1 &&
+                        tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty);
+      key[k] = ty * (uint32_t)ws.tiles_x + tx;
+      const uint64_t m = ballot(keep);
+      if (l == 0) gmask[k * (kBlock / kWave) + w] = m;
+    }
     __syncthreads();
-  }
-  if (t == 0) {
-    ws.hdr->n_listed = carry;
-    ws.hdr->n_pairs = carry;
-  }
-}
-
-// Ordered compaction of the kept candidates into tkey[0] / tval[0].
-__global__ __launch_bounds__(kBlock) void k_pair_compact(RasterWs ws) {
-  __shared__ uint32_t gpre[kEmitRun / 64];
-  __shared__ uint64_t gmask[kEmitRun / 64];
-  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
-  const uint32_t P = ws.hdr->n_cand_listed;
-  constexpr int kG = kEmitRun / 64;  // 32 ballot groups per run
-  for (uint32_t r = blockIdx.x; (uint64_t)r * kEmitRun < P; r += gridDim.x) {
-    const uint32_t p0 = r * kEmitRun;
     if (w == 0) {
-      const uint64_t m = l < kG ? ws.cmask[(size_t)r * kG + l] : 0ull;
+      const uint64_t m = l < kG ? gmask[l] : 0ull;
       const uint32_t c = (uint32_t)__popcll(m);
       const uint32_t inc = wave_incl_scan(c);
-      if (l < kG) {
-        gpre[l] = inc - c;
-        gmask[l] = m;
+      if (l < kG) gpre[l] = inc - c;
+      const uint32_t agg = __shfl(inc, kG - 1, 64);
+      const uint32_t ex = chained_lookback(ws.lb_pair, r, agg, &ws.hdr->sync_error, kSpinLimit);
+      if (l == 0) {
+        s_excl = ex;
+        s_agg = agg;
       }
     }
     __syncthreads();
-    const uint32_t base = ws.run_cnt[r];
-#pragma unroll 1
-    for (int k = 0; k < kEmitRun / kBlock; ++k) {
+    const uint32_t excl = s_excl;
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
       const int g = k * (kBlock / kWave) + w;
       const uint64_t m = gmask[g];
       if ((m >> l) & 1ull) {
-        const uint32_t p = p0 + k * kBlock + t;
-        const uint32_t dst = base + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
-        ws.tkey[0][dst] = ws.tkey[1][p];
-        ws.tval[0][dst] = ws.tval[1][p];
+        const uint32_t dst = excl + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
+        if (dst < P) {  // always true unless a look-back wait hit its bound
+          ws.tkey[0][dst] = key[k];
+          ws.tval[0][dst] = val[k];
+        }
+        for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
+        ++kept;
       }
     }
-    __syncthreads();
+    if (r == R - 1 && t == 0) {
+      ws.hdr->n_listed = sat_add(excl, s_agg);
+      ws.hdr->n_pairs = sat_add(excl, s_agg);
+    }
+  }
+  __syncthreads();
+  for (int d = 0; d < tile_passes; ++d) {
+    const uint32_t v = h[d][t];
+    if (v) atomicAdd(&ws.hist[(4 + d) * 256 + t], v);
   }
 }
 
@@ -651,16 +674,19 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   for (int i = 0; i < 2; ++i) ws.dkey[i] = (uint32_t *)take((size_t)g * 4);
   for (int i = 0; i < 2; ++i) ws.dval[i] = (uint32_t *)take((size_t)g * 4);
   ws.pair_off = (uint32_t *)take((size_t)g * 4);
-  ws.emit_blk = (uint64_t *)take((size_t)ws.nblk_g * 8);
+  ws.lb_emit = (uint32_t *)take((size_t)ws.nblk_g * 4);
+  ws.nruns = (int)((pc + kEmitRun - 1) / kEmitRun);
+  ws.run_first = (uint32_t *)take((size_t)ws.nruns * 4);
+  ws.lb_pair = (uint32_t *)take((size_t)ws.nruns * 4);
   for (int i = 0; i < 2; ++i) ws.tkey[i] = (uint32_t *)take((size_t)pc * 4);
   for (int i = 0; i < 2; ++i) ws.tval[i] = (uint32_t *)take((size_t)pc * 4);
-  ws.nruns = (int)((pc + kEmitRun - 1) / kEmitRun);
-  ws.cmask = (uint64_t *)take((size_t)ws.nruns * (kEmitRun / 64) * 8);
-  ws.run_cnt = (uint32_t *)take((size_t)ws.nruns * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
   ws.hist = (uint32_t *)take(8 * 256 * 4);
-  const int64_t parts = std::max((g + kSortPart - 1) / kSortPart, (pc + kSortPart - 1) / kSortPart);
-  ws.lookback = (uint32_t *)take((size_t)4 * parts * 256 * 4);
+  ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
+  ws.lb_words = (size_t)4 * ((g + kSortPart - 1) / kSortPart) * 256;
+  ws.lbt_words = (size_t)ws.tile_passes * ((pc + kSortPart - 1) / kSortPart) * 256;
+  ws.lookback = (uint32_t *)take(ws.lb_words * 4);
+  ws.lookback_t = (uint32_t *)take(ws.lbt_words * 4);
   ws.dproj = (float *)take((size_t)g * 9 * 4);
   ws.bytes = off;
   return ws;
@@ -691,7 +717,8 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   if (!g || !cam || !p || !rgb || !T_final || !last || !wsp) return OCTGS_EINVAL;
   if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
     return OCTGS_EINVAL;
-  if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30)) return OCTGS_EINVAL;
+  // candidate counts saturate at 2^30 - 1, which must exceed the capacity
+  if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30) - 1) return OCTGS_EINVAL;
   if (cam->width <= 0 || cam->height <= 0 || cam->width > 16 * 65535 || cam->height > 16 * 65535)
     return OCTGS_EINVAL;
   if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return OCTGS_EINVAL;
@@ -703,8 +730,6 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   auto mark = [&](int i) {
     if (stage_events && stage_events[i]) hipEventRecord((hipEvent_t)stage_events[i], s);
   };
-  hipLaunchKernelGGL(k_raster_init, dim3(std::max(8, std::min(1024, (2 * ntiles + 255) / 256))),
-                     dim3(256), 0, s, ws.hdr, ws.ranges, ntiles, ws.hist);
   ProjArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
   for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];
@@ -725,22 +750,20 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   hipLaunchKernelGGL(k_project_compact, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws, g->count);
   mark(1);
   mark(2);
+  // histograms and cleared look-back words come from the kernels above
   hipError_t e = radix_sort(ws.dkey, ws.dval, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
-                            ws.lookback, ws.hdr->part_counter, &ws.hdr->sync_error, s);
+                            ws.lookback, &ws.hdr->sync_error, true, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   mark(3);
   mark(4);
-  hipLaunchKernelGGL(k_emit_count, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
   hipLaunchKernelGGL(k_emit_scan, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
-  const int emit_grid = std::min(std::max(ws.nruns, 1), 4096);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(emit_grid), dim3(kBlock), 0, s, ws);
-  hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, s, ws);
-  hipLaunchKernelGGL(k_pair_compact, dim3(emit_grid), dim3(kBlock), 0, s, ws);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(std::max(ws.nruns, 1)), dim3(kBlock), 0, s, ws,
+                     ws.tile_passes);
   mark(5);
   mark(6);
-  const int passes = tile_sort_passes(ntiles);
+  const int passes = ws.tile_passes;
   e = radix_sort(ws.tkey, ws.tval, &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
-                 ws.lookback, ws.hdr->part_counter + 4, &ws.hdr->sync_error, s);
+                 ws.lookback_t, &ws.hdr->sync_error, true, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 8192);

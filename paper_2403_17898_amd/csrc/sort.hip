@@ -2,9 +2,10 @@
 // Onesweep structure (Adinets and Merrill, "Onesweep: A Faster Least
 // Significant Digit Radix Sort for GPUs", 2022): one kernel builds the
 // digit histograms of all passes, then each pass is a single kernel whose
-// blocks take partitions in the order they start (an atomic ticket), rank
-// keys locally and resolve the global digit offsets with a decoupled
-// look-back over the preceding partitions.
+// block p ranks the keys of partition p locally and resolves the global
+// digit offsets with a decoupled look-back over the preceding partitions.
+// Blocks are dispatched in index order, so a partition only ever waits on
+// partitions of blocks that are already running.
 //
 // CDNA4 specifics: local ranking is done per 64-lane wavefront with eight
 // ballots per item (a match-any on the digit bits); each wave owns a
@@ -59,21 +60,19 @@ struct PassSmem {
   uint32_t keys[kSortPart];
   uint32_t vals[kSortPart];
   uint32_t tmp[8];
-  uint32_t part;
 };
 
 __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const uint32_t *__restrict__ count,
     int shift, const uint32_t *__restrict__ hist, uint32_t *__restrict__ lookback,
-    uint32_t *__restrict__ part_counter, uint32_t *__restrict__ err_flag) {
+    uint32_t *__restrict__ err_flag) {
   __shared__ PassSmem sm;
   const uint32_t n = *count;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint64_t lt = lanemask_lt();
 
-  // blocks past the last partition leave before touching the ticket counter
   if (blockIdx.x >= nparts) return;
 
   // exclusive scan of the pass histogram over digits
@@ -83,13 +82,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     sm.hexcl[t] = ex;
   }
 
-  while (true) {
-    __syncthreads();
-    if (t == 0) sm.part = atomicAdd(part_counter, 1u);
+  {
     for (int i = t; i < 4 * 256; i += kBlock) (&sm.wcnt[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t part = sm.part;
-    if (part >= nparts) break;
+    const uint32_t part = blockIdx.x;
     const uint32_t base = part * kSortPart;
 
     // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
@@ -201,20 +197,22 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 }  // namespace
 
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
-                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *part_counter,
-                      uint32_t *err_flag, hipStream_t stream) {
+                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *err_flag,
+                      bool prepared, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
   const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 256);
   const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
-  hipLaunchKernelGGL(k_sort_hist, dim3(hist_grid), dim3(kBlock), 0, stream, keys[0], count,
-                     passes, hist, lookback, (uint64_t)lb_stride);
-  const int pass_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 2048);
+  if (!prepared)
+    hipLaunchKernelGGL(k_sort_hist, dim3(hist_grid), dim3(kBlock), 0, stream, keys[0], count,
+                       passes, hist, lookback, (uint64_t)lb_stride);
+  // one block per possible partition; blocks past the actual count exit
+  const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1, dst = src ^ 1;
     hipLaunchKernelGGL(k_sort_pass, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                        vals[src], keys[dst], vals[dst], count, 8 * p, hist + 256 * p,
-                       lookback + lb_stride * p, part_counter + p, err_flag);
+                       lookback + lb_stride * p, err_flag);
   }
   return hipGetLastError();
 }
