@@ -126,7 +126,7 @@ struct RasterWs {
   uint32_t *dval[2];      // [gcap] depth-sort values = slot ids
   uint32_t *pair_off;     // [gcap] exclusive prefix of rectangle tiles, depth order
   uint32_t *lb_emit;      // [nblk_g] look-back status of the candidate scan's chunks
-  uint32_t *run_first;    // [nruns] depth-order index of the survivor holding candidate 2048 r
+  uint32_t *run_first;    // [nruns] depth-order index of the survivor holding candidate kEmitRun r
   uint32_t *lb_pair;      // [nruns] look-back status of the emission's runs
   uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
   uint32_t *tval[2];      // [pcap] slot ids
@@ -143,7 +143,8 @@ struct RasterWs {
 
 constexpr int kCompThreads = 128;  // forward composite: threads per 16x16 tile (2 pixels each)
 constexpr int kCompBatch = 256;    // list entries staged in LDS per batch
-constexpr int kEmitRun = 2048;  // candidate pairs per block iteration of the emission
+constexpr int kEmitThreads = 1024;  // pair emission: threads per block
+constexpr int kEmitRun = 8192;      // candidate pairs per block of the emission
 
 RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);
 int tile_sort_passes(int ntiles);

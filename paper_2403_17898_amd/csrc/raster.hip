@@ -308,8 +308,9 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
 }
 
 // Candidate scan over the depth-ordered survivors (one chunk of 1024 per
-// block, offsets chained by decoupled look-back): pair_off[s] = rectangle tiles of the survivors before s, and
-// run_first[r] = the survivor that holds candidate 2048 r.  The chunk
+// block, offsets chained by decoupled look-back): pair_off[s] = rectangle
+// tiles of the survivors before s, and run_first[r] = the survivor that
+// holds candidate kEmitRun r.  The chunk
 // holding the last survivor publishes the total and the overflow flag.
 // Values saturate at 2^30 - 1, above any admissible pair capacity, so they
 // are exact whenever the candidates fit.
@@ -379,118 +380,121 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
 }
 
 // Pair emission with the ellipse test and ordered compaction in one pass.
-// Block r takes the run of 2048 consecutive candidate positions from 2048 r
+// Block r (1024 threads) takes the run of 8192 consecutive candidate
+// positions from 8192 r; runs this long keep the look-back chain short, as
+// each step of it is a device-scope round trip
 // (blocks are dispatched in index order, so the runs a block waits on
 // belong to blocks already running); it locates the survivors covering the positions (run_first, then a
 // binary search of their offsets in LDS), tests each candidate tile, ranks
 // the kept ones by ballots, gets the run's output offset by decoupled
 // look-back over the preceding runs and writes (tile id, slot) in order.
 // It also accumulates the digit histograms of the kept tile ids.
-__global__ __launch_bounds__(kBlock) void k_emit_pairs(RasterWs ws, int tile_passes) {
+__global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int tile_passes) {
+  constexpr int kW = kEmitThreads / kWave;  // 16 waves
+  constexpr int kG = kEmitRun / 64;         // 128 ballot groups per run
+  constexpr int kC = kEmitRun / kEmitThreads;  // 8 candidates per thread
   __shared__ uint32_t offs[kEmitRun + 1];
-  __shared__ uint32_t gpre[kEmitRun / 64];
-  __shared__ uint64_t gmask[kEmitRun / 64];
+  __shared__ uint32_t gpre[kG];
+  __shared__ uint64_t gmask[kG];
   __shared__ uint32_t h[4][256];
   __shared__ uint32_t s_agg, s_excl;
-  constexpr int kG = kEmitRun / 64;  // 32 ballot groups per run
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t P = ws.hdr->n_cand_listed;
   const uint32_t n = ws.hdr->n_visible;
   const uint32_t R = (P + kEmitRun - 1) / kEmitRun;
   if (blockIdx.x >= R) return;
-  for (int i = t; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
+  (&h[0][0])[t] = 0u;  // 1024 threads, 4 x 256 bins
+  const uint32_t r = blockIdx.x;
+  const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
+  const uint32_t lo = ws.run_first[r];
+  const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
   {
-    const uint32_t r = blockIdx.x;
-    const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
-    const uint32_t lo = ws.run_first[r];
-    const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
-    {
-      // all loads in flight before the first LDS store (clamped, so the
-      // code stays straight-line); a thread past the end rewrites the last
-      // entry with the value it holds
-      constexpr int kU = (kEmitRun + 1 + kBlock - 1) / kBlock;  // 9
-      uint32_t v[kU];
+    // all loads in flight before the first LDS store (clamped, so the code
+    // stays straight-line); a thread past the end rewrites the last entry
+    // with the value it holds
+    constexpr int kU = (kEmitRun + 1 + kEmitThreads - 1) / kEmitThreads;  // 9
+    uint32_t v[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) v[u] = ws.pair_off[lo + min((uint32_t)(t + u * kBlock), cnt - 1)];
+    for (int u = 0; u < kU; ++u) v[u] = ws.pair_off[lo + min((uint32_t)(t + u * kEmitThreads), cnt - 1)];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) offs[min((uint32_t)(t + u * kBlock), cnt - 1)] = v[u];
-    }
-    __syncthreads();
-    // three phases over the thread's 8 candidates, so that each phase's
-    // global loads are all in flight together: locate (LDS search, slot),
-    // fetch (rectangle, 2D mean and conic), test
-    constexpr int kC = kEmitRun / kBlock;
-    uint32_t key[kC], val[kC], loc[kC];
+    for (int u = 0; u < kU; ++u) offs[min((uint32_t)(t + u * kEmitThreads), cnt - 1)] = v[u];
+  }
+  __syncthreads();
+  // three phases over the thread's 8 candidates, so that each phase's
+  // global loads are all in flight together: locate (LDS search, slot),
+  // fetch (rectangle, 2D mean and conic), test
+  uint32_t key[kC], val[kC], loc[kC];
 #pragma unroll
-    for (int k = 0; k < kC; ++k) {
-      const uint32_t p = min(p0 + k * kBlock + t, p1 - 1);  // clamped; masked below
-      uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
-      while (b - a > 1) {
-        const uint32_t mid = (a + b) >> 1;
-        if (offs[mid] <= p) a = mid; else b = mid;
-      }
-      loc[k] = p - offs[a];
-      val[k] = ws.dval[0][lo + a];
+  for (int k = 0; k < kC; ++k) {
+    const uint32_t p = min(p0 + k * kEmitThreads + t, p1 - 1);  // clamped; masked below
+    uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
+    while (b - a > 1) {
+      const uint32_t mid = (a + b) >> 1;
+      if (offs[mid] <= p) a = mid; else b = mid;
     }
-    uint64_t rc[kC];
-    float4 pa[kC], pc[kC];
+    loc[k] = p - offs[a];
+    val[k] = ws.dval[0][lo + a];
+  }
+  uint64_t rc[kC];
+  float4 pa[kC], pc[kC];
 #pragma unroll
-    for (int k = 0; k < kC; ++k) {
-      rc[k] = ws.rect[val[k]];
-      pa[k] = ws.proj[3 * (size_t)val[k]];
-      pc[k] = ws.proj[3 * (size_t)val[k] + 2];
-    }
-    uint32_t kept = 0;
+  for (int k = 0; k < kC; ++k) {
+    rc[k] = ws.rect[val[k]];
+    pa[k] = ws.proj[3 * (size_t)val[k]];
+    pc[k] = ws.proj[3 * (size_t)val[k] + 2];
+  }
 #pragma unroll
-    for (int k = 0; k < kC; ++k) {
-      const uint32_t x0 = rc[k] & 0xffff, y0 = (rc[k] >> 16) & 0xffff, x1 = (rc[k] >> 32) & 0xffff;
-      const uint32_t wdt = x1 - x0;
-      const uint32_t ty = y0 + loc[k] / wdt, tx = x0 + loc[k] % wdt;
-      const bool keep = p0 + k * kBlock + t < p1 &&
-                        tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty);
-      key[k] = ty * (uint32_t)ws.tiles_x + tx;
-      const uint64_t m = ballot(keep);
-      if (l == 0) gmask[k * (kBlock / kWave) + w] = m;
-    }
-    __syncthreads();
-    if (w == 0) {
-      const uint64_t m = l < kG ? gmask[l] : 0ull;
-      const uint32_t c = (uint32_t)__popcll(m);
-      const uint32_t inc = wave_incl_scan(c);
-      if (l < kG) gpre[l] = inc - c;
-      const uint32_t agg = __shfl(inc, kG - 1, 64);
-      const uint32_t ex = chained_lookback(ws.lb_pair, r, agg, &ws.hdr->sync_error, kSpinLimit);
-      if (l == 0) {
-        s_excl = ex;
-        s_agg = agg;
-      }
-    }
-    __syncthreads();
-    const uint32_t excl = s_excl;
-#pragma unroll
-    for (int k = 0; k < kC; ++k) {
-      const int g = k * (kBlock / kWave) + w;
-      const uint64_t m = gmask[g];
-      if ((m >> l) & 1ull) {
-        const uint32_t dst = excl + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
-        if (dst < P) {  // always true unless a look-back wait hit its bound
-          ws.tkey[0][dst] = key[k];
-          ws.tval[0][dst] = val[k];
-        }
-        for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
-        ++kept;
-      }
-    }
-    if (r == R - 1 && t == 0) {
-      ws.hdr->n_listed = sat_add(excl, s_agg);
-      ws.hdr->n_pairs = sat_add(excl, s_agg);
+  for (int k = 0; k < kC; ++k) {
+    const uint32_t x0 = rc[k] & 0xffff, y0 = (rc[k] >> 16) & 0xffff, x1 = (rc[k] >> 32) & 0xffff;
+    const uint32_t wdt = x1 - x0;
+    const uint32_t ty = y0 + loc[k] / wdt, tx = x0 + loc[k] % wdt;
+    const bool keep = p0 + k * kEmitThreads + t < p1 &&
+                      tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty);
+    key[k] = ty * (uint32_t)ws.tiles_x + tx;
+    const uint64_t m = ballot(keep);
+    if (l == 0) gmask[k * kW + w] = m;
+  }
+  __syncthreads();
+  if (w == 0) {
+    // exclusive prefix over the 128 groups, two per lane
+    const uint32_t c0 = (uint32_t)__popcll(gmask[l]), c1 = (uint32_t)__popcll(gmask[64 + l]);
+    const uint32_t i0 = wave_incl_scan(c0);
+    const uint32_t t0 = __shfl(i0, 63, 64);
+    const uint32_t i1 = wave_incl_scan(c1);
+    gpre[l] = i0 - c0;
+    gpre[64 + l] = t0 + i1 - c1;
+    const uint32_t agg = t0 + __shfl(i1, 63, 64);
+    const uint32_t ex = chained_lookback(ws.lb_pair, r, agg, &ws.hdr->sync_error, kSpinLimit);
+    if (l == 0) {
+      s_excl = ex;
+      s_agg = agg;
     }
   }
   __syncthreads();
-  for (int d = 0; d < tile_passes; ++d) {
-    const uint32_t v = h[d][t];
-    if (v) atomicAdd(&ws.hist[(4 + d) * 256 + t], v);
+  const uint32_t excl = s_excl;
+#pragma unroll
+  for (int k = 0; k < kC; ++k) {
+    const int g = k * kW + w;
+    const uint64_t m = gmask[g];
+    if ((m >> l) & 1ull) {
+      const uint32_t dst = excl + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
+      if (dst < P) {  // always true unless a look-back wait hit its bound
+        ws.tkey[0][dst] = key[k];
+        ws.tval[0][dst] = val[k];
+      }
+      for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
+    }
   }
+  if (r == R - 1 && t == 0) {
+    ws.hdr->n_listed = sat_add(excl, s_agg);
+    ws.hdr->n_pairs = sat_add(excl, s_agg);
+  }
+  __syncthreads();
+  if (t < 256)
+    for (int d = 0; d < tile_passes; ++d) {
+      const uint32_t v = h[d][t];
+      if (v) atomicAdd(&ws.hist[(4 + d) * 256 + t], v);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
@@ -757,7 +761,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(3);
   mark(4);
   hipLaunchKernelGGL(k_emit_scan, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(std::max(ws.nruns, 1)), dim3(kBlock), 0, s, ws,
+  hipLaunchKernelGGL(k_emit_pairs, dim3(std::max(ws.nruns, 1)), dim3(kEmitThreads), 0, s, ws,
                      ws.tile_passes);
   mark(5);
   mark(6);

@@ -91,13 +91,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
     int dig[kSortItems];
+    // unconditional loads at a clamped index keep all of them in flight
+    // together; items past the end are masked by dig = -1
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-      uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
-      bool ok = idx < n;
-      key[j] = ok ? kin[idx] : 0u;
-      val[j] = ok ? vin[idx] : 0u;
-      dig[j] = ok ? (int)((key[j] >> shift) & 255u) : -1;
+      const uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
+      key[j] = kin[min(idx, n - 1)];
+      val[j] = vin[min(idx, n - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
+      dig[j] = idx < n ? (int)((key[j] >> shift) & 255u) : -1;
     }
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
@@ -134,36 +139,42 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     sm.wcnt[2][t] = ds + c0 + c1;
     sm.wcnt[3][t] = ds + c0 + c1 + c2;
 
-    // decoupled look-back for digit t, reading a window of kLookWin
-    // predecessors per round trip (nearest first)
+    // decoupled look-back for digit t: read a window of kLookWin
+    // predecessors (nearest first) in one round trip; if every entry up to
+    // the nearest inclusive one has been published, add them and stop at
+    // the inclusive one (or move one window back), else read the window
+    // again.  A partition outside the window never stalls the scan.
     uint32_t excl = 0;
     if (part > 0) {
       int64_t p = (int64_t)part - 1;
-      bool done = false;
-      while (!done && p >= 0) {
+      uint32_t spins = 0;
+      while (p >= 0) {
         const int cnt = (int)min<int64_t>(kLookWin, p + 1);
         uint32_t v[kLookWin];
 #pragma unroll
         for (int i = 0; i < kLookWin; ++i)
-          v[i] = i < cnt ? ld_acq(lookback + (size_t)(p - i) * 256u + t) : 0u;
+          v[i] = ld_acq(lookback + (size_t)(p - min(i, cnt - 1)) * 256u + t);
+        bool ready = true, found = false;
+        uint32_t sum = 0;
 #pragma unroll
         for (int i = 0; i < kLookWin; ++i) {
-          if (done || i >= cnt) continue;
-          uint32_t s = v[i];
-          uint32_t spins = 0;
-          while ((s & ~kValMask) == 0u && spins < kSpinLimit) {
-            __builtin_amdgcn_s_sleep(1);
-            s = ld_acq(lookback + (size_t)(p - i) * 256u + t);
-            ++spins;
+          if (i < cnt && !found) {
+            const uint32_t f = v[i] & ~kValMask;
+            ready = ready && f != 0u;
+            sum += v[i] & kValMask;
+            found = f == kFlagInc;
           }
-          if ((s & ~kValMask) == 0u) {
-            atomicOr(err_flag, 1u);
-            done = true;
-            continue;
-          }
-          excl += s & kValMask;
-          if ((s & ~kValMask) == kFlagInc) done = true;
         }
+        if (!ready) {
+          if (++spins > kSpinLimit) {
+            atomicOr(err_flag, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += sum;
+        if (found) break;
         p -= cnt;
       }
       st_rel(&lb[t], kFlagInc | ((excl + tot) & kValMask));
