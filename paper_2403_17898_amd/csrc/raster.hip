@@ -394,6 +394,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   constexpr int kG = kEmitRun / 64;         // 128 ballot groups per run
   constexpr int kC = kEmitRun / kEmitThreads;  // 8 candidates per thread
   __shared__ uint32_t offs[kEmitRun + 1];
+  __shared__ uint16_t owner[kEmitRun];
+  __shared__ uint32_t wmax[kW];
   __shared__ uint32_t gpre[kG];
   __shared__ uint64_t gmask[kG];
   __shared__ uint32_t h[4][256];
@@ -419,20 +421,50 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
 #pragma unroll
     for (int u = 0; u < kU; ++u) offs[min((uint32_t)(t + u * kEmitThreads), cnt - 1)] = v[u];
   }
+  // owner[i]: local index of the survivor holding position p0 + i.  Each
+  // survivor that starts inside the run marks its first position (offsets
+  // strictly increase), then a prefix maximum fills the gaps.
+#pragma unroll
+  for (int u = 0; u < kC; ++u) owner[t + u * kEmitThreads] = 0;
+  __syncthreads();
+  for (uint32_t a = 1 + t; a < cnt; a += kEmitThreads) {
+    const uint32_t st = offs[a];
+    if (st < p0 + kEmitRun) owner[st - p0] = (uint16_t)a;
+  }
+  __syncthreads();
+  {
+    uint32_t v[kC], m = 0;  // thread t holds positions [8 t, 8 t + 8)
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      m = max(m, (uint32_t)owner[t * kC + u]);
+      v[u] = m;
+    }
+    uint32_t inc = m;  // inclusive max-scan over the wave, then over waves
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (l >= o) inc = max(inc, y);
+    }
+    if (l == 63) wmax[w] = inc;
+    __syncthreads();
+    uint32_t before = __shfl_up(inc, 1, 64);
+    if (l == 0) before = 0;
+#pragma unroll
+    for (int i = 0; i < kW; ++i)
+      if (i < w) before = max(before, wmax[i]);
+#pragma unroll
+    for (int u = 0; u < kC; ++u) owner[t * kC + u] = (uint16_t)max(before, v[u]);
+  }
   __syncthreads();
   // three phases over the thread's 8 candidates, so that each phase's
-  // global loads are all in flight together: locate (LDS search, slot),
-  // fetch (rectangle, 2D mean and conic), test
+  // global loads are all in flight together: locate (slot), fetch
+  // (rectangle, 2D mean and conic), test
   uint32_t key[kC], val[kC], loc[kC];
 #pragma unroll
   for (int k = 0; k < kC; ++k) {
-    const uint32_t p = min(p0 + k * kEmitThreads + t, p1 - 1);  // clamped; masked below
-    uint32_t a = 0, b = cnt;  // offs[a] <= p < offs[b] (offs[cnt] treated as +inf)
-    while (b - a > 1) {
-      const uint32_t mid = (a + b) >> 1;
-      if (offs[mid] <= p) a = mid; else b = mid;
-    }
-    loc[k] = p - offs[a];
+    const uint32_t i = min((uint32_t)(k * kEmitThreads + t), p1 - 1 - p0);  // clamped; masked below
+    const uint32_t a = owner[i];
+    loc[k] = p0 + i - offs[a];
     val[k] = ws.dval[0][lo + a];
   }
   uint64_t rc[kC];
@@ -447,7 +479,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   for (int k = 0; k < kC; ++k) {
     const uint32_t x0 = rc[k] & 0xffff, y0 = (rc[k] >> 16) & 0xffff, x1 = (rc[k] >> 32) & 0xffff;
     const uint32_t wdt = x1 - x0;
-    const uint32_t ty = y0 + loc[k] / wdt, tx = x0 + loc[k] % wdt;
+    // row and column of the candidate in its rectangle: a float quotient,
+    // exact after one correction step while loc < 2^24
+    uint32_t row;
+    if (loc[k] < (1u << 24)) {
+      row = (uint32_t)((float)loc[k] * __builtin_amdgcn_rcpf((float)wdt));
+      const int32_t rem = (int32_t)(loc[k] - row * wdt);
+      row = rem < 0 ? row - 1 : (rem >= (int32_t)wdt ? row + 1 : row);
+    } else {
+      row = loc[k] / wdt;
+    }
+    const uint32_t ty = y0 + row, tx = x0 + (loc[k] - row * wdt);
     const bool keep = p0 + k * kEmitThreads + t < p1 &&
                       tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty);
     key[k] = ty * (uint32_t)ws.tiles_x + tx;
