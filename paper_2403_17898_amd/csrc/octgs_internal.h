@@ -81,6 +81,22 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
   return off + inc - v;
 }
 
+// Sum of a[0..b) by the 256 threads of a block, returned per thread
+// (partial sums; the caller reduces).  Loads are unconditional at a clamped
+// index, four per thread per step, so they are in flight together.
+__device__ __forceinline__ uint32_t partial_sum_prefix(const uint32_t *a, int b) {
+  uint32_t s = 0;
+  const int t = threadIdx.x;
+  for (int i0 = 0; i0 < b; i0 += 4 * kBlock) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[min(i0 + u * kBlock + t, b - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += i0 + u * kBlock + t < b ? v[u] : 0u;
+  }
+  return s;
+}
+
 // Relaxed device-scope (all XCDs) atomics for look-back status words.
 __device__ __forceinline__ uint32_t ld_acq(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -219,14 +219,22 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
   }
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   if (base >= n) return;
+  // every field of the thread's four slots is loaded up front (clamped
+  // index, so the loads are unconditional and all in flight together)
+  float gg[kChunkPerThread][kGaussFields];
+#pragma unroll
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t s = min(base + i * kBlock + t, (int64_t)n - 1);
+#pragma unroll
+    for (int f = 0; f < kGaussFields; ++f) gg[i][f] = a.g[f * a.gstride + s];
+  }
   uint32_t cnt = 0;
+#pragma unroll
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t s = base + i * kBlock + t;
     bool vis = false;
     if (s < n) {
-      float g[kGaussFields];
-#pragma unroll
-      for (int f = 0; f < kGaussFields; ++f) g[f] = a.g[f * a.gstride + s];
+      const float *g = gg[i];
       ProjOut o;
       vis = project_decide(a.cam, a.dil, a.jc, a.tiles_x, a.tiles_y, g, o);
       if (vis) {
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
   }
   if (base >= n) return;
   uint32_t s = 0;
-  for (int i = t; i < b; i += kBlock) s += ws.blk_cnt[i];
+  s = partial_sum_prefix(ws.blk_cnt, b);
   s = wave_sum(s);
   if (l == 0) red[w] = s;
   const int ngroups = (int)min<int64_t>(kGroups, ((int64_t)n - base + 63) / 64);
@@ -282,12 +290,20 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
   for (int i = t; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
   __syncthreads();
   const uint32_t prefix = red[0] + red[1] + red[2] + red[3];
-  for (int gi = w; gi < ngroups; gi += 4) {
-    const uint64_t m = gmask[gi];
+  // wave w owns groups w, w + 4, w + 8, w + 12; their depth keys are loaded
+  // up front (clamped index), so the loads are in flight together
+  uint32_t keys[kGroups / 4];
+#pragma unroll
+  for (int q = 0; q < kGroups / 4; ++q)
+    keys[q] = ws.depth[min(base + 64 * (w + 4 * q) + l, (int64_t)n - 1)];
+#pragma unroll
+  for (int q = 0; q < kGroups / 4; ++q) {
+    const int gi = w + 4 * q;
+    const uint64_t m = gi < ngroups ? gmask[gi] : 0ull;
     if ((m >> l) & 1ull) {
       const uint32_t pos = prefix + gpre[gi] + (uint32_t)__popcll(m & lanemask_lt());
       const uint32_t slot = (uint32_t)(base + 64 * gi + l);
-      const uint32_t key = ws.depth[slot];
+      const uint32_t key = keys[q];
       ws.dkey[0][pos] = key;
       ws.dval[0][pos] = slot;
 #pragma unroll
@@ -326,12 +342,18 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
   // chunk a block waits on belongs to a block that is already running
   const uint32_t c = blockIdx.x;
   const int64_t base = (int64_t)c * kChunk;
-  uint32_t cnt[kChunkPerThread];
+  uint32_t cnt[kChunkPerThread], slot[kChunkPerThread];
   uint64_t mine = 0;
+  // two batches of unconditional loads at clamped indices: slots, then
+  // their rectangles
+#pragma unroll
+  for (int i = 0; i < kChunkPerThread; ++i)
+    slot[i] = ws.dval[0][min(base + i * kBlock + t, (int64_t)n - 1)];
 #pragma unroll
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t sidx = base + i * kBlock + t;
-    cnt[i] = sidx < n ? min(rect_tiles(ws.rect[ws.dval[0][sidx]]), kLbVal) : 0u;
+    const uint32_t c = min(rect_tiles(ws.rect[slot[i]]), kLbVal);
+    cnt[i] = sidx < n ? c : 0u;
     mine += cnt[i];
   }
 #pragma unroll

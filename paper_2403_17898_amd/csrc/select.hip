@@ -95,14 +95,19 @@ __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera 
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   uint32_t cnt = 0;
-#pragma unroll 4
+  // the four anchors' inputs are loaded up front (clamped index, n >= 1),
+  // so all the loads are in flight together
+  float in[kChunkPerThread][5];
+#pragma unroll
+  for (int i = 0; i < kChunkPerThread; ++i) {
+    const int64_t j = min(base + i * kBlock + t, n - 1);
+    in[i][0] = pos[3 * j]; in[i][1] = pos[3 * j + 1]; in[i][2] = pos[3 * j + 2];
+    in[i][3] = thr2[j]; in[i][4] = rho[j];
+  }
+#pragma unroll
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t j = base + i * kBlock + t;
-    bool sel = false;
-    if (j < n) {
-      const float px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-      sel = anchor_selected(cam, f, px, py, pz, thr2[j], rho[j]);
-    }
+    const bool sel = j < n && anchor_selected(cam, f, in[i][0], in[i][1], in[i][2], in[i][3], in[i][4]);
     const uint64_t m = ballot(sel);
     if (l == 0 && base + i * kBlock + w * kWave < n) masks[(base + i * kBlock + w * kWave) >> 6] = m;
     cnt += (uint32_t)__popcll(m);
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const int b = blockIdx.x;
   uint32_t s = 0;
-  for (int i = t; i < b; i += kBlock) s += blk_cnt[i];
+  s = partial_sum_prefix(blk_cnt, b);
   s = wave_sum(s);
   if (l == 0) red[w] = s;
   const int64_t base = (int64_t)b * kChunk;

@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_flag_scatter(const uint32_t *count, 
   }
   if (base >= n) return;
   uint32_t s = 0;
-  for (int i = t; i < b; i += kBlock) s += blk[i];
+  s = partial_sum_prefix(blk, b);
   s = wave_sum(s);
   if (l == 0) red[w] = s;
   const int ng = (int)min<int64_t>(kGroups, (n - base + 63) / 64);
