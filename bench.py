@@ -10,8 +10,12 @@ binning, depth ordering and compositing (Eq. 2).  Steps cycle through the
 trajectory; the scene and cameras are resident before timing starts.
 
 Prints one JSON line.  value = frames per second of the fast path (BF16
-decode on MFMA); the plain FP32 path is timed the same way on the same views
-and reported beside it, with the per-view PSNR of the fast path against it.
+decode on MFMA, plus the learned anchor skip unless it falls back to full
+decode); the plain FP32 path is timed the same way on the same views and
+reported beside it, with the per-view PSNR of the fast path against it.
+Views are independent, so --inflight views (default 3) are rendered at once
+on separate streams with separate buffers; the rate with one view in flight
+is reported beside it.
 """
 
 from __future__ import annotations
@@ -37,6 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200, help="views timed per path")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--views", type=int, default=200, help="trajectory length")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="views in flight at once (one stream and buffer set each)")
     ap.add_argument("--cpu-views", type=int, default=60, help="views the CPU oracle renders")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the PSNR sweep (profiling runs)")
@@ -108,44 +114,63 @@ def main():
     torch.cuda.empty_cache()
     gcap = max(1, int(max_sel * sc.k * 1.05) + 1024)
     pcap = max(1, int(max_pairs * 1.10) + 4096)
-    vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=pcap, gauss_capacity=gcap)
-    log(f"sizing: max selected {max_sel}, max candidate pairs {max_pairs}; gcap {gcap}, pcap {pcap}")
+    # frames in flight: view i runs on stream i % D with its own buffers;
+    # views are independent, so their latency-bound stages (scans, sorts)
+    # overlap with other views' compositing
+    D = max(1, args.inflight)
+    vbs = [P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=pcap, gauss_capacity=gcap)
+           for _ in range(D)]
+    vb = vbs[0]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(D - 1)]
+    stream = streams[0]
+    log(f"sizing: max selected {max_sel}, max candidate pairs {max_pairs}; gcap {gcap}, "
+        f"pcap {pcap}; {D} frames in flight")
 
-    stream = torch.cuda.current_stream()
-
-    def run(prec, n, start=0, events=None):
-        for i in range(n):
-            c = ccams[(start + i) % len(ccams)]
-            vb.render(ds, c, prm, precision=prec, stage_events=events)
-
-    def timed(prec):
-        run(prec, args.warmup)
+    def timed_views(render_one, depth):
+        """ms for args.steps views (after args.warmup), view i on stream i % depth."""
+        def run(n):
+            for i in range(n):
+                k = i % depth
+                render_one(k, ccams[i % len(ccams)], streams[k])
+        run(args.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t_wall = time.perf_counter()
         e0.record(stream)
-        run(prec, args.steps)
+        for s in streams[1:depth]:
+            s.wait_event(e0)
+        run(args.steps)
+        for s in streams[1:depth]:
+            ev = torch.cuda.Event()
+            ev.record(s)
+            stream.wait_event(ev)
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_wall
-        ms = e0.elapsed_time(e1)
-        return ms, wall
+        for b in vbs[:depth]:
+            st = b.stats()
+            if st["pair_overflow"] or st["sync_error"]:
+                raise SystemExit(f"timed run flagged: {st}")
+        return e0.elapsed_time(e1), wall
+
+    def timed(prec, depth=D):
+        return timed_views(lambda k, c, s: vbs[k].render(ds, c, prm, precision=prec, stream=s), depth)
 
     ms32, wall32 = timed(P.OCTGS_FP32)
     ms16, wall16 = timed(P.OCTGS_BF16)
-    st = vb.stats()
-    if st["pair_overflow"] or st["sync_error"]:
-        raise SystemExit(f"timed run flagged: {st}")
+    ms32_1, _ = timed(P.OCTGS_FP32, 1)
+    ms16_1, _ = timed(P.OCTGS_BF16, 1)
     fps32 = args.steps / (ms32 / 1e3)
     fps16 = args.steps / (ms16 / 1e3)
+    single = {"fp32": round(args.steps / (ms32_1 / 1e3), 2), "bf16": round(args.steps / (ms16_1 / 1e3), 2)}
     log(f"plain FP32: {ms32 / args.steps:.3f} ms/view ({fps32:.1f} FPS); "
-        f"BF16: {ms16 / args.steps:.3f} ms/view ({fps16:.1f} FPS)")
+        f"BF16: {ms16 / args.steps:.3f} ms/view ({fps16:.1f} FPS); one frame in flight: {single}")
 
     # ---- learned anchor skip: trained on logged blend weights of random views ----
     skip = None
     if not args.no_skip:
         skip = skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None)
-        ms_sk, _ = timed_skip(args, P, vb, ds, ccams, prm, skip, torch)
+        ms_sk, _ = timed_skip(P, vbs, ds, prm, skip, timed_views, D)
         skip["fps"] = round(args.steps / (ms_sk / 1e3), 2)
         skip["ms_per_view"] = round(ms_sk / args.steps, 4)
         log(f"BF16 + learned skip: {ms_sk / args.steps:.3f} ms/view ({skip['fps']:.1f} FPS)")
@@ -258,6 +283,8 @@ def main():
                    "mean_candidates": round(mean["candidates"])},
         "fps_plain_fp32": round(fps32, 2),
         "fps_bf16_no_skip": round(fps16, 2),
+        "frames_in_flight": D,
+        "fps_one_frame_in_flight": single,
         "ms_per_step_plain_fp32": round(ms32 / args.steps, 4),
         "speedup_vs_plain": round(value / fps32, 4),
         "psnr_vs_plain_min_db": (skip["psnr_min_db"] if skip else
@@ -337,29 +364,21 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
     return res
 
 
-def timed_skip(args, P, vb, ds, ccams, prm, skip, torch):
+def timed_skip(P, vbs, ds, prm, skip, timed_views, depth):
+    """The BF16 + learned-skip path (or its full-decode fallback), timed
+    like the other paths with the same frames in flight."""
     from paper_2403_17898_amd import skip as SK
-    net, sb, thr = skip.pop("_net"), skip.pop("_sb"), skip.pop("_thr")
-
+    net, _, thr = skip.pop("_net"), skip.pop("_sb"), skip.pop("_thr")
     fallback = skip["fallback_to_full_decode"]
+    sbs = [SK.SkipBuffers(v) for v in vbs[:depth]]
 
-    def run(n):
-        for i in range(n):
-            c = ccams[i % len(ccams)]
-            if fallback:
-                vb.render(ds, c, prm, precision=P.OCTGS_BF16)
-            else:
-                SK.render_skip(vb, sb, ds, c, prm, net, thr, precision=P.OCTGS_BF16)
+    def one(k, c, s):
+        if fallback:
+            vbs[k].render(ds, c, prm, precision=P.OCTGS_BF16, stream=s)
+        else:
+            SK.render_skip(vbs[k], sbs[k], ds, c, prm, net, thr, precision=P.OCTGS_BF16, stream=s)
 
-    run(args.warmup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t = time.perf_counter()
-    e0.record()
-    run(args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1), time.perf_counter() - t
+    return timed_views(one, depth)
 
 
 def train_step_timing(args, P, S, torch, np):
