@@ -33,6 +33,29 @@ if ROOT not in sys.path:
 
 METRIC = "FPS @1080p + train-step ms, BF16+learned-skip vs plain FP32 at >=45 dB PSNR"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+FLOP_PER_BLEND = 21.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "composite_street1080p_hbm_bytes.txt")
+COMPOSITE_SOURCE = os.path.join(ROOT, "paper_2403_17898_amd", "csrc", "raster.hip")
+
+
+def composite_traffic():
+    """HBM bytes per composite launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, or None when that summary is missing or was
+    taken from a different version of the kernel source."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+        digest = hashlib.sha256(open(COMPOSITE_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if ":" in line)
+    if fields.get("source_sha256", "").strip() != digest:
+        return None
+    try:
+        return int(float(fields["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -180,7 +203,7 @@ def main():
     names = ["select", "decode"] + list(L.RASTER_STAGE_NAMES)
     tot = {k: 0.0 for k in names}
     nviews = min(args.steps, len(ccams))
-    sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0)
+    sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0, blends=0)
     ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
     sh = P.stream_handle(stream)
     for i in range(nviews):
@@ -198,6 +221,7 @@ def main():
         for s_i, nm in enumerate(L.RASTER_STAGE_NAMES):
             tot[nm] += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
         s = vb.stats()
+        sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
         sums["selected"] += s["n_selected"]
         sums["slots"] += s["n_slots"]
         sums["visible"] += s["n_visible"]
@@ -210,21 +234,26 @@ def main():
         f"visible {mean['visible']:.0f}, pairs {mean['pairs']:.0f} "
         f"(of {mean['candidates']:.0f} rectangle candidates)")
 
-    # algorithmic bytes per launch of each stage (see the design notes)
+    # The dominant kernel, compositing, is bound by vector ALU work: per
+    # pixel and Gaussian blended (Eq. 2) it evaluates the 2D Gaussian,
+    # alpha, the colour update and T, 21 FLOP counting exp as one.  Units per
+    # launch = sum over pixels of the entries each consumed (the `last`
+    # output).  Its algorithmic HBM bytes per launch are reported beside.
     npix = W * H
     ntiles = ((W + 15) // 16) * ((H + 15) // 16)
-    alg = {
-        "select": 20.0 * sc.n + 4.0 * mean["selected"],
-        "decode": (64 + 12 + 12 * sc.k + 24 + 4) * mean["selected"] + 56.0 * mean["slots"],
-        "project": 56.0 * mean["slots"] + 48.0 * mean["visible"] + 8.0 * mean["visible"],
-        "composite": 40.0 * mean["pairs"] + 20.0 * npix + 8.0 * ntiles,
-    }
-    dom = max(avg, key=lambda k: avg[k])
-    roof_kernel = dom if dom in alg else "composite"
-    ach = alg[roof_kernel] / (avg[roof_kernel] * 1e-3) / 1e9
-    roofline = {"kernel": roof_kernel, "bound": "hbm", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "stage_ms": {k: round(v, 4) for k, v in avg.items()}}
+    flop = FLOP_PER_BLEND * mean["blends"]
+    ach = flop / (avg["composite"] * 1e-3) / 1e12
+    # unique bytes: list entries 4 B per pair, the projected record 36 B per
+    # visible Gaussian, tile ranges 8 B, and 20 B written per pixel
+    alg_bytes = 4.0 * mean["pairs"] + 36.0 * mean["visible"] + 8.0 * ntiles + 20.0 * npix
+    roofline = {"kernel": "composite", "bound": "alu", "achieved": round(ach, 2),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": composite_traffic(),
+                "algorithmic_bytes": round(alg_bytes),
+                "hbm_gbs": round(alg_bytes / (avg["composite"] * 1e-3) / 1e9, 1),
+                "blends_per_launch": round(mean["blends"]),
+                "stage_ms": {k: round(v, 4) for k, v in avg.items()}}
 
     # ---- quality: BF16 path vs plain FP32, every view ----
     psnrs = []
