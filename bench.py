@@ -119,18 +119,21 @@ def main():
         f"generated in {time.time() - t0:.1f}s")
     ds = P.DeviceScene.from_scene(sc)
     ccams = [P.make_camera(c) for c in cams]
+    bcams = [P.make_camera(c, lod_blend=True) for c in cams]  # LOD transition blending
     prm = P.raster_params()
     W, H = cams[0].width, cams[0].height
 
     # ---- sizing pass (untimed): per-view selected anchors and pairs ----
     vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=48 << 20)
     per_view = []
-    for c in ccams:
+    for c in ccams + bcams:
         vb.render(ds, c, prm, precision=P.OCTGS_FP32)
         st = vb.stats()
         if st["pair_overflow"] or st["sync_error"]:
             raise SystemExit(f"sizing pass failed: {st}")
         per_view.append(st)
+    blend_sel = float(np.mean([s["n_selected"] for s in per_view[len(ccams):]]))
+    blend_pairs = float(np.mean([s["n_pairs"] for s in per_view[len(ccams):]]))
     max_sel = max(s["n_selected"] for s in per_view)
     max_pairs = max(s["n_candidates"] for s in per_view)
     del vb
@@ -149,12 +152,14 @@ def main():
     log(f"sizing: max selected {max_sel}, max candidate pairs {max_pairs}; gcap {gcap}, "
         f"pcap {pcap}; {D} frames in flight")
 
-    def timed_views(render_one, depth):
+    def timed_views(render_one, depth, views=None):
         """ms for args.steps views (after args.warmup), view i on stream i % depth."""
+        views = ccams if views is None else views
+
         def run(n):
             for i in range(n):
                 k = i % depth
-                render_one(k, ccams[i % len(ccams)], streams[k])
+                render_one(k, views[i % len(views)], streams[k])
         run(args.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -176,8 +181,9 @@ def main():
                 raise SystemExit(f"timed run flagged: {st}")
         return e0.elapsed_time(e1), wall
 
-    def timed(prec, depth=D):
-        return timed_views(lambda k, c, s: vbs[k].render(ds, c, prm, precision=prec, stream=s), depth)
+    def timed(prec, depth=D, views=None):
+        return timed_views(lambda k, c, s: vbs[k].render(ds, c, prm, precision=prec, stream=s),
+                           depth, views)
 
     ms32, wall32 = timed(P.OCTGS_FP32)
     ms16, wall16 = timed(P.OCTGS_BF16)
@@ -188,6 +194,10 @@ def main():
     single = {"fp32": round(args.steps / (ms32_1 / 1e3), 2), "bf16": round(args.steps / (ms16_1 / 1e3), 2)}
     log(f"plain FP32: {ms32 / args.steps:.3f} ms/view ({fps32:.1f} FPS); "
         f"BF16: {ms16 / args.steps:.3f} ms/view ({fps16:.1f} FPS); one frame in flight: {single}")
+    msb, _ = timed(P.OCTGS_BF16, views=bcams)
+    blend = {"fps_bf16": round(args.steps / (msb / 1e3), 2), "ms_per_view": round(msb / args.steps, 4),
+             "mean_selected": round(blend_sel), "mean_pairs": round(blend_pairs)}
+    log(f"LOD transition blending, BF16: {blend}")
 
     # ---- learned anchor skip: trained on logged blend weights of random views ----
     skip = None
@@ -313,6 +323,7 @@ def main():
         "fps_plain_fp32": round(fps32, 2),
         "fps_bf16_no_skip": round(fps16, 2),
         "frames_in_flight": D,
+        "lod_blend": blend,
         "fps_one_frame_in_flight": single,
         "ms_per_step_plain_fp32": round(ms32 / args.steps, 4),
         "speedup_vs_plain": round(value / fps32, 4),

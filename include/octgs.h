@@ -60,7 +60,12 @@ typedef enum {
 
 /* Pinhole camera.  Camera-space point = R (p - C); x right, y down, z forward.
  * Pixel (i, j) is sampled at (i + 0.5, j + 0.5).  lod_scale2 is s^2, the
- * squared focal scale factor s of Eq. 7 (Sec. IV-A, "Anchor Selection"). */
+ * squared focal scale factor s of Eq. 7 (Sec. IV-A, "Anchor Selection").
+ * lod_blend = 1 renders with LOD transition blending (Sec. IV-A, the last
+ * paragraph of "Anchor Selection"): selection also takes anchors of level
+ * L_hat + 1, and decode scales every opacity by min(1, max(0, L* - L + 1))
+ * with L* the clamped fractional level, i.e. by L* - L_hat for those
+ * anchors and by 1 for the others.  0 = the cumulative rule alone. */
 typedef struct {
   float R[9];  /* row-major world->camera rotation */
   float C[3];  /* camera centre, world */
@@ -68,6 +73,7 @@ typedef struct {
   int32_t width, height;
   float z_near;
   float lod_scale2;
+  int32_t lod_blend;
 } octgs_camera;
 
 /* Anchor set (Sec. IV-A): anchors of all octree levels in one flat array.
@@ -157,7 +163,10 @@ OCTGS_API size_t octgs_select_workspace_bytes(int64_t n);
 
 /* Anchor selection (Eq. 7 and the cumulative rule L_v <= L_hat, Sec. IV-A):
  * anchor j is selected iff its bound sphere intersects the view frustum
- * (near plane and the four side planes) and |x_v - C|^2 s^2 <= thr2[j].
+ * (near plane and the four side planes) and |x_v - C|^2 s^2 <= thr2[j]; with
+ * cam->lod_blend the threshold is that of level L_v - 1, 4 thr2[j] (exact in
+ * FP32): level L_hat + 1 is taken too, except level-1 anchors farther than
+ * where L* reaches 0 (their opacity factor would be 0).
  * Every decision is taken in FP32 by a fixed operation order.  Outputs:
  * sel_idx (device, capacity n) receives the selected indices in ascending
  * order; *sel_count (device) their number.  ws: device, >= the size above. */
@@ -168,7 +177,9 @@ OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, 
  * min(*count, out->capacity / k) anchors listed in idx (device).  Network
  * input x = [feature, |x_v - C| / d_max, (x_v - C) / |x_v - C|]; outputs
  * opacity = tanh, rgb = sigmoid, scale = base_scale * sigmoid, quaternion
- * normalised (identity when its norm is 0), mean = x_v + O_i * l_v.  A
+ * normalised (identity when its norm is 0), mean = x_v + O_i * l_v; with
+ * cam->lod_blend the opacity is scaled by the transition factor above
+ * (needs a->level and a->lod_bias; FP32, log2 of the distance ratio).  A
  * Gaussian with opacity <= 0 is written and later culled by the rasterizer.
  * precision selects the FP32 or the BF16 (needs a->feat_bf16) MFMA path.
  * Writes out->data and *out->count (device). */

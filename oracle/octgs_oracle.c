@@ -146,7 +146,7 @@ ORC_API void orc_bound_radius(int64_t n, int k, const float *offsets,
  * d^2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) for d = p - C.  Writes a 0/1
  * mask and returns the selected count. pos is [n][3]. */
 ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
-                                const float *rho, const float *camf, int W, int H,
+                                const float *rho, int blend, const float *camf, int W, int H,
                                 uint8_t *mask) {
   cam_t k = load_cam(camf, W, H);
   int64_t cnt = 0;
@@ -154,7 +154,11 @@ ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
     float px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
     float d0 = px - k.C[0], d1 = py - k.C[1], d2 = pz - k.C[2];
     float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-    int sel = (dd * k.s2 <= thr2[j]);
+    /* LOD transition blending also takes level L_hat + 1, i.e. L <= L* + 1:
+     * the threshold of level L - 1, 4 thr2 (exact in FP32).  An anchor of
+     * level 1 whose unclamped L* is negative gets factor 0 and is left out */
+    const float th = blend ? 4.0f * thr2[j] : thr2[j];
+    int sel = (dd * k.s2 <= th);
     if (sel) {
       float xc, yc, zc;
       cam_xform_f(&k, px, py, pz, &xc, &yc, &zc);
@@ -171,7 +175,7 @@ ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
  * visibility evaluated in double.  Used only to pin the threshold form. */
 ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level,
                                const float *lod_bias, float d_max, int n_levels,
-                               const float *rho, const float *camf, int W, int H,
+                               const float *rho, int blend, const float *camf, int W, int H,
                                uint8_t *mask) {
   cam_t k = load_cam(camf, W, H);
   double s = sqrt((double)k.s2);
@@ -185,7 +189,10 @@ ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level
     double lstar = log2((double)d_max / (dist * s)) + (double)lod_bias[j];
     if (lstar < 0) lstar = 0;
     if (lstar > n_levels - 1) lstar = n_levels - 1;
-    int sel = ((double)level[j] <= floor(lstar));
+    /* cumulative rule L <= L_hat; with transition blending also L = L_hat + 1
+     * when its opacity factor L* - L_hat is not 0 */
+    int sel = ((double)level[j] <= floor(lstar)) ||
+              (blend && (double)level[j] == floor(lstar) + 1.0 && lstar > floor(lstar));
     if (sel) {
       double xc = k.R[0] * d[0] + k.R[1] * d[1] + k.R[2] * d[2];
       double yc = k.R[3] * d[0] + k.R[4] * d[1] + k.R[5] * d[2];
@@ -372,11 +379,30 @@ static void decode_input(const float *feat, int F, const float *p, const float *
  *   scale   = base_scale * sigmoid(F_cov(x)_{7i..7i+2})
  *   quat    = F_cov(x)_{7i+3..7i+6} / |.| (identity when the norm is 0)
  * mlp: w1a,b1a,w2a,b2a, w1c,b1c,w2c,b2c, w1s,b1s,w2s,b2s. */
+/* Opacity factor of LOD transition blending (Sec. IV-A): the fractional
+ * level L* = clamp(log2(d_max / (d s)) + Delta L, 0, K - 1) gives anchors of
+ * level L_hat + 1 the factor L* - L_hat; min(1, max(0, L* - L + 1)) is that
+ * for them and 1 for every anchor of level <= L_hat. */
+static double lod_blend_factor(double dist, double s, float d_max, float bias, int level,
+                               int n_levels) {
+  double lstar = log2((double)d_max / (dist * s)) + (double)bias;
+  if (lstar < 0) lstar = 0;
+  if (lstar > n_levels - 1) lstar = n_levels - 1;
+  double f = lstar - (double)level + 1.0;
+  return f < 0 ? 0 : (f > 1 ? 1 : f);
+}
+
+ORC_API double orc_lod_blend_factor(double dist, double s, float d_max, float bias, int level,
+                                    int n_levels) {
+  return lod_blend_factor(dist, s, d_max, bias, level, n_levels);
+}
+
 ORC_API void orc_decode(int64_t m, const int64_t *idx, const float *pos, const float *feat,
                         const float *offsets, const float *offset_scale,
                         const float *base_scale, int k, int F, int Wd,
                         const float *const *mlp, const float *Cw, float d_max,
-                        double *out) {
+                        int blend, const uint8_t *level, const float *lod_bias, int n_levels,
+                        float s2, double *out) {
   int64_t G = m * k;
   int in = F + 4;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -399,7 +425,14 @@ ORC_API void orc_decode(int64_t m, const int64_t *idx, const float *pos, const f
       qn = sqrt(qn);
       for (int a = 0; a < 4; ++a)
         out[(6 + a) * G + g] = qn > 0 ? q[a] / qn : (a == 0 ? 1.0 : 0.0);
-      out[10 * G + g] = tanh(ya[i]);
+      double op = tanh(ya[i]);
+      if (blend) {
+        double dv[3];
+        for (int a = 0; a < 3; ++a) dv[a] = (double)pos[3 * j + a] - (double)Cw[a];
+        double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        op *= lod_blend_factor(dist, sqrt((double)s2), d_max, lod_bias[j], level[j], n_levels);
+      }
+      out[10 * G + g] = op;
       for (int a = 0; a < 3; ++a) out[(11 + a) * G + g] = sigm(yc[3 * i + a]);
     }
   }

@@ -58,12 +58,16 @@ _i32 = ctypes.c_int
 def _declare(L):
     L.orc_lod_thr2.argtypes = [_i64, _p, _p, ctypes.c_float, _p]
     L.orc_bound_radius.argtypes = [_i64, _i32, _p, _p, _p, _p]
-    L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p]
+    L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _i32, _p, _i32, _i32, _p]
     L.orc_select_fp32.restype = _i64
-    L.orc_select_eq7.argtypes = [_i64, _p, _p, _p, ctypes.c_float, _i32, _p, _p, _i32, _i32, _p]
+    L.orc_select_eq7.argtypes = [_i64, _p, _p, _p, ctypes.c_float, _i32, _p, _i32, _p, _i32, _i32,
+                                 _p]
     L.orc_select_eq7.restype = _i64
     L.orc_decode.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
-                             ctypes.c_float, _p]
+                             ctypes.c_float, _i32, _p, _p, _i32, ctypes.c_float, _p]
+    L.orc_lod_blend_factor.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_float,
+                                       ctypes.c_float, _i32, _i32]
+    L.orc_lod_blend_factor.restype = ctypes.c_double
     L.orc_project.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p, _p]
     L.orc_project.restype = _i64
     L.orc_count_pairs.argtypes = [_i64, _p, _p, _p]
@@ -131,23 +135,30 @@ def bound_radius(offsets, offset_scale, base_scale) -> np.ndarray:
     return out
 
 
-def select_mask(pos, thr2, rho, cam) -> np.ndarray:
+def select_mask(pos, thr2, rho, cam, blend=False) -> np.ndarray:
+    """Canonical FP32 selection mask; blend also takes level L_hat + 1
+    (LOD transition blending)."""
     pos = _c(pos, np.float32)
     mask = np.empty(len(pos), np.uint8)
     lib().orc_select_fp32(len(pos), _ptr(pos), _ptr(_c(thr2, np.float32)),
-                          _ptr(_c(rho, np.float32)), _ptr(cam_array(cam)), cam.width,
-                          cam.height, _ptr(mask))
+                          _ptr(_c(rho, np.float32)), int(blend), _ptr(cam_array(cam)),
+                          cam.width, cam.height, _ptr(mask))
     return mask
 
 
-def select_eq7_mask(pos, level, lod_bias, d_max, n_levels, rho, cam) -> np.ndarray:
+def select_eq7_mask(pos, level, lod_bias, d_max, n_levels, rho, cam, blend=False) -> np.ndarray:
     pos = _c(pos, np.float32)
     mask = np.empty(len(pos), np.uint8)
     lib().orc_select_eq7(len(pos), _ptr(pos), _ptr(_c(level, np.uint8)),
                          _ptr(_c(lod_bias, np.float32)), float(d_max), int(n_levels),
-                         _ptr(_c(rho, np.float32)), _ptr(cam_array(cam)), cam.width,
+                         _ptr(_c(rho, np.float32)), int(blend), _ptr(cam_array(cam)), cam.width,
                          cam.height, _ptr(mask))
     return mask
+
+
+def lod_blend_factor(dist, s, d_max, bias, level, n_levels) -> float:
+    return float(lib().orc_lod_blend_factor(float(dist), float(s), float(d_max), float(bias),
+                                            int(level), int(n_levels)))
 
 
 def scene_thresholds(scene):
@@ -156,11 +167,11 @@ def scene_thresholds(scene):
             bound_radius(scene.offsets, scene.offset_scale, scene.base_scale))
 
 
-def select(scene, cam, thr2=None, rho=None) -> np.ndarray:
+def select(scene, cam, thr2=None, rho=None, blend=False) -> np.ndarray:
     """Ascending indices of the anchors selected for cam (canonical FP32 rule)."""
     if thr2 is None or rho is None:
         thr2, rho = scene_thresholds(scene)
-    return np.flatnonzero(select_mask(scene.pos, thr2, rho, cam)).astype(np.int64)
+    return np.flatnonzero(select_mask(scene.pos, thr2, rho, cam, blend)).astype(np.int64)
 
 
 # ----------------------------------------------------------------------------
@@ -171,18 +182,22 @@ MLP_ORDER = ("w1_a", "b1_a", "w2_a", "b2_a", "w1_c", "b1_c", "w2_c", "b2_c",
              "w1_s", "b1_s", "w2_s", "b2_s")
 
 
-def decode(scene, idx, cam) -> np.ndarray:
-    """Double-precision decode of anchors idx: planar [14][len(idx) * k]."""
+def decode(scene, idx, cam, blend=False) -> np.ndarray:
+    """Double-precision decode of anchors idx: planar [14][len(idx) * k].
+    blend scales opacities by the LOD transition factor."""
     idx = _c(idx, np.int64)
     m, k = len(idx), scene.k
     keep = [_c(scene.mlp[name], np.float32) for name in MLP_ORDER]
     arr = (ctypes.c_void_p * 12)(*[a.ctypes.data for a in keep])
     out = np.empty((14, m * k), np.float64)
+    lv, lb = _c(scene.level, np.uint8), _c(scene.lod_bias, np.float32)
     lib().orc_decode(m, _ptr(idx), _ptr(_c(scene.pos, np.float32)),
                      _ptr(_c(scene.feat, np.float32)), _ptr(_c(scene.offsets, np.float32)),
                      _ptr(_c(scene.offset_scale, np.float32)),
                      _ptr(_c(scene.base_scale, np.float32)), k, scene.feat_dim,
-                     scene.width, arr, _ptr(cam.C), float(scene.d_max), _ptr(out))
+                     scene.width, arr, _ptr(_c(cam.C, np.float32)), float(scene.d_max), int(blend),
+                     _ptr(lv), _ptr(lb), int(scene.n_levels), float(cam.lod_scale) ** 2,
+                     _ptr(out))
     return out
 
 
@@ -260,10 +275,11 @@ def rasterize(gf, cam, prm, gd=None, weights=False):
     return out
 
 
-def render(scene, cam, prm, thr2=None, rho=None, weights=False):
-    """Full path for one view: select, decode, rasterize."""
-    idx = select(scene, cam, thr2, rho)
-    gd = decode(scene, idx, cam)
+def render(scene, cam, prm, thr2=None, rho=None, weights=False, blend=False):
+    """Full path for one view: select, decode, rasterize (blend: LOD
+    transition blending)."""
+    idx = select(scene, cam, thr2, rho, blend)
+    gd = decode(scene, idx, cam, blend)
     out = rasterize(gd.astype(np.float32), cam, prm, gd=gd, weights=weights)
     out.update(idx=idx, gauss=gd)
     return out

@@ -27,7 +27,8 @@ _i64 = ctypes.c_int64
 
 class Camera(ctypes.Structure):
     _fields_ = [("R", _f * 9), ("C", _f * 3), ("fx", _f), ("fy", _f), ("cx", _f), ("cy", _f),
-                ("width", _i32), ("height", _i32), ("z_near", _f), ("lod_scale2", _f)]
+                ("width", _i32), ("height", _i32), ("z_near", _f), ("lod_scale2", _f),
+                ("lod_blend", _i32)]
 
 
 class Anchors(ctypes.Structure):

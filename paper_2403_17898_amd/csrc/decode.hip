@@ -50,6 +50,11 @@ struct DecodeArgs {
   int k, W, cap_anchors;
   float inv_dmax;
   float C[3];
+  // LOD transition blending: opacity factor min(1, max(0, L* - L + 1))
+  int blend, n_levels;
+  float d_max, s;
+  const uint8_t *level;
+  const float *lod_bias;
   const float *pos, *feat, *offsets, *oscale, *bscale;
   const uint16_t *feat_bf16;
   const float *w1[3], *b1[3], *w2[3], *b2[3];
@@ -74,6 +79,7 @@ struct alignas(16) Smem {
   T H[kTM][kHS];
   float Y[kTM][kYS];
   uint32_t aidx[kTM];
+  float ofac[kTM];  // opacity factor per anchor (1 without blending)
 };
 
 // Weight staging into LDS in the path's precision T (float, or BF16 bits),
@@ -259,6 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
           const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
           const float dist = sqrtf(__builtin_fmaf(d0, d0, __builtin_fmaf(d1, d1, d2 * d2)));
           const float inv = 1.0f / dist;
+          float of = 1.0f;
+          if (a.blend) {
+            // fractional level L* = clamp(log2(d_max / (d s)) + Delta L, 0, K - 1)
+            const float ls = fminf(fmaxf(log2f(a.d_max / (dist * a.s)) + a.lod_bias[j], 0.0f),
+                                   (float)(a.n_levels - 1));
+            of = fminf(fmaxf(ls - (float)a.level[j] + 1.0f, 0.0f), 1.0f);
+          }
+          sm.ofac[r] = of;
           float e[kInPad - 32];
           e[0] = dist * a.inv_dmax;
           e[1] = d0 * inv; e[2] = d1 * inv; e[3] = d2 * inv;
@@ -363,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
       }
       a.out[6 * cap + s] = nw; a.out[7 * cap + s] = nx;
       a.out[8 * cap + s] = ny; a.out[9 * cap + s] = nz;
-      a.out[10 * cap + s] = tanhf(sm.Y[r][i]);
+      a.out[10 * cap + s] = tanhf(sm.Y[r][i]) * sm.ofac[r];
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.out[(11 + c) * cap + s] = sigmoidf(sm.Y[r][off_c + 3 * i + c]);
     }
@@ -413,6 +427,16 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   for (int h = 0; h < 3; ++h) {
     a.w1[h] = mlp->w1[h]; a.b1[h] = mlp->b1[h]; a.w2[h] = mlp->w2[h]; a.b2[h] = mlp->b2[h];
   }
+  a.blend = cam->lod_blend ? 1 : 0;
+  if (a.blend) {
+    if (!an->level || !an->lod_bias || an->n_levels < 1 || !(cam->lod_scale2 > 0.0f))
+      return OCTGS_EINVAL;
+  }
+  a.n_levels = an->n_levels;
+  a.d_max = an->d_max;
+  a.s = sqrtf(cam->lod_scale2);
+  a.level = an->level;
+  a.lod_bias = an->lod_bias;
   a.idx = idx; a.count = count; a.out = out->data; a.cap = out->capacity;
   a.out_count = out->count;
   const int64_t tiles = std::max<int64_t>(1, (a.cap_anchors + kTM - 1) / kTM);

@@ -178,6 +178,8 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
                      int64_t gauss_capacity, const octgs_anchor_grads *ga,
                      const octgs_mlp_grads *gm, void *ws, size_t ws_bytes, octgs_stream stream) {
   if (!an || !mlp || !cam || !idx || !count || !d_gauss || !ga || !gm || !ws) return OCTGS_EINVAL;
+  // transition blending is an inference-time mode; training uses Eq. 7 alone
+  if (cam->lod_blend) return OCTGS_EUNSUPPORTED;
   if (an->feat_dim != 32) return OCTGS_EUNSUPPORTED;
   if (an->k < 1 || an->k > kMaxK) return OCTGS_EUNSUPPORTED;
   if (mlp->width < 16 || mlp->width > 64 || mlp->width % 16) return OCTGS_EUNSUPPORTED;

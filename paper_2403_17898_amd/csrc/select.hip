@@ -104,6 +104,12 @@ __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera 
     in[i][0] = pos[3 * j]; in[i][1] = pos[3 * j + 1]; in[i][2] = pos[3 * j + 2];
     in[i][3] = thr2[j]; in[i][4] = rho[j];
   }
+  if (cam.lod_blend) {
+    // transition blending also takes level L_hat + 1 (L <= L* + 1): the
+    // threshold of level L - 1, which is 4 thr2 (exact)
+#pragma unroll
+    for (int i = 0; i < kChunkPerThread; ++i) in[i][3] = 4.0f * in[i][3];
+  }
 #pragma unroll
   for (int i = 0; i < kChunkPerThread; ++i) {
     const int64_t j = base + i * kBlock + t;

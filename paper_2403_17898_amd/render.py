@@ -44,9 +44,10 @@ def _events(events):
     return arr
 
 
-def make_camera(cam) -> L.Camera:
+def make_camera(cam, lod_blend: bool = False) -> L.Camera:
     """octgs_camera from any object with R (3x3), C (3), fx, fy, cx, cy,
-    width, height, z_near and lod_scale (s of Eq. 7)."""
+    width, height, z_near and lod_scale (s of Eq. 7); lod_blend turns on LOD
+    transition blending."""
     c = L.Camera()
     R = np.asarray(cam.R, np.float32).reshape(9)
     C = np.asarray(cam.C, np.float32).reshape(3)
@@ -59,6 +60,7 @@ def make_camera(cam) -> L.Camera:
     c.z_near = float(cam.z_near)
     s = float(np.float32(getattr(cam, "lod_scale", 1.0)))
     c.lod_scale2 = float(np.float32(s) * np.float32(s))
+    c.lod_blend = 1 if lod_blend else 0
     return c
 
 

@@ -285,3 +285,94 @@ def test_invalid_arguments_rejected(P):
     g = L.Gaussians()
     assert lib.octgs_rasterize_fwd(ctypes.byref(g), None, None, 0, None, None, None, None, None, 0,
                                    None, None) == L.OCTGS_EINVAL
+
+
+# --------------------------------------------------------------------------
+# LOD transition blending (Sec. IV-A)
+# --------------------------------------------------------------------------
+
+def _blend_scene(c1):
+    """Config 1 with a random LOD bias, so transition anchors span levels."""
+    rng = np.random.default_rng(21)
+    sc = S.make_config1()
+    sc.lod_bias = rng.uniform(-0.6, 0.6, sc.n).astype(np.float32)
+    return sc
+
+
+def test_select_blend_bit_exact(P, orc, c1):
+    sc = _blend_scene(c1)
+    ds = P.DeviceScene.from_scene(sc)
+    thr, rho = orc.scene_thresholds(sc)
+    for i, cam in enumerate(_cams_c1()):
+        say("select blend camera", i)
+        vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
+        vb.select(ds, P.make_camera(cam, lod_blend=True))
+        torch.cuda.synchronize()
+        m = int(vb.sel_count.item())
+        got = _np(vb.sel_idx[:m]).astype(np.int64)
+        ref = orc.select(sc, cam, thr, rho, blend=True)
+        assert np.array_equal(got, ref), (i, m, len(ref))
+        assert len(ref) >= len(orc.select(sc, cam, thr, rho))
+
+
+def test_decode_blend_factor(P, orc, c1):
+    """Blended decode equals the plain decode except the opacity, which is
+    scaled by the transition factor (FP32 log2 of the distance ratio: a few
+    ulp of L* on top of the opacity's own bound)."""
+    sc = _blend_scene(c1)
+    cam = S.look_at(9.0 * np.array([1.0, -2.0, 1.5]) / np.linalg.norm([1.0, -2.0, 1.5]),
+                    (0, 0, 0), 128, 128, 60.0)
+    thr, rho = orc.scene_thresholds(sc)
+    idx = orc.select(sc, cam, thr, rho, blend=True)
+    say("decode blend", len(idx))
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    vb.decode(ds, P.make_camera(cam, lod_blend=True), P.OCTGS_FP32, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    G = len(idx) * sc.k
+    got = _np(vb.gauss[:, :G]).astype(np.float64)
+    ref = orc.decode(sc, idx, cam, blend=True)
+    plain = orc.decode(sc, idx, cam)
+    bound = decoded_field_bounds(sc, idx, cam, plain, False)
+    err = np.abs(got - ref)
+    for f in range(14):
+        if f != 10:
+            assert np.all(err[f] <= bound[f]), f
+    fac = np.divide(ref[10], plain[10], out=np.ones_like(ref[10]), where=plain[10] != 0)
+    assert np.all(err[10] <= bound[10] * np.abs(fac) + 8e-6 * np.abs(plain[10]) + 1e-7)
+    # some anchors are in transition (0 < factor < 1) and none above L_hat + 1
+    assert np.any((fac > 0.01) & (fac < 0.99)) and np.all((fac >= 0) & (fac <= 1 + 1e-12))
+
+
+def test_end_to_end_blend_c1(P, orc, c1):
+    sc = _blend_scene(c1)
+    ds = P.DeviceScene.from_scene(sc)
+    prm = P.raster_params()
+    thr, rho = orc.scene_thresholds(sc)
+    for i, cam in enumerate(_cams_c1()[:4]):
+        say("end-to-end blend c1", i)
+        vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 18)
+        vb.render(ds, P.make_camera(cam, lod_blend=True), prm, precision=P.OCTGS_FP32)
+        torch.cuda.synchronize()
+        ref = orc.render(sc, cam, orc.params_array(), thr, rho, blend=True)
+        m = int(vb.sel_count.item())
+        assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
+        img = _np(vb.rgb).astype(np.float64)
+        err = np.abs(img - ref["img"])
+        p = psnr(img, ref["img"])
+        say(f"  max abs {err.max():.2e} PSNR {p:.1f} dB")
+        assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+
+
+def test_decode_bwd_rejects_blend(P, c1):
+    sc = c1
+    ds = P.DeviceScene.from_scene(sc)
+    cam = S.config1_camera()
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
+    vb.render(ds, P.make_camera(cam), P.raster_params())
+    vb.rasterize_bwd(P.make_camera(cam), P.raster_params(), torch.ones_like(vb.rgb))
+    grads = P.SceneGrads(ds)
+    with pytest.raises(P.OctgsError):
+        vb.decode_bwd(ds, P.make_camera(cam, lod_blend=True), grads)

@@ -372,6 +372,83 @@ def test_threshold_form_matches_literal_eq7(orc):
     assert np.count_nonzero(a0 != b0) <= 3
 
 
+# --------------------------------------------------------------------------
+# LOD transition blending (Sec. IV-A): level L_hat + 1 with opacity scaled by
+# the fractional level
+# --------------------------------------------------------------------------
+
+def test_blend_selection_matches_literal_rule(orc):
+    """The FP32 threshold rule with blending (4 thr2) equals the literal
+    rule (L <= L_hat, or L = L_hat + 1 with a nonzero factor L* - L_hat)
+    except within rounding distance of a threshold; the added anchors are
+    exactly level L_hat + 1."""
+    rng = np.random.default_rng(12)
+    K, d_max = 6, 150.0
+    pos, level, bias, rho = _random_anchor_set(rng, 200_000, K)
+    cam = S.look_at((5.0, -7.0, 3.0), (0.0, 0.0, 0.0), 256, 256, 60.0)
+    thr = orc.lod_thr2(level, bias, d_max)
+    a = orc.select_mask(pos, thr, rho, cam, blend=True)
+    b = orc.select_eq7_mask(pos, level, bias, d_max, K, rho, cam, blend=True)
+    d = np.linalg.norm(pos.astype(np.float64) - cam.C.astype(np.float64), axis=1)
+    lim = float(F32(d_max)) * 2.0 ** (bias.astype(np.float64) - level + 1)
+    diff = np.flatnonzero(a != b)
+    for j in diff:
+        assert level[j] > 0 and abs(d[j] / lim[j] - 1) < 1e-5
+    assert len(diff) <= 3
+    plain = orc.select_mask(pos, thr, rho, cam)
+    assert np.all(a[plain == 1] == 1)
+    lstar = np.clip(np.log2(float(F32(d_max)) / d) + bias, 0, K - 1)
+    extra = np.flatnonzero((a == 1) & (plain == 0))
+    near = np.abs(lstar - np.round(lstar)) < 1e-5
+    ok = (level[extra] == np.floor(lstar[extra]) + 1) | near[extra]
+    assert ok.all() and len(extra) > 1000
+
+
+def test_blend_factor_closed_form(orc):
+    """Factor 1 at and below L_hat, L* - L_hat at L_hat + 1, 0 above; L* is
+    clamped to [0, K - 1]."""
+    f = orc.lod_blend_factor
+    d_max, K = 100.0, 4
+    # d = 100 / 2^1.25 -> L* = 1.25, L_hat = 1
+    d = 100.0 / 2 ** 1.25
+    assert f(d, 1.0, d_max, 0.0, 0, K) == 1.0
+    assert f(d, 1.0, d_max, 0.0, 1, K) == 1.0
+    assert abs(f(d, 1.0, d_max, 0.0, 2, K) - 0.25) < 1e-12
+    assert f(d, 1.0, d_max, 0.0, 3, K) == 0.0
+    # bias shifts L*; s scales the distance
+    assert abs(f(d, 1.0, d_max, 0.5, 2, K) - 0.75) < 1e-12
+    assert abs(f(d / 2 ** 0.5, 2 ** 0.5, d_max, 0.0, 2, K) - 0.25) < 1e-12
+    # clamps: far away L* = 0 (level 1 gets 0), very close L* = K - 1
+    assert f(1e6, 1.0, d_max, 0.0, 1, K) == 0.0 and f(1e6, 1.0, d_max, 0.0, 0, K) == 1.0
+    assert f(1e-3, 1.0, d_max, 0.0, K - 1, K) == 1.0
+
+
+def test_blend_removes_lod_popping(orc):
+    """Moving the focal scale s across the value where a level-1 anchor's
+    L* crosses 1: without blending the image jumps (the anchor appears),
+    with blending it changes by O(eps)."""
+    sc = S.make_config1()
+    cam = S.config1_camera()
+    thr, rho = orc.scene_thresholds(sc)
+    d = np.linalg.norm(sc.pos.astype(np.float64) - cam.C.astype(np.float64), axis=1)
+    vis = orc.select_mask(sc.pos, np.full_like(thr, np.inf), rho, cam).astype(bool)
+    cand = np.flatnonzero(vis & (sc.level == 1) & (sc.lod_bias == 0))
+    j = cand[np.argmin(np.abs(d[cand] - np.median(d[cand])))]
+    s_star = float(F32(sc.d_max)) / (2.0 * d[j])   # log2(d_max / (d_j s*)) = 1
+    prm = orc.params_array()
+    eps = 1e-5
+
+    def img(scale, blend):
+        c = S.Camera(R=cam.R, C=cam.C, fx=cam.fx, fy=cam.fy, cx=cam.cx, cy=cam.cy,
+                     width=cam.width, height=cam.height, z_near=cam.z_near, lod_scale=scale)
+        return orc.render(sc, c, prm, blend=blend)["img"]
+
+    jump = np.abs(img(s_star * (1 + eps), False) - img(s_star * (1 - eps), False)).max()
+    cont = np.abs(img(s_star * (1 + eps), True) - img(s_star * (1 - eps), True)).max()
+    assert jump > 1e-3
+    assert cont < 10 * eps
+
+
 def test_level_monotone_in_distance(orc):
     """Along a ray from the camera, the anchors of each level that pass Eq. 7
     form a prefix (near ones pass, far ones do not)."""
