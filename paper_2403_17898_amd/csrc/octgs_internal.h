@@ -81,6 +81,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
   return off + inc - v;
 }
 
+// Sum of v over the 256 threads of a block, returned to thread 0 (LDS
+// scratch of 4 floats).
+__device__ __forceinline__ float block_sum_f(float v, float *red) {
+  v = wave_sum_f(v);
+  if (__lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
 // Sum of a[0..b) by the 256 threads of a block, returned per thread
 // (partial sums; the caller reduces).  Loads are unconditional at a clamped
 // index, four per thread per step, so they are in flight together.

@@ -3,13 +3,13 @@
 // (the training step of Octree-GS renders and back-propagates through the
 // Eq. 2 blending and the EWA projection of Sec. III-A).
 //
-// composite backward: one block per 16x16 tile, one pixel per thread.  Each
-// pixel starts from its final transmittance and walks its tile list in
-// reverse from the last entry the forward consumed, recovering
+// composite backward: one block of 128 threads per 16x16 tile, two pixels
+// per thread.  Each pixel starts from its final transmittance and walks its
+// tile list in reverse from the last entry the forward consumed, recovering
 // T_i = T_{i+1} / (1 - a_i) instead of storing per-pixel lists; the colour
 // behind each entry is accumulated on the way.  Per-Gaussian gradients are
-// summed over the wave with cross-lane shuffles, over the block in LDS, and
-// added to global memory once per (tile, Gaussian).
+// summed over the thread's pixels, over the wave by a halving exchange, over
+// the block in LDS, and added to global memory once per (tile, Gaussian).
 //
 // projection backward: one thread per Gaussian slot, recomputing the forward
 // quantities (rotation, 3D covariance, Jacobian, 2D covariance) in FP32.
@@ -36,117 +36,176 @@ struct BwdArgs {
   const uint32_t *last;
 };
 
+// Sum of 8 values over the 64 lanes of a wave, by halving exchanges: after
+// the xor-32, xor-16 and xor-8 steps each lane holds one partial sum of value
+// 4 b5 + 2 b4 + b3 (b = lane bits), and xor-4, -2, -1 finish it.  Lane 8 q
+// returns the total of value q; other lanes return partial sums.  34
+// operations instead of 8 separate 12-operation reductions.
+__device__ __forceinline__ float wave_sum8(const float (&v)[8], int &q) {
+  const int l = __lane_id();
+  const bool h5 = (l >> 5) & 1, h4 = (l >> 4) & 1, h3 = (l >> 3) & 1;
+  float a[4], b[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
+    a[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
+    b[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  float c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+  c += __shfl_xor(c, 4, 64);
+  c += __shfl_xor(c, 2, 64);
+  c += __shfl_xor(c, 1, 64);
+  q = 4 * h5 + 2 * h4 + h3;
+  return c;
+}
+
+// Reverse replay of one tile, 128 threads, two vertically adjacent pixels
+// per thread, exactly mirroring the forward's per-pixel alpha sequence so
+// that T_i = T_{i+1} / (1 - a_i) retraces the forward's transmittances.
 template <bool AMIN>
 __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
-  __shared__ float4 sA[kBlock], sB[kBlock];
-  __shared__ float sC[kBlock];
-  __shared__ uint32_t s_slot[kBlock];
-  __shared__ float sG[9][kBlock];
+  __shared__ float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
+  __shared__ uint32_t s_slot[kCompBatch];
+  __shared__ float sG[9][kCompBatch];
   __shared__ uint32_t s_max;
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
-  const int t = threadIdx.x;
-  const int px = tx * kTile + (t % kTile), py = ty * kTile + (t / kTile);
-  const bool inside = px < a.W && py < a.H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const int t = threadIdx.x, l = __lane_id();
+  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + 2 * (t / kTile), py1 = py0 + 1;
+  const bool in0 = px < a.W && py0 < a.H, in1 = px < a.W && py1 < a.H;
+  const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = fy0 + 1.0f;
   const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
   const uint32_t *vals = a.ws.tval[a.buf];
   const float4 *proj = a.ws.proj;
-  const size_t pix = (size_t)py * a.W + px, plane = (size_t)a.W * a.H;
-  float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
-  uint32_t last = 0;
-  if (inside) {
-    T = a.T_final[pix];
-    last = a.last[pix];
-    dr = a.dimg[pix];
-    dg = a.dimg[plane + pix];
-    db = a.dimg[2 * plane + pix];
+  const size_t plane = (size_t)a.W * a.H;
+  // per pixel: T, dL/dC, colour behind (starts as T_final * bg), entries used
+  float T[2] = {1.0f, 1.0f}, dr[2] = {0, 0}, dg[2] = {0, 0}, db[2] = {0, 0};
+  uint32_t last[2] = {0, 0};
+  const bool in[2] = {in0, in1};
+  const int py[2] = {py0, py1};
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (in[u]) {
+      const size_t pix = (size_t)py[u] * a.W + px;
+      T[u] = a.T_final[pix];
+      last[u] = a.last[pix];
+      dr[u] = a.dimg[pix];
+      dg[u] = a.dimg[plane + pix];
+      db[u] = a.dimg[2 * plane + pix];
+    }
+  float br[2], bgc[2], bb[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    br[u] = T[u] * a.bg[0];
+    bgc[u] = T[u] * a.bg[1];
+    bb[u] = T[u] * a.bg[2];
   }
-  // colour behind the current entry, starting with the background
-  float br = T * a.bg[0], bgc = T * a.bg[1], bb = T * a.bg[2];
   if (t == 0) s_max = 0;
   __syncthreads();
-  atomicMax(&s_max, last);
+  atomicMax(&s_max, max(last[0], last[1]));
   __syncthreads();
   const uint32_t n_used = min(s_max, end - start);
   const float amax = a.alpha_max, amin = a.alpha_min;
   if (n_used == 0) return;
-  for (int32_t b0 = (int32_t)((n_used - 1) / kBlock) * kBlock; b0 >= 0; b0 -= kBlock) {
-    const uint32_t e = start + (uint32_t)b0 + t;
-    const int nb = (int)min((uint32_t)kBlock, n_used - (uint32_t)b0);
-    if (t < nb) {
-      const uint32_t s = vals[e];
-      s_slot[t] = s;
-      sA[t] = proj[3 * (size_t)s];
-      sB[t] = proj[3 * (size_t)s + 1];
-      sC[t] = proj[3 * (size_t)s + 2].x;
-    }
+  for (int32_t b0 = (int32_t)((n_used - 1) / kCompBatch) * kCompBatch; b0 >= 0; b0 -= kCompBatch) {
+    const int nb = (int)min((uint32_t)kCompBatch, n_used - (uint32_t)b0);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) sG[q][t] = 0.0f;
+    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
+      const int i = t + q * kCompThreads;
+      if (i < nb) {
+        const uint32_t s = vals[start + (uint32_t)b0 + i];
+        s_slot[i] = s;
+        sA[i] = proj[3 * (size_t)s];
+        float4 bv = proj[3 * (size_t)s + 1];
+        sB[i] = bv;
+        float4 cv = proj[3 * (size_t)s + 2];
+        cv.y = __builtin_amdgcn_exp2f(-bv.y);  // 1 / opacity, for dL/dop = dL/da a / op
+        sC[i] = cv;
+      }
+#pragma unroll
+      for (int g = 0; g < 9; ++g) sG[g][i] = 0.0f;
+    }
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       const uint32_t li = (uint32_t)b0 + (uint32_t)j;  // index in the tile list
       const float4 A = sA[j];
       const float4 B = sB[j];
-      const float cb_ = sC[j];
+      const float4 Cc = sC[j];
       // the forward's sequence, so a0 (= op G') is bit-identical to it
-      const float dx = fx - A.x, dy = fy - A.y;
+      const float dx = fx - A.x;
       const float adx = fma_(A.z * dx, dx, B.y);
-      const float pwl = fma_(B.x * dy, dy, fma_(A.w * dx, dy, adx));
-      const float a0 = __builtin_amdgcn_exp2f(pwl);
-      const float al = fminf(amax, a0);
-      bool valid = li < last;
-      if (AMIN) valid = valid && !(al < amin);
-      float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (valid) {
-        const float inv1 = 1.0f / (1.0f - al);
-        const float Ti = T * inv1;
-        const float w = al * Ti;
-        g[6] = w * dr;
-        g[7] = w * dg;
-        g[8] = w * db;
-        const float cdot = fma_(B.z, dr, fma_(B.w, dg, cb_ * db));
-        const float bdot = fma_(br, dr, fma_(bgc, dg, bb * db));
-        const float dLda = Ti * cdot - bdot * inv1;
-        br = fma_(w, B.z, br);
-        bgc = fma_(w, B.w, bgc);
-        bb = fma_(w, cb_, bb);
-        T = Ti;
-        if (a0 <= amax) {
-          g[5] = dLda * __builtin_amdgcn_exp2f(pwl - B.y);  // dL/dop = dL/da G'
-          const float dpw = dLda * a0 * kLn2;
-          // p = A' dx^2 + B' dx dy + C' dy^2 with the exp2-scaled conic
-          const float dAs = dpw * dx * dx, dBs = dpw * dx * dy, dCs = dpw * dy * dy;
-          g[2] = dAs * (-0.5f * kLog2e);
-          g[3] = dBs * (-kLog2e);
-          g[4] = dCs * (-0.5f * kLog2e);
-          g[0] = -dpw * fma_(2.0f * A.z, dx, A.w * dy);
-          g[1] = -dpw * fma_(A.w, dx, 2.0f * B.x * dy);
+      const float bdx = A.w * dx;
+      const float dyv[2] = {fy0 - A.y, fy1 - A.y};
+      float gs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const float dy = dyv[u];
+        const float pwl = fma_(B.x * dy, dy, fma_(bdx, dy, adx));
+        const float a0 = __builtin_amdgcn_exp2f(pwl);
+        const float al = fminf(amax, a0);
+        bool valid = li < last[u];
+        if (AMIN) valid = valid && !(al < amin);
+        if (valid) {
+          any = true;
+          const float inv1 = 1.0f / (1.0f - al);
+          const float Ti = T[u] * inv1;
+          const float w = al * Ti;
+          gs[6] += w * dr[u];
+          gs[7] += w * dg[u];
+          gs[8] += w * db[u];
+          const float cdot = fma_(B.z, dr[u], fma_(B.w, dg[u], Cc.x * db[u]));
+          const float bdot = fma_(br[u], dr[u], fma_(bgc[u], dg[u], bb[u] * db[u]));
+          const float dLda = Ti * cdot - bdot * inv1;
+          br[u] = fma_(w, B.z, br[u]);
+          bgc[u] = fma_(w, B.w, bgc[u]);
+          bb[u] = fma_(w, Cc.x, bb[u]);
+          T[u] = Ti;
+          if (a0 <= amax) {
+            const float dpa = dLda * a0;
+            gs[5] += dpa * Cc.y;  // dL/dop = dL/da G' = dL/da a0 / op
+            const float dpw = dpa * kLn2;
+            // p = A' dx^2 + B' dx dy + C' dy^2 with the exp2-scaled conic
+            gs[2] += dpw * dx * dx * (-0.5f * kLog2e);
+            gs[3] += dpw * dx * dy * (-kLog2e);
+            gs[4] += dpw * dy * dy * (-0.5f * kLog2e);
+            gs[0] += -dpw * fma_(2.0f * A.z, dx, A.w * dy);
+            gs[1] += -dpw * fma_(A.w, dx, 2.0f * B.x * dy);
+          }
         }
       }
-      if (ballot(valid) != 0ull) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const float v = wave_sum_f(g[q]);
-          if (__lane_id() == 0 && v != 0.0f) atomicAdd(&sG[q][j], v);
-        }
+      if (ballot(any) != 0ull) {
+        int q;
+        const float v8[8] = {gs[0], gs[1], gs[2], gs[3], gs[4], gs[5], gs[6], gs[7]};
+        const float s8 = wave_sum8(v8, q);
+        const float s9 = wave_sum_f(gs[8]);
+        if ((l & 7) == 0 && s8 != 0.0f) atomicAdd(&sG[q][j], s8);
+        if (l == 0 && s9 != 0.0f) atomicAdd(&sG[8][j], s9);
       }
     }
     __syncthreads();
-    if (t < nb) {
-      float *d = a.ws.dproj + 9 * (size_t)s_slot[t];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const float v = sG[q][t];
-        if (v != 0.0f) atomicAdd(d + q, v);
+    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
+      const int i = t + q * kCompThreads;
+      if (i < nb) {
+        float *d = a.ws.dproj + 9 * (size_t)s_slot[i];
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+          const float v = sG[g][i];
+          if (v != 0.0f) atomicAdd(d + g, v);
+        }
       }
     }
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_composite_bwd(BwdArgs a) {
+__global__ __launch_bounds__(kCompThreads) void k_composite_bwd(BwdArgs a) {
   if (a.alpha_min > 0.0f)
     composite_bwd_tile<true>(a);
   else
@@ -337,7 +396,7 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   b.T_final = T_final;
   b.dimg = dL_drgb;
   b.last = last;
-  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kCompThreads), 0, s, b);
   PBwdArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
   for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];

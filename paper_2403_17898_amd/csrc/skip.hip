@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_flag_scatter(const uint32_t *count, 
 // d = wgt (sigmoid(x) - y) / B; loss += wgt * (softplus(x) - y x) / B.
 __global__ __launch_bounds__(kBlock) void k_bce(const float *x, const float *y, int B, float pw,
                                                 float *d, float *loss) {
+  __shared__ float red[4];
   float acc = 0.0f;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < B; i += gridDim.x * kBlock) {
     const float xi = x[i], yi = y[i];
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_bce(const float *x, const float *y, 
     const float sp = fmaxf(xi, 0.0f) + log1pf(__expf(-fabsf(xi)));
     acc += wgt * (sp - yi * xi);
   }
-  acc = wave_sum_f(acc);
-  if (__lane_id() == 0 && acc != 0.0f) atomicAdd(loss, acc / (float)B);
+  acc = block_sum_f(acc, red);  // one atomic per block on the loss
+  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc / (float)B);
 }
 
 struct TrainLayout {

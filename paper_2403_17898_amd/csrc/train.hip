@@ -7,19 +7,34 @@ namespace octgs {
 
 namespace {
 
+// Grid-stride with four independent elements per thread per step; one
+// atomic per block for the loss (every atomic on the one loss address is
+// serialised across the XCDs, so the grid stays small).
 __global__ __launch_bounds__(kBlock) void k_l1(const float *__restrict__ img,
                                                const float *__restrict__ tgt, int64_t n,
                                                float scale, float *__restrict__ dimg,
                                                float *__restrict__ loss) {
+  __shared__ float red[4];
   float acc = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock) {
-    const float d = img[i] - tgt[i];
-    dimg[i] = d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
-    acc += fabsf(d);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    float d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = min(i0 + u * stride, n - 1);
+      d[u] = img[i] - tgt[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+        dimg[i] = d[u] > 0.0f ? scale : (d[u] < 0.0f ? -scale : 0.0f);
+        acc += fabsf(d[u]);
+      }
+    }
   }
-  acc = wave_sum_f(acc);
-  if (__lane_id() == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
+  acc = block_sum_f(acc, red);
+  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adam(float *__restrict__ p, const float *__restrict__ g,
@@ -49,7 +64,7 @@ int octgs_l1_loss_grad(const float *img, const float *target, int64_t n, float s
                        float *loss, octgs_stream stream) {
   if (n < 0 || (n > 0 && (!img || !target || !dimg || !loss))) return OCTGS_EINVAL;
   if (n == 0) return OCTGS_OK;
-  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 512);
   hipLaunchKernelGGL(k_l1, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, img, target, n, scale,
                      dimg, loss);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
