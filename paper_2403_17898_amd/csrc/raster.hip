@@ -589,11 +589,20 @@ struct CompArgs {
 //   a = min(alpha_max, exp2(p)) = min(alpha_max, op G')
 // The loop is branch-free (lanes that are done blend alpha 0), so a wave
 // only branches on wave-uniform conditions.
+template <bool LOG>
+struct CompLds {
+  float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
+  uint32_t s_slot[LOG ? kCompBatch : 1];
+  float s_w[LOG ? kCompBatch : 1];
+};
+
+// The LDS lives in the kernel and is passed in, so the two AMIN
+// instantiations share one allocation.
 template <bool LOG, bool AMIN>
-__device__ __forceinline__ void composite_tile(const CompArgs &a) {
-  __shared__ float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
-  __shared__ uint32_t s_slot[LOG ? kCompBatch : 1];
-  __shared__ float s_w[LOG ? kCompBatch : 1];
+__device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &lds) {
+  float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
+  uint32_t *s_slot = lds.s_slot;
+  float *s_w = lds.s_w;
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
@@ -708,10 +717,11 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a) {
 
 template <bool LOG>
 __global__ __launch_bounds__(kCompThreads) void k_composite(CompArgs a) {
+  __shared__ CompLds<LOG> lds;
   if (a.alpha_min > 0.0f)
-    composite_tile<LOG, true>(a);
+    composite_tile<LOG, true>(a, lds);
   else
-    composite_tile<LOG, false>(a);
+    composite_tile<LOG, false>(a, lds);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

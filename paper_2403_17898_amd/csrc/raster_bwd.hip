@@ -66,12 +66,21 @@ __device__ __forceinline__ float wave_sum8(const float (&v)[8], int &q) {
 // Reverse replay of one tile, 128 threads, two vertically adjacent pixels
 // per thread, exactly mirroring the forward's per-pixel alpha sequence so
 // that T_i = T_{i+1} / (1 - a_i) retraces the forward's transmittances.
+struct BwdLds {
+  float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
+  uint32_t s_slot[kCompBatch];
+  float sG[9][kCompBatch];
+  uint32_t s_max;
+};
+
+// The LDS lives in the kernel and is passed in, so the two AMIN
+// instantiations share one allocation.
 template <bool AMIN>
-__device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
-  __shared__ float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
-  __shared__ uint32_t s_slot[kCompBatch];
-  __shared__ float sG[9][kCompBatch];
-  __shared__ uint32_t s_max;
+__device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds) {
+  float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
+  uint32_t *s_slot = lds.s_slot;
+  float (*sG)[kCompBatch] = lds.sG;
+  uint32_t &s_max = lds.s_max;
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
@@ -141,7 +150,10 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
       const float adx = fma_(A.z * dx, dx, B.y);
       const float bdx = A.w * dx;
       const float dyv[2] = {fy0 - A.y, fy1 - A.y};
-      float gs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      // raw per-lane sums, turned into gradients once per (tile, Gaussian):
+      // dq = dL/da a0 (0 where alpha is clamped); D = sum dq over the two
+      // pixels, Sy = sum dq dy, Qyy = sum dq dy^2; colour weights w dL/dC
+      float D = 0.0f, Sy = 0.0f, Qyy = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
       bool any = false;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -153,12 +165,12 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
         if (AMIN) valid = valid && !(al < amin);
         if (valid) {
           any = true;
-          const float inv1 = 1.0f / (1.0f - al);
+          const float inv1 = __builtin_amdgcn_rcpf(1.0f - al);
           const float Ti = T[u] * inv1;
           const float w = al * Ti;
-          gs[6] += w * dr[u];
-          gs[7] += w * dg[u];
-          gs[8] += w * db[u];
+          wr = fma_(w, dr[u], wr);
+          wg = fma_(w, dg[u], wg);
+          wb = fma_(w, db[u], wb);
           const float cdot = fma_(B.z, dr[u], fma_(B.w, dg[u], Cc.x * db[u]));
           const float bdot = fma_(br[u], dr[u], fma_(bgc[u], dg[u], bb[u] * db[u]));
           const float dLda = Ti * cdot - bdot * inv1;
@@ -166,39 +178,49 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
           bgc[u] = fma_(w, B.w, bgc[u]);
           bb[u] = fma_(w, Cc.x, bb[u]);
           T[u] = Ti;
-          if (a0 <= amax) {
-            const float dpa = dLda * a0;
-            gs[5] += dpa * Cc.y;  // dL/dop = dL/da G' = dL/da a0 / op
-            const float dpw = dpa * kLn2;
-            // p = A' dx^2 + B' dx dy + C' dy^2 with the exp2-scaled conic
-            gs[2] += dpw * dx * dx * (-0.5f * kLog2e);
-            gs[3] += dpw * dx * dy * (-kLog2e);
-            gs[4] += dpw * dy * dy * (-0.5f * kLog2e);
-            gs[0] += -dpw * fma_(2.0f * A.z, dx, A.w * dy);
-            gs[1] += -dpw * fma_(A.w, dx, 2.0f * B.x * dy);
-          }
+          const float dq = a0 <= amax ? dLda * a0 : 0.0f;
+          D += dq;
+          const float dqy = dq * dy;
+          Sy += dqy;
+          Qyy = fma_(dqy, dy, Qyy);
         }
       }
       if (ballot(any) != 0ull) {
         int q;
-        const float v8[8] = {gs[0], gs[1], gs[2], gs[3], gs[4], gs[5], gs[6], gs[7]};
+        const float v8[8] = {D, D * dx, D * dx * dx, Sy, Sy * dx, Qyy, wr, wg};
         const float s8 = wave_sum8(v8, q);
-        const float s9 = wave_sum_f(gs[8]);
+        const float s9 = wave_sum_f(wb);
         if ((l & 7) == 0 && s8 != 0.0f) atomicAdd(&sG[q][j], s8);
         if (l == 0 && s9 != 0.0f) atomicAdd(&sG[8][j], s9);
       }
     }
     __syncthreads();
+    // raw sums -> dL/d(mx, my, ca, cb, cc, op, r, g, b).  With dpw = ln2 dq
+    // and p = A' dx^2 + B' dx dy + C' dy^2 (dx = x - mx):
+    //   dmx = -(2 A' Sx + B' Sy) ln2, dmy = -(B' Sx + 2 C' Sy) ln2,
+    //   d(ca, cb, cc) = ln2 (-log2e / 2 Qxx, -log2e Qxy, -log2e / 2 Qyy),
+    //   dop = D / op
 #pragma unroll
     for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
       const int i = t + q * kCompThreads;
       if (i < nb) {
+        const float4 A = sA[i], B = sB[i], Cc = sC[i];
+        const float D = sG[0][i], Sx = sG[1][i], Qxx = sG[2][i], Sy = sG[3][i];
+        const float Qxy = sG[4][i], Qyy = sG[5][i];
+        float g[9];
+        g[0] = -kLn2 * fma_(2.0f * A.z, Sx, A.w * Sy);
+        g[1] = -kLn2 * fma_(A.w, Sx, 2.0f * B.x * Sy);
+        g[2] = -0.5f * Qxx;  // ln2 * log2e = 1
+        g[3] = -Qxy;
+        g[4] = -0.5f * Qyy;
+        g[5] = D * Cc.y;
+        g[6] = sG[6][i];
+        g[7] = sG[7][i];
+        g[8] = sG[8][i];
         float *d = a.ws.dproj + 9 * (size_t)s_slot[i];
 #pragma unroll
-        for (int g = 0; g < 9; ++g) {
-          const float v = sG[g][i];
-          if (v != 0.0f) atomicAdd(d + g, v);
-        }
+        for (int k = 0; k < 9; ++k)
+          if (g[k] != 0.0f) atomicAdd(d + k, g[k]);
       }
     }
     __syncthreads();
@@ -206,10 +228,11 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a) {
 }
 
 __global__ __launch_bounds__(kCompThreads) void k_composite_bwd(BwdArgs a) {
+  __shared__ BwdLds lds;
   if (a.alpha_min > 0.0f)
-    composite_bwd_tile<true>(a);
+    composite_bwd_tile<true>(a, lds);
   else
-    composite_bwd_tile<false>(a);
+    composite_bwd_tile<false>(a, lds);
 }
 
 struct PBwdArgs {
