@@ -49,16 +49,57 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// Cross-lane moves without LDS: DPP within 16-lane rows, permlane swaps
+// across rows (gfx950).  Controls: quad_perm [1,0,3,2] = lane ^ 1, quad_perm
+// [2,3,0,1] = lane ^ 2, row_half_mirror = 7 - lane within 8, row_ror:8 =
+// lane ^ 8 within 16.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRor8 = 0x128;
+
+// (x, y) -> (x with rows 1, 3 replaced by y's rows 0, 2; y with rows 0, 2
+// replaced by x's rows 1, 3): x + y sums lanes L and L ^ 16, keeping x's
+// value in rows 0 and 2 and y's in rows 1 and 3.
+__device__ __forceinline__ void swap16(uint32_t &x, uint32_t &y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+// The same across halves: x + y sums lanes L and L ^ 32, x's value in the
+// lower half and y's in the upper.
+__device__ __forceinline__ void swap32(uint32_t &x, uint32_t &y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+
+// Sum over the wave, the same bits in every lane.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_u<kDppXor1>(v);
+  v += dpp_u<kDppXor2>(v);
+  v += dpp_u<kDppHalfMirror>(v);
+  v += dpp_u<kDppRor8>(v);
+  uint32_t x = v, y = v;
+  swap16(x, y);
+  v = x + y;
+  x = v; y = v;
+  swap32(x, y);
+  return x + y;
 }
 
 __device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += __uint_as_float(dpp_u<kDppXor1>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppXor2>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppHalfMirror>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppRor8>(__float_as_uint(v)));
+  uint32_t x = __float_as_uint(v), y = x;
+  swap16(x, y);
+  v = __uint_as_float(x) + __uint_as_float(y);
+  x = __float_as_uint(v); y = x;
+  swap32(x, y);
+  return __uint_as_float(x) + __uint_as_float(y);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns

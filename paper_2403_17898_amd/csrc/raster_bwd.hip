@@ -36,30 +36,31 @@ struct BwdArgs {
   const uint32_t *last;
 };
 
-// Sum of 8 values over the 64 lanes of a wave, by halving exchanges: after
-// the xor-32, xor-16 and xor-8 steps each lane holds one partial sum of value
-// 4 b5 + 2 b4 + b3 (b = lane bits), and xor-4, -2, -1 finish it.  Lane 8 q
-// returns the total of value q; other lanes return partial sums.  34
-// operations instead of 8 separate 12-operation reductions.
+// Sum of 8 values over the 64 lanes of a wave, by halving exchanges: a
+// permlane32 swap, a permlane16 swap and a DPP row rotation leave each lane
+// one partial sum of value 4 b5 + 2 b4 + b3 (b = lane bits), and three DPP
+// steps finish it within 8 lanes.  Lane 8 q returns the total of value q.
 __device__ __forceinline__ float wave_sum8(const float (&v)[8], int &q) {
   const int l = __lane_id();
-  const bool h5 = (l >> 5) & 1, h4 = (l >> 4) & 1, h3 = (l >> 3) & 1;
   float a[4], b[2];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
-    a[i] = keep + __shfl_xor(send, 32, 64);
+    uint32_t x = __float_as_uint(v[i]), y = __float_as_uint(v[4 + i]);
+    swap32(x, y);
+    a[i] = __uint_as_float(x) + __uint_as_float(y);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
-    b[i] = keep + __shfl_xor(send, 16, 64);
+    uint32_t x = __float_as_uint(a[i]), y = __float_as_uint(a[2 + i]);
+    swap16(x, y);
+    b[i] = __uint_as_float(x) + __uint_as_float(y);
   }
-  float c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
-  c += __shfl_xor(c, 4, 64);
-  c += __shfl_xor(c, 2, 64);
-  c += __shfl_xor(c, 1, 64);
-  q = 4 * h5 + 2 * h4 + h3;
+  const bool h3 = (l >> 3) & 1;
+  float c = (h3 ? b[1] : b[0]) + __uint_as_float(dpp_u<kDppRor8>(__float_as_uint(h3 ? b[0] : b[1])));
+  c += __uint_as_float(dpp_u<kDppXor1>(__float_as_uint(c)));
+  c += __uint_as_float(dpp_u<kDppXor2>(__float_as_uint(c)));
+  c += __uint_as_float(dpp_u<kDppHalfMirror>(__float_as_uint(c)));
+  q = 4 * ((l >> 5) & 1) + 2 * ((l >> 4) & 1) + (int)h3;
   return c;
 }
 
