@@ -4,11 +4,12 @@
 // three MLP heads' weights and biases.
 //
 // Structure: the forward activations are recomputed (hidden pre-activations
-// and head outputs), the activation derivatives give dY, and the six GEMM
-// products of each head's backward (dW2 = relu(H)^T dY, dH = dY W2^T masked
-// by relu', dW1 = X^T dH, dX = dH W1^T) run on one tiled FP32 GEMM kernel.
-// Weight gradients reduce over anchors with split-K blocks and atomics.  The
-// anchor count lives on the device; every kernel reads it.
+// and head outputs), the activation derivatives give dY, and the products of
+// each head's backward (dW2 = relu(H)^T dY, dH = dY W2^T masked by relu',
+// dW1 = X^T dH, dX = dH W1^T) run on one tiled FP32 GEMM kernel, the three
+// heads of a product in one grouped launch.  Weight gradients reduce over
+// anchors with split-K blocks and atomics.  The anchor count lives on the
+// device; every kernel reads it.
 #include "octgs_internal.h"
 
 namespace octgs {
@@ -215,53 +216,68 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   hipLaunchKernelGGL(k_bwd_gather, dim3(grid), dim3(kBlock), 0, s, a);
   const int splitk = (int)std::min<int64_t>(std::max<int64_t>(mcap / 512, 1), 64);
   hipError_t e = hipSuccess;
-  for (int h = 0; h < 3 && e == hipSuccess; ++h) {
-    // forward recompute: Hp_h = X W1_h + b1_h; Y_h = relu(Hp_h) W2_h + b2_h
-    Gemm g = gemm_base();
-    g.A = L.X; g.lda = 36; g.B = mlp->w1[h]; g.ldb = W; g.C = L.Hp + h * W; g.ldc = 3 * W;
-    g.M = (int)mcap; g.N = W; g.K = 36; g.dyn = count; g.dyn_dim = 1; g.dyn_cap = (int)mcap;
-    g.bias = mlp->b1[h];
-    e = gemm(g, mcap, s);
-    if (e != hipSuccess) break;
-    Gemm g2 = gemm_base();
-    g2.A = L.Hp + h * W; g2.lda = 3 * W; g2.reluA = 1; g2.B = mlp->w2[h]; g2.ldb = a.outs[h];
-    g2.C = L.Y + a.off[h]; g2.ldc = a.OT; g2.M = (int)mcap; g2.N = a.outs[h]; g2.K = W;
-    g2.dyn = count; g2.dyn_dim = 1; g2.dyn_cap = (int)mcap; g2.bias = mlp->b2[h];
-    e = gemm(g2, mcap, s);
+  // Each product below runs for the three heads in one grouped launch.
+  // Forward recompute: Hp_h = X W1_h + b1_h; Y_h = relu(Hp_h) W2_h + b2_h.
+  Gemm g1 = gemm_base();
+  g1.groups = 3;
+  g1.lda = 36; g1.ldb = W; g1.ldc = 3 * W;
+  g1.M = (int)mcap; g1.K = 36; g1.dyn = count; g1.dyn_dim = 1; g1.dyn_cap = (int)mcap;
+  Gemm g2 = gemm_base();
+  g2.groups = 3;
+  g2.lda = 3 * W; g2.reluA = 1; g2.ldc = a.OT; g2.M = (int)mcap; g2.K = W;
+  g2.dyn = count; g2.dyn_dim = 1; g2.dyn_cap = (int)mcap;
+  // dW2_h += relu(Hp_h)^T dY_h
+  Gemm g3 = gemm_base();
+  g3.groups = 3;
+  g3.lda = 3 * W; g3.transA = 1; g3.reluA = 1; g3.ldb = a.OT;
+  g3.M = W; g3.K = (int)mcap; g3.dyn = count; g3.dyn_dim = 2; g3.dyn_cap = (int)mcap;
+  g3.accumulate = 1; g3.splitk = splitk;
+  // dHp_h = (dY_h W2_h^T) * (Hp_h > 0)
+  Gemm g4 = gemm_base();
+  g4.groups = 3;
+  g4.lda = a.OT; g4.transB = 1; g4.ldc = 3 * W; g4.ldm = 3 * W;
+  g4.M = (int)mcap; g4.dyn = count; g4.dyn_dim = 1; g4.dyn_cap = (int)mcap;
+  // dW1_h += X^T dHp_h
+  Gemm g5 = gemm_base();
+  g5.groups = 3;
+  g5.lda = 36; g5.transA = 1; g5.ldb = 3 * W; g5.ldc = W; g5.M = 36; g5.K = (int)mcap;
+  g5.dyn = count; g5.dyn_dim = 2; g5.dyn_cap = (int)mcap; g5.accumulate = 1; g5.splitk = splitk;
+  for (int h = 0; h < 3; ++h) {
+    g1.A3[h] = L.X; g1.B3[h] = mlp->w1[h]; g1.C3[h] = L.Hp + h * W; g1.bias3[h] = mlp->b1[h];
+    g1.N3[h] = W;
+    g2.A3[h] = L.Hp + h * W; g2.B3[h] = mlp->w2[h]; g2.ldb3[h] = a.outs[h];
+    g2.C3[h] = L.Y + a.off[h]; g2.bias3[h] = mlp->b2[h]; g2.N3[h] = a.outs[h];
+    g3.A3[h] = L.Hp + h * W; g3.B3[h] = L.dY + a.off[h]; g3.C3[h] = gm->w2[h];
+    g3.ldc3[h] = a.outs[h]; g3.N3[h] = a.outs[h];
+    g4.A3[h] = L.dY + a.off[h]; g4.B3[h] = mlp->w2[h]; g4.ldb3[h] = a.outs[h];
+    g4.C3[h] = L.dHp + h * W; g4.mask3[h] = L.Hp + h * W; g4.N3[h] = W; g4.K3[h] = a.outs[h];
+    g5.A3[h] = L.X; g5.B3[h] = L.dHp + h * W; g5.C3[h] = gm->w1[h]; g5.N3[h] = W;
   }
-  if (e != hipSuccess) return OCTGS_EHIP;
+  if ((e = gemm(g1, mcap, s)) != hipSuccess) return OCTGS_EHIP;
+  if ((e = gemm(g2, mcap, s)) != hipSuccess) return OCTGS_EHIP;
   hipLaunchKernelGGL(k_act_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  if ((e = gemm(g3, W, s)) != hipSuccess) return OCTGS_EHIP;
+  if ((e = gemm(g4, mcap, s)) != hipSuccess) return OCTGS_EHIP;
+  if ((e = gemm(g5, 36, s)) != hipSuccess) return OCTGS_EHIP;
+  {
+    // db2_h += column sums of dY_h; db1_h += column sums of dHp_h
+    const float *Y3[3] = {L.dY + a.off[0], L.dY + a.off[1], L.dY + a.off[2]};
+    float *o3[3] = {gm->b2[0], gm->b2[1], gm->b2[2]};
+    if ((e = colsum3(Y3, (int64_t)a.OT, a.outs, count, (int)mcap, o3, s)) != hipSuccess)
+      return OCTGS_EHIP;
+    const float *H3[3] = {L.dHp, L.dHp + W, L.dHp + 2 * W};
+    float *p3[3] = {gm->b1[0], gm->b1[1], gm->b1[2]};
+    const int nw[3] = {W, W, W};
+    if ((e = colsum3(H3, (int64_t)(3 * W), nw, count, (int)mcap, p3, s)) != hipSuccess)
+      return OCTGS_EHIP;
+  }
+  // dX = sum over heads of dHp_h W1_h^T (accumulated head by head)
   for (int h = 0; h < 3 && e == hipSuccess; ++h) {
-    // dW2_h += relu(Hp_h)^T dY_h
-    Gemm g = gemm_base();
-    g.A = L.Hp + h * W; g.lda = 3 * W; g.transA = 1; g.reluA = 1;
-    g.B = L.dY + a.off[h]; g.ldb = a.OT; g.C = gm->w2[h]; g.ldc = a.outs[h];
-    g.M = W; g.N = a.outs[h]; g.K = (int)mcap; g.dyn = count; g.dyn_dim = 2; g.dyn_cap = (int)mcap;
-    g.accumulate = 1; g.splitk = splitk;
-    e = gemm(g, W, s);
-    if (e != hipSuccess) break;
-    colsum(L.dY + a.off[h], (int64_t)a.OT, a.outs[h], count, (int)mcap, gm->b2[h], s);
-    // dHp_h = (dY_h W2_h^T) * (Hp_h > 0)
-    Gemm g3 = gemm_base();
-    g3.A = L.dY + a.off[h]; g3.lda = a.OT; g3.B = mlp->w2[h]; g3.ldb = a.outs[h]; g3.transB = 1;
-    g3.C = L.dHp + h * W; g3.ldc = 3 * W; g3.M = (int)mcap; g3.N = W; g3.K = a.outs[h];
-    g3.dyn = count; g3.dyn_dim = 1; g3.dyn_cap = (int)mcap; g3.mask = L.Hp + h * W; g3.ldm = 3 * W;
-    e = gemm(g3, mcap, s);
-    if (e != hipSuccess) break;
-    // dW1_h += X^T dHp_h
-    Gemm g4 = gemm_base();
-    g4.A = L.X; g4.lda = 36; g4.transA = 1; g4.B = L.dHp + h * W; g4.ldb = 3 * W;
-    g4.C = gm->w1[h]; g4.ldc = W; g4.M = 36; g4.N = W; g4.K = (int)mcap;
-    g4.dyn = count; g4.dyn_dim = 2; g4.dyn_cap = (int)mcap; g4.accumulate = 1; g4.splitk = splitk;
-    e = gemm(g4, 36, s);
-    if (e != hipSuccess) break;
-    colsum(L.dHp + h * W, (int64_t)(3 * W), W, count, (int)mcap, gm->b1[h], s);
-    // dX (+)= dHp_h W1_h^T
-    Gemm g5 = gemm_base();
-    g5.A = L.dHp + h * W; g5.lda = 3 * W; g5.B = mlp->w1[h]; g5.ldb = W; g5.transB = 1;
-    g5.C = L.dX; g5.ldc = 36; g5.M = (int)mcap; g5.N = 36; g5.K = W;
-    g5.dyn = count; g5.dyn_dim = 1; g5.dyn_cap = (int)mcap; g5.accumulate = h > 0 ? 1 : 0;
-    e = gemm(g5, mcap, s);
+    Gemm g6 = gemm_base();
+    g6.A = L.dHp + h * W; g6.lda = 3 * W; g6.B = mlp->w1[h]; g6.ldb = W; g6.transB = 1;
+    g6.C = L.dX; g6.ldc = 36; g6.M = (int)mcap; g6.N = 36; g6.K = W;
+    g6.dyn = count; g6.dyn_dim = 1; g6.dyn_cap = (int)mcap; g6.accumulate = h > 0 ? 1 : 0;
+    e = gemm(g6, mcap, s);
   }
   if (e != hipSuccess) return OCTGS_EHIP;
   hipLaunchKernelGGL(k_x_bwd, dim3(grid), dim3(kBlock), 0, s, a);

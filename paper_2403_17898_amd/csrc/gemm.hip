@@ -16,6 +16,14 @@ constexpr int GT = 64, GK = 16;
 __global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
   __shared__ float As[GK][GT + 4];
   __shared__ float Bs[GK][GT + 4];
+  const int grp = blockIdx.z / g.splitk, sk = blockIdx.z % g.splitk;
+  if (g.groups > 1) {
+    g.A = g.A3[grp]; g.B = g.B3[grp]; g.C = g.C3[grp];
+    g.bias = g.bias3[grp]; g.mask = g.mask3[grp]; g.N = g.N3[grp];
+    if (g.K3[grp]) g.K = g.K3[grp];
+    if (g.ldb3[grp]) g.ldb = g.ldb3[grp];
+    if (g.ldc3[grp]) g.ldc = g.ldc3[grp];
+  }
   int M = g.M, K = g.K;
   if (g.dyn) {
     const int d = (int)min(*g.dyn, (uint32_t)g.dyn_cap);
@@ -24,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   if (m0 >= M || n0 >= g.N) return;
   const int kchunk = (K + g.splitk - 1) / g.splitk;
-  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int kb = sk * kchunk, ke = min(K, kb + kchunk);
   if (kb >= ke) return;
   const int t = threadIdx.x, tx = t % 16, ty = t / 16;
   float acc[4][4] = {};
@@ -79,14 +87,22 @@ __global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_colsum(const float *Y, int64_t ld, int N,
-                                                   const uint32_t *dyn, int cap, float *out) {
+struct Colsum3 {
+  const float *Y[3];
+  float *out[3];
+  int N[3];
+};
+
+// blockIdx.y selects the column set; rows are strided over blockIdx.x
+__global__ __launch_bounds__(kBlock) void k_colsum(Colsum3 c, int64_t ld, const uint32_t *dyn,
+                                                   int cap) {
   const int M = dyn ? (int)min(*dyn, (uint32_t)cap) : cap;
-  const int n = threadIdx.x;
-  if (n >= N) return;
+  const int gsel = blockIdx.y, n = threadIdx.x;
+  if (n >= c.N[gsel]) return;
+  const float *Y = c.Y[gsel];
   float s = 0.0f;
   for (int m = blockIdx.x; m < M; m += gridDim.x) s += Y[(int64_t)m * ld + n];
-  if (s != 0.0f) atomicAdd(out + n, s);
+  if (s != 0.0f) atomicAdd(c.out[gsel] + n, s);
 }
 
 __global__ void k_fill(float *p, int64_t n, float v) {
@@ -99,7 +115,20 @@ __global__ void k_fill(float *p, int64_t n, float v) {
 
 hipError_t colsum(const float *Y, int64_t ld, int N, const uint32_t *dyn, int cap, float *out,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, Y, ld, N, dyn, cap, out);
+  Colsum3 c;
+  memset(&c, 0, sizeof c);
+  c.Y[0] = Y; c.out[0] = out; c.N[0] = N;
+  hipLaunchKernelGGL(k_colsum, dim3(256, 1), dim3(kBlock), 0, s, c, ld, dyn, cap);
+  return hipGetLastError();
+}
+
+hipError_t colsum3(const float *const Y3[3], int64_t ld, const int N3[3], const uint32_t *dyn,
+                   int cap, float *const out3[3], hipStream_t s) {
+  Colsum3 c;
+  for (int i = 0; i < 3; ++i) {
+    c.Y[i] = Y3[i]; c.out[i] = out3[i]; c.N[i] = N3[i];
+  }
+  hipLaunchKernelGGL(k_colsum, dim3(256, 3), dim3(kBlock), 0, s, c, ld, dyn, cap);
   return hipGetLastError();
 }
 
@@ -112,8 +141,12 @@ hipError_t fill(float *p, int64_t n, float v, hipStream_t s) {
 
 hipError_t gemm(const Gemm &g0, int64_t m_cap, hipStream_t s) {
   const int64_t mt = (std::max<int64_t>(m_cap, 1) + GT - 1) / GT;
-  const int nt = (g0.N + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk), dim3(kBlock), 0, s, g0);
+  int nmax = g0.N;
+  if (g0.groups > 1)
+    for (int i = 0; i < g0.groups; ++i) nmax = std::max(nmax, g0.N3[i]);
+  const int nt = (nmax + GT - 1) / GT;
+  const int groups = std::max(g0.groups, 1);
+  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk * groups), dim3(kBlock), 0, s, g0);
   return hipGetLastError();
 }
 
@@ -121,6 +154,7 @@ Gemm gemm_base() {
   Gemm g;
   memset(&g, 0, sizeof g);
   g.splitk = 1;
+  g.groups = 1;
   return g;
 }
 
