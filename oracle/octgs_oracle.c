@@ -142,6 +142,31 @@ ORC_API void orc_bound_radius(int64_t n, int k, const float *offsets,
   }
 }
 
+/* Bound radius of an anchor carrying explicit Gaussians (the 3D-GS
+ * instance of the anchor framework): the largest centre distance from the
+ * anchor plus three times the largest scale, so the sphere holds every
+ * Gaussian's 3-sigma extent.  Canonical FP32: d = mean - pos,
+ * |d| = sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2))); the largest scale is
+ * exp of the largest log-scale, evaluated in double and rounded once.
+ * mean and log_scale are [n][k][3]. */
+ORC_API void orc_bound_radius_explicit(int64_t n, int k, const float *pos, const float *mean,
+                                       const float *log_scale, float *rho) {
+  for (int64_t j = 0; j < n; ++j) {
+    const float *p = pos + 3 * j;
+    float m = 0.0f, lmax = -INFINITY;
+    for (int i = 0; i < k; ++i) {
+      const float *mu = mean + (j * k + i) * 3;
+      const float *ls = log_scale + (j * k + i) * 3;
+      float a = mu[0] - p[0], b = mu[1] - p[1], c = mu[2] - p[2];
+      float nn = sqrtf(fmaf(a, a, fmaf(b, b, c * c)));
+      m = fmaxf(m, nn);
+      lmax = fmaxf(lmax, fmaxf(fmaxf(ls[0], ls[1]), ls[2]));
+    }
+    const float smax = (float)exp((double)lmax);
+    rho[j] = fmaf(3.0f, smax, m);
+  }
+}
+
 /* Canonical FP32 selection: visible(sphere) && d^2 * s^2 <= thr2, with
  * d^2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) for d = p - C.  Writes a 0/1
  * mask and returns the selected count. pos is [n][3]. */

@@ -58,6 +58,7 @@ _i32 = ctypes.c_int
 def _declare(L):
     L.orc_lod_thr2.argtypes = [_i64, _p, _p, ctypes.c_float, _p]
     L.orc_bound_radius.argtypes = [_i64, _i32, _p, _p, _p, _p]
+    L.orc_bound_radius_explicit.argtypes = [_i64, _i32, _p, _p, _p, _p]
     L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _i32, _p, _i32, _i32, _p]
     L.orc_select_fp32.restype = _i64
     L.orc_select_eq7.argtypes = [_i64, _p, _p, _p, ctypes.c_float, _i32, _p, _i32, _p, _i32, _i32,
@@ -132,6 +133,16 @@ def bound_radius(offsets, offset_scale, base_scale) -> np.ndarray:
     out = np.empty(n, np.float32)
     lib().orc_bound_radius(n, k, _ptr(offsets), _ptr(_c(offset_scale, np.float32)),
                            _ptr(_c(base_scale, np.float32)), _ptr(out))
+    return out
+
+
+def bound_radius_explicit(pos, mean, log_scale) -> np.ndarray:
+    """Canonical FP32 bound radius of anchors carrying explicit Gaussians."""
+    mean = _c(mean, np.float32)
+    n, k = mean.shape[0], mean.shape[1]
+    out = np.empty(n, np.float32)
+    lib().orc_bound_radius_explicit(n, k, _ptr(_c(pos, np.float32)), _ptr(mean),
+                                    _ptr(_c(log_scale, np.float32)), _ptr(out))
     return out
 
 

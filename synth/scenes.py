@@ -566,3 +566,63 @@ def tile_aligned_gaussians(cam: Camera, depths: Sequence[float], seed: int) -> n
     rgb = rng.random((n, 3))
     g = np.concatenate([pw, s, q, op[:, None], rgb], axis=1).T
     return np.ascontiguousarray(g.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------
+# explicit Gaussians per anchor (the 3D-GS instance of the anchor framework)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ExplicitScene:
+    """Anchors that each carry k explicit 3D Gaussians (Sec. V, "Our-3D-GS":
+    the octree anchors and Eq. 7 selection of the framework with 3D-GS
+    primitives).  Per Gaussian: world mean, log-scales, an unnormalised
+    rotation quaternion (w, x, y, z), an opacity logit and spherical-harmonic
+    colour coefficients [(D+1)^2][3]."""
+
+    pos: np.ndarray        # (N, 3) float32 anchor positions
+    level: np.ndarray      # (N,) uint8
+    lod_bias: np.ndarray   # (N,) float32
+    mean: np.ndarray       # (N, k, 3) float32
+    log_scale: np.ndarray  # (N, k, 3) float32
+    rot: np.ndarray        # (N, k, 4) float32
+    opacity: np.ndarray    # (N, k) float32 logits
+    sh: np.ndarray         # (N, k, (D+1)^2, 3) float32
+    sh_degree: int
+    d_max: float
+    n_levels: int
+    k: int
+    info: Dict[str, object]
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def make_explicit(sc: Scene, sh_degree: int = 3, seed: int = 11,
+                  opacity_logit=(-4.0, 2.0), dc_sigma: float = 0.6,
+                  rest_sigma: float = 0.15) -> ExplicitScene:
+    """Explicit Gaussians on the anchors of a neural scene, drawn with
+    statistics close to what the neural decode of that scene emits: means at
+    x_v + O_i * l_v, scales base_scale * U(0.2, 0.8) (the sigmoid-bounded
+    neural scale), random unnormalised rotations, opacity logits
+    U(opacity_logit), DC colour coefficients N(0, dc_sigma^2) and degree-l
+    coefficients N(0, (rest_sigma / l)^2)."""
+    rng = np.random.default_rng(seed)
+    n, k = sc.n, sc.k
+    nc = (sh_degree + 1) ** 2
+    mean = (sc.pos[:, None, :].astype(np.float64)
+            + sc.offsets.astype(np.float64) * sc.offset_scale[:, None, :]).astype(np.float32)
+    u = rng.uniform(0.2, 0.8, (n, k, 3))
+    log_scale = (np.log(sc.base_scale.astype(np.float64))[:, None, :] + np.log(u)).astype(np.float32)
+    rot = rng.standard_normal((n, k, 4)).astype(np.float32)
+    opacity = rng.uniform(opacity_logit[0], opacity_logit[1], (n, k)).astype(np.float32)
+    sh = np.empty((n, k, nc, 3), np.float32)
+    sh[:, :, 0, :] = dc_sigma * rng.standard_normal((n, k, 3))
+    for l in range(1, sh_degree + 1):
+        sh[:, :, l * l:(l + 1) * (l + 1), :] = (rest_sigma / l) * rng.standard_normal(
+            (n, k, 2 * l + 1, 3))
+    return ExplicitScene(pos=sc.pos, level=sc.level, lod_bias=sc.lod_bias, mean=mean,
+                         log_scale=log_scale, rot=rot, opacity=opacity, sh=sh,
+                         sh_degree=sh_degree, d_max=sc.d_max, n_levels=sc.n_levels, k=k,
+                         info=dict(sc.info, explicit_seed=seed))
