@@ -321,6 +321,69 @@ OCTGS_API int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, c
                                     const octgs_skip_net_grads *grads, float *loss, void *ws,
                                     size_t ws_bytes, octgs_stream stream);
 
+/* ---- explicit Gaussians on the anchors --------------------------------
+ * The 3D-GS instance of the anchor framework (Sec. V, "Our-3D-GS"): every
+ * anchor carries k explicit 3D Gaussians (Sec. III-A) instead of a feature
+ * decoded by MLPs.  Selection (octgs_select_lod, Eq. 7) and rasterization
+ * are shared with the neural path; only the per-scene preparation and the
+ * decode differ.  Arrays are indexed by Gaussian g = anchor * k + i, device
+ * memory, FP32 unless stated. */
+typedef struct {
+  int32_t sh_degree;       /* D, 0..3: (D+1)^2 colour coefficients per channel */
+  const float *mean;       /* [n][k][3] world position */
+  const float *log_scale;  /* [n][k][3] scale = exp(log_scale) */
+  const float *rot;        /* [n][k][4] quaternion w, x, y, z (normalised on use), 16-byte aligned */
+  const float *opacity;    /* [n][k] logit; opacity = sigmoid(logit) */
+  const float *sh;         /* [n][k][(D+1)^2][3] real SH coefficients, 16-byte aligned */
+  const uint16_t *sh_bf16; /* same layout as BF16 bit patterns (OCTGS_BF16; D = 1 or 3), 16-byte
+                              aligned; may be NULL otherwise */
+} octgs_explicit;
+
+/* Gradients of the explicit arrays (same shapes; rot and sh 16-byte
+ * aligned).  Accumulated (+=). */
+typedef struct {
+  float *mean, *log_scale, *rot, *opacity, *sh;
+} octgs_explicit_grads;
+
+/* Per-scene preparation for Eq. 7 with explicit Gaussians: thr2 as in
+ * octgs_prepare_anchors; bound_r[j] = max_i |mean_i - x_v| + 3 exp(max log_scale)
+ * over the anchor's Gaussians (canonical FP32; the exponential of the
+ * largest log-scale is taken in double and rounded once), a sphere holding
+ * every Gaussian's 3-sigma extent.  Reads a->n, k, d_max, pos, level,
+ * lod_bias and e->mean, e->log_scale.  Outputs: device [n] each. */
+OCTGS_API int octgs_prepare_explicit(const octgs_anchors *a, const octgs_explicit *e,
+                                     float *thr2, float *bound_r, octgs_stream stream);
+
+/* Decode of the explicit Gaussians of the first min(*count, out->capacity / k)
+ * anchors listed in idx (device): slot p*k + i receives Gaussian i of the
+ * p-th listed anchor as mean, exp(log_scale), the normalised quaternion
+ * (identity when its norm is 0), sigmoid(logit) and the colour
+ * max(0, sum_lm sh_lm Y_lm(d) + 0.5), d the unit vector from the camera
+ * centre to the mean and Y_lm the real spherical harmonics with the
+ * Condon-Shortley phase kept, ordered l^2 + l + m (the 3D-GS colour model).
+ * With cam->lod_blend the opacity is scaled by the transition factor of
+ * octgs_camera (needs a->pos, level, lod_bias).  precision OCTGS_BF16 reads
+ * e->sh_bf16 (other attributes stay FP32; arithmetic is FP32).  Writes
+ * out->data and *out->count like octgs_decode.  Returns OCTGS_EUNSUPPORTED for
+ * D > 3, or BF16 with D other than 1 and 3; OCTGS_EINVAL for misaligned rot or
+ * sh. */
+OCTGS_API int octgs_decode_explicit(const octgs_anchors *a, const octgs_explicit *e,
+                                    const octgs_camera *cam, const uint32_t *idx,
+                                    const uint32_t *count, int precision,
+                                    const octgs_gaussians *out, octgs_stream stream);
+
+/* Backward of octgs_decode_explicit (FP32 coefficients; lod_blend returns
+ * OCTGS_EUNSUPPORTED): from dL/dGaussian planar [14][gauss_capacity] of the
+ * slots written for the first min(*count, gauss_capacity / k) anchors of idx,
+ * accumulates the gradients of their explicit arrays, the mean also through
+ * the view direction of the colour.  Each listed anchor at most once per
+ * call (no atomics). */
+OCTGS_API int octgs_decode_explicit_bwd(const octgs_anchors *a, const octgs_explicit *e,
+                                        const octgs_camera *cam, const uint32_t *idx,
+                                        const uint32_t *count, const float *d_gauss,
+                                        int64_t gauss_capacity, const octgs_explicit_grads *g,
+                                        octgs_stream stream);
+
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:
  * the stats header, the sorted pair list (tile id and slot per entry, length

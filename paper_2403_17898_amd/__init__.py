@@ -5,6 +5,6 @@
 """
 
 from ._lib import (OCTGS_BF16, OCTGS_FP32, OctgsError, lib)  # noqa: F401
-from .render import (DeviceScene, RenderFn, SceneGrads, ViewBuffers, adam_step,  # noqa: F401
+from .render import (DeviceExplicit, DeviceScene, ExplicitGrads, RenderFn, SceneGrads, ViewBuffers, adam_step,  # noqa: F401
                      l1_loss_grad, make_camera, raster_params, render_diff, stream_handle,
                      trainable)

@@ -64,6 +64,15 @@ class SkipNet(ctypes.Structure):
     _fields_ = [("w1", _p), ("b1", _p), ("w2", _p), ("b2", _p), ("w3", _p), ("b3", _p)]
 
 
+class Explicit(ctypes.Structure):
+    _fields_ = [("sh_degree", _i32), ("mean", _p), ("log_scale", _p), ("rot", _p),
+                ("opacity", _p), ("sh", _p), ("sh_bf16", _p)]
+
+
+class ExplicitGrads(ctypes.Structure):
+    _fields_ = [("mean", _p), ("log_scale", _p), ("rot", _p), ("opacity", _p), ("sh", _p)]
+
+
 class RasterStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
                 ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
@@ -103,6 +112,14 @@ SIGNATURES = [
     ("octgs_skip_train_workspace_bytes", ctypes.c_size_t, [_i32]),
     ("octgs_skip_train_grad", _i32, [ctypes.POINTER(SkipNet), _p, _p, _i32, _f,
                                      ctypes.POINTER(SkipNet), _p, _p, ctypes.c_size_t, _p]),
+    ("octgs_prepare_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit), _p, _p,
+                                      _p]),
+    ("octgs_decode_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit),
+                                     ctypes.POINTER(Camera), _p, _p, _i32,
+                                     ctypes.POINTER(Gaussians), _p]),
+    ("octgs_decode_explicit_bwd", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit),
+                                         ctypes.POINTER(Camera), _p, _p, _p, _i64,
+                                         ctypes.POINTER(ExplicitGrads), _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

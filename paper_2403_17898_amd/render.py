@@ -136,6 +136,69 @@ class DeviceScene:
         return self._anchors
 
 
+EXPLICIT_FIELDS = ("mean", "log_scale", "rot", "opacity", "sh")
+
+
+class DeviceExplicit:
+    """Anchors carrying k explicit 3D Gaussians each (the 3D-GS instance of
+    the framework), resident in HBM with their Eq. 7 thresholds and bound
+    radii.  The SH coefficients are also kept as BF16 for OCTGS_BF16."""
+
+    def __init__(self, pos, level, lod_bias, mean, log_scale, rot, opacity, sh, sh_degree: int,
+                 d_max: float, n_levels: int, stream=None):
+        dev = _dev()
+        f32 = dict(dtype=torch.float32, device=dev)
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(**f32)
+        self.n = int(np.asarray(pos).shape[0])
+        self.k = int(np.asarray(mean).shape[1])
+        self.sh_degree, self.n_levels = int(sh_degree), int(n_levels)
+        self.d_max = float(np.float32(d_max))
+        self.pos = t(pos)
+        self.level = torch.as_tensor(np.ascontiguousarray(level, np.uint8)).to(dev)
+        self.lod_bias = t(lod_bias)
+        self.mean, self.log_scale, self.rot = t(mean), t(log_scale), t(rot)
+        self.opacity, self.sh = t(opacity), t(sh)
+        self.sh_bf16 = self.sh.to(torch.bfloat16).view(torch.int16).contiguous()
+        self.thr2 = torch.empty(max(1, self.n), **f32)
+        self.bound_r = torch.empty(max(1, self.n), **f32)
+        self._ex = L.Explicit()
+        self._ex.sh_degree = self.sh_degree
+        for name in EXPLICIT_FIELDS:
+            setattr(self._ex, name, getattr(self, name).data_ptr() if self.n else None)
+        self._ex.sh_bf16 = self.sh_bf16.data_ptr() if self.n else None
+        a = L.Anchors()
+        a.n, a.k, a.feat_dim, a.n_levels, a.d_max = self.n, self.k, 0, self.n_levels, self.d_max
+        if self.n:
+            a.pos, a.level, a.lod_bias = (self.pos.data_ptr(), self.level.data_ptr(),
+                                          self.lod_bias.data_ptr())
+            a.thr2, a.bound_r = self.thr2.data_ptr(), self.bound_r.data_ptr()
+        self._anchors = a
+        L.check(L.lib().octgs_prepare_explicit(ctypes.byref(a), ctypes.byref(self._ex),
+                                              _ptr(self.thr2), _ptr(self.bound_r),
+                                              stream_handle(stream)), "octgs_prepare_explicit")
+
+    @classmethod
+    def from_scene(cls, ex, stream=None) -> "DeviceExplicit":
+        return cls(ex.pos, ex.level, ex.lod_bias, ex.mean, ex.log_scale, ex.rot, ex.opacity,
+                   ex.sh, ex.sh_degree, ex.d_max, ex.n_levels, stream)
+
+    @property
+    def anchors(self) -> L.Anchors:
+        return self._anchors
+
+
+class ExplicitGrads:
+    """Device gradient buffers shaped like a DeviceExplicit's arrays."""
+
+    def __init__(self, ex: DeviceExplicit):
+        self.arrays = {n: torch.zeros_like(getattr(ex, n)) for n in EXPLICIT_FIELDS}
+        self._g = L.ExplicitGrads(*[self.arrays[n].data_ptr() for n in EXPLICIT_FIELDS])
+
+    def zero_(self):
+        for t in self.arrays.values():
+            t.zero_()
+
+
 PARAM_NAMES = ("pos", "feat", "offsets", "offset_scale", "base_scale")
 
 
@@ -208,7 +271,8 @@ class ViewBuffers:
         self._g.count = self.gauss_count.data_ptr()
 
     # ---- stages ----
-    def select(self, scene: DeviceScene, cam: L.Camera, stream=None):
+    def select(self, scene, cam: L.Camera, stream=None):
+        """Eq. 7 selection over a DeviceScene or a DeviceExplicit."""
         L.check(L.lib().octgs_select_lod(ctypes.byref(scene.anchors), ctypes.byref(cam),
                                          _ptr(self.sel_idx), _ptr(self.sel_count),
                                          _ptr(self.sel_ws), self.sel_ws.numel(),
@@ -222,6 +286,35 @@ class ViewBuffers:
         L.check(L.lib().octgs_decode(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
                                      ctypes.byref(cam), _ptr(idx), _ptr(count), int(precision),
                                      ctypes.byref(self._g), stream_handle(stream)), "octgs_decode")
+
+    def decode_explicit(self, ex: "DeviceExplicit", cam: L.Camera, precision: int = L.OCTGS_FP32,
+                        idx: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None,
+                        stream=None):
+        idx = self.sel_idx if idx is None else idx
+        count = self.sel_count if count is None else count
+        L.check(L.lib().octgs_decode_explicit(ctypes.byref(ex.anchors), ctypes.byref(ex._ex),
+                                              ctypes.byref(cam), _ptr(idx), _ptr(count),
+                                              int(precision), ctypes.byref(self._g),
+                                              stream_handle(stream)), "octgs_decode_explicit")
+
+    def render_explicit(self, ex: "DeviceExplicit", cam: L.Camera, params: L.RasterParams,
+                        precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
+        self.select(ex, cam, stream)
+        self.decode_explicit(ex, cam, precision, stream=stream)
+        self.rasterize(cam, params, stream=stream, stage_events=stage_events)
+
+    def decode_explicit_bwd(self, ex: "DeviceExplicit", cam: L.Camera, grads: "ExplicitGrads",
+                            dgauss: Optional[torch.Tensor] = None,
+                            idx: Optional[torch.Tensor] = None,
+                            count: Optional[torch.Tensor] = None, stream=None):
+        dg = self.dgauss if dgauss is None else dgauss
+        idx = self.sel_idx if idx is None else idx
+        count = self.sel_count if count is None else count
+        L.check(L.lib().octgs_decode_explicit_bwd(ctypes.byref(ex.anchors), ctypes.byref(ex._ex),
+                                                  ctypes.byref(cam), _ptr(idx), _ptr(count),
+                                                  _ptr(dg), dg.shape[1], ctypes.byref(grads._g),
+                                                  stream_handle(stream)),
+                "octgs_decode_explicit_bwd")
 
     def rasterize(self, cam: L.Camera, params: L.RasterParams, gauss: Optional[torch.Tensor] = None,
                   count: Optional[torch.Tensor] = None, stream=None, stage_events=None):

@@ -46,6 +46,10 @@ def test_host_only_entry_points():
     # argument validation fails before any device work
     assert lib.octgs_select_lod(None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
     assert lib.octgs_decode(None, None, None, None, None, 0, None, None) == L.OCTGS_EINVAL
+    assert lib.octgs_decode_explicit(None, None, None, None, None, 0, None, None) == L.OCTGS_EINVAL
+    assert lib.octgs_decode_explicit_bwd(None, None, None, None, None, None, 0, None,
+                                         None) == L.OCTGS_EINVAL
+    assert lib.octgs_prepare_explicit(None, None, None, None, None) == L.OCTGS_EINVAL
     assert lib.octgs_strerror(L.OCTGS_ENOSPC) == b"workspace too small"
 
 
@@ -61,6 +65,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(octgs_camera), sizeof(octgs_anchors),
          sizeof(octgs_mlp), sizeof(octgs_gaussians), sizeof(octgs_raster_params),
          sizeof(octgs_raster_stats));
+  printf("%zu %zu\n", sizeof(octgs_explicit), sizeof(octgs_explicit_grads));
   return 0;
 }
 '''
@@ -71,5 +76,5 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(t) for t in (L.Camera, L.Anchors, L.Mlp, L.Gaussians, L.RasterParams,
-                                       L.RasterStats)]
+                                       L.RasterStats, L.Explicit, L.ExplicitGrads)]
     assert got == want

@@ -1,0 +1,259 @@
+"""Parity of the explicit-Gaussian path (3D-GS primitives on the anchors)
+with the FP64 oracle, through the C ABI.
+
+Bars:
+  * thresholds, bound radii and selections bit-exact (canonical FP32);
+  * decoded means bit-exact (a copy); the other fields within the FP32
+    error of their few operations: exp / sigmoid / normalisation within
+    1e-6 relative, the SH colour within 4e-6 (1 + sum |Y_lm c_lm|) (a sum
+    of at most 16 rounded products of a direction with a few ulps of error);
+  * BF16 coefficients: the same bound against the oracle fed the same
+    BF16-rounded coefficients, and within 2^-8 sum |Y c| of the FP32 result;
+  * images within 1e-4 on 99.9 % of pixels (PSNR >= 70 dB), as the neural
+    path (decoded attributes differ by rounding, so a projection decision
+    may flip at a boundary);
+  * gradients within 1e-4 normwise of the oracle's for the same upstream
+    gradient, and within 1e-3 through the whole chain.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import scenes as S
+from tests.gpu_util import psnr, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_17898_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def EX():
+    from oracle import explicit as E
+    return E
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return S.make_config1()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _bf16_round(a):
+    """Round float32 to the nearest BF16 (ties to even), returned as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r << 16).astype(np.uint32).view(np.float32)
+
+
+def _random_explicit(n, k, degree, seed, n_levels=4):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-50, 50, (n, 3)).astype(np.float32)
+    return S.ExplicitScene(
+        pos=pos, level=rng.integers(0, n_levels, n).astype(np.uint8),
+        lod_bias=rng.uniform(-0.5, 0.5, n).astype(np.float32),
+        mean=(pos[:, None, :] + rng.normal(0, 0.7, (n, k, 3))).astype(np.float32),
+        log_scale=rng.uniform(-4, 0, (n, k, 3)).astype(np.float32),
+        rot=rng.standard_normal((n, k, 4)).astype(np.float32),
+        opacity=rng.uniform(-5, 5, (n, k)).astype(np.float32),
+        sh=(0.5 * rng.standard_normal((n, k, (degree + 1) ** 2, 3))).astype(np.float32),
+        sh_degree=degree, d_max=60.0, n_levels=n_levels, k=k, info={})
+
+
+def _decode_gpu(P, ex, idx, cam, prec=None, cap=None):
+    prec = P.OCTGS_FP32 if prec is None else prec
+    de = P.DeviceExplicit.from_scene(ex)
+    cap = len(idx) * ex.k if cap is None else cap
+    vb = P.ViewBuffers(ex.n, ex.k, cam.width, cam.height, 1 << 12, gauss_capacity=max(cap, 1))
+    buf = np.zeros(max(len(idx), 1), np.int32)   # a valid buffer also when the list is empty
+    buf[:len(idx)] = idx
+    idx_t = torch.as_tensor(buf).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    vb.decode_explicit(de, P.make_camera(cam), prec, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    return vb, de
+
+
+def _check_fields(EX, ex, idx, cam, got):
+    ref = EX.decode_explicit(ex, idx, cam)
+    assert np.array_equal(got[0:3], ref[0:3].astype(np.float32))
+    for f in range(3, 11):
+        err = np.abs(got[f] - ref[f])
+        assert np.all(err <= 1e-6 * np.maximum(1.0, np.abs(ref[f]))), (f, err.max())
+    m, k = len(idx), ex.k
+    v = ex.mean[idx].reshape(m * k, 3).astype(np.float64) - cam.C.astype(np.float64)
+    Y = EX.sh_basis(v, ex.sh_degree)
+    mag = np.einsum("sl,slc->cs", np.abs(Y), np.abs(ex.sh[idx].reshape(m * k, -1, 3)))
+    err = np.abs(got[11:14] - ref[11:14])
+    bound = 4e-6 * (1.0 + mag)
+    say(f"  colour max err {err.max():.2e}, max err/bound {(err / bound).max():.3f}")
+    assert np.all(err <= bound)
+    return ref, mag
+
+
+def test_prepare_explicit_bit_exact(P, orc, EX):
+    ex = _random_explicit(20_011, 7, 1, 3)
+    say("prepare explicit", ex.n)
+    de = P.DeviceExplicit.from_scene(ex)
+    torch.cuda.synchronize()
+    thr, rho = EX.thresholds(ex)
+    assert np.array_equal(_np(de.thr2).view(np.uint32), thr.view(np.uint32))
+    assert np.array_equal(_np(de.bound_r).view(np.uint32), rho.view(np.uint32))
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_decode_explicit_fp32(P, EX, c1, degree):
+    ex = S.make_explicit(c1, sh_degree=degree)
+    cam = S.config1_camera()
+    idx = np.arange(1, ex.n, 3, dtype=np.int64)  # ragged: not a multiple of the block
+    say("decode explicit fp32 degree", degree, len(idx))
+    vb, _ = _decode_gpu(P, ex, idx, cam)
+    G = len(idx) * ex.k
+    assert int(vb.gauss_count.item()) == G
+    _check_fields(EX, ex, idx, cam, _np(vb.gauss[:, :G]).astype(np.float64))
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_decode_explicit_bf16(P, EX, c1, degree):
+    ex = S.make_explicit(c1, sh_degree=degree)
+    cam = S.config1_camera()
+    idx = np.arange(0, ex.n, 2, dtype=np.int64)
+    say("decode explicit bf16 degree", degree, len(idx))
+    vb, _ = _decode_gpu(P, ex, idx, cam, prec=P.OCTGS_BF16)
+    G = len(idx) * ex.k
+    got = _np(vb.gauss[:, :G]).astype(np.float64)
+    exb = dataclasses.replace(ex, sh=_bf16_round(ex.sh))
+    _check_fields(EX, exb, idx, cam, got)
+    ref32 = EX.decode_explicit(ex, idx, cam)
+    m, k = len(idx), ex.k
+    v = ex.mean[idx].reshape(m * k, 3).astype(np.float64) - cam.C.astype(np.float64)
+    mag = np.einsum("sl,slc->cs", np.abs(EX.sh_basis(v, degree)),
+                    np.abs(ex.sh[idx].reshape(m * k, -1, 3)))
+    assert np.all(np.abs(got[11:14] - ref32[11:14]) <= 2.0 ** -8 * mag + 4e-6 * (1 + mag))
+
+
+def test_decode_explicit_grid_stride_and_truncation(P, EX):
+    """More slots than one pass of the grid (2048 blocks x 256 slots), and a
+    capacity that truncates the list."""
+    ex = _random_explicit(60_013, 10, 3, 4)
+    cam = S.look_at((0.0, -120.0, 40.0), (0.0, 0.0, 0.0), 320, 200, 60.0)
+    idx = np.arange(ex.n, dtype=np.int64)
+    say("decode explicit large", ex.n * ex.k)
+    vb, _ = _decode_gpu(P, ex, idx, cam)
+    G = ex.n * ex.k
+    assert int(vb.gauss_count.item()) == G
+    got = _np(vb.gauss[:, :G]).astype(np.float64)
+    _check_fields(EX, ex, idx, cam, got)
+    # capacity for 1234 anchors and a bit: only whole anchors are written
+    cap = 1234 * ex.k + 3
+    vb2, _ = _decode_gpu(P, ex, idx, cam, cap=cap)
+    assert int(vb2.gauss_count.item()) == 1234 * ex.k
+    assert np.array_equal(_np(vb2.gauss[:, :1234 * ex.k]), got[:, :1234 * ex.k].astype(np.float32))
+
+
+def test_decode_explicit_zero_count(P, c1):
+    ex = S.make_explicit(c1, sh_degree=3)
+    cam = S.config1_camera()
+    vb, _ = _decode_gpu(P, ex, np.zeros(0, np.int64), cam, cap=100)
+    assert int(vb.gauss_count.item()) == 0
+
+
+def test_decode_explicit_rejects(P, c1):
+    ex = S.make_explicit(c1, sh_degree=2)
+    cam = S.config1_camera()
+    with pytest.raises(P.OctgsError):
+        _decode_gpu(P, ex, np.arange(10), cam, prec=P.OCTGS_BF16)
+
+
+@pytest.mark.parametrize("blend", [False, True])
+def test_end_to_end_explicit_c1(P, orc, EX, c1, blend):
+    ex = S.make_explicit(c1, sh_degree=3)
+    de = P.DeviceExplicit.from_scene(ex)
+    prm = P.raster_params()
+    d = np.array([1.0, -2.0, 1.5]) / np.linalg.norm([1.0, -2.0, 1.5])
+    cams = [S.config1_camera()] + [S.look_at(r * d, (0, 0, 0), 128, 128, 60.0) for r in (12.0, 5.0)]
+    cams.append(S.look_at((2.0, -3.0, 1.0), (0.0, 0.0, 0.0), 97, 61, 70.0))
+    for prec in (P.OCTGS_FP32, P.OCTGS_BF16):
+        for i, cam in enumerate(cams):
+            say("end-to-end explicit", "blend" if blend else "", "bf16" if prec else "fp32", i)
+            vb = P.ViewBuffers(ex.n, ex.k, cam.width, cam.height, 1 << 18)
+            vb.render_explicit(de, P.make_camera(cam, lod_blend=blend), prm, precision=prec)
+            torch.cuda.synchronize()
+            exr = ex if prec == P.OCTGS_FP32 else dataclasses.replace(ex, sh=_bf16_round(ex.sh))
+            ref = EX.render_explicit(exr, cam, orc.params_array(), blend=blend)
+            m = int(vb.sel_count.item())
+            assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
+            img = _np(vb.rgb).astype(np.float64)
+            err = np.abs(img - ref["img"])
+            p = psnr(img, ref["img"])
+            say(f"  {m} anchors, max abs {err.max():.2e} PSNR {p:.1f} dB, "
+                f"pixels > 1e-4: {(err > 1e-4).sum()}")
+            assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_decode_explicit_bwd_parity(P, EX, degree):
+    sc, cam = S.make_gradcheck_scene()
+    ex = S.make_explicit(sc, sh_degree=degree, seed=12)
+    idx = np.array([0, 3, 4, 9, 17, 18, 30, 49], dtype=np.int64)
+    G = len(idx) * ex.k
+    cap = G + 37
+    rng = np.random.default_rng(degree)
+    dg = np.zeros((14, cap), np.float32)
+    dg[:, :G] = rng.standard_normal((14, G))
+    say("explicit bwd degree", degree)
+    vb, de = _decode_gpu(P, ex, idx, cam, cap=cap)
+    grads = P.ExplicitGrads(de)
+    # accumulation: gradients start from a known non-zero value
+    for t in grads.arrays.values():
+        t.fill_(0.25)
+    dgt = torch.as_tensor(dg).cuda()
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    vb.decode_explicit_bwd(de, P.make_camera(cam), grads, dgauss=dgt, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    ref = EX.decode_explicit_backward(ex, idx, cam, dg.astype(np.float64))
+    for name in ("mean", "log_scale", "rot", "opacity", "sh"):
+        got = _np(grads.arrays[name]).astype(np.float64) - 0.25
+        r = ref[name].reshape(got.shape)
+        e = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-30)
+        say(f"  {name}: rel err {e:.2e}")
+        assert e <= 1e-4, name
+        assert np.abs(got - r).max() <= 1e-3 * np.abs(r).max() + 1e-7, name
+
+
+def test_explicit_full_chain_gradient(P, orc, EX):
+    sc, cam = S.make_gradcheck_scene()
+    ex = S.make_explicit(sc, sh_degree=3, seed=12)
+    de = P.DeviceExplicit.from_scene(ex)
+    prm = P.raster_params()
+    vb = P.ViewBuffers(ex.n, ex.k, cam.width, cam.height, 1 << 16)
+    c = P.make_camera(cam)
+    vb.render_explicit(de, c, prm)
+    rng = np.random.default_rng(4)
+    dimg = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+    vb.rasterize_bwd(c, prm, torch.as_tensor(dimg).cuda())
+    grads = P.ExplicitGrads(de)
+    vb.decode_explicit_bwd(de, c, grads)
+    torch.cuda.synchronize()
+    ref = EX.render_explicit_backward(ex, cam, orc.params_array(), dimg.astype(np.float64))
+    for name in ("mean", "log_scale", "rot", "opacity", "sh"):
+        got = _np(grads.arrays[name]).astype(np.float64)
+        r = ref[name].reshape(got.shape)
+        e = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-30)
+        say(f"  chain {name}: rel err {e:.2e}")
+        assert e <= 1e-3, name
