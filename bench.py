@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="skip the PSNR sweep (profiling runs)")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step timing")
     ap.add_argument("--no-skip", action="store_true", help="skip the learned-skip path")
+    ap.add_argument("--no-3dgs", action="store_true",
+                    help="skip the explicit-Gaussian (3D-GS instance) measurement")
     ap.add_argument("--skip-train-views", type=int, default=1000)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -152,9 +154,10 @@ def main():
     log(f"sizing: max selected {max_sel}, max candidate pairs {max_pairs}; gcap {gcap}, "
         f"pcap {pcap}; {D} frames in flight")
 
-    def timed_views(render_one, depth, views=None):
+    def timed_views(render_one, depth, views=None, bufs=None):
         """ms for args.steps views (after args.warmup), view i on stream i % depth."""
         views = ccams if views is None else views
+        bufs = vbs if bufs is None else bufs
 
         def run(n):
             for i in range(n):
@@ -175,7 +178,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_wall
-        for b in vbs[:depth]:
+        for b in bufs[:depth]:
             st = b.stats()
             if st["pair_overflow"] or st["sync_error"]:
                 raise SystemExit(f"timed run flagged: {st}")
@@ -198,6 +201,13 @@ def main():
     blend = {"fps_bf16": round(args.steps / (msb / 1e3), 2), "ms_per_view": round(msb / args.steps, 4),
              "mean_selected": round(blend_sel), "mean_pairs": round(blend_pairs)}
     log(f"LOD transition blending, BF16: {blend}")
+
+    # ---- Our-3D-GS: explicit Gaussians with SH colour on the same anchors ----
+    our3d = None
+    if not args.no_3dgs:
+        our3d = explicit_path(args, P, S, torch, np, sc, ccams, prm, W, H, D, streams,
+                              timed_views)
+        torch.cuda.empty_cache()
 
     # ---- learned anchor skip: trained on logged blend weights of random views ----
     skip = None
@@ -334,6 +344,7 @@ def main():
                                    if psnrs and any(math.isfinite(p) for p in psnrs) else None)),
         "psnr_bf16_no_skip_min_db": round(min(psnrs), 2) if psnrs else None,
         "skip": skip,
+        "our_3dgs": our3d,
         "wall_s_timed": round(wall16, 3),
         "train_step_ms": train["ms_per_step"] if train else None,
         "train": train,
@@ -341,6 +352,78 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# per decoded explicit Gaussian: mean, log-scale, rotation and opacity
+# logit read (44 B), the SH row (48 values, FP32 or BF16), the 56-byte
+# record written, and the anchor index (4 B per k slots)
+EXPLICIT_IO_BYTES = 44 + 56
+
+
+def explicit_path(args, P, S, torch, np, sc, ccams, prm, W, H, D, streams, timed_views):
+    """FPS of the 3D-GS instance (explicit degree-3 Gaussians on the config
+    anchors) with FP32 and BF16 SH coefficients, and the decode kernel's
+    achieved HBM rate."""
+    from paper_2403_17898_amd.hip_events import HipEvent
+    t0 = time.time()
+    ex = S.make_explicit(sc, sh_degree=3)
+    de = P.DeviceExplicit.from_scene(ex)
+    del ex
+    log(f"explicit scene: degree-3 SH, generated and uploaded in {time.time() - t0:.1f}s")
+    vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=64 << 20)
+    max_sel = max_pairs = 0
+    for c in ccams:
+        vb.render_explicit(de, c, prm)
+        st = vb.stats()
+        if st["pair_overflow"] or st["sync_error"]:
+            raise SystemExit(f"explicit sizing pass failed: {st}")
+        max_sel = max(max_sel, st["n_selected"])
+        max_pairs = max(max_pairs, st["n_candidates"])
+    del vb
+    torch.cuda.empty_cache()
+    gcap = max(1, int(max_sel * sc.k * 1.05) + 1024)
+    pcap = max(1, int(max_pairs * 1.10) + 4096)
+    xvbs = [P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=pcap, gauss_capacity=gcap)
+            for _ in range(D)]
+    res = {"sh_degree": 3}
+    for name, prec in (("fp32", P.OCTGS_FP32), ("bf16", P.OCTGS_BF16)):
+        ms, _ = timed_views(lambda k, c, s: xvbs[k].render_explicit(de, c, prm, precision=prec,
+                                                                   stream=s),
+                            D, bufs=xvbs)
+        res["fps_" + name] = round(args.steps / (ms / 1e3), 2)
+        res["ms_per_view_" + name] = round(ms / args.steps, 4)
+    # decode kernel time per launch (HIP events on the library stream)
+    vb = xvbs[0]
+    sh = P.stream_handle(streams[0])
+    ev = [HipEvent() for _ in range(2)]
+    nviews = min(args.steps, len(ccams))
+    for name, prec, sh_bytes in (("fp32", P.OCTGS_FP32, 192), ("bf16", P.OCTGS_BF16, 96)):
+        t_dec = 0.0
+        slots = sel = pairs = 0
+        for i in range(nviews):
+            c = ccams[i]
+            vb.select(de, c)
+            ev[0].record(sh)
+            vb.decode_explicit(de, c, prec)
+            ev[1].record(sh)
+            vb.rasterize(c, prm)
+            torch.cuda.synchronize()
+            t_dec += ev[0].elapsed_ms(ev[1])
+            st = vb.stats()
+            slots += st["n_slots"]
+            sel += st["n_selected"]
+            pairs += st["n_pairs"]
+        ms = t_dec / nviews
+        b = (slots / nviews) * (EXPLICIT_IO_BYTES + sh_bytes + 4.0 / sc.k)
+        res["decode_ms_" + name] = round(ms, 4)
+        res["decode_gbs_" + name] = round(b / (ms * 1e-3) / 1e9, 1)
+        res["decode_hbm_frac_" + name] = round(b / (ms * 1e-3) / 8e12, 4)
+        res["mean_selected"] = round(sel / nviews)
+        res["mean_gaussians"] = round(slots / nviews)
+        res["mean_pairs"] = round(pairs / nviews)
+    log(f"Our-3D-GS (explicit, SH degree 3): {res}")
+    del xvbs, vb, de
+    return res
 
 
 def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None):

@@ -615,13 +615,13 @@ def make_explicit(sc: Scene, sh_degree: int = 3, seed: int = 11,
             + sc.offsets.astype(np.float64) * sc.offset_scale[:, None, :]).astype(np.float32)
     u = rng.uniform(0.2, 0.8, (n, k, 3))
     log_scale = (np.log(sc.base_scale.astype(np.float64))[:, None, :] + np.log(u)).astype(np.float32)
-    rot = rng.standard_normal((n, k, 4)).astype(np.float32)
+    rot = rng.standard_normal((n, k, 4), dtype=np.float32)
     opacity = rng.uniform(opacity_logit[0], opacity_logit[1], (n, k)).astype(np.float32)
     sh = np.empty((n, k, nc, 3), np.float32)
-    sh[:, :, 0, :] = dc_sigma * rng.standard_normal((n, k, 3))
+    sh[:, :, 0, :] = dc_sigma * rng.standard_normal((n, k, 3), dtype=np.float32)
     for l in range(1, sh_degree + 1):
-        sh[:, :, l * l:(l + 1) * (l + 1), :] = (rest_sigma / l) * rng.standard_normal(
-            (n, k, 2 * l + 1, 3))
+        sh[:, :, l * l:(l + 1) * (l + 1), :] = np.float32(rest_sigma / l) * rng.standard_normal(
+            (n, k, 2 * l + 1, 3), dtype=np.float32)
     return ExplicitScene(pos=sc.pos, level=sc.level, lod_bias=sc.lod_bias, mean=mean,
                          log_scale=log_scale, rot=rot, opacity=opacity, sh=sh,
                          sh_degree=sh_degree, d_max=sc.d_max, n_levels=sc.n_levels, k=k,
