@@ -263,6 +263,37 @@ OCTGS_API int octgs_decode_bwd(const octgs_anchors *a, const octgs_mlp *mlp,
 OCTGS_API int octgs_l1_loss_grad(const float *img, const float *target, int64_t n, float scale,
                                  float *dimg, float *loss, octgs_stream stream);
 
+/* Workspace bytes of octgs_photometric_loss_grad for n_images planes of
+ * height x width. */
+OCTGS_API size_t octgs_photometric_workspace_bytes(int64_t n_images, int32_t height,
+                                                   int32_t width);
+
+/* Photometric training loss of the 3D-GS model (Sec. V, implementation
+ * details: L1 and SSIM weighted 0.8 and 0.2):
+ *   *loss += w_l1 mean|img - target| + w_ssim (1 - mean SSIM(img, target)),
+ * and dimg (overwritten) = its gradient with respect to img.  img, target,
+ * dimg: device, n_images planes of [height][width] FP32 (views x 3 colour
+ * channels, each plane an image of its own).  SSIM is the standard form of
+ * Wang et al. (2004): 11 x 11 Gaussian window with sigma 1.5, C1 = 0.01^2,
+ * C2 = 0.03^2 (data range 1), windowed statistics over a zero-padded
+ * same-size correlation, averaged over every pixel of every plane.  With
+ * w_ssim = 0 the call is the L1 term alone and needs no workspace.  ws:
+ * device, >= octgs_photometric_workspace_bytes (three derivative maps).
+ * n_images <= 65535. */
+OCTGS_API int octgs_photometric_loss_grad(const float *img, const float *target,
+                                          int64_t n_images, int32_t height, int32_t width,
+                                          float w_l1, float w_ssim, float *dimg, float *loss,
+                                          void *ws, size_t ws_bytes, octgs_stream stream);
+
+/* Volume regularisation of the Scaffold-GS model (Sec. V, implementation
+ * details: L_vol = sum_i Prod(s_i), weight 0.01): over the first
+ * min(*g->count, g->capacity) decoded slots with opacity > 0 (those the
+ * rasterizer draws), *loss += weight * sum s_x s_y s_z, and the scale rows
+ * (fields 3..5) of d_gauss (planar [14][g->capacity], device) receive
+ * += weight * the product of the other two scales. */
+OCTGS_API int octgs_volume_loss_grad(const octgs_gaussians *g, float weight, float *d_gauss,
+                                     float *loss, octgs_stream stream);
+
 /* One Adam update of n parameters (bias-corrected, step >= 1):
  * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */

@@ -101,6 +101,10 @@ SIGNATURES = [
                                 ctypes.POINTER(AnchorGrads), ctypes.POINTER(MlpGrads), _p,
                                 ctypes.c_size_t, _p]),
     ("octgs_l1_loss_grad", _i32, [_p, _p, _i64, _f, _p, _p, _p]),
+    ("octgs_photometric_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32]),
+    ("octgs_photometric_loss_grad", _i32, [_p, _p, _i64, _i32, _i32, _f, _f, _p, _p, _p,
+                                           ctypes.c_size_t, _p]),
+    ("octgs_volume_loss_grad", _i32, [ctypes.POINTER(Gaussians), _f, _p, _p, _p]),
     ("octgs_adam_step", _i32, [_p, _p, _p, _p, _i64, _f, _f, _f, _f, _i32, _p]),
     ("octgs_anchor_weights", _i32, [_p, _p, _i32, _i64, _p, _p]),
     ("octgs_skip_features", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _i64,

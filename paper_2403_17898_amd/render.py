@@ -233,6 +233,26 @@ def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, scale: float, dimg: to
             "octgs_l1_loss_grad")
 
 
+def photometric_loss_grad(img: torch.Tensor, target: torch.Tensor, dimg: torch.Tensor,
+                          loss: torch.Tensor, w_l1: float = 0.8, w_ssim: float = 0.2,
+                          ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """w_l1 L1 + w_ssim (1 - SSIM) over images [..., H, W] (each leading
+    index one plane); dimg receives the gradient, loss (device scalar) is
+    incremented.  Returns the workspace used (pass it back to reuse it)."""
+    H, W = int(img.shape[-2]), int(img.shape[-1])
+    planes = img.numel() // max(1, H * W)
+    need = L.lib().octgs_photometric_workspace_bytes(planes, H, W)
+    if w_ssim != 0.0 and (ws is None or ws.numel() < need):
+        ws = torch.empty(need, dtype=torch.uint8, device=img.device)
+    L.check(L.lib().octgs_photometric_loss_grad(_ptr(img), _ptr(target), planes, H, W,
+                                                float(w_l1), float(w_ssim), _ptr(dimg),
+                                                _ptr(loss), _ptr(ws),
+                                                0 if ws is None else ws.numel(),
+                                                stream_handle(stream)),
+            "octgs_photometric_loss_grad")
+    return ws
+
+
 def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
               lr: float, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
     L.check(L.lib().octgs_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
@@ -337,6 +357,13 @@ class ViewBuffers:
         self.select(scene, cam, stream)
         self.decode(scene, cam, precision, stream=stream)
         self.rasterize(cam, params, stream=stream, stage_events=stage_events)
+
+    def volume_loss_grad(self, weight: float, loss: torch.Tensor, stream=None):
+        """Adds weight * sum Prod(s) over the decoded, rendered slots to loss and
+        its gradient to self.dgauss (after rasterize_bwd)."""
+        L.check(L.lib().octgs_volume_loss_grad(ctypes.byref(self._g), float(weight),
+                                               _ptr(self.dgauss), _ptr(loss),
+                                               stream_handle(stream)), "octgs_volume_loss_grad")
 
     def rasterize_bwd(self, cam: L.Camera, params: L.RasterParams, dimg: torch.Tensor,
                       stream=None):
