@@ -540,15 +540,25 @@ def train_step_timing(args, P, S, torch, np):
     dimg = torch.empty(3, H, W, device=params[0].device)
     loss = torch.zeros(1, device=params[0].device)
     scale = 1.0 / (len(cams) * 3 * H * W)
-    state = {"step": 0}
+    state = {"step": 0, "ws": None}
+    nv = len(cams)
 
-    def step(timer=None):
+    def step(timer=None, full=False):
+        """full: the paper's loss for the Scaffold-GS model, 0.8 L1 +
+        0.2 (1 - SSIM) averaged over the views, plus 0.01 sum Prod(s) over
+        each view's rendered Gaussians; otherwise mean L1."""
         grads.zero_()
         loss.zero_()
         for c, tg in zip(cams, targets):
             vb.render(ds, c, prm)
-            P.l1_loss_grad(vb.rgb, tg, scale, dimg, loss)
+            if full:
+                state["ws"] = P.photometric_loss_grad(vb.rgb, tg, dimg, loss, 0.8 / nv, 0.2 / nv,
+                                                      state["ws"])
+            else:
+                P.l1_loss_grad(vb.rgb, tg, scale, dimg, loss)
             vb.rasterize_bwd(c, prm, dimg)
+            if full:
+                vb.volume_loss_grad(0.01, loss)
             vb.decode_bwd(ds, c, grads)
         if timer is not None:
             timer.record()
@@ -556,25 +566,32 @@ def train_step_timing(args, P, S, torch, np):
         for p_, g_, (m_, v_) in zip(params, gtens, mom):
             P.adam_step(p_, g_, m_, v_, 1e-3, state["step"])
 
-    for _ in range(3):
-        step()
-    torch.cuda.synchronize()
-    first_loss = loss.item()
-    n = args.train_steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-    for i in range(n):
-        ev[i][0].record()
-        step(ev[i][1])
-        ev[i][2].record()
-    torch.cuda.synchronize()
-    tot = sorted(a.elapsed_time(c) for a, b, c in ev)
-    adam = sorted(b.elapsed_time(c) for a, b, c in ev)
-    ms = tot[len(tot) // 2]
+    def timed_steps(full):
+        for _ in range(3):
+            step(full=full)
+        torch.cuda.synchronize()
+        first = loss.item()
+        n = args.train_steps
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for i in range(n):
+            ev[i][0].record()
+            step(ev[i][1], full)
+            ev[i][2].record()
+        torch.cuda.synchronize()
+        tot = sorted(a.elapsed_time(c) for a, b, c in ev)
+        adam = sorted(b.elapsed_time(c) for a, b, c in ev)
+        return tot[len(tot) // 2], adam[len(adam) // 2], first, loss.item()
+
+    ms, adam_ms, first_loss, last_loss = timed_steps(False)
     res = {"workload": "500k anchors / 6 levels, 4 views at 1600x1066, mean-L1, Adam",
-           "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam[len(adam) // 2], 3),
-           "steps_timed": n, "loss_first": round(first_loss, 6), "loss_last": round(loss.item(), 6),
-           "max_selected": max_sel, "max_pairs": max_pairs}
+           "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam_ms, 3),
+           "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
+           "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs}
+    msf, _, ff, fl = timed_steps(True)
+    res["full_loss"] = {"loss": "0.8 L1 + 0.2 (1 - SSIM) + 0.01 sum Prod(s)",
+                        "ms_per_step": round(msf, 3), "loss_first": round(ff, 6),
+                        "loss_last": round(fl, 6)}
     log(f"train step: {res}")
     return res
 
