@@ -415,6 +415,64 @@ OCTGS_API int octgs_decode_explicit_bwd(const octgs_anchors *a, const octgs_expl
                                         int64_t gauss_capacity, const octgs_explicit_grads *g,
                                         octgs_stream stream);
 
+/* ---- densification statistics (Sec. IV-B, adaptive anchor control) ----
+ * Accumulated over the training views of an interval of T iterations, then
+ * turned into growth, LOD-bias and pruning decisions.  Arrays are device
+ * memory indexed by anchor j or Gaussian g = j * k + i; the caller zeroes
+ * them at the start of an interval. */
+typedef struct {
+  float *grad_sum;       /* [n][k] sum over views of |dL/d(projected centre)|, NDC units */
+  uint32_t *grad_count;  /* [n][k] views in which the Gaussian was rasterized */
+  float *opacity_sum;    /* [n] sum over selecting views of sum_i max(opacity_i, 0) */
+  uint32_t *view_count;  /* [n] views that selected the anchor */
+} octgs_densify_stats;
+
+/* Thresholds of the decisions: tau_g and beta of the level threshold
+ * tau_g 2^(beta L) (paper defaults 0.0002 and 0.2), the LOD-bias step
+ * epsilon (0.01), the minimum average opacity tau_opacity, the minimum view
+ * frequency tau_v (0.7, 0.01 or 0.2 by dataset in the paper), and the number
+ * of training views the statistics cover. */
+typedef struct {
+  float tau_g, beta, epsilon, tau_opacity, tau_v;
+  int32_t n_views;
+} octgs_densify_params;
+
+/* Statistics of one training view, after its octgs_rasterize_bwd (g, cam,
+ * pair_capacity and raster_ws as in that call, unchanged since; g decoded
+ * from the anchors idx / count with k Gaussians each): every slot the view
+ * rasterized (survived the projection culls) adds the norm of its
+ * projected-centre gradient in normalised device coordinates (the pixel
+ * gradient scaled by (W/2, H/2)) to grad_sum and 1 to grad_count of its
+ * Gaussian; every listed anchor adds the sum of its Gaussians' opacities
+ * (negative taken as 0) to opacity_sum and 1 to view_count.  Each anchor at
+ * most once per call. */
+OCTGS_API int octgs_densify_accumulate(const octgs_gaussians *g, const octgs_camera *cam,
+                                       int64_t pair_capacity, const void *raster_ws,
+                                       size_t ws_bytes, const uint32_t *idx,
+                                       const uint32_t *count, int32_t k,
+                                       const octgs_densify_stats *st, octgs_stream stream);
+
+/* Decisions of an interval, in FP32 with the level thresholds
+ * tau_L = tau_g 2^(beta L) rounded once from double:
+ *  - grow_level[g] (device [n][k]): -1, or the level of the new anchor the
+ *    Gaussian seeds: with grad = grad_sum / grad_count (0 if never
+ *    rasterized) and L its anchor's level, L if grad > tau_L, L + 1 if also
+ *    grad > tau_(L+1) and L + 1 < K ("next-level growing", Sec. IV-B);
+ *  - lod_bias[j] (device, in/out) += epsilon where the mean grad of the
+ *    anchor's rasterized Gaussians exceeds tau_L / 4;
+ *  - prune[j] (device [n]) = 1 if view_count / n_views < tau_v, or if the
+ *    anchor was selected and opacity_sum / (k view_count) < tau_opacity;
+ *  - counts (device [4], overwritten): Gaussians that grow, of them
+ *    promoted, bias updates, pruned anchors.
+ * Reads a->n, k, n_levels (<= 64), level.  Thresholds of Eq. 7 depend on
+ * lod_bias: run octgs_prepare_anchors again after the update.  Placing the
+ * grown anchors (empty-voxel test) and removing the pruned ones are left to
+ * the caller. */
+OCTGS_API int octgs_densify_decide(const octgs_anchors *a, const octgs_densify_stats *st,
+                                   const octgs_densify_params *p, float *lod_bias,
+                                   int8_t *grow_level, uint8_t *prune, uint32_t *counts,
+                                   octgs_stream stream);
+
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:
  * the stats header, the sorted pair list (tile id and slot per entry, length

@@ -36,8 +36,10 @@ F32 = np.float32
 
 
 def level_thresholds(tau_g: float, beta: float, n_levels: int) -> np.ndarray:
-    """tau_g 2^(beta L) for L = 0..K, each rounded once to FP32."""
-    return np.array([tau_g * 2.0 ** (beta * L) for L in range(n_levels + 1)], np.float64).astype(F32)
+    """tau_g 2^(beta L) for L = 0..K from the FP32 values of tau_g and beta,
+    evaluated in double and rounded once to FP32."""
+    t, b = float(F32(tau_g)), float(F32(beta))
+    return np.array([t * np.exp2(b * L) for L in range(n_levels + 1)], np.float64).astype(F32)
 
 
 def accumulate(stats, gidx, visible, dmean2d_px, width, height, anchor_idx, opacity, k):

@@ -73,6 +73,15 @@ class ExplicitGrads(ctypes.Structure):
     _fields_ = [("mean", _p), ("log_scale", _p), ("rot", _p), ("opacity", _p), ("sh", _p)]
 
 
+class DensifyStats(ctypes.Structure):
+    _fields_ = [("grad_sum", _p), ("grad_count", _p), ("opacity_sum", _p), ("view_count", _p)]
+
+
+class DensifyParams(ctypes.Structure):
+    _fields_ = [("tau_g", _f), ("beta", _f), ("epsilon", _f), ("tau_opacity", _f), ("tau_v", _f),
+                ("n_views", _i32)]
+
+
 class RasterStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_visible", ctypes.c_uint32),
                 ("n_pairs", ctypes.c_uint32), ("pair_overflow", ctypes.c_uint32),
@@ -124,6 +133,11 @@ SIGNATURES = [
     ("octgs_decode_explicit_bwd", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit),
                                          ctypes.POINTER(Camera), _p, _p, _p, _i64,
                                          ctypes.POINTER(ExplicitGrads), _p]),
+    ("octgs_densify_accumulate", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), _i64,
+                                        _p, ctypes.c_size_t, _p, _p, _i32,
+                                        ctypes.POINTER(DensifyStats), _p]),
+    ("octgs_densify_decide", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(DensifyStats),
+                                    ctypes.POINTER(DensifyParams), _p, _p, _p, _p, _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

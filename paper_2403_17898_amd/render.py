@@ -199,6 +199,50 @@ class ExplicitGrads:
             t.zero_()
 
 
+class DensifyStats:
+    """Device statistics of one densification interval (Sec. IV-B) for n
+    anchors of k Gaussians, and the decision outputs."""
+
+    def __init__(self, n: int, k: int):
+        dev = _dev()
+        self.n, self.k = int(n), int(k)
+        self.grad_sum = torch.zeros(max(1, n * k), dtype=torch.float32, device=dev)
+        self.grad_count = torch.zeros(max(1, n * k), dtype=torch.int32, device=dev)
+        self.opacity_sum = torch.zeros(max(1, n), dtype=torch.float32, device=dev)
+        self.view_count = torch.zeros(max(1, n), dtype=torch.int32, device=dev)
+        self.grow_level = torch.empty(max(1, n * k), dtype=torch.int8, device=dev)
+        self.prune = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+        self.counts = torch.zeros(4, dtype=torch.int32, device=dev)
+        self._st = L.DensifyStats(self.grad_sum.data_ptr(), self.grad_count.data_ptr(),
+                                  self.opacity_sum.data_ptr(), self.view_count.data_ptr())
+
+    def zero_(self):
+        for t in (self.grad_sum, self.grad_count, self.opacity_sum, self.view_count):
+            t.zero_()
+
+    def accumulate(self, vb: "ViewBuffers", cam: L.Camera, idx: Optional[torch.Tensor] = None,
+                   count: Optional[torch.Tensor] = None, stream=None):
+        """Add the view last rendered and back-propagated with vb."""
+        idx = vb.sel_idx if idx is None else idx
+        count = vb.sel_count if count is None else count
+        L.check(L.lib().octgs_densify_accumulate(ctypes.byref(vb._g), ctypes.byref(cam), vb.pcap,
+                                                 _ptr(vb.ras_ws), vb.ras_ws.numel(), _ptr(idx),
+                                                 _ptr(count), self.k, ctypes.byref(self._st),
+                                                 stream_handle(stream)),
+                "octgs_densify_accumulate")
+
+    def decide(self, scene, n_views: int, tau_g=2e-4, beta=0.2, epsilon=0.01,
+               tau_opacity=0.005, tau_v=0.01, stream=None):
+        """Growth levels, pruning mask and counts; updates scene.lod_bias in
+        place (rerun the scene's threshold preparation afterwards)."""
+        p = L.DensifyParams(tau_g, beta, epsilon, tau_opacity, tau_v, int(n_views))
+        L.check(L.lib().octgs_densify_decide(ctypes.byref(scene.anchors), ctypes.byref(self._st),
+                                             ctypes.byref(p), _ptr(scene.lod_bias),
+                                             _ptr(self.grow_level), _ptr(self.prune),
+                                             _ptr(self.counts), stream_handle(stream)),
+                "octgs_densify_decide")
+
+
 PARAM_NAMES = ("pos", "feat", "offsets", "offset_scale", "base_scale")
 
 

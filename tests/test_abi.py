@@ -65,7 +65,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(octgs_camera), sizeof(octgs_anchors),
          sizeof(octgs_mlp), sizeof(octgs_gaussians), sizeof(octgs_raster_params),
          sizeof(octgs_raster_stats));
-  printf("%zu %zu\n", sizeof(octgs_explicit), sizeof(octgs_explicit_grads));
+  printf("%zu %zu %zu %zu\n", sizeof(octgs_explicit), sizeof(octgs_explicit_grads),
+         sizeof(octgs_densify_stats), sizeof(octgs_densify_params));
   return 0;
 }
 '''
@@ -76,5 +77,6 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(t) for t in (L.Camera, L.Anchors, L.Mlp, L.Gaussians, L.RasterParams,
-                                       L.RasterStats, L.Explicit, L.ExplicitGrads)]
+                                       L.RasterStats, L.Explicit, L.ExplicitGrads,
+                                       L.DensifyStats, L.DensifyParams)]
     assert got == want

@@ -21,7 +21,7 @@ def test_level_thresholds(DO):
     assert thr[0] == F32(2e-4)
     assert thr[5] == F32(4e-4)          # 2^(0.2 * 5) = 2
     assert np.all(np.diff(thr) > 0)     # growing to finer levels gets harder
-    np.testing.assert_allclose(thr, 2e-4 * 2.0 ** (0.2 * np.arange(9)), rtol=6e-8)
+    np.testing.assert_allclose(thr, 2e-4 * 2.0 ** (0.2 * np.arange(9)), rtol=2e-7)
 
 
 def _one(DO, level, grads, counts=None, K=4, bias=0.0, vc=5, opsum=None, n_views=10, **kw):
