@@ -542,6 +542,7 @@ def train_step_timing(args, P, S, torch, np):
     scale = 1.0 / (len(cams) * 3 * H * W)
     state = {"step": 0, "ws": None}
     nv = len(cams)
+    dstats = P.DensifyStats(sc.n, sc.k)
 
     def step(timer=None, full=False):
         """full: the paper's loss for the Scaffold-GS model, 0.8 L1 +
@@ -559,6 +560,7 @@ def train_step_timing(args, P, S, torch, np):
             vb.rasterize_bwd(c, prm, dimg)
             if full:
                 vb.volume_loss_grad(0.01, loss)
+                dstats.accumulate(vb, c)
             vb.decode_bwd(ds, c, grads)
         if timer is not None:
             timer.record()
@@ -589,9 +591,19 @@ def train_step_timing(args, P, S, torch, np):
            "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
            "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs}
     msf, _, ff, fl = timed_steps(True)
-    res["full_loss"] = {"loss": "0.8 L1 + 0.2 (1 - SSIM) + 0.01 sum Prod(s)",
+    # densification decisions of the interval (every T = 100 iterations)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dstats.decide(ds, max(1, state["step"] * nv))
+    e1.record()
+    torch.cuda.synchronize()
+    res["full_loss"] = {"loss": "0.8 L1 + 0.2 (1 - SSIM) + 0.01 sum Prod(s), with the "
+                                "densification statistics accumulated per view",
                         "ms_per_step": round(msf, 3), "loss_first": round(ff, 6),
-                        "loss_last": round(fl, 6)}
+                        "loss_last": round(fl, 6),
+                        "densify_decide_ms": round(e0.elapsed_time(e1) / 5, 4),
+                        "densify_counts": dstats.counts.cpu().numpy().tolist()}
     log(f"train step: {res}")
     return res
 
