@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200, help="views timed per path")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--views", type=int, default=200, help="trajectory length")
-    ap.add_argument("--inflight", type=int, default=3,
+    ap.add_argument("--inflight", type=int, default=4,
                     help="views in flight at once (one stream and buffer set each)")
     ap.add_argument("--cpu-views", type=int, default=60, help="views the CPU oracle renders")
     ap.add_argument("--no-cpu-baseline", action="store_true")

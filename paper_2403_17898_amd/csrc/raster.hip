@@ -580,20 +580,30 @@ struct CompArgs {
   float *gauss_w;
 };
 
-// One 16x16 tile per block of 128 threads; each thread owns two vertically
-// adjacent pixels of one column, so the column's dx terms are shared.
-// Batches of 256 list entries are staged in LDS as three float4 per
-// Gaussian.  Per pixel and entry (the backward pass repeats this sequence):
-//   dx = x - mx; dy = y - my
-//   p = fma(C' dy, dy, fma(B' dx, dy, fma(A' dx, dx, log2 op)))
+// One 16x16 tile per block of one wave (64 threads); each thread owns four
+// vertically adjacent pixels of one column, so the Gaussian's column terms
+// are shared four ways.  Batches of kFwdBatch list entries are staged in LDS
+// as three float4 per Gaussian.  Per entry the exponent of the first pixel
+// is evaluated directly and the next three by finite differences of the
+// quadratic in dy (exact in real arithmetic; in FP32 within a few ulps of
+// |p|):
+//   dx = x - mx; dy = y0 - my
+//   p0 = fma(C' dy, dy, fma(B' dx, dy, fma(A' dx, dx, log2 op)))
+//   d0 = p(dy + 1) - p(dy) = fma(C', 2 dy + 1, B' dx);  d(k+1) = d(k) + 2 C'
+//   p(k+1) = p(k) + d(k)
 //   a = min(alpha_max, exp2(p)) = min(alpha_max, op G')
-// The loop is branch-free (lanes that are done blend alpha 0), so a wave
-// only branches on wave-uniform conditions.
+// The loop is branch-free (lanes that are done blend alpha 0), so the wave
+// only branches on wave-uniform conditions; the tile stops when all of its
+// pixels have.
+constexpr int kFwdThreads = 64;   // forward composite: one wave per tile, 4 pixels per thread
+constexpr int kFwdBatch = 128;    // list entries staged in LDS per batch
+constexpr int kPx = 4;
+
 template <bool LOG>
 struct CompLds {
-  float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
-  uint32_t s_slot[LOG ? kCompBatch : 1];
-  float s_w[LOG ? kCompBatch : 1];
+  float4 sA[kFwdBatch], sB[kFwdBatch], sC[kFwdBatch];
+  uint32_t s_slot[LOG ? kFwdBatch : 1];
+  float s_w[LOG ? kFwdBatch : 1];
 };
 
 // The LDS lives in the kernel and is passed in, so the two AMIN
@@ -607,34 +617,41 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x;
-  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + 2 * (t / kTile), py1 = py0 + 1;
-  const bool in0 = px < a.W && py0 < a.H, in1 = px < a.W && py1 < a.H;
-  const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = fy0 + 1.0f;
+  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kPx * (t / kTile);
+  bool in[kPx];
+#pragma unroll
+  for (int k = 0; k < kPx; ++k) in[k] = px < a.W && py0 + k < a.H;
+  const float fx = (float)px + 0.5f, fy = (float)py0 + 0.5f;
   const uint32_t start = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile + 1]);
   const uint32_t *vals = a.ws.tval[a.buf];
   const float4 *proj = a.ws.proj;
   const float amax = a.alpha_max, amin = a.alpha_min, tmin = a.t_min;
-  float T0 = in0 ? 1.0f : 0.0f, T1 = in1 ? 1.0f : 0.0f;
-  float r0 = 0.0f, g0 = 0.0f, b0c = 0.0f, r1 = 0.0f, g1 = 0.0f, b1c = 0.0f;
-  uint32_t last0 = end - start, last1 = end - start;
-  bool done0 = !in0, done1 = !in1;
-  for (uint32_t b0 = start; b0 < end; b0 += kCompBatch) {
+  float T[kPx], cr[kPx], cg[kPx], cb[kPx];
+  uint32_t last[kPx];
+  bool done[kPx];
 #pragma unroll
-    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
-      const int i = t + q * kCompThreads;
-      const uint32_t e = b0 + i;
-      if (e < end) {
-        const uint32_t s = vals[e];
-        if (LOG) s_slot[i] = s;
-        sA[i] = proj[3 * (size_t)s];
-        sB[i] = proj[3 * (size_t)s + 1];
-        sC[i] = proj[3 * (size_t)s + 2];
-      }
-      if (LOG) s_w[i] = 0.0f;
+  for (int k = 0; k < kPx; ++k) {
+    T[k] = in[k] ? 1.0f : 0.0f;
+    cr[k] = 0.0f; cg[k] = 0.0f; cb[k] = 0.0f;
+    last[k] = end - start;
+    done[k] = !in[k];
+  }
+  for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
+    // one wave: the barrier only orders LDS reuse across batches
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFwdBatch / kFwdThreads; ++q) {
+      const int i = t + q * kFwdThreads;
+      const uint32_t e = min(b0 + i, end - 1u);
+      const uint32_t s = vals[e];
+      if (LOG) s_slot[i] = s;
+      sA[i] = proj[3 * (size_t)s];
+      sB[i] = proj[3 * (size_t)s + 1];
+      sC[i] = proj[3 * (size_t)s + 2];
     }
     __syncthreads();
-    const int nb = __builtin_amdgcn_readfirstlane((int)min((uint32_t)kCompBatch, end - b0));
+    const int nb = __builtin_amdgcn_readfirstlane((int)min((uint32_t)kFwdBatch, end - b0));
     const uint32_t base = b0 - start + 1u;
     auto step = [&](int j) {
       const float4 A = sA[j];
@@ -643,42 +660,41 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
       const float dx = fx - A.x;
       const float adx = fma_(A.z * dx, dx, B.y);
       const float bdx = A.w * dx;
-      const float dy0 = fy0 - A.y, dy1 = fy1 - A.y;
-      const float p0 = fma_(B.x * dy0, dy0, fma_(bdx, dy0, adx));
-      const float p1 = fma_(B.x * dy1, dy1, fma_(bdx, dy1, adx));
-      float al0 = fminf(amax, __builtin_amdgcn_exp2f(p0));
-      float al1 = fminf(amax, __builtin_amdgcn_exp2f(p1));
-      if (AMIN) {
-        al0 = al0 < amin ? 0.0f : al0;
-        al1 = al1 < amin ? 0.0f : al1;
-      }
-      al0 = done0 ? 0.0f : al0;
-      al1 = done1 ? 0.0f : al1;
-      const float w0 = al0 * T0, w1 = al1 * T1;
-      r0 = fma_(w0, B.z, r0);
-      g0 = fma_(w0, B.w, g0);
-      b0c = fma_(w0, cbl, b0c);
-      r1 = fma_(w1, B.z, r1);
-      g1 = fma_(w1, B.w, g1);
-      b1c = fma_(w1, cbl, b1c);
-      T0 = T0 - w0;
-      T1 = T1 - w1;
-      // a done lane blends nothing more, so its T stays below t_min; an
-      // outside lane starts at T = 0
-      const bool n0 = T0 < tmin, n1 = T1 < tmin;
+      const float dy = fy - A.y;
+      float p = fma_(B.x * dy, dy, fma_(bdx, dy, adx));
+      float d = fma_(B.x, fma_(2.0f, dy, 1.0f), bdx);
+      const float c2 = B.x + B.x;
       const uint32_t li = base + (uint32_t)j;
-      last0 = (n0 && !done0) ? li : last0;
-      last1 = (n1 && !done1) ? li : last1;
-      done0 = n0;
-      done1 = n1;
+      float wsum = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kPx; ++k) {
+        if (k > 0) {
+          p += d;
+          d += c2;
+        }
+        float al = fminf(amax, __builtin_amdgcn_exp2f(p));
+        if (AMIN) al = al < amin ? 0.0f : al;
+        al = done[k] ? 0.0f : al;
+        const float w = al * T[k];
+        cr[k] = fma_(w, B.z, cr[k]);
+        cg[k] = fma_(w, B.w, cg[k]);
+        cb[k] = fma_(w, cbl, cb[k]);
+        T[k] = T[k] - w;
+        // a done lane blends nothing more, so its T stays below t_min; an
+        // outside lane starts at T = 0
+        const bool n = T[k] < tmin;
+        last[k] = (n && !done[k]) ? li : last[k];
+        done[k] = n;
+        if (LOG) wsum += w;
+      }
       if (LOG) {
-        const float ws = wave_sum_f(w0 + w1);
-        if (__lane_id() == 0 && ws != 0.0f) atomicAdd(&s_w[j], ws);
+        const float ws = wave_sum_f(wsum);
+        if (__lane_id() == 0) s_w[j] = ws;
       }
     };
     // groups of 16 entries, with a wave-uniform exit check between groups
     for (int j0 = 0; j0 < nb; j0 += 16) {
-      if (!LOG && __all(done0 && done1)) break;
+      if (!LOG && __all(done[0] && done[1] && done[2] && done[3])) break;
       if (j0 + 16 <= nb) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) step(j0 + k);
@@ -689,34 +705,29 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
     if (LOG) {
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
-        const int i = t + q * kCompThreads;
+      for (int q = 0; q < kFwdBatch / kFwdThreads; ++q) {
+        const int i = t + q * kFwdThreads;
         if (i < nb && s_w[i] != 0.0f) atomicAdd(&a.gauss_w[s_slot[i]], s_w[i]);
       }
     }
-    if (__syncthreads_count(done0 && done1) == kCompThreads) break;
+    if (__all(done[0] && done[1] && done[2] && done[3])) break;
   }
   const size_t plane = (size_t)a.W * a.H;
-  if (in0) {
-    const size_t pix = (size_t)py0 * a.W + px;
-    a.rgb[pix] = fma_(T0, a.bg[0], r0);
-    a.rgb[plane + pix] = fma_(T0, a.bg[1], g0);
-    a.rgb[2 * plane + pix] = fma_(T0, a.bg[2], b0c);
-    a.T_final[pix] = T0;
-    a.last[pix] = last0;
-  }
-  if (in1) {
-    const size_t pix = (size_t)py1 * a.W + px;
-    a.rgb[pix] = fma_(T1, a.bg[0], r1);
-    a.rgb[plane + pix] = fma_(T1, a.bg[1], g1);
-    a.rgb[2 * plane + pix] = fma_(T1, a.bg[2], b1c);
-    a.T_final[pix] = T1;
-    a.last[pix] = last1;
+#pragma unroll
+  for (int k = 0; k < kPx; ++k) {
+    if (in[k]) {
+      const size_t pix = (size_t)(py0 + k) * a.W + px;
+      a.rgb[pix] = fma_(T[k], a.bg[0], cr[k]);
+      a.rgb[plane + pix] = fma_(T[k], a.bg[1], cg[k]);
+      a.rgb[2 * plane + pix] = fma_(T[k], a.bg[2], cb[k]);
+      a.T_final[pix] = T[k];
+      a.last[pix] = last[k];
+    }
   }
 }
 
 template <bool LOG>
-__global__ __launch_bounds__(kCompThreads) void k_composite(CompArgs a) {
+__global__ __launch_bounds__(kFwdThreads) void k_composite(CompArgs a) {
   __shared__ CompLds<LOG> lds;
   if (a.alpha_min > 0.0f)
     composite_tile<LOG, true>(a, lds);
@@ -862,9 +873,9 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   ca.gauss_w = gauss_w;
   mark(8);
   if (gauss_w)
-    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kCompThreads), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kFwdThreads), 0, s, ca);
   else
-    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kCompThreads), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kFwdThreads), 0, s, ca);
   mark(9);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
