@@ -34,55 +34,78 @@ struct BwdDecodeArgs {
 };
 
 // network input per listed anchor: X = [feature, dist / d_max, dir], Dn = (dist, dir)
+// Network inputs of the listed anchors, 32 lanes per anchor (one feature
+// each, coalesced 128-byte rows); lane 0 adds distance and direction.
+constexpr int kGatherLanes = 32;
+
 __global__ __launch_bounds__(kBlock) void k_bwd_gather(BwdDecodeArgs a) {
   const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
-  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+  const int f = threadIdx.x % kGatherLanes;
+  const uint32_t per = kBlock / kGatherLanes;
+  for (uint32_t m = blockIdx.x * per + threadIdx.x / kGatherLanes; m < M; m += gridDim.x * per) {
     const uint32_t j = a.idx[m];
     float *x = a.X + (size_t)m * 36;
-    for (int f = 0; f < 32; ++f) x[f] = a.feat[(size_t)j * 32 + f];
-    const float d0 = a.pos[3 * (size_t)j] - a.C[0], d1 = a.pos[3 * (size_t)j + 1] - a.C[1];
-    const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
-    const float dist = sqrtf(fma_(d0, d0, fma_(d1, d1, d2 * d2)));
-    const float inv = 1.0f / dist;
-    x[32] = dist * a.inv_dmax;
-    x[33] = d0 * inv; x[34] = d1 * inv; x[35] = d2 * inv;
-    float *dn = a.Dn + (size_t)m * 4;
-    dn[0] = dist; dn[1] = x[33]; dn[2] = x[34]; dn[3] = x[35];
+    x[f] = a.feat[(size_t)j * 32 + f];
+    if (f == 0) {
+      const float d0 = a.pos[3 * (size_t)j] - a.C[0], d1 = a.pos[3 * (size_t)j + 1] - a.C[1];
+      const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
+      const float dist = sqrtf(fma_(d0, d0, fma_(d1, d1, d2 * d2)));
+      const float inv = 1.0f / dist;
+      x[32] = dist * a.inv_dmax;
+      x[33] = d0 * inv; x[34] = d1 * inv; x[35] = d2 * inv;
+      float *dn = a.Dn + (size_t)m * 4;
+      dn[0] = dist; dn[1] = x[33]; dn[2] = x[34]; dn[3] = x[35];
+    }
   }
 }
 
-// Activation derivatives (one thread per anchor, looping over its k
-// Gaussians) and the anchor-array gradients of Eq. 3 and the scale bound.
+// Sum over the 16 lanes of a DPP row (every lane of the row gets it).
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __uint_as_float(dpp_u<kDppXor1>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppXor2>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppHalfMirror>(__float_as_uint(v)));
+  v += __uint_as_float(dpp_u<kDppRor8>(__float_as_uint(v)));
+  return v;
+}
+
+// Activation derivatives and the anchor-array gradients of Eq. 3 and the
+// scale bound: one 16-lane row per anchor, lane i for Gaussian i (k <= 16),
+// the anchor's sums over its Gaussians reduced within the row.
 __global__ __launch_bounds__(kBlock) void k_act_bwd(BwdDecodeArgs a) {
   const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
   const int k = a.k;
-  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+  const int i = threadIdx.x & 15;
+  const uint32_t per = kBlock / 16;
+  // every lane of a row runs the same iterations, so the row sums stay whole
+  for (uint32_t m = blockIdx.x * per + threadIdx.x / 16; m < M; m += gridDim.x * per) {
     const uint32_t j = a.idx[m];
+    const bool act = i < k;
+    const int ii = act ? i : 0;
     const float *y = a.Y + (size_t)m * a.OT;
     float *dy = a.dY + (size_t)m * a.OT;
-    float dp[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dbs[3] = {0, 0, 0};
     const float *l = a.oscale + 3 * (size_t)j;
     const float *bs = a.bscale + 3 * (size_t)j;
-    for (int i = 0; i < k; ++i) {
-      const size_t s = (size_t)m * k + i;
-      const float *o = a.offsets + ((size_t)j * k + i) * 3;
-      float *go = a.goff + ((size_t)j * k + i) * 3;
+    const size_t s = (size_t)m * k + ii;
+    const float *o = a.offsets + ((size_t)j * k + ii) * 3;
+    float *go = a.goff + ((size_t)j * k + ii) * 3;
+    float dp[3], dl[3], dbs[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float dm = a.dgauss[c * a.dstride + s];
-        dp[c] += dm;
-        go[c] += dm * l[c];
-        dl[c] = fma_(dm, o[c], dl[c]);
-      }
+    for (int c = 0; c < 3; ++c) {
+      const float dm = act ? a.dgauss[c * a.dstride + s] : 0.0f;
+      dp[c] = dm;
+      if (act) go[c] += dm * l[c];
+      dl[c] = dm * o[c];
+    }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float sg = sigm(y[a.off[2] + 7 * i + c]);
-        const float dsc = a.dgauss[(3 + c) * a.dstride + s];
-        dbs[c] = fma_(dsc, sg, dbs[c]);
-        dy[a.off[2] + 7 * i + c] = dsc * bs[c] * sg * (1.0f - sg);
-      }
-      const float q0 = y[a.off[2] + 7 * i + 3], q1 = y[a.off[2] + 7 * i + 4];
-      const float q2 = y[a.off[2] + 7 * i + 5], q3 = y[a.off[2] + 7 * i + 6];
+    for (int c = 0; c < 3; ++c) {
+      const float sg = sigm(y[a.off[2] + 7 * ii + c]);
+      const float dsc = act ? a.dgauss[(3 + c) * a.dstride + s] : 0.0f;
+      dbs[c] = dsc * sg;
+      if (act) dy[a.off[2] + 7 * ii + c] = dsc * bs[c] * sg * (1.0f - sg);
+    }
+    if (act) {
+      const float q0 = y[a.off[2] + 7 * ii + 3], q1 = y[a.off[2] + 7 * ii + 4];
+      const float q2 = y[a.off[2] + 7 * ii + 5], q3 = y[a.off[2] + 7 * ii + 6];
       const float n2 = fma_(q0, q0, fma_(q1, q1, fma_(q2, q2, q3 * q3)));
       float dq[4] = {0, 0, 0, 0};
       if (n2 > 0.0f) {
@@ -98,39 +121,51 @@ __global__ __launch_bounds__(kBlock) void k_act_bwd(BwdDecodeArgs a) {
         for (int c = 0; c < 4; ++c) dq[c] = (gq[c] - u[c] * dot) * inv;
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) dy[a.off[2] + 7 * i + 3 + c] = dq[c];
-      const float op = tanhf(y[a.off[0] + i]);
-      dy[a.off[0] + i] = a.dgauss[10 * a.dstride + s] * (1.0f - op * op);
+      for (int c = 0; c < 4; ++c) dy[a.off[2] + 7 * ii + 3 + c] = dq[c];
+      const float op = tanhf(y[a.off[0] + ii]);
+      dy[a.off[0] + ii] = a.dgauss[10 * a.dstride + s] * (1.0f - op * op);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float sg = sigm(y[a.off[1] + 3 * i + c]);
-        dy[a.off[1] + 3 * i + c] = a.dgauss[(11 + c) * a.dstride + s] * sg * (1.0f - sg);
+        const float sg = sigm(y[a.off[1] + 3 * ii + c]);
+        dy[a.off[1] + 3 * ii + c] = a.dgauss[(11 + c) * a.dstride + s] * sg * (1.0f - sg);
       }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      a.gpos[3 * (size_t)j + c] += dp[c];
-      a.gosc[3 * (size_t)j + c] += dl[c];
-      a.gbsc[3 * (size_t)j + c] += dbs[c];
+      dp[c] = row16_sum(dp[c]);
+      dl[c] = row16_sum(dl[c]);
+      dbs[c] = row16_sum(dbs[c]);
+    }
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a.gpos[3 * (size_t)j + c] += dp[c];
+        a.gosc[3 * (size_t)j + c] += dl[c];
+        a.gbsc[3 * (size_t)j + c] += dbs[c];
+      }
     }
   }
 }
 
-// Input gradients back to the anchor: features, and the position through the
-// relative distance and the viewing direction.
+// Input gradients back to the anchor: features (32 lanes per anchor), and
+// the position through the relative distance and the viewing direction.
 __global__ __launch_bounds__(kBlock) void k_x_bwd(BwdDecodeArgs a) {
   const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
-  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+  const int f = threadIdx.x % kGatherLanes;
+  const uint32_t per = kBlock / kGatherLanes;
+  for (uint32_t m = blockIdx.x * per + threadIdx.x / kGatherLanes; m < M; m += gridDim.x * per) {
     const uint32_t j = a.idx[m];
     const float *dx = a.dX + (size_t)m * 36;
-    for (int f = 0; f < 32; ++f) a.gfeat[(size_t)j * 32 + f] += dx[f];
-    const float *dn = a.Dn + (size_t)m * 4;
-    const float dist = dn[0], u0 = dn[1], u1 = dn[2], u2 = dn[3];
-    const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
-    const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
-    a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
-    a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
-    a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
+    a.gfeat[(size_t)j * 32 + f] += dx[f];
+    if (f == 0) {
+      const float *dn = a.Dn + (size_t)m * 4;
+      const float dist = dn[0], u0 = dn[1], u1 = dn[2], u2 = dn[3];
+      const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
+      const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
+      a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
+      a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
+      a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
+    }
   }
 }
 
@@ -212,7 +247,9 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   a.X = L.X; a.Dn = L.Dn; a.Y = L.Y; a.dY = L.dY; a.dX = L.dX;
   a.gpos = ga->pos; a.gfeat = ga->feat; a.goff = ga->offsets;
   a.gosc = ga->offset_scale; a.gbsc = ga->base_scale;
-  const int grid = (int)std::min<int64_t>((mcap + kBlock - 1) / kBlock, 2048);
+  // the per-anchor kernels give each anchor a row of 16 or 32 lanes
+  const int grid = (int)std::min<int64_t>((mcap * kGatherLanes + kBlock - 1) / kBlock, 4096);
+  const int grid16 = (int)std::min<int64_t>((mcap * 16 + kBlock - 1) / kBlock, 4096);
   hipLaunchKernelGGL(k_bwd_gather, dim3(grid), dim3(kBlock), 0, s, a);
   const int splitk = (int)std::min<int64_t>(std::max<int64_t>(mcap / 512, 1), 64);
   hipError_t e = hipSuccess;
@@ -255,7 +292,7 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   }
   if ((e = gemm(g1, mcap, s)) != hipSuccess) return OCTGS_EHIP;
   if ((e = gemm(g2, mcap, s)) != hipSuccess) return OCTGS_EHIP;
-  hipLaunchKernelGGL(k_act_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_act_bwd, dim3(grid16), dim3(kBlock), 0, s, a);
   if ((e = gemm(g3, W, s)) != hipSuccess) return OCTGS_EHIP;
   if ((e = gemm(g4, mcap, s)) != hipSuccess) return OCTGS_EHIP;
   if ((e = gemm(g5, 36, s)) != hipSuccess) return OCTGS_EHIP;

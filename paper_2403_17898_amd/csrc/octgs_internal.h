@@ -195,20 +195,22 @@ struct RasterWs {
   uint32_t *run_first;    // [nruns] depth-order index of the survivor holding candidate kEmitRun r
   uint32_t *lb_pair;      // [nruns] look-back status of the emission's runs
   uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
-  uint32_t *tval[2];      // [pcap] slot ids
+  uint32_t *tval[2];      // [pcap] tile-sort values: the pair's emission index; after the sort,
+                          // the other buffer holds the slot of each sorted pair
+  uint32_t *pair_slot;    // [pcap] slot of each pair in emission order (a Gaussian's pairs
+                          // are contiguous there)
   uint32_t *ranges;       // [tiles][2]
   uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 1..4 tile passes)
   uint32_t *lookback;     // [4][ceil(gcap / kSortPart)][256] depth-sort look-back
   uint32_t *lookback_t;   // [tile passes][ceil(pcap / kSortPart)][256] tile-sort look-back
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
+  float *gpair;           // [pcap][9] backward: the same per (tile, Gaussian) pair, emission order
   int64_t gcap, pcap;
   int32_t tiles_x, tiles_y, nblk_g, nruns, tile_passes;
   size_t lb_words, lbt_words;  // look-back words to clear before the sorts
   size_t bytes;
 };
 
-constexpr int kCompThreads = 128;  // forward composite: threads per 16x16 tile (2 pixels each)
-constexpr int kCompBatch = 256;    // list entries staged in LDS per batch
 constexpr int kEmitThreads = 1024;  // pair emission: threads per block
 constexpr int kEmitRun = 8192;      // candidate pairs per block of the emission
 

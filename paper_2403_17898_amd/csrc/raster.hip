@@ -544,7 +544,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
       const uint32_t dst = excl + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
       if (dst < P) {  // always true unless a look-back wait hit its bound
         ws.tkey[0][dst] = key[k];
-        ws.tval[0][dst] = val[k];
+        ws.tval[0][dst] = dst;
+        ws.pair_slot[dst] = val[k];
       }
       for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
     }
@@ -561,10 +562,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
     }
 }
 
+// Tile ranges of the sorted list, and the slot of every sorted pair (the
+// sort carried the pair's emission index) into the free ping-pong buffer.
 __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
   const uint32_t P = ws.hdr->n_listed;
   const uint32_t *key = ws.tkey[buf];
   for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
+    ws.tval[buf ^ 1][p] = ws.pair_slot[ws.tval[buf][p]];
     const uint32_t k = key[p];
     if (p == 0 || key[p - 1] != k) ws.ranges[2 * k] = p;
     if (p == P - 1 || key[p + 1] != k) ws.ranges[2 * k + 1] = p + 1;
@@ -624,7 +628,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
   const float fx = (float)px + 0.5f, fy = (float)py0 + 0.5f;
   const uint32_t start = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile + 1]);
-  const uint32_t *vals = a.ws.tval[a.buf];
+  const uint32_t *vals = a.ws.tval[a.buf ^ 1];  // slot of each sorted pair
   const float4 *proj = a.ws.proj;
   const float amax = a.alpha_max, amin = a.alpha_min, tmin = a.t_min;
   float T[kPx], cr[kPx], cg[kPx], cb[kPx];
@@ -769,6 +773,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.lb_pair = (uint32_t *)take((size_t)ws.nruns * 4);
   for (int i = 0; i < 2; ++i) ws.tkey[i] = (uint32_t *)take((size_t)pc * 4);
   for (int i = 0; i < 2; ++i) ws.tval[i] = (uint32_t *)take((size_t)pc * 4);
+  ws.pair_slot = (uint32_t *)take((size_t)pc * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
   ws.hist = (uint32_t *)take(8 * 256 * 4);
   ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
@@ -777,6 +782,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.lookback = (uint32_t *)take(ws.lb_words * 4);
   ws.lookback_t = (uint32_t *)take(ws.lbt_words * 4);
   ws.dproj = (float *)take((size_t)g * 9 * 4);
+  ws.gpair = (float *)take((size_t)pc * 9 * 4);
   ws.bytes = off;
   return ws;
 }
@@ -890,7 +896,7 @@ int octgs_raster_views(const void *wsp, int64_t gauss_capacity, int64_t pair_cap
   const int buf = tile_sort_passes(ws.tiles_x * ws.tiles_y) % 2;
   if (stats) *stats = (const octgs_raster_stats *)ws.hdr;
   if (pair_tile) *pair_tile = ws.tkey[buf];
-  if (pair_slot) *pair_slot = ws.tval[buf];
+  if (pair_slot) *pair_slot = ws.tval[buf ^ 1];
   if (tile_ranges) *tile_ranges = ws.ranges;
   return OCTGS_OK;
 }

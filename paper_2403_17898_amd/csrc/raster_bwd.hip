@@ -3,13 +3,16 @@
 // (the training step of Octree-GS renders and back-propagates through the
 // Eq. 2 blending and the EWA projection of Sec. III-A).
 //
-// composite backward: one block of 128 threads per 16x16 tile, two pixels
-// per thread.  Each pixel starts from its final transmittance and walks its
-// tile list in reverse from the last entry the forward consumed, recovering
+// composite backward: one wave per 16x16 tile, four pixels per thread.  Each
+// pixel starts from its final transmittance and walks its tile list in
+// reverse from the last entry the forward consumed, recovering
 // T_i = T_{i+1} / (1 - a_i) instead of storing per-pixel lists; the colour
 // behind each entry is accumulated on the way.  Per-Gaussian gradients are
-// summed over the thread's pixels, over the wave by a halving exchange, over
-// the block in LDS, and added to global memory once per (tile, Gaussian).
+// summed over the thread's pixels and over the wave by a halving exchange,
+// stored once per (tile, Gaussian) pair at the pair's emission index (plain
+// stores: float atomics on global memory are performed at the memory side
+// on this chip and were most of the pass's time), then summed per Gaussian
+// over its contiguous run of pairs.
 //
 // projection backward: one thread per Gaussian slot, recomputing the forward
 // quantities (rotation, 3D covariance, Jacobian, 2D covariance) in FP32.
@@ -64,79 +67,89 @@ __device__ __forceinline__ float wave_sum8(const float (&v)[8], int &q) {
   return c;
 }
 
-// Reverse replay of one tile, 128 threads, two vertically adjacent pixels
-// per thread, exactly mirroring the forward's per-pixel alpha sequence so
-// that T_i = T_{i+1} / (1 - a_i) retraces the forward's transmittances.
+// Reverse replay of one tile by one wave (64 threads), four vertically
+// adjacent pixels per thread, replaying the forward's per-pixel exponent
+// sequence operation for operation, so every a_i is bit-identical to the
+// forward's and T_i = T_{i+1} / (1 - a_i) retraces its transmittances.
+constexpr int kBwdThreads = 64;
+constexpr int kBwdBatch = 64;
+constexpr int kBPx = 4;
+
 struct BwdLds {
-  float4 sA[kCompBatch], sB[kCompBatch], sC[kCompBatch];
-  uint32_t s_slot[kCompBatch];
-  float sG[9][kCompBatch];
-  uint32_t s_max;
+  float4 sA[kBwdBatch], sB[kBwdBatch], sC[kBwdBatch];
+  uint32_t s_pair[kBwdBatch];
+  float sG[9][kBwdBatch];
 };
+
+// Per-pair gradients of list entries [e0, e1) that no pixel consumed are 0.
+__device__ __forceinline__ void zero_pairs(const RasterWs &ws, const uint32_t *pidx, uint32_t e0,
+                                           uint32_t e1) {
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    float *gp = ws.gpair + 9 * (size_t)pidx[e];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gp[k] = 0.0f;
+  }
+}
 
 // The LDS lives in the kernel and is passed in, so the two AMIN
 // instantiations share one allocation.
 template <bool AMIN>
 __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds) {
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
-  uint32_t *s_slot = lds.s_slot;
-  float (*sG)[kCompBatch] = lds.sG;
-  uint32_t &s_max = lds.s_max;
+  uint32_t *s_pair = lds.s_pair;
+  float (*sG)[kBwdBatch] = lds.sG;
   const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
   const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x, l = __lane_id();
-  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + 2 * (t / kTile), py1 = py0 + 1;
-  const bool in0 = px < a.W && py0 < a.H, in1 = px < a.W && py1 < a.H;
-  const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f, fy1 = fy0 + 1.0f;
+  const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kBPx * (t / kTile);
+  const float fx = (float)px + 0.5f, fy = (float)py0 + 0.5f;
   const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
-  const uint32_t *vals = a.ws.tval[a.buf];
+  const uint32_t *vals = a.ws.tval[a.buf ^ 1];  // slot of each sorted pair
+  const uint32_t *pidx = a.ws.tval[a.buf];      // its emission index
   const float4 *proj = a.ws.proj;
   const size_t plane = (size_t)a.W * a.H;
   // per pixel: T, dL/dC, colour behind (starts as T_final * bg), entries used
-  float T[2] = {1.0f, 1.0f}, dr[2] = {0, 0}, dg[2] = {0, 0}, db[2] = {0, 0};
-  uint32_t last[2] = {0, 0};
-  const bool in[2] = {in0, in1};
-  const int py[2] = {py0, py1};
+  float T[kBPx], dr[kBPx], dg[kBPx], db[kBPx], br[kBPx], bgc[kBPx], bb[kBPx];
+  uint32_t last[kBPx];
+  uint32_t mx = 0;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-    if (in[u]) {
-      const size_t pix = (size_t)py[u] * a.W + px;
-      T[u] = a.T_final[pix];
-      last[u] = a.last[pix];
-      dr[u] = a.dimg[pix];
-      dg[u] = a.dimg[plane + pix];
-      db[u] = a.dimg[2 * plane + pix];
+  for (int k = 0; k < kBPx; ++k) {
+    T[k] = 1.0f; dr[k] = 0.0f; dg[k] = 0.0f; db[k] = 0.0f; last[k] = 0;
+    if (px < a.W && py0 + k < a.H) {
+      const size_t pix = (size_t)(py0 + k) * a.W + px;
+      T[k] = a.T_final[pix];
+      last[k] = a.last[pix];
+      dr[k] = a.dimg[pix];
+      dg[k] = a.dimg[plane + pix];
+      db[k] = a.dimg[2 * plane + pix];
     }
-  float br[2], bgc[2], bb[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    br[u] = T[u] * a.bg[0];
-    bgc[u] = T[u] * a.bg[1];
-    bb[u] = T[u] * a.bg[2];
+    br[k] = T[k] * a.bg[0];
+    bgc[k] = T[k] * a.bg[1];
+    bb[k] = T[k] * a.bg[2];
+    mx = max(mx, last[k]);
   }
-  if (t == 0) s_max = 0;
-  __syncthreads();
-  atomicMax(&s_max, max(last[0], last[1]));
-  __syncthreads();
-  const uint32_t n_used = min(s_max, end - start);
-  const float amax = a.alpha_max, amin = a.alpha_min;
-  if (n_used == 0) return;
-  for (int32_t b0 = (int32_t)((n_used - 1) / kCompBatch) * kCompBatch; b0 >= 0; b0 -= kCompBatch) {
-    const int nb = (int)min((uint32_t)kCompBatch, n_used - (uint32_t)b0);
 #pragma unroll
-    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
-      const int i = t + q * kCompThreads;
-      if (i < nb) {
-        const uint32_t s = vals[start + (uint32_t)b0 + i];
-        s_slot[i] = s;
-        sA[i] = proj[3 * (size_t)s];
-        float4 bv = proj[3 * (size_t)s + 1];
-        sB[i] = bv;
-        float4 cv = proj[3 * (size_t)s + 2];
-        cv.y = __builtin_amdgcn_exp2f(-bv.y);  // 1 / opacity, for dL/dop = dL/da a / op
-        sC[i] = cv;
-      }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, kWave));
+  const uint32_t n_used = min(mx, end - start);
+  const float amax = a.alpha_max, amin = a.alpha_min;
+  zero_pairs(a.ws, pidx, start + n_used, end);
+  if (n_used == 0) return;
+  for (int32_t b0 = (int32_t)((n_used - 1) / kBwdBatch) * kBwdBatch; b0 >= 0; b0 -= kBwdBatch) {
+    const int nb = (int)min((uint32_t)kBwdBatch, n_used - (uint32_t)b0);
+    __syncthreads();  // one wave: orders the reuse of the batch buffers
+#pragma unroll
+    for (int q = 0; q < kBwdBatch / kBwdThreads; ++q) {
+      const int i = t + q * kBwdThreads;
+      const uint32_t e = start + (uint32_t)b0 + (uint32_t)min(i, nb - 1);
+      const uint32_t s = vals[e];
+      s_pair[i] = pidx[e];
+      sA[i] = proj[3 * (size_t)s];
+      const float4 bv = proj[3 * (size_t)s + 1];
+      sB[i] = bv;
+      float4 cv = proj[3 * (size_t)s + 2];
+      cv.y = __builtin_amdgcn_exp2f(-bv.y);  // 1 / opacity, for dL/dop = dL/da a / op
+      sC[i] = cv;
 #pragma unroll
       for (int g = 0; g < 9; ++g) sG[g][i] = 0.0f;
     }
@@ -146,44 +159,50 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
       const float4 A = sA[j];
       const float4 B = sB[j];
       const float4 Cc = sC[j];
-      // the forward's sequence, so a0 (= op G') is bit-identical to it
+      // the forward's sequence, so each a0 (= op G') is bit-identical to it
       const float dx = fx - A.x;
       const float adx = fma_(A.z * dx, dx, B.y);
       const float bdx = A.w * dx;
-      const float dyv[2] = {fy0 - A.y, fy1 - A.y};
+      const float dy = fy - A.y;
+      float p = fma_(B.x * dy, dy, fma_(bdx, dy, adx));
+      float d = fma_(B.x, fma_(2.0f, dy, 1.0f), bdx);
+      const float c2 = B.x + B.x;
       // raw per-lane sums, turned into gradients once per (tile, Gaussian):
-      // dq = dL/da a0 (0 where alpha is clamped); D = sum dq over the two
-      // pixels, Sy = sum dq dy, Qyy = sum dq dy^2; colour weights w dL/dC
+      // dq = dL/da a0 (0 where alpha is clamped); D = sum dq over the
+      // thread's pixels, Sy = sum dq dy, Qyy = sum dq dy^2; colour weights
       float D = 0.0f, Sy = 0.0f, Qyy = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
       bool any = false;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const float dy = dyv[u];
-        const float pwl = fma_(B.x * dy, dy, fma_(bdx, dy, adx));
-        const float a0 = __builtin_amdgcn_exp2f(pwl);
+      for (int k = 0; k < kBPx; ++k) {
+        if (k > 0) {
+          p += d;
+          d += c2;
+        }
+        const float a0 = __builtin_amdgcn_exp2f(p);
         const float al = fminf(amax, a0);
-        bool valid = li < last[u];
+        bool valid = li < last[k];
         if (AMIN) valid = valid && !(al < amin);
         if (valid) {
           any = true;
+          const float dyk = (fy + (float)k) - A.y;
           const float inv1 = __builtin_amdgcn_rcpf(1.0f - al);
-          const float Ti = T[u] * inv1;
+          const float Ti = T[k] * inv1;
           const float w = al * Ti;
-          wr = fma_(w, dr[u], wr);
-          wg = fma_(w, dg[u], wg);
-          wb = fma_(w, db[u], wb);
-          const float cdot = fma_(B.z, dr[u], fma_(B.w, dg[u], Cc.x * db[u]));
-          const float bdot = fma_(br[u], dr[u], fma_(bgc[u], dg[u], bb[u] * db[u]));
+          wr = fma_(w, dr[k], wr);
+          wg = fma_(w, dg[k], wg);
+          wb = fma_(w, db[k], wb);
+          const float cdot = fma_(B.z, dr[k], fma_(B.w, dg[k], Cc.x * db[k]));
+          const float bdot = fma_(br[k], dr[k], fma_(bgc[k], dg[k], bb[k] * db[k]));
           const float dLda = Ti * cdot - bdot * inv1;
-          br[u] = fma_(w, B.z, br[u]);
-          bgc[u] = fma_(w, B.w, bgc[u]);
-          bb[u] = fma_(w, Cc.x, bb[u]);
-          T[u] = Ti;
+          br[k] = fma_(w, B.z, br[k]);
+          bgc[k] = fma_(w, B.w, bgc[k]);
+          bb[k] = fma_(w, Cc.x, bb[k]);
+          T[k] = Ti;
           const float dq = a0 <= amax ? dLda * a0 : 0.0f;
           D += dq;
-          const float dqy = dq * dy;
+          const float dqy = dq * dyk;
           Sy += dqy;
-          Qyy = fma_(dqy, dy, Qyy);
+          Qyy = fma_(dqy, dyk, Qyy);
         }
       }
       if (ballot(any) != 0ull) {
@@ -191,8 +210,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
         const float v8[8] = {D, D * dx, D * dx * dx, Sy, Sy * dx, Qyy, wr, wg};
         const float s8 = wave_sum8(v8, q);
         const float s9 = wave_sum_f(wb);
-        if ((l & 7) == 0 && s8 != 0.0f) atomicAdd(&sG[q][j], s8);
-        if (l == 0 && s9 != 0.0f) atomicAdd(&sG[8][j], s9);
+        if ((l & 7) == 0) sG[q][j] = s8;
+        if (l == 0) sG[8][j] = s9;
       }
     }
     __syncthreads();
@@ -202,8 +221,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
     //   d(ca, cb, cc) = ln2 (-log2e / 2 Qxx, -log2e Qxy, -log2e / 2 Qyy),
     //   dop = D / op
 #pragma unroll
-    for (int q = 0; q < kCompBatch / kCompThreads; ++q) {
-      const int i = t + q * kCompThreads;
+    for (int q = 0; q < kBwdBatch / kBwdThreads; ++q) {
+      const int i = t + q * kBwdThreads;
       if (i < nb) {
         const float4 A = sA[i], B = sB[i], Cc = sC[i];
         const float D = sG[0][i], Sx = sG[1][i], Qxx = sG[2][i], Sy = sG[3][i];
@@ -218,22 +237,62 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
         g[6] = sG[6][i];
         g[7] = sG[7][i];
         g[8] = sG[8][i];
-        float *d = a.ws.dproj + 9 * (size_t)s_slot[i];
+        float *gp = a.ws.gpair + 9 * (size_t)s_pair[i];
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-          if (g[k] != 0.0f) atomicAdd(d + k, g[k]);
+        for (int k = 0; k < 9; ++k) gp[k] = g[k];
       }
     }
-    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kCompThreads) void k_composite_bwd(BwdArgs a) {
+__global__ __launch_bounds__(kBwdThreads) void k_composite_bwd(BwdArgs a) {
   __shared__ BwdLds lds;
   if (a.alpha_min > 0.0f)
     composite_bwd_tile<true>(a, lds);
   else
     composite_bwd_tile<false>(a, lds);
+}
+
+// Per-Gaussian sums of the per-pair gradients.  A Gaussian's pairs are
+// contiguous in emission order; each run is summed in chunks that end at
+// multiples of kRedChunk, so no thread walks more than kRedChunk pairs.  A
+// run held by one chunk is stored, the chunks of a longer run are added
+// atomically (the slot's row was zeroed first).
+constexpr uint32_t kRedChunk = 32;
+
+__global__ __launch_bounds__(kBlock) void k_pair_reduce(RasterWs ws) {
+  const uint32_t P = ws.hdr->n_listed;
+  for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
+    const uint32_t s = ws.pair_slot[p];
+    const bool run_start = p == 0 || ws.pair_slot[p - 1] != s;
+    if (!run_start && p % kRedChunk != 0) continue;
+    const uint32_t lim = min(P, (p / kRedChunk + 1) * kRedChunk);
+    float acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+    uint32_t q = p;
+    bool more = false;
+    while (true) {
+      const float *gp = ws.gpair + 9 * (size_t)q;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] += gp[k];
+      ++q;
+      if (q >= P || ws.pair_slot[q] != s) break;
+      if (q >= lim) {
+        more = true;
+        break;
+      }
+    }
+    float *d = ws.dproj + 9 * (size_t)s;
+    if (run_start && !more) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) d[k] = acc[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (acc[k] != 0.0f) atomicAdd(d + k, acc[k]);
+    }
+  }
 }
 
 struct PBwdArgs {
@@ -420,7 +479,9 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   b.T_final = T_final;
   b.dimg = dL_drgb;
   b.last = last;
-  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kCompThreads), 0, s, b);
+  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kBwdThreads), 0, s, b);
+  const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 4096);
+  hipLaunchKernelGGL(k_pair_reduce, dim3(rgrid), dim3(kBlock), 0, s, ws);
   PBwdArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
   for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];
