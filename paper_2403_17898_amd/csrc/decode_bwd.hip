@@ -1,62 +1,107 @@
 // Backward pass of the neural-Gaussian decode (Octree-GS Sec. III-B, Eq. 3
 // and Eq. 4): from the gradients of the decoded Gaussian attributes to the
 // gradients of the anchor features, positions, offsets, scalings and of the
-// three MLP heads' weights and biases.
+// three MLP heads' weights and biases.  FP32 throughout.
 //
-// Structure: the forward activations are recomputed (hidden pre-activations
-// and head outputs), the activation derivatives give dY, and the products of
-// each head's backward (dW2 = relu(H)^T dY, dH = dY W2^T masked by relu',
-// dW1 = X^T dH, dX = dH W1^T) run on one tiled FP32 GEMM kernel, the three
-// heads of a product in one grouped launch.  Weight gradients reduce over
-// anchors with split-K blocks and atomics.  The anchor count lives on the
-// device; every kernel reads it.
+// One fused kernel.  A persistent block stages every weight in LDS once,
+// then walks tiles of 16 listed anchors; per tile, every product runs on
+// v_mfma_f32_16x16x4_f32 out of LDS:
+//   Hp = X W1 + b1            forward recompute (per head: 36 -> W)
+//   Y  = relu(Hp) W2 + b2     forward recompute (per head: W -> k, 3k, 7k)
+//   dY                        activation derivatives; one 16-lane row per
+//                             anchor, lane i for Gaussian i, which also sums
+//                             the anchor-array gradients (Eq. 3) in the row
+//   dHp = (dY W2^T) * [Hp > 0]
+//   dX = dHp W1^T             -> feature and position gradients
+//   dW2 += relu(Hp)^T dY, dW1 += X^T dHp, db += column sums
+// The weight-gradient sums stay in MFMA accumulators across all of the
+// block's tiles; each block writes them once to its row of a workspace, and
+// a second kernel adds the rows in block order into the caller's arrays (no
+// atomics; the result is the same on every run).  The anchor count lives on
+// the device.
+//
+// MFMA 16x16x4 operand layouts (lane l, group g = l / 16, c = l % 16):
+//   A[m][k]: row m = c, k = g;  B[k][n]: column n = c, k = g;
+//   D[m][n]: column n = c, rows m = 4 g + i, i = 0..3.
 #include "octgs_internal.h"
 
 namespace octgs {
 
 namespace {
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-struct BwdDecodeArgs {
-  int k, W, OT, F;
-  int off[3], outs[3];
+constexpr int kRB = 16;                // anchors per tile
+constexpr int kIn = 36;                // feature (32) + distance + direction (3)
+constexpr int kInP = 48;               // inputs padded to three column tiles
+constexpr int kMaxW = 64;
+constexpr int kMaxOutP = 176;          // padded head outputs: 16 + 48 + 112 at k = 16
+constexpr int kXS = kInP + 4;          // LDS row pitches (floats)
+constexpr int kHS = 3 * kMaxW + 4;
+constexpr int kYS = kMaxOutP + 4;
+constexpr int kW1P = kMaxW + 4;        // W1 row pitch: conflict-free column reads for dX
+constexpr int kMaxT1 = 9;              // dW1 output tiles per wave (3 x 12 / 4)
+constexpr int kMaxT2 = 11;             // dW2 output tiles per wave (4 x 11 / 4)
+constexpr int kDecBwdGrid = 256;       // persistent blocks (one per CU: ~120 KB of LDS each)
+
+struct DecBwdArgs {
+  int k, W, cap_anchors;
+  int t[3];        // output column tiles per head
+  int outs[3];     // head widths k, 3k, 7k
+  int offp[3];     // head offsets in the padded output row (16 t[0], 16 (t[0] + t[1]))
+  int wo[3];       // offsets of the W2 heads in the staged block (0, W k, 4 W k)
+  int P;           // partial vector length
+  int p_w2, p_b1, p_b2;  // its regions: dW1 heads at 0, then dW2, db1, db2
   float inv_dmax;
   float C[3];
   const float *pos, *feat, *offsets, *oscale, *bscale;
+  const float *w1[3], *b1[3], *w2[3], *b2[3];
   const uint32_t *idx, *count;
-  int cap_anchors;
   const float *dgauss;
   int64_t dstride;
-  float *X, *Dn, *Y, *dY, *dX;
   float *gpos, *gfeat, *goff, *gosc, *gbsc;
+  float *part;     // [gridDim.x][P]
 };
 
-// network input per listed anchor: X = [feature, dist / d_max, dir], Dn = (dist, dir)
-// Network inputs of the listed anchors, 32 lanes per anchor (one feature
-// each, coalesced 128-byte rows); lane 0 adds distance and direction.
-constexpr int kGatherLanes = 32;
+struct DecBwdLds {
+  float W1s[3 * kIn * kW1P];     // W1 heads, rows of kW1P
+  float W2s[kMaxW * 11 * kMaxK]; // W2 heads [W][k], [W][3k], [W][7k], packed
+  float b1s[3 * kMaxW];
+  float b2s[kMaxOutP];           // padded output layout
+  float X[kRB][kXS];
+  float Hp[kRB][kHS];
+  float Yd[kRB][kYS];            // Y, overwritten in place by dY
+  float dH[kRB][kHS];
+  float dX[kRB][kInP];
+  float Dn[kRB][4];              // distance and unit direction per anchor
+  uint32_t aidx[kRB];
+};
 
-__global__ __launch_bounds__(kBlock) void k_bwd_gather(BwdDecodeArgs a) {
-  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
-  const int f = threadIdx.x % kGatherLanes;
-  const uint32_t per = kBlock / kGatherLanes;
-  for (uint32_t m = blockIdx.x * per + threadIdx.x / kGatherLanes; m < M; m += gridDim.x * per) {
-    const uint32_t j = a.idx[m];
-    float *x = a.X + (size_t)m * 36;
-    x[f] = a.feat[(size_t)j * 32 + f];
-    if (f == 0) {
-      const float d0 = a.pos[3 * (size_t)j] - a.C[0], d1 = a.pos[3 * (size_t)j + 1] - a.C[1];
-      const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
-      const float dist = sqrtf(fma_(d0, d0, fma_(d1, d1, d2 * d2)));
-      const float inv = 1.0f / dist;
-      x[32] = dist * a.inv_dmax;
-      x[33] = d0 * inv; x[34] = d1 * inv; x[35] = d2 * inv;
-      float *dn = a.Dn + (size_t)m * 4;
-      dn[0] = dist; dn[1] = x[33]; dn[2] = x[34]; dn[3] = x[35];
-    }
-  }
+__device__ __forceinline__ const float *pick3(const float *const p[3], int h) {
+  return h == 0 ? p[0] : (h == 1 ? p[1] : p[2]);
+}
+__device__ __forceinline__ float *pick3(float *const p[3], int h) {
+  return h == 0 ? p[0] : (h == 1 ? p[1] : p[2]);
+}
+
+// one of three kernel-argument values by a lane-varying index, without
+// indexing the argument array through scratch memory
+__device__ __forceinline__ int sel3(const int (&v)[3], int h) {
+  return h == 0 ? v[0] : (h == 1 ? v[1] : v[2]);
+}
+
+// padded output tile c -> head and the tile's first column within the head
+__device__ __forceinline__ int out_head(const DecBwdArgs &a, int c, int &col0) {
+  if (c < a.t[0]) { col0 = c * 16; return 0; }
+  if (c < a.t[0] + a.t[1]) { col0 = (c - a.t[0]) * 16; return 1; }
+  col0 = (c - a.t[0] - a.t[1]) * 16;
+  return 2;
 }
 
 // Sum over the 16 lanes of a DPP row (every lane of the row gets it).
@@ -68,132 +113,365 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-// Activation derivatives and the anchor-array gradients of Eq. 3 and the
-// scale bound: one 16-lane row per anchor, lane i for Gaussian i (k <= 16),
-// the anchor's sums over its Gaussians reduced within the row.
-__global__ __launch_bounds__(kBlock) void k_act_bwd(BwdDecodeArgs a) {
-  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
-  const int k = a.k;
-  const int i = threadIdx.x & 15;
-  const uint32_t per = kBlock / 16;
-  // every lane of a row runs the same iterations, so the row sums stay whole
-  for (uint32_t m = blockIdx.x * per + threadIdx.x / 16; m < M; m += gridDim.x * per) {
-    const uint32_t j = a.idx[m];
-    const bool act = i < k;
-    const int ii = act ? i : 0;
-    const float *y = a.Y + (size_t)m * a.OT;
-    float *dy = a.dY + (size_t)m * a.OT;
-    const float *l = a.oscale + 3 * (size_t)j;
-    const float *bs = a.bscale + 3 * (size_t)j;
-    const size_t s = (size_t)m * k + ii;
-    const float *o = a.offsets + ((size_t)j * k + ii) * 3;
-    float *go = a.goff + ((size_t)j * k + ii) * 3;
-    float dp[3], dl[3], dbs[3];
+// U float4 loads per thread, all in flight before the first store
+template <int U>
+struct Ld4 {
+  float4 v[U];
+  __device__ __forceinline__ void load(const float *src, int n4, int t) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float dm = act ? a.dgauss[c * a.dstride + s] : 0.0f;
-      dp[c] = dm;
-      if (act) go[c] += dm * l[c];
-      dl[c] = dm * o[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float sg = sigm(y[a.off[2] + 7 * ii + c]);
-      const float dsc = act ? a.dgauss[(3 + c) * a.dstride + s] : 0.0f;
-      dbs[c] = dsc * sg;
-      if (act) dy[a.off[2] + 7 * ii + c] = dsc * bs[c] * sg * (1.0f - sg);
-    }
-    if (act) {
-      const float q0 = y[a.off[2] + 7 * ii + 3], q1 = y[a.off[2] + 7 * ii + 4];
-      const float q2 = y[a.off[2] + 7 * ii + 5], q3 = y[a.off[2] + 7 * ii + 6];
-      const float n2 = fma_(q0, q0, fma_(q1, q1, fma_(q2, q2, q3 * q3)));
-      float dq[4] = {0, 0, 0, 0};
-      if (n2 > 0.0f) {
-        const float inv = 1.0f / sqrtf(n2);
-        const float u[4] = {q0 * inv, q1 * inv, q2 * inv, q3 * inv};
-        float gq[4], dot = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          gq[c] = a.dgauss[(6 + c) * a.dstride + s];
-          dot = fma_(u[c], gq[c], dot);
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dq[c] = (gq[c] - u[c] * dot) * inv;
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dy[a.off[2] + 7 * ii + 3 + c] = dq[c];
-      const float op = tanhf(y[a.off[0] + ii]);
-      dy[a.off[0] + ii] = a.dgauss[10 * a.dstride + s] * (1.0f - op * op);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float sg = sigm(y[a.off[1] + 3 * ii + c]);
-        dy[a.off[1] + 3 * ii + c] = a.dgauss[(11 + c) * a.dstride + s] * sg * (1.0f - sg);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      dp[c] = row16_sum(dp[c]);
-      dl[c] = row16_sum(dl[c]);
-      dbs[c] = row16_sum(dbs[c]);
-    }
-    if (i == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        a.gpos[3 * (size_t)j + c] += dp[c];
-        a.gosc[3 * (size_t)j + c] += dl[c];
-        a.gbsc[3 * (size_t)j + c] += dbs[c];
-      }
-    }
+    for (int u = 0; u < U; ++u) v[u] = reinterpret_cast<const float4 *>(src)[min(t + u * kBlock, n4 - 1)];
   }
-}
-
-// Input gradients back to the anchor: features (32 lanes per anchor), and
-// the position through the relative distance and the viewing direction.
-__global__ __launch_bounds__(kBlock) void k_x_bwd(BwdDecodeArgs a) {
-  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
-  const int f = threadIdx.x % kGatherLanes;
-  const uint32_t per = kBlock / kGatherLanes;
-  for (uint32_t m = blockIdx.x * per + threadIdx.x / kGatherLanes; m < M; m += gridDim.x * per) {
-    const uint32_t j = a.idx[m];
-    const float *dx = a.dX + (size_t)m * 36;
-    a.gfeat[(size_t)j * 32 + f] += dx[f];
-    if (f == 0) {
-      const float *dn = a.Dn + (size_t)m * 4;
-      const float dist = dn[0], u0 = dn[1], u1 = dn[2], u2 = dn[3];
-      const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
-      const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
-      a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
-      a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
-      a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
-    }
-  }
-}
-
-struct BwdLayout {
-  float *X, *Dn, *Hp, *Y, *dY, *dHp, *dX;
-  size_t bytes;
 };
 
-BwdLayout bwd_layout(void *base, int64_t mcap, int k, int W) {
-  BwdLayout L;
-  char *p = (char *)base;
-  size_t off = 0;
-  auto take = [&](size_t b) -> float * {
-    float *r = p ? (float *)(p + off) : nullptr;
-    off += (b + 255) & ~(size_t)255;
-    return r;
-  };
-  const int64_t m = std::max<int64_t>(mcap, 1);
-  const int OT = 11 * k;
-  L.X = take((size_t)m * 36 * 4);
-  L.Dn = take((size_t)m * 4 * 4);
-  L.Hp = take((size_t)m * 3 * W * 4);
-  L.Y = take((size_t)m * OT * 4);
-  L.dY = take((size_t)m * OT * 4);
-  L.dHp = take((size_t)m * 3 * W * 4);
-  L.dX = take((size_t)m * 36 * 4);
-  L.bytes = off;
-  return L;
+__global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
+  __shared__ DecBwdLds s;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id(), g = l / 16, lc = l % 16;
+  const int k = a.k, W = a.W;
+  const int nhw = W / 16, n1t = 3 * nhw;
+  const int n2t = a.t[0] + a.t[1] + a.t[2];
+  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
+
+  // ---- weights and biases into LDS, every load in flight first ----
+  {
+    const int n1 = kIn * W / 4, wk4 = W * k / 4;
+    {
+      Ld4<3> x0, x1, x2;
+      x0.load(a.w1[0], n1, t); x1.load(a.w1[1], n1, t); x2.load(a.w1[2], n1, t);
+      auto put1 = [&](int h, const float4 &v, int i4) {
+        // element e = 4 i4 .. 4 i4 + 3 of head h's [kIn][W], row pitch kW1P
+        const int e = 4 * i4, r = e / W, c = e - r * W;
+        float *d = &s.W1s[(h * kIn + r) * kW1P + c];
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      };
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int i4 = min(t + u * kBlock, n1 - 1);
+        put1(0, x0.v[u], i4); put1(1, x1.v[u], i4); put1(2, x2.v[u], i4);
+      }
+    }
+    Ld4<1> y0;
+    Ld4<3> y1;
+    Ld4<7> y2;
+    y0.load(a.w2[0], wk4, t); y1.load(a.w2[1], 3 * wk4, t); y2.load(a.w2[2], 7 * wk4, t);
+    float4 *w2s = reinterpret_cast<float4 *>(s.W2s);
+    w2s[min(t, wk4 - 1)] = y0.v[0];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) w2s[wk4 + min(t + u * kBlock, 3 * wk4 - 1)] = y1.v[u];
+#pragma unroll
+    for (int u = 0; u < 7; ++u) w2s[4 * wk4 + min(t + u * kBlock, 7 * wk4 - 1)] = y2.v[u];
+    if (t < 3 * W) s.b1s[t] = pick3(a.b1, t / W)[t % W];
+    if (t < 16 * n2t) {
+      int col0;
+      const int h = out_head(a, t / 16, col0), col = col0 + t % 16;
+      s.b2s[t] = col < sel3(a.outs, h) ? pick3(a.b2, h)[col] : 0.0f;
+    }
+  }
+  __syncthreads();
+
+  f4 acc1[kMaxT1], acc2[kMaxT2];
+#pragma unroll
+  for (int q = 0; q < kMaxT1; ++q) acc1[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < kMaxT2; ++q) acc2[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  float db1r = 0.0f, db2r = 0.0f;  // thread t owns hidden column t / padded output column t
+
+  for (uint32_t tile = blockIdx.x; tile * kRB < M; tile += gridDim.x) {
+    const uint32_t r0 = tile * kRB;
+    const int rows = (int)min((uint32_t)kRB, M - r0);
+    // ---- inputs: 16 threads per anchor ----
+    {
+      const int r = t / 16, part = t % 16;
+      if (r < rows) {
+        const uint32_t j = a.idx[r0 + r];
+        if (part < 8) {
+          const float4 v = *(const float4 *)(a.feat + (size_t)j * 32 + part * 4);
+          s.X[r][part * 4 + 0] = v.x; s.X[r][part * 4 + 1] = v.y;
+          s.X[r][part * 4 + 2] = v.z; s.X[r][part * 4 + 3] = v.w;
+        } else if (part == 8) {
+          s.aidx[r] = j;
+          const float d0 = a.pos[3 * (size_t)j] - a.C[0], d1 = a.pos[3 * (size_t)j + 1] - a.C[1];
+          const float d2 = a.pos[3 * (size_t)j + 2] - a.C[2];
+          const float dist = sqrtf(fma_(d0, d0, fma_(d1, d1, d2 * d2)));
+          const float inv = 1.0f / dist;
+          s.X[r][32] = dist * a.inv_dmax;
+          s.X[r][33] = d0 * inv; s.X[r][34] = d1 * inv; s.X[r][35] = d2 * inv;
+          s.Dn[r][0] = dist; s.Dn[r][1] = d0 * inv; s.Dn[r][2] = d1 * inv; s.Dn[r][3] = d2 * inv;
+        } else if (part < 12) {
+          const int c0 = kIn + 4 * (part - 9);
+          s.X[r][c0] = 0.0f; s.X[r][c0 + 1] = 0.0f; s.X[r][c0 + 2] = 0.0f; s.X[r][c0 + 3] = 0.0f;
+        }
+      } else {
+        for (int c = part; c < kInP; c += 16) s.X[r][c] = 0.0f;
+      }
+    }
+    __syncthreads();
+    // ---- Hp = X W1 + b1 ----
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ct = w + 4 * q;
+      if (ct < n1t) {
+        const int h = ct / nhw, hc = (ct - h * nhw) * 16 + lc;
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < kIn / 4; ++ks)
+          acc = mfma(s.X[lc][ks * 4 + g], s.W1s[(h * kIn + ks * 4 + g) * kW1P + hc], acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s.Hp[4 * g + i][ct * 16 + lc] = acc[i] + s.b1s[ct * 16 + lc];
+      }
+    }
+    __syncthreads();
+    // ---- Y = relu(Hp) W2 + b2 (padded output columns stay 0) ----
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int c = w + 4 * q;
+      if (c < n2t) {
+        int col0;
+        const int h = out_head(a, c, col0);
+        const int ncol = sel3(a.outs, h), col = col0 + lc;
+        const bool cv = col < ncol;
+        const float *wb = s.W2s + sel3(a.wo, h);
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < W / 4; ++ks) {
+          const float av = fmaxf(s.Hp[lc][h * W + ks * 4 + g], 0.0f);
+          acc = mfma(av, cv ? wb[(ks * 4 + g) * ncol + col] : 0.0f, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s.Yd[4 * g + i][c * 16 + lc] = cv ? acc[i] + s.b2s[c * 16 + lc] : 0.0f;
+      }
+    }
+    __syncthreads();
+    // ---- activation derivatives: row r = anchor, lane i = Gaussian ----
+    {
+      const int r = t / 16, i = t % 16;
+      if (r < rows) {
+        const uint32_t j = s.aidx[r];
+        const bool act = i < k;
+        const int ii = act ? i : 0;
+        float *yr = s.Yd[r];
+        const size_t sl = (size_t)(r0 + r) * k + ii;
+        const float *lv = a.oscale + 3 * (size_t)j;
+        const float *bs = a.bscale + 3 * (size_t)j;
+        const float *o = a.offsets + ((size_t)j * k + ii) * 3;
+        float dgv[kGaussFields];
+#pragma unroll
+        for (int f = 0; f < kGaussFields; ++f) dgv[f] = act ? a.dgauss[f * a.dstride + sl] : 0.0f;
+        float dp[3], dl[3], dbs[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dp[c] = dgv[c];
+          dl[c] = dgv[c] * o[c];
+        }
+        if (act) {
+          float *go = a.goff + ((size_t)j * k + ii) * 3;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) go[c] += dgv[c] * lv[c];
+        }
+        const int ys = a.offp[2] + 7 * ii, yc = a.offp[1] + 3 * ii, ya = a.offp[0] + ii;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float sg = sigm(yr[ys + c]);
+          dbs[c] = dgv[3 + c] * sg;
+          if (act) yr[ys + c] = dgv[3 + c] * bs[c] * sg * (1.0f - sg);
+        }
+        if (act) {
+          const float q0 = yr[ys + 3], q1 = yr[ys + 4], q2 = yr[ys + 5], q3 = yr[ys + 6];
+          const float n2 = fma_(q0, q0, fma_(q1, q1, fma_(q2, q2, q3 * q3)));
+          float dq[4] = {0, 0, 0, 0};
+          if (n2 > 0.0f) {
+            const float inv = 1.0f / sqrtf(n2);
+            const float u[4] = {q0 * inv, q1 * inv, q2 * inv, q3 * inv};
+            float dot = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dot = fma_(u[c], dgv[6 + c], dot);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dq[c] = (dgv[6 + c] - u[c] * dot) * inv;
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) yr[ys + 3 + c] = dq[c];
+          const float op = tanhf(yr[ya]);
+          yr[ya] = dgv[10] * (1.0f - op * op);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float sg = sigm(yr[yc + c]);
+            yr[yc + c] = dgv[11 + c] * sg * (1.0f - sg);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dp[c] = row16_sum(dp[c]);
+          dl[c] = row16_sum(dl[c]);
+          dbs[c] = row16_sum(dbs[c]);
+        }
+        if (i == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            a.gpos[3 * (size_t)j + c] += dp[c];
+            a.gosc[3 * (size_t)j + c] += dl[c];
+            a.gbsc[3 * (size_t)j + c] += dbs[c];
+          }
+        }
+      } else {
+        for (int c = i; c < 16 * n2t; c += 16) s.Yd[r][c] = 0.0f;
+      }
+    }
+    __syncthreads();
+    // ---- dHp = (dY W2^T) * [Hp > 0]; dW2 += relu(Hp)^T dY; db2 ----
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ct = w + 4 * q;
+      if (ct < n1t) {
+        const int h = ct / nhw, hc = (ct - h * nhw) * 16 + lc;
+        const int ncol = sel3(a.outs, h);
+        const float *wb = s.W2s + sel3(a.wo, h) + hc * ncol;
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < (ncol + 3) / 4; ++ks) {
+          const int kk = ks * 4 + g;
+          acc = mfma(s.Yd[lc][sel3(a.offp, h) + kk], kk < ncol ? wb[kk] : 0.0f, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = ct * 16 + lc;
+          s.dH[4 * g + i][col] = s.Hp[4 * g + i][col] > 0.0f ? acc[i] : 0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxT2; ++q) {
+      const int T = w + 4 * q;
+      if (T < nhw * n2t) {
+        const int rt = T / n2t, c = T - rt * n2t;
+        int col0;
+        const int h = out_head(a, c, col0);
+#pragma unroll
+        for (int ks = 0; ks < kRB / 4; ++ks) {
+          const int row = ks * 4 + g;
+          acc2[q] = mfma(fmaxf(s.Hp[row][h * W + rt * 16 + lc], 0.0f), s.Yd[row][c * 16 + lc], acc2[q]);
+        }
+      }
+    }
+    if (t < 16 * n2t)
+      for (int r = 0; r < kRB; ++r) db2r += s.Yd[r][t];
+    __syncthreads();
+    // ---- dX = dHp W1^T; dW1 += X^T dHp; db1 ----
+    if (w < 3) {
+      const int n = w * 16 + lc;
+      const bool nv = n < kIn;
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int ks = 0; ks < 3 * W / 4; ++ks) {
+        const int kk = ks * 4 + g, h = kk / W, kh = kk - h * W;
+        acc = mfma(s.dH[lc][kk], nv ? s.W1s[(h * kIn + n) * kW1P + kh] : 0.0f, acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s.dX[4 * g + i][n] = acc[i];
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxT1; ++q) {
+      const int T = w + 4 * q;
+      if (T < 3 * n1t) {
+        const int rt = T / n1t, ct = T - rt * n1t;
+#pragma unroll
+        for (int ks = 0; ks < kRB / 4; ++ks) {
+          const int row = ks * 4 + g;
+          acc1[q] = mfma(s.X[row][rt * 16 + lc], s.dH[row][ct * 16 + lc], acc1[q]);
+        }
+      }
+    }
+    if (t < 3 * W)
+      for (int r = 0; r < kRB; ++r) db1r += s.dH[r][t];
+    __syncthreads();
+    // ---- features and position: 32 lanes per anchor ----
+    for (int r = t / 32; r < rows; r += kBlock / 32) {
+      const uint32_t j = s.aidx[r];
+      const int f = t % 32;
+      a.gfeat[(size_t)j * 32 + f] += s.dX[r][f];
+      if (f == 0) {
+        const float dist = s.Dn[r][0], u0 = s.Dn[r][1], u1 = s.Dn[r][2], u2 = s.Dn[r][3];
+        const float *dx = s.dX[r];
+        const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
+        const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
+        a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
+        a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
+        a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- this block's weight-gradient sums, one row of the workspace ----
+  float *pp = a.part + (size_t)blockIdx.x * a.P;
+#pragma unroll
+  for (int q = 0; q < kMaxT1; ++q) {
+    const int T = w + 4 * q;
+    if (T < 3 * n1t) {
+      const int rt = T / n1t, ct = T - rt * n1t;
+      const int col = ct * 16 + lc, h = col / W, hc = col - h * W;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int in = rt * 16 + 4 * g + i;
+        if (in < kIn) pp[(h * kIn + in) * W + hc] = acc1[q][i];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxT2; ++q) {
+    const int T = w + 4 * q;
+    if (T < nhw * n2t) {
+      const int rt = T / n2t, c = T - rt * n2t;
+      int col0;
+      const int h = out_head(a, c, col0);
+      const int col = col0 + lc, ncol = sel3(a.outs, h);
+      if (col < ncol) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pp[a.p_w2 + sel3(a.wo, h) + (rt * 16 + 4 * g + i) * ncol + col] = acc2[q][i];
+      }
+    }
+  }
+  if (t < 3 * W) pp[a.p_b1 + t] = db1r;
+  if (t < 16 * n2t) {
+    int col0;
+    const int h = out_head(a, t / 16, col0), col = col0 + t % 16;
+    const int hoff = h == 0 ? 0 : (h == 1 ? k : 4 * k);
+    if (col < sel3(a.outs, h)) pp[a.p_b2 + hoff + col] = db2r;
+  }
+}
+
+// Adds the blocks' rows, in block order, into the weight and bias gradients.
+struct DecRedArgs {
+  int P, nblk, k, W;
+  int p_w2, p_b1, p_b2;
+  const float *part;
+  float *w1[3], *b1[3], *w2[3], *b2[3];
+};
+
+__global__ __launch_bounds__(kBlock) void k_dec_bwd_reduce(DecRedArgs a) {
+  const int o = blockIdx.x * kBlock + threadIdx.x;
+  if (o >= a.P) return;
+  float sum = 0.0f;
+  for (int b = 0; b < a.nblk; ++b) sum += a.part[(size_t)b * a.P + o];
+  const int k = a.k, W = a.W;
+  float *dst;
+  if (o < a.p_w2) {
+    const int h = o / (kIn * W);
+    dst = pick3(a.w1, h) + (o - h * kIn * W);
+  } else if (o < a.p_b1) {
+    const int r = o - a.p_w2;
+    const int h = r < W * k ? 0 : (r < 4 * W * k ? 1 : 2);
+    dst = pick3(a.w2, h) + (r - (h == 0 ? 0 : (h == 1 ? W * k : 4 * W * k)));
+  } else if (o < a.p_b2) {
+    const int r = o - a.p_b1, h = r / W;
+    dst = pick3(a.b1, h) + (r - h * W);
+  } else {
+    const int r = o - a.p_b2;
+    const int h = r < k ? 0 : (r < 4 * k ? 1 : 2);
+    dst = pick3(a.b2, h) + (r - (h == 0 ? 0 : (h == 1 ? k : 4 * k)));
+  }
+  *dst += sum;
+}
+
+int partial_len(int k, int W) { return 3 * kIn * W + 11 * k * W + 3 * W + 11 * k; }
+
+int grid_for(int64_t mcap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((mcap + kRB - 1) / kRB, kDecBwdGrid));
 }
 
 }  // namespace
@@ -205,8 +483,9 @@ using namespace octgs;
 extern "C" {
 
 size_t octgs_decode_bwd_workspace_bytes(int64_t max_anchors, int32_t k, int32_t width) {
-  if (max_anchors < 0 || k < 1 || k > kMaxK || width < 1) return 0;
-  return bwd_layout(nullptr, max_anchors, k, width).bytes;
+  if (max_anchors < 0 || k < 1 || k > kMaxK || width < 16 || width > kMaxW || width % 16)
+    return 0;
+  return (size_t)grid_for(max_anchors) * (size_t)partial_len(k, width) * sizeof(float) + 256;
 }
 
 int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_camera *cam,
@@ -218,106 +497,53 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   if (cam->lod_blend) return OCTGS_EUNSUPPORTED;
   if (an->feat_dim != 32) return OCTGS_EUNSUPPORTED;
   if (an->k < 1 || an->k > kMaxK) return OCTGS_EUNSUPPORTED;
-  if (mlp->width < 16 || mlp->width > 64 || mlp->width % 16) return OCTGS_EUNSUPPORTED;
+  if (mlp->width < 16 || mlp->width > kMaxW || mlp->width % 16) return OCTGS_EUNSUPPORTED;
   if (!an->pos || !an->feat || !an->offsets || !an->offset_scale || !an->base_scale)
     return OCTGS_EINVAL;
   if (!ga->pos || !ga->feat || !ga->offsets || !ga->offset_scale || !ga->base_scale)
     return OCTGS_EINVAL;
-  for (int h = 0; h < 3; ++h)
+  for (int h = 0; h < 3; ++h) {
     if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h] || !gm->w1[h] || !gm->b1[h] ||
         !gm->w2[h] || !gm->b2[h])
       return OCTGS_EINVAL;
+    if (((uintptr_t)mlp->w1[h] | (uintptr_t)mlp->w2[h]) & 15) return OCTGS_EINVAL;
+  }
   if (gauss_capacity < an->k || !(an->d_max > 0.0f)) return OCTGS_EINVAL;
   const int k = an->k, W = mlp->width;
   const int64_t mcap = gauss_capacity / k;
   if (mcap > 0x7fffffff) return OCTGS_EINVAL;
   if (ws_bytes < octgs_decode_bwd_workspace_bytes(mcap, k, W)) return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
-  BwdLayout L = bwd_layout(ws, mcap, k, W);
-  BwdDecodeArgs a;
-  a.k = k; a.W = W; a.OT = 11 * k; a.F = 32;
+  DecBwdArgs a;
+  a.k = k; a.W = W; a.cap_anchors = (int)mcap;
   a.outs[0] = k; a.outs[1] = 3 * k; a.outs[2] = 7 * k;
-  a.off[0] = 0; a.off[1] = k; a.off[2] = 4 * k;
+  for (int h = 0; h < 3; ++h) a.t[h] = (a.outs[h] + 15) / 16;
+  a.offp[0] = 0; a.offp[1] = 16 * a.t[0]; a.offp[2] = 16 * (a.t[0] + a.t[1]);
+  a.wo[0] = 0; a.wo[1] = W * k; a.wo[2] = 4 * W * k;
+  a.P = partial_len(k, W);
+  a.p_w2 = 3 * kIn * W; a.p_b1 = a.p_w2 + 11 * k * W; a.p_b2 = a.p_b1 + 3 * W;
   a.inv_dmax = 1.0f / an->d_max;
   for (int c = 0; c < 3; ++c) a.C[c] = cam->C[c];
   a.pos = an->pos; a.feat = an->feat; a.offsets = an->offsets;
   a.oscale = an->offset_scale; a.bscale = an->base_scale;
-  a.idx = idx; a.count = count; a.cap_anchors = (int)mcap;
+  for (int h = 0; h < 3; ++h) {
+    a.w1[h] = mlp->w1[h]; a.b1[h] = mlp->b1[h]; a.w2[h] = mlp->w2[h]; a.b2[h] = mlp->b2[h];
+  }
+  a.idx = idx; a.count = count;
   a.dgauss = d_gauss; a.dstride = gauss_capacity;
-  a.X = L.X; a.Dn = L.Dn; a.Y = L.Y; a.dY = L.dY; a.dX = L.dX;
   a.gpos = ga->pos; a.gfeat = ga->feat; a.goff = ga->offsets;
   a.gosc = ga->offset_scale; a.gbsc = ga->base_scale;
-  // the per-anchor kernels give each anchor a row of 16 or 32 lanes
-  const int grid = (int)std::min<int64_t>((mcap * kGatherLanes + kBlock - 1) / kBlock, 4096);
-  const int grid16 = (int)std::min<int64_t>((mcap * 16 + kBlock - 1) / kBlock, 4096);
-  hipLaunchKernelGGL(k_bwd_gather, dim3(grid), dim3(kBlock), 0, s, a);
-  const int splitk = (int)std::min<int64_t>(std::max<int64_t>(mcap / 512, 1), 64);
-  hipError_t e = hipSuccess;
-  // Each product below runs for the three heads in one grouped launch.
-  // Forward recompute: Hp_h = X W1_h + b1_h; Y_h = relu(Hp_h) W2_h + b2_h.
-  Gemm g1 = gemm_base();
-  g1.groups = 3;
-  g1.lda = 36; g1.ldb = W; g1.ldc = 3 * W;
-  g1.M = (int)mcap; g1.K = 36; g1.dyn = count; g1.dyn_dim = 1; g1.dyn_cap = (int)mcap;
-  Gemm g2 = gemm_base();
-  g2.groups = 3;
-  g2.lda = 3 * W; g2.reluA = 1; g2.ldc = a.OT; g2.M = (int)mcap; g2.K = W;
-  g2.dyn = count; g2.dyn_dim = 1; g2.dyn_cap = (int)mcap;
-  // dW2_h += relu(Hp_h)^T dY_h
-  Gemm g3 = gemm_base();
-  g3.groups = 3;
-  g3.lda = 3 * W; g3.transA = 1; g3.reluA = 1; g3.ldb = a.OT;
-  g3.M = W; g3.K = (int)mcap; g3.dyn = count; g3.dyn_dim = 2; g3.dyn_cap = (int)mcap;
-  g3.accumulate = 1; g3.splitk = splitk;
-  // dHp_h = (dY_h W2_h^T) * (Hp_h > 0)
-  Gemm g4 = gemm_base();
-  g4.groups = 3;
-  g4.lda = a.OT; g4.transB = 1; g4.ldc = 3 * W; g4.ldm = 3 * W;
-  g4.M = (int)mcap; g4.dyn = count; g4.dyn_dim = 1; g4.dyn_cap = (int)mcap;
-  // dW1_h += X^T dHp_h
-  Gemm g5 = gemm_base();
-  g5.groups = 3;
-  g5.lda = 36; g5.transA = 1; g5.ldb = 3 * W; g5.ldc = W; g5.M = 36; g5.K = (int)mcap;
-  g5.dyn = count; g5.dyn_dim = 2; g5.dyn_cap = (int)mcap; g5.accumulate = 1; g5.splitk = splitk;
+  a.part = (float *)ws;
+  const int grid = grid_for(mcap);
+  hipLaunchKernelGGL(k_dec_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  DecRedArgs r;
+  r.P = a.P; r.nblk = grid; r.k = k; r.W = W;
+  r.p_w2 = a.p_w2; r.p_b1 = a.p_b1; r.p_b2 = a.p_b2;
+  r.part = a.part;
   for (int h = 0; h < 3; ++h) {
-    g1.A3[h] = L.X; g1.B3[h] = mlp->w1[h]; g1.C3[h] = L.Hp + h * W; g1.bias3[h] = mlp->b1[h];
-    g1.N3[h] = W;
-    g2.A3[h] = L.Hp + h * W; g2.B3[h] = mlp->w2[h]; g2.ldb3[h] = a.outs[h];
-    g2.C3[h] = L.Y + a.off[h]; g2.bias3[h] = mlp->b2[h]; g2.N3[h] = a.outs[h];
-    g3.A3[h] = L.Hp + h * W; g3.B3[h] = L.dY + a.off[h]; g3.C3[h] = gm->w2[h];
-    g3.ldc3[h] = a.outs[h]; g3.N3[h] = a.outs[h];
-    g4.A3[h] = L.dY + a.off[h]; g4.B3[h] = mlp->w2[h]; g4.ldb3[h] = a.outs[h];
-    g4.C3[h] = L.dHp + h * W; g4.mask3[h] = L.Hp + h * W; g4.N3[h] = W; g4.K3[h] = a.outs[h];
-    g5.A3[h] = L.X; g5.B3[h] = L.dHp + h * W; g5.C3[h] = gm->w1[h]; g5.N3[h] = W;
+    r.w1[h] = gm->w1[h]; r.b1[h] = gm->b1[h]; r.w2[h] = gm->w2[h]; r.b2[h] = gm->b2[h];
   }
-  if ((e = gemm(g1, mcap, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = gemm(g2, mcap, s)) != hipSuccess) return OCTGS_EHIP;
-  hipLaunchKernelGGL(k_act_bwd, dim3(grid16), dim3(kBlock), 0, s, a);
-  if ((e = gemm(g3, W, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = gemm(g4, mcap, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = gemm(g5, 36, s)) != hipSuccess) return OCTGS_EHIP;
-  {
-    // db2_h += column sums of dY_h; db1_h += column sums of dHp_h
-    const float *Y3[3] = {L.dY + a.off[0], L.dY + a.off[1], L.dY + a.off[2]};
-    float *o3[3] = {gm->b2[0], gm->b2[1], gm->b2[2]};
-    if ((e = colsum3(Y3, (int64_t)a.OT, a.outs, count, (int)mcap, o3, s)) != hipSuccess)
-      return OCTGS_EHIP;
-    const float *H3[3] = {L.dHp, L.dHp + W, L.dHp + 2 * W};
-    float *p3[3] = {gm->b1[0], gm->b1[1], gm->b1[2]};
-    const int nw[3] = {W, W, W};
-    if ((e = colsum3(H3, (int64_t)(3 * W), nw, count, (int)mcap, p3, s)) != hipSuccess)
-      return OCTGS_EHIP;
-  }
-  // dX = sum over heads of dHp_h W1_h^T (accumulated head by head)
-  for (int h = 0; h < 3 && e == hipSuccess; ++h) {
-    Gemm g6 = gemm_base();
-    g6.A = L.dHp + h * W; g6.lda = 3 * W; g6.B = mlp->w1[h]; g6.ldb = W; g6.transB = 1;
-    g6.C = L.dX; g6.ldc = 36; g6.M = (int)mcap; g6.N = 36; g6.K = W;
-    g6.dyn = count; g6.dyn_dim = 1; g6.dyn_cap = (int)mcap; g6.accumulate = h > 0 ? 1 : 0;
-    e = gemm(g6, mcap, s);
-  }
-  if (e != hipSuccess) return OCTGS_EHIP;
-  hipLaunchKernelGGL(k_x_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_dec_bwd_reduce, dim3((a.P + kBlock - 1) / kBlock), dim3(kBlock), 0, s, r);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

@@ -195,8 +195,8 @@ struct RasterWs {
   uint32_t *run_first;    // [nruns] depth-order index of the survivor holding candidate kEmitRun r
   uint32_t *lb_pair;      // [nruns] look-back status of the emission's runs
   uint32_t *tkey[2];      // [pcap] tile keys (ping-pong)
-  uint32_t *tval[2];      // [pcap] tile-sort values: the pair's emission index; after the sort,
-                          // the other buffer holds the slot of each sorted pair
+  uint32_t *tval[2];      // [pcap] slot ids
+  uint32_t *tpair[2];     // [pcap] each pair's emission index, carried by the tile sort
   uint32_t *pair_slot;    // [pcap] slot of each pair in emission order (a Gaussian's pairs
                           // are contiguous there)
   uint32_t *ranges;       // [tiles][2]
@@ -239,9 +239,9 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 // lookback: passes * ceil(cap / kSortPart) * 256 words.  With prepared ==
 // false a first kernel builds hist ([passes][256], zeroed beforehand) and
 // clears the look-back words; with prepared == true the caller has done both.
-hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
-                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *err_flag,
-                      bool prepared, hipStream_t stream);
+hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
+                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
+                      uint32_t *lookback, uint32_t *err_flag, bool prepared, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // chained scan: decoupled look-back over one value per partition

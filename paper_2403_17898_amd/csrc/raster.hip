@@ -544,7 +544,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
       const uint32_t dst = excl + gpre[g] + (uint32_t)__popcll(m & lanemask_lt());
       if (dst < P) {  // always true unless a look-back wait hit its bound
         ws.tkey[0][dst] = key[k];
-        ws.tval[0][dst] = dst;
+        ws.tval[0][dst] = val[k];
+        ws.tpair[0][dst] = dst;
         ws.pair_slot[dst] = val[k];
       }
       for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
@@ -562,13 +563,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
     }
 }
 
-// Tile ranges of the sorted list, and the slot of every sorted pair (the
-// sort carried the pair's emission index) into the free ping-pong buffer.
 __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
   const uint32_t P = ws.hdr->n_listed;
   const uint32_t *key = ws.tkey[buf];
   for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
-    ws.tval[buf ^ 1][p] = ws.pair_slot[ws.tval[buf][p]];
     const uint32_t k = key[p];
     if (p == 0 || key[p - 1] != k) ws.ranges[2 * k] = p;
     if (p == P - 1 || key[p + 1] != k) ws.ranges[2 * k + 1] = p + 1;
@@ -628,7 +626,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
   const float fx = (float)px + 0.5f, fy = (float)py0 + 0.5f;
   const uint32_t start = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(a.ws.ranges[2 * tile + 1]);
-  const uint32_t *vals = a.ws.tval[a.buf ^ 1];  // slot of each sorted pair
+  const uint32_t *vals = a.ws.tval[a.buf];
   const float4 *proj = a.ws.proj;
   const float amax = a.alpha_max, amin = a.alpha_min, tmin = a.t_min;
   float T[kPx], cr[kPx], cg[kPx], cb[kPx];
@@ -773,6 +771,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.lb_pair = (uint32_t *)take((size_t)ws.nruns * 4);
   for (int i = 0; i < 2; ++i) ws.tkey[i] = (uint32_t *)take((size_t)pc * 4);
   for (int i = 0; i < 2; ++i) ws.tval[i] = (uint32_t *)take((size_t)pc * 4);
+  for (int i = 0; i < 2; ++i) ws.tpair[i] = (uint32_t *)take((size_t)pc * 4);
   ws.pair_slot = (uint32_t *)take((size_t)pc * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
   ws.hist = (uint32_t *)take(8 * 256 * 4);
@@ -846,7 +845,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(1);
   mark(2);
   // histograms and cleared look-back words come from the kernels above
-  hipError_t e = radix_sort(ws.dkey, ws.dval, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
+  hipError_t e = radix_sort(ws.dkey, ws.dval, nullptr, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
                             ws.lookback, &ws.hdr->sync_error, true, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   mark(3);
@@ -857,7 +856,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(5);
   mark(6);
   const int passes = ws.tile_passes;
-  e = radix_sort(ws.tkey, ws.tval, &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
+  e = radix_sort(ws.tkey, ws.tval, ws.tpair, &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
                  ws.lookback_t, &ws.hdr->sync_error, true, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;
@@ -896,7 +895,7 @@ int octgs_raster_views(const void *wsp, int64_t gauss_capacity, int64_t pair_cap
   const int buf = tile_sort_passes(ws.tiles_x * ws.tiles_y) % 2;
   if (stats) *stats = (const octgs_raster_stats *)ws.hdr;
   if (pair_tile) *pair_tile = ws.tkey[buf];
-  if (pair_slot) *pair_slot = ws.tval[buf ^ 1];
+  if (pair_slot) *pair_slot = ws.tval[buf];
   if (tile_ranges) *tile_ranges = ws.ranges;
   return OCTGS_OK;
 }

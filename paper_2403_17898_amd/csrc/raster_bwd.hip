@@ -105,8 +105,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
   const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kBPx * (t / kTile);
   const float fx = (float)px + 0.5f, fy = (float)py0 + 0.5f;
   const uint32_t start = a.ws.ranges[2 * tile], end = a.ws.ranges[2 * tile + 1];
-  const uint32_t *vals = a.ws.tval[a.buf ^ 1];  // slot of each sorted pair
-  const uint32_t *pidx = a.ws.tval[a.buf];      // its emission index
+  const uint32_t *vals = a.ws.tval[a.buf];   // slot of each sorted pair
+  const uint32_t *pidx = a.ws.tpair[a.buf];  // its emission index
   const float4 *proj = a.ws.proj;
   const size_t plane = (size_t)a.W * a.H;
   // per pixel: T, dL/dC, colour behind (starts as T_final * bg), entries used

@@ -1,4 +1,4 @@
-// Stable LSD radix sort of (u32 key, u32 value) pairs, 8-bit digits, in the
+// Stable LSD radix sort of u32 keys carrying one or two u32 values, 8-bit digits, in the
 // Onesweep structure (Adinets and Merrill, "Onesweep: A Faster Least
 // Significant Digit Radix Sort for GPUs", 2022): one kernel builds the
 // digit histograms of all passes, then each pass is a single kernel whose
@@ -52,22 +52,26 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint32_t *__restrict
   }
 }
 
+template <int NV>
 struct PassSmem {
   uint32_t wcnt[4][256];     // per-wave digit counters, then per-wave exclusive offsets
   uint32_t dstart[256];      // local start of each digit in the partition
   uint32_t gbase[256];       // global write base of each digit for this partition
   uint32_t hexcl[256];       // global exclusive prefix of the pass histogram
   uint32_t keys[kSortPart];
-  uint32_t vals[kSortPart];
+  uint32_t vals[NV][kSortPart];
   uint32_t tmp[8];
 };
 
+// NV = 1 or 2 value arrays travel with the keys.
+template <int NV>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const uint32_t *__restrict__ count,
-    int shift, const uint32_t *__restrict__ hist, uint32_t *__restrict__ lookback,
+    const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    uint32_t *__restrict__ vout2, const uint32_t *__restrict__ count, int shift,
+    const uint32_t *__restrict__ hist, uint32_t *__restrict__ lookback,
     uint32_t *__restrict__ err_flag) {
-  __shared__ PassSmem sm;
+  __shared__ PassSmem<NV> sm;
   const uint32_t n = *count;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t base = part * kSortPart;
 
     // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    uint32_t key[kSortItems], val[kSortItems], val2[kSortItems], rank[kSortItems];
     int dig[kSortItems];
     // unconditional loads at a clamped index keep all of them in flight
     // together; items past the end are masked by dig = -1
@@ -98,6 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
       const uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
       key[j] = kin[min(idx, n - 1)];
       val[j] = vin[min(idx, n - 1)];
+      if (NV == 2) val2[j] = vin2[min(idx, n - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
@@ -188,7 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
       if (dig[j] >= 0) {
         uint32_t pos = sm.wcnt[w][dig[j]] + rank[j];
         sm.keys[pos] = key[j];
-        sm.vals[pos] = val[j];
+        sm.vals[0][pos] = val[j];
+        if (NV == 2) sm.vals[NV - 1][pos] = val2[j];
       }
     }
     __syncthreads();
@@ -199,7 +205,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
       uint32_t dst = sm.gbase[d] + (i - sm.dstart[d]);
       if (dst < n) {  // always true unless a look-back wait hit its bound
         kout[dst] = k;
-        vout[dst] = sm.vals[i];
+        vout[dst] = sm.vals[0][i];
+        if (NV == 2) vout2[dst] = sm.vals[NV - 1][i];
       }
     }
   }
@@ -207,9 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 
 }  // namespace
 
-hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *count, int64_t cap,
-                      int passes, uint32_t *hist, uint32_t *lookback, uint32_t *err_flag,
-                      bool prepared, hipStream_t stream) {
+hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
+                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
+                      uint32_t *lookback, uint32_t *err_flag, bool prepared,
+                      hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
   const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 256);
@@ -221,9 +229,14 @@ hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *coun
   const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
-                       vals[src], keys[dst], vals[dst], count, 8 * p, hist + 256 * p,
-                       lookback + lb_stride * p, err_flag);
+    if (vals2)
+      hipLaunchKernelGGL(k_sort_pass<2>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
+                         vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p,
+                         hist + 256 * p, lookback + lb_stride * p, err_flag);
+    else
+      hipLaunchKernelGGL(k_sort_pass<1>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
+                         vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p,
+                         hist + 256 * p, lookback + lb_stride * p, err_flag);
   }
   return hipGetLastError();
 }
