@@ -518,8 +518,8 @@ def train_step_timing(args, P, S, torch, np):
     ds = P.DeviceScene.from_scene(sc)
     dt = P.DeviceScene.from_scene(tgt_scene)
     cams = [P.make_camera(c) for c in views]
-    prm = P.raster_params()
     W, H = views[0].width, views[0].height
+    prm = P.raster_params(train=True)
     vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=16 << 20)
     targets, max_sel, max_pairs = [], 0, 0
     for c in cams:

@@ -127,7 +127,13 @@ typedef struct {
 typedef struct {
   float alpha_max, alpha_min, t_min, dilation, jac_clamp;
   float bg[3];
+  uint32_t flags; /* OCTGS_RASTER_* bits */
 } octgs_raster_params;
+
+/* flags: the forward keeps what octgs_rasterize_bwd needs (each sorted
+ * pair's emission index, carried through the tile sort); required for a
+ * later backward of the same frame, off for rendering only. */
+#define OCTGS_RASTER_TRAIN 1u
 
 #define OCTGS_RASTER_STAGES 5
 
@@ -223,7 +229,8 @@ OCTGS_API int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *
  * its tile list in reverse from the entry count `last` the forward stored and
  * recovers transmittance as T_i = T_{i+1} / (1 - a_i) from T_final, so no
  * per-pixel list is kept.  g, cam, p, the capacities and the workspace must be
- * those of the forward call, unchanged since. */
+ * those of the forward call, unchanged since; p->flags must include
+ * OCTGS_RASTER_TRAIN (OCTGS_EINVAL otherwise). */
 OCTGS_API int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera *cam,
                                   const octgs_raster_params *p, int64_t pair_capacity,
                                   const float *T_final, const uint32_t *last,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboctgs.so")
 OCTGS_OK, OCTGS_EINVAL, OCTGS_ENOSPC, OCTGS_EHIP, OCTGS_EUNSUPPORTED = 0, -1, -2, -3, -4
 OCTGS_FP32, OCTGS_BF16 = 0, 1
 OCTGS_RASTER_STAGES = 5
+OCTGS_RASTER_TRAIN = 1
 RASTER_STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
 
 _p = ctypes.c_void_p
@@ -48,7 +49,7 @@ class Gaussians(ctypes.Structure):
 
 class RasterParams(ctypes.Structure):
     _fields_ = [("alpha_max", _f), ("alpha_min", _f), ("t_min", _f), ("dilation", _f),
-                ("jac_clamp", _f), ("bg", _f * 3)]
+                ("jac_clamp", _f), ("bg", _f * 3), ("flags", ctypes.c_uint32)]
 
 
 class AnchorGrads(ctypes.Structure):

@@ -856,7 +856,8 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(5);
   mark(6);
   const int passes = ws.tile_passes;
-  e = radix_sort(ws.tkey, ws.tval, ws.tpair, &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
+  e = radix_sort(ws.tkey, ws.tval, (p->flags & OCTGS_RASTER_TRAIN) ? ws.tpair : nullptr,
+                 &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
                  ws.lookback_t, &ws.hdr->sync_error, true, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;

@@ -457,6 +457,8 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
                                    const float *dL_drgb, float *d_gauss, void *wsp,
                                    size_t ws_bytes, octgs_stream stream) {
   if (!g || !cam || !p || !T_final || !last || !dL_drgb || !d_gauss || !wsp) return OCTGS_EINVAL;
+  // the pair indices of the forward's tile sort are kept only in training mode
+  if (!(p->flags & OCTGS_RASTER_TRAIN)) return OCTGS_EINVAL;
   if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
     return OCTGS_EINVAL;
   if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30)) return OCTGS_EINVAL;

@@ -65,12 +65,15 @@ def make_camera(cam, lod_blend: bool = False) -> L.Camera:
 
 
 def raster_params(alpha_max=0.99, alpha_min=0.0, t_min=1e-4, dilation=0.3, jac_clamp=1.3,
-                  bg=(0.0, 0.0, 0.0)) -> L.RasterParams:
+                  bg=(0.0, 0.0, 0.0), train: bool = False) -> L.RasterParams:
+    """Rasterizer constants; train=True makes the forward keep what the
+    backward pass needs (required before rasterize_bwd)."""
     p = L.RasterParams()
     p.alpha_max, p.alpha_min, p.t_min = alpha_max, alpha_min, t_min
     p.dilation, p.jac_clamp = dilation, jac_clamp
     for i in range(3):
         p.bg[i] = bg[i]
+    p.flags = L.OCTGS_RASTER_TRAIN if train else 0
     return p
 
 
@@ -468,7 +471,8 @@ class ViewBuffers:
 
 class RenderFn(torch.autograd.Function):
     """Differentiable view render: decode + rasterize forward through the
-    library, backward through octgs_rasterize_bwd and octgs_decode_bwd.
+    library, backward through octgs_rasterize_bwd and octgs_decode_bwd
+    (params made with raster_params(train=True)).
     The inputs after the first four are the scene's trainable tensors (the
     ones the DeviceScene points to), in PARAM_NAMES then sorted MLP-key order;
     their gradients are returned."""

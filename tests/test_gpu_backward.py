@@ -50,10 +50,10 @@ def test_raster_backward_parity(P, orc, W, H, n, seed):
     gt = torch.as_tensor(gf).cuda()
     cnt = torch.tensor([n], dtype=torch.int32).cuda()
     c = P.make_camera(cam)
-    vb.rasterize(c, P.raster_params(), gauss=gt, count=cnt)
+    vb.rasterize(c, P.raster_params(train=True), gauss=gt, count=cnt)
     vb.gauss.copy_(gt)  # the backward reads the Gaussians of the forward call
     vb.gauss_count.copy_(cnt)
-    vb.rasterize_bwd(c, P.raster_params(), torch.as_tensor(dimg).cuda())
+    vb.rasterize_bwd(c, P.raster_params(train=True), torch.as_tensor(dimg).cuda())
     torch.cuda.synchronize()
     got = _np(vb.dgauss).astype(np.float64)
     names = ("mean", "scale", "quat", "opacity", "rgb")
@@ -102,7 +102,7 @@ def test_full_chain_gradient(P, orc):
     ds = P.DeviceScene.from_scene(sc)
     vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
     c = P.make_camera(cam)
-    pr = P.raster_params()
+    pr = P.raster_params(train=True)
     vb.render(ds, c, pr)
     vb.rasterize_bwd(c, pr, torch.as_tensor(dimg).cuda())
     grads = P.SceneGrads(ds)
@@ -172,7 +172,7 @@ def test_autograd_function_matches_direct(P):
     sc, cam = S.make_gradcheck_scene()
     ds = P.DeviceScene.from_scene(sc)
     c = P.make_camera(cam)
-    pr = P.raster_params()
+    pr = P.raster_params(train=True)
     vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 16)
     ts = P.trainable(ds)
     for t in ts:
@@ -193,3 +193,17 @@ def test_autograd_function_matches_direct(P):
     for t, nm in zip(ts, names):
         assert t.grad is not None, nm
         assert rel(_np(t.grad), _np(direct[nm])) <= 1e-5, nm
+
+
+def test_backward_needs_training_forward(P):
+    """The forward keeps the pair indices the backward needs only in
+    training mode; the backward refuses parameters without that flag."""
+    cam = S.look_at((0.0, -8.0, 0.0), (0.0, 0.0, 0.0), 32, 32, 60.0)
+    gf = S.random_gaussians(50, cam, 3)
+    vb = P.ViewBuffers(50, 1, 32, 32, 1 << 12, gauss_capacity=50)
+    gt = torch.as_tensor(gf).cuda()
+    cnt = torch.tensor([50], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    vb.rasterize(c, P.raster_params(), gauss=gt, count=cnt)
+    with pytest.raises(P.OctgsError):
+        vb.rasterize_bwd(c, P.raster_params(), torch.zeros(3, 32, 32, device="cuda"))

@@ -99,7 +99,7 @@ def test_decide_empty(P):
 def test_accumulate_parity(P, orc, DO):
     sc = S.make_config1()
     ds = P.DeviceScene.from_scene(sc)
-    prm = P.raster_params()
+    prm = P.raster_params(train=True)
     d = np.array([1.0, -2.0, 1.5]) / np.linalg.norm([1.0, -2.0, 1.5])
     cams = [S.config1_camera(), S.look_at(12.0 * d, (0, 0, 0), 128, 128, 60.0),
             S.look_at((2.0, -3.0, 1.0), (0.0, 0.0, 0.0), 97, 61, 70.0)]

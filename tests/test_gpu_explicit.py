@@ -240,7 +240,7 @@ def test_explicit_full_chain_gradient(P, orc, EX):
     sc, cam = S.make_gradcheck_scene()
     ex = S.make_explicit(sc, sh_degree=3, seed=12)
     de = P.DeviceExplicit.from_scene(ex)
-    prm = P.raster_params()
+    prm = P.raster_params(train=True)
     vb = P.ViewBuffers(ex.n, ex.k, cam.width, cam.height, 1 << 16)
     c = P.make_camera(cam)
     vb.render_explicit(de, c, prm)

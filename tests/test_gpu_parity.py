@@ -371,8 +371,8 @@ def test_decode_bwd_rejects_blend(P, c1):
     ds = P.DeviceScene.from_scene(sc)
     cam = S.config1_camera()
     vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
-    vb.render(ds, P.make_camera(cam), P.raster_params())
-    vb.rasterize_bwd(P.make_camera(cam), P.raster_params(), torch.ones_like(vb.rgb))
+    vb.render(ds, P.make_camera(cam), P.raster_params(train=True))
+    vb.rasterize_bwd(P.make_camera(cam), P.raster_params(train=True), torch.ones_like(vb.rgb))
     grads = P.SceneGrads(ds)
     with pytest.raises(P.OctgsError):
         vb.decode_bwd(ds, P.make_camera(cam, lod_blend=True), grads)
