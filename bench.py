@@ -537,6 +537,7 @@ def train_step_timing(args, P, S, torch, np):
     gl = grads.all()
     gtens = [gl[n] for n in gnames]
     mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    adam = P.AdamMany(params, gtens, mom)
     dimg = torch.empty(3, H, W, device=params[0].device)
     loss = torch.zeros(1, device=params[0].device)
     scale = 1.0 / (len(cams) * 3 * H * W)
@@ -565,8 +566,7 @@ def train_step_timing(args, P, S, torch, np):
         if timer is not None:
             timer.record()
         state["step"] += 1
-        for p_, g_, (m_, v_) in zip(params, gtens, mom):
-            P.adam_step(p_, g_, m_, v_, 1e-3, state["step"])
+        adam.step(1e-3, state["step"])
 
     def timed_steps(full):
         for _ in range(3):

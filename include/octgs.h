@@ -308,6 +308,14 @@ OCTGS_API int octgs_adam_step(float *param, const float *grad, float *m, float *
                               float lr, float beta1, float beta2, float eps, int32_t step,
                               octgs_stream stream);
 
+/* The same update for count arrays at once (one launch per 32 arrays):
+ * params[i], grads[i], m[i], v[i] are device arrays of n[i] floats; the
+ * pointer tables and n are host arrays read during the call. */
+OCTGS_API int octgs_adam_step_many(int32_t count, float *const *params, const float *const *grads,
+                                   float *const *m, float *const *v, const int64_t *n, float lr,
+                                   float beta1, float beta2, float eps, int32_t step,
+                                   octgs_stream stream);
+
 /* ---- learned anchor skip ---------------------------------------------
  * A per-anchor contribution predictor extending the view-dependent anchor
  * selection of Sec. IV-A: input z = [feature (32), unit direction camera ->

@@ -5,7 +5,7 @@
 """
 
 from ._lib import (OCTGS_BF16, OCTGS_FP32, OctgsError, lib)  # noqa: F401
-from .render import (DensifyStats, DeviceExplicit, DeviceScene, ExplicitGrads, RenderFn,  # noqa: F401
+from .render import (AdamMany, DensifyStats, DeviceExplicit, DeviceScene, ExplicitGrads, RenderFn,  # noqa: F401
                      SceneGrads, ViewBuffers, adam_step, l1_loss_grad, make_camera,
                      photometric_loss_grad, raster_params, render_diff, stream_handle,
                      trainable)

@@ -116,6 +116,7 @@ SIGNATURES = [
                                            ctypes.c_size_t, _p]),
     ("octgs_volume_loss_grad", _i32, [ctypes.POINTER(Gaussians), _f, _p, _p, _p]),
     ("octgs_adam_step", _i32, [_p, _p, _p, _p, _i64, _f, _f, _f, _f, _i32, _p]),
+    ("octgs_adam_step_many", _i32, [_i32, _p, _p, _p, _p, _p, _f, _f, _f, _f, _i32, _p]),
     ("octgs_anchor_weights", _i32, [_p, _p, _i32, _i64, _p, _p]),
     ("octgs_skip_features", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _i64,
                                    _p, _p]),

@@ -443,11 +443,34 @@ struct DecRedArgs {
   float *w1[3], *b1[3], *w2[3], *b2[3];
 };
 
+// 64 outputs per block, four thread groups per output, each summing every
+// fourth row with eight loads in flight; the four group sums are added in a
+// fixed order.
+constexpr int kRedOut = 64;
+
 __global__ __launch_bounds__(kBlock) void k_dec_bwd_reduce(DecRedArgs a) {
-  const int o = blockIdx.x * kBlock + threadIdx.x;
-  if (o >= a.P) return;
+  __shared__ float red[kBlock / kRedOut][kRedOut];
+  const int oc = threadIdx.x % kRedOut, grp = threadIdx.x / kRedOut;
+  const int o = blockIdx.x * kRedOut + oc;
+  const int oo = min(o, a.P - 1);
+  float part = 0.0f;
+  for (int b0 = grp; b0 < a.nblk; b0 += 8 * (kBlock / kRedOut)) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = min(b0 + u * (kBlock / kRedOut), a.nblk - 1);
+      v[u] = a.part[(size_t)b * a.P + oo];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u * (kBlock / kRedOut) < a.nblk) part += v[u];
+  }
+  red[grp][oc] = part;
+  __syncthreads();
+  if (grp != 0 || o >= a.P) return;
   float sum = 0.0f;
-  for (int b = 0; b < a.nblk; ++b) sum += a.part[(size_t)b * a.P + o];
+#pragma unroll
+  for (int q = 0; q < kBlock / kRedOut; ++q) sum += red[q][oc];
   const int k = a.k, W = a.W;
   float *dst;
   if (o < a.p_w2) {
@@ -543,7 +566,7 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   for (int h = 0; h < 3; ++h) {
     r.w1[h] = gm->w1[h]; r.b1[h] = gm->b1[h]; r.w2[h] = gm->w2[h]; r.b2[h] = gm->b2[h];
   }
-  hipLaunchKernelGGL(k_dec_bwd_reduce, dim3((a.P + kBlock - 1) / kBlock), dim3(kBlock), 0, s, r);
+  hipLaunchKernelGGL(k_dec_bwd_reduce, dim3((a.P + kRedOut - 1) / kRedOut), dim3(kBlock), 0, s, r);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

@@ -254,43 +254,53 @@ __global__ __launch_bounds__(kBwdThreads) void k_composite_bwd(BwdArgs a) {
 }
 
 // Per-Gaussian sums of the per-pair gradients.  A Gaussian's pairs are
-// contiguous in emission order; each run is summed in chunks that end at
-// multiples of kRedChunk, so no thread walks more than kRedChunk pairs.  A
-// run held by one chunk is stored, the chunks of a longer run are added
-// atomically (the slot's row was zeroed first).
-constexpr uint32_t kRedChunk = 32;
-
+// contiguous in emission order.  Each wave takes 64 consecutive pairs and
+// runs a segmented inclusive scan keyed by slot (six shuffle steps); the last
+// lane of each run then holds the run's sum.  A run that lies inside the
+// wave's 64 pairs is stored; a run cut by the wave's first or last pair is
+// added atomically (the slot rows were zeroed first), at most two per wave.
 __global__ __launch_bounds__(kBlock) void k_pair_reduce(RasterWs ws) {
   const uint32_t P = ws.hdr->n_listed;
-  for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {
-    const uint32_t s = ws.pair_slot[p];
-    const bool run_start = p == 0 || ws.pair_slot[p - 1] != s;
-    if (!run_start && p % kRedChunk != 0) continue;
-    const uint32_t lim = min(P, (p / kRedChunk + 1) * kRedChunk);
-    float acc[9];
+  const int l = __lane_id();
+  const uint32_t nw = gridDim.x * (kBlock / kWave);
+  for (uint32_t c0 = (blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (uint32_t)kWave; c0 < P;
+       c0 += nw * kWave) {
+    const uint32_t p = c0 + l;
+    const bool valid = p < P;
+    const uint32_t pc = valid ? p : P - 1;
+    const uint32_t s = valid ? ws.pair_slot[pc] : 0xffffffffu;
+    float v[9];
+    const float *gp = ws.gpair + 9 * (size_t)pc;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-    uint32_t q = p;
-    bool more = false;
-    while (true) {
-      const float *gp = ws.gpair + 9 * (size_t)q;
+    for (int k = 0; k < 9; ++k) v[k] = valid ? gp[k] : 0.0f;
+    const uint32_t sp = __shfl_up(s, 1, kWave);
+    const bool head = l == 0 || sp != s;
+    const uint64_t heads = ballot(head);
+    // lane of this run's head within the wave
+    const int hl = 63 - __builtin_clzll(heads & (lanemask_lt() | (1ull << l)));
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc[k] += gp[k];
-      ++q;
-      if (q >= P || ws.pair_slot[q] != s) break;
-      if (q >= lim) {
-        more = true;
-        break;
+    for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float u = __shfl_up(v[k], d, kWave);
+        if (l - d >= hl) v[k] += u;
       }
     }
-    float *d = ws.dproj + 9 * (size_t)s;
-    if (run_start && !more) {
+    const uint32_t sn = __shfl_down(s, 1, kWave);
+    const bool tail = valid && (l == kWave - 1 || sn != s);
+    if (tail) {
+      // does the run continue across the wave's boundaries?
+      const bool from_prev = hl == 0 && c0 > 0 && ws.pair_slot[c0 - 1] == s;
+      const bool into_next = l == kWave - 1 && p + 1 < P && ws.pair_slot[p + 1] == s;
+      float *d = ws.dproj + 9 * (size_t)s;
+      if (!from_prev && !into_next) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) d[k] = acc[k];
-    } else {
+        for (int k = 0; k < 9; ++k) d[k] = v[k];
+      } else {
 #pragma unroll
-      for (int k = 0; k < 9; ++k)
-        if (acc[k] != 0.0f) atomicAdd(d + k, acc[k]);
+        for (int k = 0; k < 9; ++k)
+          if (v[k] != 0.0f) atomicAdd(d + k, v[k]);
+      }
     }
   }
 }
@@ -482,7 +492,7 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   b.dimg = dL_drgb;
   b.last = last;
   hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kBwdThreads), 0, s, b);
-  const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 4096);
+  const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 2048);
   hipLaunchKernelGGL(k_pair_reduce, dim3(rgrid), dim3(kBlock), 0, s, ws);
   PBwdArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];

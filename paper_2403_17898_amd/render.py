@@ -307,6 +307,28 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
                                     stream_handle(stream)), "octgs_adam_step")
 
 
+class AdamMany:
+    """One Adam update of several device arrays per launch; the pointer
+    tables are built once for a fixed list of (param, grad, m, v)."""
+
+    def __init__(self, params, grads, moments):
+        cnt = len(params)
+        arr = lambda ts: (ctypes.c_void_p * max(1, cnt))(*[t.data_ptr() for t in ts])
+        self.count = cnt
+        self._p = arr(params)
+        self._g = arr(grads)
+        self._m = arr([m for m, _ in moments])
+        self._v = arr([v for _, v in moments])
+        self._n = (ctypes.c_int64 * max(1, cnt))(*[p.numel() for p in params])
+        self._keep = (params, grads, moments)
+
+    def step(self, lr: float, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+        L.check(L.lib().octgs_adam_step_many(self.count, self._p, self._g, self._m, self._v,
+                                             self._n, float(lr), float(beta1), float(beta2),
+                                             float(eps), int(step), stream_handle(stream)),
+                "octgs_adam_step_many")
+
+
 class ViewBuffers:
     """Per-view device buffers: selection, decoded Gaussians, rasterizer
     workspace and outputs, sized for a scene, an image and a pair capacity."""

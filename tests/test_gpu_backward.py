@@ -207,3 +207,27 @@ def test_backward_needs_training_forward(P):
     vb.rasterize(c, P.raster_params(), gauss=gt, count=cnt)
     with pytest.raises(P.OctgsError):
         vb.rasterize_bwd(c, P.raster_params(), torch.zeros(3, 32, 32, device="cuda"))
+
+
+def test_adam_many_matches_single(P):
+    """One launch over several arrays (sizes across chunk boundaries, an
+    empty one) updates each exactly as the single-array update does."""
+    rng = np.random.default_rng(11)
+    sizes = [1, 4095, 4096, 4097, 0, 100_003, 37]
+    mk = lambda n: torch.as_tensor(rng.standard_normal(n).astype(np.float32)).cuda()
+    ps = [mk(n) for n in sizes]
+    gs = [mk(n) for n in sizes]
+    ms = [(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")) for n in sizes]
+    ref_p = [p.clone() for p in ps]
+    ref_m = [(m.clone(), v.clone()) for m, v in ms]
+    opt = P.AdamMany(ps, gs, ms)
+    for step in (1, 2, 3):
+        opt.step(1e-2, step, eps=1e-8)
+        for p, g, (m, v) in zip(ref_p, gs, ref_m):
+            if p.numel():
+                P.adam_step(p, g, m, v, 1e-2, step, eps=1e-8)
+    torch.cuda.synchronize()
+    for a, b in zip(ps, ref_p):
+        assert torch.equal(a, b)
+    for (m1, v1), (m2, v2) in zip(ms, ref_m):
+        assert torch.equal(m1, m2) and torch.equal(v1, v2)
