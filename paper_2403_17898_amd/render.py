@@ -253,8 +253,19 @@ class SceneGrads:
     """Device gradient buffers shaped like a DeviceScene's trainable arrays."""
 
     def __init__(self, scene: "DeviceScene"):
-        self.arrays = {n: torch.zeros_like(getattr(scene, n)) for n in PARAM_NAMES}
-        self.mlp = {k: torch.zeros_like(v) for k, v in scene.mlp.items()}
+        # one flat buffer (each array 256-byte aligned), so zeroing is one launch
+        shapes = [(n, getattr(scene, n).shape) for n in PARAM_NAMES]
+        shapes += [(k, v.shape) for k, v in scene.mlp.items()]
+        sizes = [int(np.prod(sh)) for _, sh in shapes]
+        offs, o = [], 0
+        for n_ in sizes:
+            offs.append(o)
+            o += (n_ + 63) // 64 * 64
+        self.flat = torch.zeros(max(o, 1), dtype=torch.float32, device=scene.pos.device)
+        views = {name: self.flat[off:off + n_].view(sh)
+                 for (name, sh), off, n_ in zip(shapes, offs, sizes)}
+        self.arrays = {n: views[n] for n in PARAM_NAMES}
+        self.mlp = {k: views[k] for k in scene.mlp}
         self._ag = L.AnchorGrads(*[self.arrays[n].data_ptr() for n in PARAM_NAMES])
         self._mg = L.MlpGrads()
         for h, name in enumerate(MLP_HEADS):
@@ -264,8 +275,7 @@ class SceneGrads:
             self._mg.b2[h] = self.mlp["b2_" + name].data_ptr()
 
     def zero_(self):
-        for t in list(self.arrays.values()) + list(self.mlp.values()):
-            t.zero_()
+        self.flat.zero_()
 
     def all(self) -> Dict[str, torch.Tensor]:
         d = dict(self.arrays)
