@@ -7,11 +7,12 @@
 //
 // Layout and traffic.  The SH block of a Gaussian ((D+1)^2 x 3 values, 192 B
 // in FP32 at degree 3) dominates the bytes.  Each block of 256 threads owns
-// 256 consecutive output slots; the slots of one listed anchor are k
+// consecutive output slots; the slots of one listed anchor are k
 // consecutive Gaussians in memory, so the block first copies all its SH rows
 // into LDS with consecutive lanes reading consecutive 16-byte words (whole
 // cache lines per instruction), then each thread evaluates its own row from
 // LDS (row pitch padded to an odd number of 16-byte words: conflict-free).
+// Blocks hold 128 slots.
 // A thread-per-slot read of 192-byte rows straight from memory would touch
 // 64 lines per instruction and re-fetch them from L2 as L1 thrashes.
 //
@@ -39,6 +40,11 @@ constexpr float kD = 5.900435899e-01f, kE = 2.890611443e+00f, kF = 4.570457995e-
 constexpr float kG = 3.731763326e-01f, kH = 1.445305721e+00f;
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Gaussians (slots) per block and per iteration, one per thread.  128-slot
+// blocks keep the LDS of a block at ~27 KB (degree 3, FP32), so five blocks
+// are resident per CU and their loads overlap.
+constexpr int kExT = 128;
 
 template <int D>
 __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
@@ -145,14 +151,14 @@ __device__ __forceinline__ void stage_rows(const void *src, const int64_t *gidx,
   U v[R::CH];
 #pragma unroll
   for (int r = 0; r < R::CH; ++r) {
-    const int q = t + r * kBlock;
+    const int q = t + r * kExT;
     const int ls = q / R::CH, part = q - ls * R::CH;
     const int lsc = ls < nsl ? ls : 0;
     v[r] = g[gidx[lsc] * R::CH + part];
   }
 #pragma unroll
   for (int r = 0; r < R::CH; ++r) {
-    const int q = t + r * kBlock;
+    const int q = t + r * kExT;
     const int ls = q / R::CH, part = q - ls * R::CH;
     if (ls < nsl) rows[ls * R::PITCH + part] = v[r];
   }
@@ -177,20 +183,20 @@ __device__ __forceinline__ void load_row(const typename ShRow<D, BF16>::U *rows,
 
 template <int D, bool BF16>
 struct ExLds {
-  typename ShRow<D, BF16>::U rows[kBlock * ShRow<D, BF16>::PITCH];
-  int64_t gidx[kBlock];
+  typename ShRow<D, BF16>::U rows[kExT * ShRow<D, BF16>::PITCH];
+  int64_t gidx[kExT];
 };
 
 template <int D, bool BF16>
-__global__ __launch_bounds__(kBlock) void k_decode_explicit(ExArgs a) {
+__global__ __launch_bounds__(kExT) void k_decode_explicit(ExArgs a) {
   using R = ShRow<D, BF16>;
   __shared__ ExLds<D, BF16> sm;
   const int t = threadIdx.x, k = a.k;
   const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
   const int64_t total = (int64_t)m_total * k;
   if (blockIdx.x == 0 && t == 0) *a.out_count = (uint32_t)total;
-  for (int64_t s0 = (int64_t)blockIdx.x * kBlock; s0 < total; s0 += (int64_t)gridDim.x * kBlock) {
-    const int nsl = (int)min<int64_t>(kBlock, total - s0);
+  for (int64_t s0 = (int64_t)blockIdx.x * kExT; s0 < total; s0 += (int64_t)gridDim.x * kExT) {
+    const int nsl = (int)min<int64_t>(kExT, total - s0);
     const int64_t s = s0 + min(t, nsl - 1);
     const uint32_t p = (uint32_t)(s / k);
     const int i = (int)(s - (int64_t)p * k);
@@ -253,14 +259,14 @@ __global__ __launch_bounds__(kBlock) void k_decode_explicit(ExArgs a) {
 // go back through LDS so the accumulation into the [slot][NV] array is one
 // coalesced read-modify-write per 16-byte word.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_decode_explicit_bwd(ExArgs a) {
+__global__ __launch_bounds__(kExT) void k_decode_explicit_bwd(ExArgs a) {
   using R = ShRow<D, false>;
   __shared__ ExLds<D, false> sm;
   const int t = threadIdx.x, k = a.k;
   const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
   const int64_t total = (int64_t)m_total * k;
-  for (int64_t s0 = (int64_t)blockIdx.x * kBlock; s0 < total; s0 += (int64_t)gridDim.x * kBlock) {
-    const int nsl = (int)min<int64_t>(kBlock, total - s0);
+  for (int64_t s0 = (int64_t)blockIdx.x * kExT; s0 < total; s0 += (int64_t)gridDim.x * kExT) {
+    const int nsl = (int)min<int64_t>(kExT, total - s0);
     const int64_t s = s0 + min(t, nsl - 1);
     const uint32_t p = (uint32_t)(s / k);
     const int i = (int)(s - (int64_t)p * k);
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_decode_explicit_bwd(ExArgs a) {
       U *gsh = (U *)a.g_sh;
 #pragma unroll
       for (int r = 0; r < R::CH; ++r) {
-        const int qq = t + r * kBlock;
+        const int qq = t + r * kExT;
         const int ls = qq / R::CH, part = qq - ls * R::CH;
         if (ls < nsl) {
           U *dst = gsh + sm.gidx[ls] * R::CH + part;
@@ -384,10 +390,10 @@ __global__ void k_zero_count_ex(uint32_t *p) { *p = 0u; }
 template <bool BF16>
 void launch_decode(int D, int grid, hipStream_t s, const ExArgs &a) {
   switch (D) {
-    case 0: if constexpr (!BF16) hipLaunchKernelGGL((k_decode_explicit<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_decode_explicit<1, BF16>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: if constexpr (!BF16) hipLaunchKernelGGL((k_decode_explicit<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_decode_explicit<3, BF16>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 0: if constexpr (!BF16) hipLaunchKernelGGL((k_decode_explicit<0, false>), dim3(grid), dim3(kExT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_decode_explicit<1, BF16>), dim3(grid), dim3(kExT), 0, s, a); break;
+    case 2: if constexpr (!BF16) hipLaunchKernelGGL((k_decode_explicit<2, false>), dim3(grid), dim3(kExT), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_decode_explicit<3, BF16>), dim3(grid), dim3(kExT), 0, s, a); break;
   }
 }
 
@@ -411,7 +417,7 @@ int fill_common(const octgs_anchors *an, const octgs_explicit *e, const octgs_ca
 int grid_for(int64_t gauss_capacity) {
   // 256 slots per block and iteration; LDS holds two FP32 degree-3 blocks
   // per CU, so a few resident rounds over 256 CUs is enough to stream
-  return (int)std::max<int64_t>(1, std::min<int64_t>((gauss_capacity + kBlock - 1) / kBlock, 2048));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((gauss_capacity + kExT - 1) / kExT, 4096));
 }
 
 }  // namespace
@@ -490,10 +496,10 @@ int octgs_decode_explicit_bwd(const octgs_anchors *an, const octgs_explicit *e,
   const int grid = grid_for(gauss_capacity);
   hipStream_t s = (hipStream_t)stream;
   switch (e->sh_degree) {
-    case 0: hipLaunchKernelGGL(k_decode_explicit_bwd<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_decode_explicit_bwd<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_decode_explicit_bwd<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_decode_explicit_bwd<3>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(k_decode_explicit_bwd<0>, dim3(grid), dim3(kExT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_decode_explicit_bwd<1>, dim3(grid), dim3(kExT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_decode_explicit_bwd<2>, dim3(grid), dim3(kExT), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_decode_explicit_bwd<3>, dim3(grid), dim3(kExT), 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
