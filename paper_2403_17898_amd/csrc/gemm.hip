@@ -1,5 +1,4 @@
-// Tiled FP32 GEMM used by the backward passes and the skip-predictor
-// training: 64x64 output tiles, K in steps of 16 staged through LDS, 4x4
+// Tiled FP32 GEMM used by the skip-predictor training: 64x64 output tiles, K in steps of 16 staged through LDS, 4x4
 // outputs per thread, optional split-K with atomic accumulation, and an
 // epilogue with bias add and a ReLU-derivative mask.  One of M or K may be a
 // device-resident count, so launches need no host synchronisation.
@@ -16,14 +15,7 @@ constexpr int GT = 64, GK = 16;
 __global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
   __shared__ float As[GK][GT + 4];
   __shared__ float Bs[GK][GT + 4];
-  const int grp = blockIdx.z / g.splitk, sk = blockIdx.z % g.splitk;
-  if (g.groups > 1) {
-    g.A = g.A3[grp]; g.B = g.B3[grp]; g.C = g.C3[grp];
-    g.bias = g.bias3[grp]; g.mask = g.mask3[grp]; g.N = g.N3[grp];
-    if (g.K3[grp]) g.K = g.K3[grp];
-    if (g.ldb3[grp]) g.ldb = g.ldb3[grp];
-    if (g.ldc3[grp]) g.ldc = g.ldc3[grp];
-  }
+  const int sk = blockIdx.z;
   int M = g.M, K = g.K;
   if (g.dyn) {
     const int d = (int)min(*g.dyn, (uint32_t)g.dyn_cap);
@@ -87,22 +79,15 @@ __global__ __launch_bounds__(kBlock) void k_gemm(Gemm g) {
   }
 }
 
-struct Colsum3 {
-  const float *Y[3];
-  float *out[3];
-  int N[3];
-};
-
-// blockIdx.y selects the column set; rows are strided over blockIdx.x
-__global__ __launch_bounds__(kBlock) void k_colsum(Colsum3 c, int64_t ld, const uint32_t *dyn,
-                                                   int cap) {
+// column sums of Y[M][N] (row stride ld) added to out; rows strided over blocks
+__global__ __launch_bounds__(kBlock) void k_colsum(const float *Y, int64_t ld, int N,
+                                                   const uint32_t *dyn, int cap, float *out) {
   const int M = dyn ? (int)min(*dyn, (uint32_t)cap) : cap;
-  const int gsel = blockIdx.y, n = threadIdx.x;
-  if (n >= c.N[gsel]) return;
-  const float *Y = c.Y[gsel];
+  const int n = threadIdx.x;
+  if (n >= N) return;
   float s = 0.0f;
   for (int m = blockIdx.x; m < M; m += gridDim.x) s += Y[(int64_t)m * ld + n];
-  if (s != 0.0f) atomicAdd(c.out[gsel] + n, s);
+  if (s != 0.0f) atomicAdd(out + n, s);
 }
 
 __global__ void k_fill(float *p, int64_t n, float v) {
@@ -115,20 +100,7 @@ __global__ void k_fill(float *p, int64_t n, float v) {
 
 hipError_t colsum(const float *Y, int64_t ld, int N, const uint32_t *dyn, int cap, float *out,
                   hipStream_t s) {
-  Colsum3 c;
-  memset(&c, 0, sizeof c);
-  c.Y[0] = Y; c.out[0] = out; c.N[0] = N;
-  hipLaunchKernelGGL(k_colsum, dim3(256, 1), dim3(kBlock), 0, s, c, ld, dyn, cap);
-  return hipGetLastError();
-}
-
-hipError_t colsum3(const float *const Y3[3], int64_t ld, const int N3[3], const uint32_t *dyn,
-                   int cap, float *const out3[3], hipStream_t s) {
-  Colsum3 c;
-  for (int i = 0; i < 3; ++i) {
-    c.Y[i] = Y3[i]; c.out[i] = out3[i]; c.N[i] = N3[i];
-  }
-  hipLaunchKernelGGL(k_colsum, dim3(256, 3), dim3(kBlock), 0, s, c, ld, dyn, cap);
+  hipLaunchKernelGGL(k_colsum, dim3(256), dim3(kBlock), 0, s, Y, ld, N, dyn, cap, out);
   return hipGetLastError();
 }
 
@@ -141,12 +113,8 @@ hipError_t fill(float *p, int64_t n, float v, hipStream_t s) {
 
 hipError_t gemm(const Gemm &g0, int64_t m_cap, hipStream_t s) {
   const int64_t mt = (std::max<int64_t>(m_cap, 1) + GT - 1) / GT;
-  int nmax = g0.N;
-  if (g0.groups > 1)
-    for (int i = 0; i < g0.groups; ++i) nmax = std::max(nmax, g0.N3[i]);
-  const int nt = (nmax + GT - 1) / GT;
-  const int groups = std::max(g0.groups, 1);
-  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk * groups), dim3(kBlock), 0, s, g0);
+  const int nt = (g0.N + GT - 1) / GT;
+  hipLaunchKernelGGL(k_gemm, dim3(nt, (unsigned)mt, g0.splitk), dim3(kBlock), 0, s, g0);
   return hipGetLastError();
 }
 
@@ -154,7 +122,6 @@ Gemm gemm_base() {
   Gemm g;
   memset(&g, 0, sizeof g);
   g.splitk = 1;
-  g.groups = 1;
   return g;
 }
 

@@ -304,10 +304,7 @@ __device__ __forceinline__ uint32_t chained_lookback(uint32_t *status, uint32_t 
 // One of M (dyn_dim = 1) or K (dyn_dim = 2) may be min(*dyn, dyn_cap).
 // accumulate adds into C (atomically when splitk > 1).
 // ---------------------------------------------------------------------------
-// C = op(A) op(B) (+ bias, masked, accumulated), FP32.  groups > 1 runs up
-// to three independent products in one launch: group g takes A3[g], B3[g],
-// C3[g], bias3[g], mask3[g], N3[g], and K3[g], ldb3[g], ldc3[g] where those
-// are nonzero; lda, M, the flags and the remaining fields are shared.
+// C = op(A) op(B) (+ bias, masked, accumulated), FP32.
 struct Gemm {
   const float *A, *B;
   float *C;
@@ -320,12 +317,6 @@ struct Gemm {
   const float *mask;
   int64_t ldm;
   int accumulate, splitk;
-  int groups;
-  const float *A3[3], *B3[3];
-  float *C3[3];
-  const float *bias3[3], *mask3[3];
-  int N3[3], K3[3];
-  int64_t ldb3[3], ldc3[3];
 };
 
 hipError_t gemm(const Gemm &g, int64_t m_cap, hipStream_t s);
@@ -334,8 +325,7 @@ Gemm gemm_base();
 hipError_t colsum(const float *Y, int64_t ld, int N, const uint32_t *dyn, int cap, float *out,
                   hipStream_t s);
 // three column sums in one launch: out3[g][n] += sum_m Y3[g][m * ld + n], n < N3[g]
-hipError_t colsum3(const float *const Y3[3], int64_t ld, const int N3[3], const uint32_t *dyn,
-                   int cap, float *const out3[3], hipStream_t s);
+
 hipError_t fill(float *p, int64_t n, float v, hipStream_t s);
 
 }  // namespace octgs
