@@ -75,6 +75,10 @@ def parse():
                     help="skip the explicit-Gaussian (3D-GS instance) measurement")
     ap.add_argument("--skip-train-views", type=int, default=1000)
     ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--city", action="store_true",
+                    help="also measure the city-scale scene (4M anchors / 10 levels): the "
+                         "3840x2160 zoom-out and the 8-view 2048x1024 train step (several minutes)")
+    ap.add_argument("--city-skip-views", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
     return ap.parse_args()
@@ -82,6 +86,37 @@ def parse():
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def time_views(args, torch, streams, views, bufs, render_one, depth):
+    """(event ms, wall s) for args.steps views after args.warmup untimed
+    ones; view i runs on stream i % depth with buffers bufs[i % depth]."""
+    stream = streams[0]
+
+    def run(n):
+        for i in range(n):
+            k = i % depth
+            render_one(k, views[i % len(views)], streams[k])
+    run(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for s in streams[1:depth]:
+        s.wait_event(e0)
+    run(args.steps)
+    for s in streams[1:depth]:
+        ev = torch.cuda.Event()
+        ev.record(s)
+        stream.wait_event(ev)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    for b in bufs[:depth]:
+        st = b.stats()
+        if st["pair_overflow"] or st["sync_error"]:
+            raise SystemExit(f"timed run flagged: {st}")
+    return e0.elapsed_time(e1), wall
 
 
 def main():
@@ -156,33 +191,8 @@ def main():
 
     def timed_views(render_one, depth, views=None, bufs=None):
         """ms for args.steps views (after args.warmup), view i on stream i % depth."""
-        views = ccams if views is None else views
-        bufs = vbs if bufs is None else bufs
-
-        def run(n):
-            for i in range(n):
-                k = i % depth
-                render_one(k, views[i % len(views)], streams[k])
-        run(args.warmup)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t_wall = time.perf_counter()
-        e0.record(stream)
-        for s in streams[1:depth]:
-            s.wait_event(e0)
-        run(args.steps)
-        for s in streams[1:depth]:
-            ev = torch.cuda.Event()
-            ev.record(s)
-            stream.wait_event(ev)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
-        for b in bufs[:depth]:
-            st = b.stats()
-            if st["pair_overflow"] or st["sync_error"]:
-                raise SystemExit(f"timed run flagged: {st}")
-        return e0.elapsed_time(e1), wall
+        return time_views(args, torch, streams, ccams if views is None else views,
+                          vbs if bufs is None else bufs, render_one, depth)
 
     def timed(prec, depth=D, views=None):
         return timed_views(lambda k, c, s: vbs[k].render(ds, c, prm, precision=prec, stream=s),
@@ -305,6 +315,7 @@ def main():
         log(f"CPU oracle: {cpu}")
 
     train = None if args.no_train else train_step_timing(args, P, S, torch, np)
+    city = city_path(args, P, S, torch, np, prm, D, streams) if args.city else None
 
     value = skip["fps"] if skip else fps16
     ms_value = skip["ms_per_view"] if skip else ms16 / args.steps
@@ -351,6 +362,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if city is not None:
+        out["city"] = city
     print(json.dumps(out), flush=True)
 
 
@@ -426,14 +439,16 @@ def explicit_path(args, P, S, torch, np, sc, ccams, prm, W, H, D, streams, timed
     return res
 
 
-def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None):
+def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None,
+              view_dist=(500.0, 10.0, 800.0), n_train=None):
     """Train the anchor-skip predictor on blend weights logged by the plain
     renderer over random views of the same scene, pick its threshold on
     held-out training views (worst view >= 47 dB against full decode), and
     judge it on the zoom-out: PSNR of BF16 + skip against plain FP32."""
     from paper_2403_17898_amd import skip as SK
     t0 = time.time()
-    views = S.random_views(args.skip_train_views + 20, 4, 500.0, 10.0, 800.0, W, H)
+    n_train = args.skip_train_views if n_train is None else n_train
+    views = S.random_views(n_train + 20, 4, *view_dist, W, H)
     cams = [P.make_camera(c) for c in views]
     train_cams, hold_cams = cams[:-20], cams[-20:]
     # random views can select more anchors than the zoom-out: whole-scene capacities
@@ -504,16 +519,100 @@ def timed_skip(P, vbs, ds, prm, skip, timed_views, depth):
     return timed_views(one, depth)
 
 
-def train_step_timing(args, P, S, torch, np):
-    """Training step of the 500k-anchor, 6-level scene: 4 views at 1600x1066,
-    mean-L1 against targets rendered from a copy with feature noise
-    sigma = 0.05, gradients through compositing, projection and the anchor
-    MLPs, then Adam on every trainable array."""
+def city_path(args, P, S, torch, np, prm, D, streams):
+    """The city-scale scene, 4M anchors over 10 levels on 8,000 boxes over
+    [-2000, 2000]^2: FPS of the 200-view 3840x2160 zoom-out (20 -> 3000 m)
+    with plain FP32 decode, BF16 decode and BF16 + learned skip (the
+    predictor trained on random views of this scene), PSNR of BF16 against
+    FP32, and the train step of 8 views at 2048x1024."""
     t0 = time.time()
-    sc = S.make_config3()
+    sc = S.make_config5()
+    ccams_c = S.config5_cameras(args.views)
+    log(f"city scene: {sc.n} anchors, levels {sc.level_counts()}, generated in "
+        f"{time.time() - t0:.1f}s")
+    ds = P.DeviceScene.from_scene(sc)
+    W, H = ccams_c[0].width, ccams_c[0].height
+    cams = [P.make_camera(c) for c in ccams_c]
+    vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=160 << 20)
+    per_view = []
+    for c in cams:
+        vb.render(ds, c, prm, precision=P.OCTGS_FP32)
+        st = vb.stats()
+        if st["pair_overflow"] or st["sync_error"]:
+            raise SystemExit(f"city sizing pass failed: {st}")
+        per_view.append(st)
+    max_sel = max(s["n_selected"] for s in per_view)
+    max_pairs = max(s["n_candidates"] for s in per_view)
+    mean = {k: float(np.mean([s[k] for s in per_view]))
+            for k in ("n_selected", "n_slots", "n_visible", "n_pairs")}
+    del vb
+    torch.cuda.empty_cache()
+    gcap = max(1, int(max_sel * sc.k * 1.05) + 1024)
+    pcap = max(1, int(max_pairs * 1.10) + 4096)
+    vbs = [P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=pcap, gauss_capacity=gcap)
+           for _ in range(D)]
+
+    def timed(prec):
+        return time_views(args, torch, streams, cams, vbs,
+                          lambda k, c, s: vbs[k].render(ds, c, prm, precision=prec, stream=s), D)
+
+    ms32, _ = timed(P.OCTGS_FP32)
+    ms16, _ = timed(P.OCTGS_BF16)
+    res = {"workload": "city scene: 4M anchors / 10 LOD levels, 200-view zoom-out 20->3000 m, "
+                       "3840x2160",
+           "n_anchors": sc.n, "views": len(cams),
+           "fps_plain_fp32": round(args.steps / (ms32 / 1e3), 2),
+           "fps_bf16": round(args.steps / (ms16 / 1e3), 2),
+           "mean_selected": round(mean["n_selected"]), "mean_gaussians": round(mean["n_slots"]),
+           "mean_visible": round(mean["n_visible"]), "mean_pairs": round(mean["n_pairs"]),
+           "max_selected": max_sel, "max_candidate_pairs": max_pairs, "frames_in_flight": D}
+    vb = vbs[0]
+    psn = []
+    for c in cams[::10]:
+        vb.render(ds, c, prm, precision=P.OCTGS_FP32)
+        ref = vb.rgb.clone()
+        vb.render(ds, c, prm, precision=P.OCTGS_BF16)
+        mse = torch.mean((vb.rgb - ref) ** 2).item()
+        psn.append(float("inf") if mse == 0 else 10 * math.log10(1.0 / mse))
+    res["psnr_bf16_vs_fp32_min_db"] = round(min(psn), 2)
+    res["psnr_views"] = len(psn)
+    log(f"city: FP32 {res['fps_plain_fp32']} FPS, BF16 {res['fps_bf16']} FPS, "
+        f"BF16 vs FP32 min PSNR {res['psnr_bf16_vs_fp32_min_db']} dB over {len(psn)} views")
+    if not args.no_skip:
+        skip = skip_path(args, P, S, torch, np, sc, ds, cams, prm, W, H, vb,
+                         view_dist=(2000.0, 20.0, 3000.0), n_train=args.city_skip_views)
+        ms_sk, _ = timed_skip(P, vbs, ds, prm, skip,
+                              lambda one, depth: time_views(args, torch, streams, cams, vbs, one,
+                                                            depth), D)
+        skip["fps"] = round(args.steps / (ms_sk / 1e3), 2)
+        res["skip"] = skip
+        log(f"city BF16 + learned skip: {skip['fps']} FPS")
+    del vbs, vb
+    torch.cuda.empty_cache()
+    if not args.no_train:
+        tv = S.config5_train_views()
+        res["train"] = train_step_timing(
+            args, P, S, torch, np, sc=sc, views=tv,
+            workload="4M anchors / 10 levels, 8 views at 2048x1024, mean-L1, Adam",
+            with_full_loss=False)
+    del ds
+    torch.cuda.empty_cache()
+    return res
+
+
+def train_step_timing(args, P, S, torch, np, sc=None, views=None,
+                      workload="500k anchors / 6 levels, 4 views at 1600x1066, mean-L1, Adam",
+                      with_full_loss=True):
+    """Training step (by default of the 500k-anchor, 6-level scene: 4 views
+    at 1600x1066): mean-L1 against targets rendered from a copy with feature
+    noise sigma = 0.05, gradients through compositing, projection and the
+    anchor MLPs, then Adam on every trainable array."""
+    t0 = time.time()
+    if sc is None:
+        sc = S.make_config3()
+        views = S.config3_views()
     tgt_scene = S.perturbed_copy(sc, 0.05, seed=3)
-    views = S.config3_views()
-    log(f"train scene: {sc.n} anchors, levels {sc.level_counts()}, generated in "
+    log(f"train scene: {sc.n} anchors, levels {sc.level_counts()}, ready in "
         f"{time.time() - t0:.1f}s")
     ds = P.DeviceScene.from_scene(sc)
     dt = P.DeviceScene.from_scene(tgt_scene)
@@ -586,10 +685,13 @@ def train_step_timing(args, P, S, torch, np):
         return tot[len(tot) // 2], adam[len(adam) // 2], first, loss.item()
 
     ms, adam_ms, first_loss, last_loss = timed_steps(False)
-    res = {"workload": "500k anchors / 6 levels, 4 views at 1600x1066, mean-L1, Adam",
+    res = {"workload": workload,
            "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam_ms, 3),
            "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
            "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs}
+    if not with_full_loss:
+        log(f"train step: {res}")
+        return res
     msf, _, ff, fl = timed_steps(True)
     # densification decisions of the interval (every T = 100 iterations)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -20,6 +20,8 @@ from .scenes import (  # noqa: F401
     config3_views,
     perturbed_copy,
     make_config5,
+    config5_cameras,
+    config5_train_views,
     make_gradcheck_scene,
     random_gaussians,
     tile_aligned_gaussians,

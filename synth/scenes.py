@@ -479,14 +479,33 @@ def make_config3(seed: int = 3, delta: Optional[float] = C3_DELTA) -> Scene:
                       subsample=2_500_000, near=near, delta=delta, info=dict(name="c3"))
 
 
-def make_config5(seed: int = 5) -> Scene:
-    """4M anchors over 10 levels from 80M points on 8,000 boxes over [-2000, 2000]^2."""
+def config5_cameras(n: int = 200, width: int = 3840, height: int = 2160):
+    return zoomout_trajectory(n, 20.0, 3000.0, width, height, 60.0)
+
+
+def config5_train_views():
+    """The training step's 8 views at 2048x1024: evenly spaced along the
+    zoom-out, where the pruned scene keeps its fine levels."""
+    return zoomout_trajectory(8, 20.0, 3000.0, 2048, 1024, 60.0)
+
+
+# base voxel size bisected once for the default config-5 arguments
+# (4,000,407 anchors; per level 109592, 496537, 1012137, 1015771, 890174,
+# 380807, 84299, 10671, 419, 0: no camera of the zoom-out comes within
+# d_max / 2^9 of a surface, so the pruning leaves the finest level empty)
+C5_DELTA = 18.174696515286612
+
+
+def make_config5(seed: int = 5, delta: Optional[float] = C5_DELTA) -> Scene:
+    """4M anchors over 10 levels from 80M points on 8,000 boxes over
+    [-2000, 2000]^2, with the same path pruning as config 2 along the
+    20 -> 3000 m zoom-out."""
     rng = np.random.default_rng(seed)
     pts = _street_points(rng, 80_000_000, 8000, 2000.0)
-    cams = zoomout_trajectory(200, 20.0, 3000.0, 3840, 2160)
-    return make_scene(pts, 10, 4_000_000, cams, k=10, feat_dim=32, width=64, seed=seed,
-                      scale_mode="voxel", offset_sigma=0.25, subsample=5_000_000,
-                      info=dict(name="c5"))
+    near = [((0.0, -20.0, 20.0), (0.0, -3000.0, 3000.0))]
+    return make_scene(pts, 10, 4_000_000, config5_cameras(), k=10, feat_dim=32, width=64,
+                      seed=seed, scale_mode="voxel", offset_sigma=0.25, subsample=10_000_000,
+                      near=near, delta=delta, info=dict(name="c5"))
 
 
 def make_gradcheck_scene(seed: int = 7, n: int = 50, k: int = 10, feat_dim: int = 32,
