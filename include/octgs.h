@@ -101,8 +101,7 @@ typedef struct {
  * a quaternion w, x, y, z).  Each head is Linear(in, width) -> ReLU ->
  * Linear(width, out) with in = feat_dim + 4 (feature, relative distance,
  * viewing direction).  w1 is [in][width], w2 is [width][out], row-major,
- * FP32, device memory, each 16-byte aligned (octgs_decode returns
- * OCTGS_EINVAL otherwise); the BF16 path rounds them to BF16 itself. */
+ * FP32, device memory; the BF16 path rounds them to BF16 itself. */
 typedef struct {
   int32_t width; /* hidden width, 16..64, multiple of 16 */
   const float *w1[3], *b1[3], *w2[3], *b2[3];
@@ -179,6 +178,11 @@ OCTGS_API size_t octgs_select_workspace_bytes(int64_t n);
 OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
                      uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream);
 
+/* Workspace bytes of octgs_decode for a precision (OCTGS_FP32 or
+ * OCTGS_BF16; 0 for any other value).  It does not depend on the scene or
+ * the MLP size. */
+OCTGS_API size_t octgs_decode_workspace_bytes(int32_t precision);
+
 /* Neural-Gaussian decode (Eq. 3 and Eq. 4, Sec. III-B) of the first
  * min(*count, out->capacity / k) anchors listed in idx (device).  Network
  * input x = [feature, |x_v - C| / d_max, (x_v - C) / |x_v - C|]; outputs
@@ -188,10 +192,15 @@ OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, 
  * (needs a->level and a->lod_bias; FP32, log2 of the distance ratio).  A
  * Gaussian with opacity <= 0 is written and later culled by the rasterizer.
  * precision selects the FP32 or the BF16 (needs a->feat_bf16) MFMA path.
- * Writes out->data and *out->count (device). */
+ * ws: device, 16-byte aligned, >= octgs_decode_workspace_bytes(precision);
+ * each call first writes the MLP weights there in the operand layout of its
+ * matrix instructions (rounded to BF16 on that path), so a call always uses
+ * the weights as they are when it runs.  Calls that may run at the same time
+ * (different streams) need separate workspaces.  Writes out->data and
+ * *out->count (device). */
 OCTGS_API int octgs_decode(const octgs_anchors *a, const octgs_mlp *mlp, const octgs_camera *cam,
                  const uint32_t *idx, const uint32_t *count, int precision,
-                 const octgs_gaussians *out, octgs_stream stream);
+                 const octgs_gaussians *out, void *ws, size_t ws_bytes, octgs_stream stream);
 
 /* Workspace bytes of octgs_rasterize_fwd / _bwd for a Gaussian-slot capacity,
  * a (tile, Gaussian) pair capacity and an image size. */

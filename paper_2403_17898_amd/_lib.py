@@ -96,8 +96,9 @@ SIGNATURES = [
     ("octgs_select_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("octgs_select_lod", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _p,
                                 ctypes.c_size_t, _p]),
+    ("octgs_decode_workspace_bytes", ctypes.c_size_t, [_i32]),
     ("octgs_decode", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp), ctypes.POINTER(Camera),
-                            _p, _p, _i32, ctypes.POINTER(Gaussians), _p]),
+                            _p, _p, _i32, ctypes.POINTER(Gaussians), _p, ctypes.c_size_t, _p]),
     ("octgs_raster_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i32, _i32]),
     ("octgs_rasterize_fwd", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
                                    ctypes.POINTER(RasterParams), _i64, _p, _p, _p, _p, _p,

@@ -8,7 +8,11 @@
 // two layers are GEMMs [32 x 36] x [36 x 3W] and, per head, [32 x W] x [W x out]
 // run on MFMA; the block's waves split the output columns, so each wave keeps
 // its slice of the weights (the B operands) in registers for the whole
-// persistent loop, and only the activations go through LDS.  Two variants:
+// persistent loop, and only the activations go through LDS.  A first small
+// kernel writes those B operands once per call into the caller's workspace,
+// already rounded to the path's precision and in the lane order the MFMA
+// reads them, so each block loads its slices with a few fully coalesced loads
+// instead of staging and converting every weight itself.  Two variants:
 //   FP32: v_mfma_f32_16x16x4_f32 on FP32 inputs and weights;
 //   BF16: v_mfma_f32_16x16x16_bf16 on BF16 features, inputs and weights,
 //         FP32 accumulation; biases, activations and the Gaussian assembly
@@ -57,7 +61,7 @@ struct DecodeArgs {
   const float *lod_bias;
   const float *pos, *feat, *offsets, *oscale, *bscale;
   const uint16_t *feat_bf16;
-  const float *w1[3], *b1[3], *w2[3], *b2[3];
+  const void *frag;  // weight fragments (Frag layout), written by k_decode_prep
   const uint32_t *idx, *count;
   float *out;
   int64_t cap;
@@ -82,57 +86,110 @@ struct alignas(16) Smem {
   float ofac[kTM];  // opacity factor per anchor (1 without blending)
 };
 
-// Weight staging into LDS in the path's precision T (float, or BF16 bits),
-// every 16-byte load in flight before the first store.  Loads and stores are
-// unconditional at a clamped index (a thread past the end rewrites the last
-// element with the value it holds), which keeps the code straight-line so
-// the loads are not serialised behind branches.  U bounds the float4 loads
-// per thread; n >= 1 float4.
-template <typename T>
-__device__ __forceinline__ void put4(T *dst, int i4, const float4 &v) {
-  if constexpr (std::is_same<T, float>::value) {
-    reinterpret_cast<float4 *>(dst)[i4] = v;
-  } else {
-    uint2 u;
-    u.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-    u.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
-    reinterpret_cast<uint2 *>(dst)[i4] = u;
-  }
-}
-
-template <int U>
-struct Ld4 {
-  float4 v[U];
-  __device__ __forceinline__ void load(const float *src, int n, int t) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = reinterpret_cast<const float4 *>(src)[min(t + u * kBlock, n - 1)];
-  }
-  template <typename T>
-  __device__ __forceinline__ void store(T *dst, int n, int t) const {
-#pragma unroll
-    for (int u = 0; u < U; ++u) put4(dst, min(t + u * kBlock, n - 1), v[u]);
-  }
-};
-
 // One of three pointers by a lane-varying index, without indexing the
 // kernel-argument array through memory.
 __device__ __forceinline__ const float *pick3(const float *const p[3], int h) {
   return h == 0 ? p[0] : (h == 1 ? p[1] : p[2]);
 }
 
-constexpr int kStageElems = 3 * kIn * kMaxW + kMaxW * kMaxNO;  // w1 then w2, every head
-
+// Weight fragments in the workspace, per wave w (0..3) and column-tile slot
+// q (0..2, tile w + 4 q), one 64-lane vector each:
+//   B1[w][q][ks] (ks < KS1), B2[w][q][ks] (ks < KS2), bias1[w][q], bias2[w][q]
+// An operand is one float (FP32 path) or four BF16 values (BF16 path).
 template <bool BF16>
-union alignas(16) DecodeLds {
-  Smem<BF16> sm;
-  typename Smem<BF16>::T stage[kStageElems];
+struct Frag {
+  static constexpr int KS1 = BF16 ? kInPad / 16 : kIn / 4;   // 3 or 9 k-steps
+  static constexpr int KS2 = BF16 ? kMaxW / 16 : kMaxW / 4;  // 4 or 16 k-steps (W <= 64)
+  static constexpr int KV = BF16 ? 4 : 1;                     // k values per lane per step
+  typedef typename std::conditional<BF16, s4, float>::type Op;
+  static constexpr size_t n1 = 4 * 3 * KS1 * kWave, n2 = 4 * 3 * KS2 * kWave, nb = 4 * 3 * kWave;
+  static constexpr size_t bytes = (n1 + n2) * sizeof(Op) + 2 * nb * sizeof(float);
 };
+
+struct PrepArgs {
+  int k, W;
+  const float *w1[3], *b1[3], *w2[3], *b2[3];
+  void *ws;
+};
+
+// One thread per fragment lane: the operand element(s) the MFMA lane reads,
+// zero outside the real rows and columns.
+//   layer 1, tile ct = w + 4 q of the 3W columns: column n = 16 ct + lane % 16,
+//     head n / W; k index ks * 4 KV + (lane / 16) KV + j of the 36 inputs
+//   layer 2, tile c = w + 4 q of the padded output columns (l2_tile)
+template <bool BF16>
+__global__ __launch_bounds__(kBlock) void k_decode_prep(PrepArgs a) {
+  typedef Frag<BF16> F;
+  typedef typename F::Op Op;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int k = a.k, W = a.W;
+  const int n1tiles = 3 * W / 16;
+  const int n2tiles = (k + 15) / 16 + (3 * k + 15) / 16 + (7 * k + 15) / 16;
+  Op *f1 = reinterpret_cast<Op *>(a.ws);
+  Op *f2 = f1 + F::n1;
+  float *fb1 = reinterpret_cast<float *>(f2 + F::n2);
+  float *fb2 = fb1 + F::nb;
+  const int l = i % kWave, g = l / 16, lc = l % 16;
+  auto put = [&](Op *dst, const float (&v)[F::KV]) {
+    if constexpr (BF16) {
+      s4 s;
+      s[0] = (short)f2bf(v[0]); s[1] = (short)f2bf(v[1]);
+      s[2] = (short)f2bf(v[2]); s[3] = (short)f2bf(v[3]);
+      *dst = s;
+    } else {
+      *dst = v[0];
+    }
+  };
+  if (i < (int)F::n1) {
+    const int ks = (i / kWave) % F::KS1, q = (i / kWave / F::KS1) % 3, w = i / kWave / F::KS1 / 3;
+    const int ct = w + 4 * q;
+    const int n = ct * 16 + lc;
+    const bool on = ct < n1tiles;
+    const int head = on ? n / W : 0, hc = on ? n - head * W : 0;
+    float v[F::KV];
+#pragma unroll
+    for (int j = 0; j < F::KV; ++j) {
+      const int kk = ks * (4 * F::KV) + g * F::KV + j;
+      v[j] = (on && kk < kIn) ? pick3(a.w1, head)[kk * W + hc] : 0.0f;
+    }
+    put(f1 + i, v);
+  } else if (i < (int)(F::n1 + F::n2)) {
+    const int r = i - (int)F::n1;
+    const int ks = (r / kWave) % F::KS2, q = (r / kWave / F::KS2) % 3, w = r / kWave / F::KS2 / 3;
+    const int c = w + 4 * q;
+    const bool on = c < n2tiles;
+    int head = 0, col0 = 0, ncol = 0;
+    if (on) l2_tile(c, k, head, col0, ncol);
+    const int col = col0 + lc;
+    const bool cv = on && col < ncol;
+    float v[F::KV];
+#pragma unroll
+    for (int j = 0; j < F::KV; ++j) {
+      const int kk = ks * (4 * F::KV) + g * F::KV + j;
+      v[j] = (cv && kk < W) ? pick3(a.w2, head)[kk * ncol + col] : 0.0f;
+    }
+    put(f2 + r, v);
+  } else if (i < (int)(F::n1 + F::n2 + F::nb)) {
+    const int r = i - (int)(F::n1 + F::n2);
+    const int q = (r / kWave) % 3, w = r / kWave / 3;
+    const int ct = w + 4 * q;
+    const int n = ct * 16 + lc;
+    const bool on = ct < n1tiles;
+    const int head = on ? n / W : 0, hc = on ? n - head * W : 0;
+    fb1[r] = on ? pick3(a.b1, head)[hc] : 0.0f;
+    const int c = w + 4 * q;
+    const bool on2 = c < n2tiles;
+    int h2 = 0, col0 = 0, ncol = 0;
+    if (on2) l2_tile(c, k, h2, col0, ncol);
+    const int col = col0 + lc;
+    fb2[r] = (on2 && col < ncol) ? pick3(a.b2, h2)[col] : 0.0f;
+  }
+}
 
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
-  typedef typename Smem<BF16>::T T;
-  __shared__ DecodeLds<BF16> lds;
-  Smem<BF16> &sm = lds.sm;
+  typedef Frag<BF16> F;
+  __shared__ Smem<BF16> sm;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const int g = l / 16, lc = l % 16;
   const int k = a.k, W = a.W;
@@ -147,98 +204,24 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
   if ((uint64_t)blockIdx.x * kTM >= m_total) return;
 
   // ---- weights of this wave's column tiles, kept in registers ----
-  // All weights are staged through LDS first (before the tile buffers are
-  // used) with one batch of coalesced loads; gathering the fragment layout
-  // straight from global memory would serialise dozens of L2 round trips.
-  // Layout: w1 of heads 0..2 ([kIn][W] each), then w2 of heads 0..2
-  // ([W][k], [W][3k], [W][7k]).
-  const int wk = W * k;
-  const int w2off[3] = {3 * kIn * W, 3 * kIn * W + wk, 3 * kIn * W + 4 * wk};
-  {
-    // float4 per thread: w1 head <= 576 / 256 -> 3; w2 heads <= 256, 768, 1792 -> 1, 3, 7
-    const int n1 = kIn * W / 4;
-    Ld4<3> x0, x1, x2;
-    Ld4<1> y0;
-    Ld4<3> y1;
-    Ld4<7> y2;
-    x0.load(a.w1[0], n1, t); x1.load(a.w1[1], n1, t); x2.load(a.w1[2], n1, t);
-    y0.load(a.w2[0], wk / 4, t); y1.load(a.w2[1], 3 * wk / 4, t); y2.load(a.w2[2], 7 * wk / 4, t);
-    x0.store(lds.stage, n1, t);
-    x1.store(lds.stage + kIn * W, n1, t);
-    x2.store(lds.stage + 2 * kIn * W, n1, t);
-    y0.store(lds.stage + w2off[0], wk / 4, t);
-    y1.store(lds.stage + w2off[1], 3 * wk / 4, t);
-    y2.store(lds.stage + w2off[2], 7 * wk / 4, t);
-  }
-  __syncthreads();
-  auto wval = [&](int off) -> float {
-    if constexpr (BF16) return __uint_as_float((uint32_t)lds.stage[off] << 16);
-    else return lds.stage[off];
-  };
-  // layer 1: tiles w, w + 4, w + 8 of the 3W columns
-  constexpr int KS1 = BF16 ? kInPad / 16 : kIn / 4;  // 3 or 9 k-steps
-  constexpr int KV = BF16 ? 4 : 1;                   // k values per lane per step
-  float b1r[3];
-  typename std::conditional<BF16, s4, float>::type B1[3][KS1];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int ct = w + 4 * q;
-    const int n = ct * 16 + lc;
-    const bool on = ct < n1tiles;
-    const int head = on ? n / W : 0, hc = on ? n - head * W : 0;
-    b1r[q] = on ? pick3(a.b1, head)[hc] : 0.0f;
-#pragma unroll
-    for (int ks = 0; ks < KS1; ++ks) {
-      float v[KV];
-#pragma unroll
-      for (int j = 0; j < KV; ++j) {
-        const int kk = ks * (4 * KV) + g * KV + j;
-        v[j] = (on && kk < kIn) ? wval((head * kIn + kk) * W + hc) : 0.0f;
-      }
-      if constexpr (BF16) {
-        s4 s;  // already BF16 values: the conversion is exact
-        s[0] = (short)f2bf(v[0]); s[1] = (short)f2bf(v[1]);
-        s[2] = (short)f2bf(v[2]); s[3] = (short)f2bf(v[3]);
-        B1[q][ks] = s;
-      } else {
-        B1[q][ks] = v[0];
-      }
-    }
-  }
-  // layer 2: tiles w, w + 4, w + 8 of the padded output columns
-  constexpr int KS2 = BF16 ? kMaxW / 16 : kMaxW / 4;  // 4 or 16 k-steps (W = 64)
+  constexpr int KS1 = F::KS1, KS2 = F::KS2;
   const int ks2 = BF16 ? W / 16 : W / 4;
-  float b2r[3];
-  typename std::conditional<BF16, s4, float>::type B2[3][KS2];
+  typedef typename F::Op Op;
+  const Op *f1 = reinterpret_cast<const Op *>(a.frag);
+  const Op *f2 = f1 + F::n1;
+  const float *fb1 = reinterpret_cast<const float *>(f2 + F::n2);
+  const float *fb2 = fb1 + F::nb;
+  Op B1[3][KS1], B2[3][KS2];
+  float b1r[3], b2r[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int c = w + 4 * q;
-    const bool on = c < n2tiles;
-    int head = 0, col0 = 0, ncol = 0;
-    if (on) l2_tile(c, k, head, col0, ncol);
-    const int col = col0 + lc;
-    const bool cv = on && col < ncol;
-    b2r[q] = cv ? pick3(a.b2, head)[col] : 0.0f;
-    const int base = head == 0 ? w2off[0] : (head == 1 ? w2off[1] : w2off[2]);
 #pragma unroll
-    for (int ks = 0; ks < KS2; ++ks) {
-      float v[KV];
+    for (int ks = 0; ks < KS1; ++ks) B1[q][ks] = f1[((w * 3 + q) * KS1 + ks) * kWave + l];
 #pragma unroll
-      for (int j = 0; j < KV; ++j) {
-        const int kk = ks * (4 * KV) + g * KV + j;
-        v[j] = (cv && kk < W) ? wval(base + kk * ncol + col) : 0.0f;
-      }
-      if constexpr (BF16) {
-        s4 s;
-        s[0] = (short)f2bf(v[0]); s[1] = (short)f2bf(v[1]);
-        s[2] = (short)f2bf(v[2]); s[3] = (short)f2bf(v[3]);
-        B2[q][ks] = s;
-      } else {
-        B2[q][ks] = v[0];
-      }
-    }
+    for (int ks = 0; ks < KS2; ++ks) B2[q][ks] = f2[((w * 3 + q) * KS2 + ks) * kWave + l];
+    b1r[q] = fb1[(w * 3 + q) * kWave + l];
+    b2r[q] = fb2[(w * 3 + q) * kWave + l];
   }
-  __syncthreads();
 
   const int64_t cap = a.cap;
 
@@ -393,15 +376,24 @@ __global__ void k_zero_count(uint32_t *p) { *p = 0u; }
 
 using namespace octgs;
 
+extern "C" size_t octgs_decode_workspace_bytes(int32_t precision) {
+  if (precision == OCTGS_BF16) return Frag<true>::bytes;
+  if (precision == OCTGS_FP32) return Frag<false>::bytes;
+  return 0;
+}
+
 extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
                             const octgs_camera *cam, const uint32_t *idx, const uint32_t *count,
-                            int precision, const octgs_gaussians *out, octgs_stream stream) {
+                            int precision, const octgs_gaussians *out, void *ws, size_t ws_bytes,
+                            octgs_stream stream) {
   if (!an || !mlp || !cam || !idx || !count || !out) return OCTGS_EINVAL;
   if (!out->data || !out->count || out->capacity < 0) return OCTGS_EINVAL;
   if (an->feat_dim != 32) return OCTGS_EUNSUPPORTED;
   if (an->k < 1 || an->k > kMaxK) return OCTGS_EUNSUPPORTED;
   if (mlp->width < 16 || mlp->width > kMaxW || mlp->width % 16) return OCTGS_EUNSUPPORTED;
   if (precision != OCTGS_FP32 && precision != OCTGS_BF16) return OCTGS_EINVAL;
+  if (!ws || ((uintptr_t)ws & 15) || ws_bytes < octgs_decode_workspace_bytes(precision))
+    return OCTGS_EINVAL;
   if (an->n == 0) {  // nothing can be listed: the output is empty
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, (hipStream_t)stream, out->count);
     return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
@@ -410,11 +402,16 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   if (precision == OCTGS_FP32 && !an->feat) return OCTGS_EINVAL;
   if (precision == OCTGS_BF16 && !an->feat_bf16) return OCTGS_EINVAL;
   if (!(an->d_max > 0.0f)) return OCTGS_EINVAL;
-  for (int h = 0; h < 3; ++h) {
+  for (int h = 0; h < 3; ++h)
     if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h]) return OCTGS_EINVAL;
-    if (((uintptr_t)mlp->w1[h] | (uintptr_t)mlp->w2[h]) & 15) return OCTGS_EINVAL;
-  }
   if (out->capacity / an->k > 0x7fffffff) return OCTGS_EINVAL;
+  PrepArgs pa;
+  pa.k = an->k;
+  pa.W = mlp->width;
+  for (int h = 0; h < 3; ++h) {
+    pa.w1[h] = mlp->w1[h]; pa.b1[h] = mlp->b1[h]; pa.w2[h] = mlp->w2[h]; pa.b2[h] = mlp->b2[h];
+  }
+  pa.ws = ws;
   DecodeArgs a;
   a.n = an->n;
   a.k = an->k;
@@ -424,9 +421,7 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   for (int c = 0; c < 3; ++c) a.C[c] = cam->C[c];
   a.pos = an->pos; a.feat = an->feat; a.feat_bf16 = an->feat_bf16;
   a.offsets = an->offsets; a.oscale = an->offset_scale; a.bscale = an->base_scale;
-  for (int h = 0; h < 3; ++h) {
-    a.w1[h] = mlp->w1[h]; a.b1[h] = mlp->b1[h]; a.w2[h] = mlp->w2[h]; a.b2[h] = mlp->b2[h];
-  }
+  a.frag = ws;
   a.blend = cam->lod_blend ? 1 : 0;
   if (a.blend) {
     if (!an->level || !an->lod_bias || an->n_levels < 1 || !(cam->lod_scale2 > 0.0f))
@@ -441,13 +436,18 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   a.out_count = out->count;
   const int64_t tiles = std::max<int64_t>(1, (a.cap_anchors + kTM - 1) / kTM);
   // persistent blocks: each loads its weight slices once and loops over
-  // tiles; as many as stay resident at once (LDS: 2 FP32 or 4 BF16 blocks
-  // per CU), blocks without a tile exit before loading weights
+  // tiles; as many as stay resident at once (2 FP32 or 4 BF16 blocks per
+  // CU); blocks without a tile exit before loading weights
   const int grid = (int)std::min<int64_t>(tiles, precision == OCTGS_BF16 ? 1024 : 512);
   hipStream_t s = (hipStream_t)stream;
-  if (precision == OCTGS_BF16)
+  if (precision == OCTGS_BF16) {
+    constexpr size_t n = Frag<true>::n1 + Frag<true>::n2 + Frag<true>::nb;
+    hipLaunchKernelGGL(k_decode_prep<true>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pa);
     hipLaunchKernelGGL(k_decode<true>, dim3(grid), dim3(kBlock), 0, s, a);
-  else
+  } else {
+    constexpr size_t n = Frag<false>::n1 + Frag<false>::n2 + Frag<false>::nb;
+    hipLaunchKernelGGL(k_decode_prep<false>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pa);
     hipLaunchKernelGGL(k_decode<false>, dim3(grid), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }

@@ -382,9 +382,15 @@ class ViewBuffers:
                stream=None):
         idx = self.sel_idx if idx is None else idx
         count = self.sel_count if count is None else count
-        L.check(L.lib().octgs_decode(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
-                                     ctypes.byref(cam), _ptr(idx), _ptr(count), int(precision),
-                                     ctypes.byref(self._g), stream_handle(stream)), "octgs_decode")
+        lib = L.lib()
+        need = lib.octgs_decode_workspace_bytes(int(precision))
+        if getattr(self, "dec_fwd_ws", None) is None or self.dec_fwd_ws.numel() < need:
+            self.dec_fwd_ws = torch.empty(max(need, 16), dtype=torch.uint8,
+                                          device=self.gauss.device)
+        L.check(lib.octgs_decode(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                 ctypes.byref(cam), _ptr(idx), _ptr(count), int(precision),
+                                 ctypes.byref(self._g), _ptr(self.dec_fwd_ws),
+                                 self.dec_fwd_ws.numel(), stream_handle(stream)), "octgs_decode")
 
     def decode_explicit(self, ex: "DeviceExplicit", cam: L.Camera, precision: int = L.OCTGS_FP32,
                         idx: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None,

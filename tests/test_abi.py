@@ -45,7 +45,7 @@ def test_host_only_entry_points():
     assert lib.octgs_raster_workspace_bytes(-1, 0, 1, 1) == 0
     # argument validation fails before any device work
     assert lib.octgs_select_lod(None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
-    assert lib.octgs_decode(None, None, None, None, None, 0, None, None) == L.OCTGS_EINVAL
+    assert lib.octgs_decode(None, None, None, None, None, 0, None, None, 0, None) == L.OCTGS_EINVAL
     assert lib.octgs_decode_explicit(None, None, None, None, None, 0, None, None) == L.OCTGS_EINVAL
     assert lib.octgs_decode_explicit_bwd(None, None, None, None, None, None, 0, None,
                                          None) == L.OCTGS_EINVAL
