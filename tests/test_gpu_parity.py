@@ -7,6 +7,8 @@ generators (synth) or from the oracle; nothing the oracle reads comes from
 the GPU.
 """
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -376,3 +378,48 @@ def test_decode_bwd_rejects_blend(P, c1):
     grads = P.SceneGrads(ds)
     with pytest.raises(P.OctgsError):
         vb.decode_bwd(ds, P.make_camera(cam, lod_blend=True), grads)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_decode_follows_weight_updates(P, orc, c1, bf16):
+    """Each decode call rewrites its weight fragments from the MLP as it is
+    at that moment: after the weights change in place, the next decode with
+    the same workspace matches the oracle's decode of the new weights (and
+    differs from the old result); a workspace below the stated size is
+    rejected."""
+    import copy
+    sc = copy.copy(c1)
+    sc.mlp = {k: v.copy() for k, v in c1.mlp.items()}
+    cam = S.config1_camera()
+    idx = np.arange(0, sc.n, 3, dtype=np.int64)
+    prec = P.OCTGS_BF16 if bf16 else P.OCTGS_FP32
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 16)
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    G = len(idx) * sc.k
+    vb.decode(ds, c, prec, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    first = _np(vb.gauss[:, :G]).copy()
+    rng = np.random.default_rng(5)
+    for name in sorted(sc.mlp):
+        sc.mlp[name] = (sc.mlp[name] * np.float32(0.5)
+                        + np.float32(0.1) * rng.standard_normal(sc.mlp[name].shape)
+                        ).astype(np.float32)
+        ds.mlp[name].copy_(torch.as_tensor(sc.mlp[name]))
+    say("decode after a weight update", "bf16" if bf16 else "fp32", len(idx))
+    vb.decode(ds, c, prec, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    got = _np(vb.gauss[:, :G]).astype(np.float64)
+    ref = orc.decode(sc, idx, cam)
+    bound = decoded_field_bounds(sc, idx, cam, ref, bf16)
+    assert np.all(np.abs(got - ref) <= bound)
+    assert np.abs(got[10:] - first[10:]).max() > 1e-3
+    from paper_2403_17898_amd import _lib as L
+    need = L.lib().octgs_decode_workspace_bytes(int(prec))
+    assert need > 0 and L.lib().octgs_decode_workspace_bytes(7) == 0
+    r = L.lib().octgs_decode(ctypes.byref(ds.anchors), ctypes.byref(ds._mlp), ctypes.byref(c),
+                             idx_t.data_ptr(), cnt_t.data_ptr(), int(prec), ctypes.byref(vb._g),
+                             vb.dec_fwd_ws.data_ptr(), need - 16, None)
+    assert r == L.OCTGS_EINVAL
