@@ -200,7 +200,8 @@ struct RasterWs {
   uint32_t *pair_slot;    // [pcap] slot of each pair in emission order (a Gaussian's pairs
                           // are contiguous there)
   uint32_t *ranges;       // [tiles][2]
-  uint32_t *hist;         // [8][256] radix histograms (4 depth passes, then 1..4 tile passes)
+  uint32_t *hist;         // [kHistCopies][8][256] radix histograms (4 depth passes, then 1..4
+                          // tile passes); block b adds into copy b % kHistCopies
   uint32_t *lookback;     // [4][ceil(gcap / kSortPart)][256] depth-sort look-back
   uint32_t *lookback_t;   // [tile passes][ceil(pcap / kSortPart)][256] tile-sort look-back
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
@@ -210,6 +211,13 @@ struct RasterWs {
   size_t lb_words, lbt_words;  // look-back words to clear before the sorts
   size_t bytes;
 };
+
+// Producers spread their histogram atomics over this many copies (one per
+// XCD for round-robin dispatch), which the sort sums: atomics on global
+// memory are performed at the memory side, and one copy served by every
+// block serialises them.
+constexpr int kHistCopies = 8;
+constexpr uint32_t kHistStride = 8 * 256;
 
 constexpr int kEmitThreads = 1024;  // pair emission: threads per block
 constexpr int kEmitRun = 8192;      // candidate pairs per block of the emission
@@ -236,12 +244,14 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
 // key, stably.  On return the sorted data is in buffers index `passes % 2`.
-// lookback: passes * ceil(cap / kSortPart) * 256 words.  With prepared ==
-// false a first kernel builds hist ([passes][256], zeroed beforehand) and
-// clears the look-back words; with prepared == true the caller has done both.
+// hist: the digit histograms of the passes, [passes][256] words, as the sum
+// of hist_copies copies hist_stride words apart (built by the producer of
+// the keys); lookback: passes * ceil(cap / kSortPart) * 256 words, cleared
+// by the producer for the partitions in use.
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
-                      uint32_t *lookback, uint32_t *err_flag, bool prepared, hipStream_t stream);
+                      const uint32_t *count, int64_t cap, int passes, const uint32_t *hist,
+                      int hist_copies, uint32_t hist_stride, uint32_t *lookback,
+                      uint32_t *err_flag, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // chained scan: decoupled look-back over one value per partition

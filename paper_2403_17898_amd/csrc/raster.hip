@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
       reinterpret_cast<uint32_t *>(ws.hdr)[t] = t == 0 ? n : 0u;  // n_slots is word 0
     const size_t nr = 2 * (size_t)ws.tiles_x * ws.tiles_y;
     for (size_t i = gi; i < nr; i += gs) ws.ranges[i] = 0u;
-    for (size_t i = gi; i < 8 * 256; i += gs) ws.hist[i] = 0u;
+    for (size_t i = gi; i < kHistCopies * kHistStride; i += gs) ws.hist[i] = 0u;
     for (size_t i = gi; i < (size_t)ws.nblk_g; i += gs) ws.lb_emit[i] = 0u;
     for (size_t i = gi; i < (size_t)ws.nruns; i += gs) ws.lb_pair[i] = 0u;
   }
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     const uint32_t v = h[d][t];
-    if (v) atomicAdd(&ws.hist[d * 256 + t], v);
+    if (v) atomicAdd(&ws.hist[(blockIdx.x % kHistCopies) * kHistStride + d * 256 + t], v);
   }
 }
 
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   if (t < 256)
     for (int d = 0; d < tile_passes; ++d) {
       const uint32_t v = h[d][t];
-      if (v) atomicAdd(&ws.hist[(4 + d) * 256 + t], v);
+      if (v) atomicAdd(&ws.hist[(blockIdx.x % kHistCopies) * kHistStride + (4 + d) * 256 + t], v);
     }
 }
 
@@ -774,7 +774,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   for (int i = 0; i < 2; ++i) ws.tpair[i] = (uint32_t *)take((size_t)pc * 4);
   ws.pair_slot = (uint32_t *)take((size_t)pc * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
-  ws.hist = (uint32_t *)take(8 * 256 * 4);
+  ws.hist = (uint32_t *)take(kHistCopies * kHistStride * 4);
   ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
   ws.lb_words = (size_t)4 * ((g + kSortPart - 1) / kSortPart) * 256;
   ws.lbt_words = (size_t)ws.tile_passes * ((pc + kSortPart - 1) / kSortPart) * 256;
@@ -846,7 +846,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(2);
   // histograms and cleared look-back words come from the kernels above
   hipError_t e = radix_sort(ws.dkey, ws.dval, nullptr, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
-                            ws.lookback, &ws.hdr->sync_error, true, s);
+                            kHistCopies, kHistStride, ws.lookback, &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   mark(3);
   mark(4);
@@ -857,8 +857,8 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(6);
   const int passes = ws.tile_passes;
   e = radix_sort(ws.tkey, ws.tval, (p->flags & OCTGS_RASTER_TRAIN) ? ws.tpair : nullptr,
-                 &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256,
-                 ws.lookback_t, &ws.hdr->sync_error, true, s);
+                 &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256, kHistCopies,
+                 kHistStride, ws.lookback_t, &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 8192);

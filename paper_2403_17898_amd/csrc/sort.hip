@@ -1,7 +1,7 @@
 // Stable LSD radix sort of u32 keys carrying one or two u32 values, 8-bit digits, in the
 // Onesweep structure (Adinets and Merrill, "Onesweep: A Faster Least
-// Significant Digit Radix Sort for GPUs", 2022): one kernel builds the
-// digit histograms of all passes, then each pass is a single kernel whose
+// Significant Digit Radix Sort for GPUs", 2022): the kernels that produce the
+// keys build the digit histograms of all passes, then each pass is a single kernel whose
 // block p ranks the keys of partition p locally and resolves the global
 // digit offsets with a decoupled look-back over the preceding partitions.
 // Blocks are dispatched in index order, so a partition only ever waits on
@@ -22,36 +22,6 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr int kLookWin = 16;
 
-// Histogram of every pass at once, plus clearing of the look-back words the
-// passes will use.  Grid-stride over the keys.
-__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint32_t *__restrict__ keys,
-                                                      const uint32_t *__restrict__ count,
-                                                      int passes, uint32_t *__restrict__ hist,
-                                                      uint32_t *__restrict__ lookback,
-                                                      uint64_t lb_stride) {
-  __shared__ uint32_t h[4][256];
-  const uint32_t n = *count;
-  const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
-  // clear the look-back words of the partitions each pass will use
-  const uint64_t nlb = (uint64_t)nparts * 256u;
-  for (int p = 0; p < passes; ++p)
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nlb;
-         i += (uint64_t)gridDim.x * kBlock)
-      lookback[lb_stride * p + i] = 0u;
-  for (int i = threadIdx.x; i < 4 * 256; i += kBlock) (&h[0][0])[i] = 0u;
-  __syncthreads();
-  if (blockIdx.x * kBlock >= n) return;  // no keys for this block
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    uint32_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
-  }
-  __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-    uint32_t v = h[p][threadIdx.x];
-    if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
-  }
-}
-
 template <int NV>
 struct PassSmem {
   uint32_t wcnt[4][256];     // per-wave digit counters, then per-wave exclusive offsets
@@ -69,8 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     uint32_t *__restrict__ vout2, const uint32_t *__restrict__ count, int shift,
-    const uint32_t *__restrict__ hist, uint32_t *__restrict__ lookback,
-    uint32_t *__restrict__ err_flag) {
+    const uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride,
+    uint32_t *__restrict__ lookback, uint32_t *__restrict__ err_flag) {
   __shared__ PassSmem<NV> sm;
   const uint32_t n = *count;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
@@ -79,10 +49,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 
   if (blockIdx.x >= nparts) return;
 
-  // exclusive scan of the pass histogram over digits
+  // exclusive scan of the pass histogram (the sum of its copies) over digits
   {
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(hist[t], sm.tmp, &tot);
+    uint32_t hv = 0, tot;
+    for (int c = 0; c < hist_copies; ++c) hv += hist[(size_t)c * hist_stride + t];
+    uint32_t ex = block_excl_scan(hv, sm.tmp, &tot);
     sm.hexcl[t] = ex;
   }
 
@@ -215,16 +186,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 }  // namespace
 
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
-                      uint32_t *lookback, uint32_t *err_flag, bool prepared,
-                      hipStream_t stream) {
+                      const uint32_t *count, int64_t cap, int passes, const uint32_t *hist,
+                      int hist_copies, uint32_t hist_stride, uint32_t *lookback,
+                      uint32_t *err_flag, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
-  const int hist_grid = (int)std::min<int64_t>(std::max<int64_t>(nparts_cap, 1), 256);
   const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
-  if (!prepared)
-    hipLaunchKernelGGL(k_sort_hist, dim3(hist_grid), dim3(kBlock), 0, stream, keys[0], count,
-                       passes, hist, lookback, (uint64_t)lb_stride);
   // one block per possible partition; blocks past the actual count exit
   const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
   for (int p = 0; p < passes; ++p) {
@@ -232,11 +199,13 @@ hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *val
     if (vals2)
       hipLaunchKernelGGL(k_sort_pass<2>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p,
-                         hist + 256 * p, lookback + lb_stride * p, err_flag);
+                         hist + 256 * p, hist_copies, hist_stride, lookback + lb_stride * p,
+                         err_flag);
     else
       hipLaunchKernelGGL(k_sort_pass<1>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p,
-                         hist + 256 * p, lookback + lb_stride * p, err_flag);
+                         hist + 256 * p, hist_copies, hist_stride, lookback + lb_stride * p,
+                         err_flag);
   }
   return hipGetLastError();
 }
