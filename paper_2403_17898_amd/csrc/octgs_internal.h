@@ -245,11 +245,12 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
 // key, stably.  On return the sorted data is in buffers index `passes % 2`.
 // hist: the digit histograms of the passes, [passes][256] words, as the sum
-// of hist_copies copies hist_stride words apart (built by the producer of
-// the keys); lookback: passes * ceil(cap / kSortPart) * 256 words, cleared
-// by the producer for the partitions in use.
+// of hist_copies (1..kHistCopies) copies hist_stride words apart (built by
+// the producer of the keys; the first pass folds the later passes' copies
+// into copy 0); lookback: passes * ceil(cap / kSortPart) * 256 words,
+// cleared by the producer for the partitions in use.
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, const uint32_t *hist,
+                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
                       uint32_t *err_flag, hipStream_t stream);
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     uint32_t *__restrict__ vout2, const uint32_t *__restrict__ count, int shift,
-    const uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride,
+    uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride, int fold_passes,
     uint32_t *__restrict__ lookback, uint32_t *__restrict__ err_flag) {
   __shared__ PassSmem<NV> sm;
   const uint32_t n = *count;
@@ -51,8 +51,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 
   // exclusive scan of the pass histogram (the sum of its copies) over digits
   {
-    uint32_t hv = 0, tot;
-    for (int c = 0; c < hist_copies; ++c) hv += hist[(size_t)c * hist_stride + t];
+    uint32_t hc[kHistCopies], hv = 0, tot;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c)
+      hc[c] = c < hist_copies ? hist[(size_t)c * hist_stride + t] : 0u;  // all loads in flight
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) hv += hc[c];
     uint32_t ex = block_excl_scan(hv, sm.tmp, &tot);
     sm.hexcl[t] = ex;
   }
@@ -181,30 +185,46 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
       }
     }
   }
+  // the first pass folds the later passes' histogram copies into copy 0,
+  // after its own look-back so the chain does not wait for it; the later
+  // passes then read one copy
+  if (blockIdx.x == 0) {
+    for (int q = 1; q <= fold_passes; ++q) {
+      uint32_t hc[kHistCopies], hv = 0;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c)
+        hc[c] = c < hist_copies ? hist[(size_t)c * hist_stride + 256 * q + t] : 0u;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) hv += hc[c];
+      hist[256 * q + t] = hv;
+    }
+  }
 }
 
 }  // namespace
 
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, const uint32_t *hist,
+                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
                       uint32_t *err_flag, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
+  if (hist_copies < 1 || hist_copies > kHistCopies) return hipErrorInvalidValue;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
   const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
   // one block per possible partition; blocks past the actual count exit
   const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
   for (int p = 0; p < passes; ++p) {
     const int src = p & 1, dst = src ^ 1;
+    const int copies = p == 0 ? hist_copies : 1, fold = p == 0 ? passes - 1 : 0;
     if (vals2)
       hipLaunchKernelGGL(k_sort_pass<2>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p,
-                         hist + 256 * p, hist_copies, hist_stride, lookback + lb_stride * p,
+                         hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
                          err_flag);
     else
       hipLaunchKernelGGL(k_sort_pass<1>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p,
-                         hist + 256 * p, hist_copies, hist_stride, lookback + lb_stride * p,
+                         hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
                          err_flag);
   }
   return hipGetLastError();

@@ -7,9 +7,16 @@ namespace octgs {
 
 namespace {
 
-// Grid-stride with four independent elements per thread per step; one
-// atomic per block for the loss (every atomic on the one loss address is
-// serialised across the XCDs, so the grid stays small).
+// Grid-stride over float4 groups, four groups per thread per step with all
+// loads issued before any use; one atomic per block for the loss (every
+// atomic on the one loss address is serialised across the XCDs, so the grid
+// stays small).  The tail (n % 4 elements) and unaligned arrays take the
+// scalar loop.
+__device__ __forceinline__ float l1_one(float d, float scale, float &acc) {
+  acc += fabsf(d);
+  return d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+}
+
 __global__ __launch_bounds__(kBlock) void k_l1(const float *__restrict__ img,
                                                const float *__restrict__ tgt, int64_t n,
                                                float scale, float *__restrict__ dimg,
@@ -17,22 +24,34 @@ __global__ __launch_bounds__(kBlock) void k_l1(const float *__restrict__ img,
   __shared__ float red[4];
   float acc = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += 4 * stride) {
-    float d[4];
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool vec = (((uintptr_t)img | (uintptr_t)tgt | (uintptr_t)dimg) & 15) == 0;
+  const int64_t n4 = vec ? n / 4 : 0;
+  const float4 *a4 = reinterpret_cast<const float4 *>(img);
+  const float4 *b4 = reinterpret_cast<const float4 *>(tgt);
+  float4 *d4 = reinterpret_cast<float4 *>(dimg);
+  for (int64_t i0 = tid; i0 < n4; i0 += 4 * stride) {
+    float4 a[4], b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t i = min(i0 + u * stride, n - 1);
-      d[u] = img[i] - tgt[i];
+      const int64_t i = min(i0 + u * stride, n4 - 1);
+      a[u] = a4[i];
+      b[u] = b4[i];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t i = i0 + u * stride;
-      if (i < n) {
-        dimg[i] = d[u] > 0.0f ? scale : (d[u] < 0.0f ? -scale : 0.0f);
-        acc += fabsf(d[u]);
+      if (i < n4) {
+        float4 d;
+        d.x = l1_one(a[u].x - b[u].x, scale, acc);
+        d.y = l1_one(a[u].y - b[u].y, scale, acc);
+        d.z = l1_one(a[u].z - b[u].z, scale, acc);
+        d.w = l1_one(a[u].w - b[u].w, scale, acc);
+        d4[i] = d;
       }
     }
   }
+  for (int64_t i = 4 * n4 + tid; i < n; i += stride) dimg[i] = l1_one(img[i] - tgt[i], scale, acc);
   acc = block_sum_f(acc, red);
   if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
 }
@@ -67,6 +86,18 @@ struct AdamMany {
   int count;
 };
 
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr, float b1,
+                                         float b2, float eps, float c1, float c2) {
+  m = __builtin_fmaf(b1, m, (1.0f - b1) * g);
+  v = __builtin_fmaf(b2, v, (1.0f - b2) * g * g);
+  p -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+}
+
+// Each block updates one kAdamChunk-element chunk of one array: four float4
+// groups per thread, all of their loads issued before the first update (the
+// compiler cannot reorder loads across the stores itself, the arrays may
+// alias as far as it knows).  Arrays whose four pointers are not 16-byte
+// aligned, and the end of an array, take the scalar loop.
 __global__ __launch_bounds__(kBlock) void k_adam_many(AdamMany a, float lr, float b1, float b2,
                                                       float eps, float c1, float c2) {
   const uint32_t b = blockIdx.x;
@@ -81,13 +112,39 @@ __global__ __launch_bounds__(kBlock) void k_adam_many(AdamMany a, float lr, floa
     }
   const int64_t e0 = (int64_t)(b - b0) * kAdamChunk;
   const int64_t e1 = min(n, e0 + kAdamChunk);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const float gi = g[e];
-    const float mi = __builtin_fmaf(b1, m[e], (1.0f - b1) * gi);
-    const float vi = __builtin_fmaf(b2, v[e], (1.0f - b2) * gi * gi);
-    m[e] = mi;
-    v[e] = vi;
-    p[e] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  const bool vec = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15) == 0;
+  const int t = threadIdx.x;
+  int64_t done = e0;
+  if (vec && e1 - e0 == kAdamChunk) {
+    constexpr int U = kAdamChunk / (4 * kBlock);
+    float4 pv[U], gv[U], mv[U], vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = e0 / 4 + u * kBlock + t;
+      pv[u] = reinterpret_cast<const float4 *>(p)[i];
+      gv[u] = reinterpret_cast<const float4 *>(g)[i];
+      mv[u] = reinterpret_cast<const float4 *>(m)[i];
+      vv[u] = reinterpret_cast<const float4 *>(v)[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      adam_one(pv[u].x, gv[u].x, mv[u].x, vv[u].x, lr, b1, b2, eps, c1, c2);
+      adam_one(pv[u].y, gv[u].y, mv[u].y, vv[u].y, lr, b1, b2, eps, c1, c2);
+      adam_one(pv[u].z, gv[u].z, mv[u].z, vv[u].z, lr, b1, b2, eps, c1, c2);
+      adam_one(pv[u].w, gv[u].w, mv[u].w, vv[u].w, lr, b1, b2, eps, c1, c2);
+      const int64_t i = e0 / 4 + u * kBlock + t;
+      reinterpret_cast<float4 *>(p)[i] = pv[u];
+      reinterpret_cast<float4 *>(m)[i] = mv[u];
+      reinterpret_cast<float4 *>(v)[i] = vv[u];
+    }
+    done = e1;
+  }
+  for (int64_t e = done + t; e < e1; e += kBlock) {
+    float pe = p[e], me = m[e], ve = v[e];
+    adam_one(pe, g[e], me, ve, lr, b1, b2, eps, c1, c2);
+    m[e] = me;
+    v[e] = ve;
+    p[e] = pe;
   }
 }
 
