@@ -109,8 +109,10 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
   const uint32_t *pidx = a.ws.tpair[a.buf];  // its emission index
   const float4 *proj = a.ws.proj;
   const size_t plane = (size_t)a.W * a.H;
-  // per pixel: T, dL/dC, colour behind (starts as T_final * bg), entries used
-  float T[kBPx], dr[kBPx], dg[kBPx], db[kBPx], br[kBPx], bgc[kBPx], bb[kBPx];
+  // per pixel: T, dL/dC, S = dL/dC . (colour behind) (starts as T_final
+  // dL/dC . bg; dL/dC is fixed per pixel, so the dot product is accumulated
+  // instead of the colour), entries used
+  float T[kBPx], dr[kBPx], dg[kBPx], db[kBPx], S[kBPx];
   uint32_t last[kBPx];
   uint32_t mx = 0;
 #pragma unroll
@@ -124,9 +126,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
       dg[k] = a.dimg[plane + pix];
       db[k] = a.dimg[2 * plane + pix];
     }
-    br[k] = T[k] * a.bg[0];
-    bgc[k] = T[k] * a.bg[1];
-    bb[k] = T[k] * a.bg[2];
+    S[k] = T[k] * fma_(a.bg[0], dr[k], fma_(a.bg[1], dg[k], a.bg[2] * db[k]));
     mx = max(mx, last[k]);
   }
 #pragma unroll
@@ -168,9 +168,11 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
       float d = fma_(B.x, fma_(2.0f, dy, 1.0f), bdx);
       const float c2 = B.x + B.x;
       // raw per-lane sums, turned into gradients once per (tile, Gaussian):
-      // dq = dL/da a0 (0 where alpha is clamped); D = sum dq over the
-      // thread's pixels, Sy = sum dq dy, Qyy = sum dq dy^2; colour weights
-      float D = 0.0f, Sy = 0.0f, Qyy = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
+      // dq = dL/da a0 (0 where alpha is clamped); over the thread's pixels
+      // k = 0..3 (dy = dy0 + k), D = sum dq, E = sum k dq, F = sum k^2 dq,
+      // so sum dq dy = dy0 D + E and sum dq dy^2 = dy0^2 D + 2 dy0 E + F;
+      // colour weights
+      float D = 0.0f, E = 0.0f, F = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kBPx; ++k) {
@@ -184,7 +186,6 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
         if (AMIN) valid = valid && !(al < amin);
         if (valid) {
           any = true;
-          const float dyk = (fy + (float)k) - A.y;
           const float inv1 = __builtin_amdgcn_rcpf(1.0f - al);
           const float Ti = T[k] * inv1;
           const float w = al * Ti;
@@ -192,21 +193,21 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
           wg = fma_(w, dg[k], wg);
           wb = fma_(w, db[k], wb);
           const float cdot = fma_(B.z, dr[k], fma_(B.w, dg[k], Cc.x * db[k]));
-          const float bdot = fma_(br[k], dr[k], fma_(bgc[k], dg[k], bb[k] * db[k]));
-          const float dLda = Ti * cdot - bdot * inv1;
-          br[k] = fma_(w, B.z, br[k]);
-          bgc[k] = fma_(w, B.w, bgc[k]);
-          bb[k] = fma_(w, Cc.x, bb[k]);
+          const float dLda = Ti * cdot - S[k] * inv1;
+          S[k] = fma_(w, cdot, S[k]);
           T[k] = Ti;
           const float dq = a0 <= amax ? dLda * a0 : 0.0f;
           D += dq;
-          const float dqy = dq * dyk;
-          Sy += dqy;
-          Qyy = fma_(dqy, dyk, Qyy);
+          if (k > 0) {
+            E = fma_((float)k, dq, E);
+            F = fma_((float)(k * k), dq, F);
+          }
         }
       }
       if (ballot(any) != 0ull) {
         int q;
+        const float Sy = fma_(dy, D, E);
+        const float Qyy = fma_(dy, fma_(dy, D, 2.0f * E), F);
         const float v8[8] = {D, D * dx, D * dx * dx, Sy, Sy * dx, Qyy, wr, wg};
         const float s8 = wave_sum8(v8, q);
         const float s9 = wave_sum_f(wb);
