@@ -1,7 +1,8 @@
-// Tiled FP32 GEMM used by the skip-predictor training: 64x64 output tiles, K in steps of 16 staged through LDS, 4x4
-// outputs per thread, optional split-K with atomic accumulation, and an
-// epilogue with bias add and a ReLU-derivative mask.  One of M or K may be a
-// device-resident count, so launches need no host synchronisation.
+// Tiled FP32 GEMM used by the skip-predictor training: 64x64 output tiles,
+// K in steps of 16 staged through LDS, 4x4 outputs per thread, optional
+// split-K with atomic accumulation, and an epilogue with bias add and a
+// ReLU-derivative mask.  One of M or K may be a device-resident count, so
+// launches need no host synchronisation.
 #include "octgs_internal.h"
 
 namespace octgs {
