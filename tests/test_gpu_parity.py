@@ -423,3 +423,42 @@ def test_decode_follows_weight_updates(P, orc, c1, bf16):
                              idx_t.data_ptr(), cnt_t.data_ptr(), int(prec), ctypes.byref(vb._g),
                              vb.dec_fwd_ws.data_ptr(), need - 16, None)
     assert r == L.OCTGS_EINVAL
+
+
+@pytest.mark.parametrize("k,W", [(1, 16), (16, 64), (7, 48), (13, 32)])
+def test_decode_shapes(P, orc, k, W):
+    """Decode forward (FP32 and BF16, within the per-element bounds) and the
+    fused decode backward (against the oracle's FP64 gradients) at the
+    extremes of the supported shapes: k = 1..16 Gaussians per anchor, MLP
+    width 16..64, with a ragged anchor count (not a multiple of the tile)."""
+    sc, cam = S.make_gradcheck_scene(seed=11 + k, n=77, k=k, width=W)
+    idx = np.arange(0, sc.n, dtype=np.int64)[::-1][:71].copy()
+    ds = P.DeviceScene.from_scene(sc)
+    G = len(idx) * k
+    vb = P.ViewBuffers(sc.n, k, 64, 64, 1 << 14, gauss_capacity=G + 5 * k)
+    idx_t = torch.as_tensor(idx.astype(np.int32)).cuda()
+    cnt_t = torch.tensor([len(idx)], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    ref = orc.decode(sc, idx, cam)
+    for bf16 in (False, True):
+        say(f"decode k={k} W={W}", "bf16" if bf16 else "fp32")
+        vb.decode(ds, c, P.OCTGS_BF16 if bf16 else P.OCTGS_FP32, idx=idx_t, count=cnt_t)
+        torch.cuda.synchronize()
+        assert int(vb.gauss_count.item()) == G
+        got = _np(vb.gauss[:, :G]).astype(np.float64)
+        bound = decoded_field_bounds(sc, idx, cam, ref, bf16)
+        assert np.all(np.abs(got - ref) <= bound), np.argwhere(np.abs(got - ref) > bound)[:5]
+    rng = np.random.default_rng(k * 100 + W)
+    dg = rng.standard_normal((14, G)).astype(np.float32)
+    want = orc.decode_backward(sc, idx, cam, dg.astype(np.float64))
+    grads = P.SceneGrads(ds)
+    dgt = torch.zeros(14, vb.gcap, device="cuda")
+    dgt[:, :G] = torch.as_tensor(dg).cuda()
+    vb.decode_bwd(ds, c, grads, dgauss=dgt, idx=idx_t, count=cnt_t)
+    torch.cuda.synchronize()
+    got = {n: _np(v) for n, v in grads.all().items()}
+    for name, r in want.items():
+        a, b = np.asarray(got[name], np.float64), np.asarray(r, np.float64)
+        e = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+        say(f"  d{name}: rel err {e:.2e}")
+        assert e <= 1e-4, name
