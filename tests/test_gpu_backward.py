@@ -231,3 +231,34 @@ def test_adam_many_matches_single(P):
         assert torch.equal(a, b)
     for (m1, v1), (m2, v2) in zip(ms, ref_m):
         assert torch.equal(m1, m2) and torch.equal(v1, v2)
+
+
+@pytest.mark.parametrize("n,seed", [(1800, 31), (6000, 32)])
+def test_raster_backward_long_tile_lists(P, orc, n, seed):
+    """The backward over tiles whose lists hold thousands of entries (each
+    pair's emission index travels through the tile sort with it)."""
+    cam = S.look_at((0.0, -8.0, 0.0), (0.0, 0.0, 0.0), 48, 32, 60.0)
+    gf = S.random_gaussians(n, cam, seed, depth=(3.0, 6.0), scale=(1.5, 3.0), margin=0.0,
+                            opacity=(0.002, 0.02))
+    prm = orc.params_array()
+    rng = np.random.default_rng(seed)
+    dimg = rng.standard_normal((3, 32, 48)).astype(np.float32)
+    say("raster backward, long lists", n)
+    ref = orc.rasterize(gf, cam, prm)
+    dproj = orc.composite_backward(ref["pj"], ref["bs"], cam, prm, dimg.astype(np.float64))
+    dref = orc.project_backward(gf.astype(np.float64), ref["pj"], cam, prm, dproj)
+    vb = P.ViewBuffers(n, 1, 48, 32, ref["bs"]["n_rect_pairs"] + 16, gauss_capacity=n)
+    gt = torch.as_tensor(gf).cuda()
+    cnt = torch.tensor([n], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    vb.rasterize(c, P.raster_params(train=True), gauss=gt, count=cnt)
+    vb.gauss.copy_(gt)
+    vb.gauss_count.copy_(cnt)
+    vb.rasterize_bwd(c, P.raster_params(train=True), torch.as_tensor(dimg).cuda())
+    torch.cuda.synchronize()
+    got = _np(vb.dgauss).astype(np.float64)
+    for nm, (a, b) in zip(("mean", "scale", "quat", "opacity", "rgb"),
+                          ((0, 3), (3, 6), (6, 10), (10, 11), (11, 14))):
+        e = rel(got[a:b], dref[a:b])
+        say(f"  d{nm}: rel err {e:.2e}")
+        assert e <= 1e-3, nm

@@ -462,3 +462,35 @@ def test_decode_shapes(P, orc, k, W):
         e = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
         say(f"  d{name}: rel err {e:.2e}")
         assert e <= 1e-4, name
+
+
+@pytest.mark.parametrize("n,seed", [(300, 21), (1800, 22), (6000, 23)])
+def test_raster_long_tile_lists(P, orc, n, seed):
+    """Every Gaussian covers every tile of a 48x32 image, so each tile's list
+    holds exactly n entries (up to 6000, longer than any benchmark view's).
+    Sorted lists and tile ranges bit-exact, image within 1e-4, blend-weight
+    log within its bar."""
+    cam = S.look_at((0.0, -8.0, 0.0), (0.0, 0.0, 0.0), 48, 32, 60.0)
+    gf = S.random_gaussians(n, cam, seed, depth=(3.0, 6.0), scale=(1.5, 3.0), margin=0.0,
+                            opacity=(0.002, 0.02))
+    prm_o = orc.params_array()
+    say("raster long lists", n, seed)
+    ref = orc.rasterize(gf, cam, prm_o, weights=True)
+    lens = ref["bs"]["ranges"][:, 1].astype(np.int64) - ref["bs"]["ranges"][:, 0]
+    say(f"  list lengths {lens.min()}..{lens.max()}")
+    vb = P.ViewBuffers(n, 1, 48, 32, max(ref["bs"]["n_rect_pairs"], 1), gauss_capacity=n,
+                       log_weights=True)
+    _gpu_raster(P, vb, gf, cam, P.raster_params())
+    st = vb.stats()
+    assert st["sync_error"] == 0 and st["pair_overflow"] == 0
+    assert st["n_pairs"] == ref["bs"]["n_pairs"]
+    tile, slot, ranges = vb.sorted_lists()
+    assert np.array_equal(tile, ref["bs"]["tile_of"])
+    assert np.array_equal(slot, ref["bs"]["gid_of"])
+    assert np.array_equal(ranges, ref["bs"]["ranges"])
+    img = _np(vb.rgb).astype(np.float64)
+    e = np.abs(img - ref["img"]).max()
+    say(f"  img max abs {e:.2e}")
+    assert e <= 1e-4
+    np.testing.assert_allclose(_np(vb.gauss_w).astype(np.float64), ref["weights"], rtol=2e-4,
+                               atol=2e-4)
