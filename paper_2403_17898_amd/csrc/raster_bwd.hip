@@ -24,13 +24,6 @@ namespace {
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-__global__ void k_zero_f32(float *p, const uint32_t *count_u, int64_t cap, int per) {
-  const uint64_t n = (uint64_t)min<int64_t>(*count_u, cap) * (uint64_t)per;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0f;
-}
-
 struct BwdArgs {
   RasterWs ws;
   int buf, W, H;
@@ -248,6 +241,14 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
 
 __global__ __launch_bounds__(kBwdThreads) void k_composite_bwd(BwdArgs a) {
   __shared__ BwdLds lds;
+  {
+    // the per-slot rows k_pair_reduce fills (partly by atomics) start at
+    // zero; this kernel does not touch them, so its blocks clear them
+    const uint64_t nz = (uint64_t)min<int64_t>(a.ws.hdr->n_slots, a.ws.gcap) * 9u;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBwdThreads + threadIdx.x; i < nz;
+         i += (uint64_t)gridDim.x * kBwdThreads)
+      a.ws.dproj[i] = 0.0f;
+  }
   if (a.alpha_min > 0.0f)
     composite_bwd_tile<true>(a, lds);
   else
@@ -480,7 +481,6 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   hipStream_t s = (hipStream_t)stream;
   RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
   const int ntiles = ws.tiles_x * ws.tiles_y;
-  hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, ws.dproj, &ws.hdr->n_slots, ws.gcap, 9);
   BwdArgs b;
   b.ws = ws;
   b.buf = tile_sort_passes(ntiles) % 2;
