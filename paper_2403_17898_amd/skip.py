@@ -174,7 +174,7 @@ def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
 def choose_threshold(vb: ViewBuffers, sb: SkipBuffers, scene: DeviceScene, cams, params, net,
                      candidates, min_psnr: float):
     """Most aggressive logit threshold whose worst-view PSNR against the full
-    decode (the judge) on the given views is >= min_psnr; None if none is."""
+    decode (the arbiter of quality) on the given views is >= min_psnr; None if none is."""
     refs = []
     for c in cams:
         vb.render(scene, c, params, precision=L.OCTGS_FP32)

@@ -3,8 +3,8 @@ regularisation) with the FP64 oracle, through the C ABI.
 
 Bars: the loss within 2e-6 (FP32 sums of 1024 terms in [0, 1] per block,
 the block sums then added in double); the image gradient within 1e-4
-normwise and 1e-3 of the largest entry elementwise (the spec gradient
-bar; the windowed variances lose a few bits to cancellation); the volume
+normwise and 1e-3 of the largest entry elementwise (the gradient
+bar used throughout; the windowed variances lose a few bits to cancellation); the volume
 gradient within 1e-6 relative (three FP32 products).
 """
 

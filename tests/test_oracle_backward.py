@@ -142,7 +142,7 @@ def _with(sc, name, arr):
 def test_full_chain_gradcheck_fd(orc):
     """50-anchor scene at 64x64: gradient of sum(w * image) through
     compositing, projection and decode, against central differences of the
-    FP64 forward; spec bar: normwise relative error <= 1e-3."""
+    FP64 forward; gradient bar: normwise relative error <= 1e-3."""
     sc, cam = S.make_gradcheck_scene()
     prm = orc.params_array()
     thr, rho = orc.scene_thresholds(sc)
