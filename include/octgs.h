@@ -203,7 +203,10 @@ OCTGS_API int octgs_decode(const octgs_anchors *a, const octgs_mlp *mlp, const o
                  const octgs_gaussians *out, void *ws, size_t ws_bytes, octgs_stream stream);
 
 /* Workspace bytes of octgs_rasterize_fwd / _bwd for a Gaussian-slot capacity,
- * a (tile, Gaussian) pair capacity and an image size. */
+ * a (tile, Gaussian) pair capacity and an image size; 0 for a negative
+ * capacity or an image outside the rasterizer's range (at most 2^24 16x16
+ * tiles, about 4.3 gigapixels; the two calls reject such images with
+ * OCTGS_EINVAL). */
 OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pair_capacity,
                                     int32_t width, int32_t height);
 

@@ -155,16 +155,43 @@ __device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Remap a linear block index so that each of the 8 XCDs (blocks are dealt
-// round-robin over XCDs) receives a contiguous range of work items.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
-  constexpr uint32_t kXcd = 8;
-  uint32_t per = nblocks / kXcd, rem = nblocks % kXcd;
-  uint32_t xcd = bid % kXcd, slot = bid / kXcd;
-  // XCDs with index < rem own per + 1 items
-  uint32_t start = xcd * per + (xcd < rem ? xcd : rem);
-  uint32_t own = per + (xcd < rem ? 1u : 0u);
-  return slot < own ? start + slot : bid;  // the fallback never triggers for full grids
+// Tile scheduling of the per-tile kernels (one block per tile).  Blocks are
+// dealt round-robin over the 8 XCDs, so block b runs on XCD b % 8.  Tiles
+// are grouped in squares of kTileGroup x kTileGroup and group g goes to XCD
+// g % 8: every XCD gets groups from all over the image, which balances the
+// dense and sparse regions of a view across the XCDs, while the tiles of one
+// group, which share most of their Gaussians, stay in one L2.
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kTileGroup = 4;
+// Largest number of 16x16 tiles per image (about 4.3 gigapixels): tile ids,
+// sort keys and the per-tile grids stay well inside 32 bits.
+constexpr int64_t kMaxTiles = int64_t(1) << 24;
+inline bool image_tiles_ok(int32_t width, int32_t height) {
+  if (width <= 0 || height <= 0) return false;
+  return (int64_t)((width + 15) / 16) * ((height + 15) / 16) <= kMaxTiles;
+}
+
+// Blocks to launch: 8 x kTileGroup^2 x ceil(groups / 8); the blocks past the
+// last group and those on tiles outside a partial edge group exit at once.
+inline uint32_t tile_grid_blocks(int tiles_x, int tiles_y) {
+  const uint32_t gx = (tiles_x + kTileGroup - 1) / kTileGroup;
+  const uint32_t gy = (tiles_y + kTileGroup - 1) / kTileGroup;
+  return (gx * gy + kXcds - 1) / kXcds * kXcds * kTileGroup * kTileGroup;
+}
+
+// The tile of block bid, or -1 for a block without one.  A bijection from
+// the blocks that have a tile onto the tiles.
+__device__ __forceinline__ int32_t tile_of_block(uint32_t bid, int tiles_x, int tiles_y) {
+  const uint32_t gx = (tiles_x + kTileGroup - 1) / kTileGroup;
+  const uint32_t gy = (tiles_y + kTileGroup - 1) / kTileGroup;
+  const uint32_t xcd = bid % kXcds, slot = bid / kXcds;
+  const uint32_t g = xcd + kXcds * (slot / (kTileGroup * kTileGroup));
+  const uint32_t w = slot % (kTileGroup * kTileGroup);
+  if (g >= gx * gy) return -1;
+  const uint32_t tx = (g % gx) * kTileGroup + w % kTileGroup;
+  const uint32_t ty = (g / gx) * kTileGroup + w / kTileGroup;
+  if (tx >= (uint32_t)tiles_x || ty >= (uint32_t)tiles_y) return -1;
+  return (int32_t)(ty * (uint32_t)tiles_x + tx);
 }
 
 // ---------------------------------------------------------------------------

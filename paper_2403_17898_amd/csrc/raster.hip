@@ -615,8 +615,8 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
   uint32_t *s_slot = lds.s_slot;
   float *s_w = lds.s_w;
-  const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
-  const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int32_t tile = tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
+  if (tile < 0) return;
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x;
   const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kPx * (t / kTile);
@@ -800,7 +800,7 @@ extern "C" {
 
 size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pair_capacity, int32_t width,
                                     int32_t height) {
-  if (gauss_capacity < 0 || pair_capacity < 0 || width <= 0 || height <= 0) return 0;
+  if (gauss_capacity < 0 || pair_capacity < 0 || !image_tiles_ok(width, height)) return 0;
   return raster_layout(nullptr, gauss_capacity, pair_capacity, width, height).bytes;
 }
 
@@ -813,14 +813,12 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
     return OCTGS_EINVAL;
   // candidate counts saturate at 2^30 - 1, which must exceed the capacity
   if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30) - 1) return OCTGS_EINVAL;
-  if (cam->width <= 0 || cam->height <= 0 || cam->width > 16 * 65535 || cam->height > 16 * 65535)
-    return OCTGS_EINVAL;
+  if (!image_tiles_ok(cam->width, cam->height)) return OCTGS_EINVAL;
   if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return OCTGS_EINVAL;
   if (ws_bytes < octgs_raster_workspace_bytes(g->capacity, pair_capacity, cam->width, cam->height))
     return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
   RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
-  const int ntiles = ws.tiles_x * ws.tiles_y;
   auto mark = [&](int i) {
     if (stage_events && stage_events[i]) hipEventRecord((hipEvent_t)stage_events[i], s);
   };
@@ -879,9 +877,11 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   ca.gauss_w = gauss_w;
   mark(8);
   if (gauss_w)
-    hipLaunchKernelGGL(k_composite<true>, dim3(ntiles), dim3(kFwdThreads), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<true>, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
+                       dim3(kFwdThreads), 0, s, ca);
   else
-    hipLaunchKernelGGL(k_composite<false>, dim3(ntiles), dim3(kFwdThreads), 0, s, ca);
+    hipLaunchKernelGGL(k_composite<false>, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
+                       dim3(kFwdThreads), 0, s, ca);
   mark(9);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }

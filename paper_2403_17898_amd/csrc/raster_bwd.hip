@@ -91,8 +91,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
   uint32_t *s_pair = lds.s_pair;
   float (*sG)[kBwdBatch] = lds.sG;
-  const int ntiles = a.ws.tiles_x * a.ws.tiles_y;
-  const uint32_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int32_t tile = tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
+  if (tile < 0) return;
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x, l = __lane_id();
   const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kBPx * (t / kTile);
@@ -474,7 +474,7 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
     return OCTGS_EINVAL;
   if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30)) return OCTGS_EINVAL;
-  if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
+  if (!image_tiles_ok(cam->width, cam->height) || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
     return OCTGS_EINVAL;
   if (ws_bytes < octgs_raster_workspace_bytes(g->capacity, pair_capacity, cam->width, cam->height))
     return OCTGS_ENOSPC;
@@ -492,7 +492,8 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   b.T_final = T_final;
   b.dimg = dL_drgb;
   b.last = last;
-  hipLaunchKernelGGL(k_composite_bwd, dim3(ntiles), dim3(kBwdThreads), 0, s, b);
+  hipLaunchKernelGGL(k_composite_bwd, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
+                     dim3(kBwdThreads), 0, s, b);
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 2048);
   hipLaunchKernelGGL(k_pair_reduce, dim3(rgrid), dim3(kBlock), 0, s, ws);
   PBwdArgs pa;

@@ -43,6 +43,10 @@ def test_host_only_entry_points():
     b = lib.octgs_raster_workspace_bytes(2000, 5000, 128, 128)
     assert 0 < a < b
     assert lib.octgs_raster_workspace_bytes(-1, 0, 1, 1) == 0
+    # at most 2^24 16x16 tiles per image
+    assert lib.octgs_raster_workspace_bytes(0, 0, 65536, 65536) > 0
+    assert lib.octgs_raster_workspace_bytes(0, 0, 65536, 65537) == 0
+    assert lib.octgs_raster_workspace_bytes(0, 0, 1 << 30, 1 << 30) == 0
     # argument validation fails before any device work
     assert lib.octgs_select_lod(None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
     assert lib.octgs_decode(None, None, None, None, None, 0, None, None, 0, None) == L.OCTGS_EINVAL
