@@ -133,6 +133,14 @@ typedef struct {
  * pair's emission index, carried through the tile sort); required for a
  * later backward of the same frame, off for rendering only. */
 #define OCTGS_RASTER_TRAIN 1u
+/* flags: before compositing, order each XCD's tiles by list length, longest
+ * first (one small extra kernel), so the last blocks to run are short ones;
+ * the backward of the same frame then uses the same order.  It shortens the
+ * compositing kernels when the frame runs alone on the GPU (a training step,
+ * a single view); with several frames in flight their kernels already fill
+ * each other's tails, and the extra kernel costs more than it saves.  The
+ * image is the same bit for bit either way. */
+#define OCTGS_RASTER_TILE_ORDER 2u
 
 #define OCTGS_RASTER_STAGES 5
 

@@ -18,6 +18,7 @@ OCTGS_OK, OCTGS_EINVAL, OCTGS_ENOSPC, OCTGS_EHIP, OCTGS_EUNSUPPORTED = 0, -1, -2
 OCTGS_FP32, OCTGS_BF16 = 0, 1
 OCTGS_RASTER_STAGES = 5
 OCTGS_RASTER_TRAIN = 1
+OCTGS_RASTER_TILE_ORDER = 2
 RASTER_STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
 
 _p = ctypes.c_void_p

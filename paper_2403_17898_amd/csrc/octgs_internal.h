@@ -160,7 +160,9 @@ __device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
 // are grouped in squares of kTileGroup x kTileGroup and group g goes to XCD
 // g % 8: every XCD gets groups from all over the image, which balances the
 // dense and sparse regions of a view across the XCDs, while the tiles of one
-// group, which share most of their Gaussians, stay in one L2.
+// group, which share most of their Gaussians, stay in one L2.  On request
+// (OCTGS_RASTER_TILE_ORDER) the rasterizer then orders each XCD's tiles by
+// list length, longest first (k_tile_order), so its last blocks are short.
 constexpr uint32_t kXcds = 8;
 constexpr uint32_t kTileGroup = 4;
 // Largest number of 16x16 tiles per image (about 4.3 gigapixels): tile ids,
@@ -173,7 +175,7 @@ inline bool image_tiles_ok(int32_t width, int32_t height) {
 
 // Blocks to launch: 8 x kTileGroup^2 x ceil(groups / 8); the blocks past the
 // last group and those on tiles outside a partial edge group exit at once.
-inline uint32_t tile_grid_blocks(int tiles_x, int tiles_y) {
+__host__ __device__ inline uint32_t tile_grid_blocks(int tiles_x, int tiles_y) {
   const uint32_t gx = (tiles_x + kTileGroup - 1) / kTileGroup;
   const uint32_t gy = (tiles_y + kTileGroup - 1) / kTileGroup;
   return (gx * gy + kXcds - 1) / kXcds * kXcds * kTileGroup * kTileGroup;
@@ -203,7 +205,8 @@ struct RasterHeader {
   uint32_t n_candidates;  // rectangle tiles of the survivors (saturated at 2^32 - 1)
   uint32_t n_cand_listed; // candidates written (n_candidates, or 0 on overflow)
   uint32_t n_listed;      // pairs in the sorted list (n_pairs, or 0 on overflow)
-  uint32_t reserved[24];
+  uint32_t tile_ordered;  // 1 if the forward wrote tile_order (OCTGS_RASTER_TILE_ORDER)
+  uint32_t reserved[23];
 };
 
 struct RasterWs {
@@ -227,6 +230,8 @@ struct RasterWs {
   uint32_t *pair_slot;    // [pcap] slot of each pair in emission order (a Gaussian's pairs
                           // are contiguous there)
   uint32_t *ranges;       // [tiles][2]
+  uint32_t *tile_order;   // [tile_grid_blocks] tile of each compositing block (~0u: none),
+                          // written only with OCTGS_RASTER_TILE_ORDER
   uint32_t *hist;         // [kHistCopies][8][256] radix histograms (4 depth passes, then 1..4
                           // tile passes); block b adds into copy b % kHistCopies
   uint32_t *lookback;     // [4][ceil(gcap / kSortPart)][256] depth-sort look-back

@@ -573,9 +573,102 @@ __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
   }
 }
 
+constexpr int kOrderBuckets = 64;  // = kWave: one scan lane per bucket
+
+// Half-octave bucket of a tile's list length, longest lists first; empty
+// tiles and blocks without a tile go last (kOrderBuckets - 1).
+__device__ __forceinline__ uint32_t order_bucket(int32_t tile, const uint32_t *ranges) {
+  if (tile < 0) return kOrderBuckets - 1;
+  const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+  if (len == 0) return kOrderBuckets - 1;
+  const uint32_t lg = 31u - (uint32_t)__clz(len);
+  const uint32_t half = lg > 0 ? (len >> (lg - 1)) & 1u : 0u;
+  return (uint32_t)(kOrderBuckets - 2) - min(2u * lg + half, (uint32_t)(kOrderBuckets - 2));
+}
+
+// Block x takes the slots that the group mapping gives XCD x and writes
+// their tiles to tile_order[x + 8 * position] in a stable order by bucket
+// (longest lists first):
+// a counting pass, then chunks of 1024 slots ranked per wave with ballots
+// (match-any on the bucket bits), each wave owning a contiguous run.  Every
+// position of the XCD is written once, so tile_order is a permutation of the
+// group mapping.
+__global__ __launch_bounds__(kBlock) void k_tile_order(RasterWs ws) {
+  constexpr int kItems = 4;
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ uint32_t cnt[kOrderBuckets];
+  __shared__ uint32_t wcnt[kWaves][kOrderBuckets];
+  __shared__ uint32_t run[kOrderBuckets];
+  const uint32_t xcd = blockIdx.x;
+  const uint32_t nslots = tile_grid_blocks(ws.tiles_x, ws.tiles_y) / kXcds;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id();
+  const uint64_t lt = lanemask_lt();
+  if (xcd == 0 && t == 0) ws.hdr->tile_ordered = 1u;
+  if (t < kOrderBuckets) cnt[t] = 0u;
+  __syncthreads();
+  for (uint32_t q = t; q < nslots; q += kBlock)
+    atomicAdd(&cnt[order_bucket(tile_of_block(xcd + kXcds * q, ws.tiles_x, ws.tiles_y),
+                                ws.ranges)], 1u);
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t v = cnt[l];
+    run[l] = wave_incl_scan(v) - v;
+  }
+  for (uint32_t c0 = 0; c0 < nslots; c0 += kBlock * kItems) {
+    (&wcnt[0][0])[t] = 0u;  // kWaves * kOrderBuckets == kBlock
+    int32_t tl[kItems];
+    uint32_t key[kItems], rank[kItems];
+    bool ok[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t q = c0 + (uint32_t)(w * kWave * kItems + j * kWave + l);
+      ok[j] = q < nslots;
+      tl[j] = ok[j] ? tile_of_block(xcd + kXcds * q, ws.tiles_x, ws.tiles_y) : -1;
+      key[j] = order_bucket(tl[j], ws.ranges);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      uint64_t peers = ballot(ok[j]);
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const int bit = (key[j] >> b) & 1;
+        const uint64_t bal = ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      uint32_t before = 0;
+      if (ok[j]) before = wcnt[w][key[j]];
+      // all lanes of the wave have read before any leader writes
+      __builtin_amdgcn_wave_barrier();
+      if (ok[j]) {
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        if ((peers & lt) == 0) wcnt[w][key[j]] = before + (uint32_t)__popcll(peers);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (t < kOrderBuckets) {
+      uint32_t base = run[t];
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) {
+        const uint32_t c = wcnt[v][t];
+        wcnt[v][t] = base;
+        base += c;
+      }
+      run[t] = base;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+      if (ok[j]) ws.tile_order[xcd + kXcds * (wcnt[w][key[j]] + rank[j])] = (uint32_t)tl[j];
+    __syncthreads();
+  }
+}
+
 struct CompArgs {
   RasterWs ws;
   int buf, W, H;
+  int ordered;  // blocks take their tile from ws.tile_order
   float alpha_max, alpha_min, t_min, bg[3];
   float *rgb, *T_final;
   uint32_t *last;
@@ -615,7 +708,8 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
   uint32_t *s_slot = lds.s_slot;
   float *s_w = lds.s_w;
-  const int32_t tile = tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
+  const int32_t tile = a.ordered ? (int32_t)a.ws.tile_order[blockIdx.x]
+                                 : tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
   if (tile < 0) return;
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x;
@@ -774,6 +868,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   for (int i = 0; i < 2; ++i) ws.tpair[i] = (uint32_t *)take((size_t)pc * 4);
   ws.pair_slot = (uint32_t *)take((size_t)pc * 4);
   ws.ranges = (uint32_t *)take((size_t)ws.tiles_x * ws.tiles_y * 8);
+  ws.tile_order = (uint32_t *)take((size_t)tile_grid_blocks(ws.tiles_x, ws.tiles_y) * 4);
   ws.hist = (uint32_t *)take(kHistCopies * kHistStride * 4);
   ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
   ws.lb_words = (size_t)4 * ((g + kSortPart - 1) / kSortPart) * 256;
@@ -861,10 +956,13 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   const int buf = passes % 2;
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 8192);
   hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kBlock), 0, s, ws, buf);
+  const bool ordered = (p->flags & OCTGS_RASTER_TILE_ORDER) != 0;
+  if (ordered) hipLaunchKernelGGL(k_tile_order, dim3(kXcds), dim3(kBlock), 0, s, ws);
   mark(7);
   CompArgs ca;
   ca.ws = ws;
   ca.buf = buf;
+  ca.ordered = ordered ? 1 : 0;
   ca.W = cam->width;
   ca.H = cam->height;
   ca.alpha_max = p->alpha_max;

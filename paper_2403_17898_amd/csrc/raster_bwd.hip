@@ -91,8 +91,12 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
   uint32_t *s_pair = lds.s_pair;
   float (*sG)[kBwdBatch] = lds.sG;
-  const int32_t tile = tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
-  if (tile < 0) return;
+  // the tile order the forward used: its per-view order (a permutation of
+  // the group mapping) if it wrote one, else the group mapping
+  const int32_t tile = a.ws.hdr->tile_ordered
+                           ? (int32_t)a.ws.tile_order[blockIdx.x]
+                           : tile_of_block(blockIdx.x, a.ws.tiles_x, a.ws.tiles_y);
+  if (tile < 0 || tile >= a.ws.tiles_x * a.ws.tiles_y) return;
   const int tx = tile % a.ws.tiles_x, ty = tile / a.ws.tiles_x;
   const int t = threadIdx.x, l = __lane_id();
   const int px = tx * kTile + (t % kTile), py0 = ty * kTile + kBPx * (t / kTile);

@@ -65,15 +65,21 @@ def make_camera(cam, lod_blend: bool = False) -> L.Camera:
 
 
 def raster_params(alpha_max=0.99, alpha_min=0.0, t_min=1e-4, dilation=0.3, jac_clamp=1.3,
-                  bg=(0.0, 0.0, 0.0), train: bool = False) -> L.RasterParams:
+                  bg=(0.0, 0.0, 0.0), train: bool = False,
+                  tile_order=None) -> L.RasterParams:
     """Rasterizer constants; train=True makes the forward keep what the
-    backward pass needs (required before rasterize_bwd)."""
+    backward pass needs (required before rasterize_bwd).  tile_order orders
+    each XCD's tiles longest-first before compositing (faster for a frame
+    that runs alone on the GPU, slower with several frames in flight); it
+    defaults to train."""
     p = L.RasterParams()
     p.alpha_max, p.alpha_min, p.t_min = alpha_max, alpha_min, t_min
     p.dilation, p.jac_clamp = dilation, jac_clamp
     for i in range(3):
         p.bg[i] = bg[i]
-    p.flags = L.OCTGS_RASTER_TRAIN if train else 0
+    if tile_order is None:
+        tile_order = train
+    p.flags = (L.OCTGS_RASTER_TRAIN if train else 0) | (L.OCTGS_RASTER_TILE_ORDER if tile_order else 0)
     return p
 
 
