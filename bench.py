@@ -88,6 +88,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _finite(v):
+    """The result with non-finite floats (e.g. the PSNR of an exact image)
+    as null, so the line is strict JSON."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
+
+
 def time_views(args, torch, streams, views, bufs, render_one, depth):
     """(event ms, wall s) for args.steps views after args.warmup untimed
     ones; view i runs on stream i % depth with buffers bufs[i % depth]."""
@@ -366,7 +378,7 @@ def main():
     }
     if city is not None:
         out["city"] = city
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
 
 
 # per decoded explicit Gaussian: mean, log-scale, rotation and opacity
