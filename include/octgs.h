@@ -151,7 +151,9 @@ typedef struct {
   uint32_t n_pairs;       /* (tile, Gaussian) pairs listed: tiles the 3-sigma ellipse meets
                              (0 on overflow) */
   uint32_t pair_overflow; /* 1 if n_candidates exceeded the pair capacity (image incomplete) */
-  uint32_t sync_error;    /* 1 if a radix-sort look-back wait hit its bound (output invalid) */
+  uint32_t sync_error;    /* 1 if a look-back wait (scans, sorts) hit its bound (output
+                             invalid); partitions are taken in the order blocks start, so
+                             every wait is on a running block and this is not expected */
   uint32_t n_candidates;  /* tiles of the survivors' 3-sigma rectangles, tested against the
                              ellipse; the pair capacity must hold this many (saturates) */
   uint32_t reserved[10];

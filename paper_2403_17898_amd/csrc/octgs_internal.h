@@ -200,13 +200,19 @@ __device__ __forceinline__ int32_t tile_of_block(uint32_t bid, int tiles_x, int 
 // rasterizer workspace
 // ---------------------------------------------------------------------------
 
+constexpr int kTicketScan = 0, kTicketEmit = 1, kTicketDepth = 2, kTicketTile = 6;
+constexpr int kTicketSlots = 10;
+
 struct RasterHeader {
   uint32_t n_slots, n_visible, n_pairs, pair_overflow, sync_error;
   uint32_t n_candidates;  // rectangle tiles of the survivors (saturated at 2^32 - 1)
   uint32_t n_cand_listed; // candidates written (n_candidates, or 0 on overflow)
   uint32_t n_listed;      // pairs in the sorted list (n_pairs, or 0 on overflow)
   uint32_t tile_ordered;  // 1 if the forward wrote tile_order (OCTGS_RASTER_TILE_ORDER)
-  uint32_t reserved[23];
+  // partition tickets of the kernels chained by look-back: candidate scan,
+  // emission, then the depth sort's 4 passes and the tile sort's passes
+  uint32_t ticket[kTicketSlots];
+  uint32_t reserved[23 - kTicketSlots];
 };
 
 struct RasterWs {
@@ -276,6 +282,8 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
 // key, stably.  On return the sorted data is in buffers index `passes % 2`.
+// tickets: one zeroed word per pass, from which the pass's blocks take their
+// partition index in the order they start.
 // hist: the digit histograms of the passes, [passes][256] words, as the sum
 // of hist_copies (1..kHistCopies) copies hist_stride words apart (built by
 // the producer of the keys; the first pass folds the later passes' copies
@@ -284,7 +292,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
                       const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
-                      uint32_t *err_flag, hipStream_t stream);
+                      uint32_t *tickets, uint32_t *err_flag, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // chained scan: decoupled look-back over one value per partition

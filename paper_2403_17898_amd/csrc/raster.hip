@@ -338,9 +338,12 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
   const uint32_t n = ws.hdr->n_visible;
   const uint32_t nch = (n + kChunk - 1) / kChunk;
   if (blockIdx.x >= nch) return;  // n == 0: the cleared header already says 0
-  // chunk id = block id: blocks are dispatched in index order, so every
-  // chunk a block waits on belongs to a block that is already running
-  const uint32_t c = blockIdx.x;
+  // chunk id = ticket, taken in the order blocks start, so every chunk a
+  // block waits on belongs to a block that is already running
+  __shared__ uint32_t s_c;
+  if (t == 0) s_c = atomicAdd(&ws.hdr->ticket[kTicketScan], 1u);
+  __syncthreads();
+  const uint32_t c = s_c;
   const int64_t base = (int64_t)c * kChunk;
   uint32_t cnt[kChunkPerThread], slot[kChunkPerThread];
   uint64_t mine = 0;
@@ -405,8 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
 // Block r (1024 threads) takes the run of 8192 consecutive candidate
 // positions from 8192 r; runs this long keep the look-back chain short, as
 // each step of it is a device-scope round trip
-// (blocks are dispatched in index order, so the runs a block waits on
-// belong to blocks already running); it locates the survivors covering the positions (run_first, then a
+// (r is a ticket taken in the order blocks start, so the runs a block waits
+// on belong to blocks already running); it locates the survivors covering the positions (run_first, then a
 // binary search of their offsets in LDS), tests each candidate tile, ranks
 // the kept ones by ballots, gets the run's output offset by decoupled
 // look-back over the preceding runs and writes (tile id, slot) in order.
@@ -427,8 +430,11 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   const uint32_t n = ws.hdr->n_visible;
   const uint32_t R = (P + kEmitRun - 1) / kEmitRun;
   if (blockIdx.x >= R) return;
+  __shared__ uint32_t s_r;
+  if (t == 0) s_r = atomicAdd(&ws.hdr->ticket[kTicketEmit], 1u);
   (&h[0][0])[t] = 0u;  // 1024 threads, 4 x 256 bins
-  const uint32_t r = blockIdx.x;
+  __syncthreads();
+  const uint32_t r = s_r;
   const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
   const uint32_t lo = ws.run_first[r];
   const uint32_t cnt = min((uint32_t)kEmitRun + 1, n - lo);
@@ -939,7 +945,8 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(2);
   // histograms and cleared look-back words come from the kernels above
   hipError_t e = radix_sort(ws.dkey, ws.dval, nullptr, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
-                            kHistCopies, kHistStride, ws.lookback, &ws.hdr->sync_error, s);
+                            kHistCopies, kHistStride, ws.lookback,
+                            &ws.hdr->ticket[kTicketDepth], &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   mark(3);
   mark(4);
@@ -951,7 +958,8 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   const int passes = ws.tile_passes;
   e = radix_sort(ws.tkey, ws.tval, (p->flags & OCTGS_RASTER_TRAIN) ? ws.tpair : nullptr,
                  &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256, kHistCopies,
-                 kHistStride, ws.lookback_t, &ws.hdr->sync_error, s);
+                 kHistStride, ws.lookback_t, &ws.hdr->ticket[kTicketTile],
+                 &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
   const int buf = passes % 2;
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 8192);

@@ -2,10 +2,14 @@
 // Onesweep structure (Adinets and Merrill, "Onesweep: A Faster Least
 // Significant Digit Radix Sort for GPUs", 2022): the kernels that produce the
 // keys build the digit histograms of all passes, then each pass is a single kernel whose
-// block p ranks the keys of partition p locally and resolves the global
+// blocks each rank the keys of one partition locally and resolve the global
 // digit offsets with a decoupled look-back over the preceding partitions.
-// Blocks are dispatched in index order, so a partition only ever waits on
-// partitions of blocks that are already running.
+// A block takes its partition index from an atomic ticket when it starts, so
+// every partition it waits on belongs to a block that is already running.
+// (Block index as partition index is not enough: blocks are dealt to the 8
+// XCDs round-robin and each XCD dispatches its share on its own, so with
+// other kernels resident a block can start before its predecessor, and two
+// look-back kernels can then wait on each other.)
 //
 // CDNA4 specifics: local ranking is done per 64-lane wavefront with eight
 // ballots per item (a match-any on the digit bits); each wave owns a
@@ -40,14 +44,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     uint32_t *__restrict__ vout2, const uint32_t *__restrict__ count, int shift,
     uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride, int fold_passes,
-    uint32_t *__restrict__ lookback, uint32_t *__restrict__ err_flag) {
+    uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
+    uint32_t *__restrict__ err_flag) {
   __shared__ PassSmem<NV> sm;
+  __shared__ uint32_t s_part;
   const uint32_t n = *count;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint64_t lt = lanemask_lt();
 
+  // exactly the first nparts blocks stay, and they take tickets 0..nparts-1
   if (blockIdx.x >= nparts) return;
+  if (t == 0) s_part = atomicAdd(ticket, 1u);  // its latency overlaps the histogram scan
 
   // exclusive scan of the pass histogram (the sum of its copies) over digits
   {
@@ -64,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
   {
     for (int i = t; i < 4 * 256; i += kBlock) (&sm.wcnt[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t part = blockIdx.x;
+    const uint32_t part = s_part;
     const uint32_t base = part * kSortPart;
 
     // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
                       const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
-                      uint32_t *err_flag, hipStream_t stream) {
+                      uint32_t *tickets, uint32_t *err_flag, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   if (hist_copies < 1 || hist_copies > kHistCopies) return hipErrorInvalidValue;
   const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
@@ -220,12 +228,12 @@ hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *val
       hipLaunchKernelGGL(k_sort_pass<2>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p,
                          hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
-                         err_flag);
+                         tickets + p, err_flag);
     else
       hipLaunchKernelGGL(k_sort_pass<1>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
                          vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p,
                          hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
-                         err_flag);
+                         tickets + p, err_flag);
   }
   return hipGetLastError();
 }
