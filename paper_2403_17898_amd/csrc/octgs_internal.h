@@ -241,7 +241,7 @@ struct RasterWs {
   uint32_t *hist;         // [kHistCopies][8][256] radix histograms (4 depth passes, then 1..4
                           // tile passes); block b adds into copy b % kHistCopies
   uint32_t *lookback;     // [4][ceil(gcap / kSortPart)][256] depth-sort look-back
-  uint32_t *lookback_t;   // [tile passes][ceil(pcap / kSortPart)][256] tile-sort look-back
+  uint32_t *lookback_t;   // [tile passes][ceil(pcap / kTileSortPart)][256] tile-sort look-back
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
   float *gpair;           // [pcap][9] backward: the same per (tile, Gaussian) pair, emission order
   int64_t gcap, pcap;
@@ -277,7 +277,11 @@ struct CamParams {
 // ---------------------------------------------------------------------------
 
 constexpr int kSortItems = 8;
-constexpr int kSortPart = kBlock * kSortItems;  // 2048 keys per partition
+constexpr int kSortPart = kBlock * kSortItems;  // 2048 keys per partition (depth sort)
+// The tile sort has ~10x more keys: 4096-key partitions halve its blocks,
+// and with them the same-address ticket atomics and the look-back chain.
+constexpr int kTileSortItems = 16;
+constexpr int kTileSortPart = kBlock * kTileSortItems;
 constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
@@ -287,10 +291,12 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 // hist: the digit histograms of the passes, [passes][256] words, as the sum
 // of hist_copies (1..kHistCopies) copies hist_stride words apart (built by
 // the producer of the keys; the first pass folds the later passes' copies
-// into copy 0); lookback: passes * ceil(cap / kSortPart) * 256 words,
+// into copy 0); items: keys per thread of a partition (kSortItems or
+// kTileSortItems; a partition is 256 * items keys); lookback:
+// passes * ceil(cap / (256 * items)) * 256 words,
 // cleared by the producer for the partitions in use.
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
+                      const uint32_t *count, int64_t cap, int items, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
                       uint32_t *tickets, uint32_t *err_flag, hipStream_t stream);
 

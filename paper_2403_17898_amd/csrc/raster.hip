@@ -167,12 +167,12 @@ __device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa,
 }
 
 // Zeroes the radix-sort look-back words (256 per partition) of partitions
-// j with kSortPart j in [a, b), j < nparts, in each of `passes` regions of
+// j with part j in [a, b) (part = keys per partition), j < nparts, in each of `passes` regions of
 // `stride` words; all threads of the block take part.
 __device__ __forceinline__ void clear_partitions(uint32_t *lb, size_t stride, uint32_t a, uint32_t b,
-                                                 int passes, size_t nparts) {
-  const uint32_t j0 = (a + kSortPart - 1) / kSortPart;
-  const uint32_t j1 = (uint32_t)std::min<uint64_t>(((uint64_t)b + kSortPart - 1) / kSortPart, nparts);
+                                                 int passes, size_t nparts, uint32_t part) {
+  const uint32_t j0 = (a + part - 1) / part;
+  const uint32_t j1 = (uint32_t)std::min<uint64_t>(((uint64_t)b + part - 1) / part, nparts);
   for (int p = 0; p < passes; ++p)
     for (uint32_t j = j0; j < j1; ++j) lb[p * stride + (size_t)j * 256 + threadIdx.x] = 0u;
 }
@@ -314,7 +314,8 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
   if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) ws.hdr->n_visible = prefix + mine;
   // clear the depth sort's look-back words of the partitions that start in
   // this block's output range [prefix, prefix + mine), for all four passes
-  clear_partitions(ws.lookback, ws.lb_words / 4, prefix, prefix + mine, 4, ws.lb_words / 4 / 256);
+  clear_partitions(ws.lookback, ws.lb_words / 4, prefix, prefix + mine, 4, ws.lb_words / 4 / 256,
+                   kSortPart);
   __syncthreads();
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
@@ -376,7 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
   // chunk (kept pairs are a prefix-closed subset of the positions)
   if (excl < kLbVal)
     clear_partitions(ws.lookback_t, ws.lbt_words / max(ws.tile_passes, 1), excl,
-                     sat_add(excl, agg), ws.tile_passes, ws.lbt_words / max(ws.tile_passes, 1) / 256);
+                     sat_add(excl, agg), ws.tile_passes, ws.lbt_words / max(ws.tile_passes, 1) / 256,
+                     kTileSortPart);
   // consecutive 256-entry rows of the chunk, scanned in order (32-bit sums
   // are exact when the chunk total is below 2^30)
   uint32_t carry = 0;
@@ -878,7 +880,7 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.hist = (uint32_t *)take(kHistCopies * kHistStride * 4);
   ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
   ws.lb_words = (size_t)4 * ((g + kSortPart - 1) / kSortPart) * 256;
-  ws.lbt_words = (size_t)ws.tile_passes * ((pc + kSortPart - 1) / kSortPart) * 256;
+  ws.lbt_words = (size_t)ws.tile_passes * ((pc + kTileSortPart - 1) / kTileSortPart) * 256;
   ws.lookback = (uint32_t *)take(ws.lb_words * 4);
   ws.lookback_t = (uint32_t *)take(ws.lbt_words * 4);
   ws.dproj = (float *)take((size_t)g * 9 * 4);
@@ -944,7 +946,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(1);
   mark(2);
   // histograms and cleared look-back words come from the kernels above
-  hipError_t e = radix_sort(ws.dkey, ws.dval, nullptr, &ws.hdr->n_visible, ws.gcap, 4, ws.hist,
+  hipError_t e = radix_sort(ws.dkey, ws.dval, nullptr, &ws.hdr->n_visible, ws.gcap, kSortItems, 4, ws.hist,
                             kHistCopies, kHistStride, ws.lookback,
                             &ws.hdr->ticket[kTicketDepth], &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;
@@ -957,7 +959,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(6);
   const int passes = ws.tile_passes;
   e = radix_sort(ws.tkey, ws.tval, (p->flags & OCTGS_RASTER_TRAIN) ? ws.tpair : nullptr,
-                 &ws.hdr->n_listed, ws.pcap, passes, ws.hist + 4 * 256, kHistCopies,
+                 &ws.hdr->n_listed, ws.pcap, kTileSortItems, passes, ws.hist + 4 * 256, kHistCopies,
                  kHistStride, ws.lookback_t, &ws.hdr->ticket[kTicketTile],
                  &ws.hdr->sync_error, s);
   if (e != hipSuccess) return OCTGS_EHIP;

@@ -26,19 +26,20 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr int kLookWin = 16;
 
-template <int NV>
+template <int NV, int PART>
 struct PassSmem {
   uint32_t wcnt[4][256];     // per-wave digit counters, then per-wave exclusive offsets
   uint32_t dstart[256];      // local start of each digit in the partition
   uint32_t gbase[256];       // global write base of each digit for this partition
   uint32_t hexcl[256];       // global exclusive prefix of the pass histogram
-  uint32_t keys[kSortPart];
-  uint32_t vals[NV][kSortPart];
+  uint32_t keys[PART];
+  uint32_t vals[NV][PART];
   uint32_t tmp[8];
 };
 
-// NV = 1 or 2 value arrays travel with the keys.
-template <int NV>
+// NV = 1 or 2 value arrays travel with the keys; ITEMS keys per thread, so a
+// partition is PART = 256 * ITEMS keys.
+template <int NV, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -46,10 +47,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride, int fold_passes,
     uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
     uint32_t *__restrict__ err_flag) {
-  __shared__ PassSmem<NV> sm;
+  constexpr int PART = kBlock * ITEMS;
+  __shared__ PassSmem<NV, PART> sm;
   __shared__ uint32_t s_part;
   const uint32_t n = *count;
-  const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+  const uint32_t nparts = (n + PART - 1) / PART;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint64_t lt = lanemask_lt();
 
@@ -73,27 +75,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     for (int i = t; i < 4 * 256; i += kBlock) (&sm.wcnt[0][0])[i] = 0u;
     __syncthreads();
     const uint32_t part = s_part;
-    const uint32_t base = part * kSortPart;
+    const uint32_t base = part * PART;
 
     // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
-    uint32_t key[kSortItems], val[kSortItems], val2[kSortItems], rank[kSortItems];
-    int dig[kSortItems];
+    uint32_t key[ITEMS], val[ITEMS], val2[ITEMS], rank[ITEMS];
+    int dig[ITEMS];
     // unconditional loads at a clamped index keep all of them in flight
     // together; items past the end are masked by dig = -1
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t idx = base + w * (kWave * ITEMS) + j * kWave + l;
       key[j] = kin[min(idx, n - 1)];
       val[j] = vin[min(idx, n - 1)];
       if (NV == 2) val2[j] = vin2[min(idx, n - 1)];
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-      const uint32_t idx = base + w * (kWave * kSortItems) + j * kWave + l;
+    for (int j = 0; j < ITEMS; ++j) {
+      const uint32_t idx = base + w * (kWave * ITEMS) + j * kWave + l;
       dig[j] = idx < n ? (int)((key[j] >> shift) & 255u) : -1;
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
       const int d = dig[j];
       uint64_t peers = ballot(d >= 0);
 #pragma unroll
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 
     // place keys in LDS in local sorted order
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
       if (dig[j] >= 0) {
         uint32_t pos = sm.wcnt[w][dig[j]] + rank[j];
         sm.keys[pos] = key[j];
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
       }
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kSortPart, n - base);
+    const uint32_t cnt = min((uint32_t)PART, n - base);
     for (uint32_t i = t; i < cnt; i += kBlock) {
       uint32_t k = sm.keys[i];
       uint32_t d = (k >> shift) & 255u;
@@ -209,31 +211,47 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
   }
 }
 
+// Pass p of a sort: from buffers p % 2 to the others.
+template <int ITEMS>
+void launch_pass(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
+                 const uint32_t *count, int p, int grid, uint32_t *hist, int copies,
+                 uint32_t hist_stride, int fold, uint32_t *lookback, uint32_t *ticket,
+                 uint32_t *err_flag, hipStream_t stream) {
+  const int src = p & 1, dst = src ^ 1;
+  if (vals2)
+    hipLaunchKernelGGL((k_sort_pass<2, ITEMS>), dim3(grid), dim3(kBlock), 0, stream, keys[src],
+                       vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p, hist,
+                       copies, hist_stride, fold, lookback, ticket, err_flag);
+  else
+    hipLaunchKernelGGL((k_sort_pass<1, ITEMS>), dim3(grid), dim3(kBlock), 0, stream, keys[src],
+                       vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p, hist,
+                       copies, hist_stride, fold, lookback, ticket, err_flag);
+}
+
 }  // namespace
 
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
-                      const uint32_t *count, int64_t cap, int passes, uint32_t *hist,
+                      const uint32_t *count, int64_t cap, int items, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,
                       uint32_t *tickets, uint32_t *err_flag, hipStream_t stream) {
   if (passes <= 0) return hipSuccess;
   if (hist_copies < 1 || hist_copies > kHistCopies) return hipErrorInvalidValue;
-  const int64_t nparts_cap = (cap + kSortPart - 1) / kSortPart;
+  if (items != kSortItems && items != kTileSortItems) return hipErrorInvalidValue;
+  const int64_t part = (int64_t)kBlock * items;
+  const int64_t nparts_cap = (cap + part - 1) / part;
   const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
   // one block per possible partition; blocks past the actual count exit
   const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
   for (int p = 0; p < passes; ++p) {
-    const int src = p & 1, dst = src ^ 1;
     const int copies = p == 0 ? hist_copies : 1, fold = p == 0 ? passes - 1 : 0;
-    if (vals2)
-      hipLaunchKernelGGL(k_sort_pass<2>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
-                         vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p,
-                         hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
-                         tickets + p, err_flag);
+    if (items == kTileSortItems)
+      launch_pass<kTileSortItems>(keys, vals, vals2, count, p, pass_grid, hist + 256 * p, copies,
+                                  hist_stride, fold, lookback + lb_stride * p, tickets + p,
+                                  err_flag, stream);
     else
-      hipLaunchKernelGGL(k_sort_pass<1>, dim3(pass_grid), dim3(kBlock), 0, stream, keys[src],
-                         vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p,
-                         hist + 256 * p, copies, hist_stride, fold, lookback + lb_stride * p,
-                         tickets + p, err_flag);
+      launch_pass<kSortItems>(keys, vals, vals2, count, p, pass_grid, hist + 256 * p, copies,
+                              hist_stride, fold, lookback + lb_stride * p, tickets + p, err_flag,
+                              stream);
   }
   return hipGetLastError();
 }
