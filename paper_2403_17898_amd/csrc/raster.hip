@@ -923,7 +923,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   hipStream_t s = (hipStream_t)stream;
   RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
   auto mark = [&](int i) {
-    if (stage_events && stage_events[i]) hipEventRecord((hipEvent_t)stage_events[i], s);
+    if (stage_events && stage_events[i]) (void)hipEventRecord((hipEvent_t)stage_events[i], s);  // timing only
   };
   ProjArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];

@@ -404,7 +404,7 @@ int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float
   g.A = L.H2; g.lda = kH; g.transA = 1; g.reluA = 1; g.B = L.dX3; g.ldb = 1; g.C = gr->w3; g.ldc = 1;
   g.M = kH; g.N = 1; g.K = B; g.accumulate = 1; g.splitk = splitk;
   if ((e = gemm(g, kH, s)) != hipSuccess) return OCTGS_EHIP;
-  colsum(L.dX3, 1, 1, nullptr, B, gr->b3, s);
+  if ((e = colsum(L.dX3, 1, 1, nullptr, B, gr->b3, s)) != hipSuccess) return OCTGS_EHIP;
   g = gemm_base();
   g.A = L.dX3; g.lda = 1; g.B = net->w3; g.ldb = 1; g.transB = 1; g.C = L.dH2; g.ldc = kH;
   g.M = B; g.N = kH; g.K = 1; g.mask = L.H2; g.ldm = kH;
@@ -414,7 +414,7 @@ int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float
   g.A = L.H1; g.lda = kH; g.transA = 1; g.reluA = 1; g.B = L.dH2; g.ldb = kH; g.C = gr->w2; g.ldc = kH;
   g.M = kH; g.N = kH; g.K = B; g.accumulate = 1; g.splitk = splitk;
   if ((e = gemm(g, kH, s)) != hipSuccess) return OCTGS_EHIP;
-  colsum(L.dH2, kH, kH, nullptr, B, gr->b2, s);
+  if ((e = colsum(L.dH2, kH, kH, nullptr, B, gr->b2, s)) != hipSuccess) return OCTGS_EHIP;
   g = gemm_base();
   g.A = L.dH2; g.lda = kH; g.B = net->w2; g.ldb = kH; g.transB = 1; g.C = L.dH1; g.ldc = kH;
   g.M = B; g.N = kH; g.K = kH; g.mask = L.H1; g.ldm = kH;
@@ -424,7 +424,7 @@ int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float
   g.A = z; g.lda = kZ; g.transA = 1; g.B = L.dH1; g.ldb = kH; g.C = gr->w1; g.ldc = kH;
   g.M = kZ; g.N = kH; g.K = B; g.accumulate = 1; g.splitk = splitk;
   if ((e = gemm(g, kZ, s)) != hipSuccess) return OCTGS_EHIP;
-  colsum(L.dH1, kH, kH, nullptr, B, gr->b1, s);
+  if ((e = colsum(L.dH1, kH, kH, nullptr, B, gr->b1, s)) != hipSuccess) return OCTGS_EHIP;
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 
