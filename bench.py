@@ -248,6 +248,7 @@ def main():
     tot = {k: 0.0 for k in names}
     nviews = min(args.steps, len(ccams))
     sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0, blends=0)
+    view_ms = []
     ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
     sh = P.stream_handle(stream)
     for i in range(nviews):
@@ -260,10 +261,13 @@ def main():
         ev[3].record(sh)
         vb.rasterize(c, prm, stage_events=ev[4:])
         torch.cuda.synchronize()
+        vms = ev[0].elapsed_ms(ev[1]) + ev[2].elapsed_ms(ev[3])
         tot["select"] += ev[0].elapsed_ms(ev[1])
         tot["decode"] += ev[2].elapsed_ms(ev[3])
         for s_i, nm in enumerate(L.RASTER_STAGE_NAMES):
             tot[nm] += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
+            vms += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
+        view_ms.append(vms)
         s = vb.stats()
         sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
         sums["selected"] += s["n_selected"]
@@ -277,6 +281,24 @@ def main():
     log(f"mean per view: selected {mean['selected']:.0f}, Gaussians {mean['slots']:.0f}, "
         f"visible {mean['visible']:.0f}, pairs {mean['pairs']:.0f} "
         f"(of {mean['candidates']:.0f} rectangle candidates)")
+    # each view alone on the GPU (the loop above) against the camera altitude
+    vm = np.array(view_ms)
+    alts = np.array([float(cams[i].C[2]) for i in range(nviews)])
+    edges = np.linspace(0, nviews, 11).round().astype(int)
+    per_view = {"ms_mean": round(float(vm.mean()), 4), "ms_max": round(float(vm.max()), 4),
+                "slowest_view": int(vm.argmax()),
+                "slowest_altitude_m": round(float(alts[vm.argmax()]), 1),
+                "min_fps": round(1e3 / float(vm.max()), 1),
+                "altitude_m_vs_ms": [[round(float(alts[a:b].mean()), 1), round(float(vm[a:b].mean()), 4)]
+                                     for a, b in zip(edges[:-1], edges[1:]) if b > a]}
+    log(f"each view alone: {per_view}")
+    # decode on MFMA: first layers 36 -> 3 x W, second layers W -> 11 k (k
+    # opacities, 3k colours, 7k covariance terms), 2 FLOP per multiply-add
+    dec_flop = 2.0 * (36 * 3 * sc.width + sc.width * 11 * sc.k) * mean["selected"]
+    decode_mfma = {"flop_per_anchor": int(dec_flop / max(mean["selected"], 1)),
+                   "tflops": round(dec_flop / (avg["decode"] * 1e-3) / 1e12, 2)}
+    decode_mfma["frac_bf16"] = round(decode_mfma["tflops"] / 2500.0, 5)
+    log(f"decode (BF16, per call incl. the weight-fragment kernel): {decode_mfma}")
 
     # The dominant kernel, compositing, is bound by vector ALU work: per
     # pixel and Gaussian blended (Eq. 2) it evaluates the 2D Gaussian,
@@ -326,6 +348,17 @@ def main():
                "kind": "oracle",
                "sample": f"{len(pick)} evenly spaced views of the same trajectory, full FP64 "
                          f"select+decode+rasterize, {dt:.1f} s"}
+        # one core, on three views of the same trajectory
+        nthr = O.num_threads()
+        O.set_num_threads(1)
+        pick1 = np.linspace(0, len(cams) - 1, 3).round().astype(int)
+        t1 = time.perf_counter()
+        for i in pick1:
+            O.render(sc, cams[i], O.params_array(), thr, rho)
+        dt1 = time.perf_counter() - t1
+        O.set_num_threads(nthr)
+        cpu["one_core"] = {"value": round(len(pick1) / dt1, 4), "unit": "FPS", "cores": 1,
+                           "sample": f"views {pick1.tolist()} of the trajectory, {dt1:.1f} s"}
         log(f"CPU oracle: {cpu}")
 
     train = None if args.no_train else train_step_timing(args, P, S, torch, np)
@@ -374,6 +407,8 @@ def main():
         "train_step_ms": train["ms_per_step"] if train else None,
         "train": train,
         "roofline": roofline,
+        "each_view_alone": per_view,
+        "decode_mfma": decode_mfma,
         "cpu_baseline": cpu,
     }
     if city is not None:
@@ -492,10 +527,22 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
     sb = SK.SkipBuffers(vb)
     # judge on the zoom-out: every view against the plain FP32 full decode
     psn, sel, kept = [], 0, 0
+    from paper_2403_17898_amd.hip_events import HipEvent
+    pe = (HipEvent(), HipEvent())
+    sh = P.stream_handle(None)
+    pred_ms = 0.0
     for c in ccams:
         vb.render(ds, c, prm, precision=P.OCTGS_FP32)
         ref = vb.rgb.clone()
-        SK.render_skip(vb, sb, ds, c, prm, net, thr, precision=P.OCTGS_BF16)
+        # render_skip's steps, with the predictor call timed on its own
+        vb.select(ds, c)
+        pe[0].record(sh)
+        SK.predict(vb, sb, ds, c, net, thr)
+        pe[1].record(sh)
+        vb.decode(ds, c, P.OCTGS_BF16, idx=sb.keep_idx, count=sb.keep_count)
+        vb.rasterize(c, prm)
+        pe[1].synchronize()
+        pred_ms += pe[0].elapsed_ms(pe[1])
         sel += int(vb.sel_count.item())
         kept += int(sb.keep_count.item())
         if fallback:
@@ -511,6 +558,12 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
            "skipped_fraction": 0.0 if fallback else round(1.0 - kept / max(sel, 1), 4),
            "psnr_min_db": round(min(psn), 2), "psnr_mean_db": round(float(np.mean(fin)), 2) if fin else None,
            "train_s": round(time.time() - t0, 1)}
+    # predictor call per view: features, the 37-64-64-1 MLP on BF16 MFMA
+    # (13,056 FLOP per selected anchor), keep-list compaction
+    pms = pred_ms / max(len(ccams), 1)
+    res["predict_ms_per_view"] = round(pms, 4)
+    res["predict_mfma_tflops"] = round(13056.0 * sel / max(len(ccams), 1) / (pms * 1e-3) / 1e12, 2)
+    res["predict_mfma_frac_bf16"] = round(res["predict_mfma_tflops"] / 2500.0, 5)
     log(f"skip predictor: {res}")
     res["_net"], res["_sb"], res["_thr"] = net, sb, thr
     return res

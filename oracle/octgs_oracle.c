@@ -761,6 +761,15 @@ ORC_API int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel regions that follow (timing on fewer cores). */
+ORC_API void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ======================================================================
  * Backward passes (double precision), for the training step of Sec. V
  * (losses on rendered images) and the gradient checks.

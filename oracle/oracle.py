@@ -82,6 +82,8 @@ def _declare(L):
     L.orc_composite.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p]
     L.orc_render_bruteforce.argtypes = [_i64, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_num_threads.restype = _i32
+    L.orc_set_num_threads.argtypes = [_i32]
+    L.orc_set_num_threads.restype = None
     L.orc_composite_backward.argtypes = [_p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_project_backward.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_skip_features.argtypes = [_i64, _p, _p, _p, _p, _p, _p, ctypes.c_float, _p]
@@ -100,6 +102,11 @@ def _c(a, dtype):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on (for timing)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def cam_array(cam) -> np.ndarray:
