@@ -88,6 +88,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _finite(v):
     """The result with non-finite floats (e.g. the PSNR of an exact image)
     as null, so the line is strict JSON."""
@@ -359,6 +371,7 @@ def main():
         O.set_num_threads(nthr)
         cpu["one_core"] = {"value": round(len(pick1) / dt1, 4), "unit": "FPS", "cores": 1,
                            "sample": f"views {pick1.tolist()} of the trajectory, {dt1:.1f} s"}
+        cpu["cpu_model"] = cpu_model()
         log(f"CPU oracle: {cpu}")
 
     train = None if args.no_train else train_step_timing(args, P, S, torch, np)
