@@ -57,6 +57,25 @@ def test_host_only_entry_points():
     assert lib.octgs_strerror(L.OCTGS_ENOSPC) == b"workspace too small"
 
 
+def test_header_constants_match_binding():
+    """Every integer #define and enum value of the header that the binding
+    mirrors has the header's value; the rasterizer flags are mirrored."""
+    from paper_2403_17898_amd import _lib as L
+    src = open(HEADER).read()
+    consts = {m.group(1): int(m.group(2)) for m in
+              re.finditer(r"^#define\s+(OCTGS_\w+)\s+(\d+)u?\b", src, flags=re.M)}
+    consts.update({m.group(1): int(m.group(2)) for m in
+                   re.finditer(r"^\s*(OCTGS_\w+)\s*=\s*(-?\d+)", src, flags=re.M)})
+    for must in ("OCTGS_RASTER_TRAIN", "OCTGS_RASTER_TILE_ORDER", "OCTGS_EINVAL"):
+        assert must in consts and hasattr(L, must), must
+    checked = 0
+    for name, v in consts.items():
+        if hasattr(L, name):
+            assert getattr(L, name) == v, name
+            checked += 1
+    assert checked >= 3
+
+
 def test_struct_sizes_match_header():
     """ctypes mirrors of the C structs have the C sizes (checked with gcc)."""
     import subprocess
