@@ -708,8 +708,14 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         st = vb.stats()
         max_sel, max_pairs = max(max_sel, st["n_selected"]), max(max_pairs, st["n_candidates"])
     del vb
-    vb = P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=int(max_pairs * 1.2) + 4096,
-                       gauss_capacity=int(max_sel * sc.k * 1.2) + 1024)
+    # views run concurrently, one buffer set and stream each (up to
+    # --inflight); the shared gradients are updated in view order (below)
+    nv = len(cams)
+    nbuf = max(1, min(args.inflight, nv))
+    vbs = [P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=int(max_pairs * 1.2) + 4096,
+                         gauss_capacity=int(max_sel * sc.k * 1.2) + 1024) for _ in range(nbuf)]
+    main = torch.cuda.current_stream()
+    streams = [main] + [torch.cuda.Stream() for _ in range(nbuf - 1)]
     grads = P.SceneGrads(ds)
     params = P.trainable(ds)
     gnames = list(P.render.PARAM_NAMES) + sorted(ds.mlp)
@@ -717,11 +723,10 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
     gtens = [gl[n] for n in gnames]
     mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     adam = P.AdamMany(params, gtens, mom)
-    dimg = torch.empty(3, H, W, device=params[0].device)
-    loss = torch.zeros(1, device=params[0].device)
+    dimgs = [torch.empty(3, H, W, device=params[0].device) for _ in range(nbuf)]
+    losses = torch.zeros(nv, device=params[0].device)  # one slot per view
     scale = 1.0 / (len(cams) * 3 * H * W)
-    state = {"step": 0, "ws": None}
-    nv = len(cams)
+    state = {"step": 0, "ws": [None] * nbuf}
     dstats = P.DensifyStats(sc.n, sc.k)
 
     def step(timer=None, full=False):
@@ -729,19 +734,39 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         0.2 (1 - SSIM) averaged over the views, plus 0.01 sum Prod(s) over
         each view's rendered Gaussians; otherwise mean L1."""
         grads.zero_()
-        loss.zero_()
-        for c, tg in zip(cams, targets):
-            vb.render(ds, c, prm)
+        losses.zero_()
+        go = torch.cuda.Event()
+        go.record(main)
+        for st in streams[1:]:
+            st.wait_event(go)
+        # View i runs on stream i % nbuf with buffer set i % nbuf (stream
+        # order protects a reused set).  Forward, loss and rasterizer backward
+        # of different views overlap; the steps that read-modify-write shared
+        # arrays (decode backward into the scene gradients, densification
+        # statistics) are chained in view order by events, so the gradients
+        # are those of the views taken one after another.
+        chain = None
+        for i, (c, tg) in enumerate(zip(cams, targets)):
+            k = i % nbuf
+            st, vb, dimg, li = streams[k], vbs[k], dimgs[k], losses[i:i + 1]
+            vb.render(ds, c, prm, stream=st)
             if full:
-                state["ws"] = P.photometric_loss_grad(vb.rgb, tg, dimg, loss, 0.8 / nv, 0.2 / nv,
-                                                      state["ws"])
+                state["ws"][k] = P.photometric_loss_grad(vb.rgb, tg, dimg, li, 0.8 / nv, 0.2 / nv,
+                                                         state["ws"][k], stream=st)
             else:
-                P.l1_loss_grad(vb.rgb, tg, scale, dimg, loss)
-            vb.rasterize_bwd(c, prm, dimg)
+                P.l1_loss_grad(vb.rgb, tg, scale, dimg, li, stream=st)
+            vb.rasterize_bwd(c, prm, dimg, stream=st)
             if full:
-                vb.volume_loss_grad(0.01, loss)
-                dstats.accumulate(vb, c)
-            vb.decode_bwd(ds, c, grads)
+                vb.volume_loss_grad(0.01, li, stream=st)
+            if chain is not None:
+                st.wait_event(chain)
+            if full:
+                dstats.accumulate(vb, c, stream=st)
+            vb.decode_bwd(ds, c, grads, stream=st)
+            chain = torch.cuda.Event()
+            chain.record(st)
+        # the last link follows every view's work
+        main.wait_event(chain)
         if timer is not None:
             timer.record()
         state["step"] += 1
@@ -751,7 +776,7 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         for _ in range(3):
             step(full=full)
         torch.cuda.synchronize()
-        first = loss.item()
+        first = losses.sum().item()
         n = args.train_steps
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(n)]
@@ -762,13 +787,14 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         torch.cuda.synchronize()
         tot = sorted(a.elapsed_time(c) for a, b, c in ev)
         adam = sorted(b.elapsed_time(c) for a, b, c in ev)
-        return tot[len(tot) // 2], adam[len(adam) // 2], first, loss.item()
+        return tot[len(tot) // 2], adam[len(adam) // 2], first, losses.sum().item()
 
     ms, adam_ms, first_loss, last_loss = timed_steps(False)
     res = {"workload": workload,
            "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam_ms, 3),
            "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
-           "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs}
+           "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs,
+           "views_in_flight": nbuf}
     if not with_full_loss:
         log(f"train step: {res}")
         return res
