@@ -708,14 +708,12 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         st = vb.stats()
         max_sel, max_pairs = max(max_sel, st["n_selected"]), max(max_pairs, st["n_candidates"])
     del vb
-    # views run concurrently, one buffer set and stream each (up to
-    # --inflight); the shared gradients are updated in view order (below)
+    # views in flight, one buffer set and stream each (up to --inflight)
     nv = len(cams)
-    nbuf = max(1, min(args.inflight, nv))
-    vbs = [P.ViewBuffers(sc.n, sc.k, W, H, pair_capacity=int(max_pairs * 1.2) + 4096,
-                         gauss_capacity=int(max_sel * sc.k * 1.2) + 1024) for _ in range(nbuf)]
-    main = torch.cuda.current_stream()
-    streams = [main] + [torch.cuda.Stream() for _ in range(nbuf - 1)]
+    mv = P.MultiViewBackward(ds, W, H, nv, pair_capacity=int(max_pairs * 1.2) + 4096,
+                             gauss_capacity=int(max_sel * sc.k * 1.2) + 1024,
+                             inflight=args.inflight)
+    nbuf = mv.nbuf
     grads = P.SceneGrads(ds)
     params = P.trainable(ds)
     gnames = list(P.render.PARAM_NAMES) + sorted(ds.mlp)
@@ -723,50 +721,17 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
     gtens = [gl[n] for n in gnames]
     mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     adam = P.AdamMany(params, gtens, mom)
-    dimgs = [torch.empty(3, H, W, device=params[0].device) for _ in range(nbuf)]
-    losses = torch.zeros(nv, device=params[0].device)  # one slot per view
+    losses = mv.losses  # one slot per view
     scale = 1.0 / (len(cams) * 3 * H * W)
-    state = {"step": 0, "ws": [None] * nbuf}
+    state = {"step": 0}
     dstats = P.DensifyStats(sc.n, sc.k)
 
     def step(timer=None, full=False):
         """full: the paper's loss for the Scaffold-GS model, 0.8 L1 +
         0.2 (1 - SSIM) averaged over the views, plus 0.01 sum Prod(s) over
         each view's rendered Gaussians; otherwise mean L1."""
-        grads.zero_()
-        losses.zero_()
-        go = torch.cuda.Event()
-        go.record(main)
-        for st in streams[1:]:
-            st.wait_event(go)
-        # View i runs on stream i % nbuf with buffer set i % nbuf (stream
-        # order protects a reused set).  Forward, loss and rasterizer backward
-        # of different views overlap; the steps that read-modify-write shared
-        # arrays (decode backward into the scene gradients, densification
-        # statistics) are chained in view order by events, so the gradients
-        # are those of the views taken one after another.
-        chain = None
-        for i, (c, tg) in enumerate(zip(cams, targets)):
-            k = i % nbuf
-            st, vb, dimg, li = streams[k], vbs[k], dimgs[k], losses[i:i + 1]
-            vb.render(ds, c, prm, stream=st)
-            if full:
-                state["ws"][k] = P.photometric_loss_grad(vb.rgb, tg, dimg, li, 0.8 / nv, 0.2 / nv,
-                                                         state["ws"][k], stream=st)
-            else:
-                P.l1_loss_grad(vb.rgb, tg, scale, dimg, li, stream=st)
-            vb.rasterize_bwd(c, prm, dimg, stream=st)
-            if full:
-                vb.volume_loss_grad(0.01, li, stream=st)
-            if chain is not None:
-                st.wait_event(chain)
-            if full:
-                dstats.accumulate(vb, c, stream=st)
-            vb.decode_bwd(ds, c, grads, stream=st)
-            chain = torch.cuda.Event()
-            chain.record(st)
-        # the last link follows every view's work
-        main.wait_event(chain)
+        mv.run(ds, cams, targets, prm, grads, l1_scale=scale, full=full,
+               dstats=dstats if full else None)
         if timer is not None:
             timer.record()
         state["step"] += 1

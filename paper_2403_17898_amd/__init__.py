@@ -9,3 +9,4 @@ from .render import (AdamMany, DensifyStats, DeviceExplicit, DeviceScene, Explic
                      SceneGrads, ViewBuffers, adam_step, l1_loss_grad, make_camera,
                      photometric_loss_grad, raster_params, render_diff, stream_handle,
                      trainable)
+from .train import MultiViewBackward  # noqa: F401
