@@ -17,6 +17,12 @@
  *    only.
  *  - Every call only enqueues work on `stream` (a hipStream_t passed as
  *    void*, NULL = the null stream) and returns without synchronising.
+ *  - Calls on different streams may run at the same time when they write
+ *    disjoint memory (each its own workspace and outputs): several frames in
+ *    flight, each with its own buffers, is the intended use.  Calls that
+ *    accumulate into the same arrays (octgs_decode_bwd into one set of
+ *    gradients, octgs_densify_accumulate into one set of statistics, the
+ *    loss scalars) must be ordered by the caller, e.g. with events.
  *    Element counts produced on the device (selected anchors, Gaussians,
  *    pairs) stay on the device; kernels read them from device scalars.
  *  - Return value: OCTGS_OK, or a negative octgs_status when host-side
