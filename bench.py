@@ -374,7 +374,8 @@ def main():
         cpu["cpu_model"] = cpu_model()
         log(f"CPU oracle: {cpu}")
 
-    train = None if args.no_train else train_step_timing(args, P, S, torch, np)
+    train = None if args.no_train else train_step_timing(args, P, S, torch, np,
+                                                         oracle_step=not args.no_cpu_baseline)
     city = city_path(args, P, S, torch, np, prm, D, streams) if args.city else None
 
     value = skip["fps"] if skip else fps16
@@ -658,6 +659,20 @@ def city_path(args, P, S, torch, np, prm, D, streams):
     res["psnr_views"] = len(psn)
     log(f"city: FP32 {res['fps_plain_fp32']} FPS, BF16 {res['fps_bf16']} FPS, "
         f"BF16 vs FP32 min PSNR {res['psnr_bf16_vs_fp32_min_db']} dB over {len(psn)} views")
+    if not args.no_cpu_baseline:
+        # the oracle on 10 evenly spaced views of the 4K zoom-out
+        from oracle import oracle as O
+        O.build(force=False)
+        thr, rho = O.scene_thresholds(sc)
+        pick = np.linspace(0, len(ccams_c) - 1, 10).round().astype(int)
+        t1 = time.perf_counter()
+        for i in pick:
+            O.render(sc, ccams_c[i], O.params_array(), thr, rho)
+        dt = time.perf_counter() - t1
+        res["cpu_baseline"] = {"value": round(len(pick) / dt, 4), "unit": "FPS",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"10 evenly spaced views, full FP64 path, {dt:.1f} s"}
+        log(f"city CPU oracle: {res['cpu_baseline']}")
     if not args.no_skip:
         skip = skip_path(args, P, S, torch, np, sc, ds, cams, prm, W, H, vb,
                          view_dist=(2000.0, 20.0, 3000.0), n_train=args.city_skip_views)
@@ -682,7 +697,7 @@ def city_path(args, P, S, torch, np, prm, D, streams):
 
 def train_step_timing(args, P, S, torch, np, sc=None, views=None,
                       workload="500k anchors / 6 levels, 4 views at 1600x1066, mean-L1, Adam",
-                      with_full_loss=True):
+                      with_full_loss=True, oracle_step=False):
     """Training step (by default of the 500k-anchor, 6-level scene: 4 views
     at 1600x1066): mean-L1 against targets rendered from a copy with feature
     noise sigma = 0.05, gradients through compositing, projection and the
@@ -755,11 +770,31 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         return tot[len(tot) // 2], adam[len(adam) // 2], first, losses.sum().item()
 
     ms, adam_ms, first_loss, last_loss = timed_steps(False)
+    cpu_step = None
+    if oracle_step:
+        # the oracle's step on the same views and targets: FP64 forward and
+        # analytic backward through compositing, projection and decode
+        from oracle import oracle as O
+        O.build(force=False)
+        thr, rho = O.scene_thresholds(sc)
+        prm_o = O.params_array()
+        tg = [t.double().cpu().numpy() for t in targets]
+        t1 = time.perf_counter()
+        for v, t_img in zip(views, tg):
+            fwd = O.render(sc, v, prm_o, thr, rho)
+            d = np.sign(fwd["img"] - t_img) / (len(views) * 3 * H * W)  # mean-L1 gradient
+            O.render_backward(sc, v, prm_o, d, fwd=fwd)
+        dt = time.perf_counter() - t1
+        cpu_step = {"value": round(dt * 1e3, 1), "unit": "ms/step", "cores": O.num_threads(),
+                    "kind": "oracle", "sample": f"one step: {len(views)} views, FP64 forward and "
+                                                f"backward (no optimiser update)"}
     res = {"workload": workload,
            "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam_ms, 3),
            "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
            "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs,
            "views_in_flight": nbuf}
+    if cpu_step is not None:
+        res["cpu_oracle_step"] = cpu_step
     if not with_full_loss:
         log(f"train step: {res}")
         return res
