@@ -194,6 +194,23 @@ OCTGS_API size_t octgs_select_workspace_bytes(int64_t n);
 OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
                      uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection as octgs_select_lod, with the same outputs, but its ballots and
+ * block counts live in a buffer the library holds in static device memory
+ * (about 1 MiB per GPU, kept until the process ends) instead of a workspace
+ * argument.  It allocates nothing.  At most OCTGS_SELECT_NOALLOC_MAX_ANCHORS
+ * anchors: a larger a->n returns OCTGS_ENOSPC and enqueues nothing.  The
+ * first call on a device looks up that device's buffer address (the device
+ * must be current, and `stream`, when not NULL, must belong to it;
+ * OCTGS_EINVAL otherwise).  Every call on one GPU shares that GPU's buffer:
+ * calls that may overlap on one GPU (different streams, several host
+ * threads) race and must be ordered by the caller. */
+#define OCTGS_SELECT_NOALLOC_MAX_ANCHORS 8388608 /* 2^23 */
+OCTGS_API int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam,
+                                       uint32_t *sel_idx, uint32_t *sel_count,
+                                       octgs_stream stream);
+
 /* Workspace bytes of octgs_decode for a precision (OCTGS_FP32 or
  * OCTGS_BF16; 0 for any other value).  It does not depend on the scene or
  * the MLP size. */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboctgs.so")
 OCTGS_OK, OCTGS_EINVAL, OCTGS_ENOSPC, OCTGS_EHIP, OCTGS_EUNSUPPORTED = 0, -1, -2, -3, -4
 OCTGS_FP32, OCTGS_BF16 = 0, 1
 OCTGS_RASTER_STAGES = 5
+OCTGS_SELECT_NOALLOC_MAX_ANCHORS = 1 << 23
 OCTGS_RASTER_TRAIN = 1
 OCTGS_RASTER_TILE_ORDER = 2
 RASTER_STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
@@ -97,6 +98,8 @@ SIGNATURES = [
     ("octgs_select_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("octgs_select_lod", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _p,
                                 ctypes.c_size_t, _p]),
+    ("octgs_select_lod_noalloc", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p,
+                                        _p, _p]),
     ("octgs_decode_workspace_bytes", ctypes.c_size_t, [_i32]),
     ("octgs_decode", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp), ctypes.POINTER(Camera),
                             _p, _p, _i32, ctypes.POINTER(Gaussians), _p, ctypes.c_size_t, _p]),

@@ -16,6 +16,8 @@
 //   visible = zc + rho >= z_near and, per side, +-x (or +-y) <= fmaf(tan, zc, rho * sec)
 #include "octgs_internal.h"
 
+#include <mutex>
+
 namespace octgs {
 
 namespace {
@@ -166,6 +168,70 @@ __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
+// Workspace of the two selection passes for n anchors: one 64-bit ballot per
+// 64 anchors, then one count per 1024-anchor block (256-byte aligned).
+constexpr size_t select_ws_bytes(int64_t n) {
+  return (size_t)(((n + kChunk - 1) / kChunk) * (kChunk / 64) * 8 +
+                  ((((n + kChunk - 1) / kChunk) * 4 + 255) / 256) * 256 + 256);
+}
+
+// Selection without a workspace argument: its ballots and block counts live
+// in this file-scope array, sized for at most kScratchMaxAnchors anchors.
+// Each GPU the library runs on holds its own copy until the process ends.
+constexpr int64_t kScratchMaxAnchors = OCTGS_SELECT_NOALLOC_MAX_ANCHORS;
+static_assert(kScratchMaxAnchors < (int64_t(1) << 31), "anchor indices are 32-bit");
+constexpr size_t kScratchBytes = select_ws_bytes(kScratchMaxAnchors);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` per device ordinal, looked up once per device
+// with that device current (the host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(hipStream_t s, void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return OCTGS_EHIP;
+  if (s) {
+    int sdev = -1;
+    if (hipStreamGetDevice(s, &sdev) != hipSuccess) return OCTGS_EHIP;
+    if (sdev != dev) return OCTGS_EINVAL;  // the stream must be on the current device
+  }
+  if (dev < 0 || dev >= kMaxDevices) return OCTGS_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OCTGS_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return OCTGS_OK;
+}
+
+// The two selection passes with the workspace at `ws` (>= select_ws_bytes(n)).
+int launch_select(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
+                  uint32_t *sel_count, void *ws, hipStream_t s) {
+  const int64_t nblk = (a->n + kChunk - 1) / kChunk;
+  uint64_t *masks = (uint64_t *)ws;
+  uint32_t *blk = (uint32_t *)((char *)ws + nblk * (kChunk / 64) * 8);
+  hipLaunchKernelGGL(k_select_mark, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, *cam,
+                     a->pos, a->thr2, a->bound_r, masks, blk);
+  hipLaunchKernelGGL(k_select_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, masks,
+                     blk, sel_idx, sel_count);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+// Host-side checks shared by both selection entry points.
+int check_select_args(const octgs_anchors *a, const octgs_camera *cam, const uint32_t *sel_idx,
+                      const uint32_t *sel_count) {
+  if (!a || !cam || !sel_idx || !sel_count) return OCTGS_EINVAL;
+  if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
+  if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
+    return OCTGS_EINVAL;
+  if (a->n > 0 && (!a->pos || !a->thr2 || !a->bound_r)) return OCTGS_EINVAL;
+  return OCTGS_OK;
+}
+
 }  // namespace
 
 }  // namespace octgs
@@ -193,32 +259,39 @@ int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
 
 size_t octgs_select_workspace_bytes(int64_t n) {
   if (n < 0) return 0;
-  const int64_t nblk = (n + kChunk - 1) / kChunk;
-  const int64_t ngrp = nblk * (kChunk / 64);
-  return (size_t)(ngrp * 8 + ((nblk * 4 + 255) / 256) * 256 + 256);
+  return select_ws_bytes(n);
 }
 
 int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
                      uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream) {
-  if (!a || !cam || !sel_idx || !sel_count) return OCTGS_EINVAL;
-  if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
-  if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
-    return OCTGS_EINVAL;
+  const int st = check_select_args(a, cam, sel_idx, sel_count);
+  if (st != OCTGS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (a->n == 0) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, sel_count);
     return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
   }
-  if (!a->pos || !a->thr2 || !a->bound_r || !ws) return OCTGS_EINVAL;
+  if (!ws) return OCTGS_EINVAL;
   if (ws_bytes < octgs_select_workspace_bytes(a->n)) return OCTGS_ENOSPC;
-  const int64_t nblk = (a->n + kChunk - 1) / kChunk;
-  uint64_t *masks = (uint64_t *)ws;
-  uint32_t *blk = (uint32_t *)((char *)ws + nblk * (kChunk / 64) * 8);
-  hipLaunchKernelGGL(k_select_mark, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, *cam,
-                     a->pos, a->thr2, a->bound_r, masks, blk);
-  hipLaunchKernelGGL(k_select_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, masks,
-                     blk, sel_idx, sel_count);
-  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+  return launch_select(a, cam, sel_idx, sel_count, ws, s);
+}
+
+int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
+                             uint32_t *sel_count, octgs_stream stream) {
+  const int st = check_select_args(a, cam, sel_idx, sel_count);
+  if (st != OCTGS_OK) return st;
+  if (a->n > kScratchMaxAnchors) return OCTGS_ENOSPC;
+  hipStream_t s = (hipStream_t)stream;
+  if (a->n == 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, sel_count);
+    return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+  }
+  void *ws = nullptr;
+  const int sa = scratch_address(s, &ws);
+  if (sa != OCTGS_OK) return sa;
+  // every scratch word the two passes read is written by the first pass of
+  // the same call, so nothing needs clearing
+  return launch_select(a, cam, sel_idx, sel_count, ws, s);
 }
 
 }  // extern "C"
