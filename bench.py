@@ -112,15 +112,30 @@ def _finite(v):
     return v
 
 
+def view_order(steps: int, nviews: int):
+    """Indices of the views a pass of `steps` renders: a stride through the
+    whole trajectory (every view once when steps == nviews), so any step
+    count samples the zoom-out from its first to its last altitude."""
+    if steps >= nviews:
+        return [i % nviews for i in range(steps)]
+    return [(i * nviews) // steps for i in range(steps)]
+
+
 def time_views(args, torch, streams, views, bufs, render_one, depth):
     """(event ms, wall s) for args.steps views after args.warmup untimed
-    ones; view i runs on stream i % depth with buffers bufs[i % depth]."""
+    ones; the i-th rendered view, views[view_order(...)[i]], runs on stream
+    i % depth with buffers bufs[i % depth]."""
     stream = streams[0]
 
     def run(n):
+        order = view_order(n, len(views))
         for i in range(n):
             k = i % depth
-            render_one(k, views[i % len(views)], streams[k])
+            render_one(k, views[order[i]], streams[k])
+            # every frame's overflow / look-back / truncation bits, checked after the loop
+            bufs[k].add_status(stream=streams[k])
+    for b in bufs[:depth]:
+        b.status.zero_()
     run(args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -137,9 +152,7 @@ def time_views(args, torch, streams, views, bufs, render_one, depth):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     for b in bufs[:depth]:
-        st = b.stats()
-        if st["pair_overflow"] or st["sync_error"]:
-            raise SystemExit(f"timed run flagged: {st}")
+        b.check_status("timed frames")
     return e0.elapsed_time(e1), wall
 
 
@@ -258,15 +271,16 @@ def main():
     from paper_2403_17898_amd.hip_events import HipEvent
     names = ["select", "decode"] + list(L.RASTER_STAGE_NAMES)
     tot = {k: 0.0 for k in names}
-    nviews = min(args.steps, len(ccams))
+    order = view_order(args.steps, len(ccams))  # the timed passes' views
+    nviews = len(order)
     sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0, blends=0)
     view_ms = []
     ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
     sh = P.stream_handle(stream)
     for i in range(nviews):
-        c = ccams[i]
+        c = ccams[order[i]]
         ev[0].record(sh)
-        vb.select(ds, c)
+        vb.select(ds, c, prm)
         ev[1].record(sh)
         ev[2].record(sh)
         vb.decode(ds, c, P.OCTGS_BF16)
@@ -295,10 +309,10 @@ def main():
         f"(of {mean['candidates']:.0f} rectangle candidates)")
     # each view alone on the GPU (the loop above) against the camera altitude
     vm = np.array(view_ms)
-    alts = np.array([float(cams[i].C[2]) for i in range(nviews)])
+    alts = np.array([float(cams[order[i]].C[2]) for i in range(nviews)])
     edges = np.linspace(0, nviews, 11).round().astype(int)
     per_view = {"ms_mean": round(float(vm.mean()), 4), "ms_max": round(float(vm.max()), 4),
-                "slowest_view": int(vm.argmax()),
+                "slowest_view": int(order[int(vm.argmax())]),
                 "slowest_altitude_m": round(float(alts[vm.argmax()]), 1),
                 "min_fps": round(1e3 / float(vm.max()), 1),
                 "altitude_m_vs_ms": [[round(float(alts[a:b].mean()), 1), round(float(vm[a:b].mean()), 4)]
@@ -478,7 +492,7 @@ def explicit_path(args, P, S, torch, np, sc, ccams, prm, W, H, D, streams, timed
         slots = sel = pairs = 0
         for i in range(nviews):
             c = ccams[i]
-            vb.select(de, c)
+            vb.select(de, c, prm)
             ev[0].record(sh)
             vb.decode_explicit(de, c, prec)
             ev[1].record(sh)
@@ -530,7 +544,7 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
     sbl = SK.SkipBuffers(vbl)
     hsel = hkept = 0
     for c in hold_cams:
-        vbl.select(ds, c)
+        vbl.select(ds, c, prm)
         SK.predict(vbl, sbl, ds, c, net, thr)
         hsel += int(vbl.sel_count.item())
         hkept += int(sbl.keep_count.item())
@@ -549,7 +563,7 @@ def skip_path(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vb, timed_fn=None
         vb.render(ds, c, prm, precision=P.OCTGS_FP32)
         ref = vb.rgb.clone()
         # render_skip's steps, with the predictor call timed on its own
-        vb.select(ds, c)
+        vb.select(ds, c, prm)
         pe[0].record(sh)
         SK.predict(vb, sb, ds, c, net, thr)
         pe[1].record(sh)
@@ -770,6 +784,7 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         return tot[len(tot) // 2], adam[len(adam) // 2], first, losses.sum().item()
 
     ms, adam_ms, first_loss, last_loss = timed_steps(False)
+    mv.check()  # no view of any step overflowed, hit a wait bound or was truncated
     cpu_step = None
     if oracle_step:
         # the oracle's step on the same views and targets: FP64 forward and
@@ -799,6 +814,7 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
         log(f"train step: {res}")
         return res
     msf, _, ff, fl = timed_steps(True)
+    mv.check()
     # densification decisions of the interval (every T = 100 iterations)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -94,7 +94,8 @@ typedef struct {
   const uint8_t *level;      /* [n] octree level L_v */
   const float *lod_bias;     /* [n] learnable LOD bias Delta L_v */
   const float *feat;         /* [n][feat_dim] FP32 feature (plain path) */
-  const uint16_t *feat_bf16; /* [n][feat_dim] BF16 bit patterns (BF16 path), may be NULL otherwise */
+  const uint16_t *feat_bf16; /* [n][feat_dim] BF16 bit patterns (BF16 path; written by
+                                octgs_prepare_anchors), may be NULL otherwise */
   const float *offsets;      /* [n][k][3] offsets O_i of Eq. 3 */
   const float *offset_scale; /* [n][3] scaling l_v of Eq. 3 */
   const float *base_scale;   /* [n][3] upper bound of each decoded Gaussian scale */
@@ -173,26 +174,41 @@ typedef struct {
  * iff |x_v - C|^2 s^2 <= thr2 (the clamp of Eq. 7 applied to the sum of the
  * log term and Delta L).  bound_r[j] = max_i |O_i * l_v| + 3 max(base_scale),
  * a sphere around x_v that holds the 3-sigma extent of every Gaussian the
- * anchor can decode.  Reads pos-independent fields of `a` (level, lod_bias,
- * offsets, offset_scale, base_scale, d_max); a->thr2 / a->bound_r are
- * ignored.  Outputs: device [n] each. */
+ * anchor can decode.  feat_bf16 (nullable, device [n][feat_dim]): the BF16
+ * copy of a->feat that the OCTGS_BF16 decode reads, each value rounded to
+ * nearest even.  Reads pos-independent fields of `a` (level, lod_bias,
+ * offsets, offset_scale, base_scale, d_max; feat with feat_bf16);
+ * a->thr2 / a->bound_r are ignored.  Outputs: device [n] each.  All three
+ * depend on trained arrays: call again after every update of offsets,
+ * offset_scale, base_scale, feat or lod_bias, before the next selection or
+ * decode reads them. */
 OCTGS_API int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
-                          octgs_stream stream);
+                                    uint16_t *feat_bf16, octgs_stream stream);
 
 /* Workspace bytes octgs_select_lod needs for n anchors. */
 OCTGS_API size_t octgs_select_workspace_bytes(int64_t n);
 
 /* Anchor selection (Eq. 7 and the cumulative rule L_v <= L_hat, Sec. IV-A):
- * anchor j is selected iff its bound sphere intersects the view frustum
- * (near plane and the four side planes) and |x_v - C|^2 s^2 <= thr2[j]; with
- * cam->lod_blend the threshold is that of level L_v - 1, 4 thr2[j] (exact in
- * FP32): level L_hat + 1 is taken too, except level-1 anchors farther than
- * where L* reaches 0 (their opacity factor would be 0).
+ * anchor j is selected iff |x_v - C|^2 s^2 <= thr2[j] and its bound sphere
+ * is visible; with cam->lod_blend the threshold is that of level L_v - 1,
+ * 4 thr2[j] (exact in FP32): level L_hat + 1 is taken too, except level-1
+ * anchors farther than where L* reaches 0 (their opacity factor would be 0).
+ * Visibility ("visible anchors", Sec. IV-A) is conservative for a render
+ * with the raster parameters p: the sphere is dropped only if it lies in
+ * front of the near plane or beyond a side plane by enough that none of its
+ * Gaussians' dilated 3-sigma EWA ellipses (Jacobian clamped by
+ * p->jac_clamp) reaches a pixel centre; each side plane is moved out by
+ * 3 sqrt(p->dilation) pixels and the sphere's radius is weighted by the
+ * plane normal's length plus the clamped Jacobian's largest slope change.
  * Every decision is taken in FP32 by a fixed operation order.  Outputs:
  * sel_idx (device, capacity n) receives the selected indices in ascending
- * order; *sel_count (device) their number.  ws: device, >= the size above. */
-OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
-                     uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream);
+ * order; *sel_count (device) their number.  ws: device, >= the size above.
+ * OCTGS_EINVAL also for cam->z_near <= 0, p->dilation < 0 or
+ * p->jac_clamp <= 0. */
+OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam,
+                               const octgs_raster_params *p, uint32_t *sel_idx,
+                               uint32_t *sel_count, void *ws, size_t ws_bytes,
+                               octgs_stream stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -208,8 +224,8 @@ OCTGS_API int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, 
  * threads) race and must be ordered by the caller. */
 #define OCTGS_SELECT_NOALLOC_MAX_ANCHORS 8388608 /* 2^23 */
 OCTGS_API int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam,
-                                       uint32_t *sel_idx, uint32_t *sel_count,
-                                       octgs_stream stream);
+                                       const octgs_raster_params *p, uint32_t *sel_idx,
+                                       uint32_t *sel_count, octgs_stream stream);
 
 /* Workspace bytes of octgs_decode for a precision (OCTGS_FP32 or
  * OCTGS_BF16; 0 for any other value).  It does not depend on the scene or
@@ -249,9 +265,9 @@ OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pa
  *    definite, or a 3-sigma rectangle outside the image;
  *  - bin into 16x16 tiles: candidates are the tiles of the rectangle around
  *    the 3-sigma circle; a candidate is kept iff the 3-sigma ellipse
- *    {q(x) <= 9} meets the box spanned by the tile's pixel centres
- *    (canonical FP32 test); order each tile's list by camera-space depth of
- *    the Gaussian centre, ties by slot index;
+ *    {q(x) <= 9} meets the box spanned by the tile's pixel centres inside
+ *    the image (canonical FP32 test); order each tile's list by camera-space
+ *    depth of the Gaussian centre, ties by slot index;
  *  - per pixel: a_i = min(alpha_max, opacity_i * G'_i(x')), C = sum T_i a_i c_i,
  *    T_i = prod_{j<i} (1 - a_j), stop after T < t_min, add T * bg.
  * Outputs (device): rgb planar [3][H][W]; T_final [H][W]; last [H][W] = list
@@ -261,7 +277,9 @@ OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pa
  * with octgs_raster_stats.  stage_events (nullable): 2 * OCTGS_RASTER_STAGES
  * hipEvent_t created by the caller; events 2s and 2s+1 are recorded on
  * `stream` around stage s (0 project + compaction, 1 depth sort, 2 pair
- * emission, 3 tile sort + ranges, 4 composite) for per-stage timing. */
+ * emission, 3 tile sort + ranges, 4 composite) for per-stage timing.
+ * OCTGS_EINVAL also for cam->z_near <= 0 (depth keys are the float bits of
+ * positive depths), p->dilation < 0 or p->jac_clamp <= 0. */
 OCTGS_API int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
                         const octgs_raster_params *p, int64_t pair_capacity, float *rgb,
                         float *T_final, uint32_t *last, float *gauss_w, void *ws,
@@ -440,10 +458,14 @@ typedef struct {
  * octgs_prepare_anchors; bound_r[j] = max_i |mean_i - x_v| + 3 exp(max log_scale)
  * over the anchor's Gaussians (canonical FP32; the exponential of the
  * largest log-scale is taken in double and rounded once), a sphere holding
- * every Gaussian's 3-sigma extent.  Reads a->n, k, d_max, pos, level,
- * lod_bias and e->mean, e->log_scale.  Outputs: device [n] each. */
+ * every Gaussian's 3-sigma extent.  sh_bf16 (nullable, device, the layout
+ * of e->sh): the BF16 copy of e->sh that the OCTGS_BF16 decode reads, each
+ * value rounded to nearest even.  Reads a->n, k, d_max, pos, level,
+ * lod_bias and e->mean, e->log_scale (e->sh with sh_bf16).  Outputs: device
+ * [n] each.  Call again after any update of those arrays. */
 OCTGS_API int octgs_prepare_explicit(const octgs_anchors *a, const octgs_explicit *e,
-                                     float *thr2, float *bound_r, octgs_stream stream);
+                                     float *thr2, float *bound_r, uint16_t *sh_bf16,
+                                     octgs_stream stream);
 
 /* Decode of the explicit Gaussians of the first min(*count, out->capacity / k)
  * anchors listed in idx (device): slot p*k + i receives Gaussian i of the
@@ -532,6 +554,23 @@ OCTGS_API int octgs_densify_decide(const octgs_anchors *a, const octgs_densify_s
                                    const octgs_densify_params *p, float *lod_bias,
                                    int8_t *grow_level, uint8_t *prune, uint32_t *counts,
                                    octgs_stream stream);
+
+/* Status bits of octgs_frame_status. */
+#define OCTGS_STATUS_PAIR_OVERFLOW 1u /* the pair list overflowed: the image is incomplete */
+#define OCTGS_STATUS_SYNC_ERROR 2u    /* a look-back wait hit its bound: the output is invalid */
+#define OCTGS_STATUS_TRUNCATED 4u     /* more listed anchors than the Gaussian capacity holds */
+
+/* Adds the conditions one frame detected on the device to a caller-owned
+ * status word, so a caller can render many frames and check once:
+ * *status (device u32) |= OCTGS_STATUS_PAIR_OVERFLOW / _SYNC_ERROR from the
+ * stats header octgs_rasterize_fwd left at byte 0 of ws, and
+ * OCTGS_STATUS_TRUNCATED if count (nullable, device: the anchors listed for
+ * the decode) times k exceeds gauss_capacity (the decode then drops the
+ * rest).  Enqueue on the frame's stream after its octgs_rasterize_fwd;
+ * frames on several streams may add to one word (atomic OR).  The word is
+ * never cleared by the library. */
+OCTGS_API int octgs_frame_status(const void *ws, const uint32_t *count, int32_t k,
+                                 int64_t gauss_capacity, uint32_t *status, octgs_stream stream);
 
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:

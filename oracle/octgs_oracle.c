@@ -87,20 +87,50 @@ static void cam_xform_f(const cam_t *k, float px, float py, float pz,
   *zc = fmaf(k->R[6], d0, fmaf(k->R[7], d1, k->R[8] * d2));
 }
 
-/* Sphere (camera-space centre, radius rho) against the near plane and the
- * four side planes of the pinhole frustum.  tan of each side plane is a
- * float division of the image-edge offset by the focal length; its secant is
- * sqrtf(fmaf(t, t, 1)). */
-static int sphere_visible_f(const cam_t *k, float xc, float yc, float zc, float rho) {
-  float tl = k->cx / k->fx, tr = ((float)k->W - k->cx) / k->fx;
-  float tt = k->cy / k->fy, tb = ((float)k->H - k->cy) / k->fy;
-  float sl = sqrtf(fmaf(tl, tl, 1.0f)), sr = sqrtf(fmaf(tr, tr, 1.0f));
-  float st = sqrtf(fmaf(tt, tt, 1.0f)), sb = sqrtf(fmaf(tb, tb, 1.0f));
+/* Visibility of an anchor's bound sphere (camera-space centre, radius rho),
+ * conservative for the render: the sphere is culled only if no Gaussian
+ * inside it can reach a pixel centre of the image.  Reading of "visible
+ * anchors" (Sec. IV-A) with the EWA projection of Sec. III-A:
+ *  - near plane: every Gaussian centre of a sphere entirely in front of
+ *    z_near fails the projection's z > z_near cull;
+ *  - side planes: the drawn footprint of a Gaussian is the 3-sigma ellipse of
+ *    J W Sigma W^T J^T + dilation I.  It lies inside the linear image of the
+ *    3-sigma ellipsoid widened by 3 sqrt(dilation) pixels (support functions
+ *    add under the square root bound), so each side plane is moved out by
+ *    pad = 3 sqrt(dilation) pixels.  The linear image uses the Jacobian at the
+ *    Gaussian's centre with x/z clamped to +-lx (lx = jac_clamp * half-image
+ *    tangent); for the right plane x = t z (t = (W - cx + pad) / fx) a point p
+ *    of the ellipsoid maps to u - (cx + fx t) = (fx / z_mu) [h(p) -
+ *    (t_c - t)(z_p - z_mu)] with h = x - t z and t_c the clamped slope, and
+ *    |t_c - t| <= |lx - t| whenever the centre is beyond the plane, while
+ *    |z_p - z_mu| <= 3 max scale <= rho.  So the sphere is culled only if
+ *    h(centre) > rho (sec + |lx - t|), sec = sqrt(1 + t^2) (the plane
+ *    normal's length); the other three planes alike.
+ * Canonical FP32 sequence:
+ *   pad = 3 * sqrtf(dilation)
+ *   tl = (cx + pad) / fx, tr = ((W - cx) + pad) / fx, tt = (cy + pad) / fy,
+ *   tb = ((H - cy) + pad) / fy
+ *   lx = jac_clamp * ((0.5 * W) / fx), ly = jac_clamp * ((0.5 * H) / fy)
+ *   m_side = sqrtf(fmaf(t, t, 1)) + fabsf(l - t) with (t, l) of that side
+ *   visible iff zc + rho >= z_near and xc <= fmaf(tr, zc, rho * mr),
+ *   -xc <= fmaf(tl, zc, rho * ml), yc <= fmaf(tb, zc, rho * mb),
+ *   -yc <= fmaf(tt, zc, rho * mt). */
+static int sphere_visible_f(const cam_t *k, const prm_t *pp, float xc, float yc, float zc,
+                            float rho) {
+  float pad = 3.0f * sqrtf(pp->dilation);
+  float tl = (k->cx + pad) / k->fx, tr = (((float)k->W - k->cx) + pad) / k->fx;
+  float tt = (k->cy + pad) / k->fy, tb = (((float)k->H - k->cy) + pad) / k->fy;
+  float lx = pp->jac_clamp * ((0.5f * (float)k->W) / k->fx);
+  float ly = pp->jac_clamp * ((0.5f * (float)k->H) / k->fy);
+  float ml = sqrtf(fmaf(tl, tl, 1.0f)) + fabsf(lx - tl);
+  float mr = sqrtf(fmaf(tr, tr, 1.0f)) + fabsf(lx - tr);
+  float mt = sqrtf(fmaf(tt, tt, 1.0f)) + fabsf(ly - tt);
+  float mb = sqrtf(fmaf(tb, tb, 1.0f)) + fabsf(ly - tb);
   if (!(zc + rho >= k->z_near)) return 0;
-  if (!(xc <= fmaf(tr, zc, rho * sr))) return 0;
-  if (!(-xc <= fmaf(tl, zc, rho * sl))) return 0;
-  if (!(yc <= fmaf(tb, zc, rho * sb))) return 0;
-  if (!(-yc <= fmaf(tt, zc, rho * st))) return 0;
+  if (!(xc <= fmaf(tr, zc, rho * mr))) return 0;
+  if (!(-xc <= fmaf(tl, zc, rho * ml))) return 0;
+  if (!(yc <= fmaf(tb, zc, rho * mb))) return 0;
+  if (!(-yc <= fmaf(tt, zc, rho * mt))) return 0;
   return 1;
 }
 
@@ -172,8 +202,9 @@ ORC_API void orc_bound_radius_explicit(int64_t n, int k, const float *pos, const
  * mask and returns the selected count. pos is [n][3]. */
 ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
                                 const float *rho, int blend, const float *camf, int W, int H,
-                                uint8_t *mask) {
+                                const float *prmf, uint8_t *mask) {
   cam_t k = load_cam(camf, W, H);
+  prm_t pp = load_prm(prmf);
   int64_t cnt = 0;
   for (int64_t j = 0; j < n; ++j) {
     float px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
@@ -187,7 +218,7 @@ ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
     if (sel) {
       float xc, yc, zc;
       cam_xform_f(&k, px, py, pz, &xc, &yc, &zc);
-      sel = sphere_visible_f(&k, xc, yc, zc, rho[j]);
+      sel = sphere_visible_f(&k, &pp, xc, yc, zc, rho[j]);
     }
     mask[j] = (uint8_t)sel;
     cnt += sel;
@@ -201,11 +232,16 @@ ORC_API int64_t orc_select_fp32(int64_t n, const float *pos, const float *thr2,
 ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level,
                                const float *lod_bias, float d_max, int n_levels,
                                const float *rho, int blend, const float *camf, int W, int H,
-                               uint8_t *mask) {
+                               const float *prmf, uint8_t *mask) {
   cam_t k = load_cam(camf, W, H);
+  prm_t pp = load_prm(prmf);
   double s = sqrt((double)k.s2);
-  double tl = (double)k.cx / k.fx, tr = ((double)W - k.cx) / k.fx;
-  double tt = (double)k.cy / k.fy, tb = ((double)H - k.cy) / k.fy;
+  double pad = 3.0 * sqrt((double)pp.dilation);
+  double tl = ((double)k.cx + pad) / k.fx, tr = ((double)W - k.cx + pad) / k.fx;
+  double tt = ((double)k.cy + pad) / k.fy, tb = ((double)H - k.cy + pad) / k.fy;
+  double lx = (double)pp.jac_clamp * 0.5 * W / k.fx, ly = (double)pp.jac_clamp * 0.5 * H / k.fy;
+  double ml = sqrt(tl * tl + 1) + fabs(lx - tl), mr = sqrt(tr * tr + 1) + fabs(lx - tr);
+  double mt = sqrt(tt * tt + 1) + fabs(ly - tt), mb = sqrt(tb * tb + 1) + fabs(ly - tb);
   int64_t cnt = 0;
   for (int64_t j = 0; j < n; ++j) {
     double d[3];
@@ -223,10 +259,8 @@ ORC_API int64_t orc_select_eq7(int64_t n, const float *pos, const uint8_t *level
       double yc = k.R[3] * d[0] + k.R[4] * d[1] + k.R[5] * d[2];
       double zc = k.R[6] * d[0] + k.R[7] * d[1] + k.R[8] * d[2];
       double r = rho[j];
-      sel = (zc + r >= k.z_near) && (xc <= tr * zc + r * sqrt(tr * tr + 1)) &&
-            (-xc <= tl * zc + r * sqrt(tl * tl + 1)) &&
-            (yc <= tb * zc + r * sqrt(tb * tb + 1)) &&
-            (-yc <= tt * zc + r * sqrt(tt * tt + 1));
+      sel = (zc + r >= k.z_near) && (xc <= tr * zc + r * mr) && (-xc <= tl * zc + r * ml) &&
+            (yc <= tb * zc + r * mb) && (-yc <= tt * zc + r * mt);
     }
     mask[j] = (uint8_t)sel;
     cnt += sel;
@@ -325,21 +359,22 @@ static int project_decide_f(const cam_t *k, const prm_t *pp, const float *g, int
 
 /* Tile test (canonical FP32): does the 3-sigma ellipse {q(p) <= 9},
  * q(p) = qa dx^2 + 2 qb dx dy + qc dy^2 around the float 2D mean, meet the
- * rectangle spanned by the tile's pixel centres [16 tx + 0.5, 16 tx + 15.5] x
- * [16 ty + 0.5, 16 ty + 15.5]?  The minimum of the convex quadratic over the
- * rectangle is 0 when the mean is inside, else it lies on an edge facing the
- * mean, where the one-dimensional minimiser is clamped to the edge:
- *   X0 = (float)(16 tx) + 0.5, X1 = X0 + 15 (Y alike)
+ * rectangle spanned by the tile's pixel centres that lie in the W x H image,
+ * [16 tx + 0.5, min(16 tx + 15.5, W - 0.5)] x [16 ty + 0.5, min(16 ty + 15.5,
+ * H - 0.5)]?  The minimum of the convex quadratic over the rectangle is 0
+ * when the mean is inside, else it lies on an edge facing the mean, where
+ * the one-dimensional minimiser is clamped to the edge:
+ *   X0 = (float)(16 tx) + 0.5, X1 = fminf(X0 + 15, (float)W - 0.5) (Y alike)
  *   if the mean's x is outside [X0, X1]: xe = nearer of X0, X1; dx = xe - mx;
  *     ys = min(max(my - (qb * dx) / qc, Y0), Y1); dy = ys - my;
  *     q1 = fmaf(qa * dx, dx, fmaf(2 * qb * dx, dy, qc * dy * dy))
  *   if the mean's y is outside [Y0, Y1]: ye, dy = ye - my;
  *     xs = min(max(mx - (qb * dy) / qa, X0), X1); dx = xs - mx; q2 = same form
  *   keep iff min(q1, q2) <= 9. */
-static int tile_meets_ellipse_f(const float cf[5], int tx, int ty) {
+static int tile_meets_ellipse_f(const float cf[5], int tx, int ty, int W, int H) {
   float mx = cf[0], my = cf[1], qa = cf[2], qb = cf[3], qc = cf[4];
-  float X0 = (float)(16 * tx) + 0.5f, X1 = X0 + 15.0f;
-  float Y0 = (float)(16 * ty) + 0.5f, Y1 = Y0 + 15.0f;
+  float X0 = (float)(16 * tx) + 0.5f, X1 = fminf(X0 + 15.0f, (float)W - 0.5f);
+  float Y0 = (float)(16 * ty) + 0.5f, Y1 = fminf(Y0 + 15.0f, (float)H - 0.5f);
   int in_x = !(mx < X0) && !(mx > X1), in_y = !(my < Y0) && !(my > Y1);
   if (in_x && in_y) return 1;
   float q = INFINITY;
@@ -563,6 +598,253 @@ ORC_API int64_t orc_project(int64_t n, int64_t stride, const float *gf, const do
 }
 
 /* ======================================================================
+ * Decisions near their thresholds
+ *
+ * The HIP path decodes in FP32, so its decoded attributes differ from the
+ * oracle's FP64 ones by up to a known per-attribute bound, and its discrete
+ * decisions (the culls, the tile rectangle, the tile test, the depth order)
+ * are taken on those slightly different values.  A decision whose
+ * continuous quantity lies within that bound (propagated to first order,
+ * times 1.5) plus an FP32 evaluation slack of its threshold may legitimately
+ * come out either way.  These functions flag such Gaussians, so that a
+ * parity test can ask for bit-exact lists and images everywhere else.
+ * ====================================================================== */
+
+/* Continuous quantities behind the canonical decisions of one Gaussian, in
+ * double, in the order of project_decide_f: v[0] opacity, v[1] zc,
+ * v[2] det of the dilated 2D covariance, v[3] 3 sqrt(lambda_max),
+ * v[4] px, v[5] py, v[6..8] conic (qa, qb, qc), v[9] |a c| + b^2. */
+enum { DQ_OP, DQ_Z, DQ_DET, DQ_R3, DQ_PX, DQ_PY, DQ_QA, DQ_QB, DQ_QC, DQ_DETSCALE, DQ_N };
+
+static void decision_values(const cam_t *k, const prm_t *pp, const double *g, double *v) {
+  double d[3] = {g[0] - k->C[0], g[1] - k->C[1], g[2] - k->C[2]};
+  double xc = k->R[0] * d[0] + k->R[1] * d[1] + k->R[2] * d[2];
+  double yc = k->R[3] * d[0] + k->R[4] * d[1] + k->R[5] * d[2];
+  double zc = k->R[6] * d[0] + k->R[7] * d[1] + k->R[8] * d[2];
+  v[DQ_OP] = g[10];
+  v[DQ_Z] = zc;
+  double zs = zc > 1e-30 ? zc : 1e-30;
+  /* the decoded quaternion is unit; a perturbed one is taken back to unit
+   * length, so that its change is a rotation */
+  double qn = sqrt(g[6] * g[6] + g[7] * g[7] + g[8] * g[8] + g[9] * g[9]);
+  if (!(qn > 0)) qn = 1;
+  double w = g[6] / qn, x = g[7] / qn, y = g[8] / qn, z = g[9] / qn;
+  double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  double M[9], S[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = Rq[3 * a + b] * g[3 + b];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      S[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+  double lx = (double)pp->jac_clamp * (0.5 * k->W / (double)k->fx);
+  double ly = (double)pp->jac_clamp * (0.5 * k->H / (double)k->fy);
+  double rx = xc / zs, ry = yc / zs;
+  double tx = fmin(lx, fmax(-lx, rx)) * zs, ty = fmin(ly, fmax(-ly, ry)) * zs;
+  double J00 = k->fx / zs, J02 = -k->fx * tx / (zs * zs);
+  double J11 = k->fy / zs, J12 = -k->fy * ty / (zs * zs);
+  double T0[3], T1[3];
+  for (int c = 0; c < 3; ++c) {
+    T0[c] = J00 * k->R[c] + J02 * k->R[6 + c];
+    T1[c] = J11 * k->R[3 + c] + J12 * k->R[6 + c];
+  }
+  double a = 0, b = 0, c = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      a += T0[i] * S[3 * i + j] * T0[j];
+      b += T1[i] * S[3 * i + j] * T0[j];
+      c += T1[i] * S[3 * i + j] * T1[j];
+    }
+  a += pp->dilation;
+  c += pp->dilation;
+  double det = a * c - b * b;
+  double mid = 0.5 * (a + c);
+  double lam = mid + sqrt(fmax(mid * mid - det, 0.0));
+  v[DQ_DET] = det;
+  v[DQ_R3] = 3.0 * sqrt(fmax(lam, 0.0));
+  v[DQ_PX] = k->fx * rx + k->cx;
+  v[DQ_PY] = k->fy * ry + k->cy;
+  double dd = det != 0 ? det : 1e-300;
+  v[DQ_QA] = c / dd;
+  v[DQ_QB] = -b / dd;
+  v[DQ_QC] = a / dd;
+  v[DQ_DETSCALE] = fabs(a * c) + b * b;
+}
+
+/* Minimum of q = qa dx^2 + 2 qb dx dy + qc dy^2 over the box of tile
+ * (tx, ty)'s pixel centres inside the image, in double (0 with the mean
+ * inside); also the sum of the magnitudes of its three terms there. */
+static double tile_qmin_d(double mx, double my, double qa, double qb, double qc, int tx, int ty,
+                          int W, int H, double *scale) {
+  double X0 = 16.0 * tx + 0.5, X1 = fmin(X0 + 15.0, W - 0.5);
+  double Y0 = 16.0 * ty + 0.5, Y1 = fmin(Y0 + 15.0, H - 0.5);
+  int in_x = mx >= X0 && mx <= X1, in_y = my >= Y0 && my <= Y1;
+  *scale = 0;
+  if (in_x && in_y) return 0.0;
+  double q = INFINITY;
+  if (!in_x) {
+    double dx = (mx < X0 ? X0 : X1) - mx;
+    double ys = fmin(fmax(my - qb * dx / qc, Y0), Y1), dy = ys - my;
+    q = qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy;
+    *scale = fabs(qa * dx * dx) + fabs(2 * qb * dx * dy) + fabs(qc * dy * dy);
+  }
+  if (!in_y) {
+    double dy = (my < Y0 ? Y0 : Y1) - my;
+    double xs = fmin(fmax(mx - qb * dy / qa, X0), X1), dx = xs - mx;
+    double q2 = qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy;
+    if (q2 < q) {
+      q = q2;
+      *scale = fabs(qa * dx * dx) + fabs(2 * qb * dx * dy) + fabs(qc * dy * dy);
+    }
+  }
+  return q;
+}
+
+static int near_integer(double v, double m) { return fabs(v - nearbyint(v)) <= m; }
+
+/* Marks tile t of the W x H image (tx, ty in range) in the tile mask. */
+static void mark_tile(uint8_t *tmask, int tiles_x, int tiles_y, int tx, int ty) {
+  if (tx < 0 || ty < 0 || tx >= tiles_x || ty >= tiles_y) return;
+#pragma omp atomic write
+  tmask[(size_t)ty * tiles_x + tx] = 1;
+}
+
+/* Near-threshold decisions of Gaussians with planar double attributes
+ * gd[14][stride], each within eb[14][stride] of what the HIP path decodes;
+ * vis / rect are the oracle's canonical projection of the same Gaussians.
+ * For each Gaussian, the quantities behind its decisions are evaluated in
+ * double and their change under eb is propagated to first order (one
+ * perturbation of +-eb per attribute, the changes added, times 1.5); a
+ * decision is near its threshold when the quantity lies within that change
+ * plus slack (relative FP32 evaluation slack) of it.  Tiles whose list or
+ * pixels such a decision can change are marked in tmask [tiles_y][tiles_x]:
+ *   bit 0 (flags): a whole-Gaussian cull (opacity > 0, zc > z_near,
+ *          det > 0) is near its threshold: every tile of the 3-sigma
+ *          square, one tile wider on each side, is marked;
+ *   bit 1: the tile test of a tile of the rectangle is near q = 9: that tile;
+ *   bit 3: the rectangle (ceil of 3 sqrt(lambda), floor of (p -+ r) / 16) is
+ *          near a threshold: the tiles on its border, one tile either way,
+ *          where the tile test does not reject the Gaussian with margin.
+ * zdepth[i], zmargin[i]: camera depth and its margin, for the depth-order
+ * check the caller makes over the visible Gaussians (the depth is one
+ * canonical FP32 sequence on the mean, which both sides form with one
+ * rounding of x_v + O l, so its margin comes from the mean's bound alone).
+ * Returns the number of flagged Gaussians. */
+ORC_API int64_t orc_fragile(int64_t n, int64_t stride, const double *gd, const double *eb,
+                            const float *camf, int W, int H, const float *prmf,
+                            const uint8_t *vis, const int32_t *rect, double slack,
+                            uint8_t *flags, double *zdepth, double *zmargin, uint8_t *tmask) {
+  cam_t k = load_cam(camf, W, H);
+  prm_t pp = load_prm(prmf);
+  const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+  int64_t cnt = 0;
+#pragma omp parallel for reduction(+ : cnt) schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    double g[14], v0[DQ_N], e[DQ_N] = {0};
+    for (int f = 0; f < 14; ++f) g[f] = gd[f * stride + i];
+    decision_values(&k, &pp, g, v0);
+    for (int f = 0; f < 11; ++f) {  /* colour takes no decision */
+      double h = eb[f * stride + i];
+      if (!(h > 0)) continue;
+      double best[DQ_N] = {0};
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        double gp[14], v[DQ_N];
+        memcpy(gp, g, sizeof gp);
+        gp[f] += sgn * h;
+        decision_values(&k, &pp, gp, v);
+        for (int q = 0; q < DQ_N; ++q) best[q] = fmax(best[q], fabs(v[q] - v0[q]));
+      }
+      for (int q = 0; q < DQ_N; ++q) e[q] += best[q];
+    }
+    /* first order, with half again for the second-order terms */
+    for (int q = 0; q < DQ_N; ++q) e[q] *= 1.5;
+    uint8_t fl = 0;
+    const double r3 = v0[DQ_R3], r = ceil(r3), px = v0[DQ_PX], py = v0[DQ_PY];
+    const double in5[5] = {px, py, v0[DQ_QA], v0[DQ_QB], v0[DQ_QC]};
+    const double e5[5] = {e[DQ_PX], e[DQ_PY], e[DQ_QA], e[DQ_QB], e[DQ_QC]};
+    /* q_min of tile (tx, ty) and its margin */
+#define QMIN_MARGIN(tx, ty, q0, mq)                                                          \
+    do {                                                                                       \
+      double sc0_, eq_ = 0;                                                                    \
+      q0 = tile_qmin_d(in5[0], in5[1], in5[2], in5[3], in5[4], tx, ty, W, H, &sc0_);           \
+      for (int a_ = 0; a_ < 5; ++a_) {                                                         \
+        double b_ = 0;                                                                         \
+        for (int s_ = -1; s_ <= 1; s_ += 2) {                                                  \
+          double p_[5], sc1_;                                                                  \
+          memcpy(p_, in5, sizeof p_);                                                          \
+          p_[a_] += s_ * e5[a_];                                                               \
+          b_ = fmax(b_, fabs(tile_qmin_d(p_[0], p_[1], p_[2], p_[3], p_[4], tx, ty, W, H,      \
+                                         &sc1_) - q0));                                        \
+        }                                                                                      \
+        eq_ += b_;                                                                             \
+      }                                                                                        \
+      mq = eq_ + slack * (9.0 + sc0_);                                                         \
+    } while (0)
+    const int cull_near =
+        fabs(v0[DQ_OP]) <= e[DQ_OP] + slack * 1e-2 ||
+        fabs(v0[DQ_Z] - k.z_near) <= e[DQ_Z] + slack * fabs(v0[DQ_Z]) ||
+        fabs(v0[DQ_DET]) <= e[DQ_DET] + slack * v0[DQ_DETSCALE];
+    if (cull_near) {
+      fl |= 1;
+      if (isfinite(px) && isfinite(py) && isfinite(r)) {
+        int x0 = (int)fmax(floor((px - r) / 16.0) - 1, -1), x1 = (int)fmin(floor((px + r) / 16.0) + 1, tiles_x);
+        int y0 = (int)fmax(floor((py - r) / 16.0) - 1, -1), y1 = (int)fmin(floor((py + r) / 16.0) + 1, tiles_y);
+        for (int ty = y0; ty <= y1; ++ty)
+          for (int tx = x0; tx <= x1; ++tx) mark_tile(tmask, tiles_x, tiles_y, tx, ty);
+      } else {
+        for (int t = 0; t < tiles_x * tiles_y; ++t) mark_tile(tmask, tiles_x, tiles_y, t % tiles_x, t / tiles_x);
+      }
+    } else if (v0[DQ_Z] > k.z_near && v0[DQ_DET] > 0 && v0[DQ_OP] > 0) {
+      /* the rectangle: the possible radii ceil(3 sqrt(lambda) -+ margin) and
+       * 2D means give a range for each edge x0 = floor((px - r) / 16),
+       * x1 = floor((px + r) / 16) + 1 (rows alike); the columns (rows)
+       * between an edge's extremes are candidates on one side only.  Such a
+       * tile changes the list only where the tile test may keep the
+       * Gaussian. */
+      const double mr = e[DQ_R3] + slack * r3;
+      const double rlo = ceil(r3 - mr), rhi = ceil(r3 + mr);
+      const double ex = e[DQ_PX] + slack * (fabs(px) + rhi), ey = e[DQ_PY] + slack * (fabs(py) + rhi);
+      const int x0a = (int)floor((px - ex - rhi) / 16.0), x0b = (int)floor((px + ex - rlo) / 16.0);
+      const int x1a = (int)floor((px - ex + rlo) / 16.0) + 1, x1b = (int)floor((px + ex + rhi) / 16.0) + 1;
+      const int y0a = (int)floor((py - ey - rhi) / 16.0), y0b = (int)floor((py + ey - rlo) / 16.0);
+      const int y1a = (int)floor((py - ey + rlo) / 16.0) + 1, y1b = (int)floor((py + ey + rhi) / 16.0) + 1;
+      if (x0a != x0b || x1a != x1b || y0a != y0b || y1a != y1b) {
+        for (int ty = (y0a > 0 ? y0a : 0); ty < y1b && ty < tiles_y; ++ty)
+          for (int tx = (x0a > 0 ? x0a : 0); tx < x1b && tx < tiles_x; ++tx) {
+            const int sure = tx >= x0b && tx < x1a && ty >= y0b && ty < y1a;
+            if (sure) continue;  /* a candidate whichever way the edges go */
+            double q0, mq;
+            QMIN_MARGIN(tx, ty, q0, mq);
+            if (q0 <= 9.0 + mq) {
+              fl |= 8;
+              mark_tile(tmask, tiles_x, tiles_y, tx, ty);
+            }
+          }
+      }
+      if (vis[i]) {
+        const int32_t *rc = rect + 4 * i;
+        for (int ty = rc[1]; ty < rc[3]; ++ty)
+          for (int tx = rc[0]; tx < rc[2]; ++tx) {
+            double q0, mq;
+            QMIN_MARGIN(tx, ty, q0, mq);
+            if (fabs(q0 - 9.0) <= mq) {
+              fl |= 2;
+              mark_tile(tmask, tiles_x, tiles_y, tx, ty);
+            }
+          }
+      }
+    }
+#undef QMIN_MARGIN
+    flags[i] = fl;
+    zdepth[i] = v0[DQ_Z];
+    zmargin[i] = e[DQ_Z];
+    cnt += fl != 0;
+  }
+  return cnt;
+}
+
+/* ======================================================================
  * Tile binning and depth ordering
  * ====================================================================== */
 
@@ -587,13 +869,13 @@ static uint32_t fbits(float f) {
 /* Count the (tile, Gaussian) pairs: tiles of each visible Gaussian's
  * rectangle that its 3-sigma ellipse meets. */
 ORC_API int64_t orc_count_pairs(int64_t n, const uint8_t *vis, const int32_t *rect,
-                                const float *cf) {
+                                const float *cf, int W, int H) {
   int64_t p = 0;
   for (int64_t i = 0; i < n; ++i) {
     if (!vis[i]) continue;
     const int32_t *r = rect + 4 * i;
     for (int y = r[1]; y < r[3]; ++y)
-      for (int x = r[0]; x < r[2]; ++x) p += tile_meets_ellipse_f(cf + 5 * i, x, y);
+      for (int x = r[0]; x < r[2]; ++x) p += tile_meets_ellipse_f(cf + 5 * i, x, y, W, H);
   }
   return p;
 }
@@ -606,7 +888,9 @@ ORC_API int64_t orc_count_rect_pairs(int64_t n, const uint8_t *vis, const int32_
   return p;
 }
 
-ORC_API int orc_tile_test(const float *cf, int tx, int ty) { return tile_meets_ellipse_f(cf, tx, ty); }
+ORC_API int orc_tile_test(const float *cf, int tx, int ty, int W, int H) {
+  return tile_meets_ellipse_f(cf, tx, ty, W, H);
+}
 
 /* All (tile, Gaussian) pairs (tiles of the rectangle that the 3-sigma
  * ellipse meets) ordered by tile, then depth (positive float bits order like
@@ -616,7 +900,7 @@ ORC_API int64_t orc_bin_sort(int64_t n, const uint8_t *vis, const int32_t *rect,
                              const float *cf, const float *depth, int W, int H, uint32_t *tile_of,
                              uint32_t *gid_of, uint32_t *ranges) {
   int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
-  int64_t P = orc_count_pairs(n, vis, rect, cf);
+  int64_t P = orc_count_pairs(n, vis, rect, cf, W, H);
   pair_t *pr = (pair_t *)malloc(sizeof(pair_t) * (size_t)(P > 0 ? P : 1));
   int64_t q = 0;
   for (int64_t i = 0; i < n; ++i) {
@@ -624,7 +908,7 @@ ORC_API int64_t orc_bin_sort(int64_t n, const uint8_t *vis, const int32_t *rect,
     const int32_t *r = rect + 4 * i;
     for (int y = r[1]; y < r[3]; ++y)
       for (int x = r[0]; x < r[2]; ++x) {
-        if (!tile_meets_ellipse_f(cf + 5 * i, x, y)) continue;
+        if (!tile_meets_ellipse_f(cf + 5 * i, x, y, W, H)) continue;
         pr[q].tile = (uint32_t)(y * tiles_x + x);
         pr[q].dkey = fbits(depth[i]);
         pr[q].gid = (uint32_t)i;
@@ -734,7 +1018,7 @@ ORC_API void orc_render_bruteforce(int64_t n, const uint8_t *vis, const int32_t 
       for (int64_t i = 0; i < n; ++i) {
         const int32_t *r = rect + 4 * i;
         if (vis[i] && tx >= r[0] && tx < r[2] && ty >= r[1] && ty < r[3] &&
-            tile_meets_ellipse_f(cf + 5 * i, tx, ty)) {
+            tile_meets_ellipse_f(cf + 5 * i, tx, ty, W, H)) {
           buf[m].dkey = fbits(depth[i]);
           buf[m].gid = (uint32_t)i;
           ++m;

@@ -50,6 +50,40 @@ def lib():
     return _lib
 
 
+def source() -> str:
+    """The oracle's C source text."""
+    with open(_SRC) as f:
+        return f.read()
+
+
+class variant:
+    """Context manager for tests that plant a mistake in the oracle: compiles
+    the given C source text (normally source() with one edit) into `dirname`
+    and routes this module's calls to it until the block ends."""
+
+    def __init__(self, src_text: str, dirname: str, tag: str = "variant"):
+        self.src = os.path.join(dirname, f"octgs_oracle_{tag}.c")
+        self.so = os.path.join(dirname, f"liboctgs_oracle_{tag}.so")
+        with open(self.src, "w") as f:
+            f.write(src_text)
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", self.so, self.src,
+                               "-lm"])
+
+    def __enter__(self):
+        global _lib
+        self._saved = lib()
+        v = ctypes.CDLL(self.so)
+        _declare(v)
+        _lib = v
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int
@@ -59,10 +93,10 @@ def _declare(L):
     L.orc_lod_thr2.argtypes = [_i64, _p, _p, ctypes.c_float, _p]
     L.orc_bound_radius.argtypes = [_i64, _i32, _p, _p, _p, _p]
     L.orc_bound_radius_explicit.argtypes = [_i64, _i32, _p, _p, _p, _p]
-    L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _i32, _p, _i32, _i32, _p]
+    L.orc_select_fp32.argtypes = [_i64, _p, _p, _p, _i32, _p, _i32, _i32, _p, _p]
     L.orc_select_fp32.restype = _i64
     L.orc_select_eq7.argtypes = [_i64, _p, _p, _p, ctypes.c_float, _i32, _p, _i32, _p, _i32, _i32,
-                                 _p]
+                                 _p, _p]
     L.orc_select_eq7.restype = _i64
     L.orc_decode.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, _p,
                              ctypes.c_float, _i32, _p, _p, _i32, ctypes.c_float, _p]
@@ -71,11 +105,14 @@ def _declare(L):
     L.orc_lod_blend_factor.restype = ctypes.c_double
     L.orc_project.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _p, _p, _p]
     L.orc_project.restype = _i64
-    L.orc_count_pairs.argtypes = [_i64, _p, _p, _p]
+    L.orc_count_pairs.argtypes = [_i64, _p, _p, _p, _i32, _i32]
+    L.orc_fragile.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, ctypes.c_double,
+                              _p, _p, _p, _p]
+    L.orc_fragile.restype = _i64
     L.orc_count_pairs.restype = _i64
     L.orc_count_rect_pairs.argtypes = [_i64, _p, _p]
     L.orc_count_rect_pairs.restype = _i64
-    L.orc_tile_test.argtypes = [_p, _i32, _i32]
+    L.orc_tile_test.argtypes = [_p, _i32, _i32, _i32, _i32]
     L.orc_tile_test.restype = _i32
     L.orc_bin_sort.argtypes = [_i64, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]
     L.orc_bin_sort.restype = _i64
@@ -153,24 +190,28 @@ def bound_radius_explicit(pos, mean, log_scale) -> np.ndarray:
     return out
 
 
-def select_mask(pos, thr2, rho, cam, blend=False) -> np.ndarray:
+def select_mask(pos, thr2, rho, cam, blend=False, prm=None) -> np.ndarray:
     """Canonical FP32 selection mask; blend also takes level L_hat + 1
-    (LOD transition blending)."""
+    (LOD transition blending).  The visibility test is conservative for a
+    render with raster parameters prm (default params_array())."""
     pos = _c(pos, np.float32)
     mask = np.empty(len(pos), np.uint8)
+    prm = params_array() if prm is None else prm
     lib().orc_select_fp32(len(pos), _ptr(pos), _ptr(_c(thr2, np.float32)),
                           _ptr(_c(rho, np.float32)), int(blend), _ptr(cam_array(cam)),
-                          cam.width, cam.height, _ptr(mask))
+                          cam.width, cam.height, _ptr(_c(prm, np.float32)), _ptr(mask))
     return mask
 
 
-def select_eq7_mask(pos, level, lod_bias, d_max, n_levels, rho, cam, blend=False) -> np.ndarray:
+def select_eq7_mask(pos, level, lod_bias, d_max, n_levels, rho, cam, blend=False,
+                    prm=None) -> np.ndarray:
     pos = _c(pos, np.float32)
     mask = np.empty(len(pos), np.uint8)
+    prm = params_array() if prm is None else prm
     lib().orc_select_eq7(len(pos), _ptr(pos), _ptr(_c(level, np.uint8)),
                          _ptr(_c(lod_bias, np.float32)), float(d_max), int(n_levels),
                          _ptr(_c(rho, np.float32)), int(blend), _ptr(cam_array(cam)), cam.width,
-                         cam.height, _ptr(mask))
+                         cam.height, _ptr(_c(prm, np.float32)), _ptr(mask))
     return mask
 
 
@@ -185,11 +226,11 @@ def scene_thresholds(scene):
             bound_radius(scene.offsets, scene.offset_scale, scene.base_scale))
 
 
-def select(scene, cam, thr2=None, rho=None, blend=False) -> np.ndarray:
+def select(scene, cam, thr2=None, rho=None, blend=False, prm=None) -> np.ndarray:
     """Ascending indices of the anchors selected for cam (canonical FP32 rule)."""
     if thr2 is None or rho is None:
         thr2, rho = scene_thresholds(scene)
-    return np.flatnonzero(select_mask(scene.pos, thr2, rho, cam, blend)).astype(np.int64)
+    return np.flatnonzero(select_mask(scene.pos, thr2, rho, cam, blend, prm)).astype(np.int64)
 
 
 # ----------------------------------------------------------------------------
@@ -238,9 +279,11 @@ def project(gf: np.ndarray, cam, prm: np.ndarray, gd: Optional[np.ndarray] = Non
     return dict(vis=vis, rect=rect, depth=depth, proj=proj, cf=cf, n_visible=int(cnt))
 
 
-def tile_test(cf_row, tx, ty) -> bool:
-    """Canonical FP32 tile test of one Gaussian (cf_row = mx, my, qa, qb, qc)."""
-    return bool(lib().orc_tile_test(_ptr(_c(cf_row, np.float32)), int(tx), int(ty)))
+def tile_test(cf_row, tx, ty, W, H) -> bool:
+    """Canonical FP32 tile test of one Gaussian (cf_row = mx, my, qa, qb, qc)
+    against tile (tx, ty) of a W x H image."""
+    return bool(lib().orc_tile_test(_ptr(_c(cf_row, np.float32)), int(tx), int(ty), int(W),
+                                    int(H)))
 
 
 def count_rect_pairs(pj) -> int:
@@ -249,7 +292,8 @@ def count_rect_pairs(pj) -> int:
 
 def bin_sort(pj: Dict[str, np.ndarray], cam) -> Dict[str, np.ndarray]:
     n = len(pj["vis"])
-    P = int(lib().orc_count_pairs(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["cf"])))
+    P = int(lib().orc_count_pairs(n, _ptr(pj["vis"]), _ptr(pj["rect"]), _ptr(pj["cf"]),
+                                  cam.width, cam.height))
     tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
     tile_of = np.empty(max(P, 1), np.uint32)
     gid_of = np.empty(max(P, 1), np.uint32)
@@ -293,10 +337,70 @@ def rasterize(gf, cam, prm, gd=None, weights=False):
     return out
 
 
+def fragile(out, cam, prm, eb, slack=2e-6) -> Dict[str, np.ndarray]:
+    """Tiles of a render (`out` from rasterize or render, its double
+    Gaussians in out["gauss"] or out["gd"]) whose lists or pixels a decision
+    near its threshold can change, when the Gaussians are decoded in FP32
+    within eb[14][n] of the oracle's values (orc_fragile in the C source
+    explains the margins).  Also a depth-order check: visible Gaussians
+    whose depth intervals (depth -+ margin) overlap a neighbour's mark every
+    tile they are listed in.  Returns flags per Gaussian (bits: 1 cull,
+    2 tile test, 4 depth order, 8 rectangle), `tiles` [tiles_y][tiles_x]
+    bool, the pixel mask `near_flagged` of those tiles, and `near_t_min`:
+    pixels whose transmittance after the last entry, or before it where the
+    pixel stopped, is within 1e-3 relative of t_min, where the stop decision
+    can flip."""
+    gd = _c(out["gauss"] if "gauss" in out else out["gd"], np.float64)
+    n = gd.shape[1]
+    pj, bs = out["pj"], out["bs"]
+    W, H = cam.width, cam.height
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    flags = np.zeros(n, np.uint8)
+    z = np.zeros(n)
+    zm = np.zeros(n)
+    tmask = np.zeros((ty, tx), np.uint8)
+    lib().orc_fragile(n, n, _ptr(gd), _ptr(_c(eb, np.float64)), _ptr(cam_array(cam)), W, H,
+                      _ptr(_c(prm, np.float32)), _ptr(pj["vis"]), _ptr(pj["rect"]), float(slack),
+                      _ptr(flags), _ptr(z), _ptr(zm), _ptr(tmask))
+    tiles = tmask.astype(bool)
+    # depth order: visible Gaussians whose depth intervals overlap a neighbour's
+    vis = np.flatnonzero(pj["vis"])
+    order = vis[np.argsort(z[vis], kind="stable")]
+    if len(order) > 1:
+        zs, ms = z[order], zm[order]
+        close = (zs[1:] - zs[:-1]) <= (ms[1:] + ms[:-1])
+        hit = np.zeros(len(order), bool)
+        hit[1:] |= close
+        hit[:-1] |= close
+        flags[order[hit]] |= 4
+        if hit.any():
+            dep = np.zeros(n, bool)
+            dep[order[hit]] = True
+            listed = bs["tile_of"][dep[bs["gid_of"]]]
+            tiles.reshape(-1)[listed] = True
+    near_flagged = np.repeat(np.repeat(tiles, 16, 0), 16, 1)[:H, :W]
+    # the stop decision: T after the last entry, and before it for pixels
+    # that stopped, within 1e-3 relative of t_min
+    t_min = float(np.float32(prm[2]))
+    T = out["T"]
+    near_t = np.abs(T - t_min) <= 1e-3 * t_min
+    ys, xs = np.nonzero((T < t_min) & (out["last"] > 0))
+    if len(ys):
+        e = bs["ranges"][(ys // 16) * tx + xs // 16, 0].astype(np.int64) + out["last"][ys, xs] - 1
+        q = pj["proj"][bs["gid_of"][e]]
+        dx, dy = xs + 0.5 - q[:, 0], ys + 0.5 - q[:, 1]
+        a = np.minimum(float(np.float32(prm[0])),
+                       q[:, 5] * np.exp(-0.5 * (q[:, 2] * dx * dx + q[:, 4] * dy * dy) - q[:, 3] * dx * dy))
+        T_prev = T[ys, xs] / np.maximum(1.0 - a, 1e-300)
+        near_t[ys, xs] |= np.abs(T_prev - t_min) <= 1e-3 * t_min
+    return dict(flags=flags, tiles=tiles, near_flagged=near_flagged, near_t_min=near_t,
+                n_flagged=int(np.count_nonzero(flags)))
+
+
 def render(scene, cam, prm, thr2=None, rho=None, weights=False, blend=False):
     """Full path for one view: select, decode, rasterize (blend: LOD
     transition blending)."""
-    idx = select(scene, cam, thr2, rho, blend)
+    idx = select(scene, cam, thr2, rho, blend, prm)
     gd = decode(scene, idx, cam, blend)
     out = rasterize(gd.astype(np.float32), cam, prm, gd=gd, weights=weights)
     out.update(idx=idx, gauss=gd)

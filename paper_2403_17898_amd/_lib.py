@@ -20,6 +20,7 @@ OCTGS_RASTER_STAGES = 5
 OCTGS_SELECT_NOALLOC_MAX_ANCHORS = 1 << 23
 OCTGS_RASTER_TRAIN = 1
 OCTGS_RASTER_TILE_ORDER = 2
+OCTGS_STATUS_PAIR_OVERFLOW, OCTGS_STATUS_SYNC_ERROR, OCTGS_STATUS_TRUNCATED = 1, 2, 4
 RASTER_STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
 
 _p = ctypes.c_void_p
@@ -94,12 +95,12 @@ class RasterStats(ctypes.Structure):
 
 # (name, restype, argtypes); kept in the order of include/octgs.h
 SIGNATURES = [
-    ("octgs_prepare_anchors", _i32, [ctypes.POINTER(Anchors), _p, _p, _p]),
+    ("octgs_prepare_anchors", _i32, [ctypes.POINTER(Anchors), _p, _p, _p, _p]),
     ("octgs_select_workspace_bytes", ctypes.c_size_t, [_i64]),
-    ("octgs_select_lod", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p, _p, _p,
-                                ctypes.c_size_t, _p]),
-    ("octgs_select_lod_noalloc", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera), _p,
-                                        _p, _p]),
+    ("octgs_select_lod", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera),
+                                ctypes.POINTER(RasterParams), _p, _p, _p, ctypes.c_size_t, _p]),
+    ("octgs_select_lod_noalloc", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Camera),
+                                        ctypes.POINTER(RasterParams), _p, _p, _p]),
     ("octgs_decode_workspace_bytes", ctypes.c_size_t, [_i32]),
     ("octgs_decode", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp), ctypes.POINTER(Camera),
                             _p, _p, _i32, ctypes.POINTER(Gaussians), _p, ctypes.c_size_t, _p]),
@@ -133,7 +134,7 @@ SIGNATURES = [
     ("octgs_skip_train_grad", _i32, [ctypes.POINTER(SkipNet), _p, _p, _i32, _f,
                                      ctypes.POINTER(SkipNet), _p, _p, ctypes.c_size_t, _p]),
     ("octgs_prepare_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit), _p, _p,
-                                      _p]),
+                                      _p, _p]),
     ("octgs_decode_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit),
                                      ctypes.POINTER(Camera), _p, _p, _i32,
                                      ctypes.POINTER(Gaussians), _p]),
@@ -145,6 +146,7 @@ SIGNATURES = [
                                         ctypes.POINTER(DensifyStats), _p]),
     ("octgs_densify_decide", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(DensifyStats),
                                     ctypes.POINTER(DensifyParams), _p, _p, _p, _p, _p]),
+    ("octgs_frame_status", _i32, [_p, _p, _i32, _i64, _p, _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

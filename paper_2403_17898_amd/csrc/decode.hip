@@ -40,12 +40,6 @@ constexpr int kXS = kInPad + 4;    // LDS row strides (elements)
 constexpr int kHS = kMaxN1 + 4;
 constexpr int kYS = kMaxNO + 1;
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
 

@@ -429,7 +429,7 @@ using namespace octgs;
 extern "C" {
 
 int octgs_prepare_explicit(const octgs_anchors *a, const octgs_explicit *e, float *thr2,
-                           float *bound_r, octgs_stream stream) {
+                           float *bound_r, uint16_t *sh_bf16, octgs_stream stream) {
   if (!a || !e) return OCTGS_EINVAL;
   if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
   if (a->k < 1 || a->k > kMaxK) return OCTGS_EUNSUPPORTED;
@@ -437,10 +437,14 @@ int octgs_prepare_explicit(const octgs_anchors *a, const octgs_explicit *e, floa
   if (!thr2 || !bound_r || !a->level || !a->lod_bias || !a->pos || !e->mean || !e->log_scale)
     return OCTGS_EINVAL;
   if (!(a->d_max > 0.0f)) return OCTGS_EINVAL;
+  if (sh_bf16 && (!e->sh || e->sh_degree < 0 || e->sh_degree > 3)) return OCTGS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
   const int grid = (int)((a->n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_prepare_explicit, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a->n,
+  hipLaunchKernelGGL(k_prepare_explicit, dim3(grid), dim3(kBlock), 0, s, a->n,
                      a->k, a->d_max, a->level, a->lod_bias, a->pos, e->mean, e->log_scale, thr2,
                      bound_r);
+  const int64_t nsh = a->n * a->k * (int64_t)(e->sh_degree + 1) * (e->sh_degree + 1) * 3;
+  if (sh_bf16 && launch_round_bf16(e->sh, sh_bf16, nsh, s) != hipSuccess) return OCTGS_EHIP;
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

@@ -25,6 +25,14 @@ constexpr int kGaussFields = 14;
 constexpr int kProjVec = 3;          // float4 records per projected Gaussian
 constexpr int kMaxK = 16;
 
+// FP32 -> BF16 bit pattern, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // ---------------------------------------------------------------------------
 // wave64 helpers
 // ---------------------------------------------------------------------------
@@ -246,6 +254,7 @@ struct RasterWs {
   float *gpair;           // [pcap][9] backward: the same per (tile, Gaussian) pair, emission order
   int64_t gcap, pcap;
   int32_t tiles_x, tiles_y, nblk_g, nruns, tile_passes;
+  float xmax, ymax;            // last pixel centre of the image: W - 0.5, H - 0.5
   size_t lb_words, lbt_words;  // look-back words to clear before the sorts
   size_t bytes;
 };
@@ -261,6 +270,10 @@ constexpr int kEmitThreads = 1024;  // pair emission: threads per block
 constexpr int kEmitRun = 8192;      // candidate pairs per block of the emission
 
 RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_t H);
+
+// dst[i] = BF16 bits of src[i] rounded to nearest even, i < count (device
+// arrays); enqueues one kernel on s.
+hipError_t launch_round_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
 int tile_sort_passes(int ntiles);
 
 constexpr float kLog2e = 1.4426950408889634f;

@@ -133,20 +133,23 @@ __device__ __forceinline__ bool project_decide(const Cam &k, float dil, float jc
 
 // Tile test, canonical FP32: does the 3-sigma ellipse q(p) <= 9,
 // q = qa dx^2 + 2 qb dx dy + qc dy^2 around (mx, my), meet the box of the
-// tile's pixel centres [16 tx + 0.5, 16 tx + 15.5] x [16 ty + 0.5, 16 ty + 15.5]?
-// The convex quadratic's minimum over the box is 0 with the mean inside;
-// otherwise it lies on an edge facing the mean, at the 1D minimiser clamped
-// to the edge:
-//   X0 = (float)(16 tx) + 0.5, X1 = X0 + 15 (Y alike)
+// tile's pixel centres inside the image, [16 tx + 0.5, min(16 tx + 15.5,
+// W - 0.5)] x [16 ty + 0.5, min(16 ty + 15.5, H - 0.5)]?  (Pixels of a
+// partial edge tile past the image are not drawn, so they do not list a
+// Gaussian.)  The convex quadratic's minimum over the box is 0 with the mean
+// inside; otherwise it lies on an edge facing the mean, at the 1D minimiser
+// clamped to the edge:
+//   X0 = (float)(16 tx) + 0.5, X1 = fminf(X0 + 15, xmax) (Y alike)
 //   mean's x outside [X0, X1]: xe = nearer of X0, X1; dx = xe - mx;
 //     ys = min(max(my - (qb * dx) / qc, Y0), Y1); dy = ys - my;
 //     q1 = fmaf(qa * dx, dx, fmaf(2 * qb * dx, dy, qc * dy * dy))
 //   mean's y outside [Y0, Y1]: the same with the roles of x and y swapped
 //   keep iff min(q1, q2) <= 9.
 __device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa, float qb, float qc,
-                                                   uint32_t tx, uint32_t ty) {
-  const float X0 = (float)(16u * tx) + 0.5f, X1 = X0 + 15.0f;
-  const float Y0 = (float)(16u * ty) + 0.5f, Y1 = Y0 + 15.0f;
+                                                   uint32_t tx, uint32_t ty, float xmax,
+                                                   float ymax) {
+  const float X0 = (float)(16u * tx) + 0.5f, X1 = fminf(X0 + 15.0f, xmax);
+  const float Y0 = (float)(16u * ty) + 0.5f, Y1 = fminf(Y0 + 15.0f, ymax);
   const bool in_x = !(mx < X0) && !(mx > X1), in_y = !(my < Y0) && !(my > Y1);
   float q = INFINITY;
   if (!in_x) {
@@ -521,7 +524,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
     }
     const uint32_t ty = y0 + row, tx = x0 + (loc[k] - row * wdt);
     const bool keep = p0 + k * kEmitThreads + t < p1 &&
-                      tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty);
+                      tile_meets_ellipse(pa[k].x, pa[k].y, pc[k].y, pc[k].z, pc[k].w, tx, ty,
+                                         ws.xmax, ws.ymax);
     key[k] = ty * (uint32_t)ws.tiles_x + tx;
     const uint64_t m = ballot(keep);
     if (l == 0) gmask[k * kW + w] = m;
@@ -855,6 +859,8 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   const int64_t g = std::max<int64_t>(gcap, 1), pc = std::max<int64_t>(pcap, 1);
   ws.gcap = g;
   ws.pcap = pc;
+  ws.xmax = (float)W - 0.5f;
+  ws.ymax = (float)H - 0.5f;
   ws.tiles_x = (W + kTile - 1) / kTile;
   ws.tiles_y = (H + kTile - 1) / kTile;
   ws.nblk_g = (int)((g + kChunk - 1) / kChunk);
@@ -895,6 +901,17 @@ int tile_sort_passes(int ntiles) {
   return (bits + 7) / 8;
 }
 
+// One thread: OR a frame's device-detected conditions into a status word.
+__global__ void k_frame_status(const RasterHeader *__restrict__ hdr,
+                               const uint32_t *__restrict__ count, int k, int64_t gcap,
+                               uint32_t *__restrict__ status) {
+  uint32_t f = 0;
+  if (hdr->pair_overflow) f |= OCTGS_STATUS_PAIR_OVERFLOW;
+  if (hdr->sync_error) f |= OCTGS_STATUS_SYNC_ERROR;
+  if (count && (uint64_t)*count * (uint64_t)k > (uint64_t)gcap) f |= OCTGS_STATUS_TRUNCATED;
+  if (f) atomicOr(status, f);
+}
+
 }  // namespace octgs
 
 using namespace octgs;
@@ -918,6 +935,9 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   if (pair_capacity < 0 || pair_capacity >= (int64_t(1) << 30) - 1) return OCTGS_EINVAL;
   if (!image_tiles_ok(cam->width, cam->height)) return OCTGS_EINVAL;
   if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return OCTGS_EINVAL;
+  // z_near > 0 keeps every listed depth positive (the depth keys are float bits)
+  if (!(cam->z_near > 0.0f)) return OCTGS_EINVAL;
+  if (!(p->dilation >= 0.0f) || !(p->jac_clamp > 0.0f)) return OCTGS_EINVAL;
   if (ws_bytes < octgs_raster_workspace_bytes(g->capacity, pair_capacity, cam->width, cam->height))
     return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
@@ -991,6 +1011,14 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
     hipLaunchKernelGGL(k_composite<false>, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
                        dim3(kFwdThreads), 0, s, ca);
   mark(9);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+int octgs_frame_status(const void *ws, const uint32_t *count, int32_t k, int64_t gauss_capacity,
+                       uint32_t *status, octgs_stream stream) {
+  if (!ws || !status || k < 1 || gauss_capacity < 0) return OCTGS_EINVAL;
+  hipLaunchKernelGGL(k_frame_status, dim3(1), dim3(1), 0, (hipStream_t)stream,
+                     (const RasterHeader *)ws, count, k, gauss_capacity, status);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

@@ -12,8 +12,15 @@
 // fmaf, no contraction - the library is built with -ffp-contract=off):
 //   d = p - C;  dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));  lod = dd * s2 <= thr2
 //   (xc, yc, zc) rows fmaf(R0, d0, fmaf(R1, d1, R2 * d2))
-//   tan of each side plane = edge offset / focal; sec = sqrtf(fmaf(t, t, 1))
-//   visible = zc + rho >= z_near and, per side, +-x (or +-y) <= fmaf(tan, zc, rho * sec)
+//   visibility, conservative for a render with the given raster parameters
+//   (a sphere is culled only if none of the Gaussians inside it can reach a
+//   pixel centre of the image under the dilated EWA projection):
+//   pad = 3 sqrtf(dilation); side-plane slopes tl = (cx + pad) / fx,
+//   tr = ((W - cx) + pad) / fx, tt = (cy + pad) / fy, tb = ((H - cy) + pad) / fy;
+//   the projection's Jacobian clamp lx = jac_clamp ((0.5 W) / fx), ly alike;
+//   per side m = sqrtf(fmaf(t, t, 1)) + fabsf(l - t) (plane-normal length plus
+//   the largest slope change of the clamped Jacobian across the Gaussian);
+//   visible = zc + rho >= z_near and, per side, +-x (or +-y) <= fmaf(t, zc, rho * m)
 #include "octgs_internal.h"
 
 #include <mutex>
@@ -51,20 +58,37 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_ma
   rho[j] = __builtin_fmaf(3.0f, bmax, m);
 }
 
+// BF16 copy of an FP32 array, four elements per thread (8-byte stores).
+__global__ __launch_bounds__(kBlock) void k_round_bf16(const float *__restrict__ src,
+                                                       uint16_t *__restrict__ dst, int64_t count) {
+  const int64_t i = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+  if (i + 4 <= count && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0) {
+    const float4 v = *(const float4 *)(src + i);
+    ushort4 o;
+    o.x = f2bf(v.x); o.y = f2bf(v.y); o.z = f2bf(v.z); o.w = f2bf(v.w);
+    *(ushort4 *)(dst + i) = o;
+  } else {
+    for (int64_t j = i; j < min(i + 4, count); ++j) dst[j] = f2bf(src[j]);
+  }
+}
+
 struct Frustum {
-  float tl, tr, tt, tb, sl, sr, st, sb;
+  float tl, tr, tt, tb, ml, mr, mt, mb;
 };
 
-__device__ __forceinline__ Frustum frustum(const octgs_camera &c) {
+__device__ __forceinline__ Frustum frustum(const octgs_camera &c, float dilation, float jac_clamp) {
   Frustum f;
-  f.tl = c.cx / c.fx;
-  f.tr = ((float)c.width - c.cx) / c.fx;
-  f.tt = c.cy / c.fy;
-  f.tb = ((float)c.height - c.cy) / c.fy;
-  f.sl = sqrtf(__builtin_fmaf(f.tl, f.tl, 1.0f));
-  f.sr = sqrtf(__builtin_fmaf(f.tr, f.tr, 1.0f));
-  f.st = sqrtf(__builtin_fmaf(f.tt, f.tt, 1.0f));
-  f.sb = sqrtf(__builtin_fmaf(f.tb, f.tb, 1.0f));
+  const float pad = 3.0f * sqrtf(dilation);
+  f.tl = (c.cx + pad) / c.fx;
+  f.tr = (((float)c.width - c.cx) + pad) / c.fx;
+  f.tt = (c.cy + pad) / c.fy;
+  f.tb = (((float)c.height - c.cy) + pad) / c.fy;
+  const float lx = jac_clamp * ((0.5f * (float)c.width) / c.fx);
+  const float ly = jac_clamp * ((0.5f * (float)c.height) / c.fy);
+  f.ml = sqrtf(__builtin_fmaf(f.tl, f.tl, 1.0f)) + fabsf(lx - f.tl);
+  f.mr = sqrtf(__builtin_fmaf(f.tr, f.tr, 1.0f)) + fabsf(lx - f.tr);
+  f.mt = sqrtf(__builtin_fmaf(f.tt, f.tt, 1.0f)) + fabsf(ly - f.tt);
+  f.mb = sqrtf(__builtin_fmaf(f.tb, f.tb, 1.0f)) + fabsf(ly - f.tb);
   return f;
 }
 
@@ -77,23 +101,24 @@ __device__ __forceinline__ bool anchor_selected(const octgs_camera &c, const Fru
   const float yc = __builtin_fmaf(c.R[3], d0, __builtin_fmaf(c.R[4], d1, c.R[5] * d2));
   const float zc = __builtin_fmaf(c.R[6], d0, __builtin_fmaf(c.R[7], d1, c.R[8] * d2));
   if (!(zc + rho >= c.z_near)) return false;
-  if (!(xc <= __builtin_fmaf(f.tr, zc, rho * f.sr))) return false;
-  if (!(-xc <= __builtin_fmaf(f.tl, zc, rho * f.sl))) return false;
-  if (!(yc <= __builtin_fmaf(f.tb, zc, rho * f.sb))) return false;
-  if (!(-yc <= __builtin_fmaf(f.tt, zc, rho * f.st))) return false;
+  if (!(xc <= __builtin_fmaf(f.tr, zc, rho * f.mr))) return false;
+  if (!(-xc <= __builtin_fmaf(f.tl, zc, rho * f.ml))) return false;
+  if (!(yc <= __builtin_fmaf(f.tb, zc, rho * f.mb))) return false;
+  if (!(-yc <= __builtin_fmaf(f.tt, zc, rho * f.mt))) return false;
   return true;
 }
 
 // Pass 1: block b tests anchors [b*1024, (b+1)*1024) with coalesced loads,
 // stores one 64-bit ballot per 64 consecutive anchors and the block count.
 __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera cam,
+                                                        float dilation, float jac_clamp,
                                                         const float *__restrict__ pos,
                                                         const float *__restrict__ thr2,
                                                         const float *__restrict__ rho,
                                                         uint64_t *__restrict__ masks,
                                                         uint32_t *__restrict__ blk_cnt) {
   __shared__ uint32_t wsum[4];
-  const Frustum f = frustum(cam);
+  const Frustum f = frustum(cam, dilation, jac_clamp);
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   uint32_t cnt = 0;
@@ -209,30 +234,41 @@ int scratch_address(hipStream_t s, void **out) {
 }
 
 // The two selection passes with the workspace at `ws` (>= select_ws_bytes(n)).
-int launch_select(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
-                  uint32_t *sel_count, void *ws, hipStream_t s) {
+int launch_select(const octgs_anchors *a, const octgs_camera *cam, const octgs_raster_params *p,
+                  uint32_t *sel_idx, uint32_t *sel_count, void *ws, hipStream_t s) {
   const int64_t nblk = (a->n + kChunk - 1) / kChunk;
   uint64_t *masks = (uint64_t *)ws;
   uint32_t *blk = (uint32_t *)((char *)ws + nblk * (kChunk / 64) * 8);
   hipLaunchKernelGGL(k_select_mark, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, *cam,
-                     a->pos, a->thr2, a->bound_r, masks, blk);
+                     p->dilation, p->jac_clamp, a->pos, a->thr2, a->bound_r, masks, blk);
   hipLaunchKernelGGL(k_select_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, a->n, masks,
                      blk, sel_idx, sel_count);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 
 // Host-side checks shared by both selection entry points.
-int check_select_args(const octgs_anchors *a, const octgs_camera *cam, const uint32_t *sel_idx,
-                      const uint32_t *sel_count) {
-  if (!a || !cam || !sel_idx || !sel_count) return OCTGS_EINVAL;
+int check_select_args(const octgs_anchors *a, const octgs_camera *cam, const octgs_raster_params *p,
+                      const uint32_t *sel_idx, const uint32_t *sel_count) {
+  if (!a || !cam || !p || !sel_idx || !sel_count) return OCTGS_EINVAL;
   if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
   if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f))
     return OCTGS_EINVAL;
+  // z_near > 0 keeps every listed depth positive (the depth keys are float bits)
+  if (!(cam->z_near > 0.0f)) return OCTGS_EINVAL;
+  if (!(p->dilation >= 0.0f) || !(p->jac_clamp > 0.0f)) return OCTGS_EINVAL;
   if (a->n > 0 && (!a->pos || !a->thr2 || !a->bound_r)) return OCTGS_EINVAL;
   return OCTGS_OK;
 }
 
 }  // namespace
+
+hipError_t launch_round_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t threads = (count + 3) / 4;
+  hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, src, dst, count);
+  return hipGetLastError();
+}
 
 }  // namespace octgs
 
@@ -241,7 +277,7 @@ using namespace octgs;
 extern "C" {
 
 int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
-                          octgs_stream stream) {
+                          uint16_t *feat_bf16, octgs_stream stream) {
   if (!a) return OCTGS_EINVAL;
   if (a->n < 0 || a->n >= (int64_t(1) << 31)) return OCTGS_EINVAL;
   if (a->k < 1 || a->k > kMaxK) return OCTGS_EUNSUPPORTED;
@@ -250,10 +286,14 @@ int octgs_prepare_anchors(const octgs_anchors *a, float *thr2, float *bound_r,
   if (!a->level || !a->lod_bias || !a->offsets || !a->offset_scale || !a->base_scale)
     return OCTGS_EINVAL;
   if (!(a->d_max > 0.0f)) return OCTGS_EINVAL;
+  if (feat_bf16 && (!a->feat || a->feat_dim < 1)) return OCTGS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
   const int grid = (int)((a->n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a->n, a->k,
+  hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(kBlock), 0, s, a->n, a->k,
                      a->d_max, a->level, a->lod_bias, a->offsets, a->offset_scale,
                      a->base_scale, thr2, bound_r);
+  if (feat_bf16 && launch_round_bf16(a->feat, feat_bf16, a->n * a->feat_dim, s) != hipSuccess)
+    return OCTGS_EHIP;
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 
@@ -262,9 +302,10 @@ size_t octgs_select_workspace_bytes(int64_t n) {
   return select_ws_bytes(n);
 }
 
-int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
-                     uint32_t *sel_count, void *ws, size_t ws_bytes, octgs_stream stream) {
-  const int st = check_select_args(a, cam, sel_idx, sel_count);
+int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, const octgs_raster_params *p,
+                     uint32_t *sel_idx, uint32_t *sel_count, void *ws, size_t ws_bytes,
+                     octgs_stream stream) {
+  const int st = check_select_args(a, cam, p, sel_idx, sel_count);
   if (st != OCTGS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (a->n == 0) {
@@ -273,12 +314,13 @@ int octgs_select_lod(const octgs_anchors *a, const octgs_camera *cam, uint32_t *
   }
   if (!ws) return OCTGS_EINVAL;
   if (ws_bytes < octgs_select_workspace_bytes(a->n)) return OCTGS_ENOSPC;
-  return launch_select(a, cam, sel_idx, sel_count, ws, s);
+  return launch_select(a, cam, p, sel_idx, sel_count, ws, s);
 }
 
-int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam, uint32_t *sel_idx,
+int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam,
+                             const octgs_raster_params *p, uint32_t *sel_idx,
                              uint32_t *sel_count, octgs_stream stream) {
-  const int st = check_select_args(a, cam, sel_idx, sel_count);
+  const int st = check_select_args(a, cam, p, sel_idx, sel_count);
   if (st != OCTGS_OK) return st;
   if (a->n > kScratchMaxAnchors) return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
@@ -291,7 +333,7 @@ int octgs_select_lod_noalloc(const octgs_anchors *a, const octgs_camera *cam, ui
   if (sa != OCTGS_OK) return sa;
   // every scratch word the two passes read is written by the first pass of
   // the same call, so nothing needs clearing
-  return launch_select(a, cam, sel_idx, sel_count, ws, s);
+  return launch_select(a, cam, p, sel_idx, sel_count, ws, s);
 }
 
 }  // extern "C"

@@ -83,6 +83,16 @@ def raster_params(alpha_max=0.99, alpha_min=0.0, t_min=1e-4, dilation=0.3, jac_c
     return p
 
 
+def raise_on_status(bits: int, what: str = "frames"):
+    """Raise OctgsError naming the OCTGS_STATUS_* bits set in `bits`."""
+    if bits:
+        names = [n for b, n in ((L.OCTGS_STATUS_PAIR_OVERFLOW, "pair list overflow"),
+                                (L.OCTGS_STATUS_SYNC_ERROR, "look-back wait bound"),
+                                (L.OCTGS_STATUS_TRUNCATED, "decode truncated at the Gaussian "
+                                                           "capacity")) if bits & b]
+        raise L.OctgsError(f"{what}: " + ", ".join(names))
+
+
 class DeviceScene:
     """An anchor set resident in HBM, with its per-scene Eq. 7 thresholds."""
 
@@ -99,8 +109,8 @@ class DeviceScene:
         self.level = torch.as_tensor(np.ascontiguousarray(level, np.uint8)).to(dev)
         self.lod_bias = t(lod_bias)
         self.feat = t(feat)
-        # BF16 copy for the fast path (round to nearest even)
-        self.feat_bf16 = self.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+        # BF16 copy for the fast path, written by octgs_prepare_anchors
+        self.feat_bf16 = torch.empty(self.feat.shape, dtype=torch.int16, device=dev)
         self.offsets = t(offsets)
         self.offset_scale = t(offset_scale)
         self.base_scale = t(base_scale)
@@ -108,10 +118,7 @@ class DeviceScene:
         self.thr2 = torch.empty(self.n, **f32)
         self.bound_r = torch.empty(self.n, **f32)
         self._anchors = self._make_anchors()
-        L.check(L.lib().octgs_prepare_anchors(ctypes.byref(self._anchors), _ptr(self.thr2),
-                                             _ptr(self.bound_r), stream_handle(stream)),
-                "octgs_prepare_anchors")
-        self._anchors = self._make_anchors()
+        self.refresh(stream)
         self._mlp = L.Mlp()
         self._mlp.width = self.width
         for h, name in enumerate(MLP_HEADS):
@@ -119,6 +126,16 @@ class DeviceScene:
             self._mlp.b1[h] = self.mlp["b1_" + name].data_ptr()
             self._mlp.w2[h] = self.mlp["w2_" + name].data_ptr()
             self._mlp.b2[h] = self.mlp["b2_" + name].data_ptr()
+
+    def refresh(self, stream=None):
+        """Recompute what the library derives from the trained arrays: the
+        Eq. 7 thresholds (lod_bias), the bound radii (offsets, offset_scale,
+        base_scale) and the BF16 feature copy.  Needed after every update of
+        those arrays (an optimiser step, a LOD-bias update) before the next
+        selection or decode."""
+        L.check(L.lib().octgs_prepare_anchors(ctypes.byref(self._anchors), _ptr(self.thr2),
+                                             _ptr(self.bound_r), _ptr(self.feat_bf16),
+                                             stream_handle(stream)), "octgs_prepare_anchors")
 
     @classmethod
     def from_scene(cls, sc, stream=None) -> "DeviceScene":
@@ -167,7 +184,8 @@ class DeviceExplicit:
         self.lod_bias = t(lod_bias)
         self.mean, self.log_scale, self.rot = t(mean), t(log_scale), t(rot)
         self.opacity, self.sh = t(opacity), t(sh)
-        self.sh_bf16 = self.sh.to(torch.bfloat16).view(torch.int16).contiguous()
+        # BF16 copy of the coefficients, written by octgs_prepare_explicit
+        self.sh_bf16 = torch.empty(self.sh.shape, dtype=torch.int16, device=dev)
         self.thr2 = torch.empty(max(1, self.n), **f32)
         self.bound_r = torch.empty(max(1, self.n), **f32)
         self._ex = L.Explicit()
@@ -182,8 +200,14 @@ class DeviceExplicit:
                                           self.lod_bias.data_ptr())
             a.thr2, a.bound_r = self.thr2.data_ptr(), self.bound_r.data_ptr()
         self._anchors = a
-        L.check(L.lib().octgs_prepare_explicit(ctypes.byref(a), ctypes.byref(self._ex),
+        self.refresh(stream)
+
+    def refresh(self, stream=None):
+        """Recompute the Eq. 7 thresholds, bound radii and the BF16 SH copy
+        from the current arrays (after any update of them)."""
+        L.check(L.lib().octgs_prepare_explicit(ctypes.byref(self._anchors), ctypes.byref(self._ex),
                                               _ptr(self.thr2), _ptr(self.bound_r),
+                                              _ptr(self.sh_bf16) if self.n else None,
                                               stream_handle(stream)), "octgs_prepare_explicit")
 
     @classmethod
@@ -374,14 +398,37 @@ class ViewBuffers:
         self._g.capacity = self.gcap
         self._g.data = self.gauss.data_ptr()
         self._g.count = self.gauss_count.data_ptr()
+        # OCTGS_STATUS_* bits of every frame passed to add_status since the last clear
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    # ---- frame status ----
+    def add_status(self, count: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                   stream=None):
+        """OR the last frame's device-detected conditions (pair overflow,
+        look-back bound, decode truncation of the `count` listed anchors,
+        default the selection) into `status` (default self.status); no sync."""
+        count = self.sel_count if count is None else count
+        status = self.status if status is None else status
+        L.check(L.lib().octgs_frame_status(_ptr(self.ras_ws), _ptr(count), self.k, self.gcap,
+                                           _ptr(status), stream_handle(stream)),
+                "octgs_frame_status")
+
+    def check_status(self, what: str = "frames", status: Optional[torch.Tensor] = None):
+        """Raise if any frame added to `status` flagged a condition (syncs)."""
+        status = self.status if status is None else status
+        raise_on_status(int(status.item()), what)
 
     # ---- stages ----
-    def select(self, scene, cam: L.Camera, stream=None):
-        """Eq. 7 selection over a DeviceScene or a DeviceExplicit."""
+    def select(self, scene, cam: L.Camera, params: Optional[L.RasterParams] = None, stream=None):
+        """Eq. 7 selection over a DeviceScene or a DeviceExplicit; the
+        visibility test is conservative for a render with `params` (default
+        raster_params())."""
+        params = raster_params() if params is None else params
         L.check(L.lib().octgs_select_lod(ctypes.byref(scene.anchors), ctypes.byref(cam),
-                                         _ptr(self.sel_idx), _ptr(self.sel_count),
-                                         _ptr(self.sel_ws), self.sel_ws.numel(),
-                                         stream_handle(stream)), "octgs_select_lod")
+                                         ctypes.byref(params), _ptr(self.sel_idx),
+                                         _ptr(self.sel_count), _ptr(self.sel_ws),
+                                         self.sel_ws.numel(), stream_handle(stream)),
+                "octgs_select_lod")
 
     def decode(self, scene: DeviceScene, cam: L.Camera, precision: int = L.OCTGS_FP32,
                idx: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None,
@@ -410,7 +457,7 @@ class ViewBuffers:
 
     def render_explicit(self, ex: "DeviceExplicit", cam: L.Camera, params: L.RasterParams,
                         precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
-        self.select(ex, cam, stream)
+        self.select(ex, cam, params, stream=stream)
         self.decode_explicit(ex, cam, precision, stream=stream)
         self.rasterize(cam, params, stream=stream, stage_events=stage_events)
 
@@ -445,7 +492,7 @@ class ViewBuffers:
 
     def render(self, scene: DeviceScene, cam: L.Camera, params: L.RasterParams,
                precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
-        self.select(scene, cam, stream)
+        self.select(scene, cam, params, stream=stream)
         self.decode(scene, cam, precision, stream=stream)
         self.rasterize(cam, params, stream=stream, stage_events=stage_events)
 
@@ -523,7 +570,12 @@ class RenderFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vb, scene, cam, params, *tensors):
+        # the trained tensors may have changed in place since the last call
+        scene.refresh()
         vb.render(scene, cam, params, precision=L.OCTGS_FP32)
+        vb.status.zero_()
+        vb.add_status()
+        vb.check_status("RenderFn forward")
         ctx.vb, ctx.scene, ctx.cam, ctx.params = vb, scene, cam, params
         return vb.rgb.clone()
 

@@ -93,3 +93,57 @@ def report(name, gpu, ref, tol):
     diff = np.abs(np.asarray(gpu, np.float64) - np.asarray(ref, np.float64))
     say(f"{name}: max abs err {diff.max() if diff.size else 0:.3e} (tol {tol:.1e})")
     return diff
+
+
+def decision_bounds(scene, idx, cam, gd):
+    """Bounds [14][m*k] on how far the FP32 decode of the HIP path can lie
+    from the oracle's decode rounded to FP32, for the near-threshold check of
+    the rasterizer's decisions (oracle.fragile).  As decoded_field_bounds,
+    except the mean: both sides form x_v + O l with one rounding to FP32 (a
+    fused multiply-add there, the double sum rounded here), which agree
+    unless the double sum lies within one double ulp of a float midpoint;
+    only such coordinates keep their half-ulp bound."""
+    eb = decoded_field_bounds(scene, idx, cam, gd, False)
+    m = gd[0:3]
+    f = m.astype(np.float32).astype(np.float64)
+    ulp_f = np.spacing(np.abs(m.astype(np.float32))).astype(np.float64)
+    mid_lo, mid_hi = f - ulp_f / 2, f + ulp_f / 2
+    ulp_d = np.spacing(np.abs(m))
+    near_mid = (np.abs(m - mid_lo) <= ulp_d) | (np.abs(m - mid_hi) <= ulp_d)
+    eb[0:3] = np.where(near_mid, eb[0:3], 0.0)
+    return eb
+
+
+def e2e_compare(vb, ref, fr, tol=1e-4, min_checked=0.0, what=""):
+    """End-to-end FP32 parity of a HIP render (ViewBuffers after render)
+    with the oracle's render `ref`, given the near-threshold marks `fr` of
+    oracle.fragile: in every tile no near-threshold decision touches, the
+    sorted (tile, slot) list is bit-exact; on every pixel of those tiles
+    whose stop decision is not near t_min, the image and the final
+    transmittance are within tol.  Prints the counts; returns them."""
+    tile, slot, ranges = vb.sorted_lists()
+    ok_tile = ~fr["tiles"].reshape(-1)
+    mg, mr = ok_tile[tile], ok_tile[ref["bs"]["tile_of"]]
+    lists_equal = (np.array_equal(tile[mg], ref["bs"]["tile_of"][mr]) and
+                   np.array_equal(slot[mg], ref["bs"]["gid_of"][mr]))
+    checked = ~fr["near_flagged"] & ~fr["near_t_min"]
+    img = vb.rgb.detach().cpu().numpy().astype(np.float64)
+    T = vb.T.detach().cpu().numpy().astype(np.float64)
+    err = np.abs(img - ref["img"]).max(axis=0)
+    e_chk = float(err[checked].max()) if checked.any() else 0.0
+    e_T = float(np.abs(T - ref["T"])[checked].max()) if checked.any() else 0.0
+    res = dict(pairs=int(len(tile)), pairs_ref=int(ref["bs"]["n_pairs"]),
+               flagged_gaussians=fr["n_flagged"], flagged_tiles=int(fr["tiles"].sum()),
+               checked_frac=float(checked.mean()), max_abs_checked=e_chk, max_abs_T_checked=e_T,
+               max_abs_all=float(err.max()), pixels_over_tol_all=int((err > tol).sum()),
+               psnr_all=psnr(img, ref["img"]), lists_equal_unflagged=lists_equal,
+               list_pairs_checked=int(mg.sum()))
+    say(f"{what} e2e: pairs {res['pairs']} (oracle {res['pairs_ref']}), flagged "
+        f"{res['flagged_gaussians']} Gaussians / {res['flagged_tiles']} tiles, checked "
+        f"{100 * res['checked_frac']:.1f}% of pixels: max abs {e_chk:.2e} (T {e_T:.2e}); "
+        f"all pixels: max abs {res['max_abs_all']:.2e}, {res['pixels_over_tol_all']} over "
+        f"{tol:.0e}, PSNR {res['psnr_all']:.1f} dB; unflagged lists equal: {lists_equal}")
+    assert lists_equal, what
+    assert e_chk <= tol and e_T <= tol, what
+    assert res["checked_frac"] >= min_checked, (what, res["checked_frac"])
+    return res

@@ -80,6 +80,63 @@ def test_select_bit_exact_c1(P, orc, c1):
     assert True
 
 
+def test_select_hand_placed_spheres(P, orc):
+    """Spheres just inside and just outside each frustum plane of a rotated,
+    non-square, off-centre camera (the oracle's pin cases): the GPU takes
+    the oracle's decisions, which are the geometric ones."""
+    from tests.test_oracle_visibility import generic_camera, hand_placed_cases, world
+    import math as _m
+    cam = generic_camera()
+    prm = P.raster_params()
+    pad = 3.0 * _m.sqrt(float(np.float32(0.3)))
+    rows = hand_placed_cases(cam, pad, 1.3)
+    n = len(rows)
+    pos = world(cam, np.array([r[0] for r in rows])).astype(np.float32)
+    rho = np.array([r[1] for r in rows], np.float32)
+    want = np.array([r[2] for r in rows])
+    k = 1
+    rng = np.random.default_rng(0)
+    ds = P.DeviceScene(pos, np.zeros(n, np.uint8), np.zeros(n, np.float32),
+                       rng.standard_normal((n, 32)).astype(np.float32),
+                       np.zeros((n, k, 3), np.float32), np.ones((n, 3), np.float32),
+                       np.full((n, 3), 1e-3, np.float32), S.xavier_mlp(rng, 36, 16, k), 100.0, 1,
+                       k, 16)
+    ds.bound_r.copy_(torch.as_tensor(rho))
+    vb = P.ViewBuffers(n, k, cam.width, cam.height, 1 << 12)
+    say("select hand-placed spheres", n)
+    vb.select(ds, P.make_camera(cam), prm)
+    torch.cuda.synchronize()
+    m = int(vb.sel_count.item())
+    got = np.zeros(n, bool)
+    got[_np(vb.sel_idx[:m]).astype(np.int64)] = True
+    ref = orc.select_mask(pos, np.full(n, np.inf, np.float32), rho, cam).astype(bool)
+    assert np.array_equal(ref, want)
+    assert np.array_equal(got, ref)
+
+
+def test_culling_never_changes_the_image(P, orc):
+    """On the GPU too: rendering with the real bound radii equals, bit for
+    bit, rendering with every LOD-passing anchor kept (bound radius inf)."""
+    from tests.test_oracle_visibility import generic_camera
+    sc = S.make_config1()
+    cam = generic_camera(C=(5.0, -9.0, 4.0), target=(0.5, 0.0, 0.0))
+    prm = P.raster_params()
+    ds = P.DeviceScene.from_scene(sc)
+    vb = P.ViewBuffers(sc.n, sc.k, cam.width, cam.height, 1 << 18)
+    say("culling vs no culling, config 1, rotated off-centre camera")
+    vb.render(ds, P.make_camera(cam), prm)
+    torch.cuda.synchronize()
+    m_cut = int(vb.sel_count.item())
+    img_cut, T_cut, last_cut = _np(vb.rgb).copy(), _np(vb.T).copy(), _np(vb.last).copy()
+    ds.bound_r.fill_(float("inf"))
+    vb.render(ds, P.make_camera(cam), prm)
+    torch.cuda.synchronize()
+    assert int(vb.sel_count.item()) > m_cut + 100
+    assert np.array_equal(_np(vb.rgb), img_cut)
+    assert np.array_equal(_np(vb.T), T_cut)
+    assert np.array_equal(_np(vb.last), last_cut)
+
+
 def test_select_bit_exact_random_bias(P, orc):
     rng = np.random.default_rng(2)
     n, K = 300_001, 7
@@ -282,7 +339,7 @@ def test_invalid_arguments_rejected(P):
     import ctypes
     from paper_2403_17898_amd import _lib as L
     lib = L.lib()
-    assert lib.octgs_select_lod(None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
+    assert lib.octgs_select_lod(None, None, None, None, None, None, 0, None) == L.OCTGS_EINVAL
     assert lib.octgs_raster_workspace_bytes(-1, 0, 10, 10) == 0
     g = L.Gaussians()
     assert lib.octgs_rasterize_fwd(ctypes.byref(g), None, None, 0, None, None, None, None, None, 0,

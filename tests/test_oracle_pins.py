@@ -248,7 +248,7 @@ def test_bin_sort_against_enumeration(orc):
         x0, y0, x1, y1 = pj["rect"][i]
         for y in range(y0, y1):
             for x in range(x0, x1):
-                if orc.tile_test(pj["cf"][i], x, y):
+                if orc.tile_test(pj["cf"][i], x, y, 80, 70):
                     rows.append((y * tx + x, pj["depth"][i].view(np.uint32), i))
     rows = np.array(rows, dtype=np.int64)
     order = np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))
@@ -269,6 +269,7 @@ def test_tile_test_against_root_form(orc):
     a pixel centre inside the ellipse."""
     rng = np.random.default_rng(7)
     n_chk = n_tie = 0
+    W, H = 117, 121  # the last tile column and row hold 5 and 9 pixel centres
     for _ in range(400):
         mx, my = rng.uniform(-20, 100, 2)
         sx, sy = np.exp(rng.uniform(np.log(0.7), np.log(25), 2))
@@ -283,16 +284,18 @@ def test_tile_test_against_root_form(orc):
         for tx in range(-1, 8):
             for ty in range(-1, 8):
                 X0, Y0 = 16.0 * tx + 0.5, 16.0 * ty + 0.5
-                got = orc.tile_test(cf, tx, ty)
-                qmin = box_qmin_sampled(fx, fy, A, B, C, X0, X0 + 15, Y0, Y0 + 15)
+                X1, Y1 = min(X0 + 15, W - 0.5), min(Y0 + 15, H - 0.5)
+                got = orc.tile_test(cf, tx, ty, W, H)
+                qmin = box_qmin_sampled(fx, fy, A, B, C, X0, X1, Y0, Y1)
                 if abs(qmin - 9.0) < 1e-3:
                     n_tie += 1
                     continue
                 n_chk += 1
-                assert got == ellipse_meets_box(fx, fy, A, B, C, X0, X0 + 15, Y0, Y0 + 15), \
+                assert got == ellipse_meets_box(fx, fy, A, B, C, X0, X1, Y0, Y1), \
                     (mx, my, sx, sy, th, tx, ty)
                 px = np.arange(16) + 16 * tx + 0.5
-                X, Y = np.meshgrid(px, np.arange(16) + 16 * ty + 0.5)
+                py = np.arange(16) + 16 * ty + 0.5
+                X, Y = np.meshgrid(px[px < W], py[py < H])
                 q = A * (X - fx) ** 2 + 2 * B * (X - fx) * (Y - fy) + C * (Y - fy) ** 2
                 if q.min() <= 9.0:
                     assert got

@@ -39,26 +39,28 @@ def _random_scene(P, n, seed):
     return P.DeviceScene(pos, level, bias, feat, offsets, osc, bsc, mlp, 180.0, K, k, 16)
 
 
-def _both(P, ds, cam):
+def _both(P, ds, cam, prm=None):
     """(indices, count) from the workspace entry point and from the
     allocation-free one, outputs pre-filled with a sentinel."""
     from paper_2403_17898_amd import _lib as L
     lib = L.lib()
     n = ds.n
     dev = torch.device("cuda", 0)
+    prm = P.raster_params() if prm is None else prm
     out = []
     for noalloc in (False, True):
         idx = torch.full((max(1, n),), -1, dtype=torch.int32, device=dev)
         cnt = torch.full((1,), -1, dtype=torch.int32, device=dev)
         if noalloc:
             st = lib.octgs_select_lod_noalloc(ctypes.byref(ds.anchors), ctypes.byref(cam),
-                                              idx.data_ptr(), cnt.data_ptr(), None)
+                                              ctypes.byref(prm), idx.data_ptr(), cnt.data_ptr(),
+                                              None)
         else:
             ws = torch.empty(max(256, lib.octgs_select_workspace_bytes(n)), dtype=torch.uint8,
                              device=dev)
             st = lib.octgs_select_lod(ctypes.byref(ds.anchors), ctypes.byref(cam),
-                                      idx.data_ptr(), cnt.data_ptr(), ws.data_ptr(), ws.numel(),
-                                      None)
+                                      ctypes.byref(prm), idx.data_ptr(), cnt.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), None)
         assert st == L.OCTGS_OK, st
         torch.cuda.synchronize()
         m = int(cnt.item())
@@ -92,15 +94,16 @@ def test_noalloc_empty_and_limit(P):
     dev = torch.device("cuda", 0)
     idx = torch.zeros(4, dtype=torch.int32, device=dev)
     cnt = torch.full((1,), 7, dtype=torch.int32, device=dev)
+    prm = P.raster_params()
     a = L.Anchors.from_buffer_copy(ds.anchors)
     a.n = 0
     say("noalloc select: empty input")
-    assert lib.octgs_select_lod_noalloc(ctypes.byref(a), ctypes.byref(cam), idx.data_ptr(),
-                                        cnt.data_ptr(), None) == L.OCTGS_OK
+    assert lib.octgs_select_lod_noalloc(ctypes.byref(a), ctypes.byref(cam), ctypes.byref(prm),
+                                        idx.data_ptr(), cnt.data_ptr(), None) == L.OCTGS_OK
     torch.cuda.synchronize()
     assert int(cnt.item()) == 0
     # above the stated maximum: refused before any device work
     a.n = L.OCTGS_SELECT_NOALLOC_MAX_ANCHORS + 1
     say("noalloc select: above the maximum")
-    assert lib.octgs_select_lod_noalloc(ctypes.byref(a), ctypes.byref(cam), idx.data_ptr(),
-                                        cnt.data_ptr(), None) == L.OCTGS_ENOSPC
+    assert lib.octgs_select_lod_noalloc(ctypes.byref(a), ctypes.byref(cam), ctypes.byref(prm),
+                                        idx.data_ptr(), cnt.data_ptr(), None) == L.OCTGS_ENOSPC
