@@ -24,11 +24,19 @@ SKIP_ORDER = ("w1", "b1", "w2", "b2", "w3", "b3")
 Z_DIM, HID = 37, 64
 
 
+# columns of the predictor input z: the anchor feature, the camera-frame
+# viewing direction, log2 of the distance over d_max, the octree level
+Z_FEATURE, Z_DIRECTION, Z_LOG_DISTANCE, Z_LEVEL = range(0, 32), range(32, 35), 35, 36
+
+
 class SkipNet:
     """FP32 master weights of the 37 -> 64 -> 64 -> 1 predictor, with their
-    gradient buffers and Adam moments, on the current device."""
+    gradient buffers and Adam moments, on the current device.  `inputs`
+    restricts the network to some columns of z (the first layer's other
+    rows are held at zero): the same network and kernels then implement a
+    rule on, say, the distance alone."""
 
-    def __init__(self, seed: int = 0):
+    def __init__(self, seed: int = 0, inputs=None):
         dev = torch.device("cuda", torch.cuda.current_device())
         g = torch.Generator().manual_seed(seed)
 
@@ -44,6 +52,12 @@ class SkipNet:
         self.v = {k: torch.zeros_like(v) for k, v in self.w.items()}
         self.step = 0
         self._ws = None
+        self.row_mask = None
+        if inputs is not None:
+            mask = torch.zeros(Z_DIM, 1, device=dev)
+            mask[list(inputs)] = 1.0
+            self.row_mask = mask
+            self.w["w1"].mul_(mask)
 
     def struct(self) -> L.SkipNet:
         return L.SkipNet(*[self.w[k].data_ptr() for k in SKIP_ORDER])
@@ -67,6 +81,8 @@ class SkipNet:
 
     def adam(self, lr: float):
         self.step += 1
+        if self.row_mask is not None:
+            self.g["w1"].mul_(self.row_mask)
         for k in SKIP_ORDER:
             adam_step(self.w[k], self.g[k], self.m[k], self.v[k], lr, self.step, eps=1e-8)
 
@@ -133,6 +149,7 @@ def collect(vb: ViewBuffers, scene: DeviceScene, cams: List[L.Camera], params: L
     gen = torch.Generator(device=dev).manual_seed(seed)
     for c in cams:
         vb.render(scene, c, params, precision=L.OCTGS_FP32)
+        vb.add_status()  # checked by the caller (vb.check_status)
         anchor_weights(vb, w)
         features(vb, scene, c, zbuf)
         m = int(vb.sel_count.item())
@@ -188,3 +205,20 @@ def choose_threshold(vb: ViewBuffers, sb: SkipBuffers, scene: DeviceScene, cams,
         if worst >= min_psnr:
             best = (thr, worst)
     return best
+
+
+def weight_keep_lists(vb: ViewBuffers, scene: DeviceScene, cams: List[L.Camera],
+                      params: L.RasterParams, tau: float):
+    """Per view, the selected anchors whose logged blend weight exceeds tau
+    (what a perfect predictor of the label would keep), as (idx, count)
+    device tensors ready for the decode; vb needs log_weights=True."""
+    dev = vb.gauss.device
+    w = torch.empty(max(1, vb.n), device=dev)
+    out = []
+    for c in cams:
+        vb.render(scene, c, params, precision=L.OCTGS_FP32)
+        anchor_weights(vb, w)
+        m = int(vb.sel_count.item())
+        keep = vb.sel_idx[:m][w[:m] > tau].contiguous()
+        out.append((keep, torch.tensor([keep.numel()], dtype=torch.int32, device=dev)))
+    return out

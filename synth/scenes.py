@@ -134,6 +134,23 @@ def zoomout_trajectory(n: int, h0: float, h1: float, width: int, height: int,
     return cams
 
 
+def trajectory_family_views(n: int, seed: int, h_lo: float, h_hi: float, width: int,
+                            height: int, fov_x_deg: float = 60.0, jitter: float = 0.1) -> List[Camera]:
+    """Views of the zoom-out's family: altitude h log-uniform in [h_lo, h_hi],
+    the camera at (0, -h, h) + N(0, (jitter h)^2) per horizontal axis and
+    looking at its own ground point (0, 0, 0) + the same offset plus
+    N(0, (jitter h)^2) per horizontal axis, so the pitch stays near 45
+    degrees and the yaw near the trajectory's."""
+    rng = np.random.default_rng(seed)
+    cams = []
+    for _ in range(n):
+        h = math.exp(rng.uniform(math.log(h_lo), math.log(h_hi)))
+        ox, oy = rng.normal(0.0, jitter * h, 2)
+        tx, ty = rng.normal(0.0, jitter * h, 2)
+        cams.append(look_at((ox, oy - h, h), (ox + tx, oy + ty, 0.0), width, height, fov_x_deg))
+    return cams
+
+
 def random_views(n: int, seed: int, extent: float, h_lo: float, h_hi: float,
                  width: int, height: int, fov_x_deg: float = 60.0) -> List[Camera]:
     """Random aerial views: altitude log-uniform in [h_lo, h_hi], position

@@ -2,15 +2,17 @@
 gradients (themselves pinned by finite differences), through the C ABI.
 
 Bar: per-array normwise relative error <= 1e-3 (the gradient-check bar),
-and the FP32 GPU gradient against central differences of the FP64 oracle
-forward on the 50-anchor 64x64 scene.
+element-wise within 1e-3 relative on every entry above 1e-6 of its array's
+largest (on the end-to-end chain: of anchors that no near-threshold decision
+touches), and the FP32 GPU gradient against central differences of the FP64
+oracle forward on the 50-anchor 64x64 scene.
 """
 
 import numpy as np
 import pytest
 
 from synth import scenes as S
-from tests.gpu_util import say
+from tests.gpu_util import decision_bounds, elementwise, grad_compare, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -62,6 +64,9 @@ def test_raster_backward_parity(P, orc, W, H, n, seed):
         e = rel(got[a:b], dref[a:b])
         say(f"  d{nm}: rel err {e:.2e}")
         assert e <= 1e-3, nm
+        # identical FP32 Gaussians: every decision is the same on both sides
+        _, nbad, _ = elementwise(got[a:b].T, dref[a:b].T, what="d" + nm)
+        assert nbad == 0, nm
 
 
 def test_decode_backward_parity(P, orc):
@@ -85,6 +90,8 @@ def test_decode_backward_parity(P, orc):
         e = rel(got[name], r)
         say(f"  {name}: rel err {e:.2e}")
         assert e <= 1e-4, name
+        _, nbad, _ = elementwise(got[name], r, what=name)
+        assert nbad == 0, name
 
 
 def test_full_chain_gradient(P, orc):
@@ -109,10 +116,8 @@ def test_full_chain_gradient(P, orc):
     vb.decode_bwd(ds, c, grads)
     torch.cuda.synchronize()
     got = {k: _np(v) for k, v in grads.all().items()}
-    errs = {name: rel(got[name], r) for name, r in ref.items()}
-    for name, e in errs.items():
-        say(f"  {name}: GPU vs oracle rel err {e:.2e}")
-    assert max(errs.values()) <= 1e-3, errs
+    fr = orc.fragile(fwd, cam, prm, decision_bounds(sc, fwd["idx"], cam, fwd["gauss"]))
+    grad_compare(got, ref, fwd, fr, sc.k, what="50 anchors, 64x64")
     # central differences of the FP64 oracle forward, float32-exact steps
     fd_err = []
     for name in ("feat", "offsets", "w1_a", "w2_c", "w2_s"):

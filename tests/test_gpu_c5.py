@@ -3,14 +3,16 @@ boxes over [-2000, 2000]^2), at its full sizes and in the launch
 configuration the benchmark's city measurement uses.
 
 * Views of the 3840x2160 zoom-out (20 -> 3000 m) rendered end to end:
-  selection bit-exact; FP32 images at the image bar on 99.9 % of pixels and
-  >= 70 dB; BF16 images above the 45 dB gate.
+  selection bit-exact; in FP32, tile lists bit-exact and images within 1e-4
+  wherever no decision lies within the decode's error bound of its
+  threshold; BF16 images above the 45 dB gate.
 * The rasterizer alone on the oracle's decoded Gaussians of the densest
   zoom-out view (~1.7M Gaussians, ~5.4M pairs): sorted tile lists and
   ranges bit-exact, image within 1e-4.
 * One view of the 8-view 2048x1024 training step: gradients through
   compositing, projection and decode against the oracle's analytic FP64
-  gradients (1e-3 normwise).
+  gradients (1e-3 normwise, and element-wise on significant entries of
+  anchors no near-threshold decision touches).
 
 The scene takes about a minute to generate; it is built once per module.
 """
@@ -19,7 +21,7 @@ import numpy as np
 import pytest
 
 from synth import scenes as S
-from tests.gpu_util import psnr, say
+from tests.gpu_util import decision_bounds, e2e_compare, grad_compare, psnr, say
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +64,7 @@ def test_city_view_end_to_end(P, orc, c5, dev5, view):
     cam = S.config5_cameras()[view]
     thr, rho = orc.scene_thresholds(c5)
     ref = orc.render(c5, cam, orc.params_array(), thr, rho)
+    fr = orc.fragile(ref, cam, orc.params_array(), decision_bounds(c5, ref["idx"], cam, ref["gauss"]))
     n_sel = len(ref["idx"])
     pcap = int(ref["bs"]["n_rect_pairs"] * 1.10) + 4096
     vb = P.ViewBuffers(c5.n, c5.k, cam.width, cam.height, pcap,
@@ -75,14 +78,13 @@ def test_city_view_end_to_end(P, orc, c5, dev5, view):
         assert st["pair_overflow"] == 0 and st["sync_error"] == 0
         m = int(vb.sel_count.item())
         assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
-        img = _np(vb.rgb).astype(np.float64)
-        err = np.abs(img - ref["img"])
-        p = psnr(img, ref["img"])
-        say(f"  pairs {st['n_pairs']}, max abs {err.max():.2e}, PSNR {p:.1f} dB, "
-            f"pixels > 1e-4: {(err > 1e-4).sum()}")
         if prec == P.OCTGS_FP32:
-            assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+            e2e_compare(vb, ref, fr, 1e-4, min_checked=0.2, what=f"city view {view}")
         else:
+            img = _np(vb.rgb).astype(np.float64)
+            err = np.abs(img - ref["img"])
+            p = psnr(img, ref["img"])
+            say(f"  BF16: max abs {err.max():.2e}, PSNR {p:.1f} dB against the FP64 oracle")
             assert p >= 45.0
 
 
@@ -135,7 +137,5 @@ def test_city_training_view_gradients(P, orc, c5, dev5):
     m = int(vb.sel_count.item())
     assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), fwd["idx"])
     got = {k: _np(v) for k, v in grads.all().items()}
-    for name, r in ref.items():
-        e = _rel(got[name], r)
-        say(f"  {name}: rel err {e:.2e}")
-        assert e <= 1e-3, name
+    fr = orc.fragile(fwd, cam, prm_o, decision_bounds(c5, fwd["idx"], cam, fwd["gauss"]))
+    grad_compare(got, ref, fwd, fr, c5.k, what="city training view")

@@ -22,7 +22,7 @@ import numpy as np
 import pytest
 
 from synth import scenes as S
-from tests.gpu_util import psnr, say
+from tests.gpu_util import e2e_compare, psnr, say
 
 pytestmark = pytest.mark.gpu
 
@@ -197,12 +197,18 @@ def test_end_to_end_explicit_c1(P, orc, EX, c1, blend):
             ref = EX.render_explicit(exr, cam, orc.params_array(), blend=blend)
             m = int(vb.sel_count.item())
             assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
-            img = _np(vb.rgb).astype(np.float64)
-            err = np.abs(img - ref["img"])
-            p = psnr(img, ref["img"])
-            say(f"  {m} anchors, max abs {err.max():.2e} PSNR {p:.1f} dB, "
-                f"pixels > 1e-4: {(err > 1e-4).sum()}")
-            assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+            # what the decode may differ by: the mean is a copy; exp, sigmoid
+            # and the normalisation within 1e-6 relative; the blend factor's
+            # FP32 log2 on top of the opacity
+            gd = ref["gauss"]
+            eb = np.zeros_like(gd)
+            eb[3:11] = 1e-6 * np.maximum(1.0, np.abs(gd[3:11]))
+            if blend:
+                eb[10] += 8e-6 * np.abs(gd[10]) + 1e-7
+            fr = orc.fragile(ref, cam, orc.params_array(), eb)
+            e2e_compare(vb, ref, fr, 1e-4, min_checked=0.5,
+                        what=f"explicit view {i}{' blended' if blend else ''}"
+                             f"{' bf16 SH' if prec else ''}")
 
 
 @pytest.mark.parametrize("degree", [0, 1, 2, 3])

@@ -1,21 +1,24 @@
 """Parity at the benchmark's full sizes, in its launch configuration.
 
 * The 1M-anchor street scene at 1920x1080: views across the 200-view
-  zoom-out rendered end to end (selection bit-exact; FP32 images at the
-  image bar on 99.9 % of pixels; BF16 images above the 45 dB gate), and the
+  zoom-out rendered end to end (selection bit-exact; in FP32, tile lists
+  bit-exact and images within 1e-4 wherever no decision lies within the
+  decode's error bound of its threshold; BF16 images above the 45 dB gate
+  against the FP64 oracle), and the
   rasterizer alone on the oracle's decoded Gaussians of a view (sorted tile
   lists and ranges bit-exact, image within 1e-4), with the capacities sized
   the way the benchmark sizes them.
 * The 500k-anchor training scene at 1600x1066: the gradients of one view
   through compositing, projection and decode against the oracle's analytic
-  FP64 gradients (1e-3 normwise).
+  FP64 gradients (1e-3 normwise, and element-wise on every significant entry
+  of anchors that no near-threshold decision touches).
 """
 
 import numpy as np
 import pytest
 
 from synth import scenes as S
-from tests.gpu_util import psnr, say
+from tests.gpu_util import decision_bounds, e2e_compare, grad_compare, psnr, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +54,7 @@ def test_street_view_end_to_end(P, orc, c2, view):
     cam = S.config2_cameras()[view]
     thr, rho = orc.scene_thresholds(c2)
     ref = orc.render(c2, cam, orc.params_array(), thr, rho)
+    fr = orc.fragile(ref, cam, orc.params_array(), decision_bounds(c2, ref["idx"], cam, ref["gauss"]))
     n_sel = len(ref["idx"])
     pcap = int(ref["bs"]["n_rect_pairs"] * 1.10) + 4096
     ds = P.DeviceScene.from_scene(c2)
@@ -64,14 +68,13 @@ def test_street_view_end_to_end(P, orc, c2, view):
         assert st["pair_overflow"] == 0 and st["sync_error"] == 0
         m = int(vb.sel_count.item())
         assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), ref["idx"])
-        img = _np(vb.rgb).astype(np.float64)
-        err = np.abs(img - ref["img"])
-        p = psnr(img, ref["img"])
-        say(f"  pairs {st['n_pairs']} (oracle {ref['bs']['n_pairs']}), max abs {err.max():.2e}, "
-            f"PSNR {p:.1f} dB, pixels > 1e-4: {(err > 1e-4).sum()}")
         if prec == P.OCTGS_FP32:
-            assert p >= 70.0 and np.mean(err <= 1e-4) >= 0.999
+            e2e_compare(vb, ref, fr, 1e-4, min_checked=0.2, what=f"street view {view}")
         else:
+            img = _np(vb.rgb).astype(np.float64)
+            err = np.abs(img - ref["img"])
+            p = psnr(img, ref["img"])
+            say(f"  BF16: max abs {err.max():.2e}, PSNR {p:.1f} dB against the FP64 oracle")
             assert p >= 45.0
 
 
@@ -130,7 +133,5 @@ def test_training_view_gradients(P, orc):
     m = int(vb.sel_count.item())
     assert np.array_equal(_np(vb.sel_idx[:m]).astype(np.int64), fwd["idx"])
     got = {k: _np(v) for k, v in grads.all().items()}
-    for name, r in ref.items():
-        e = _rel(got[name], r)
-        say(f"  {name}: rel err {e:.2e}")
-        assert e <= 1e-3, name
+    fr = orc.fragile(fwd, cam, prm_o, decision_bounds(sc, fwd["idx"], cam, fwd["gauss"]))
+    grad_compare(got, ref, fwd, fr, sc.k, what="training view")

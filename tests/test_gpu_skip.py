@@ -141,27 +141,24 @@ def test_anchor_weights_parity(P, SK, orc):
 
 
 def test_trained_predictor_gains(P, SK):
-    """On the 1M-anchor street scene: a predictor trained on logged blend
-    weights of random views skips a larger share of selected anchors, at the
-    same worst-view PSNR against full decode (45 dB), than the same network
-    untrained, on held-out zoom-out views."""
+    """On the 1M-anchor street scene at 640x360: the predictor trained on
+    logged blend weights of views of the zoom-out's family skips a larger
+    share of selected anchors on held-out zoom-out views, at the same bound
+    on the worst view's PSNR against full decode (45 dB), than the same
+    network trained on one input alone (the log distance, or the level),
+    by at least 3 percentage points; and more than the untrained network."""
     sc = S.make_config2()
     ds = P.DeviceScene.from_scene(sc)
     W, H = 640, 360
-    train_cams = [P.make_camera(c) for c in S.random_views(60, 4, 500.0, 10.0, 800.0, W, H)]
+    train_cams = [P.make_camera(c) for c in S.trajectory_family_views(200, 4, 10.0, 800.0, W, H)]
     eval_cams = [P.make_camera(c) for c in S.zoomout_trajectory(12, 10.0, 800.0, W, H)]
     prm = P.raster_params()
     vb = P.ViewBuffers(sc.n, sc.k, W, H, 8 << 20, gauss_capacity=1 << 20, log_weights=True)
     sb = SK.SkipBuffers(vb)
     say("skip gain: collect")
     z, y = SK.collect(vb, ds, train_cams, prm, tau=1e-2, rows_per_view=20000)
-    pos = y.mean().item()
-    say(f"  rows {z.shape[0]}, positive fraction {pos:.3f}")
-    net = SK.SkipNet(seed=1)
-    untrained = SK.SkipNet(seed=1)
-    hist = SK.train(net, z, y, epochs=6, batch=8192, lr=2e-3)
-    say(f"  loss per epoch {[round(h, 4) for h in hist]}")
-    assert hist[-1] < hist[0]
+    vb.check_status("skip training views")
+    say(f"  rows {z.shape[0]}, positive fraction {y.mean().item():.3f}")
 
     def skip_at(netx):
         cands = [-4.0, -3.0, -2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 2.0]
@@ -171,13 +168,22 @@ def test_trained_predictor_gains(P, SK):
         thr = best[0]
         sel = kept = 0
         for c in eval_cams:
-            vb.select(ds, c)
+            vb.select(ds, c, prm)
             SK.predict(vb, sb, ds, c, netx, thr)
             sel += int(vb.sel_count.item())
             kept += int(sb.keep_count.item())
         return 1.0 - kept / max(sel, 1), best
 
-    s_tr, b_tr = skip_at(net)
-    s_un, b_un = skip_at(untrained)
-    say(f"  skipped at >=45 dB: trained {s_tr:.3f} ({b_tr}), untrained {s_un:.3f} ({b_un})")
-    assert s_tr > s_un
+    res = {}
+    for name, inputs in (("learned", None), ("distance only", [SK.Z_LOG_DISTANCE]),
+                         ("level only", [SK.Z_LEVEL])):
+        net = SK.SkipNet(seed=1, inputs=inputs)
+        hist = SK.train(net, z, y, epochs=6, batch=8192, lr=2e-3, pos_weight=4.0)
+        assert hist[-1] < hist[0], name
+        res[name] = skip_at(net)
+        say(f"  {name}: loss {[round(h, 4) for h in hist]}, skipped at >=45 dB {res[name]}")
+    res["untrained"] = skip_at(SK.SkipNet(seed=1))
+    say(f"  untrained: {res['untrained']}")
+    best_single = max(res["distance only"][0], res["level only"][0])
+    assert res["learned"][0] >= best_single + 0.03, res
+    assert res["learned"][0] > res["untrained"][0], res
