@@ -127,6 +127,15 @@ def parse():
                     help="timed views the CPU oracle renders (evenly spaced among them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the PSNR sweep (profiling runs)")
+    ap.add_argument("--stages-only", action="store_true",
+                    help="profiling runs: only the sizing pass and the per-stage timing loop "
+                         "(one view at a time); no throughput passes, no line printed")
+    ap.add_argument("--predict-stages", action="store_true",
+                    help="with --stages-only: also run the skip predictor (untrained weights) "
+                         "on each view after its render, for kernel profiles")
+    ap.add_argument("--train-only", action="store_true",
+                    help="profiling runs: only the training-step timing (use --inflight 1 "
+                         "for uncontended launches); no line printed")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step timing")
     ap.add_argument("--no-skip", action="store_true", help="skip the learned-skip study")
     ap.add_argument("--no-3dgs", action="store_true",
@@ -190,9 +199,9 @@ def time_views(args, torch, streams, views, bufs, render_one, depth):
         for _ in range(passes):
             for v in views:
                 k = i % depth
+                # every frame's overflow / look-back / truncation bits land in
+                # its buffer set's status word, checked after the loop
                 render_one(k, v, streams[k])
-                # every frame's overflow / look-back / truncation bits, checked after the loop
-                bufs[k].add_status(stream=streams[k])
                 i += 1
     for b in bufs[:depth]:
         b.status.zero_()
@@ -246,6 +255,11 @@ def main():
         log("copy calibration: 5 x 256 MiB device-to-device copies")
         del src, dst
 
+    if args.train_only:
+        res = train_step_timing(args, P, S, torch, np, with_full_loss=False)
+        log(f"train step only: {res}")
+        return
+
     t0 = time.time()
     sc = S.make_config2()
     cams = S.config2_cameras(args.views)
@@ -291,6 +305,10 @@ def main():
     log(f"timed: {args.steps} passes over the {nv} views; max selected {max_sel}, max "
         f"candidate pairs {max_pairs}; gcap {gcap}, pcap {pcap}; {D} frames in flight")
 
+    if args.stages_only:
+        stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, order)
+        return
+
     def timed_views(render_one, depth, views=None, bufs=None):
         """ms for args.steps views (after args.warmup), view i on stream i % depth."""
         return time_views(args, torch, streams, ccams if views is None else views,
@@ -332,40 +350,9 @@ def main():
                           order, fps32)
 
     # ---- per-stage timing with HIP events on the library's stream ----
-    from paper_2403_17898_amd.hip_events import HipEvent
-    names = ["select", "decode"] + list(L.RASTER_STAGE_NAMES)
-    tot = {k: 0.0 for k in names}
+    avg, mean, view_ms = stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream,
+                                    order)
     nviews = len(order)
-    sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0, blends=0)
-    view_ms = []
-    ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
-    sh = P.stream_handle(stream)
-    for i in range(nviews):
-        c = ccams[order[i]]
-        ev[0].record(sh)
-        vb.select(ds, c, prm)
-        ev[1].record(sh)
-        ev[2].record(sh)
-        vb.decode(ds, c, P.OCTGS_BF16)
-        ev[3].record(sh)
-        vb.rasterize(c, prm, stage_events=ev[4:])
-        torch.cuda.synchronize()
-        vms = ev[0].elapsed_ms(ev[1]) + ev[2].elapsed_ms(ev[3])
-        tot["select"] += ev[0].elapsed_ms(ev[1])
-        tot["decode"] += ev[2].elapsed_ms(ev[3])
-        for s_i, nm in enumerate(L.RASTER_STAGE_NAMES):
-            tot[nm] += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
-            vms += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
-        view_ms.append(vms)
-        st = vb.stats()
-        sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
-        sums["selected"] += st["n_selected"]
-        sums["slots"] += st["n_slots"]
-        sums["visible"] += st["n_visible"]
-        sums["pairs"] += st["n_pairs"]
-        sums["candidates"] += st["n_candidates"]
-    avg = {k: v / nviews for k, v in tot.items()}  # ms per launch
-    mean = {k: v / nviews for k, v in sums.items()}
     log("per-stage ms/view: " + ", ".join(f"{k} {v:.4f}" for k, v in avg.items()))
     log(f"mean per view: selected {mean['selected']:.0f}, Gaussians {mean['slots']:.0f}, "
         f"visible {mean['visible']:.0f}, pairs {mean['pairs']:.0f} "
@@ -503,6 +490,53 @@ def main():
     if city is not None:
         out["city"] = city
     print(json.dumps(_finite(out), allow_nan=False), flush=True)
+
+
+def stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, order):
+    """Each view alone on the GPU, BF16 decode, with HIP events around every
+    stage on the library's stream: (ms per stage per view, mean per-view
+    counts, per-view ms)."""
+    from paper_2403_17898_amd.hip_events import HipEvent
+    names = ["select", "decode"] + list(L.RASTER_STAGE_NAMES)
+    tot = {k: 0.0 for k in names}
+    nviews = len(order)
+    sums = dict(selected=0, slots=0, visible=0, pairs=0, candidates=0, blends=0)
+    view_ms = []
+    ev = [HipEvent() for _ in range(4 + 2 * L.OCTGS_RASTER_STAGES)]
+    sh = P.stream_handle(stream)
+    if args.predict_stages:
+        from paper_2403_17898_amd import skip as SK
+        net, sb = SK.SkipNet(seed=1), SK.SkipBuffers(vb)
+    for i in range(nviews):
+        c = ccams[order[i]]
+        ev[0].record(sh)
+        vb.select(ds, c, prm)
+        ev[1].record(sh)
+        ev[2].record(sh)
+        vb.decode(ds, c, P.OCTGS_BF16)
+        ev[3].record(sh)
+        vb.rasterize(c, prm, stage_events=ev[4:])
+        torch.cuda.synchronize()
+        vms = ev[0].elapsed_ms(ev[1]) + ev[2].elapsed_ms(ev[3])
+        tot["select"] += ev[0].elapsed_ms(ev[1])
+        tot["decode"] += ev[2].elapsed_ms(ev[3])
+        for s_i, nm in enumerate(L.RASTER_STAGE_NAMES):
+            tot[nm] += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
+            vms += ev[4 + 2 * s_i].elapsed_ms(ev[5 + 2 * s_i])
+        view_ms.append(vms)
+        if args.predict_stages:
+            SK.predict(vb, sb, ds, c, net, 0.0, stream=stream)
+            torch.cuda.synchronize()
+        st = vb.stats()
+        sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
+        sums["selected"] += st["n_selected"]
+        sums["slots"] += st["n_slots"]
+        sums["visible"] += st["n_visible"]
+        sums["pairs"] += st["n_pairs"]
+        sums["candidates"] += st["n_candidates"]
+    avg = {k: v / nviews for k, v in tot.items()}  # ms per launch
+    mean = {k: v / nviews for k, v in sums.items()}
+    return avg, mean, view_ms
 
 
 def cpu_baseline(args, P, S, torch, np, sc, cams, ccams, ds, prm, vb, tset):
@@ -920,6 +954,49 @@ def city_path(args, P, S, torch, np, prm, D, streams):
     return res
 
 
+# Per (pixel, list entry) the backward replay of Eq. 2 recomputes the
+# Gaussian, alpha and T (10 FLOP: quadratic, exp counted as one, clamp,
+# T = T' / (1 - a)), forms dL/dc (3 FMA), dL/da from the colour behind and
+# dL/dC (3 FMA + 2), the running sum of the colour behind (3), dL/dq (2),
+# and accumulates the nine per-Gaussian sums (2D mean 2 x 3, conic 3 x 2,
+# opacity 2): 50 FLOP.
+FLOP_PER_BLEND_BWD = 50.0
+
+
+def composite_bwd_roofline(P, torch, np, vb, ds, cams, prm, targets, scale, W, H):
+    """The train step's dominant kernel, the compositing backward, against
+    the FP32 vector peak: each training view alone on the GPU, forward then
+    L1 gradient then backward, with HIP events around the compositing
+    backward; units = the entries each pixel consumed (Sigma last)."""
+    from paper_2403_17898_amd import _lib as L
+    from paper_2403_17898_amd.hip_events import HipEvent
+    ev = [HipEvent() for _ in range(2 * L.OCTGS_RASTER_BWD_STAGES)]
+    sh = P.stream_handle(None)
+    dimg = torch.empty(3, H, W, device=vb.gauss.device)
+    loss = torch.zeros(1, device=vb.gauss.device)
+    t_ms, blends, pairs = 0.0, 0, 0
+    for c, tg in zip(cams, targets):
+        vb.render(ds, c, prm)
+        P.l1_loss_grad(vb.rgb, tg, scale, dimg, loss)
+        vb.rasterize_bwd(c, prm, dimg, stage_events=ev)
+        torch.cuda.synchronize()
+        t_ms += ev[0].elapsed_ms(ev[1])
+        blends += int(vb.last.sum(dtype=torch.int64).item())
+        pairs += vb.stats()["n_pairs"]
+    n = len(cams)
+    ms = t_ms / n
+    tf = FLOP_PER_BLEND_BWD * blends / n / (ms * 1e-3) / 1e12
+    # algorithmic bytes: 40 B read and 36 B written per pair (its record and
+    # its nine gradients), 32 B per pixel (T, last, dL/dC, ...)
+    alg = (40.0 + 36.0) * pairs / n + 32.0 * W * H
+    return {"kernel": "composite_bwd", "bound": "alu", "achieved": round(tf, 2),
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "flop_per_blend": FLOP_PER_BLEND_BWD,
+            "blends_per_launch": round(blends / n), "launch_ms": round(ms, 5),
+            "algorithmic_bytes": round(alg), "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
+            "traffic": None}
+
+
 def train_step_timing(args, P, S, torch, np, sc=None, views=None,
                       workload="500k anchors / 6 levels, 4 views at 1600x1066, mean-L1, Adam",
                       with_full_loss=True, oracle_step=False):
@@ -996,6 +1073,8 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
 
     ms, adam_ms, first_loss, last_loss = timed_steps(False)
     mv.check()  # no view of any step overflowed, hit a wait bound or was truncated
+    roof_bwd = composite_bwd_roofline(P, torch, np, mv.vbs[0], ds, cams, prm, targets, scale,
+                                      W, H)
     cpu_step = None
     if oracle_step:
         # the oracle's step on the same views and targets: FP64 forward and
@@ -1018,7 +1097,7 @@ def train_step_timing(args, P, S, torch, np, sc=None, views=None,
            "n_anchors": sc.n, "ms_per_step": round(ms, 3), "adam_ms": round(adam_ms, 3),
            "steps_timed": args.train_steps, "loss_first": round(first_loss, 6),
            "loss_last": round(last_loss, 6), "max_selected": max_sel, "max_pairs": max_pairs,
-           "views_in_flight": nbuf}
+           "views_in_flight": nbuf, "roofline_bwd": roof_bwd}
     if cpu_step is not None:
         res["cpu_oracle_step"] = cpu_step
     if not with_full_loss:
@@ -1152,13 +1231,14 @@ def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, views: in
     total = sum(sum(v) for v in agg.values())
     tl = [f"{'kernel':<44}{'calls':>7}{'avg_us':>10}{'min_us':>10}{'max_us':>10}{'share':>8}"]
     for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:24]:
-        short = name.split("(")[0].replace("octgs::", "").replace("(anonymous namespace)::", "")
+        short = name.replace("(anonymous namespace)::", "").replace("octgs::", "")
+        short = short.split("(")[0].removeprefix("void ")
         tl.append(f"{short[:43]:<44}{len(v):>7}{sum(v) / len(v):>10.2f}{min(v):>10.2f}"
                   f"{max(v):>10.2f}{100 * sum(v) / total:>7.2f}%")
     trace_txt = (
         "Kernel trace of the street-scene render benchmark (1M anchors, 8 LOD levels, 1920x1080;\n"
-        f"the {views} views of the zoom-out), --quick run\n"
-        "(no PSNR sweep, no train step, no skip study, no explicit path, no city scene).\n\n"
+        f"the {views} views of the zoom-out), --stages-only run (the sizing pass and the\n"
+        "per-stage timing loop, one view at a time).\n\n"
         f"command ($REPO = repository root):\n  {cmds[0]}\n\n" + "\n".join(tl) + "\n\n"
         f"per-stage timing loop (the last {views} views), kernel-trace average per view:\n" +
         "\n".join(f"  {k:<22}{per[k][3]:>9.2f} us" for k in per) + "\n"
@@ -1171,8 +1251,81 @@ def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, views: in
         print(f"wrote profiles/{name}")
 
 
+def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_name: str,
+                       kernels=None, title=None):
+    """Writes profiles/<out_name> from one rocprofv3 --pmc run of SQ counters
+    (and GRBM_GUI_ACTIVE) over the per-stage timing loop: per kernel, VALU
+    busy, VALU lane utilisation, MFMA busy and the BF16 MFMA rate the
+    counters imply, each over the last `views` views' dispatches.
+    GRBM_GUI_ACTIVE reads the sum over the 8 XCDs of the GPU-busy cycles
+    (8x a dispatch's duration in cycles), so it is divided by 8; the SIMD
+    count is 1024 (256 CUs x 4)."""
+    from collections import defaultdict
+    rows = _csv_rows(sq_dir, "counter_collection.csv")
+    trace = _csv_rows(trace_dir, "kernel_trace.csv")
+    by = defaultdict(dict)
+    name = {}
+    for r in rows:
+        d = int(r["Dispatch_Id"])
+        by[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        name[d] = r["Kernel_Name"]
+    order = sorted(by)
+    simds = 1024
+    lines = [f"{'kernel':<22}{'per unit':>9}{'us':>8}{'waves':>8}{'VALU busy':>11}{'lane use':>10}"
+             f"{'MFMA busy':>11}{'BF16 TF/s':>11}{'of peak':>9}"]
+    for label, sub, per_view in (kernels or VIEW_KERNELS):
+        n = per_view * views
+        ds = [d for d in order if sub in name[d]][-n:]
+        if len(ds) < n:
+            raise SystemExit(f"only {len(ds)} dispatches of {sub} with counters, need {n}")
+        c = defaultdict(float)
+        for d in ds:
+            for k, v in by[d].items():
+                c[k] += v
+        cyc = c["GRBM_GUI_ACTIVE"] / 8.0
+        t = _last(trace, sub, n)
+        us = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in t) / 1e3 / n
+        valu = 4.0 * c["SQ_ACTIVE_INST_VALU"] / (simds * cyc)
+        lane = c["SQ_THREAD_CYCLES_VALU"] / max(64.0 * c["SQ_ACTIVE_INST_VALU"], 1.0)
+        mfma = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc)
+        tf = c["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512 / n / (us * 1e-6) / 1e12
+        lines.append(f"{label:<22}{per_view:>9}{us:>8.1f}{c['SQ_WAVES'] / n:>8.0f}{100 * valu:>10.1f}%"
+                     f"{100 * lane:>9.1f}%{100 * mfma:>10.2f}%{tf:>11.2f}{tf / 2500.0:>9.4f}")
+    head = title.replace("\\n", "\n") + "\n" if title else (
+        "SQ counters of the street-scene render benchmark (1M anchors, 8 LOD levels, 1920x1080,\n"
+        f"the {views} views of the zoom-out, one view at a time), per kernel over the per-stage\n"
+        "timing loop (--stages-only), from one rocprofv3 --pmc run:\n")
+    txt = (
+        head +
+        "  VALU busy  = 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x cycles)   (the counter is in quad-cycles)\n"
+        "  lane use   = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)\n"
+        "  MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles)\n"
+        "  BF16 TF/s  = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 per dispatch / kernel-trace duration,\n"
+        "               'of peak' against the 2.5 PFLOP/s dense BF16 peak\n"
+        "  cycles     = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs);\n"
+        "  us         = kernel-trace average duration of the same dispatches (a separate run\n"
+        "               without counters).\n\n"
+        f"command ($REPO = repository root):\n  {cmd}\n\n" + "\n".join(lines) + f"\nunits: {views}\n")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
+        f.write(txt)
+    print(f"wrote profiles/{out_name}")
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        # python bench.py --summarize-counters SQ_DIR TRACE_DIR UNITS CMD OUT_NAME [SPEC [TITLE]]
+        # SPEC: "label=kernel-name substring:dispatches per unit;..." (default: the
+        # per-view render kernels); TITLE: first lines of the summary
+        a = sys.argv[2:]
+        spec = None
+        if len(a) > 5:
+            spec = []
+            for item in a[5].split(";"):
+                lab, rest = item.split("=", 1)
+                sub, cnt = rest.rsplit(":", 1)
+                spec.append((lab, sub, int(cnt)))
+        summarize_counters(a[0], a[1], int(a[2]), a[3], a[4], spec, a[6] if len(a) > 6 else None)
+    elif len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
         # python bench.py --summarize-profiles TRACE_DIR FETCH_DIR WRITE_DIR VIEWS CMD1 CMD2 CMD3
         a = sys.argv[2:]
         summarize_profiles(a[0], a[1], a[2], int(a[3]), a[4:7])

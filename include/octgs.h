@@ -117,12 +117,22 @@ typedef struct {
 /* Decoded neural Gaussians, planar [14][capacity] FP32 in the field order
  * mean(3), scale(3), quat(w, x, y, z), opacity, rgb(3).  Slot s*k + i holds
  * Gaussian i of the s-th listed anchor.  *count (device) is the number of
- * slots written by octgs_decode and read by octgs_rasterize_fwd. */
+ * slots written by octgs_decode and read by octgs_rasterize_fwd.  status
+ * (device, nullable): a caller-owned word the calls that write these
+ * Gaussians, and the rasterizer that reads them, OR their device-detected
+ * conditions into (OCTGS_STATUS_* bits), so a caller can render many frames
+ * and check once; the library never clears it. */
 typedef struct {
   int64_t capacity;
   float *data;
   uint32_t *count;
+  uint32_t *status;
 } octgs_gaussians;
+
+/* Status bits OR-ed into octgs_gaussians.status. */
+#define OCTGS_STATUS_PAIR_OVERFLOW 1u /* octgs_rasterize_fwd: the pair list overflowed (image incomplete) */
+#define OCTGS_STATUS_SYNC_ERROR 2u    /* octgs_rasterize_fwd: a look-back wait hit its bound (invalid) */
+#define OCTGS_STATUS_TRUNCATED 4u     /* octgs_decode*: more listed anchors than capacity / k (the rest dropped) */
 
 /* Rasterizer constants.  alpha_max clamps each per-pixel alpha; entries with
  * alpha below alpha_min are skipped; a pixel stops after the Gaussian that
@@ -293,12 +303,17 @@ OCTGS_API int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *
  * recovers transmittance as T_i = T_{i+1} / (1 - a_i) from T_final, so no
  * per-pixel list is kept.  g, cam, p, the capacities and the workspace must be
  * those of the forward call, unchanged since; p->flags must include
- * OCTGS_RASTER_TRAIN (OCTGS_EINVAL otherwise). */
+ * OCTGS_RASTER_TRAIN (OCTGS_EINVAL otherwise).  stage_events (nullable):
+ * 2 * OCTGS_RASTER_BWD_STAGES hipEvent_t; events 2s and 2s+1 are recorded on
+ * `stream` around stage s (0 the compositing backward, 1 the per-Gaussian
+ * reduction and the projection backward). */
+#define OCTGS_RASTER_BWD_STAGES 2
 OCTGS_API int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera *cam,
                                   const octgs_raster_params *p, int64_t pair_capacity,
                                   const float *T_final, const uint32_t *last,
                                   const float *dL_drgb, float *d_gauss, void *ws,
-                                  size_t ws_bytes, octgs_stream stream);
+                                  size_t ws_bytes, void *const *stage_events,
+                                  octgs_stream stream);
 
 /* Gradients of the anchor arrays (device, same shapes as octgs_anchors'
  * pos, feat, offsets, offset_scale, base_scale).  Accumulated (+=). */
@@ -421,14 +436,22 @@ OCTGS_API int octgs_skip_predict(const octgs_anchors *a, const octgs_camera *cam
 /* Workspace bytes of octgs_skip_train_grad for a batch size. */
 OCTGS_API size_t octgs_skip_train_workspace_bytes(int32_t batch);
 
-/* Gradient of the mean weighted binary cross-entropy of the predictor (FP32)
- * on a batch: z [batch][37], labels y [batch] in {0, 1}, positives weighted
- * by pos_weight.  Gradients are overwritten; *loss (device) is incremented by
- * the batch loss.  Pair with octgs_adam_step for the update. */
+/* Gradient of the mean weighted binary cross-entropy of the predictor on a
+ * batch: row b of the batch is z[r][0..36], label y[r] in {0, 1}, with
+ * r = rows[b] (device, nullable: r = b); positives are weighted by
+ * pos_weight.  Inputs whose bit in input_mask is clear read as zero, so their
+ * rows of the w1 gradient are zero (all 37 inputs: (1 << 37) - 1).  Forward
+ * and backward run on BF16 MFMA (16x16x16, FP32 accumulation) with BF16
+ * copies of the FP32 weights; layer 3, the loss and the bias gradients are
+ * FP32.  Gradients are overwritten; *loss (device) is incremented by the
+ * batch loss.  The result does not depend on scheduling: each block sums its
+ * rows in a fixed order and the block sums are added in block order.
+ * Every rows[b] must index a row of z and y (not checked).  Pair with
+ * octgs_adam_step for the update. */
 OCTGS_API int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float *y,
-                                    int32_t batch, float pos_weight,
-                                    const octgs_skip_net_grads *grads, float *loss, void *ws,
-                                    size_t ws_bytes, octgs_stream stream);
+                                    const uint32_t *rows, int32_t batch, uint64_t input_mask,
+                                    float pos_weight, const octgs_skip_net_grads *grads,
+                                    float *loss, void *ws, size_t ws_bytes, octgs_stream stream);
 
 /* ---- explicit Gaussians on the anchors --------------------------------
  * The 3D-GS instance of the anchor framework (Sec. V, "Our-3D-GS"): every
@@ -554,23 +577,6 @@ OCTGS_API int octgs_densify_decide(const octgs_anchors *a, const octgs_densify_s
                                    const octgs_densify_params *p, float *lod_bias,
                                    int8_t *grow_level, uint8_t *prune, uint32_t *counts,
                                    octgs_stream stream);
-
-/* Status bits of octgs_frame_status. */
-#define OCTGS_STATUS_PAIR_OVERFLOW 1u /* the pair list overflowed: the image is incomplete */
-#define OCTGS_STATUS_SYNC_ERROR 2u    /* a look-back wait hit its bound: the output is invalid */
-#define OCTGS_STATUS_TRUNCATED 4u     /* more listed anchors than the Gaussian capacity holds */
-
-/* Adds the conditions one frame detected on the device to a caller-owned
- * status word, so a caller can render many frames and check once:
- * *status (device u32) |= OCTGS_STATUS_PAIR_OVERFLOW / _SYNC_ERROR from the
- * stats header octgs_rasterize_fwd left at byte 0 of ws, and
- * OCTGS_STATUS_TRUNCATED if count (nullable, device: the anchors listed for
- * the decode) times k exceeds gauss_capacity (the decode then drops the
- * rest).  Enqueue on the frame's stream after its octgs_rasterize_fwd;
- * frames on several streams may add to one word (atomic OR).  The word is
- * never cleared by the library. */
-OCTGS_API int octgs_frame_status(const void *ws, const uint32_t *count, int32_t k,
-                                 int64_t gauss_capacity, uint32_t *status, octgs_stream stream);
 
 /* Device pointers into a rasterizer workspace (as laid out for these
  * capacities and image size) to the state octgs_rasterize_fwd leaves there:

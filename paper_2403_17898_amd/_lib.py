@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboctgs.so")
 OCTGS_OK, OCTGS_EINVAL, OCTGS_ENOSPC, OCTGS_EHIP, OCTGS_EUNSUPPORTED = 0, -1, -2, -3, -4
 OCTGS_FP32, OCTGS_BF16 = 0, 1
 OCTGS_RASTER_STAGES = 5
+OCTGS_RASTER_BWD_STAGES = 2
 OCTGS_SELECT_NOALLOC_MAX_ANCHORS = 1 << 23
 OCTGS_RASTER_TRAIN = 1
 OCTGS_RASTER_TILE_ORDER = 2
@@ -47,7 +48,7 @@ class Mlp(ctypes.Structure):
 
 
 class Gaussians(ctypes.Structure):
-    _fields_ = [("capacity", _i64), ("data", _p), ("count", _p)]
+    _fields_ = [("capacity", _i64), ("data", _p), ("count", _p), ("status", _p)]
 
 
 class RasterParams(ctypes.Structure):
@@ -110,7 +111,7 @@ SIGNATURES = [
                                    ctypes.c_size_t, _p, _p]),
     ("octgs_rasterize_bwd", _i32, [ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
                                    ctypes.POINTER(RasterParams), _i64, _p, _p, _p, _p, _p,
-                                   ctypes.c_size_t, _p]),
+                                   ctypes.c_size_t, _p, _p]),
     ("octgs_decode_bwd_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32]),
     ("octgs_decode_bwd", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),
                                 ctypes.POINTER(Camera), _p, _p, _p, _i64,
@@ -131,8 +132,8 @@ SIGNATURES = [
                                   ctypes.POINTER(SkipNet), _f, _p, _p, _i64, _p, _p, _p, _p,
                                   ctypes.c_size_t, _p]),
     ("octgs_skip_train_workspace_bytes", ctypes.c_size_t, [_i32]),
-    ("octgs_skip_train_grad", _i32, [ctypes.POINTER(SkipNet), _p, _p, _i32, _f,
-                                     ctypes.POINTER(SkipNet), _p, _p, ctypes.c_size_t, _p]),
+    ("octgs_skip_train_grad", _i32, [ctypes.POINTER(SkipNet), _p, _p, _p, _i32, ctypes.c_uint64,
+                                     _f, ctypes.POINTER(SkipNet), _p, _p, ctypes.c_size_t, _p]),
     ("octgs_prepare_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit), _p, _p,
                                       _p, _p]),
     ("octgs_decode_explicit", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Explicit),
@@ -146,7 +147,6 @@ SIGNATURES = [
                                         ctypes.POINTER(DensifyStats), _p]),
     ("octgs_densify_decide", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(DensifyStats),
                                     ctypes.POINTER(DensifyParams), _p, _p, _p, _p, _p]),
-    ("octgs_frame_status", _i32, [_p, _p, _i32, _i64, _p, _p]),
     ("octgs_raster_views", _i32, [_p, _i64, _i64, _i32, _i32, ctypes.POINTER(_p),
                                   ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
     ("octgs_strerror", ctypes.c_char_p, [_i32]),

@@ -60,6 +60,7 @@ struct DecodeArgs {
   float *out;
   int64_t cap;
   uint32_t *out_count;
+  uint32_t *status;  // nullable: OCTGS_STATUS_TRUNCATED when the listed anchors exceed the capacity
 };
 
 // layer-2 column tile c -> (head, first output column of the tile in that head)
@@ -194,7 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
 
   // blocks beyond the listed anchors exit before loading any weights
   const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
-  if (blockIdx.x == 0 && t == 0) *a.out_count = m_total * (uint32_t)k;
+  if (blockIdx.x == 0 && t == 0) {
+    *a.out_count = m_total * (uint32_t)k;
+    if (a.status && *a.count > (uint32_t)a.cap_anchors) atomicOr(a.status, OCTGS_STATUS_TRUNCATED);
+  }
   if ((uint64_t)blockIdx.x * kTM >= m_total) return;
 
   // ---- weights of this wave's column tiles, kept in registers ----
@@ -406,7 +410,7 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
     pa.w1[h] = mlp->w1[h]; pa.b1[h] = mlp->b1[h]; pa.w2[h] = mlp->w2[h]; pa.b2[h] = mlp->b2[h];
   }
   pa.ws = ws;
-  DecodeArgs a;
+  DecodeArgs a{};
   a.n = an->n;
   a.k = an->k;
   a.W = mlp->width;
@@ -428,6 +432,7 @@ extern "C" int octgs_decode(const octgs_anchors *an, const octgs_mlp *mlp,
   a.lod_bias = an->lod_bias;
   a.idx = idx; a.count = count; a.out = out->data; a.cap = out->capacity;
   a.out_count = out->count;
+  a.status = out->status;
   const int64_t tiles = std::max<int64_t>(1, (a.cap_anchors + kTM - 1) / kTM);
   // persistent blocks: each loads its weight slices once and loops over
   // tiles; as many as stay resident at once (2 FP32 or 4 BF16 blocks per

@@ -131,6 +131,7 @@ struct ExArgs {
   float *out;
   int64_t cap;
   uint32_t *out_count;
+  uint32_t *status;  // nullable: OCTGS_STATUS_TRUNCATED when the listed anchors exceed the capacity
   // backward
   const float *dg;
   int64_t dstride;
@@ -194,7 +195,10 @@ __global__ __launch_bounds__(kExT) void k_decode_explicit(ExArgs a) {
   const int t = threadIdx.x, k = a.k;
   const uint32_t m_total = min(*a.count, (uint32_t)a.cap_anchors);
   const int64_t total = (int64_t)m_total * k;
-  if (blockIdx.x == 0 && t == 0) *a.out_count = (uint32_t)total;
+  if (blockIdx.x == 0 && t == 0) {
+    *a.out_count = (uint32_t)total;
+    if (a.status && *a.count > (uint32_t)a.cap_anchors) atomicOr(a.status, OCTGS_STATUS_TRUNCATED);
+  }
   for (int64_t s0 = (int64_t)blockIdx.x * kExT; s0 < total; s0 += (int64_t)gridDim.x * kExT) {
     const int nsl = (int)min<int64_t>(kExT, total - s0);
     const int64_t s = s0 + min(t, nsl - 1);
@@ -453,7 +457,7 @@ int octgs_decode_explicit(const octgs_anchors *an, const octgs_explicit *e,
                           int precision, const octgs_gaussians *out, octgs_stream stream) {
   if (!out || !out->data || !out->count || out->capacity < 0) return OCTGS_EINVAL;
   if (precision != OCTGS_FP32 && precision != OCTGS_BF16) return OCTGS_EINVAL;
-  ExArgs a;
+  ExArgs a{};
   const int st = fill_common(an, e, cam, idx, count, out->capacity, a);
   if (st != OCTGS_OK) return st;
   const bool bf16 = precision == OCTGS_BF16;
@@ -471,7 +475,7 @@ int octgs_decode_explicit(const octgs_anchors *an, const octgs_explicit *e,
                   !(cam->lod_scale2 > 0.0f) || !(an->d_max > 0.0f)))
     return OCTGS_EINVAL;
   a.sh = sh;
-  a.out = out->data; a.cap = out->capacity; a.out_count = out->count;
+  a.out = out->data; a.cap = out->capacity; a.out_count = out->count; a.status = out->status;
   const int grid = grid_for(out->capacity);
   if (bf16) launch_decode<true>(e->sh_degree, grid, s, a);
   else launch_decode<false>(e->sh_degree, grid, s, a);
@@ -484,7 +488,7 @@ int octgs_decode_explicit_bwd(const octgs_anchors *an, const octgs_explicit *e,
                               int64_t gauss_capacity, const octgs_explicit_grads *g,
                               octgs_stream stream) {
   if (!d_gauss || !g) return OCTGS_EINVAL;
-  ExArgs a;
+  ExArgs a{};
   const int st = fill_common(an, e, cam, idx, count, gauss_capacity, a);
   if (st != OCTGS_OK) return st;
   if (cam->lod_blend) return OCTGS_EUNSUPPORTED;

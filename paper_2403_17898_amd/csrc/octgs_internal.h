@@ -367,35 +367,5 @@ __device__ __forceinline__ uint32_t chained_lookback(uint32_t *status, uint32_t 
   return excl;
 }
 
-// ---------------------------------------------------------------------------
-// FP32 GEMM: C (+)= op(A) op(B) [+ bias] [* (mask > 0)]
-// op(A) is M x K: A[m*lda + k], or A[k*lda + m] when transA (reluA: max(0, .)).
-// op(B) is K x N: B[k*ldb + n], or B[n*ldb + k] when transB.
-// One of M (dyn_dim = 1) or K (dyn_dim = 2) may be min(*dyn, dyn_cap).
-// accumulate adds into C (atomically when splitk > 1).
-// ---------------------------------------------------------------------------
-// C = op(A) op(B) (+ bias, masked, accumulated), FP32.
-struct Gemm {
-  const float *A, *B;
-  float *C;
-  int64_t lda, ldb, ldc;
-  int transA, transB, reluA;
-  int M, N, K;
-  const uint32_t *dyn;
-  int dyn_dim, dyn_cap;
-  const float *bias;
-  const float *mask;
-  int64_t ldm;
-  int accumulate, splitk;
-};
-
-hipError_t gemm(const Gemm &g, int64_t m_cap, hipStream_t s);
-Gemm gemm_base();
-// out[n] += sum over the first M rows of Y[m * ld + n], M = dyn ? min(*dyn, cap) : cap
-hipError_t colsum(const float *Y, int64_t ld, int N, const uint32_t *dyn, int cap, float *out,
-                  hipStream_t s);
-// three column sums in one launch: out3[g][n] += sum_m Y3[g][m * ld + n], n < N3[g]
-
-hipError_t fill(float *p, int64_t n, float v, hipStream_t s);
 
 }  // namespace octgs

@@ -685,6 +685,7 @@ struct CompArgs {
   float *rgb, *T_final;
   uint32_t *last;
   float *gauss_w;
+  uint32_t *status;  // nullable: the frame's pair-overflow / look-back bits are OR-ed in
 };
 
 // One 16x16 tile per block of one wave (64 threads); each thread owns four
@@ -837,6 +838,13 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
 template <bool LOG>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompArgs a) {
   __shared__ CompLds<LOG> lds;
+  // the conditions of the earlier stages are final here: one thread adds
+  // them to the caller's status word
+  if (a.status && blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t f = (a.ws.hdr->pair_overflow ? OCTGS_STATUS_PAIR_OVERFLOW : 0u) |
+                       (a.ws.hdr->sync_error ? OCTGS_STATUS_SYNC_ERROR : 0u);
+    if (f) atomicOr(a.status, f);
+  }
   if (a.alpha_min > 0.0f)
     composite_tile<LOG, true>(a, lds);
   else
@@ -899,17 +907,6 @@ int tile_sort_passes(int ntiles) {
   int bits = 1;
   while ((1 << bits) < ntiles) ++bits;
   return (bits + 7) / 8;
-}
-
-// One thread: OR a frame's device-detected conditions into a status word.
-__global__ void k_frame_status(const RasterHeader *__restrict__ hdr,
-                               const uint32_t *__restrict__ count, int k, int64_t gcap,
-                               uint32_t *__restrict__ status) {
-  uint32_t f = 0;
-  if (hdr->pair_overflow) f |= OCTGS_STATUS_PAIR_OVERFLOW;
-  if (hdr->sync_error) f |= OCTGS_STATUS_SYNC_ERROR;
-  if (count && (uint64_t)*count * (uint64_t)k > (uint64_t)gcap) f |= OCTGS_STATUS_TRUNCATED;
-  if (f) atomicOr(status, f);
 }
 
 }  // namespace octgs
@@ -1003,6 +1000,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   ca.T_final = T_final;
   ca.last = last;
   ca.gauss_w = gauss_w;
+  ca.status = g->status;
   mark(8);
   if (gauss_w)
     hipLaunchKernelGGL(k_composite<true>, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
@@ -1011,14 +1009,6 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
     hipLaunchKernelGGL(k_composite<false>, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
                        dim3(kFwdThreads), 0, s, ca);
   mark(9);
-  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
-}
-
-int octgs_frame_status(const void *ws, const uint32_t *count, int32_t k, int64_t gauss_capacity,
-                       uint32_t *status, octgs_stream stream) {
-  if (!ws || !status || k < 1 || gauss_capacity < 0) return OCTGS_EINVAL;
-  hipLaunchKernelGGL(k_frame_status, dim3(1), dim3(1), 0, (hipStream_t)stream,
-                     (const RasterHeader *)ws, count, k, gauss_capacity, status);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

@@ -471,7 +471,8 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
                                    const octgs_raster_params *p, int64_t pair_capacity,
                                    const float *T_final, const uint32_t *last,
                                    const float *dL_drgb, float *d_gauss, void *wsp,
-                                   size_t ws_bytes, octgs_stream stream) {
+                                   size_t ws_bytes, void *const *stage_events,
+                                   octgs_stream stream) {
   if (!g || !cam || !p || !T_final || !last || !dL_drgb || !d_gauss || !wsp) return OCTGS_EINVAL;
   // the pair indices of the forward's tile sort are kept only in training mode
   if (!(p->flags & OCTGS_RASTER_TRAIN)) return OCTGS_EINVAL;
@@ -484,6 +485,9 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
     return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
   RasterWs ws = raster_layout(wsp, g->capacity, pair_capacity, cam->width, cam->height);
+  auto mark = [&](int i) {
+    if (stage_events && stage_events[i]) (void)hipEventRecord((hipEvent_t)stage_events[i], s);  // timing only
+  };
   const int ntiles = ws.tiles_x * ws.tiles_y;
   BwdArgs b;
   b.ws = ws;
@@ -496,8 +500,11 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   b.T_final = T_final;
   b.dimg = dL_drgb;
   b.last = last;
+  mark(0);
   hipLaunchKernelGGL(k_composite_bwd, dim3(tile_grid_blocks(ws.tiles_x, ws.tiles_y)),
                      dim3(kBwdThreads), 0, s, b);
+  mark(1);
+  mark(2);
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 2048);
   hipLaunchKernelGGL(k_pair_reduce, dim3(rgrid), dim3(kBlock), 0, s, ws);
   PBwdArgs pa;
@@ -514,5 +521,6 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   pa.dstride = g->capacity;
   const int pgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.gcap + kBlock - 1) / kBlock, 1), 4096);
   hipLaunchKernelGGL(k_project_bwd, dim3(pgrid), dim3(kBlock), 0, s, pa);
+  mark(3);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }

@@ -29,6 +29,10 @@ namespace octgs {
 
 namespace {
 
+// Thresholds and bound radii, one thread per anchor.  The offset rows (3k
+// floats per anchor) are staged through LDS: the block's rows are one
+// contiguous span, read with coalesced loads, then each thread reduces its
+// own row.
 __global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_max,
                                                     const uint8_t *__restrict__ level,
                                                     const float *__restrict__ bias,
@@ -37,7 +41,14 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_ma
                                                     const float *__restrict__ bscale,
                                                     float *__restrict__ thr2,
                                                     float *__restrict__ rho) {
-  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ float rows[kBlock * 3 * kMaxK];
+  const int rl = 3 * k;
+  const int64_t j0 = (int64_t)blockIdx.x * kBlock;
+  const int na = (int)min<int64_t>(kBlock, n - j0);
+  const float *src = offsets + (size_t)j0 * rl;
+  for (int e = threadIdx.x; e < na * rl; e += kBlock) rows[e] = src[e];
+  __syncthreads();
+  const int64_t j = j0 + threadIdx.x;
   if (j >= n) return;
   const int L = level[j];
   if (L == 0) {
@@ -48,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_ma
   }
   const float l0 = oscale[3 * j], l1 = oscale[3 * j + 1], l2 = oscale[3 * j + 2];
   float m = 0.0f;
-  const float *o = offsets + (size_t)j * k * 3;
+  const float *o = rows + threadIdx.x * rl;
   for (int i = 0; i < k; ++i) {
     float a = o[3 * i] * l0, b = o[3 * i + 1] * l1, c = o[3 * i + 2] * l2;
     float nn = sqrtf(__builtin_fmaf(a, a, __builtin_fmaf(b, b, c * c)));

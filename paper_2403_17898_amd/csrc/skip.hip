@@ -13,7 +13,8 @@
 // Inference runs the two 64-wide layers on BF16 MFMA (16x16x16) with FP32
 // accumulation and keeps an anchor iff its logit >= the threshold; the kept
 // anchors are compacted in ascending order so decoding is unchanged.
-// Training (FP32, binary cross-entropy) runs on the tiled GEMM.
+// Training (binary cross-entropy) runs forward and backward on BF16 MFMA
+// with FP32 master weights.
 #include "octgs_internal.h"
 
 namespace octgs {
@@ -231,47 +232,262 @@ __global__ __launch_bounds__(kBlock) void k_flag_scatter(const uint32_t *count, 
     *out_count = prefix + gpre[ng - 1] + (uint32_t)__popcll(gmask[ng - 1]);
 }
 
-// Binary cross-entropy on logits, mean over the batch, positives weighted:
-// d = wgt (sigmoid(x) - y) / B; loss += wgt * (softplus(x) - y x) / B.
-__global__ __launch_bounds__(kBlock) void k_bce(const float *x, const float *y, int B, float pw,
-                                                float *d, float *loss) {
-  __shared__ float red[4];
-  float acc = 0.0f;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < B; i += gridDim.x * kBlock) {
-    const float xi = x[i], yi = y[i];
-    const float wgt = yi > 0.5f ? pw : 1.0f;
-    const float sg = 1.0f / (1.0f + __expf(-xi));
-    d[i] = wgt * (sg - yi) / (float)B;
-    const float sp = fmaxf(xi, 0.0f) + log1pf(__expf(-fabsf(xi)));
-    acc += wgt * (sp - yi * xi);
-  }
-  acc = block_sum_f(acc, red);  // one atomic per block on the loss
-  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc / (float)B);
-}
+// ---- training: one fused BF16 MFMA pass per batch ----------------------
+// Weighted binary cross-entropy on the logit x of a row with label y:
+//   loss = wgt (softplus(x) - y x),  dloss/dx = wgt (sigmoid(x) - y),
+// wgt = pos_weight for positives and 1 otherwise, averaged over the batch.
+// Forward and backward of the three layers run per tile of 64 rows: the two
+// 64-wide layers, dH1 = dH2 W2^T and both weight gradients dW = X^T dY (the
+// tile's rows being the reduction dimension) are BF16 MFMA products with
+// FP32 accumulation on BF16 copies of the FP32 master weights; layer 3, the
+// loss and the bias gradients stay in FP32.  Each block keeps its gradient
+// sums in registers over its tiles and writes them once; a second kernel adds
+// the block partials in block order, so the result does not depend on timing.
+constexpr int kTR = 64;            // batch rows per tile
+constexpr int kTrainBlocks = 256;  // partial-sum blocks at most
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kZ * kH;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + kH;
+constexpr int kOffLoss = kOffB3 + 1;
+constexpr int kPartLen = kOffLoss + 1;  // floats per block partial
 
-struct TrainLayout {
-  float *H1, *H2, *X3, *dX3, *dH2, *dH1;
-  size_t bytes;
+struct TrainArgs {
+  const float *w1, *b1, *w2, *b2, *w3, *b3;
+  const float *z, *y;
+  const uint32_t *rows;  // nullable: batch row b is row rows[b] of z and y
+  int B;
+  uint64_t in_mask;      // bit i clear: input i reads as zero
+  float pw;
+  float *part;           // [gridDim.x][kPartLen]
 };
 
-TrainLayout train_layout(void *base, int B) {
-  TrainLayout L;
-  char *p = (char *)base;
-  size_t off = 0;
-  auto take = [&](size_t b) -> float * {
-    float *r = p ? (float *)(p + off) : nullptr;
-    off += (b + 255) & ~(size_t)255;
-    return r;
-  };
-  const size_t m = (size_t)std::max(B, 1);
-  L.H1 = take(m * kH * 4);
-  L.H2 = take(m * kH * 4);
-  L.X3 = take(m * 4);
-  L.dX3 = take(m * 4);
-  L.dH2 = take(m * kH * 4);
-  L.dH1 = take(m * kH * 4);
-  L.bytes = off;
-  return L;
+struct TrainLds {
+  alignas(16) uint16_t z[kTR][kZPad + 8];  // BF16 inputs of the tile
+  alignas(16) uint16_t h1[kTR][kH + 8];    // BF16 ReLU(layer 1)
+  alignas(16) uint16_t d2[kTR][kH + 8];    // BF16 dloss/d(layer-2 pre-activation)
+  alignas(16) uint16_t d1[kTR][kH + 8];    // BF16 dloss/d(layer-1 pre-activation)
+  float h2[kTR][kH + 1];       // FP32 ReLU(layer 2)
+  float dx[kTR];               // dloss/dlogit per row (0 on padding rows)
+  float yv[kTR];
+  float red[4][kH];
+};
+
+__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_skip_train(TrainArgs a) {
+  __shared__ TrainLds s;
+  const int t = threadIdx.x, w = t / kWave, l = __lane_id(), g = l / 16, lc = l % 16;
+  const int n = w * 16 + lc;  // this lane's column in every 16x16 MFMA tile
+  // BF16 fragments of W1 and W2 (forward) and of W2^T (for dH1)
+  s4 B1[3], B2[4], B2t[4];
+#pragma unroll
+  for (int ks = 0; ks < 3; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = ks * 16 + g * 4 + j;
+      B1[ks][j] = (short)f2bf(kk < kZ ? a.w1[kk * kH + n] : 0.0f);
+    }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = ks * 16 + g * 4 + j;
+      B2[ks][j] = (short)f2bf(a.w2[kk * kH + n]);
+      B2t[ks][j] = (short)f2bf(a.w2[n * kH + kk]);
+    }
+  const float bias1 = a.b1[n], bias2 = a.b2[n];
+  // elementwise work: thread t owns hidden column c for rows q*16 .. q*16+15
+  const int c = t & 63, q = t >> 6;
+  const float w3c = a.w3[c];
+  // layer 3: four threads per row, 16 hidden units each
+  const int r3 = t >> 2, p3 = t & 3;
+  float w3p[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) w3p[u] = a.w3[p3 * 16 + u];
+  const float b3 = a.b3[0], invB = 1.0f / (float)a.B;
+
+  f4 gW1[3], gW2[4];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) gW1[m] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) gW2[m] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  float gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, gloss = 0.0f;
+
+  const int ntiles = (a.B + kTR - 1) / kTR;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int r0 = tile * kTR, rows = min(kTR, a.B - r0);
+    for (int e = t; e < kTR * kZPad; e += kBlock) {
+      const int r = e / kZPad, col = e % kZPad;
+      float v = 0.0f;
+      if (r < rows && col < kZ && ((a.in_mask >> col) & 1u)) {
+        const size_t row = a.rows ? (size_t)a.rows[r0 + r] : (size_t)(r0 + r);
+        v = a.z[row * kZ + col];
+      }
+      s.z[r][col] = f2bf(v);
+    }
+    if (t < kTR) s.yv[t] = t < rows ? a.y[a.rows ? (size_t)a.rows[r0 + t] : (size_t)(r0 + t)] : 0.0f;
+    __syncthreads();
+    // layer 1
+#pragma unroll
+    for (int rt = 0; rt < kTR / 16; ++rt) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 3; ++ks) acc = mfma16(*(const s4 *)&s.z[rt * 16 + lc][ks * 16 + g * 4], B1[ks], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s.h1[rt * 16 + 4 * g + i][n] = f2bf(fmaxf(acc[i] + bias1, 0.0f));
+    }
+    __syncthreads();
+    // layer 2
+#pragma unroll
+    for (int rt = 0; rt < kTR / 16; ++rt) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acc = mfma16(*(const s4 *)&s.h1[rt * 16 + lc][ks * 16 + g * 4], B2[ks], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s.h2[rt * 16 + 4 * g + i][n] = fmaxf(acc[i] + bias2, 0.0f);
+    }
+    __syncthreads();
+    // layer 3, the loss and its derivative per row
+    {
+      float x = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x = __builtin_fmaf(s.h2[r3][p3 * 16 + u], w3p[u], x);
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      if (p3 == 0) {
+        float d = 0.0f;
+        if (r3 < rows) {
+          x += b3;
+          const float yy = s.yv[r3], wgt = yy > 0.5f ? a.pw : 1.0f;
+          d = wgt * (1.0f / (1.0f + expf(-x)) - yy) * invB;
+          gloss += wgt * (fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))) - yy * x);
+          gb3 += d;
+        }
+        s.dx[r3] = d;
+      }
+    }
+    __syncthreads();
+    // dH2 = dx w3 where layer 2 is active; dW3 and db2 in FP32
+#pragma unroll 4
+    for (int i = 0; i < kTR / 4; ++i) {
+      const int r = q * (kTR / 4) + i;
+      const float h = s.h2[r][c], dx = s.dx[r];
+      const float d = h > 0.0f ? dx * w3c : 0.0f;
+      gw3 = __builtin_fmaf(h, dx, gw3);
+      gb2 += d;
+      s.d2[r][c] = f2bf(d);
+    }
+    __syncthreads();
+    // dH1 = dH2 W2^T where layer 1 is active
+#pragma unroll
+    for (int rt = 0; rt < kTR / 16; ++rt) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acc = mfma16(*(const s4 *)&s.d2[rt * 16 + lc][ks * 16 + g * 4], B2t[ks], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rt * 16 + 4 * g + i;
+        const float d = bf2f(s.h1[r][n]) > 0.0f ? acc[i] : 0.0f;
+        gb1 += d;
+        s.d1[r][n] = f2bf(d);
+      }
+    }
+    // dW2 += H1^T dH2 over the tile's rows
+#pragma unroll
+    for (int ks = 0; ks < kTR / 16; ++ks) {
+      s4 bv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = (short)s.d2[ks * 16 + g * 4 + j][n];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        s4 av;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) av[j] = (short)s.h1[ks * 16 + g * 4 + j][mt * 16 + lc];
+        gW2[mt] = mfma16(av, bv, gW2[mt]);
+      }
+    }
+    __syncthreads();
+    // dW1 += Z^T dH1 over the tile's rows
+#pragma unroll
+    for (int ks = 0; ks < kTR / 16; ++ks) {
+      s4 bv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = (short)s.d1[ks * 16 + g * 4 + j][n];
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt) {
+        s4 av;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) av[j] = (short)s.z[ks * 16 + g * 4 + j][mt * 16 + lc];
+        gW1[mt] = mfma16(av, bv, gW1[mt]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // this block's partial sums
+  float *P = a.part + (size_t)blockIdx.x * kPartLen;
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = mt * 16 + 4 * g + i;
+      if (r < kZ) P[kOffW1 + r * kH + n] = gW1[mt][i];
+    }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P[kOffW2 + (mt * 16 + 4 * g + i) * kH + n] = gW2[mt][i];
+  // db1: the four lane groups g of a wave share column n
+  gb1 += __shfl_xor(gb1, 16, 64);
+  gb1 += __shfl_xor(gb1, 32, 64);
+  if (g == 0) P[kOffB1 + n] = gb1;
+  // db2 and dW3: the four row quarters q share column c
+  s.red[q][c] = gb2;
+  __syncthreads();
+  if (t < kH) P[kOffB2 + t] = s.red[0][t] + s.red[1][t] + s.red[2][t] + s.red[3][t];
+  __syncthreads();
+  s.red[q][c] = gw3;
+  __syncthreads();
+  if (t < kH) P[kOffW3 + t] = s.red[0][t] + s.red[1][t] + s.red[2][t] + s.red[3][t];
+  __syncthreads();
+  // db3 and the loss sit on the threads with p3 == 0
+  const float sb3 = wave_sum_f(gb3), sl = wave_sum_f(gloss);
+  if (l == 0) {
+    s.red[0][w] = sb3;
+    s.red[1][w] = sl;
+  }
+  __syncthreads();
+  if (t == 0) {
+    P[kOffB3] = s.red[0][0] + s.red[0][1] + s.red[0][2] + s.red[0][3];
+    P[kOffLoss] = (s.red[1][0] + s.red[1][1] + s.red[1][2] + s.red[1][3]) * invB;
+  }
+}
+
+// Sum of the block partials in block order; gradients are overwritten and
+// the loss is added to *loss.
+__global__ __launch_bounds__(kBlock) void k_skip_train_reduce(const float *part, int nblk,
+                                                              octgs_skip_net_grads gr,
+                                                              float *loss) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= kPartLen) return;
+  float acc = 0.0f;
+  for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * kPartLen + j];
+  if (j < kOffB1) gr.w1[j - kOffW1] = acc;
+  else if (j < kOffW2) gr.b1[j - kOffB1] = acc;
+  else if (j < kOffB2) gr.w2[j - kOffW2] = acc;
+  else if (j < kOffW3) gr.b2[j - kOffB2] = acc;
+  else if (j < kOffB3) gr.w3[j - kOffW3] = acc;
+  else if (j < kOffLoss) gr.b3[0] = acc;
+  else *loss += acc;
+}
+
+int train_blocks(int32_t batch) {
+  return (int)std::min<int64_t>(((int64_t)batch + kTR - 1) / kTR, kTrainBlocks);
 }
 
 FeatArgs feat_args(const octgs_anchors *an, const octgs_camera *cam, const uint32_t *idx,
@@ -356,10 +572,11 @@ int octgs_skip_predict(const octgs_anchors *an, const octgs_camera *cam, const o
 
 size_t octgs_skip_train_workspace_bytes(int32_t batch) {
   if (batch < 1) return 0;
-  return train_layout(nullptr, batch).bytes;
+  return (size_t)train_blocks(batch) * kPartLen * sizeof(float);
 }
 
-int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float *y, int32_t batch,
+int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float *y,
+                          const uint32_t *rows, int32_t batch, uint64_t input_mask,
                           float pos_weight, const octgs_skip_net_grads *gr, float *loss, void *ws,
                           size_t ws_bytes, octgs_stream stream) {
   if (!net || !z || !y || !gr || !loss || !ws || batch < 1) return OCTGS_EINVAL;
@@ -367,58 +584,19 @@ int octgs_skip_train_grad(const octgs_skip_net *net, const float *z, const float
   if (!gr->w1 || !gr->b1 || !gr->w2 || !gr->b2 || !gr->w3 || !gr->b3) return OCTGS_EINVAL;
   if (ws_bytes < octgs_skip_train_workspace_bytes(batch)) return OCTGS_ENOSPC;
   hipStream_t s = (hipStream_t)stream;
-  TrainLayout L = train_layout(ws, batch);
-  const int B = batch;
-  const int splitk = std::max(1, std::min(64, B / 256));
-  hipError_t e = hipSuccess;
-  // gradients are overwritten
-  e = fill(gr->w1, kZ * kH, 0.0f, s);
-  if (e == hipSuccess) e = fill(gr->b1, kH, 0.0f, s);
-  if (e == hipSuccess) e = fill(gr->w2, kH * kH, 0.0f, s);
-  if (e == hipSuccess) e = fill(gr->b2, kH, 0.0f, s);
-  if (e == hipSuccess) e = fill(gr->w3, kH, 0.0f, s);
-  if (e == hipSuccess) e = fill(gr->b3, 1, 0.0f, s);
-  if (e != hipSuccess) return OCTGS_EHIP;
-  Gemm g = gemm_base();
-  g.A = z; g.lda = kZ; g.B = net->w1; g.ldb = kH; g.C = L.H1; g.ldc = kH;
-  g.M = B; g.N = kH; g.K = kZ; g.bias = net->b1;
-  if ((e = gemm(g, B, s)) != hipSuccess) return OCTGS_EHIP;
-  g = gemm_base();
-  g.A = L.H1; g.lda = kH; g.reluA = 1; g.B = net->w2; g.ldb = kH; g.C = L.H2; g.ldc = kH;
-  g.M = B; g.N = kH; g.K = kH; g.bias = net->b2;
-  if ((e = gemm(g, B, s)) != hipSuccess) return OCTGS_EHIP;
-  g = gemm_base();
-  g.A = L.H2; g.lda = kH; g.reluA = 1; g.B = net->w3; g.ldb = 1; g.C = L.X3; g.ldc = 1;
-  g.M = B; g.N = 1; g.K = kH; g.bias = net->b3;
-  if ((e = gemm(g, B, s)) != hipSuccess) return OCTGS_EHIP;
-  hipLaunchKernelGGL(k_bce, dim3(std::min(1024, (B + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     L.X3, y, B, pos_weight, L.dX3, loss);
-  // layer 3
-  g = gemm_base();
-  g.A = L.H2; g.lda = kH; g.transA = 1; g.reluA = 1; g.B = L.dX3; g.ldb = 1; g.C = gr->w3; g.ldc = 1;
-  g.M = kH; g.N = 1; g.K = B; g.accumulate = 1; g.splitk = splitk;
-  if ((e = gemm(g, kH, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = colsum(L.dX3, 1, 1, nullptr, B, gr->b3, s)) != hipSuccess) return OCTGS_EHIP;
-  g = gemm_base();
-  g.A = L.dX3; g.lda = 1; g.B = net->w3; g.ldb = 1; g.transB = 1; g.C = L.dH2; g.ldc = kH;
-  g.M = B; g.N = kH; g.K = 1; g.mask = L.H2; g.ldm = kH;
-  if ((e = gemm(g, B, s)) != hipSuccess) return OCTGS_EHIP;
-  // layer 2
-  g = gemm_base();
-  g.A = L.H1; g.lda = kH; g.transA = 1; g.reluA = 1; g.B = L.dH2; g.ldb = kH; g.C = gr->w2; g.ldc = kH;
-  g.M = kH; g.N = kH; g.K = B; g.accumulate = 1; g.splitk = splitk;
-  if ((e = gemm(g, kH, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = colsum(L.dH2, kH, kH, nullptr, B, gr->b2, s)) != hipSuccess) return OCTGS_EHIP;
-  g = gemm_base();
-  g.A = L.dH2; g.lda = kH; g.B = net->w2; g.ldb = kH; g.transB = 1; g.C = L.dH1; g.ldc = kH;
-  g.M = B; g.N = kH; g.K = kH; g.mask = L.H1; g.ldm = kH;
-  if ((e = gemm(g, B, s)) != hipSuccess) return OCTGS_EHIP;
-  // layer 1
-  g = gemm_base();
-  g.A = z; g.lda = kZ; g.transA = 1; g.B = L.dH1; g.ldb = kH; g.C = gr->w1; g.ldc = kH;
-  g.M = kZ; g.N = kH; g.K = B; g.accumulate = 1; g.splitk = splitk;
-  if ((e = gemm(g, kZ, s)) != hipSuccess) return OCTGS_EHIP;
-  if ((e = colsum(L.dH1, kH, kH, nullptr, B, gr->b1, s)) != hipSuccess) return OCTGS_EHIP;
+  TrainArgs a;
+  a.w1 = net->w1; a.b1 = net->b1; a.w2 = net->w2; a.b2 = net->b2; a.w3 = net->w3; a.b3 = net->b3;
+  a.z = z;
+  a.y = y;
+  a.rows = rows;
+  a.B = batch;
+  a.in_mask = input_mask;
+  a.pw = pos_weight;
+  a.part = (float *)ws;
+  const int nblk = train_blocks(batch);
+  hipLaunchKernelGGL(k_skip_train, dim3(nblk), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_skip_train_reduce, dim3((kPartLen + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     s, (const float *)ws, nblk, *gr, loss);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 

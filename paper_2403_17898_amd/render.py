@@ -93,6 +93,14 @@ def raise_on_status(bits: int, what: str = "frames"):
         raise L.OctgsError(f"{what}: " + ", ".join(names))
 
 
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
 class DeviceScene:
     """An anchor set resident in HBM, with its per-scene Eq. 7 thresholds."""
 
@@ -127,15 +135,18 @@ class DeviceScene:
             self._mlp.w2[h] = self.mlp["w2_" + name].data_ptr()
             self._mlp.b2[h] = self.mlp["b2_" + name].data_ptr()
 
-    def refresh(self, stream=None):
+    def refresh(self, stream=None, bf16: bool = True):
         """Recompute what the library derives from the trained arrays: the
         Eq. 7 thresholds (lod_bias), the bound radii (offsets, offset_scale,
-        base_scale) and the BF16 feature copy.  Needed after every update of
-        those arrays (an optimiser step, a LOD-bias update) before the next
-        selection or decode."""
+        base_scale) and, unless bf16 is False, the BF16 feature copy.  Needed
+        after every update of those arrays (an optimiser step, a LOD-bias
+        update) before the next selection or decode.  A BF16 decode after a
+        refresh without the copy raises until the copy is refreshed."""
         L.check(L.lib().octgs_prepare_anchors(ctypes.byref(self._anchors), _ptr(self.thr2),
-                                             _ptr(self.bound_r), _ptr(self.feat_bf16),
+                                             _ptr(self.bound_r),
+                                             _ptr(self.feat_bf16) if bf16 else None,
                                              stream_handle(stream)), "octgs_prepare_anchors")
+        self.bf16_valid = bool(bf16)
 
     @classmethod
     def from_scene(cls, sc, stream=None) -> "DeviceScene":
@@ -394,29 +405,28 @@ class ViewBuffers:
         self.T = torch.empty((self.H, self.W), dtype=torch.float32, device=dev)
         self.last = torch.empty((self.H, self.W), dtype=torch.int32, device=dev)
         self.gauss_w = torch.empty(self.gcap, dtype=torch.float32, device=dev) if log_weights else None
+        # OCTGS_STATUS_* bits of every frame decoded and rasterized with these
+        # buffers since the last clear_status (the library ORs them in)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self._g = L.Gaussians()
         self._g.capacity = self.gcap
         self._g.data = self.gauss.data_ptr()
         self._g.count = self.gauss_count.data_ptr()
-        # OCTGS_STATUS_* bits of every frame passed to add_status since the last clear
-        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._g.status = self.status.data_ptr()
 
     # ---- frame status ----
-    def add_status(self, count: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
-                   stream=None):
-        """OR the last frame's device-detected conditions (pair overflow,
-        look-back bound, decode truncation of the `count` listed anchors,
-        default the selection) into `status` (default self.status); no sync."""
-        count = self.sel_count if count is None else count
-        status = self.status if status is None else status
-        L.check(L.lib().octgs_frame_status(_ptr(self.ras_ws), _ptr(count), self.k, self.gcap,
-                                           _ptr(status), stream_handle(stream)),
-                "octgs_frame_status")
+    def clear_status(self, stream=None):
+        """Zero the status word (enqueued on `stream`)."""
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            self.status.zero_()
 
-    def check_status(self, what: str = "frames", status: Optional[torch.Tensor] = None):
-        """Raise if any frame added to `status` flagged a condition (syncs)."""
-        status = self.status if status is None else status
-        raise_on_status(int(status.item()), what)
+    def check_status(self, what: str = "frames"):
+        """Raise if any frame since the last clear flagged a pair-list
+        overflow, a look-back wait bound or a truncated decode (syncs), then
+        clear the word."""
+        bits = int(self.status.item())
+        self.status.zero_()
+        raise_on_status(bits, what)
 
     # ---- stages ----
     def select(self, scene, cam: L.Camera, params: Optional[L.RasterParams] = None, stream=None):
@@ -435,6 +445,8 @@ class ViewBuffers:
                stream=None):
         idx = self.sel_idx if idx is None else idx
         count = self.sel_count if count is None else count
+        if int(precision) == L.OCTGS_BF16 and not getattr(scene, "bf16_valid", True):
+            raise L.OctgsError("the BF16 feature copy is stale: call scene.refresh() first")
         lib = L.lib()
         need = lib.octgs_decode_workspace_bytes(int(precision))
         if getattr(self, "dec_fwd_ws", None) is None or self.dec_fwd_ws.numel() < need:
@@ -482,6 +494,7 @@ class ViewBuffers:
             g.capacity = gauss.shape[1]
             g.data = gauss.data_ptr()
             g.count = count.data_ptr()
+            g.status = self.status.data_ptr()
             if gauss.shape[1] != self.gcap:
                 raise L.OctgsError("Gaussian buffer capacity must equal the workspace capacity")
         L.check(L.lib().octgs_rasterize_fwd(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(params),
@@ -504,7 +517,7 @@ class ViewBuffers:
                                                stream_handle(stream)), "octgs_volume_loss_grad")
 
     def rasterize_bwd(self, cam: L.Camera, params: L.RasterParams, dimg: torch.Tensor,
-                      stream=None):
+                      stream=None, stage_events=None):
         """dL/dGaussian planar [14][gcap] into self.dgauss, for the image of
         the last rasterize() with these buffers."""
         if getattr(self, "dgauss", None) is None:
@@ -513,7 +526,8 @@ class ViewBuffers:
                                             ctypes.byref(params), self.pcap, _ptr(self.T),
                                             _ptr(self.last), _ptr(dimg.contiguous()),
                                             _ptr(self.dgauss), _ptr(self.ras_ws),
-                                            self.ras_ws.numel(), stream_handle(stream)),
+                                            self.ras_ws.numel(), _events(stage_events),
+                                            stream_handle(stream)),
                 "octgs_rasterize_bwd")
 
     def decode_bwd(self, scene: "DeviceScene", cam: L.Camera, grads: SceneGrads,
@@ -571,10 +585,9 @@ class RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vb, scene, cam, params, *tensors):
         # the trained tensors may have changed in place since the last call
-        scene.refresh()
-        vb.render(scene, cam, params, precision=L.OCTGS_FP32)
+        scene.refresh(bf16=False)  # this render decodes in FP32
         vb.status.zero_()
-        vb.add_status()
+        vb.render(scene, cam, params, precision=L.OCTGS_FP32)
         vb.check_status("RenderFn forward")
         ctx.vb, ctx.scene, ctx.cam, ctx.params = vb, scene, cam, params
         return vb.rgb.clone()

@@ -39,12 +39,20 @@ class SkipNet:
     def __init__(self, seed: int = 0, inputs=None):
         dev = torch.device("cuda", torch.cuda.current_device())
         g = torch.Generator().manual_seed(seed)
+        used = list(range(Z_DIM)) if inputs is None else sorted(set(inputs))
+        # bit i set: input i is read (the training kernel zeroes the others)
+        self.input_mask = sum(1 << i for i in used)
 
-        def xavier(i, o):
+        def xavier(i, o, rows=None):
             a = math.sqrt(6.0 / (i + o))
-            return ((torch.rand(i, o, generator=g) * 2 - 1) * a).to(dev)
+            w = (torch.rand(i, o, generator=g) * 2 - 1) * a
+            if rows is not None:
+                keep = torch.zeros(i, 1)
+                keep[rows] = 1.0
+                w = w * keep  # host-side initialisation
+            return w.to(dev)
 
-        self.w = {"w1": xavier(Z_DIM, HID), "b1": torch.zeros(HID, device=dev),
+        self.w = {"w1": xavier(Z_DIM, HID, used), "b1": torch.zeros(HID, device=dev),
                   "w2": xavier(HID, HID), "b2": torch.zeros(HID, device=dev),
                   "w3": xavier(HID, 1), "b3": torch.zeros(1, device=dev)}
         self.g = {k: torch.zeros_like(v) for k, v in self.w.items()}
@@ -52,12 +60,6 @@ class SkipNet:
         self.v = {k: torch.zeros_like(v) for k, v in self.w.items()}
         self.step = 0
         self._ws = None
-        self.row_mask = None
-        if inputs is not None:
-            mask = torch.zeros(Z_DIM, 1, device=dev)
-            mask[list(inputs)] = 1.0
-            self.row_mask = mask
-            self.w["w1"].mul_(mask)
 
     def struct(self) -> L.SkipNet:
         return L.SkipNet(*[self.w[k].data_ptr() for k in SKIP_ORDER])
@@ -68,21 +70,26 @@ class SkipNet:
     def numpy(self) -> Dict[str, np.ndarray]:
         return {k: v.detach().cpu().numpy() for k, v in self.w.items()}
 
-    def train_grad(self, z: torch.Tensor, y: torch.Tensor, pos_weight: float, loss: torch.Tensor):
-        B = z.shape[0]
+    def train_grad(self, z: torch.Tensor, y: torch.Tensor, pos_weight: float, loss: torch.Tensor,
+                   rows: Optional[torch.Tensor] = None, batch: Optional[int] = None):
+        """Gradients of the batch rows `rows` (int32 row indices of z and y;
+        None: all rows of z) into self.g; adds the batch loss to `loss`."""
+        B = int(batch if batch is not None else (rows.numel() if rows is not None else z.shape[0]))
+        if rows is not None:
+            assert rows.dtype == torch.int32 and rows.numel() >= B
         need = L.lib().octgs_skip_train_workspace_bytes(B)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=z.device)
         net, gr = self.struct(), self.grad_struct()
-        L.check(L.lib().octgs_skip_train_grad(ctypes.byref(net), _ptr(z), _ptr(y), B,
-                                              float(pos_weight), ctypes.byref(gr), _ptr(loss),
-                                              _ptr(self._ws), self._ws.numel(), stream_handle()),
+        L.check(L.lib().octgs_skip_train_grad(ctypes.byref(net), _ptr(z), _ptr(y),
+                                              _ptr(rows), B,
+                                              self.input_mask, float(pos_weight),
+                                              ctypes.byref(gr), _ptr(loss), _ptr(self._ws),
+                                              self._ws.numel(), stream_handle()),
                 "octgs_skip_train_grad")
 
     def adam(self, lr: float):
         self.step += 1
-        if self.row_mask is not None:
-            self.g["w1"].mul_(self.row_mask)
         for k in SKIP_ORDER:
             adam_step(self.w[k], self.g[k], self.m[k], self.v[k], lr, self.step, eps=1e-8)
 
@@ -148,8 +155,7 @@ def collect(vb: ViewBuffers, scene: DeviceScene, cams: List[L.Camera], params: L
     zs, ys = [], []
     gen = torch.Generator(device=dev).manual_seed(seed)
     for c in cams:
-        vb.render(scene, c, params, precision=L.OCTGS_FP32)
-        vb.add_status()  # checked by the caller (vb.check_status)
+        vb.render(scene, c, params, precision=L.OCTGS_FP32)  # status checked by the caller
         anchor_weights(vb, w)
         features(vb, scene, c, zbuf)
         m = int(vb.sel_count.item())
@@ -170,13 +176,11 @@ def train(net: SkipNet, z: torch.Tensor, y: torch.Tensor, epochs: int = 4, batch
     loss = torch.zeros(1, device=z.device)
     hist = []
     for _ in range(epochs):
-        perm = torch.randperm(R, generator=gen, device=z.device)
+        perm = torch.randperm(R, generator=gen, device=z.device, dtype=torch.int32)
         loss.zero_()
         nb = 0
         for s in range(0, R - batch + 1, batch):
-            sel = perm[s:s + batch]
-            zb, yb = z[sel].contiguous(), y[sel].contiguous()
-            net.train_grad(zb, yb, pos_weight, loss)
+            net.train_grad(z, y, pos_weight, loss, rows=perm[s:s + batch])
             net.adam(lr)
             nb += 1
         hist.append(loss.item() / max(nb, 1))

@@ -35,15 +35,15 @@ class MultiViewBackward:
         self.dimgs = [torch.empty(3, height, width, device=dev) for _ in range(self.nbuf)]
         self.losses = torch.zeros(self.n_views, device=dev)  # one slot per view
         self._ssim_ws: List[Optional[torch.Tensor]] = [None] * self.nbuf
-        # OCTGS_STATUS_* bits of every view run() rendered since the last check()
-        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
-
     def check(self):
         """Raise if any view rendered since the last check overflowed its pair
         list, hit a look-back wait bound or selected more anchors than the
-        Gaussian capacity decodes (syncs), then clear the status."""
-        bits = int(self.status.item())
-        self.status.zero_()
+        Gaussian capacity decodes (syncs), then clear the status words (each
+        buffer set's, which the library ORs every frame's conditions into)."""
+        bits = 0
+        for vb in self.vbs:
+            bits |= int(vb.status.item())
+            vb.status.zero_()
         raise_on_status(bits, "training views")
 
     def run(self, scene: DeviceScene, cams: List[L.Camera], targets: List[torch.Tensor],
@@ -57,14 +57,15 @@ class MultiViewBackward:
         dstats (optional) accumulates the densification statistics.  params
         must include OCTGS_RASTER_TRAIN.  Returns the per-view losses
         (device); the caller's current stream has waited for all of it.
-        The scene's derived arrays (thresholds, bound radii, BF16 copy) are
-        recomputed first, since an optimiser step may have changed the
-        trained arrays; each view's device-detected conditions are added to
-        self.status (see check())."""
+        The scene's derived arrays (thresholds, bound radii) are recomputed
+        first, since an optimiser step may have changed the trained arrays
+        (the BF16 feature copy is left stale: refresh the scene before a BF16
+        render); each view's device-detected conditions are kept in
+        its buffer set's status word (see check())."""
         assert len(cams) == len(targets) == self.n_views
         main = torch.cuda.current_stream()
         streams = [main] + self.side
-        scene.refresh(stream=main)
+        scene.refresh(stream=main, bf16=False)  # the train step decodes in FP32
         grads.zero_()
         self.losses.zero_()
         go = torch.cuda.Event()
@@ -77,7 +78,6 @@ class MultiViewBackward:
             k = i % self.nbuf
             st, vb, dimg, li = streams[k], self.vbs[k], self.dimgs[k], self.losses[i:i + 1]
             vb.render(scene, c, params, stream=st)
-            vb.add_status(status=self.status, stream=st)
             if full:
                 self._ssim_ws[k] = photometric_loss_grad(vb.rgb, tg, dimg, li, w_l1 / nv,
                                                          w_ssim / nv, self._ssim_ws[k], stream=st)

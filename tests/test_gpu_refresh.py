@@ -9,8 +9,9 @@ trained arrays, and per-frame device conditions reach the caller.
     the bound radii, thresholds and BF16 copy up to date: the selection is
     then bit-exact against the oracle run on the updated arrays, and the
     BF16 image equals that of a scene built fresh from them.
-  * octgs_frame_status reports a pair-list overflow and a decode truncated
-    at the Gaussian capacity, and MultiViewBackward.check raises on them.
+  * the status word the Gaussians carry reports a pair-list overflow and a
+    decode truncated at the Gaussian capacity, and MultiViewBackward.check
+    raises on them.
 """
 
 import numpy as np
@@ -168,12 +169,10 @@ def test_frame_status_reports_overflow_and_truncation(P):
     say("frame status: clean frame")
     vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 18)
     vb.render(ds, cam, prm)
-    vb.add_status()
     vb.check_status()
     say("frame status: pair overflow")
     vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 64)
     vb.render(ds, cam, prm)
-    vb.add_status()
     torch.cuda.synchronize()
     assert int(vb.status.item()) == P.OCTGS_STATUS_PAIR_OVERFLOW
     with pytest.raises(P.OctgsError, match="overflow"):
@@ -181,7 +180,6 @@ def test_frame_status_reports_overflow_and_truncation(P):
     say("frame status: truncated decode")
     vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 18, gauss_capacity=5 * sc.k)
     vb.render(ds, cam, prm)
-    vb.add_status()
     torch.cuda.synchronize()
     assert int(vb.status.item()) & P.OCTGS_STATUS_TRUNCATED
     say("frame status: a training step with too small a pair capacity")

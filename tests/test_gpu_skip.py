@@ -61,22 +61,123 @@ def test_features_parity(P, SK, orc):
     assert np.abs(got - ref).max() <= 1e-5
 
 
-def test_train_gradient_parity(P, SK, orc):
-    rng = np.random.default_rng(1)
-    B = 4096
-    z = rng.standard_normal((B, 37)).astype(np.float32)
-    y = (rng.random(B) < 0.3).astype(np.float32)
-    net = SK.SkipNet(seed=3)
-    say("skip train grad", B)
-    loss = torch.zeros(1, device="cuda")
-    net.train_grad(torch.as_tensor(z).cuda(), torch.as_tensor(y).cuda(), 2.5, loss)
+def bf16_round(x):
+    """FP32 -> nearest BF16 (ties to even), returned as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _grad_bounds(z, y, net, pw, depth, lam=8.0):
+    """Bounds on |GPU - exact| for the fused BF16 training pass, per gradient
+    entry and for the loss.  z and the weights are taken already rounded as
+    the kernel rounds them (BF16 copies of z, w1, w2), so the exact values
+    are the gradient of that network; what remains is the rounding of
+    ReLU(layer 1), dH2 and dH1 to BF16 (u = 2^-8) and FP32 arithmetic.
+    Per row, first-order worst-case error terms are propagated through the
+    forward and backward; a ReLU mask counts as uncertain wherever its
+    pre-activation lies within its error bound.  Rows round independently,
+    so their contributions to a batch sum are combined as lam times the root
+    sum of squares (Hoeffding: each entry exceeds it with probability below
+    2 exp(-lam^2 / 2)), plus the worst-case FP32 summation error gamma_depth
+    sum |term| of a sum evaluated `depth` additions deep."""
+    w1, b1, w2, b2, w3, b3 = (np.asarray(net[k], np.float64)
+                              for k in ("w1", "b1", "w2", "b2", "w3", "b3"))
+    w3 = w3[:, 0]
+    B = z.shape[0]
+    u, g, gd = UBF, 70 * U32, depth * U32
+    az, A1, A2, A3 = np.abs(z), np.abs(w1), np.abs(w2), np.abs(w3)
+    a1 = z @ w1 + b1
+    h1 = np.maximum(a1, 0)
+    e_a1 = g * (az @ A1 + np.abs(b1))
+    e_h1 = e_a1 + u * (h1 + e_a1)
+    H1 = h1 + e_h1
+    a2 = h1 @ w2 + b2
+    h2 = np.maximum(a2, 0)
+    e_a2 = e_h1 @ A2 + g * (H1 @ A2 + np.abs(b2))
+    H2 = h2 + e_a2
+    x = h2 @ w3 + b3[0]
+    e_x = e_a2 @ A3 + g * (H2 @ A3 + abs(b3[0]))
+    wgt = np.where(y > 0.5, pw, 1.0)
+    sg = 1.0 / (1.0 + np.exp(-x))
+    dx = wgt * (sg - y) / B
+    e_dx = wgt / B * (e_x / 4 + 8 * U32)
+    adx = np.abs(dx)
+    D2 = np.outer(adx + e_dx, A3)                           # >= |dH2|
+    e_d2 = (np.abs(a2) <= e_a2) * D2 + np.outer(e_dx, A3) + U32 * D2
+    e_d2b = e_d2 + u * D2
+    pre = D2 @ A2.T
+    e_pre = e_d2b @ A2.T + g * pre
+    D1 = pre + e_pre                                        # >= |dH1|
+    e_d1 = (np.abs(a1) <= e_a1) * D1 + e_pre
+    e_d1b = e_d1 + u * D1
+    rss = lambda sq: lam * np.sqrt(sq)
+    e = {}
+    e["b3"] = np.array([rss(np.sum(e_dx ** 2)) + gd * adx.sum()])
+    e["w3"] = (rss(2 * (e_a2 ** 2).T @ (adx ** 2) + 2 * (H2 ** 2).T @ (e_dx ** 2))
+               + gd * (H2.T @ adx))[:, None]
+    e["b2"] = rss((e_d2 ** 2).sum(0)) + gd * D2.sum(0)
+    e["w2"] = (rss(2 * (e_h1 ** 2).T @ (D2 ** 2) + 2 * (H1 ** 2).T @ (e_d2b ** 2))
+               + gd * (H1.T @ D2))
+    e["b1"] = rss((e_d1 ** 2).sum(0)) + gd * D1.sum(0)
+    e["w1"] = rss((az ** 2).T @ (e_d1b ** 2)) + gd * (az.T @ D1)
+    sp = np.maximum(x, 0) + np.log1p(np.exp(-np.abs(x)))
+    t_loss = wgt / B * (sp + np.abs(y * x))
+    e_row = wgt / B * (np.abs(sg - y) * e_x) + 8 * U32 * t_loss
+    e_loss = float(rss(np.sum(e_row ** 2)) + gd * t_loss.sum())
+    return e, e_loss
+
+
+def _check_train(SK, orc, z, y, rows, mask_cols, pw, seed):
+    """One fused training pass against the oracle's FP64 gradient of the
+    network the kernel evaluates (BF16-rounded z, w1, w2), entry by entry
+    within the derived bound."""
+    net = SK.SkipNet(seed=seed, inputs=mask_cols)
+    zt, yt = torch.as_tensor(z).cuda(), torch.as_tensor(y).cuda()
+    rt = None if rows is None else torch.as_tensor(rows.astype(np.int32)).cuda()
+    loss = torch.full((1,), 0.25, device="cuda")
+    net.train_grad(zt, yt, pw, loss, rows=rt)
     torch.cuda.synchronize()
-    _, lref, gref = orc.skip_mlp(z.astype(np.float64), net.numpy(), y, pos_weight=2.5, grads=True)
-    assert abs(loss.item() - lref) <= 1e-5 * abs(lref)
+    zb = (z[rows] if rows is not None else z).astype(np.float64)
+    yb = (y[rows] if rows is not None else y).astype(np.float64)
+    if mask_cols is not None:
+        off = np.setdiff1d(np.arange(37), np.asarray(list(mask_cols)))
+        zb[:, off] = 0.0
+    B = zb.shape[0]
+    w = net.numpy()
+    wr = dict(w, w1=bf16_round(w["w1"]), w2=bf16_round(w["w2"]))
+    zr = bf16_round(zb)
+    _, lref, gref = orc.skip_mlp(zr, wr, yb.astype(np.float32), pos_weight=pw, grads=True)
+    # the kernel sums each block's rows, then the block sums in order
+    nblk = min((B + 63) // 64, 256)
+    depth = 64 * ((B + 64 * nblk - 1) // (64 * nblk)) + nblk
+    eb, eloss = _grad_bounds(zr, yb, wr, pw, depth)
+    got_loss = loss.item() - 0.25
+    say(f"  loss {got_loss:.6f} ref {lref:.6f} err/bound {abs(got_loss - lref) / eloss:.3f}")
+    assert abs(got_loss - lref) <= eloss + 2 * U32
     for k in SK.SKIP_ORDER:
-        e = rel(_np(net.g[k]), gref[k])
-        say(f"  d{k}: rel err {e:.2e}")
-        assert e <= 1e-4, k
+        got = _np(net.g[k]).astype(np.float64).reshape(gref[k].shape)
+        bound = eb[k].reshape(gref[k].shape) + 1e-30
+        err = np.abs(got - gref[k])
+        say(f"  d{k}: max err {err.max():.2e}, max err/bound {(err / bound).max():.3f}, "
+            f"rel {rel(got, gref[k]):.2e}")
+        assert np.all(err <= bound), k
+    if mask_cols is not None:
+        assert np.all(_np(net.g["w1"])[off] == 0.0)
+
+
+def test_train_gradient_parity(P, SK, orc):
+    """BF16 MFMA training pass: a ragged batch (not a multiple of the 64-row
+    tile), several tiles per block, gathered rows and restricted inputs."""
+    rng = np.random.default_rng(1)
+    for B, gather, cols in ((4133, False, None), (20011, False, None), (3000, True, None),
+                            (2500, True, [35, 36])):
+        R = B + 1500 if gather else B
+        z = rng.standard_normal((R, 37)).astype(np.float32)
+        y = (rng.random(R) < 0.3).astype(np.float32)
+        rows = rng.permutation(R)[:B] if gather else None
+        say("skip train grad", B, "gathered" if gather else "", cols)
+        _check_train(SK, orc, z, y, rows, cols, 2.5, seed=3 + B % 7)
 
 
 def _logit_bound(z, net):
