@@ -37,6 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "FPS @1080p + train-step ms, BF16+learned-skip vs plain FP32 at >=45 dB PSNR"
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
@@ -1251,6 +1252,51 @@ def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, views: in
         print(f"wrote profiles/{name}")
 
 
+def _short(name: str) -> str:
+    s_ = name.replace("(anonymous namespace)::", "").replace("octgs::", "")
+    return s_.split("(")[0].removeprefix("void ")
+
+
+def summarize_train_trace(trace_dir: str, steps: int, cmd: str, log_path: str):
+    """Writes profiles/train_step_c3_kernel_trace.txt from a kernel trace of
+    `bench.py --train-only --inflight 1 --train-steps STEPS`: the dispatches
+    of the timed steps (after the third warm-up step's Adam update, through
+    the last timed step's), per kernel per step."""
+    from collections import defaultdict
+    trace = _csv_rows(trace_dir, "kernel_trace.csv")
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    adam = [r for r in trace if "k_adam_many" in r["Kernel_Name"]]
+    if len(adam) < 3 + steps:
+        raise SystemExit(f"{len(adam)} Adam updates in the trace, need {3 + steps}")
+    t0, t1 = int(adam[2]["End_Timestamp"]), int(adam[2 + steps]["End_Timestamp"])
+    agg = defaultdict(list)
+    for r in trace:
+        if t0 < int(r["Start_Timestamp"]) <= t1:
+            agg[_short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in agg.values())
+    lines = [f"{'kernel':<38}{'per step':>9}{'avg_us':>10}{'ms/step':>10}{'share':>9}"]
+    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{name[:37]:<38}{len(v) / steps:>9.1f}{sum(v) / len(v):>10.2f}"
+                     f"{sum(v) / steps / 1e3:>10.3f}{100 * sum(v) / total:>8.2f}%")
+    said = ""
+    if log_path and os.path.exists(log_path):
+        said = [ln.strip() for ln in open(log_path) if "train step only" in ln]
+        said = ("\nbench.py in the traced run (HIP events, median step; the profiler adds launch "
+                "gaps): " + said[-1].split("] ", 1)[-1] + "\n") if said else ""
+    txt = (
+        "Kernel trace of the training step (500k anchors / 6 levels, 4 views at 1600x1066; forward,\n"
+        "mean-L1 loss, backward through compositing, projection and decode, Adam), run with one view\n"
+        "in flight (--inflight 1) so that every launch is uncontended; the benchmark's default step\n"
+        f"runs the views on separate streams and overlaps them.  The table covers the {steps} timed\n"
+        "steps of the traced run (the dispatches after the third warm-up step's Adam update through\n"
+        "the last timed step's).\n\n"
+        f"command ($REPO = repository root):\n  {cmd}\n\n" + "\n".join(lines) + "\n\n"
+        f"kernel time per step (sum of dispatch durations): {total / steps / 1e3:.3f} ms\n" + said)
+    with open(os.path.join(ROOT, "profiles", "train_step_c3_kernel_trace.txt"), "w") as f:
+        f.write(txt)
+    print("wrote profiles/train_step_c3_kernel_trace.txt")
+
+
 def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_name: str,
                        kernels=None, title=None):
     """Writes profiles/<out_name> from one rocprofv3 --pmc run of SQ counters
@@ -1261,6 +1307,8 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
     (8x a dispatch's duration in cycles), so it is divided by 8; the SIMD
     count is 1024 (256 CUs x 4)."""
     from collections import defaultdict
+    if os.path.basename(out_name) != out_name:
+        raise SystemExit("the summary name is a file name under profiles/, not a path")
     rows = _csv_rows(sq_dir, "counter_collection.csv")
     trace = _csv_rows(trace_dir, "kernel_trace.csv")
     by = defaultdict(dict)
@@ -1272,7 +1320,8 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
     order = sorted(by)
     simds = 1024
     lines = [f"{'kernel':<22}{'per unit':>9}{'us':>8}{'waves':>8}{'VALU busy':>11}{'lane use':>10}"
-             f"{'MFMA busy':>11}{'BF16 TF/s':>11}{'of peak':>9}"]
+             f"{'MFMA busy':>11}{'BF16 TF/s':>11}{'of peak':>9}{'F32 TF/s':>10}{'of peak':>9}"
+             f"{'GRBM GHz':>10}"]
     for label, sub, per_view in (kernels or VIEW_KERNELS):
         n = per_view * views
         ds = [d for d in order if sub in name[d]][-n:]
@@ -1282,15 +1331,18 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
         for d in ds:
             for k, v in by[d].items():
                 c[k] += v
-        cyc = c["GRBM_GUI_ACTIVE"] / 8.0
         t = _last(trace, sub, n)
         us = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in t) / 1e3 / n
+        cyc = us * 1e-6 * CLOCK_HZ * n  # the dispatches' cycles at the peak engine clock
+        grbm_ghz = c["GRBM_GUI_ACTIVE"] / 8.0 / (us * 1e-6 * n) / 1e9
         valu = 4.0 * c["SQ_ACTIVE_INST_VALU"] / (simds * cyc)
         lane = c["SQ_THREAD_CYCLES_VALU"] / max(64.0 * c["SQ_ACTIVE_INST_VALU"], 1.0)
         mfma = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc)
         tf = c["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512 / n / (us * 1e-6) / 1e12
+        tf32 = c["SQ_INSTS_VALU_MFMA_MOPS_F32"] * 512 / n / (us * 1e-6) / 1e12
         lines.append(f"{label:<22}{per_view:>9}{us:>8.1f}{c['SQ_WAVES'] / n:>8.0f}{100 * valu:>10.1f}%"
-                     f"{100 * lane:>9.1f}%{100 * mfma:>10.2f}%{tf:>11.2f}{tf / 2500.0:>9.4f}")
+                     f"{100 * lane:>9.1f}%{100 * mfma:>10.2f}%{tf:>11.2f}{tf / 2500.0:>9.4f}"
+                     f"{tf32:>10.2f}{tf32 / 157.3:>9.4f}{grbm_ghz:>10.2f}")
     head = title.replace("\\n", "\n") + "\n" if title else (
         "SQ counters of the street-scene render benchmark (1M anchors, 8 LOD levels, 1920x1080,\n"
         f"the {views} views of the zoom-out, one view at a time), per kernel over the per-stage\n"
@@ -1302,9 +1354,13 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
         "  MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles)\n"
         "  BF16 TF/s  = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 per dispatch / kernel-trace duration,\n"
         "               'of peak' against the 2.5 PFLOP/s dense BF16 peak\n"
-        "  cycles     = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs);\n"
+        "  F32 TF/s   = the same for SQ_INSTS_VALU_MFMA_MOPS_F32 (FP32 MFMA), against 157.3 TFLOP/s\n"
         "  us         = kernel-trace average duration of the same dispatches (a separate run\n"
-        "               without counters).\n\n"
+        "               without counters); cycles = us x 2.4 GHz, the peak engine clock, so the\n"
+        "               busy fractions are lower bounds if the clock ran lower\n"
+        "  GRBM GHz   = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs) / us: about 2.4 for\n"
+        "               long kernels; above it for short ones, whose counter-collection\n"
+        "               dispatches carry fixed overhead.\n\n"
         f"command ($REPO = repository root):\n  {cmd}\n\n" + "\n".join(lines) + f"\nunits: {views}\n")
     with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
         f.write(txt)
@@ -1312,7 +1368,11 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
 
 
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-train-trace":
+        # python bench.py --summarize-train-trace TRACE_DIR STEPS CMD [LOG]
+        a = sys.argv[2:]
+        summarize_train_trace(a[0], int(a[1]), a[2], a[3] if len(a) > 3 else "")
+    elif len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         # python bench.py --summarize-counters SQ_DIR TRACE_DIR UNITS CMD OUT_NAME [SPEC [TITLE]]
         # SPEC: "label=kernel-name substring:dispatches per unit;..." (default: the
         # per-view render kernels); TITLE: first lines of the summary

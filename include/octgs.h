@@ -146,9 +146,10 @@ typedef struct {
   uint32_t flags; /* OCTGS_RASTER_* bits */
 } octgs_raster_params;
 
-/* flags: the forward keeps what octgs_rasterize_bwd needs (each sorted
- * pair's emission index, carried through the tile sort); required for a
- * later backward of the same frame, off for rendering only. */
+/* flags: the forward keeps what octgs_rasterize_bwd needs (each emitted
+ * pair's slot, and each sorted pair's emission index, carried through the
+ * tile sort); required for a later backward of the same frame, off for
+ * rendering only (two fewer 4-byte writes per pair and a lighter sort). */
 #define OCTGS_RASTER_TRAIN 1u
 /* flags: before compositing, order each XCD's tiles by list length, longest
  * first (one small extra kernel), so the last blocks to run are short ones;

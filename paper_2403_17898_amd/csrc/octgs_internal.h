@@ -255,7 +255,8 @@ struct RasterWs {
   int64_t gcap, pcap;
   int32_t tiles_x, tiles_y, nblk_g, nruns, tile_passes;
   float xmax, ymax;            // last pixel centre of the image: W - 0.5, H - 0.5
-  size_t lb_words, lbt_words;  // look-back words to clear before the sorts
+  size_t lb_words, lbt_words;  // look-back words of the depth and tile sorts (all passes)
+  int64_t lb_parts, lbt_parts; // partitions per pass at capacity
   size_t bytes;
 };
 
@@ -296,6 +297,15 @@ constexpr int kSortPart = kBlock * kSortItems;  // 2048 keys per partition (dept
 constexpr int kTileSortItems = 16;
 constexpr int kTileSortPart = kBlock * kTileSortItems;
 constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
+// Look-back status of one sort pass: a row of 2 x 256 words per partition
+// (the digits' aggregate, upgraded to the inclusive prefix, and a copy of the
+// aggregate), then one row of 256 words per group of kGroupParts partitions.
+constexpr int kGroupParts = 16;
+constexpr int kLbRow = 512;
+__host__ __device__ inline size_t lookback_pass_words(int64_t nparts) {
+  const int64_t np = nparts < 1 ? 1 : nparts;
+  return (size_t)np * kLbRow + (size_t)((np + kGroupParts - 1) / kGroupParts) * 256;
+}
 
 // Sort (keys, vals) of length *count (device) by bits [0, 8 * passes) of the
 // key, stably.  On return the sorted data is in buffers index `passes % 2`.
@@ -306,8 +316,8 @@ constexpr uint32_t kSpinLimit = 1u << 22;       // look-back wait bound
 // the producer of the keys; the first pass folds the later passes' copies
 // into copy 0); items: keys per thread of a partition (kSortItems or
 // kTileSortItems; a partition is 256 * items keys); lookback:
-// passes * ceil(cap / (256 * items)) * 256 words,
-// cleared by the producer for the partitions in use.
+// passes * lookback_pass_words(ceil(cap / (256 * items))) words, cleared by
+// the producer for the partitions in use (clear_partitions).
 hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
                       const uint32_t *count, int64_t cap, int items, int passes, uint32_t *hist,
                       int hist_copies, uint32_t hist_stride, uint32_t *lookback,

@@ -172,12 +172,23 @@ __device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa,
 // Zeroes the radix-sort look-back words (256 per partition) of partitions
 // j with part j in [a, b) (part = keys per partition), j < nparts, in each of `passes` regions of
 // `stride` words; all threads of the block take part.
-__device__ __forceinline__ void clear_partitions(uint32_t *lb, size_t stride, uint32_t a, uint32_t b,
-                                                 int passes, size_t nparts, uint32_t part) {
+// Clears, for each of `passes` sort passes (pass_words apart), the look-back
+// rows of the partitions that start in [a, b) (partitions of `part` keys,
+// nparts of them at capacity) and the group rows of the groups they open.
+__device__ __forceinline__ void clear_partitions(uint32_t *lb, size_t pass_words, uint32_t a,
+                                                 uint32_t b, int passes, int64_t nparts,
+                                                 uint32_t part) {
   const uint32_t j0 = (a + part - 1) / part;
-  const uint32_t j1 = (uint32_t)std::min<uint64_t>(((uint64_t)b + part - 1) / part, nparts);
-  for (int p = 0; p < passes; ++p)
-    for (uint32_t j = j0; j < j1; ++j) lb[p * stride + (size_t)j * 256 + threadIdx.x] = 0u;
+  const uint32_t j1 = (uint32_t)std::min<uint64_t>(((uint64_t)b + part - 1) / part, (uint64_t)nparts);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t *base = lb + p * pass_words;
+    for (uint32_t j = j0; j < j1; ++j) {
+      base[(size_t)j * kLbRow + threadIdx.x] = 0u;
+      base[(size_t)j * kLbRow + 256 + threadIdx.x] = 0u;
+      if (j % kGroupParts == 0)
+        base[(size_t)nparts * kLbRow + (size_t)(j / kGroupParts) * 256 + threadIdx.x] = 0u;
+    }
+  }
 }
 
 __device__ __forceinline__ uint64_t pack_rect(int x0, int y0, int x1, int y1) {
@@ -317,8 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
   if ((int64_t)b == ((int64_t)n - 1) / kChunk && t == 0) ws.hdr->n_visible = prefix + mine;
   // clear the depth sort's look-back words of the partitions that start in
   // this block's output range [prefix, prefix + mine), for all four passes
-  clear_partitions(ws.lookback, ws.lb_words / 4, prefix, prefix + mine, 4, ws.lb_words / 4 / 256,
-                   kSortPart);
+  clear_partitions(ws.lookback, ws.lb_words / 4, prefix, prefix + mine, 4, ws.lb_parts, kSortPart);
   __syncthreads();
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
@@ -380,8 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
   // chunk (kept pairs are a prefix-closed subset of the positions)
   if (excl < kLbVal)
     clear_partitions(ws.lookback_t, ws.lbt_words / max(ws.tile_passes, 1), excl,
-                     sat_add(excl, agg), ws.tile_passes, ws.lbt_words / max(ws.tile_passes, 1) / 256,
-                     kTileSortPart);
+                     sat_add(excl, agg), ws.tile_passes, ws.lbt_parts, kTileSortPart);
   // consecutive 256-entry rows of the chunk, scanned in order (32-bit sums
   // are exact when the chunk total is below 2^30)
   uint32_t carry = 0;
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
 // the kept ones by ballots, gets the run's output offset by decoupled
 // look-back over the preceding runs and writes (tile id, slot) in order.
 // It also accumulates the digit histograms of the kept tile ids.
-__global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int tile_passes) {
+__global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int tile_passes, int train) {
   constexpr int kW = kEmitThreads / kWave;  // 16 waves
   constexpr int kG = kEmitRun / 64;         // 128 ballot groups per run
   constexpr int kC = kEmitRun / kEmitThreads;  // 8 candidates per thread
@@ -557,8 +566,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
       if (dst < P) {  // always true unless a look-back wait hit its bound
         ws.tkey[0][dst] = key[k];
         ws.tval[0][dst] = val[k];
-        ws.tpair[0][dst] = dst;
-        ws.pair_slot[dst] = val[k];
+        if (train) {  // what the backward needs: emission index and slot per pair
+          ws.tpair[0][dst] = dst;
+          ws.pair_slot[dst] = val[k];
+        }
       }
       for (int d = 0; d < tile_passes; ++d) atomicAdd(&h[d][(key[k] >> (8 * d)) & 255u], 1u);
     }
@@ -893,8 +904,10 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.tile_order = (uint32_t *)take((size_t)tile_grid_blocks(ws.tiles_x, ws.tiles_y) * 4);
   ws.hist = (uint32_t *)take(kHistCopies * kHistStride * 4);
   ws.tile_passes = tile_sort_passes(ws.tiles_x * ws.tiles_y);
-  ws.lb_words = (size_t)4 * ((g + kSortPart - 1) / kSortPart) * 256;
-  ws.lbt_words = (size_t)ws.tile_passes * ((pc + kTileSortPart - 1) / kTileSortPart) * 256;
+  ws.lb_parts = (g + kSortPart - 1) / kSortPart;
+  ws.lbt_parts = (pc + kTileSortPart - 1) / kTileSortPart;
+  ws.lb_words = (size_t)4 * lookback_pass_words(ws.lb_parts);
+  ws.lbt_words = (size_t)ws.tile_passes * lookback_pass_words(ws.lbt_parts);
   ws.lookback = (uint32_t *)take(ws.lb_words * 4);
   ws.lookback_t = (uint32_t *)take(ws.lbt_words * 4);
   ws.dproj = (float *)take((size_t)g * 9 * 4);
@@ -971,7 +984,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
   mark(4);
   hipLaunchKernelGGL(k_emit_scan, dim3(ws.nblk_g), dim3(kBlock), 0, s, ws);
   hipLaunchKernelGGL(k_emit_pairs, dim3(std::max(ws.nruns, 1)), dim3(kEmitThreads), 0, s, ws,
-                     ws.tile_passes);
+                     ws.tile_passes, (p->flags & OCTGS_RASTER_TRAIN) ? 1 : 0);
   mark(5);
   mark(6);
   const int passes = ws.tile_passes;

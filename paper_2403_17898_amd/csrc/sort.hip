@@ -11,6 +11,15 @@
 // other kernels resident a block can start before its predecessor, and two
 // look-back kernels can then wait on each other.)
 //
+// The look-back is two-level: partitions form groups of kGroupParts, and
+// the last partition of each group publishes the group's aggregate (from
+// per-partition aggregate copies that are never upgraded) and later its
+// inclusive prefix.  A block sums its own group's predecessors, then whole
+// groups, so it reads at most kGroupParts + ceil(groups / kLookWin) windows
+// instead of one window per kLookWin predecessors back to the nearest
+// inclusive one, which with hundreds of partitions all starting together
+// was a long chain of round trips and a quadratic volume of status reads.
+//
 // CDNA4 specifics: local ranking is done per 64-lane wavefront with eight
 // ballots per item (a match-any on the digit bits); each wave owns a
 // contiguous run of the partition so ranks stay stable; look-back status
@@ -25,6 +34,45 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr int kLookWin = 16;
+
+// Sum, for the status words w(q) = lb[q * stride] with q from p down to lo
+// (nearest first), of the values up to and including the nearest inclusive
+// word; spins while any word it needs is unpublished.  Returns whether an
+// inclusive word was met (otherwise everything down to lo was summed).  A
+// wait past the bound sets *err_flag and stops.
+__device__ __forceinline__ bool lookback_sum(const uint32_t *lb, size_t stride, int64_t p,
+                                             int64_t lo, uint32_t &acc, uint32_t *err_flag) {
+  uint32_t spins = 0;
+  while (p >= lo) {
+    const int cnt = (int)min<int64_t>(kLookWin, p - lo + 1);
+    uint32_t v[kLookWin];
+#pragma unroll
+    for (int i = 0; i < kLookWin; ++i) v[i] = ld_acq(lb + (size_t)(p - min(i, cnt - 1)) * stride);
+    bool ready = true, found = false;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kLookWin; ++i) {
+      if (i < cnt && !found) {
+        const uint32_t f = v[i] & ~kValMask;
+        ready = ready && f != 0u;
+        sum += v[i] & kValMask;
+        found = f == kFlagInc;
+      }
+    }
+    if (!ready) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err_flag, 1u);
+        return true;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    acc += sum;
+    if (found) return true;
+    p -= cnt;
+  }
+  return false;
+}
 
 template <int NV, int PART>
 struct PassSmem {
@@ -45,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t *__restrict__ vin2, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
     uint32_t *__restrict__ vout2, const uint32_t *__restrict__ count, int shift,
     uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride, int fold_passes,
-    uint32_t *__restrict__ lookback, uint32_t *__restrict__ ticket,
+    uint32_t *__restrict__ lookback, uint32_t *__restrict__ groups, uint32_t *__restrict__ ticket,
     uint32_t *__restrict__ err_flag) {
   constexpr int PART = kBlock * ITEMS;
   __shared__ PassSmem<NV, PART> sm;
@@ -119,8 +167,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     // thread t owns digit t: per-wave exclusive offsets and the block total
     uint32_t c0 = sm.wcnt[0][t], c1 = sm.wcnt[1][t], c2 = sm.wcnt[2][t], c3 = sm.wcnt[3][t];
     uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t *lb = lookback + (size_t)part * 256u;
-    st_rel(&lb[t], (part == 0 ? kFlagInc : kFlagAgg) | tot);
+    // status rows: [part][0..255] the digit's aggregate, later its inclusive
+    // prefix; [part][256..511] a copy of the aggregate for the group sum
+    uint32_t *row = lookback + (size_t)part * kLbRow;
+    st_rel(&row[t], (part == 0 ? kFlagInc : kFlagAgg) | tot);
+    st_rel(&row[256 + t], kFlagAgg | tot);
     uint32_t blk_tot;
     uint32_t ds = block_excl_scan(tot, sm.tmp, &blk_tot);
     sm.dstart[t] = ds;
@@ -129,45 +180,23 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     sm.wcnt[2][t] = ds + c0 + c1;
     sm.wcnt[3][t] = ds + c0 + c1 + c2;
 
-    // decoupled look-back for digit t: read a window of kLookWin
-    // predecessors (nearest first) in one round trip; if every entry up to
-    // the nearest inclusive one has been published, add them and stop at
-    // the inclusive one (or move one window back), else read the window
-    // again.  A partition outside the window never stalls the scan.
+    const uint32_t grp = part / kGroupParts;
+    const bool closer = part % kGroupParts == kGroupParts - 1;
+    if (closer) {
+      // the group's aggregate: its partitions' aggregate copies, all running
+      uint32_t gs = 0;
+      lookback_sum(lookback + 256 + t, kLbRow, part, (int64_t)grp * kGroupParts, gs, err_flag);
+      st_rel(&groups[(size_t)grp * 256 + t], kFlagAgg | (gs & kValMask));
+    }
     uint32_t excl = 0;
     if (part > 0) {
-      int64_t p = (int64_t)part - 1;
-      uint32_t spins = 0;
-      while (p >= 0) {
-        const int cnt = (int)min<int64_t>(kLookWin, p + 1);
-        uint32_t v[kLookWin];
-#pragma unroll
-        for (int i = 0; i < kLookWin; ++i)
-          v[i] = ld_acq(lookback + (size_t)(p - min(i, cnt - 1)) * 256u + t);
-        bool ready = true, found = false;
-        uint32_t sum = 0;
-#pragma unroll
-        for (int i = 0; i < kLookWin; ++i) {
-          if (i < cnt && !found) {
-            const uint32_t f = v[i] & ~kValMask;
-            ready = ready && f != 0u;
-            sum += v[i] & kValMask;
-            found = f == kFlagInc;
-          }
-        }
-        if (!ready) {
-          if (++spins > kSpinLimit) {
-            atomicOr(err_flag, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += sum;
-        if (found) break;
-        p -= cnt;
-      }
-      st_rel(&lb[t], kFlagInc | ((excl + tot) & kValMask));
+      // the own group's predecessors, then whole groups
+      const bool found = lookback_sum(lookback + t, kLbRow, (int64_t)part - 1,
+                                      (int64_t)grp * kGroupParts, excl, err_flag);
+      if (!found && grp > 0) lookback_sum(groups + t, 256, (int64_t)grp - 1, 0, excl, err_flag);
+      const uint32_t inc = kFlagInc | ((excl + tot) & kValMask);
+      st_rel(&row[t], inc);
+      if (closer) st_rel(&groups[(size_t)grp * 256 + t], inc);
     }
     sm.gbase[t] = sm.hexcl[t] + excl;
     __syncthreads();
@@ -215,17 +244,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
 template <int ITEMS>
 void launch_pass(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *vals2,
                  const uint32_t *count, int p, int grid, uint32_t *hist, int copies,
-                 uint32_t hist_stride, int fold, uint32_t *lookback, uint32_t *ticket,
-                 uint32_t *err_flag, hipStream_t stream) {
+                 uint32_t hist_stride, int fold, uint32_t *lookback, uint32_t *groups,
+                 uint32_t *ticket, uint32_t *err_flag, hipStream_t stream) {
   const int src = p & 1, dst = src ^ 1;
   if (vals2)
     hipLaunchKernelGGL((k_sort_pass<2, ITEMS>), dim3(grid), dim3(kBlock), 0, stream, keys[src],
                        vals[src], vals2[src], keys[dst], vals[dst], vals2[dst], count, 8 * p, hist,
-                       copies, hist_stride, fold, lookback, ticket, err_flag);
+                       copies, hist_stride, fold, lookback, groups, ticket, err_flag);
   else
     hipLaunchKernelGGL((k_sort_pass<1, ITEMS>), dim3(grid), dim3(kBlock), 0, stream, keys[src],
                        vals[src], nullptr, keys[dst], vals[dst], nullptr, count, 8 * p, hist,
-                       copies, hist_stride, fold, lookback, ticket, err_flag);
+                       copies, hist_stride, fold, lookback, groups, ticket, err_flag);
 }
 
 }  // namespace
@@ -238,20 +267,20 @@ hipError_t radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint32_t *const *val
   if (hist_copies < 1 || hist_copies > kHistCopies) return hipErrorInvalidValue;
   if (items != kSortItems && items != kTileSortItems) return hipErrorInvalidValue;
   const int64_t part = (int64_t)kBlock * items;
-  const int64_t nparts_cap = (cap + part - 1) / part;
-  const size_t lb_stride = (size_t)std::max<int64_t>(nparts_cap, 1) * 256u;
+  const int64_t nparts_cap = std::max<int64_t>((cap + part - 1) / part, 1);
+  const size_t lb_stride = lookback_pass_words(nparts_cap);
   // one block per possible partition; blocks past the actual count exit
-  const int pass_grid = (int)std::max<int64_t>(nparts_cap, 1);
+  const int pass_grid = (int)nparts_cap;
   for (int p = 0; p < passes; ++p) {
     const int copies = p == 0 ? hist_copies : 1, fold = p == 0 ? passes - 1 : 0;
+    uint32_t *lb = lookback + lb_stride * p;
+    uint32_t *groups = lb + (size_t)nparts_cap * kLbRow;
     if (items == kTileSortItems)
       launch_pass<kTileSortItems>(keys, vals, vals2, count, p, pass_grid, hist + 256 * p, copies,
-                                  hist_stride, fold, lookback + lb_stride * p, tickets + p,
-                                  err_flag, stream);
+                                  hist_stride, fold, lb, groups, tickets + p, err_flag, stream);
     else
       launch_pass<kSortItems>(keys, vals, vals2, count, p, pass_grid, hist + 256 * p, copies,
-                              hist_stride, fold, lookback + lb_stride * p, tickets + p, err_flag,
-                              stream);
+                              hist_stride, fold, lb, groups, tickets + p, err_flag, stream);
   }
   return hipGetLastError();
 }

@@ -141,6 +141,8 @@ def test_refresh_follows_in_place_updates(P, orc):
 
 
 def test_training_run_refreshes_the_scene(P, orc):
+    """A training run recomputes the bound radii from the updated arrays
+    (the selection depends on them); the BF16 copy waits for a refresh."""
     sc = S.make_config1()
     ds = P.DeviceScene.from_scene(sc)
     cams = [P.make_camera(c) for c in _cams()[:1]] * 2
@@ -158,6 +160,15 @@ def test_training_run_refreshes_the_scene(P, orc):
     now = _scene_now(sc, ds)
     _, rho = orc.scene_thresholds(now)
     assert np.array_equal(_np(ds.bound_r).view(np.uint32), rho.view(np.uint32))
+    # the train step decodes in FP32 and leaves the BF16 copy stale: a BF16
+    # render refuses until the scene is refreshed, and then reads the update
+    assert not ds.bf16_valid
+    vb = P.ViewBuffers(sc.n, sc.k, 128, 128, 1 << 18)
+    with pytest.raises(P.OctgsError):
+        vb.render(ds, cams[0], P.raster_params(), precision=P.OCTGS_BF16)
+    ds.refresh()
+    torch.cuda.synchronize()
+    assert ds.bf16_valid
     assert np.array_equal(_np(ds.feat_bf16).view(np.uint16), _rne_bits(now.feat))
 
 
