@@ -41,12 +41,28 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t n, int k, float d_ma
                                                     const float *__restrict__ bscale,
                                                     float *__restrict__ thr2,
                                                     float *__restrict__ rho) {
-  __shared__ float rows[kBlock * 3 * kMaxK];
+  __shared__ alignas(16) float rows[kBlock * 3 * kMaxK];
   const int rl = 3 * k;
   const int64_t j0 = (int64_t)blockIdx.x * kBlock;
   const int na = (int)min<int64_t>(kBlock, n - j0);
   const float *src = offsets + (size_t)j0 * rl;
-  for (int e = threadIdx.x; e < na * rl; e += kBlock) rows[e] = src[e];
+  const int nf = na * rl;
+  // the span starts 1024 rl bytes into the array, so it is 16-byte aligned
+  // whenever the array is; all loads are issued before the first store
+  const int nv = (((uintptr_t)offsets & 15) == 0) ? nf >> 2 : 0;
+  constexpr int kV = 3 * kMaxK / 4;  // float4s per thread at most (12)
+  float4 v[kV];
+#pragma unroll
+  for (int u = 0; u < kV; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    v[u] = i < nv ? ((const float4 *)src)[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+#pragma unroll
+  for (int u = 0; u < kV; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    if (i < nv) ((float4 *)rows)[i] = v[u];
+  }
+  for (int e = 4 * nv + threadIdx.x; e < nf; e += kBlock) rows[e] = src[e];
   __syncthreads();
   const int64_t j = j0 + threadIdx.x;
   if (j >= n) return;
