@@ -28,8 +28,11 @@
  *  - Return value: OCTGS_OK, or a negative octgs_status when host-side
  *    argument validation fails (nothing is enqueued then), or OCTGS_EHIP if a
  *    launch reports an error.  Device-detected conditions (pair-list
- *    overflow, a look-back wait that exceeded its bound) are reported in
- *    octgs_raster_stats, readable once the stream has passed the call.
+ *    overflow, a look-back wait that exceeded its bound, decode truncation
+ *    at the Gaussian capacity) are ORed into the caller's status word
+ *    (octgs_gaussians.status), and the rasterizer's also appear in
+ *    octgs_raster_stats; both are readable once the stream has passed the
+ *    call.
  *  - Layouts are structure-of-arrays unless stated; "planar [F][cap]" means
  *    field f of slot i at index f * cap + i.
  */

@@ -429,9 +429,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
 // look-back over the preceding runs and writes (tile id, slot) in order.
 // It also accumulates the digit histograms of the kept tile ids.
 __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int tile_passes, int train) {
-  constexpr int kW = kEmitThreads / kWave;  // 16 waves
-  constexpr int kG = kEmitRun / 64;         // 128 ballot groups per run
-  constexpr int kC = kEmitRun / kEmitThreads;  // 8 candidates per thread
+  constexpr int kW = kEmitThreads / kWave;     // waves per block
+  constexpr int kG = kEmitRun / 64;            // ballot groups per run
+  constexpr int kC = kEmitRun / kEmitThreads;  // candidates per thread (8)
+  static_assert(kEmitThreads >= 256 && kC * kEmitThreads == kEmitRun, "emission shape");
   __shared__ uint32_t offs[kEmitRun + 1];
   __shared__ uint16_t owner[kEmitRun];
   __shared__ uint32_t wmax[kW];
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   if (blockIdx.x >= R) return;
   __shared__ uint32_t s_r;
   if (t == 0) s_r = atomicAdd(&ws.hdr->ticket[kTicketEmit], 1u);
-  (&h[0][0])[t] = 0u;  // 1024 threads, 4 x 256 bins
+  for (int i = t; i < 4 * 256; i += kEmitThreads) (&h[0][0])[i] = 0u;
   __syncthreads();
   const uint32_t r = s_r;
   const uint32_t p0 = r * kEmitRun, p1 = min(P, p0 + kEmitRun);
@@ -541,14 +542,16 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
   }
   __syncthreads();
   if (w == 0) {
-    // exclusive prefix over the 128 groups, two per lane
-    const uint32_t c0 = (uint32_t)__popcll(gmask[l]), c1 = (uint32_t)__popcll(gmask[64 + l]);
-    const uint32_t i0 = wave_incl_scan(c0);
-    const uint32_t t0 = __shfl(i0, 63, 64);
-    const uint32_t i1 = wave_incl_scan(c1);
-    gpre[l] = i0 - c0;
-    gpre[64 + l] = t0 + i1 - c1;
-    const uint32_t agg = t0 + __shfl(i1, 63, 64);
+    // exclusive prefix over the kG ballot groups, up to one per lane per step
+    uint32_t agg = 0;
+#pragma unroll
+    for (int q = 0; q < (kG + 63) / 64; ++q) {
+      const int gi = q * 64 + l;
+      const uint32_t c = gi < kG ? (uint32_t)__popcll(gmask[gi]) : 0u;
+      const uint32_t inc = wave_incl_scan(c);
+      if (gi < kG) gpre[gi] = agg + inc - c;
+      agg += __shfl(inc, 63, 64);
+    }
     const uint32_t ex = chained_lookback(ws.lb_pair, r, agg, &ws.hdr->sync_error, kSpinLimit);
     if (l == 0) {
       s_excl = ex;
