@@ -438,6 +438,7 @@ def main():
     use_skip = skip is not None and not skip["fallback_to_full_decode"]
     value = skip["fps"] if use_skip else fps16
     ms_value = nv * 1e3 / value  # one step = one pass over the trajectory
+    copy_gbs = measured_copy_gbs(torch)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -483,6 +484,7 @@ def main():
         "train": train,
         "roofline": roofline,
         "raster_hbm": raster_hbm,
+        "measured_copy_gbs": copy_gbs,
         "each_view_alone": per_view,
         "decode_mfma": decode_mfma,
         "cpu_baseline": cpu,
@@ -491,6 +493,24 @@ def main():
     if city is not None:
         out["city"] = city
     print(json.dumps(_finite(out), allow_nan=False), flush=True)
+
+
+def measured_copy_gbs(torch) -> float:
+    """Attainable HBM rate for context: a plain 256 MiB device-to-device copy
+    (read + write bytes over the HIP-event time, best of 5)."""
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * (256 << 20) / (best * 1e-3) / 1e9, 1)
 
 
 def stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, order):

@@ -30,7 +30,15 @@
  * Parity pins (checked by tests that do not call the HIP path): closed-form
  * single- and two-Gaussian images, brute-force per-pixel compositing, the
  * threshold form of Eq. 7 against its literal log2 form, invariants of the
- * transmittance, and central finite differences of the backward pass.
+ * transmittance, and central finite differences of the backward pass;
+ * visibility against points and spheres placed just inside and outside each
+ * frustum plane of a generic camera (planes built from back-projected edge
+ * rays), conservativeness (culling never changes the image), invariance of
+ * lists and images under a rotation of scene and camera together, and the
+ * closed-form conic of Gaussians given in camera space under a rotated
+ * camera; the predictor's inputs in closed form, its loss against the
+ * textbook cross-entropy and its gradient against finite differences.  The
+ * pin families are shown to catch mistakes planted in copies of this file.
  */
 #include <math.h>
 #include <stdint.h>

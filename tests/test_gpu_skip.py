@@ -168,10 +168,12 @@ def _check_train(SK, orc, z, y, rows, mask_cols, pw, seed):
 
 def test_train_gradient_parity(P, SK, orc):
     """BF16 MFMA training pass: a ragged batch (not a multiple of the 64-row
-    tile), several tiles per block, gathered rows and restricted inputs."""
+    tile), several tiles per block, gathered rows, restricted inputs, a
+    single row, a batch below one tile and a network that reads no input."""
     rng = np.random.default_rng(1)
     for B, gather, cols in ((4133, False, None), (20011, False, None), (3000, True, None),
-                            (2500, True, [35, 36])):
+                            (2500, True, [35, 36]), (1, False, None), (63, True, None),
+                            (65, False, [])):
         R = B + 1500 if gather else B
         z = rng.standard_normal((R, 37)).astype(np.float32)
         y = (rng.random(R) < 0.3).astype(np.float32)
