@@ -201,8 +201,20 @@ CASES = [(64, 64, 300, 1), (128, 128, 3000, 2), (97, 61, 1500, 3), (333, 200, 20
 
 @pytest.mark.parametrize("W,H,n,seed", CASES)
 def test_raster_stage_parity(P, orc, W, H, n, seed):
+    _stage_parity(P, orc, W, H, n, seed, (0.01, 0.4))
+
+
+def test_raster_three_tile_sort_passes(P, orc):
+    """An image of more than 2^16 tiles (8192 x 2112: 512 x 132 = 67,584),
+    so tile ids take 17 bits and the tile sort runs three 8-bit passes; the
+    bottom four tile rows (ids from 65,536) hold ~57k of the 1.76M pairs."""
+    assert (8192 // 16) * (2112 // 16) > 1 << 16
+    _stage_parity(P, orc, 8192, 2112, 30000, 6, (0.005, 0.05), min_high_tile=1 << 16)
+
+
+def _stage_parity(P, orc, W, H, n, seed, scale, min_high_tile=None):
     cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
-    gf = S.random_gaussians(n, cam, seed, scale=(0.01, 0.4), neg_opacity_frac=0.1,
+    gf = S.random_gaussians(n, cam, seed, scale=scale, neg_opacity_frac=0.1,
                             behind_frac=0.05)
     prm_o = orc.params_array()
     say("raster stage", W, H, n, seed)
@@ -218,6 +230,9 @@ def test_raster_stage_parity(P, orc, W, H, n, seed):
     assert st["n_candidates"] == C_ref
     assert st["n_pairs"] == P_ref
     tile, slot, ranges = vb.sorted_lists()
+    if min_high_tile is not None:
+        say(f"  pairs with tile id >= {min_high_tile}: {int((tile >= min_high_tile).sum())}")
+        assert (tile >= min_high_tile).sum() > 1000
     assert np.array_equal(tile, ref["bs"]["tile_of"])
     assert np.array_equal(slot, ref["bs"]["gid_of"])
     assert np.array_equal(ranges, ref["bs"]["ranges"])
