@@ -219,6 +219,74 @@ def test_partition_of_unity_and_weights(orc):
                 assert T[y, x] < 1e-4
 
 
+def test_skip_error_certificate(orc):
+    _check_skip_certificate(orc)
+
+
+def test_skip_certificate_catches_a_planted_mistake(orc):
+    """Logging a_i T_(i+1) (the transmittance after the Gaussian) instead of
+    a_i T_i, in a copy of the oracle, breaks the certificate."""
+    import tempfile
+    src = orc.source()
+    good = "      w[list[i]] += wt;"
+    assert src.count(good) == 1
+    with tempfile.TemporaryDirectory() as d:
+        with orc.variant(src.replace(good, "      w[list[i]] += wt * (1.0 - a);"), d,
+                         tag="weight_after"):
+            with pytest.raises(AssertionError):
+                _check_skip_certificate(orc)
+
+
+def _check_skip_certificate(orc):
+    """The logged blend weight bounds what leaving an anchor out can change:
+    with colours and background in [0, 1] and no early stop (t_min = 0),
+    removing anchor j's Gaussians changes each channel by at most
+    sum_{i in j} a_i T_i at every pixel, so summed over the image by at
+    most the anchor's logged weight w_j.  Groups of k = 10 consecutive
+    Gaussians stand for anchors."""
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), 64, 64, 60.0)
+    g = S.random_gaussians(800, cam, 9)
+    rng = np.random.default_rng(9)
+    g[11:14] = rng.uniform(0.0, 1.0, (3, g.shape[1])).astype(np.float32)
+    prm = orc.params_array(t_min=0.0, bg=(0.3, 0.6, 0.9))
+    base = orc.rasterize(g, cam, prm, weights=True)
+    k = 10
+    w = base["weights"].reshape(-1, k).sum(axis=1)
+    order = np.argsort(-w)
+    tight = []
+    for j in list(order[:10]) + list(order[40:50]):
+        g2 = g.copy()
+        g2[10, j * k:(j + 1) * k] = 0.0  # opacity 0: culled
+        out = orc.rasterize(g2, cam, prm)
+        d = np.abs(out["img"] - base["img"]).sum(axis=(1, 2))
+        assert np.all(d <= w[j] * (1 + 1e-12) + 1e-12), (j, d, w[j])
+        tight.append(d.max() / max(w[j], 1e-300))
+    # the bound is not vacuous: for the heaviest anchors it is within a few times
+    assert max(tight[:10]) > 0.2, tight
+    # and it is exact where nothing overlaps: 16 small white Gaussians on a
+    # grid, black background, so removing one changes the image by exactly
+    # its logged weight (T_i = 1 at each of its pixels)
+    cam = S.look_at((0.0, -20.0, 0.0), (0.0, 0.0, 0.0), 128, 128, 60.0)
+    xs = (-6.0, -2.0, 2.0, 6.0)
+    n = 16
+    g = np.zeros((14, n), np.float32)
+    g[0] = np.repeat(xs, 4)
+    g[2] = np.tile(xs, 4)
+    g[3:6] = 0.05
+    g[6] = 1.0  # identity rotation (w, x, y, z)
+    g[10] = 0.7
+    g[11:14] = 1.0
+    prm = orc.params_array(t_min=0.0)
+    base = orc.rasterize(g, cam, prm, weights=True)
+    assert base["bs"]["n_pairs"] >= n
+    for j in range(n):
+        g2 = g.copy()
+        g2[10, j] = 0.0
+        out = orc.rasterize(g2, cam, prm)
+        d = (base["img"] - out["img"]).sum(axis=(1, 2))
+        np.testing.assert_allclose(d, base["weights"][j], rtol=1e-9)
+
+
 def test_transmittance_monotone(orc):
     """T after each prefix of a pixel's list is non-increasing: rendering the
     first j Gaussians (front-most) of the depth order gives T_j >= T_{j+1}."""
