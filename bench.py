@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--views", type=int, default=200, help="trajectory length")
     ap.add_argument("--inflight", type=int, default=4,
                     help="views in flight at once (one stream and buffer set each)")
-    ap.add_argument("--cpu-views", type=int, default=20,
+    ap.add_argument("--cpu-views", type=int, default=40,
                     help="timed views the CPU oracle renders (evenly spaced among them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the PSNR sweep (profiling runs)")
