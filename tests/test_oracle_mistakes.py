@@ -6,6 +6,8 @@ pins.  CPU only: the copies are built with gcc into a temporary directory."""
 
 import tempfile
 
+import numpy as np
+
 import pytest
 
 from tests import test_oracle_backward as B
@@ -102,3 +104,58 @@ def test_a_pin_catches_the_mistake(orc, name):
 def test_the_unplanted_oracle_passes_every_pin(orc):
     for p in PINS.values():
         p(orc)
+
+
+# ---- the Python oracles: a mistake is planted by replacing a module
+# attribute (a constant or a function) for the duration of the check ----
+
+def _explicit_pins(orc):
+    import tests.test_oracle_explicit as TE
+    from oracle import explicit as EX
+    TE.test_sh_basis_matches_scipy(EX)
+    TE.test_sh_low_order_closed_forms(EX)
+    TE.test_decode_explicit_closed_forms(EX)
+
+
+def _loss_pins(orc):
+    import tests.test_oracle_losses as TL
+    from oracle import losses as LO
+    TL.test_ssim_matches_brute_force(LO)
+    TL.test_ssim_constant_images_closed_form(LO)
+    TL.test_photometric_gradient_fd(LO)
+
+
+def _densify_pins(orc):
+    import tests.test_oracle_densify as TD
+    from oracle import densify as DO
+    TD.test_level_thresholds(DO)
+
+
+def _sh_norm_swapped(l, m):
+    import math
+    return math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l + m) / math.factorial(l - m))
+
+
+PY_MISTAKES = {
+    "SH normalisation with (l - m)! and (l + m)! swapped": ("oracle.explicit", "_norm",
+                                                           _sh_norm_swapped, _explicit_pins),
+    "SSIM window of sigma 1.0": ("oracle.losses", "SSIM_SIGMA", 1.0, _loss_pins),
+    "SSIM constants swapped": ("oracle.losses", "SSIM_C1", 0.03 ** 2, _loss_pins),
+    "densification thresholds from 2^(-beta L)": (
+        "oracle.densify", "level_thresholds",
+        lambda tau_g, beta, n_levels: np.array(
+            [float(np.float32(tau_g)) * np.exp2(-float(np.float32(beta)) * L)
+             for L in range(n_levels + 1)]).astype(np.float32),
+        _densify_pins),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MISTAKES))
+def test_a_pin_catches_the_python_mistake(orc, monkeypatch, name):
+    import importlib
+    mod, attr, bad, pins = PY_MISTAKES[name]
+    m = importlib.import_module(mod)
+    pins(orc)  # the unmodified module passes
+    monkeypatch.setattr(m, attr, bad)
+    with pytest.raises(AssertionError):
+        pins(orc)
