@@ -2,12 +2,12 @@
 a plausible slip would (a dropped term, a wrong sign, a swapped operand) and
 checks that at least one of the listed pins, which never reuse the oracle's
 own formulas, now fails.  A mistake no pin catches would be a gap in the
-pins.  CPU only: the copies are built with gcc into a temporary directory."""
+pins.  The Python oracles get theirs by replacing a module attribute.  CPU
+only: the C copies are built with gcc into a temporary directory."""
 
 import tempfile
 
 import numpy as np
-
 import pytest
 
 from tests import test_oracle_backward as B
