@@ -103,3 +103,20 @@ int main(void) {
                                        L.RasterStats, L.Explicit, L.ExplicitGrads,
                                        L.DensifyStats, L.DensifyParams)]
     assert got == want
+
+
+def test_no_fallback_without_the_library_or_a_gpu(monkeypatch):
+    """The product path never falls back: a missing library raises, and so
+    does asking for device buffers without a GPU."""
+    import torch
+    from paper_2403_17898_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/liboctgs.so")
+    with pytest.raises(L.OctgsError):
+        L.lib()
+    if not torch.cuda.is_available():
+        import paper_2403_17898_amd as P
+        from synth import scenes as S
+        sc = S.make_config1()
+        with pytest.raises(P.OctgsError):
+            P.DeviceScene.from_scene(sc)
