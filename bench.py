@@ -316,7 +316,8 @@ def main():
                           vbs if bufs is None else bufs, render_one, depth)
 
     def timed(prec, depth=D, views=None, params=prm):
-        return timed_views(lambda k, c, s_: vbs[k].render(ds, c, params, precision=prec, stream=s_),
+        return timed_views(lambda k, c, s_: vbs[k].render(ds, c, params, precision=prec, stream=s_,
+                                                          keep_last=False),
                            depth, views)
 
     ms32, wall32 = timed(P.OCTGS_FP32)
@@ -383,14 +384,16 @@ def main():
     # pixel and Gaussian blended (Eq. 2) it evaluates the 2D Gaussian,
     # alpha, the colour update and T, 21 FLOP counting exp as one.  Units per
     # launch = sum over pixels of the entries each consumed (the `last`
-    # output).  Its algorithmic HBM bytes per launch are reported beside.
+    # output of a counting pass; the timed launches leave it out).  Its
+    # algorithmic HBM bytes per launch are reported beside.
     npix = W * H
     ntiles = ((W + 15) // 16) * ((H + 15) // 16)
     flop = FLOP_PER_BLEND * mean["blends"]
     ach = flop / (avg["composite"] * 1e-3) / 1e12
     # unique bytes: list entries 4 B per pair, the projected record 36 B per
-    # visible Gaussian, tile ranges 8 B, and 20 B written per pixel
-    alg_bytes = 4.0 * mean["pairs"] + 36.0 * mean["visible"] + 8.0 * ntiles + 20.0 * npix
+    # visible Gaussian, tile ranges 8 B, and 16 B written per pixel (colour
+    # and T_final)
+    alg_bytes = 4.0 * mean["pairs"] + 36.0 * mean["visible"] + 8.0 * ntiles + 16.0 * npix
     roofline = {"kernel": "composite", "bound": "alu", "achieved": round(ach, 2),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
@@ -528,6 +531,13 @@ def stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, orde
     if args.predict_stages:
         from paper_2403_17898_amd import skip as SK
         net, sb = SK.SkipNet(seed=1), SK.SkipBuffers(vb)
+    # the timed composites leave out the per-pixel entry count (no backward
+    # follows them); a pass before the timed loop, so that the loop's
+    # dispatches are the last of each kernel, renders the same views with
+    # it to count the blends
+    for i in range(nviews):
+        vb.render(ds, ccams[order[i]], prm, precision=P.OCTGS_BF16, keep_last=True)
+        sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
     for i in range(nviews):
         c = ccams[order[i]]
         ev[0].record(sh)
@@ -536,7 +546,7 @@ def stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, orde
         ev[2].record(sh)
         vb.decode(ds, c, P.OCTGS_BF16)
         ev[3].record(sh)
-        vb.rasterize(c, prm, stage_events=ev[4:])
+        vb.rasterize(c, prm, stage_events=ev[4:], keep_last=False)
         torch.cuda.synchronize()
         vms = ev[0].elapsed_ms(ev[1]) + ev[2].elapsed_ms(ev[3])
         tot["select"] += ev[0].elapsed_ms(ev[1])
@@ -549,7 +559,6 @@ def stage_loop(args, P, L, torch, np, sc, cams, ccams, ds, prm, vb, stream, orde
             SK.predict(vb, sb, ds, c, net, 0.0, stream=stream)
             torch.cuda.synchronize()
         st = vb.stats()
-        sums["blends"] += int(vb.last.sum(dtype=torch.int64).item())
         sums["selected"] += st["n_selected"]
         sums["slots"] += st["n_slots"]
         sums["visible"] += st["n_visible"]
@@ -641,7 +650,7 @@ def explicit_path(args, P, S, torch, np, sc, ccams, prm, W, H, D, streams, timed
     res = {"sh_degree": 3}
     for name, prec in (("fp32", P.OCTGS_FP32), ("bf16", P.OCTGS_BF16)):
         ms, _ = timed_views(lambda k, c, s: xvbs[k].render_explicit(de, c, prm, precision=prec,
-                                                                   stream=s),
+                                                                   stream=s, keep_last=False),
                             D, bufs=xvbs)
         res["fps_" + name] = round(rate(args, ms, len(ccams)), 2)
         res["ms_per_view_" + name] = round(1e3 / rate(args, ms, len(ccams)), 4)
@@ -763,7 +772,7 @@ def skip_study(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vbs, D, streams,
 
         def one(k, c, s_, net=net, thr=thr):
             SK.render_skip(vbs[k], sbs[k], ds, c, prm, net, thr, precision=P.OCTGS_BF16,
-                           stream=s_)
+                           stream=s_, keep_last=False)
 
         r = {"logit_threshold": thr, "holdout_worst_psnr_db": round(best[1], 2) if best else None,
              "holdout_skipped_fraction": round(1.0 - hkept / max(hsel, 1), 4),
@@ -793,7 +802,7 @@ def skip_study(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vbs, D, streams,
         c, i = v
         vbs[k].select(ds, c, prm, stream=s_)
         vbs[k].decode(ds, c, P.OCTGS_BF16, idx=keep[i][0], count=keep[i][1], stream=s_)
-        vbs[k].rasterize(c, prm, stream=s_)
+        vbs[k].rasterize(c, prm, stream=s_, keep_last=False)
 
     psn, sel, kept, pairs = [], 0, 0, 0
     for i in tset:
@@ -820,7 +829,7 @@ def skip_study(args, P, S, torch, np, sc, ds, ccams, prm, W, H, vbs, D, streams,
     # the fast path without the predictor, full BF16 decode, on the same views
     ms16, _ = time_views(args, torch, streams, ccams, vbs,
                          lambda k, c, s_: vbs[k].render(ds, c, prm, precision=P.OCTGS_BF16,
-                                                       stream=s_), D)
+                                                       stream=s_, keep_last=False), D)
     fps_full = rate(args, ms16, len(ccams))
     # full decode is the fallback when the predictor skips under 1 % of the
     # held-out anchors or its path is not faster than full decode
@@ -905,7 +914,8 @@ def city_path(args, P, S, torch, np, prm, D, streams):
 
     def timed(prec):
         return time_views(args, torch, streams, cams, vbs,
-                          lambda k, c, s_: vbs[k].render(ds, c, prm, precision=prec, stream=s_), D)
+                          lambda k, c, s_: vbs[k].render(ds, c, prm, precision=prec, stream=s_,
+                                                         keep_last=False), D)
 
     ms32, _ = timed(P.OCTGS_FP32)
     ms16, _ = timed(P.OCTGS_BF16)

@@ -285,7 +285,8 @@ OCTGS_API size_t octgs_raster_workspace_bytes(int64_t gauss_capacity, int64_t pa
  *  - per pixel: a_i = min(alpha_max, opacity_i * G'_i(x')), C = sum T_i a_i c_i,
  *    T_i = prod_{j<i} (1 - a_j), stop after T < t_min, add T * bg.
  * Outputs (device): rgb planar [3][H][W]; T_final [H][W]; last [H][W] = list
- * entries the pixel consumed (needed by the backward pass); gauss_w (nullable,
+ * entries the pixel consumed (needed by the backward pass; nullable for a
+ * render that no backward follows, which then skips counting); gauss_w (nullable,
  * [g->capacity]) = per-slot sum over pixels of a_i T_i (blend-weight log).
  * The workspace keeps the sorted lists for octgs_rasterize_bwd and starts
  * with octgs_raster_stats.  stage_events (nullable): 2 * OCTGS_RASTER_STAGES

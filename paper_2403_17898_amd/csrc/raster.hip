@@ -16,8 +16,9 @@
 //   sort      Onesweep on the tile id (1-3 passes over pairs); stable, so
 //             each tile keeps depth order, ties by slot index
 //   ranges    [start, end) per tile
-//   composite one 256-thread block per 16x16 tile, batches of 256
-//             Gaussians staged in LDS, block exit once every pixel is done
+//   composite one wave per 16x16 tile (four pixels of a column per lane),
+//             batches of 128 Gaussians staged in LDS, exit once every pixel
+//             is done
 //
 // Sorting depth once per Gaussian and then only the tile id per pair gives
 // the same (tile, depth, slot) order as one sort of 64-bit tile|depth keys
@@ -730,7 +731,7 @@ struct CompLds {
 
 // The LDS lives in the kernel and is passed in, so the two AMIN
 // instantiations share one allocation.
-template <bool LOG, bool AMIN>
+template <bool LOG, bool AMIN, bool LAST>
 __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &lds) {
   float4 *sA = lds.sA, *sB = lds.sB, *sC = lds.sC;
   uint32_t *s_slot = lds.s_slot;
@@ -803,11 +804,13 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
         cg[k] = fma_(w, B.w, cg[k]);
         cb[k] = fma_(w, cbl, cb[k]);
         T[k] = T[k] - w;
-        // a done lane blends nothing more, so its T stays below t_min; an
-        // outside lane starts at T = 0
-        const bool n = T[k] < tmin;
-        last[k] = (n && !done[k]) ? li : last[k];
-        done[k] = n;
+        // `last` follows every entry a live pixel blends and freezes once the
+        // pixel is done: the entry that took T below t_min, else the list
+        // length (a live pixel keeps the wave going to the end).  A done lane
+        // blends nothing more, so its T stays below t_min; an outside lane
+        // starts at T = 0.
+        if (LAST) last[k] = done[k] ? last[k] : li;
+        done[k] = T[k] < tmin;
         if (LOG) wsum += w;
       }
       if (LOG) {
@@ -844,7 +847,7 @@ __device__ __forceinline__ void composite_tile(const CompArgs &a, CompLds<LOG> &
       a.rgb[plane + pix] = fma_(T[k], a.bg[1], cg[k]);
       a.rgb[2 * plane + pix] = fma_(T[k], a.bg[2], cb[k]);
       a.T_final[pix] = T[k];
-      a.last[pix] = last[k];
+      if (LAST) a.last[pix] = last[k];
     }
   }
 }
@@ -859,10 +862,19 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompArgs a) {
                        (a.ws.hdr->sync_error ? OCTGS_STATUS_SYNC_ERROR : 0u);
     if (f) atomicOr(a.status, f);
   }
-  if (a.alpha_min > 0.0f)
-    composite_tile<LOG, true>(a, lds);
-  else
-    composite_tile<LOG, false>(a, lds);
+  // a render that no backward follows may leave out the per-pixel entry
+  // count, one select per pixel and entry
+  if (a.alpha_min > 0.0f) {
+    if (a.last)
+      composite_tile<LOG, true, true>(a, lds);
+    else
+      composite_tile<LOG, true, false>(a, lds);
+  } else {
+    if (a.last)
+      composite_tile<LOG, false, true>(a, lds);
+    else
+      composite_tile<LOG, false, false>(a, lds);
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -941,7 +953,7 @@ int octgs_rasterize_fwd(const octgs_gaussians *g, const octgs_camera *cam,
                         const octgs_raster_params *p, int64_t pair_capacity, float *rgb,
                         float *T_final, uint32_t *last, float *gauss_w, void *wsp,
                         size_t ws_bytes, void *const *stage_events, octgs_stream stream) {
-  if (!g || !cam || !p || !rgb || !T_final || !last || !wsp) return OCTGS_EINVAL;
+  if (!g || !cam || !p || !rgb || !T_final || !wsp) return OCTGS_EINVAL;
   if (!g->data || !g->count || g->capacity < 0 || g->capacity >= (int64_t(1) << 31))
     return OCTGS_EINVAL;
   // candidate counts saturate at 2^30 - 1, which must exceed the capacity

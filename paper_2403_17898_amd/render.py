@@ -468,10 +468,12 @@ class ViewBuffers:
                                               stream_handle(stream)), "octgs_decode_explicit")
 
     def render_explicit(self, ex: "DeviceExplicit", cam: L.Camera, params: L.RasterParams,
-                        precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
+                        precision: int = L.OCTGS_FP32, stream=None, stage_events=None,
+                        keep_last: bool = True):
         self.select(ex, cam, params, stream=stream)
         self.decode_explicit(ex, cam, precision, stream=stream)
-        self.rasterize(cam, params, stream=stream, stage_events=stage_events)
+        self.rasterize(cam, params, stream=stream, stage_events=stage_events,
+                       keep_last=keep_last)
 
     def decode_explicit_bwd(self, ex: "DeviceExplicit", cam: L.Camera, grads: "ExplicitGrads",
                             dgauss: Optional[torch.Tensor] = None,
@@ -487,7 +489,11 @@ class ViewBuffers:
                 "octgs_decode_explicit_bwd")
 
     def rasterize(self, cam: L.Camera, params: L.RasterParams, gauss: Optional[torch.Tensor] = None,
-                  count: Optional[torch.Tensor] = None, stream=None, stage_events=None):
+                  count: Optional[torch.Tensor] = None, stream=None, stage_events=None,
+                  keep_last: bool = True):
+        """Forward rasterization into self.rgb and self.T; self.last (the
+        per-pixel list entry count the backward replays from) only with
+        keep_last, which a render that no backward follows may leave off."""
         g = self._g
         if gauss is not None:
             g = L.Gaussians()
@@ -498,16 +504,20 @@ class ViewBuffers:
             if gauss.shape[1] != self.gcap:
                 raise L.OctgsError("Gaussian buffer capacity must equal the workspace capacity")
         L.check(L.lib().octgs_rasterize_fwd(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(params),
-                                            self.pcap, _ptr(self.rgb), _ptr(self.T), _ptr(self.last),
+                                            self.pcap, _ptr(self.rgb), _ptr(self.T),
+                                            _ptr(self.last) if keep_last else None,
                                             _ptr(self.gauss_w), _ptr(self.ras_ws), self.ras_ws.numel(),
                                             _events(stage_events), stream_handle(stream)),
                 "octgs_rasterize_fwd")
+        self.last_valid = bool(keep_last)
 
     def render(self, scene: DeviceScene, cam: L.Camera, params: L.RasterParams,
-               precision: int = L.OCTGS_FP32, stream=None, stage_events=None):
+               precision: int = L.OCTGS_FP32, stream=None, stage_events=None,
+               keep_last: bool = True):
         self.select(scene, cam, params, stream=stream)
         self.decode(scene, cam, precision, stream=stream)
-        self.rasterize(cam, params, stream=stream, stage_events=stage_events)
+        self.rasterize(cam, params, stream=stream, stage_events=stage_events,
+                       keep_last=keep_last)
 
     def volume_loss_grad(self, weight: float, loss: torch.Tensor, stream=None):
         """Adds weight * sum Prod(s) over the decoded, rendered slots to loss and
@@ -520,6 +530,8 @@ class ViewBuffers:
                       stream=None, stage_events=None):
         """dL/dGaussian planar [14][gcap] into self.dgauss, for the image of
         the last rasterize() with these buffers."""
+        if not getattr(self, "last_valid", False):
+            raise L.OctgsError("rasterize_bwd needs a forward rasterize() with keep_last=True")
         if getattr(self, "dgauss", None) is None:
             self.dgauss = torch.empty_like(self.gauss)
         L.check(L.lib().octgs_rasterize_bwd(ctypes.byref(self._g), ctypes.byref(cam),

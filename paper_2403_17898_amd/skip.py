@@ -121,12 +121,13 @@ def predict(vb: ViewBuffers, sb: SkipBuffers, scene: DeviceScene, cam: L.Camera,
 
 def render_skip(vb: ViewBuffers, sb: SkipBuffers, scene: DeviceScene, cam: L.Camera,
                 params: L.RasterParams, net: SkipNet, logit_threshold: float,
-                precision: int = L.OCTGS_BF16, stream=None, stage_events=None):
+                precision: int = L.OCTGS_BF16, stream=None, stage_events=None,
+                keep_last: bool = True):
     """select -> skip prediction -> decode of the kept anchors -> rasterize."""
     vb.select(scene, cam, params, stream=stream)
     predict(vb, sb, scene, cam, net, logit_threshold, stream=stream)
     vb.decode(scene, cam, precision, idx=sb.keep_idx, count=sb.keep_count, stream=stream)
-    vb.rasterize(cam, params, stream=stream, stage_events=stage_events)
+    vb.rasterize(cam, params, stream=stream, stage_events=stage_events, keep_last=keep_last)
 
 
 def anchor_weights(vb: ViewBuffers, out: torch.Tensor, stream=None):

@@ -249,6 +249,42 @@ def _stage_parity(P, orc, W, H, n, seed, scale, min_high_tile=None):
     np.testing.assert_allclose(w, ref["weights"], rtol=2e-4, atol=2e-4)
 
 
+@pytest.mark.parametrize("alpha_min,log", [(0.0, False), (1.0 / 255.0, False), (0.0, True),
+                                             (1.0 / 255.0, True)])
+def test_forward_without_entry_count(P, alpha_min, log):
+    """A forward with a null `last` (a render that no backward follows)
+    writes the same image, transmittance and blend-weight log bit for bit,
+    leaves the `last` buffer alone, and the backward then refuses to run."""
+    W, H, n = 333, 200, 20000
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
+    gf = S.random_gaussians(n, cam, 9, scale=(0.01, 0.4), neg_opacity_frac=0.1,
+                            behind_frac=0.05)
+    say("forward without last", alpha_min, log)
+    prm = P.raster_params(alpha_min=alpha_min)
+    vb = P.ViewBuffers(n, 1, W, H, 1 << 22, gauss_capacity=n, log_weights=log)
+    gt = torch.as_tensor(gf).cuda()
+    cnt = torch.tensor([n], dtype=torch.int32).cuda()
+    c = P.make_camera(cam)
+    out = []
+    for keep in (True, False):
+        vb.last.fill_(-7)
+        if log:
+            vb.gauss_w.zero_()
+        vb.rasterize(c, prm, gauss=gt, count=cnt, keep_last=keep)
+        torch.cuda.synchronize()
+        out.append((_np(vb.rgb).copy(), _np(vb.T).copy(), _np(vb.last).copy(),
+                    _np(vb.gauss_w).copy() if log else None))
+    (i1, t1, l1, w1), (i2, t2, l2, w2) = out
+    assert np.array_equal(i1.view(np.uint32), i2.view(np.uint32))
+    assert np.array_equal(t1.view(np.uint32), t2.view(np.uint32))
+    assert (l1 >= 0).all() and (l2 == -7).all()
+    if log:
+        # per-slot sums gathered with float atomics: the order can differ
+        np.testing.assert_allclose(w1, w2, rtol=1e-5, atol=1e-7)
+    with pytest.raises(P.OctgsError):
+        vb.rasterize_bwd(c, prm, torch.zeros(3, H, W, device="cuda"))
+
+
 def test_raster_equal_depths(P, orc):
     cam = S.look_at((0.0, 0.0, -10.0), (0.0, 0.0, 0.0), 64, 64, 60.0)
     gf = S.tile_aligned_gaussians(cam, [5.0] * 40 + [7.0] * 40, seed=3)
