@@ -3,9 +3,11 @@
 // gradients of the anchor features, positions, offsets, scalings and of the
 // three MLP heads' weights and biases.  FP32 throughout.
 //
-// One fused kernel.  A persistent block stages every weight in LDS once,
-// then walks tiles of 16 listed anchors; per tile, every product runs on
-// v_mfma_f32_16x16x4_f32 out of LDS:
+// One fused kernel.  A persistent block of two wave groups (4 waves each)
+// stages every weight in LDS once, then walks pairs of tiles of 16 listed
+// anchors, one tile per group, the groups in step at the block's barriers so
+// that each hides the other's memory and LDS latency; per tile, every
+// product runs on v_mfma_f32_16x16x4_f32 out of LDS:
 //   Hp = X W1 + b1            forward recompute (per head: 36 -> W)
 //   Y  = relu(Hp) W2 + b2     forward recompute (per head: W -> k, 3k, 7k)
 //   dY                        activation derivatives; one 16-lane row per
@@ -15,7 +17,8 @@
 //   dX = dHp W1^T             -> feature and position gradients
 //   dW2 += relu(Hp)^T dY, dW1 += X^T dHp, db += column sums
 // The weight-gradient sums stay in MFMA accumulators across all of the
-// block's tiles; each block writes them once to its row of a workspace, and
+// block's tiles; the second group hands its sums to the first through LDS
+// (added in group order), each block writes them once to its row of a workspace, and
 // a second kernel adds the rows in block order into the caller's arrays (no
 // atomics; the result is the same on every run).  The anchor count lives on
 // the device.
@@ -48,7 +51,9 @@ constexpr int kYS = kMaxOutP + 4;
 constexpr int kW1P = kMaxW + 4;        // W1 row pitch: conflict-free column reads for dX
 constexpr int kMaxT1 = 9;              // dW1 output tiles per wave (3 x 12 / 4)
 constexpr int kMaxT2 = 11;             // dW2 output tiles per wave (4 x 11 / 4)
-constexpr int kDecBwdGrid = 256;       // persistent blocks (one per CU: ~120 KB of LDS each)
+constexpr int kDecBwdGrid = 256;       // persistent blocks (one per CU: ~159 KB of LDS each)
+constexpr int kDecGroups = 2;          // wave groups per block, one tile each
+constexpr int kDecBwdThreads = kDecGroups * kBlock;
 
 struct DecBwdArgs {
   int k, W, cap_anchors;
@@ -69,11 +74,8 @@ struct DecBwdArgs {
   float *part;     // [gridDim.x][P]
 };
 
-struct DecBwdLds {
-  float W1s[3 * kIn * kW1P];     // W1 heads, rows of kW1P
-  float W2s[kMaxW * 11 * kMaxK]; // W2 heads [W][k], [W][3k], [W][7k], packed
-  float b1s[3 * kMaxW];
-  float b2s[kMaxOutP];           // padded output layout
+// one group's tile buffers
+struct DecBwdTile {
   float X[kRB][kXS];
   float Hp[kRB][kHS];
   float Yd[kRB][kYS];            // Y, overwritten in place by dY
@@ -82,6 +84,22 @@ struct DecBwdLds {
   float Dn[kRB][4];              // distance and unit direction per anchor
   uint32_t aidx[kRB];
 };
+
+// the second group's weight-gradient sums, handed to the first at the end
+// (in the tile buffers, which are free by then): per lane kMaxT1 + kMaxT2
+// accumulator tiles of 4 floats and the two bias sums
+constexpr int kXchSlots = 4 * (kMaxT1 + kMaxT2) + 2;
+
+struct DecBwdLds {
+  float W1s[3 * kIn * kW1P];     // W1 heads, rows of kW1P
+  float W2s[kMaxW * 11 * kMaxK]; // W2 heads [W][k], [W][3k], [W][7k], packed
+  float b1s[3 * kMaxW];
+  float b2s[kMaxOutP];           // padded output layout
+  DecBwdTile tl[kDecGroups];
+};
+static_assert(sizeof(DecBwdTile) * kDecGroups >= sizeof(float) * kXchSlots * kBlock,
+              "the hand-over of the second group's sums fits in the tile buffers");
+static_assert(sizeof(DecBwdLds) <= 160 * 1024, "LDS of one CU");
 
 __device__ __forceinline__ const float *pick3(const float *const p[3], int h) {
   return h == 0 ? p[0] : (h == 1 ? p[1] : p[2]);
@@ -113,19 +131,25 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-// U float4 loads per thread, all in flight before the first store
+// U float4 loads per thread (thread t of the block's kDecBwdThreads), all in
+// flight before the first store
 template <int U>
 struct Ld4 {
   float4 v[U];
   __device__ __forceinline__ void load(const float *src, int n4, int t) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = reinterpret_cast<const float4 *>(src)[min(t + u * kBlock, n4 - 1)];
+    for (int u = 0; u < U; ++u)
+      v[u] = reinterpret_cast<const float4 *>(src)[min(t + u * kDecBwdThreads, n4 - 1)];
   }
 };
 
-__global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
-  __shared__ DecBwdLds s;
-  const int t = threadIdx.x, w = t / kWave, l = __lane_id(), g = l / 16, lc = l % 16;
+__global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
+  __shared__ DecBwdLds sh;
+  // tb: thread of the block (weight staging); t, w: thread and wave within
+  // the group, which owns tile buffers s
+  const int tb = threadIdx.x, grp = tb / kBlock, t = tb % kBlock;
+  const int w = t / kWave, l = __lane_id(), g = l / 16, lc = l % 16;
+  DecBwdTile &s = sh.tl[grp];
   const int k = a.k, W = a.W;
   const int nhw = W / 16, n1t = 3 * nhw;
   const int n2t = a.t[0] + a.t[1] + a.t[2];
@@ -135,35 +159,41 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
   {
     const int n1 = kIn * W / 4, wk4 = W * k / 4;
     {
-      Ld4<3> x0, x1, x2;
-      x0.load(a.w1[0], n1, t); x1.load(a.w1[1], n1, t); x2.load(a.w1[2], n1, t);
+      constexpr int kU1 = (kIn * kMaxW / 4 + kDecBwdThreads - 1) / kDecBwdThreads;  // 2
+      Ld4<kU1> x0, x1, x2;
+      x0.load(a.w1[0], n1, tb); x1.load(a.w1[1], n1, tb); x2.load(a.w1[2], n1, tb);
       auto put1 = [&](int h, const float4 &v, int i4) {
         // element e = 4 i4 .. 4 i4 + 3 of head h's [kIn][W], row pitch kW1P
         const int e = 4 * i4, r = e / W, c = e - r * W;
-        float *d = &s.W1s[(h * kIn + r) * kW1P + c];
+        float *d = &sh.W1s[(h * kIn + r) * kW1P + c];
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
       };
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int i4 = min(t + u * kBlock, n1 - 1);
+      for (int u = 0; u < kU1; ++u) {
+        const int i4 = min(tb + u * kDecBwdThreads, n1 - 1);
         put1(0, x0.v[u], i4); put1(1, x1.v[u], i4); put1(2, x2.v[u], i4);
       }
     }
-    Ld4<1> y0;
-    Ld4<3> y1;
-    Ld4<7> y2;
-    y0.load(a.w2[0], wk4, t); y1.load(a.w2[1], 3 * wk4, t); y2.load(a.w2[2], 7 * wk4, t);
-    float4 *w2s = reinterpret_cast<float4 *>(s.W2s);
-    w2s[min(t, wk4 - 1)] = y0.v[0];
+    constexpr int kWk4 = kMaxW * kMaxK / 4;  // float4s of the k-wide head at most (256)
+    constexpr int kU20 = (kWk4 + kDecBwdThreads - 1) / kDecBwdThreads;          // 1
+    constexpr int kU21 = (3 * kWk4 + kDecBwdThreads - 1) / kDecBwdThreads;      // 2
+    constexpr int kU22 = (7 * kWk4 + kDecBwdThreads - 1) / kDecBwdThreads;      // 4
+    Ld4<kU20> y0;
+    Ld4<kU21> y1;
+    Ld4<kU22> y2;
+    y0.load(a.w2[0], wk4, tb); y1.load(a.w2[1], 3 * wk4, tb); y2.load(a.w2[2], 7 * wk4, tb);
+    float4 *w2s = reinterpret_cast<float4 *>(sh.W2s);
 #pragma unroll
-    for (int u = 0; u < 3; ++u) w2s[wk4 + min(t + u * kBlock, 3 * wk4 - 1)] = y1.v[u];
+    for (int u = 0; u < kU20; ++u) w2s[min(tb + u * kDecBwdThreads, wk4 - 1)] = y0.v[u];
 #pragma unroll
-    for (int u = 0; u < 7; ++u) w2s[4 * wk4 + min(t + u * kBlock, 7 * wk4 - 1)] = y2.v[u];
-    if (t < 3 * W) s.b1s[t] = pick3(a.b1, t / W)[t % W];
-    if (t < 16 * n2t) {
+    for (int u = 0; u < kU21; ++u) w2s[wk4 + min(tb + u * kDecBwdThreads, 3 * wk4 - 1)] = y1.v[u];
+#pragma unroll
+    for (int u = 0; u < kU22; ++u) w2s[4 * wk4 + min(tb + u * kDecBwdThreads, 7 * wk4 - 1)] = y2.v[u];
+    if (tb < 3 * W) sh.b1s[tb] = pick3(a.b1, tb / W)[tb % W];
+    if (tb < 16 * n2t) {
       int col0;
-      const int h = out_head(a, t / 16, col0), col = col0 + t % 16;
-      s.b2s[t] = col < sel3(a.outs, h) ? pick3(a.b2, h)[col] : 0.0f;
+      const int h = out_head(a, tb / 16, col0), col = col0 + tb % 16;
+      sh.b2s[tb] = col < sel3(a.outs, h) ? pick3(a.b2, h)[col] : 0.0f;
     }
   }
   __syncthreads();
@@ -175,9 +205,11 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
   for (int q = 0; q < kMaxT2; ++q) acc2[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   float db1r = 0.0f, db2r = 0.0f;  // thread t owns hidden column t / padded output column t
 
-  for (uint32_t tile = blockIdx.x; tile * kRB < M; tile += gridDim.x) {
-    const uint32_t r0 = tile * kRB;
-    const int rows = (int)min((uint32_t)kRB, M - r0);
+  // pairs of tiles, one per group; a group past the last anchor runs the
+  // pass on zero rows (every barrier is the whole block's)
+  for (uint32_t pair = blockIdx.x; (uint64_t)pair * kDecGroups * kRB < M; pair += gridDim.x) {
+    const uint32_t r0 = (pair * kDecGroups + grp) * kRB;
+    const int rows = r0 < M ? (int)min((uint32_t)kRB, M - r0) : 0;
     // ---- inputs: 16 threads per anchor ----
     {
       const int r = t / 16, part = t % 16;
@@ -214,9 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < kIn / 4; ++ks)
-          acc = mfma(s.X[lc][ks * 4 + g], s.W1s[(h * kIn + ks * 4 + g) * kW1P + hc], acc);
+          acc = mfma(s.X[lc][ks * 4 + g], sh.W1s[(h * kIn + ks * 4 + g) * kW1P + hc], acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s.Hp[4 * g + i][ct * 16 + lc] = acc[i] + s.b1s[ct * 16 + lc];
+        for (int i = 0; i < 4; ++i) s.Hp[4 * g + i][ct * 16 + lc] = acc[i] + sh.b1s[ct * 16 + lc];
       }
     }
     __syncthreads();
@@ -229,14 +261,14 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
         const int h = out_head(a, c, col0);
         const int ncol = sel3(a.outs, h), col = col0 + lc;
         const bool cv = col < ncol;
-        const float *wb = s.W2s + sel3(a.wo, h);
+        const float *wb = sh.W2s + sel3(a.wo, h);
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int ks = 0; ks < W / 4; ++ks) {
           const float av = fmaxf(s.Hp[lc][h * W + ks * 4 + g], 0.0f);
           acc = mfma(av, cv ? wb[(ks * 4 + g) * ncol + col] : 0.0f, acc);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s.Yd[4 * g + i][c * 16 + lc] = cv ? acc[i] + s.b2s[c * 16 + lc] : 0.0f;
+        for (int i = 0; i < 4; ++i) s.Yd[4 * g + i][c * 16 + lc] = cv ? acc[i] + sh.b2s[c * 16 + lc] : 0.0f;
       }
     }
     __syncthreads();
@@ -322,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
       if (ct < n1t) {
         const int h = ct / nhw, hc = (ct - h * nhw) * 16 + lc;
         const int ncol = sel3(a.outs, h);
-        const float *wb = s.W2s + sel3(a.wo, h) + hc * ncol;
+        const float *wb = sh.W2s + sel3(a.wo, h) + hc * ncol;
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int ks = 0; ks < (ncol + 3) / 4; ++ks) {
           const int kk = ks * 4 + g;
@@ -359,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
       f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int ks = 0; ks < 3 * W / 4; ++ks) {
         const int kk = ks * 4 + g, h = kk / W, kh = kk - h * W;
-        acc = mfma(s.dH[lc][kk], nv ? s.W1s[(h * kIn + n) * kW1P + kh] : 0.0f, acc);
+        acc = mfma(s.dH[lc][kk], nv ? sh.W1s[(h * kIn + n) * kW1P + kh] : 0.0f, acc);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) s.dX[4 * g + i][n] = acc[i];
@@ -397,7 +429,34 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd(DecBwdArgs a) {
     __syncthreads();
   }
 
-  // ---- this block's weight-gradient sums, one row of the workspace ----
+  // ---- the second group's sums into the first's (group order), then this
+  // block's weight-gradient sums, one row of the workspace ----
+  float *xch = reinterpret_cast<float *>(&sh.tl[0]);
+  __syncthreads();  // every group is done with its tile buffers
+  if (grp == 1) {
+#pragma unroll
+    for (int q = 0; q < kMaxT1; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xch[(4 * q + i) * kBlock + t] = acc1[q][i];
+#pragma unroll
+    for (int q = 0; q < kMaxT2; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xch[(4 * (kMaxT1 + q) + i) * kBlock + t] = acc2[q][i];
+    xch[(kXchSlots - 2) * kBlock + t] = db1r;
+    xch[(kXchSlots - 1) * kBlock + t] = db2r;
+  }
+  __syncthreads();
+  if (grp == 1) return;
+#pragma unroll
+  for (int q = 0; q < kMaxT1; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc1[q][i] += xch[(4 * q + i) * kBlock + t];
+#pragma unroll
+  for (int q = 0; q < kMaxT2; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc2[q][i] += xch[(4 * (kMaxT1 + q) + i) * kBlock + t];
+  db1r += xch[(kXchSlots - 2) * kBlock + t];
+  db2r += xch[(kXchSlots - 1) * kBlock + t];
   float *pp = a.part + (size_t)blockIdx.x * a.P;
 #pragma unroll
   for (int q = 0; q < kMaxT1; ++q) {
@@ -493,8 +552,10 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd_reduce(DecRedArgs a) {
 
 int partial_len(int k, int W) { return 3 * kIn * W + 11 * k * W + 3 * W + 11 * k; }
 
+// persistent blocks, each taking pairs of 16-anchor tiles
 int grid_for(int64_t mcap) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>((mcap + kRB - 1) / kRB, kDecBwdGrid));
+  const int64_t per = (int64_t)kDecGroups * kRB;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((mcap + per - 1) / per, kDecBwdGrid));
 }
 
 }  // namespace
@@ -558,7 +619,7 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   a.gosc = ga->offset_scale; a.gbsc = ga->base_scale;
   a.part = (float *)ws;
   const int grid = grid_for(mcap);
-  hipLaunchKernelGGL(k_dec_bwd, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_dec_bwd, dim3(grid), dim3(kDecBwdThreads), 0, s, a);
   DecRedArgs r;
   r.P = a.P; r.nblk = grid; r.k = k; r.W = W;
   r.p_w2 = a.p_w2; r.p_b1 = a.p_b1; r.p_b2 = a.p_b2;

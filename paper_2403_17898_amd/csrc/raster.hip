@@ -170,12 +170,10 @@ __device__ __forceinline__ bool tile_meets_ellipse(float mx, float my, float qa,
   return (in_x && in_y) || q <= 9.0f;
 }
 
-// Zeroes the radix-sort look-back words (256 per partition) of partitions
-// j with part j in [a, b) (part = keys per partition), j < nparts, in each of `passes` regions of
-// `stride` words; all threads of the block take part.
 // Clears, for each of `passes` sort passes (pass_words apart), the look-back
 // rows of the partitions that start in [a, b) (partitions of `part` keys,
-// nparts of them at capacity) and the group rows of the groups they open.
+// nparts of them at capacity) and the group rows of the groups they open;
+// called by whole blocks of 256 threads, one digit's words per thread.
 __device__ __forceinline__ void clear_partitions(uint32_t *lb, size_t pass_words, uint32_t a,
                                                  uint32_t b, int passes, int64_t nparts,
                                                  uint32_t part) {

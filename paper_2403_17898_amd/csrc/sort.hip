@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     const uint32_t part = s_part;
     const uint32_t base = part * PART;
 
-    // load and rank: wave w owns keys [base + w*512, base + (w+1)*512)
+    // load and rank: wave w owns keys [base + 64 w ITEMS, base + 64 (w + 1) ITEMS)
     uint32_t key[ITEMS], val[ITEMS], val2[ITEMS], rank[ITEMS];
     int dig[ITEMS];
     // unconditional loads at a clamped index keep all of them in flight
