@@ -69,9 +69,17 @@ def test_raster_backward_parity(P, orc, W, H, n, seed):
         assert nbad == 0, nm
 
 
-def test_decode_backward_parity(P, orc):
+@pytest.mark.parametrize("count", [25, 1, 16, 17, 33, 49])
+def test_decode_backward_parity(P, orc, count):
+    """Anchor lists of 1 to 49 rows: tiles of 16 go to the block's two wave
+    groups in pairs, so these cover a lone partial tile, a full pair, a pair
+    whose second tile holds one row, and a last pair with no second tile."""
     sc, cam = S.make_gradcheck_scene()
-    idx = np.arange(1, sc.n, 2, dtype=np.int64)
+    if count == 25:
+        idx = np.arange(1, sc.n, 2, dtype=np.int64)
+    else:
+        idx = np.random.default_rng(count).permutation(sc.n)[:count].astype(np.int64)
+    assert len(idx) == count
     rng = np.random.default_rng(3)
     G = len(idx) * sc.k
     dgauss = rng.standard_normal((14, G)).astype(np.float32)
