@@ -238,17 +238,44 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
     }
     __syncthreads();
     // ---- Hp = X W1 + b1 ----
+    // The wave's three column tiles share the A operand; each chunk of k-steps
+    // loads all of its operands before its products, so the matrix pipe does
+    // not wait on LDS between them.  (A tile past n1t reads a valid address
+    // and is not stored.)
+    {
+      f4 acc[3];
+      int boff[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int ct = w + 4 * q;
-      if (ct < n1t) {
+      for (int q = 0; q < 3; ++q) {
+        acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int ct = min(w + 4 * q, n1t - 1);
         const int h = ct / nhw, hc = (ct - h * nhw) * 16 + lc;
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        boff[q] = (h * kIn + g) * kW1P + hc;
+      }
 #pragma unroll
-        for (int ks = 0; ks < kIn / 4; ++ks)
-          acc = mfma(s.X[lc][ks * 4 + g], sh.W1s[(h * kIn + ks * 4 + g) * kW1P + hc], acc);
+      for (int k0 = 0; k0 < kIn / 4; k0 += 3) {
+        float av[3], bv[3][3];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s.Hp[4 * g + i][ct * 16 + lc] = acc[i] + sh.b1s[ct * 16 + lc];
+        for (int kk = 0; kk < 3; ++kk) {
+          av[kk] = s.X[lc][(k0 + kk) * 4 + g];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) bv[q][kk] = sh.W1s[boff[q] + (k0 + kk) * 4 * kW1P];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) acc[q] = mfma(av[kk], bv[q][kk], acc[q]);
+        // the chunk's 12 LDS reads first, then its 9 products
+        __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 9, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int ct = w + 4 * q;
+        if (ct < n1t) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s.Hp[4 * g + i][ct * 16 + lc] = acc[q][i] + sh.b1s[ct * 16 + lc];
+        }
       }
     }
     __syncthreads();
@@ -263,9 +290,19 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
         const bool cv = col < ncol;
         const float *wb = sh.W2s + sel3(a.wo, h);
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int ks = 0; ks < W / 4; ++ks) {
-          const float av = fmaxf(s.Hp[lc][h * W + ks * 4 + g], 0.0f);
-          acc = mfma(av, cv ? wb[(ks * 4 + g) * ncol + col] : 0.0f, acc);
+        // chunks of four k-steps, operands loaded first (W / 4 is a multiple of 4)
+        for (int k0 = 0; k0 < W / 4; k0 += 4) {
+          float av[4], bv[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int ks = k0 + kk;
+            av[kk] = fmaxf(s.Hp[lc][h * W + ks * 4 + g], 0.0f);
+            bv[kk] = wb[(ks * 4 + g) * ncol + (cv ? col : 0)];
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = mfma(av[kk], cv ? bv[kk] : 0.0f, acc);
+          __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) s.Yd[4 * g + i][c * 16 + lc] = cv ? acc[i] + sh.b2s[c * 16 + lc] : 0.0f;
@@ -355,10 +392,24 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
         const int h = ct / nhw, hc = (ct - h * nhw) * 16 + lc;
         const int ncol = sel3(a.outs, h);
         const float *wb = sh.W2s + sel3(a.wo, h) + hc * ncol;
+        const float *yr = s.Yd[lc] + sel3(a.offp, h);
+        const int nks = (ncol + 3) / 4;
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int ks = 0; ks < (ncol + 3) / 4; ++ks) {
-          const int kk = ks * 4 + g;
-          acc = mfma(s.Yd[lc][sel3(a.offp, h) + kk], kk < ncol ? wb[kk] : 0.0f, acc);
+        // chunks of four k-steps, operands loaded first (clamped reads; a
+        // k past ncol multiplies by 0)
+        for (int k0 = 0; k0 < nks; k0 += 4) {
+          float av[4], bv[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int kq = min((k0 + kk) * 4 + g, ncol - 1);
+            av[kk] = yr[kq];
+            bv[kk] = wb[kq];
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            if (k0 + kk < nks) acc = mfma(av[kk], (k0 + kk) * 4 + g < ncol ? bv[kk] : 0.0f, acc);
+          __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -367,19 +418,35 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
         }
       }
     }
+    // two output tiles at a time, their 16 operands loaded first (a tile
+    // past the last reads tile 0's and is skipped)
 #pragma unroll
-    for (int q = 0; q < kMaxT2; ++q) {
-      const int T = w + 4 * q;
-      if (T < nhw * n2t) {
-        const int rt = T / n2t, c = T - rt * n2t;
+    for (int q0 = 0; q0 < kMaxT2; q0 += 2) {
+      float av[2][kRB / 4], bv[2][kRB / 4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int T = w + 4 * (q0 + u);
+        const int Tc = T < nhw * n2t ? T : 0;
+        const int rt = Tc / n2t, c = Tc - rt * n2t;
         int col0;
         const int h = out_head(a, c, col0);
 #pragma unroll
         for (int ks = 0; ks < kRB / 4; ++ks) {
           const int row = ks * 4 + g;
-          acc2[q] = mfma(fmaxf(s.Hp[row][h * W + rt * 16 + lc], 0.0f), s.Yd[row][c * 16 + lc], acc2[q]);
+          av[u][ks] = fmaxf(s.Hp[row][h * W + rt * 16 + lc], 0.0f);
+          bv[u][ks] = s.Yd[row][c * 16 + lc];
         }
       }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = q0 + u;
+        if (q < kMaxT2 && w + 4 * q < nhw * n2t) {
+#pragma unroll
+          for (int ks = 0; ks < kRB / 4; ++ks) acc2[q] = mfma(av[u][ks], bv[u][ks], acc2[q]);
+        }
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
     }
     if (t < 16 * n2t)
       for (int r = 0; r < kRB; ++r) db2r += s.Yd[r][t];
@@ -389,24 +456,49 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
       const int n = w * 16 + lc;
       const bool nv = n < kIn;
       f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      for (int ks = 0; ks < 3 * W / 4; ++ks) {
-        const int kk = ks * 4 + g, h = kk / W, kh = kk - h * W;
-        acc = mfma(s.dH[lc][kk], nv ? sh.W1s[(h * kIn + n) * kW1P + kh] : 0.0f, acc);
+      // chunks of eight k-steps (3 W / 4 is a multiple of 12), operands first
+      const int nn = nv ? n : 0;
+      for (int k0 = 0; k0 < 3 * W / 4; k0 += 4) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kq = (k0 + kk) * 4 + g, h = kq / W, kh = kq - h * W;
+          av[kk] = s.dH[lc][kq];
+          bv[kk] = sh.W1s[(h * kIn + nn) * kW1P + kh];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = mfma(av[kk], nv ? bv[kk] : 0.0f, acc);
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) s.dX[4 * g + i][n] = acc[i];
     }
 #pragma unroll
-    for (int q = 0; q < kMaxT1; ++q) {
-      const int T = w + 4 * q;
-      if (T < 3 * n1t) {
-        const int rt = T / n1t, ct = T - rt * n1t;
+    for (int q0 = 0; q0 < kMaxT1; q0 += 2) {
+      float av[2][kRB / 4], bv[2][kRB / 4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int T = w + 4 * (q0 + u);
+        const int Tc = T < 3 * n1t ? T : 0;
+        const int rt = Tc / n1t, ct = Tc - rt * n1t;
 #pragma unroll
         for (int ks = 0; ks < kRB / 4; ++ks) {
           const int row = ks * 4 + g;
-          acc1[q] = mfma(s.X[row][rt * 16 + lc], s.dH[row][ct * 16 + lc], acc1[q]);
+          av[u][ks] = s.X[row][rt * 16 + lc];
+          bv[u][ks] = s.dH[row][ct * 16 + lc];
         }
       }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = q0 + u;
+        if (q < kMaxT1 && w + 4 * q < 3 * n1t) {
+#pragma unroll
+          for (int ks = 0; ks < kRB / 4; ++ks) acc1[q] = mfma(av[u][ks], bv[u][ks], acc1[q]);
+        }
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
     }
     if (t < 3 * W)
       for (int r = 0; r < kRB; ++r) db1r += s.dH[r][t];
