@@ -252,6 +252,9 @@ struct RasterWs {
   uint32_t *lookback_t;   // [tile passes][ceil(pcap / kTileSortPart)][256] tile-sort look-back
   float *dproj;           // [gcap][9] backward: d(mx, my, ca, cb, cc, opacity, r, g, b)
   float *gpair;           // [pcap][9] backward: the same per (tile, Gaussian) pair, emission order
+  float *chunk_part;      // [ceil(pcap / 64)][2][9] backward: sums of a 64-pair chunk's first and
+                          // last run where the run crosses the chunk's start or end
+  uint32_t *chunk_info;   // [ceil(pcap / 64)] backward: which of those the chunk has
   int64_t gcap, pcap;
   int32_t tiles_x, tiles_y, nblk_g, nruns, tile_passes;
   float xmax, ymax;            // last pixel centre of the image: W - 0.5, H - 0.5

@@ -925,6 +925,8 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
   ws.lookback_t = (uint32_t *)take(ws.lbt_words * 4);
   ws.dproj = (float *)take((size_t)g * 9 * 4);
   ws.gpair = (float *)take((size_t)pc * 9 * 4);
+  ws.chunk_part = (float *)take((size_t)((pc + 63) / 64) * 18 * 4);
+  ws.chunk_info = (uint32_t *)take((size_t)((pc + 63) / 64) * 4);
   ws.bytes = off;
   return ws;
 }

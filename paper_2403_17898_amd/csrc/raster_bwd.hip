@@ -246,8 +246,9 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
 __global__ __launch_bounds__(kBwdThreads) void k_composite_bwd(BwdArgs a) {
   __shared__ BwdLds lds;
   {
-    // the per-slot rows k_pair_reduce fills (partly by atomics) start at
-    // zero; this kernel does not touch them, so its blocks clear them
+    // the reduction writes the per-slot rows of Gaussians with pairs only;
+    // the others must read zero, and this kernel does not touch the rows,
+    // so its blocks clear them
     const uint64_t nz = (uint64_t)min<int64_t>(a.ws.hdr->n_slots, a.ws.gcap) * 9u;
     for (uint64_t i = (uint64_t)blockIdx.x * kBwdThreads + threadIdx.x; i < nz;
          i += (uint64_t)gridDim.x * kBwdThreads)
@@ -259,16 +260,39 @@ __global__ __launch_bounds__(kBwdThreads) void k_composite_bwd(BwdArgs a) {
     composite_bwd_tile<false>(a, lds);
 }
 
+// v[k] += (the DPP-moved v[k]) where take holds; lanes the move does not
+// reach (past a row's start, or outside row_mask) receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void seg_step(float (&v)[9], bool take) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const float u = __uint_as_float(
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v[k]), CTRL, ROWMASK, 0xF, true));
+    v[k] += take ? u : 0.0f;
+  }
+}
+
 // Per-Gaussian sums of the per-pair gradients.  A Gaussian's pairs are
-// contiguous in emission order.  Each wave takes 64 consecutive pairs and
-// runs a segmented inclusive scan keyed by slot (six shuffle steps); the last
-// lane of each run then holds the run's sum.  A run that lies inside the
-// wave's 64 pairs is stored; a run cut by the wave's first or last pair is
-// added atomically (the slot rows were zeroed first), at most two per wave.
+// contiguous in emission order.  Each wave takes a chunk of 64 consecutive
+// pairs and runs a segmented inclusive scan keyed by slot (six DPP steps);
+// the last lane of each run then holds the run's sum.  A run that lies inside
+// the chunk is stored.  A run that crosses the chunk's start or end leaves
+// its sum in the chunk's two partial slots (the first and the last run; one
+// run covering the whole chunk is its first), and k_pair_fix adds a crossing
+// run's partials in chunk order: no atomics, the same sums on every run.
+constexpr uint32_t kChunkFirst = 1u;   // the chunk's first run continues from the previous chunk
+constexpr uint32_t kChunkLast = 2u;    // its last run continues into the next chunk
+constexpr uint32_t kChunkWhole = 4u;   // one run covers the chunk and continues both ways
 __global__ __launch_bounds__(kBlock) void k_pair_reduce(RasterWs ws) {
+  // a full chunk's 64 records (2,304 bytes, 16-byte aligned) are read with
+  // lane-contiguous float4 loads into LDS, then each lane takes its own 9
+  // floats (odd stride: no bank conflicts)
+  constexpr int kRec4 = kWave * 9 / 4;  // 144
+  __shared__ float4 stage[kBlock / kWave][kRec4];
   const uint32_t P = ws.hdr->n_listed;
   const int l = __lane_id();
   const uint32_t nw = gridDim.x * (kBlock / kWave);
+  float4 *sw = stage[threadIdx.x / kWave];
   for (uint32_t c0 = (blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (uint32_t)kWave; c0 < P;
        c0 += nw * kWave) {
     const uint32_t p = c0 + l;
@@ -276,38 +300,109 @@ __global__ __launch_bounds__(kBlock) void k_pair_reduce(RasterWs ws) {
     const uint32_t pc = valid ? p : P - 1;
     const uint32_t s = valid ? ws.pair_slot[pc] : 0xffffffffu;
     float v[9];
-    const float *gp = ws.gpair + 9 * (size_t)pc;
+    if (c0 + kWave <= P) {
+      const float4 *src = reinterpret_cast<const float4 *>(ws.gpair + 9 * (size_t)c0);
+      float4 r[3];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) v[k] = valid ? gp[k] : 0.0f;
+      for (int u = 0; u < 3; ++u) r[u] = src[min(l + kWave * u, kRec4 - 1)];
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+        if (l + kWave * u < kRec4) sw[l + kWave * u] = r[u];
+      // the wave's LDS writes are complete before any lane reads them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const float *sf = reinterpret_cast<const float *>(sw) + 9 * l;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = sf[k];
+      // every lane has read before the next chunk overwrites the stage
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      const float *gp = ws.gpair + 9 * (size_t)pc;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = valid ? gp[k] : 0.0f;
+    }
+    // does the chunk's first (last) run continue from (into) its neighbour?
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(s);
+    const uint32_t s63 = (uint32_t)__builtin_amdgcn_readlane((int)s, kWave - 1);
+    const bool first_cont = c0 > 0 && ws.pair_slot[c0 - 1] == s0;
+    const bool last_cont = c0 + kWave < P && ws.pair_slot[c0 + kWave] == s63;
     const uint32_t sp = __shfl_up(s, 1, kWave);
     const bool head = l == 0 || sp != s;
     const uint64_t heads = ballot(head);
     // lane of this run's head within the wave
     const int hl = 63 - __builtin_clzll(heads & (lanemask_lt() | (1ull << l)));
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const float u = __shfl_up(v[k], d, kWave);
-        if (l - d >= hl) v[k] += u;
-      }
-    }
+    // segmented inclusive scan by DPP (no LDS round trips): shifts by 1, 2,
+    // 4 and 8 within each 16-lane row, then the last lane of row 0 into row 1
+    // and of row 2 into row 3, then lane 31 into rows 2 and 3; a lane adds a
+    // partial only if the partial's lane lies in its own run
+    seg_step<0x111, 0xF>(v, l - 1 >= hl);
+    seg_step<0x112, 0xF>(v, l - 2 >= hl);
+    seg_step<0x114, 0xF>(v, l - 4 >= hl);
+    seg_step<0x118, 0xF>(v, l - 8 >= hl);
+    seg_step<0x142, 0xA>(v, (l & ~15) - 1 >= hl);
+    seg_step<0x143, 0xC>(v, 31 >= hl);
     const uint32_t sn = __shfl_down(s, 1, kWave);
     const bool tail = valid && (l == kWave - 1 || sn != s);
+    const uint32_t chunk = c0 / kWave;
+    const bool from_prev = hl == 0 && first_cont;
+    const bool into_next = l == kWave - 1 && last_cont;
     if (tail) {
-      // does the run continue across the wave's boundaries?
-      const bool from_prev = hl == 0 && c0 > 0 && ws.pair_slot[c0 - 1] == s;
-      const bool into_next = l == kWave - 1 && p + 1 < P && ws.pair_slot[p + 1] == s;
       float *d = ws.dproj + 9 * (size_t)s;
-      if (!from_prev && !into_next) {
+      if (from_prev) d = ws.chunk_part + 18 * (size_t)chunk;          // first run (or whole chunk)
+      else if (into_next) d = ws.chunk_part + 18 * (size_t)chunk + 9;  // last run
 #pragma unroll
-        for (int k = 0; k < 9; ++k) d[k] = v[k];
-      } else {
+      for (int k = 0; k < 9; ++k) d[k] = v[k];
+    }
+    if (l == kWave - 1)
+      ws.chunk_info[chunk] = (first_cont ? kChunkFirst : 0u) | (last_cont ? kChunkLast : 0u) |
+                             (first_cont && last_cont && hl == 0 ? kChunkWhole : 0u);
+  }
+}
+
+// One thread per chunk whose last run starts in it and continues into the
+// next chunk: that run's sum is its partial here, plus the partials of the
+// following chunks in order (the whole-chunk ones, then the one where the
+// run ends), stored once into the run's slot row.
+__global__ __launch_bounds__(kBlock) void k_pair_fix(RasterWs ws) {
+  const uint32_t P = ws.hdr->n_listed;
+  const uint32_t nch = (P + kWave - 1) / kWave;
+  for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nch; c += gridDim.x * kBlock) {
+    const uint32_t info = ws.chunk_info[c];
+    if (!(info & kChunkLast) || (info & kChunkWhole)) continue;
+    float t[9];
+    const float *src = ws.chunk_part + 18 * (size_t)c + 9;
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-          if (v[k] != 0.0f) atomicAdd(d + k, v[k]);
+    for (int k = 0; k < 9; ++k) t[k] = src[k];
+    // a run that continues into the next chunk ends in some later chunk
+    // (the last chunk's last run cannot continue), so the walk stops.  The
+    // following chunks are read eight at a time (one round trip for most
+    // runs, a few for a Gaussian listed in thousands of tiles) and added in
+    // chunk order.
+    constexpr int kAhead = 8;
+    bool done = false;
+    for (uint32_t j0 = c + 1; j0 < nch && !done; j0 += kAhead) {
+      uint32_t inf[kAhead];
+      float pv[kAhead][9];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const uint32_t j = min(j0 + (uint32_t)u, nch - 1);
+        inf[u] = ws.chunk_info[j];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pv[u][k] = ws.chunk_part[18 * (size_t)j + k];
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        if (!done && j0 + (uint32_t)u < nch) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) t[k] += pv[u][k];
+          done = !(inf[u] & kChunkWhole);
+        }
       }
     }
+    float *d = ws.dproj + 9 * (size_t)ws.pair_slot[c * (size_t)kWave + kWave - 1];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = t[k];
   }
 }
 
@@ -507,6 +602,8 @@ extern "C" int octgs_rasterize_bwd(const octgs_gaussians *g, const octgs_camera 
   mark(2);
   const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + kBlock - 1) / kBlock, 1), 2048);
   hipLaunchKernelGGL(k_pair_reduce, dim3(rgrid), dim3(kBlock), 0, s, ws);
+  const int fgrid = (int)std::min<int64_t>(std::max<int64_t>((ws.pcap + 64 * kBlock - 1) / (64 * kBlock), 1), 1024);
+  hipLaunchKernelGGL(k_pair_fix, dim3(fgrid), dim3(kBlock), 0, s, ws);
   PBwdArgs pa;
   for (int i = 0; i < 9; ++i) pa.cam.R[i] = cam->R[i];
   for (int i = 0; i < 3; ++i) pa.cam.C[i] = cam->C[i];
