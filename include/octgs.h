@@ -347,6 +347,27 @@ OCTGS_API int octgs_decode_bwd(const octgs_anchors *a, const octgs_mlp *mlp,
                                const octgs_mlp_grads *gm, void *ws, size_t ws_bytes,
                                octgs_stream stream);
 
+/* octgs_decode_bwd in two halves (Sec. III-B, Eq. 3 and Eq. 4), for several
+ * views whose gradients go into one set of arrays.  octgs_decode_bwd_rows
+ * computes every listed anchor's gradient row and the MLP weight-gradient
+ * partial sums into ws and touches no gradient array, so the rows of
+ * different views (separate workspaces) may run at the same time.
+ * octgs_decode_bwd_apply adds a workspace's rows into ga (each listed anchor
+ * once) and its partial sums into gm; applies that share ga and gm must be
+ * ordered by the caller.  octgs_decode_bwd is the two in sequence, and the
+ * arguments mean the same as there; apply takes the idx, count, capacity
+ * and workspace of its rows call, unchanged since. */
+OCTGS_API int octgs_decode_bwd_rows(const octgs_anchors *a, const octgs_mlp *mlp,
+                                    const octgs_camera *cam, const uint32_t *idx,
+                                    const uint32_t *count, const float *d_gauss,
+                                    int64_t gauss_capacity, void *ws, size_t ws_bytes,
+                                    octgs_stream stream);
+OCTGS_API int octgs_decode_bwd_apply(const octgs_anchors *a, const octgs_mlp *mlp,
+                                     const uint32_t *idx, const uint32_t *count,
+                                     int64_t gauss_capacity, const octgs_anchor_grads *ga,
+                                     const octgs_mlp_grads *gm, const void *ws, size_t ws_bytes,
+                                     octgs_stream stream);
+
 /* Mean-L1 image loss of the training step: dimg = scale * sign(img - target)
  * and *loss += scale * sum |img - target| (device scalar, accumulated), over n
  * elements.  scale is 1 / (elements averaged over). */

@@ -117,6 +117,12 @@ SIGNATURES = [
                                 ctypes.POINTER(Camera), _p, _p, _p, _i64,
                                 ctypes.POINTER(AnchorGrads), ctypes.POINTER(MlpGrads), _p,
                                 ctypes.c_size_t, _p]),
+    ("octgs_decode_bwd_rows", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),
+                                     ctypes.POINTER(Camera), _p, _p, _p, _i64, _p,
+                                     ctypes.c_size_t, _p]),
+    ("octgs_decode_bwd_apply", _i32, [ctypes.POINTER(Anchors), ctypes.POINTER(Mlp), _p, _p, _i64,
+                                      ctypes.POINTER(AnchorGrads), ctypes.POINTER(MlpGrads), _p,
+                                      ctypes.c_size_t, _p]),
     ("octgs_l1_loss_grad", _i32, [_p, _p, _i64, _f, _p, _p, _p]),
     ("octgs_photometric_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32]),
     ("octgs_photometric_loss_grad", _i32, [_p, _p, _i64, _i32, _i32, _f, _f, _p, _p, _p,

@@ -18,10 +18,13 @@
 //   dW2 += relu(Hp)^T dY, dW1 += X^T dHp, db += column sums
 // The weight-gradient sums stay in MFMA accumulators across all of the
 // block's tiles; the second group hands its sums to the first through LDS
-// (added in group order), each block writes them once to its row of a workspace, and
-// a second kernel adds the rows in block order into the caller's arrays (no
-// atomics; the result is the same on every run).  The anchor count lives on
-// the device.
+// (added in group order), and each block writes them once to its row of a
+// workspace.  Each listed anchor's gradients go to its own row of the
+// workspace too.  A second pair of kernels (the apply half, which the caller
+// may order after other views' rows) adds the anchor rows into the anchor
+// arrays and the block rows, in block order, into the weight gradients: no
+// atomics, the same result on every run.  The anchor count lives on the
+// device.
 //
 // MFMA 16x16x4 operand layouts (lane l, group g = l / 16, c = l % 16):
 //   A[m][k]: row m = c, k = g;  B[k][n]: column n = c, k = g;
@@ -53,6 +56,12 @@ constexpr int kMaxT1 = 9;              // dW1 output tiles per wave (3 x 12 / 4)
 constexpr int kMaxT2 = 11;             // dW2 output tiles per wave (4 x 11 / 4)
 constexpr int kDecBwdGrid = 256;       // persistent blocks (one per CU: ~159 KB of LDS each)
 constexpr int kDecGroups = 2;          // wave groups per block, one tile each
+// A listed anchor's gradient row: position, feature, k offsets, offset
+// scale, base scale (41 + 3k floats).
+constexpr int kRowPos = 0, kRowFeat = 3, kRowOff = 35;
+__host__ __device__ inline int row_osc(int k) { return kRowOff + 3 * k; }
+__host__ __device__ inline int row_bsc(int k) { return kRowOff + 3 * k + 3; }
+__host__ __device__ inline int row_len(int k) { return kRowOff + 3 * k + 6; }
 constexpr int kDecBwdThreads = kDecGroups * kBlock;
 
 struct DecBwdArgs {
@@ -70,7 +79,8 @@ struct DecBwdArgs {
   const uint32_t *idx, *count;
   const float *dgauss;
   int64_t dstride;
-  float *gpos, *gfeat, *goff, *gosc, *gbsc;
+  float *rows;     // [cap_anchors][rstride]: each listed anchor's gradient row (kRow* layout)
+  int rstride;
   float *part;     // [gridDim.x][P]
 };
 
@@ -82,6 +92,7 @@ struct DecBwdTile {
   float dH[kRB][kHS];
   float dX[kRB][kInP];
   float Dn[kRB][4];              // distance and unit direction per anchor
+  float dp[kRB][3];              // position gradient through the decoded means
   uint32_t aidx[kRB];
 };
 
@@ -330,10 +341,10 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
           dp[c] = dgv[c];
           dl[c] = dgv[c] * o[c];
         }
+        float *row = a.rows + (size_t)(r0 + r) * a.rstride;
         if (act) {
-          float *go = a.goff + ((size_t)j * k + ii) * 3;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) go[c] += dgv[c] * lv[c];
+          for (int c = 0; c < 3; ++c) row[kRowOff + 3 * ii + c] = dgv[c] * lv[c];
         }
         const int ys = a.offp[2] + 7 * ii, yc = a.offp[1] + 3 * ii, ya = a.offp[0] + ii;
 #pragma unroll
@@ -374,9 +385,9 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
         if (i == 0) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            a.gpos[3 * (size_t)j + c] += dp[c];
-            a.gosc[3 * (size_t)j + c] += dl[c];
-            a.gbsc[3 * (size_t)j + c] += dbs[c];
+            s.dp[r][c] = dp[c];
+            row[row_osc(k) + c] = dl[c];
+            row[row_bsc(k) + c] = dbs[c];
           }
         }
       } else {
@@ -505,17 +516,19 @@ __global__ __launch_bounds__(kDecBwdThreads) void k_dec_bwd(DecBwdArgs a) {
     __syncthreads();
     // ---- features and position: 32 lanes per anchor ----
     for (int r = t / 32; r < rows; r += kBlock / 32) {
-      const uint32_t j = s.aidx[r];
       const int f = t % 32;
-      a.gfeat[(size_t)j * 32 + f] += s.dX[r][f];
+      float *row = a.rows + (size_t)(r0 + r) * a.rstride;
+      row[kRowFeat + f] = s.dX[r][f];
       if (f == 0) {
+        // the position enters through the decoded means and through the
+        // distance and direction inputs
         const float dist = s.Dn[r][0], u0 = s.Dn[r][1], u1 = s.Dn[r][2], u2 = s.Dn[r][3];
         const float *dx = s.dX[r];
         const float dot = fma_(u0, dx[33], fma_(u1, dx[34], u2 * dx[35]));
         const float sd = dx[32] * a.inv_dmax, id = 1.0f / dist;
-        a.gpos[3 * (size_t)j + 0] += fma_(u0, sd, (dx[33] - u0 * dot) * id);
-        a.gpos[3 * (size_t)j + 1] += fma_(u1, sd, (dx[34] - u1 * dot) * id);
-        a.gpos[3 * (size_t)j + 2] += fma_(u2, sd, (dx[35] - u2 * dot) * id);
+        row[kRowPos + 0] = s.dp[r][0] + fma_(u0, sd, (dx[33] - u0 * dot) * id);
+        row[kRowPos + 1] = s.dp[r][1] + fma_(u1, sd, (dx[34] - u1 * dot) * id);
+        row[kRowPos + 2] = s.dp[r][2] + fma_(u2, sd, (dx[35] - u2 * dot) * id);
       }
     }
     __syncthreads();
@@ -642,12 +655,47 @@ __global__ __launch_bounds__(kBlock) void k_dec_bwd_reduce(DecRedArgs a) {
   *dst += sum;
 }
 
+// Adds each listed anchor's gradient row into the anchor arrays; one
+// thread per row element.  The anchors of one list are distinct, so no two
+// threads touch the same element.
+struct DecApplyArgs {
+  int k, rstride, cap_anchors;
+  const uint32_t *idx, *count;
+  const float *rows;
+  float *gpos, *gfeat, *goff, *gosc, *gbsc;
+};
+
+__global__ __launch_bounds__(kBlock) void k_dec_bwd_apply(DecApplyArgs a) {
+  const uint32_t M = min(*a.count, (uint32_t)a.cap_anchors);
+  const uint64_t n = (uint64_t)M * a.rstride;
+  const int k = a.k;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t r = (uint32_t)(e / a.rstride);
+    const int q = (int)(e - (uint64_t)r * a.rstride);
+    const size_t j = a.idx[r];
+    float *d;
+    if (q < kRowFeat) d = a.gpos + 3 * j + q;
+    else if (q < kRowOff) d = a.gfeat + 32 * j + (q - kRowFeat);
+    else if (q < row_osc(k)) d = a.goff + 3 * (size_t)k * j + (q - kRowOff);
+    else if (q < row_bsc(k)) d = a.gosc + 3 * j + (q - row_osc(k));
+    else d = a.gbsc + 3 * j + (q - row_bsc(k));
+    *d += a.rows[e];
+  }
+}
+
 int partial_len(int k, int W) { return 3 * kIn * W + 11 * k * W + 3 * W + 11 * k; }
+
 
 // persistent blocks, each taking pairs of 16-anchor tiles
 int grid_for(int64_t mcap) {
   const int64_t per = (int64_t)kDecGroups * kRB;
   return (int)std::max<int64_t>(1, std::min<int64_t>((mcap + per - 1) / per, kDecBwdGrid));
+}
+
+// the anchor rows follow the block partial rows, 256-byte aligned
+size_t rows_offset(int64_t mcap, int k, int W) {
+  return ((size_t)grid_for(mcap) * (size_t)partial_len(k, W) * sizeof(float) + 255) & ~(size_t)255;
 }
 
 }  // namespace
@@ -659,37 +707,45 @@ using namespace octgs;
 extern "C" {
 
 size_t octgs_decode_bwd_workspace_bytes(int64_t max_anchors, int32_t k, int32_t width) {
-  if (max_anchors < 0 || k < 1 || k > kMaxK || width < 16 || width > kMaxW || width % 16)
+  if (max_anchors < 0 || max_anchors > 0x7fffffff || k < 1 || k > kMaxK || width < 16 ||
+      width > kMaxW || width % 16)
     return 0;
-  return (size_t)grid_for(max_anchors) * (size_t)partial_len(k, width) * sizeof(float) + 256;
+  return rows_offset(max_anchors, k, width) + (size_t)max_anchors * row_len(k) * sizeof(float) + 256;
 }
 
-int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_camera *cam,
-                     const uint32_t *idx, const uint32_t *count, const float *d_gauss,
-                     int64_t gauss_capacity, const octgs_anchor_grads *ga,
-                     const octgs_mlp_grads *gm, void *ws, size_t ws_bytes, octgs_stream stream) {
-  if (!an || !mlp || !cam || !idx || !count || !d_gauss || !ga || !gm || !ws) return OCTGS_EINVAL;
-  // transition blending is an inference-time mode; training uses Eq. 7 alone
-  if (cam->lod_blend) return OCTGS_EUNSUPPORTED;
+namespace {
+
+// Shared argument checks of the two halves; 0 or an octgs_status.
+int check_shapes(const octgs_anchors *an, const octgs_mlp *mlp, int64_t gauss_capacity,
+                 size_t ws_bytes) {
   if (an->feat_dim != 32) return OCTGS_EUNSUPPORTED;
   if (an->k < 1 || an->k > kMaxK) return OCTGS_EUNSUPPORTED;
   if (mlp->width < 16 || mlp->width > kMaxW || mlp->width % 16) return OCTGS_EUNSUPPORTED;
+  if (gauss_capacity < an->k) return OCTGS_EINVAL;
+  const int64_t mcap = gauss_capacity / an->k;
+  if (mcap > 0x7fffffff) return OCTGS_EINVAL;
+  if (ws_bytes < octgs_decode_bwd_workspace_bytes(mcap, an->k, mlp->width)) return OCTGS_ENOSPC;
+  return OCTGS_OK;
+}
+
+}  // namespace
+
+int octgs_decode_bwd_rows(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_camera *cam,
+                          const uint32_t *idx, const uint32_t *count, const float *d_gauss,
+                          int64_t gauss_capacity, void *ws, size_t ws_bytes, octgs_stream stream) {
+  if (!an || !mlp || !cam || !idx || !count || !d_gauss || !ws) return OCTGS_EINVAL;
+  // transition blending is an inference-time mode; training uses Eq. 7 alone
+  if (cam->lod_blend) return OCTGS_EUNSUPPORTED;
+  if (const int e = check_shapes(an, mlp, gauss_capacity, ws_bytes)) return e;
   if (!an->pos || !an->feat || !an->offsets || !an->offset_scale || !an->base_scale)
     return OCTGS_EINVAL;
-  if (!ga->pos || !ga->feat || !ga->offsets || !ga->offset_scale || !ga->base_scale)
-    return OCTGS_EINVAL;
   for (int h = 0; h < 3; ++h) {
-    if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h] || !gm->w1[h] || !gm->b1[h] ||
-        !gm->w2[h] || !gm->b2[h])
-      return OCTGS_EINVAL;
+    if (!mlp->w1[h] || !mlp->b1[h] || !mlp->w2[h] || !mlp->b2[h]) return OCTGS_EINVAL;
     if (((uintptr_t)mlp->w1[h] | (uintptr_t)mlp->w2[h]) & 15) return OCTGS_EINVAL;
   }
-  if (gauss_capacity < an->k || !(an->d_max > 0.0f)) return OCTGS_EINVAL;
+  if (!(an->d_max > 0.0f)) return OCTGS_EINVAL;
   const int k = an->k, W = mlp->width;
   const int64_t mcap = gauss_capacity / k;
-  if (mcap > 0x7fffffff) return OCTGS_EINVAL;
-  if (ws_bytes < octgs_decode_bwd_workspace_bytes(mcap, k, W)) return OCTGS_ENOSPC;
-  hipStream_t s = (hipStream_t)stream;
   DecBwdArgs a;
   a.k = k; a.W = W; a.cap_anchors = (int)mcap;
   a.outs[0] = k; a.outs[1] = 3 * k; a.outs[2] = 7 * k;
@@ -707,20 +763,58 @@ int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_
   }
   a.idx = idx; a.count = count;
   a.dgauss = d_gauss; a.dstride = gauss_capacity;
-  a.gpos = ga->pos; a.gfeat = ga->feat; a.goff = ga->offsets;
-  a.gosc = ga->offset_scale; a.gbsc = ga->base_scale;
   a.part = (float *)ws;
-  const int grid = grid_for(mcap);
-  hipLaunchKernelGGL(k_dec_bwd, dim3(grid), dim3(kDecBwdThreads), 0, s, a);
+  a.rows = (float *)((char *)ws + rows_offset(mcap, k, W));
+  a.rstride = row_len(k);
+  hipLaunchKernelGGL(k_dec_bwd, dim3(grid_for(mcap)), dim3(kDecBwdThreads), 0, (hipStream_t)stream, a);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+int octgs_decode_bwd_apply(const octgs_anchors *an, const octgs_mlp *mlp, const uint32_t *idx,
+                           const uint32_t *count, int64_t gauss_capacity,
+                           const octgs_anchor_grads *ga, const octgs_mlp_grads *gm, const void *ws,
+                           size_t ws_bytes, octgs_stream stream) {
+  if (!an || !mlp || !idx || !count || !ga || !gm || !ws) return OCTGS_EINVAL;
+  if (const int e = check_shapes(an, mlp, gauss_capacity, ws_bytes)) return e;
+  if (!ga->pos || !ga->feat || !ga->offsets || !ga->offset_scale || !ga->base_scale)
+    return OCTGS_EINVAL;
+  for (int h = 0; h < 3; ++h)
+    if (!gm->w1[h] || !gm->b1[h] || !gm->w2[h] || !gm->b2[h]) return OCTGS_EINVAL;
+  const int k = an->k, W = mlp->width;
+  const int64_t mcap = gauss_capacity / k;
+  hipStream_t s = (hipStream_t)stream;
+  DecApplyArgs ap;
+  ap.k = k; ap.rstride = row_len(k); ap.cap_anchors = (int)mcap;
+  ap.idx = idx; ap.count = count;
+  ap.rows = (const float *)((const char *)ws + rows_offset(mcap, k, W));
+  ap.gpos = ga->pos; ap.gfeat = ga->feat; ap.goff = ga->offsets;
+  ap.gosc = ga->offset_scale; ap.gbsc = ga->base_scale;
+  const int agrid = (int)std::min<int64_t>(std::max<int64_t>((mcap * row_len(k) + kBlock - 1) / kBlock, 1), 4096);
+  hipLaunchKernelGGL(k_dec_bwd_apply, dim3(agrid), dim3(kBlock), 0, s, ap);
   DecRedArgs r;
-  r.P = a.P; r.nblk = grid; r.k = k; r.W = W;
-  r.p_w2 = a.p_w2; r.p_b1 = a.p_b1; r.p_b2 = a.p_b2;
-  r.part = a.part;
+  r.P = partial_len(k, W); r.nblk = grid_for(mcap); r.k = k; r.W = W;
+  r.p_w2 = 3 * kIn * W; r.p_b1 = r.p_w2 + 11 * k * W; r.p_b2 = r.p_b1 + 3 * W;
+  r.part = (const float *)ws;
   for (int h = 0; h < 3; ++h) {
     r.w1[h] = gm->w1[h]; r.b1[h] = gm->b1[h]; r.w2[h] = gm->w2[h]; r.b2[h] = gm->b2[h];
   }
-  hipLaunchKernelGGL(k_dec_bwd_reduce, dim3((a.P + kRedOut - 1) / kRedOut), dim3(kBlock), 0, s, r);
+  hipLaunchKernelGGL(k_dec_bwd_reduce, dim3((r.P + kRedOut - 1) / kRedOut), dim3(kBlock), 0, s, r);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
+}
+
+int octgs_decode_bwd(const octgs_anchors *an, const octgs_mlp *mlp, const octgs_camera *cam,
+                     const uint32_t *idx, const uint32_t *count, const float *d_gauss,
+                     int64_t gauss_capacity, const octgs_anchor_grads *ga,
+                     const octgs_mlp_grads *gm, void *ws, size_t ws_bytes, octgs_stream stream) {
+  if (!ga || !gm) return OCTGS_EINVAL;
+  if (!ga->pos || !ga->feat || !ga->offsets || !ga->offset_scale || !ga->base_scale)
+    return OCTGS_EINVAL;
+  for (int h = 0; h < 3; ++h)
+    if (!gm->w1[h] || !gm->b1[h] || !gm->w2[h] || !gm->b2[h]) return OCTGS_EINVAL;
+  const int e = octgs_decode_bwd_rows(an, mlp, cam, idx, count, d_gauss, gauss_capacity, ws,
+                                      ws_bytes, stream);
+  if (e != OCTGS_OK) return e;
+  return octgs_decode_bwd_apply(an, mlp, idx, count, gauss_capacity, ga, gm, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -542,21 +542,47 @@ class ViewBuffers:
                                             stream_handle(stream)),
                 "octgs_rasterize_bwd")
 
+    def _dec_ws(self, scene: "DeviceScene", cap: int):
+        need = L.lib().octgs_decode_bwd_workspace_bytes(cap // self.k, self.k, scene.width)
+        if getattr(self, "dec_ws", None) is None or self.dec_ws.numel() < need:
+            self.dec_ws = torch.empty(need, dtype=torch.uint8, device=self.gauss.device)
+        return self.dec_ws
+
     def decode_bwd(self, scene: "DeviceScene", cam: L.Camera, grads: SceneGrads,
                    dgauss: Optional[torch.Tensor] = None, idx: Optional[torch.Tensor] = None,
                    count: Optional[torch.Tensor] = None, stream=None):
-        lib = L.lib()
-        need = lib.octgs_decode_bwd_workspace_bytes(self.gcap // self.k, self.k, scene.width)
-        if getattr(self, "dec_ws", None) is None or self.dec_ws.numel() < need:
-            self.dec_ws = torch.empty(need, dtype=torch.uint8, device=self.gauss.device)
+        """Decode backward of the listed anchors (default: the last
+        selection), added into grads."""
         dg = self.dgauss if dgauss is None else dgauss
         idx = self.sel_idx if idx is None else idx
         count = self.sel_count if count is None else count
-        L.check(lib.octgs_decode_bwd(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
-                                     ctypes.byref(cam), _ptr(idx), _ptr(count), _ptr(dg),
-                                     dg.shape[1], ctypes.byref(grads._ag), ctypes.byref(grads._mg),
-                                     _ptr(self.dec_ws), self.dec_ws.numel(),
-                                     stream_handle(stream)), "octgs_decode_bwd")
+        ws = self._dec_ws(scene, dg.shape[1])
+        L.check(L.lib().octgs_decode_bwd(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                         ctypes.byref(cam), _ptr(idx), _ptr(count), _ptr(dg),
+                                         dg.shape[1], ctypes.byref(grads._ag),
+                                         ctypes.byref(grads._mg), _ptr(ws), ws.numel(),
+                                         stream_handle(stream)), "octgs_decode_bwd")
+
+    def decode_bwd_rows(self, scene: "DeviceScene", cam: L.Camera, stream=None):
+        """The first half of decode_bwd for the last selection: gradient rows
+        and weight partial sums into this buffer set's workspace, no gradient
+        array touched (views in flight run theirs at the same time)."""
+        ws = self._dec_ws(scene, self.dgauss.shape[1])
+        L.check(L.lib().octgs_decode_bwd_rows(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                              ctypes.byref(cam), _ptr(self.sel_idx),
+                                              _ptr(self.sel_count), _ptr(self.dgauss),
+                                              self.dgauss.shape[1], _ptr(ws), ws.numel(),
+                                              stream_handle(stream)), "octgs_decode_bwd_rows")
+
+    def decode_bwd_apply(self, scene: "DeviceScene", grads: SceneGrads, stream=None):
+        """The second half: add the rows of the last decode_bwd_rows into
+        grads (order the applies of views that share grads)."""
+        ws = self._dec_ws(scene, self.dgauss.shape[1])
+        L.check(L.lib().octgs_decode_bwd_apply(ctypes.byref(scene.anchors), ctypes.byref(scene._mlp),
+                                               _ptr(self.sel_idx), _ptr(self.sel_count),
+                                               self.dgauss.shape[1], ctypes.byref(grads._ag),
+                                               ctypes.byref(grads._mg), _ptr(ws), ws.numel(),
+                                               stream_handle(stream)), "octgs_decode_bwd_apply")
 
     # ---- readback helpers (synchronise) ----
     def stats(self) -> Dict[str, int]:

@@ -1,10 +1,11 @@
 """Gradient of a photometric loss summed over several training views, with
 the views in flight on separate streams (the multi-view loss of Sec. V).
 
-Each view renders, computes its loss and runs the rasterizer backward on
-its own stream and buffer set, so the views' latency-bound kernels (scans,
-sorts, emission) overlap.  The steps that read-modify-write arrays shared
-by all views, the decode backward into the scene gradients and the
+Each view renders, computes its loss and runs the rasterizer backward and
+the decode backward's compute half on its own stream and buffer set, so the
+views' latency-bound kernels (scans, sorts, emission, the MLP backward)
+overlap.  The steps that read-modify-write arrays shared by all views, the
+decode backward's apply half into the scene gradients and the
 densification statistics, run in view order, chained by events, so the
 gradients are those of the views taken one after another."""
 
@@ -35,6 +36,7 @@ class MultiViewBackward:
         self.dimgs = [torch.empty(3, height, width, device=dev) for _ in range(self.nbuf)]
         self.losses = torch.zeros(self.n_views, device=dev)  # one slot per view
         self._ssim_ws: List[Optional[torch.Tensor]] = [None] * self.nbuf
+
     def check(self):
         """Raise if any view rendered since the last check overflowed its pair
         list, hit a look-back wait bound or selected more anchors than the
@@ -86,12 +88,14 @@ class MultiViewBackward:
             vb.rasterize_bwd(c, params, dimg, stream=st)
             if full:
                 vb.volume_loss_grad(w_vol, li, stream=st)
-            # shared arrays: one view after another
+            # the decode backward's own work, then what touches the shared
+            # arrays: one view after another
+            vb.decode_bwd_rows(scene, c, stream=st)
             if chain is not None:
                 st.wait_event(chain)
             if dstats is not None:
                 dstats.accumulate(vb, c, stream=st)
-            vb.decode_bwd(scene, c, grads, stream=st)
+            vb.decode_bwd_apply(scene, grads, stream=st)
             chain = torch.cuda.Event()
             chain.record(st)
         # the last link follows every view's work

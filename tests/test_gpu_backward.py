@@ -102,6 +102,41 @@ def test_decode_backward_parity(P, orc, count):
         assert nbad == 0, name
 
 
+def test_decode_bwd_halves_match_whole(P):
+    """Two views' decode backwards into one set of gradients: the rows of
+    both computed first (separate workspaces) and then applied in view order
+    give the same gradients bit for bit as the whole call per view."""
+    sc, cam = S.make_gradcheck_scene()
+    ds = P.DeviceScene.from_scene(sc)
+    c = P.make_camera(cam)
+    rng = np.random.default_rng(12)
+    views = []
+    for m in (37, 45):
+        idx = rng.permutation(sc.n)[:m].astype(np.int32)
+        dg = rng.standard_normal((14, m * sc.k)).astype(np.float32)
+        views.append((torch.as_tensor(idx).cuda(), torch.tensor([m], dtype=torch.int32).cuda(),
+                      torch.as_tensor(dg).cuda()))
+    whole = P.SceneGrads(ds)
+    vbw = P.ViewBuffers(sc.n, sc.k, 64, 64, 1 << 12, gauss_capacity=45 * sc.k)
+    for idx, cnt, dg in views:
+        vbw.decode_bwd(ds, c, whole, dgauss=dg, idx=idx, count=cnt)
+    halves = P.SceneGrads(ds)
+    vbs = []
+    for idx, cnt, dg in views:
+        vb = P.ViewBuffers(sc.n, sc.k, 64, 64, 1 << 12, gauss_capacity=dg.shape[1])
+        vb.sel_idx, vb.sel_count, vb.dgauss = idx, cnt, dg
+        vb.decode_bwd_rows(ds, c)
+        vbs.append(vb)
+    for vb in vbs:
+        vb.decode_bwd_apply(ds, halves)
+    torch.cuda.synchronize()
+    a, b = whole.all(), halves.all()
+    for name in a:
+        x, y = _np(a[name]), _np(b[name])
+        assert np.count_nonzero(x) > 0, name
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), name
+
+
 def test_full_chain_gradient(P, orc):
     """50 anchors, 64x64: GPU FP32 gradient of sum(w * image) against the
     oracle's FP64 analytic gradient and against central differences of the
