@@ -383,6 +383,60 @@ def test_ellipse_binning_keeps_rect_subset(orc):
     assert np.all((tx >= r[gi, 0]) & (tx < r[gi, 2]) & (ty >= r[gi, 1]) & (ty < r[gi, 3]))
 
 
+def test_ellipse_cutoff_bounded_on_the_image(orc):
+    """The ellipse/tile cut (R16) changes the image by no more than the alpha
+    of the entries it drops.  With no early stop and colours and background
+    in [0, 1], leaving entries out of a pixel's front-to-back list changes
+    each channel by at most the sum of their a_i.  So the render that keeps
+    every tile of each Gaussian's rectangle (3D-GS's binning, same depth
+    order) and the ellipse-cut render differ per pixel by at most that sum,
+    computed here from the dropped entries, each of which lies outside the
+    3-sigma ellipse at every pixel of its tile (q > 9, so a < 0.0112 op)."""
+    cam = ident_cam(96, 80)
+    g = S.random_gaussians(400, cam, seed=9)
+    prm = orc.params_array(t_min=0.0)
+    out = orc.rasterize(g, cam, prm)
+    pj, bs = out["pj"], out["bs"]
+    W, H = cam.width, cam.height
+    ntx, nty = (W + 15) // 16, (H + 15) // 16
+    vis = np.flatnonzero(pj["vis"])
+    order = vis[np.lexsort((vis, pj["depth"][vis]))]  # depth, then slot
+    lists = [[] for _ in range(ntx * nty)]
+    for gid in order:
+        x0, y0, x1, y1 = pj["rect"][gid]
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                lists[ty * ntx + tx].append(int(gid))
+    gid_of = np.array([q for lst in lists for q in lst], np.uint32)
+    ends = np.cumsum([len(lst) for lst in lists])
+    ranges = np.stack([ends - [len(lst) for lst in lists], ends], axis=1).astype(np.uint32)
+    full = orc.composite(pj, dict(gid_of=gid_of, ranges=ranges, n_pairs=len(gid_of)), cam, prm)
+    bound = np.zeros((H, W))
+    n_drop = 0
+    for t, lst in enumerate(lists):
+        s_, e_ = bs["ranges"][t]
+        kept = set(int(q) for q in bs["gid_of"][s_:e_])
+        tx, ty = t % ntx, t // ntx
+        xs = np.arange(16 * tx, min(16 * tx + 16, W)) + 0.5
+        ys = np.arange(16 * ty, min(16 * ty + 16, H)) + 0.5
+        X, Y = np.meshgrid(xs, ys)
+        for gid in lst:
+            if gid in kept:
+                continue
+            n_drop += 1
+            mx, my, ca, cb, cc, op = pj["proj"][gid][:6]
+            dx, dy = X - mx, Y - my
+            q = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy
+            assert q.min() > 9.0
+            a = np.minimum(prm[0], op * np.exp(-0.5 * q))
+            assert a.max() < 0.0112 * op
+            bound[16 * ty:16 * ty + len(ys), 16 * tx:16 * tx + len(xs)] += a
+    assert n_drop > 500
+    diff = np.abs(full["img"] - out["img"]).max(axis=0)
+    assert diff.max() > 0.0
+    assert np.all(diff <= bound + 1e-12)
+
+
 def test_equal_depth_tie_break(orc):
     cam = ident_cam(64, 64, 60.0)
     g = S.tile_aligned_gaussians(cam, [5.0] * 6 + [7.0] * 6, seed=3)
