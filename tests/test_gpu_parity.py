@@ -397,6 +397,13 @@ def test_invalid_arguments_rejected(P):
     g = L.Gaussians()
     assert lib.octgs_rasterize_fwd(ctypes.byref(g), None, None, 0, None, None, None, None, None, 0,
                                    None, None) == L.OCTGS_EINVAL
+    # the decode backward's halves check their pointers before any launch
+    assert lib.octgs_decode_bwd_rows(None, None, None, None, None, None, 0, None, 0,
+                                     None) == L.OCTGS_EINVAL
+    assert lib.octgs_decode_bwd_apply(None, None, None, None, 0, None, None, None, 0,
+                                      None) == L.OCTGS_EINVAL
+    assert lib.octgs_decode_bwd_workspace_bytes(-1, 10, 64) == 0
+    assert lib.octgs_decode_bwd_workspace_bytes(100, 17, 64) == 0  # k above 16
 
 
 # --------------------------------------------------------------------------
