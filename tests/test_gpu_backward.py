@@ -41,6 +41,28 @@ def test_raster_backward_parity(P, orc, W, H, n, seed):
     cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
     gf = S.random_gaussians(n, cam, seed, scale=(0.05, 0.6), neg_opacity_frac=0.1,
                             behind_frac=0.05)
+    _raster_backward_parity(P, orc, cam, gf, seed)
+
+
+def test_raster_backward_parity_huge_gaussians(P, orc):
+    """40 Gaussians that cover most or all of a 640x400 image's 1,000 tiles
+    among 3,000 smaller ones: their pairs span up to 16 chunks of the
+    per-Gaussian reduction (several rounds of its chunk walk)."""
+    W, H = 640, 400
+    cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
+    small = S.random_gaussians(3000, cam, 7, scale=(0.05, 0.6), neg_opacity_frac=0.1,
+                               behind_frac=0.05)
+    huge = S.random_gaussians(40, cam, 8, scale=(1.5, 3.0), opacity=(0.02, 0.2))
+    gf = np.concatenate([small, huge], axis=1)
+    ref = orc.rasterize(gf, cam, orc.params_array())
+    per = np.bincount(ref["bs"]["gid_of"].astype(np.int64), minlength=gf.shape[1])
+    say(f"  Gaussians listed in more than 512 tiles: {(per > 512).sum()}, most {per.max()}")
+    assert (per > 8 * 64).sum() >= 20
+    _raster_backward_parity(P, orc, cam, gf, 4)
+
+
+def _raster_backward_parity(P, orc, cam, gf, seed):
+    W, H, n = cam.width, cam.height, gf.shape[1]
     prm = orc.params_array()
     rng = np.random.default_rng(seed)
     dimg = rng.standard_normal((3, H, W)).astype(np.float32)

@@ -126,8 +126,8 @@ def test_tile_order_long_lists(P):
 
 def test_backward_deterministic(P):
     """The backward run twice on the same view gives the same gradients bit
-    for bit, with Gaussians listed in hundreds of tiles (their pairs span
-    several 64-pair chunks of the per-Gaussian reduction)."""
+    for bit, with Gaussians listed in thousands of tiles (their pairs span
+    up to ~110 64-pair chunks of the per-Gaussian reduction)."""
     W, H, n = 1920, 1080, 150000
     cam = S.look_at((3.0, -20.0, 4.0), (0.0, 0.0, 0.0), W, H, 60.0)
     gf = S.random_gaussians(n, cam, 5, scale=(0.01, 0.4), neg_opacity_frac=0.1, behind_frac=0.05)
@@ -137,7 +137,7 @@ def test_backward_deterministic(P):
     b = _run(P, gf, cam, True, True, pcap, 5)
     per = np.bincount(_pairs_per_slot(P, gf, cam, pcap), minlength=n)
     say(f"  most tiles of one Gaussian: {per.max()}")
-    assert per.max() > 3 * 64
+    assert per.max() > 8 * 64  # the chunk walk takes several rounds of eight
     _same_grads(a["dg"], b["dg"])
 
 
