@@ -15,7 +15,7 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # decisions are taken with explicit fmaf; nothing else may be fused
     "-ffp-contract=off",
-    # hardware float atomics for the blend-weight log and the backward pass
+    # hardware float atomics for the blend-weight log and the loss scalars
     "-munsafe-fp-atomics",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
