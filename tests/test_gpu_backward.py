@@ -157,6 +157,16 @@ def test_decode_bwd_halves_match_whole(P):
         x, y = _np(a[name]), _np(b[name])
         assert np.count_nonzero(x) > 0, name
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), name
+    # an empty list adds nothing
+    before = {k: _np(v).copy() for k, v in halves.all().items()}
+    vb = vbs[0]
+    vb.sel_count = torch.zeros(1, dtype=torch.int32).cuda()
+    vb.decode_bwd_rows(ds, c)
+    vb.decode_bwd_apply(ds, halves)
+    torch.cuda.synchronize()
+    for name, v in halves.all().items():
+        # value equality: the weight sums add +0.0, which turns a -0.0 into +0.0
+        assert np.array_equal(_np(v), before[name]), name
 
 
 def test_full_chain_gradient(P, orc):
