@@ -16,7 +16,7 @@
 namespace octgs {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;          // threads per block in every kernel
+constexpr int kBlock = 256;          // threads per block unless a kernel states its own
 constexpr int kTile = 16;            // screen tile edge in pixels
 constexpr int kChunk = 1024;         // elements per block in the two-pass compactions
 constexpr int kChunkPerThread = kChunk / kBlock;  // 4
@@ -278,6 +278,10 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
 // dst[i] = BF16 bits of src[i] rounded to nearest even, i < count (device
 // arrays); enqueues one kernel on s.
 hipError_t launch_round_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
+// dimg[i] = scale sign(img[i] - tgt[i]) and *loss += scale sum |img - tgt|
+// over n elements (the L1 term's kernel, shared by both loss entry points).
+hipError_t launch_l1(const float *img, const float *tgt, int64_t n, float scale, float *dimg,
+                     float *loss, hipStream_t s);
 int tile_sort_passes(int ntiles);
 
 constexpr float kLog2e = 1.4426950408889634f;
