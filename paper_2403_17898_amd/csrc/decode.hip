@@ -114,7 +114,6 @@ struct PrepArgs {
 //   layer 2, tile c = w + 4 q of the padded output columns (l2_tile)
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void k_decode_prep(PrepArgs a) {
-  chain_priority();
   typedef Frag<BF16> F;
   typedef typename F::Op Op;
   const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -184,7 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_decode_prep(PrepArgs a) {
 
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void k_decode(DecodeArgs a) {
-  chain_priority();
   typedef Frag<BF16> F;
   __shared__ Smem<BF16> sm;
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();

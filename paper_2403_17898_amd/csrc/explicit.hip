@@ -190,7 +190,6 @@ struct ExLds {
 
 template <int D, bool BF16>
 __global__ __launch_bounds__(kExT) void k_decode_explicit(ExArgs a) {
-  chain_priority();
   using R = ShRow<D, BF16>;
   __shared__ ExLds<D, BF16> sm;
   const int t = threadIdx.x, k = a.k;

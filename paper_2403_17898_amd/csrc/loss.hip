@@ -227,21 +227,43 @@ __global__ __launch_bounds__(kBlock) void k_loss_finish(const float *__restrict_
   if (threadIdx.x == 0) *loss = (float)((double)*loss + (double)base + red[0]);
 }
 
-// Volume regularisation over the rendered slots (opacity > 0).  One block
-// of 1024 threads per compute unit at most, so that few blocks add to the
-// one loss address (those atomics are serialised).
-constexpr int kVolBlock = 1024;
-constexpr int kVolGrid = 256;
+// L1 only (w_ssim = 0): elementwise, four independent elements per step.
+__global__ __launch_bounds__(kBlock) void k_l1_only(const float *__restrict__ x,
+                                                    const float *__restrict__ y, int64_t n,
+                                                    float scale, float *__restrict__ dimg,
+                                                    float *__restrict__ loss) {
+  __shared__ float red[4];
+  float acc = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    float d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = min(i0 + u * stride, n - 1);
+      d[u] = x[i] - y[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+        dimg[i] = d[u] > 0.0f ? scale : (d[u] < 0.0f ? -scale : 0.0f);
+        acc += fabsf(d[u]);
+      }
+    }
+  }
+  acc = block_sum_f(acc, red);
+  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
+}
 
-__global__ __launch_bounds__(kVolBlock) void k_volume(const float *__restrict__ g, int64_t cap,
-                                                      const uint32_t *__restrict__ count, float w,
-                                                      float *__restrict__ dg,
-                                                      float *__restrict__ loss) {
-  __shared__ float red[kVolBlock / kWave];
+// Volume regularisation over the rendered slots (opacity > 0).
+__global__ __launch_bounds__(kBlock) void k_volume(const float *__restrict__ g, int64_t cap,
+                                                   const uint32_t *__restrict__ count, float w,
+                                                   float *__restrict__ dg, float *__restrict__ loss) {
+  __shared__ float red[4];
   const int64_t n = min((int64_t)*count, cap);
   float acc = 0.0f;
-  for (int64_t s = (int64_t)blockIdx.x * kVolBlock + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * kVolBlock) {
+  for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * kBlock) {
     const float op = g[10 * cap + s];
     const float s0 = g[3 * cap + s], s1 = g[4 * cap + s], s2 = g[5 * cap + s];
     if (op > 0.0f) {
@@ -251,14 +273,8 @@ __global__ __launch_bounds__(kVolBlock) void k_volume(const float *__restrict__ 
       dg[5 * cap + s] += w * (s0 * s1);
     }
   }
-  acc = wave_sum_f(acc);
-  if (__lane_id() == 0) red[threadIdx.x / kWave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.0f;
-    for (int i = 0; i < kVolBlock / kWave; ++i) t += red[i];
-    if (t != 0.0f) atomicAdd(loss, w * t);
-  }
+  acc = block_sum_f(acc, red);
+  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, w * acc);
 }
 
 }  // namespace
@@ -286,9 +302,10 @@ int octgs_photometric_loss_grad(const float *img, const float *target, int64_t n
   if (n_images > 65535 || !(w_l1 >= 0.0f) || !(w_ssim >= 0.0f)) return OCTGS_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (w_ssim == 0.0f) {
-    return launch_l1(img, target, n, (float)(w_l1 / (double)n), dimg, loss, s) == hipSuccess
-               ? OCTGS_OK
-               : OCTGS_EHIP;
+    const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 512);
+    hipLaunchKernelGGL(k_l1_only, dim3(grid), dim3(kBlock), 0, s, img, target, n,
+                       (float)(w_l1 / (double)n), dimg, loss);
+    return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
   }
   if (!ws) return OCTGS_EINVAL;
   if (ws_bytes < octgs_photometric_workspace_bytes(n_images, height, width)) return OCTGS_ENOSPC;
@@ -317,8 +334,8 @@ int octgs_volume_loss_grad(const octgs_gaussians *g, float weight, float *d_gaus
                            octgs_stream stream) {
   if (!g || !g->data || !g->count || g->capacity < 0 || !d_gauss || !loss) return OCTGS_EINVAL;
   if (g->capacity == 0) return OCTGS_OK;
-  const int grid = (int)std::min<int64_t>((g->capacity + kVolBlock - 1) / kVolBlock, kVolGrid);
-  hipLaunchKernelGGL(k_volume, dim3(grid), dim3(kVolBlock), 0, (hipStream_t)stream, g->data,
+  const int grid = (int)std::min<int64_t>((g->capacity + kBlock - 1) / kBlock, 512);
+  hipLaunchKernelGGL(k_volume, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, g->data,
                      g->capacity, g->count, weight, d_gauss, loss);
   return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }

@@ -16,7 +16,7 @@
 namespace octgs {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;          // threads per block unless a kernel states its own
+constexpr int kBlock = 256;          // threads per block in every kernel
 constexpr int kTile = 16;            // screen tile edge in pixels
 constexpr int kChunk = 1024;         // elements per block in the two-pass compactions
 constexpr int kChunkPerThread = kChunk / kBlock;  // 4
@@ -132,16 +132,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 
 // Sum of v over the 256 threads of a block, returned to thread 0 (LDS
 // scratch of 4 floats).
-// The kernels of a frame's chain (selection, decode, projection, the two
-// sorts, emission, tile ranges) raise their waves' issue priority.  With
-// several frames in flight a compositing kernel's VALU-bound waves occupy
-// every SIMD, while the chain's kernels wait on dependent memory round trips
-// and issue few instructions; issuing those first shortens each frame's
-// chain and costs the compositing little (about 2 % more frames per second
-// with four in flight).  The backward's kernels keep the default: raised,
-// they slowed the multi-view training step.
-__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(1); }
-
 __device__ __forceinline__ float block_sum_f(float v, float *red) {
   v = wave_sum_f(v);
   if (__lane_id() == 0) red[threadIdx.x / kWave] = v;
@@ -288,10 +278,6 @@ RasterWs raster_layout(void *base, int64_t gcap, int64_t pcap, int32_t W, int32_
 // dst[i] = BF16 bits of src[i] rounded to nearest even, i < count (device
 // arrays); enqueues one kernel on s.
 hipError_t launch_round_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
-// dimg[i] = scale sign(img[i] - tgt[i]) and *loss += scale sum |img - tgt|
-// over n elements (the L1 term's kernel, shared by both loss entry points).
-hipError_t launch_l1(const float *img, const float *tgt, int64_t n, float scale, float *dimg,
-                     float *loss, hipStream_t s);
 int tile_sort_passes(int ntiles);
 
 constexpr float kLog2e = 1.4426950408889634f;

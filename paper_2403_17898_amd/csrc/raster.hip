@@ -216,7 +216,6 @@ struct ProjArgs {
 // radix histograms, the scans' look-back status words), which the kernel
 // itself never reads.
 __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
-  chain_priority();
   __shared__ uint32_t wsum[4];
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
   const uint32_t n = (uint32_t)min<int64_t>(*a.count, a.gcap);
@@ -275,7 +274,6 @@ __global__ __launch_bounds__(kBlock) void k_project_mark(ProjArgs a) {
 // It also accumulates the four 8-bit digit histograms of the depth keys for
 // the radix sort.
 __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const uint32_t *count) {
-  chain_priority();
   __shared__ uint32_t red[4];
   __shared__ uint32_t gpre[64];
   __shared__ uint64_t gmask[64];
@@ -346,7 +344,6 @@ __global__ __launch_bounds__(kBlock) void k_project_compact(RasterWs ws, const u
 // Values saturate at 2^30 - 1, above any admissible pair capacity, so they
 // are exact whenever the candidates fit.
 __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
-  chain_priority();
   __shared__ uint32_t tmp[8];
   __shared__ uint64_t red[4];
   __shared__ uint32_t s_excl;
@@ -431,7 +428,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_scan(RasterWs ws) {
 // look-back over the preceding runs and writes (tile id, slot) in order.
 // It also accumulates the digit histograms of the kept tile ids.
 __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int tile_passes, int train) {
-  chain_priority();
   constexpr int kW = kEmitThreads / kWave;     // waves per block
   constexpr int kG = kEmitRun / 64;            // ballot groups per run
   constexpr int kC = kEmitRun / kEmitThreads;  // candidates per thread (8)
@@ -593,7 +589,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(RasterWs ws, int ti
 }
 
 __global__ __launch_bounds__(kBlock) void k_ranges(RasterWs ws, int buf) {
-  chain_priority();
   const uint32_t P = ws.hdr->n_listed;
   const uint32_t *key = ws.tkey[buf];
   for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P; p += gridDim.x * kBlock) {

@@ -128,15 +128,8 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, kWave));
-  // the same on every lane after the butterfly; read from lane 0 so that the
-  // compiler treats the entry loops as uniform (scalar counters and branches)
-  const uint32_t n_used = min((uint32_t)__builtin_amdgcn_readfirstlane((int)mx), end - start);
-  const float amin = a.alpha_min;
-  // alpha_max in a vector register, copied once: the per-pixel select below
-  // cannot read both it and the compare mask from scalar registers, and the
-  // compiler would otherwise copy it before every use
-  float amax;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(amax) : "s"(a.alpha_max));
+  const uint32_t n_used = min(mx, end - start);
+  const float amax = a.alpha_max, amin = a.alpha_min;
   zero_pairs(a.ws, pidx, start + n_used, end);
   if (n_used == 0) return;
   for (int32_t b0 = (int32_t)((n_used - 1) / kBwdBatch) * kBwdBatch; b0 >= 0; b0 -= kBwdBatch) {
@@ -176,8 +169,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
       // k = 0..3 (dy = dy0 + k), D = sum dq, E = sum k dq, F = sum k^2 dq,
       // so sum dq dy = dy0 D + E and sum dq dy^2 = dy0^2 D + 2 dy0 E + F;
       // colour weights
-      // -0 is the additive identity that folds away (0 + x is not x for x = -0)
-      float D = -0.0f, E = -0.0f, F = -0.0f, wr = -0.0f, wg = -0.0f, wb = -0.0f;
+      float D = 0.0f, E = 0.0f, F = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kBPx; ++k) {
@@ -186,11 +178,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
           d += c2;
         }
         const float a0 = __builtin_amdgcn_exp2f(p);
-        // min(amax, a0) as a select on the one compare that also gates dq
-        // (the same value as fminf, NaN included, without its operand
-        // canonicalisation inside the branch)
-        const bool unclamped = a0 <= amax;
-        const float al = unclamped ? a0 : amax;
+        const float al = fminf(amax, a0);
         bool valid = li < last[k];
         if (AMIN) valid = valid && !(al < amin);
         if (valid) {
@@ -205,7 +193,7 @@ __device__ __forceinline__ void composite_bwd_tile(const BwdArgs &a, BwdLds &lds
           const float dLda = Ti * cdot - S[k] * inv1;
           S[k] = fma_(w, cdot, S[k]);
           T[k] = Ti;
-          const float dq = unclamped ? dLda * a0 : 0.0f;
+          const float dq = a0 <= amax ? dLda * a0 : 0.0f;
           D += dq;
           if (k > 0) {
             E = fma_((float)k, dq, E);

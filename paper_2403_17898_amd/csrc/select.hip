@@ -144,7 +144,6 @@ __global__ __launch_bounds__(kBlock) void k_select_mark(int64_t n, octgs_camera 
                                                         const float *__restrict__ rho,
                                                         uint64_t *__restrict__ masks,
                                                         uint32_t *__restrict__ blk_cnt) {
-  chain_priority();
   __shared__ uint32_t wsum[4];
   const Frustum f = frustum(cam, dilation, jac_clamp);
   const int t = threadIdx.x, w = t / kWave, l = __lane_id();
@@ -185,7 +184,6 @@ __global__ __launch_bounds__(kBlock) void k_select_scatter(int64_t n,
                                                            const uint32_t *__restrict__ blk_cnt,
                                                            uint32_t *__restrict__ sel_idx,
                                                            uint32_t *__restrict__ sel_count) {
-  chain_priority();
   __shared__ uint32_t red[4];
   __shared__ uint32_t gpre[64];
   __shared__ uint64_t gmask[64];

@@ -95,7 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
     uint32_t *__restrict__ hist, int hist_copies, uint32_t hist_stride, int fold_passes,
     uint32_t *__restrict__ lookback, uint32_t *__restrict__ groups, uint32_t *__restrict__ ticket,
     uint32_t *__restrict__ err_flag) {
-  chain_priority();
   constexpr int PART = kBlock * ITEMS;
   __shared__ PassSmem<NV, PART> sm;
   __shared__ uint32_t s_part;

@@ -8,27 +8,23 @@ namespace octgs {
 namespace {
 
 // Grid-stride over float4 groups, four groups per thread per step with all
-// loads issued before any use; one atomic per block for the loss.  Every
+// loads issued before any use; one atomic per block for the loss (every
 // atomic on the one loss address is serialised across the XCDs, so the grid
-// is one block of 1024 threads per compute unit (256 atomics): 512 blocks of
-// 256 took a third longer over a 1600 x 1066 image.  The tail (n % 4
-// elements) and unaligned arrays take the scalar loop.
-constexpr int kL1Block = 1024;
-constexpr int kL1Grid = 256;
-
+// stays small).  The tail (n % 4 elements) and unaligned arrays take the
+// scalar loop.
 __device__ __forceinline__ float l1_one(float d, float scale, float &acc) {
   acc += fabsf(d);
   return d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
 }
 
-__global__ __launch_bounds__(kL1Block) void k_l1(const float *__restrict__ img,
-                                                 const float *__restrict__ tgt, int64_t n,
-                                                 float scale, float *__restrict__ dimg,
-                                                 float *__restrict__ loss) {
-  __shared__ float red[kL1Block / kWave];
+__global__ __launch_bounds__(kBlock) void k_l1(const float *__restrict__ img,
+                                               const float *__restrict__ tgt, int64_t n,
+                                               float scale, float *__restrict__ dimg,
+                                               float *__restrict__ loss) {
+  __shared__ float red[4];
   float acc = 0.0f;
-  const int64_t stride = (int64_t)gridDim.x * kL1Block;
-  const int64_t tid = (int64_t)blockIdx.x * kL1Block + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool vec = (((uintptr_t)img | (uintptr_t)tgt | (uintptr_t)dimg) & 15) == 0;
   const int64_t n4 = vec ? n / 4 : 0;
   const float4 *a4 = reinterpret_cast<const float4 *>(img);
@@ -56,14 +52,8 @@ __global__ __launch_bounds__(kL1Block) void k_l1(const float *__restrict__ img,
     }
   }
   for (int64_t i = 4 * n4 + tid; i < n; i += stride) dimg[i] = l1_one(img[i] - tgt[i], scale, acc);
-  acc = wave_sum_f(acc);
-  if (__lane_id() == 0) red[threadIdx.x / kWave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.0f;
-    for (int w = 0; w < kL1Block / kWave; ++w) t += red[w];
-    if (t != 0.0f) atomicAdd(loss, t * scale);
-  }
+  acc = block_sum_f(acc, red);
+  if (threadIdx.x == 0 && acc != 0.0f) atomicAdd(loss, acc * scale);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adam(float *__restrict__ p, const float *__restrict__ g,
@@ -160,13 +150,6 @@ __global__ __launch_bounds__(kBlock) void k_adam_many(AdamMany a, float lr, floa
 
 }  // namespace
 
-hipError_t launch_l1(const float *img, const float *tgt, int64_t n, float scale, float *dimg,
-                     float *loss, hipStream_t s) {
-  const int grid = (int)std::min<int64_t>((n + kL1Block - 1) / kL1Block, kL1Grid);
-  hipLaunchKernelGGL(k_l1, dim3(grid), dim3(kL1Block), 0, s, img, tgt, n, scale, dimg, loss);
-  return hipGetLastError();
-}
-
 }  // namespace octgs
 
 using namespace octgs;
@@ -177,9 +160,10 @@ int octgs_l1_loss_grad(const float *img, const float *target, int64_t n, float s
                        float *loss, octgs_stream stream) {
   if (n < 0 || (n > 0 && (!img || !target || !dimg || !loss))) return OCTGS_EINVAL;
   if (n == 0) return OCTGS_OK;
-  return launch_l1(img, target, n, scale, dimg, loss, (hipStream_t)stream) == hipSuccess
-             ? OCTGS_OK
-             : OCTGS_EHIP;
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 512);
+  hipLaunchKernelGGL(k_l1, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, img, target, n, scale,
+                     dimg, loss);
+  return hipGetLastError() == hipSuccess ? OCTGS_OK : OCTGS_EHIP;
 }
 
 int octgs_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
