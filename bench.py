@@ -45,6 +45,8 @@ FLOP_PER_BLEND = 21.0
 COMPOSITE_PMC = os.path.join(ROOT, "profiles", "composite_street1080p_hbm_bytes.txt")
 RASTER_PMC = os.path.join(ROOT, "profiles", "raster_street1080p_hbm_bytes.txt")
 RASTER_SOURCES = ("paper_2403_17898_amd/csrc/raster.hip", "paper_2403_17898_amd/csrc/sort.hip")
+COMPOSITE_BWD_PMC = os.path.join(ROOT, "profiles", "composite_bwd_train_c3_hbm_bytes.txt")
+BWD_SOURCES = ("paper_2403_17898_amd/csrc/raster_bwd.hip",)
 
 # The paper's own rendering rates, for context only: another scene, another
 # resolution and another GPU (Tab. matrix_traj, Sec. V-B: MatrixCity
@@ -111,6 +113,22 @@ def raster_traffic(views: int):
         return None
     try:
         return int(float(f["hbm_bytes_per_view"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def composite_bwd_traffic():
+    """HBM bytes per launch of the compositing backward on the training
+    views from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
+    it is missing or was taken from another version of the kernel source."""
+    f = read_summary(COMPOSITE_BWD_PMC)
+    if not f:
+        return None
+    for rel in BWD_SOURCES:
+        if f.get("source_sha256 " + os.path.basename(rel)) != sha256_of(rel):
+            return None
+    try:
+        return int(float(f["hbm_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
 
@@ -1025,7 +1043,7 @@ def composite_bwd_roofline(P, torch, np, vb, ds, cams, prm, targets, scale, W, H
             "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "flop_per_blend": FLOP_PER_BLEND_BWD,
             "blends_per_launch": round(blends / n), "launch_ms": round(ms, 5),
             "algorithmic_bytes": round(alg), "hbm_gbs": round(alg / (ms * 1e-3) / 1e9, 1),
-            "traffic": None}
+            "traffic": composite_bwd_traffic()}
 
 
 def train_step_timing(args, P, S, torch, np, sc=None, views=None,
@@ -1397,6 +1415,47 @@ def summarize_counters(sq_dir: str, trace_dir: str, views: int, cmd: str, out_na
     print(f"wrote profiles/{out_name}")
 
 
+def summarize_bwd_traffic(fetch_dir: str, write_dir: str, steps: int, cmds):
+    """Writes profiles/composite_bwd_train_c3_hbm_bytes.txt from the
+    FETCH_SIZE and WRITE_SIZE runs `cmds` of `bench.py --train-only
+    --inflight 1 --train-steps STEPS --copy-calibration`: the last four
+    dispatches of k_composite_bwd, which are the launches the backward's
+    roofline times (each training view once, alone on the GPU), KiB per
+    dispatch scaled by what each counter reads for the 256 MiB copies."""
+    fetch = [r for r in _csv_rows(fetch_dir, "counter_collection.csv") if r["Counter_Name"] == "FETCH_SIZE"]
+    write = [r for r in _csv_rows(write_dir, "counter_collection.csv") if r["Counter_Name"] == "WRITE_SIZE"]
+
+    def copy_mean(rows):
+        cp = sorted((float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]),
+                    reverse=True)[:5]
+        if not cp:
+            raise SystemExit("no calibration copies in the counter run")
+        return sum(cp) / len(cp)
+
+    cf, cw = copy_mean(fetch), copy_mean(write)
+    sf, sw = 262144.0 / cf, 262144.0 / cw
+    n = 4
+    rd = sum(float(r["Counter_Value"]) for r in _last(fetch, "k_composite_bwd", n)) / n * 1024 * sf
+    wr = sum(float(r["Counter_Value"]) for r in _last(write, "k_composite_bwd", n)) / n * 1024 * sw
+    shas = [f"source_sha256 {os.path.basename(f)}: {sha256_of(f)}" for f in BWD_SOURCES]
+    cmd_txt = "\n".join("  " + c for c in cmds)
+    txt = (
+        "HBM bytes per launch of k_composite_bwd in the training step (500k anchors / 6 levels,\n"
+        "4 views at 1600x1066, one view in flight), from the FETCH_SIZE and WRITE_SIZE counters (KiB\n"
+        "per dispatch), each scaled by what the same counter reads for a plain 256 MiB device copy in\n"
+        f"the same run, over the last {n} dispatches: the launches that the backward's roofline in\n"
+        f"bench.py times, each training view once, after {steps} timed steps.\n\n"
+        f"commands ($REPO = repository root):\n{cmd_txt}\n\n"
+        f"FETCH_SIZE 256 MiB copy mean KiB: {cf:.1f} -> scale {sf:.3f}\n"
+        f"WRITE_SIZE 256 MiB copy mean KiB: {cw:.1f} -> scale {sw:.3f}\n"
+        f"hbm_bytes_per_launch: {int(rd + wr)}\n"
+        f"read bytes per launch (scaled): {int(rd)}\nwrite bytes per launch (scaled): {int(wr)}\n"
+        + "\n".join(shas) + "\n")
+    with open(COMPOSITE_BWD_PMC, "w") as f:
+        f.write(txt)
+    print(txt)
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-train-trace":
         # python bench.py --summarize-train-trace TRACE_DIR STEPS CMD [LOG]
@@ -1415,6 +1474,10 @@ if __name__ == "__main__":
                 sub, cnt = rest.rsplit(":", 1)
                 spec.append((lab, sub, int(cnt)))
         summarize_counters(a[0], a[1], int(a[2]), a[3], a[4], spec, a[6] if len(a) > 6 else None)
+    elif len(sys.argv) > 1 and sys.argv[1] == "--summarize-bwd-traffic":
+        # python bench.py --summarize-bwd-traffic FETCH_DIR WRITE_DIR STEPS CMD1 CMD2
+        a = sys.argv[2:]
+        summarize_bwd_traffic(a[0], a[1], int(a[2]), a[3:5])
     elif len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
         # python bench.py --summarize-profiles TRACE_DIR FETCH_DIR WRITE_DIR VIEWS CMD1 CMD2 CMD3
         a = sys.argv[2:]
